@@ -1,0 +1,159 @@
+/*
+ * hq.h -- spectral projectors of symmetric banded matrices by QDWH in HODLR format, on one AMD
+ * Instinct MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * Problem (Sec. 1 of Kressner & Susnjara, "Fast computation of spectral projectors of banded
+ * matrices"): for a symmetric b-banded A of order n and a shift mu with
+ * lambda_nu < mu < lambda_{nu+1}, compute Pi_{<mu}(A), the orthogonal projector onto the
+ * eigenvectors of the nu eigenvalues below mu, as Pi = (I - sign(A - mu I)) / 2 (Sec. 2).  The sign
+ * function is the limit of the QDWH iteration (eq. reccur, weights eq. qdwh_parameters_abc); the
+ * first step uses the structured QR of Sec. 4 (Algorithms 1/2), every later step the Cholesky form
+ * (eq. qdwh_chol_reccur), all in HODLR format (Sec. 3.1.1) -- Algorithm hQDWH (Sec. 5).
+ *
+ * Conventions
+ *  - Band input: LAPACK lower band storage, column-major, ab[i + j*ldab] = A(j+i, j) for
+ *    0 <= i <= b, ldab >= b+1; only the lower triangle is read (A is symmetric by construction).
+ *  - Pointers documented "device" are HIP device pointers; "host" are ordinary host pointers.
+ *    Inputs are borrowed: they must stay valid until the call's work has completed on `stream`.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Every call returns hq_status; 0 is success.  No C++ exception crosses the ABI.  On error the
+ *    output handle is set to NULL.  hq_last_error() gives a message for the calling thread.
+ *  - A handle owns all device memory of its HODLR matrix until hodlr_destroy.  Calls on one handle
+ *    are not reentrant: issue them from one thread, in order.
+ */
+#ifndef HQ_H
+#define HQ_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HQ_OK = 0,
+  HQ_ERR_ARG = -1,            /* invalid argument; hq_last_error() names it */
+  HQ_ERR_ALLOC = -2,          /* device or host allocation failed */
+  HQ_ERR_DEVICE = -3,         /* HIP runtime error */
+  HQ_ERR_UNSUPPORTED = -4,    /* e.g. bandwidth larger than the smallest diagonal block */
+  HQ_ERR_SINGULAR_SHIFT = 1,  /* mu is (numerically) an eigenvalue: no positive lower bound l0 */
+  HQ_ERR_NOT_POSDEF = 2,      /* a leaf of Z = I + c X^T X lost positive definiteness */
+  HQ_ERR_NO_CONVERGENCE = 3,  /* |1 - l_k| > delta after max_iter steps of the weight recurrence */
+  HQ_ERR_RANK_OVERFLOW = 4    /* an off-diagonal rank exceeded opts.max_rank even after regrowth */
+} hq_status;
+
+typedef struct hq_hodlr_s* hq_hodlr_t; /* opaque HODLR matrix on the device */
+
+typedef struct {
+  int32_t leaf;      /* n_min: diagonal blocks have at most this many rows (Alg. 3 input), >= 2 */
+  double tol;        /* epsilon: absolute truncation tolerance of every recompression (Sec. 5), > 0 */
+  double delta;      /* stopping tolerance |1 - l_k| <= delta (Alg. 3), default 1e-15 */
+  int32_t max_rank;  /* largest off-diagonal rank a block may reach, default 512 */
+  int32_t max_iter;  /* bound on QDWH iterations, default 10 */
+} hq_opts;
+
+typedef struct {
+  int32_t iters;             /* QDWH iterations K */
+  double alpha;              /* scaling alpha >= ||A - mu I||_2 */
+  double l0;                 /* certified lower bound of sigma_min((A - mu I)/alpha) */
+  double a[16], b[16], c[16];/* weights of each iteration */
+  int32_t max_rank_iter[16]; /* largest off-diagonal rank of X_{k+1} */
+  int32_t max_rank;          /* largest off-diagonal rank of the returned matrix */
+  int32_t redo_count;        /* iterations repeated after a capacity overflow */
+  int64_t bytes;             /* device bytes of the returned matrix */
+  int64_t peak_bytes;        /* peak device working set of the solve */
+  int64_t launches;          /* kernel launches issued */
+  double seconds;            /* wall time of the call */
+  double setup_seconds;      /* alpha, l0 and the weight schedule (host) */
+  double givens_seconds;     /* Algorithms 1/2 and the Q factors (host) */
+} hq_info;
+
+/* Fill *o with the defaults: leaf 256, tol 1e-10, delta 1e-15, max_rank 512, max_iter 10. */
+hq_status hq_default_opts(hq_opts* o);
+
+/*
+ * X0 = (A - shift I) / scale as an exact HODLR matrix (Alg. 3, X_0 = A/alpha with the shift of
+ * Sec. 2).  band: device.  Every off-diagonal block is the b x b corner next to the diagonal, stored
+ * with rank b; requires b <= the smallest diagonal block.  Stream-ordered, asynchronous.
+ */
+hq_status hodlr_build(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
+                      const hq_opts* opts, void* stream, hq_hodlr_t* out);
+
+/*
+ * U ~ sign(A - mu I) in HODLR format (Sec. 2; Alg. 3 lines up to "U = X_k", symmetrised).
+ * band: device.  Blocks until done (returns host status and info).  info may be NULL.
+ */
+hq_status qdwh_sign(const double* band, int64_t n, int32_t b, int64_t ldab, double mu, const hq_opts* opts,
+                    void* stream, hq_hodlr_t* sign_out, hq_info* info);
+
+/*
+ * P ~ Pi_{<mu}(A) = (I - sign(A - mu I)) / 2 in HODLR format (Alg. 3, output P).  band: device.
+ * Blocks until done.  info may be NULL.
+ */
+hq_status spectral_projector(const double* band, int64_t n, int32_t b, int64_t ldab, double mu,
+                             const hq_opts* opts, void* stream, hq_hodlr_t* P_out, hq_info* info);
+
+/*
+ * Y = P X for a HODLR matrix P (Table complexity_HODLR, matrix-vector product, O(k n log n) per
+ * column).  X: device, n x ncols, column-major, ldx >= n.  Y: device, ldy >= n, overwritten; must
+ * not overlap X.  Stream-ordered, asynchronous.
+ */
+hq_status apply_projector(hq_hodlr_t P, const double* X, int64_t ldx, int32_t ncols, double* Y, int64_t ldy,
+                          void* stream);
+
+/* Dense copy (device, n x n, ld >= n) of a HODLR matrix; meant for tests and small n. */
+hq_status hodlr_to_dense(hq_hodlr_t H, double* out, int64_t ld, void* stream);
+
+/* Structure of a handle: order, tree levels, number of leaves, sum of leaf traces (host values). */
+hq_status hodlr_shape(hq_hodlr_t H, int64_t* n, int32_t* levels, int32_t* nleaves, int32_t* max_rank);
+/* Host copy of leaf i: rows/cols [*lo, *lo + *m); out: host, ld >= m. */
+hq_status hodlr_get_leaf(hq_hodlr_t H, int32_t i, double* out, int64_t ld, int64_t* lo, int64_t* m);
+/* Host copy of off-diagonal block `which` (0 upper, 1 lower) of internal node `node` (heap order):
+ * U: rows x rank, V: cols x rank (ld >= rows/cols, capacity >= *rank).  Pass U = V = NULL to query
+ * rank and extents only.  lo/mid/hi give the node's row range and split. */
+hq_status hodlr_get_block(hq_hodlr_t H, int32_t node, int32_t which, double* U, double* V, int64_t ld,
+                          int32_t* rank, int64_t* lo, int64_t* mid, int64_t* hi);
+
+/*
+ * mu between lambda_nu and lambda_{nu+1}: the midpoint, by Sylvester-inertia bisection on the host
+ * (band: host).  Also returns the gap lambda_{nu+1} - lambda_nu.  1 <= nu < n.
+ */
+hq_status hq_shift_for_count(const double* band, int64_t n, int32_t b, int64_t ldab, int64_t nu, double* mu,
+                             double* gap);
+
+void hodlr_destroy(hq_hodlr_t H);
+const char* hq_status_string(hq_status s);
+const char* hq_last_error(void);
+
+/* ---- Test hooks: single building blocks of the path, exposed so that tests can compare each one
+ *      with an independent reference.  All pointers device unless stated. ---- */
+/* C = alpha op(A) op(B) + beta C through the batched FP64 MFMA kernel. */
+hq_status hq_test_gemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k,
+                       int32_t lda, int32_t ldb, int32_t ldc, int32_t opA, int32_t opB, double alpha, double beta,
+                       void* stream);
+/* R factor (r x r, upper, ldr = r) of the Householder TSQR of M (rows x r). */
+hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, double* R, void* stream);
+/* Truncated recompression of Us (m x r) Vs^T (n x r): U (m x k), V (n x k), *k host. */
+hq_status hq_test_recompress(const double* Us, int32_t m, const double* Vs, int32_t n, int32_t r, double tol,
+                             int32_t kcap, double* U, double* V, int32_t* k, void* stream);
+/* HODLR approximation of a dense symmetric-or-not matrix (device, n x n, ld) by truncated SVD of
+ * every off-diagonal block. */
+hq_status hq_test_from_dense(const double* dense, int64_t n, int64_t ld, const hq_opts* opts, int32_t cap,
+                             void* stream, hq_hodlr_t* out);
+/* C = alpha op(A) op(B) + delta * (D or I); lower_only keeps the lower blocks only (symmetric C). */
+hq_status hq_test_product(hq_hodlr_t A, int32_t transA, hq_hodlr_t B, int32_t transB, double alpha, hq_hodlr_t D,
+                          int32_t d_identity, double delta, int32_t lower_only, int32_t cap, double tol,
+                          void* stream, hq_hodlr_t* out);
+/* L^{-1} of the Cholesky factor of a symmetric positive definite HODLR Z (lower blocks used). */
+hq_status hq_test_cholesky_inverse(hq_hodlr_t Z, int32_t cap, double tol, void* stream, hq_hodlr_t* out);
+/* Q1, Q2 of the structured QR of [scale*(A - shift I); I] (band: host) in HODLR format. */
+hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
+                            int32_t leaf, void* stream, hq_hodlr_t* q1, hq_hodlr_t* q2, int64_t* nrot);
+
+/* Host-only: the same Q1, Q2 assembled densely (Q1, Q2: host, n x n, ld n).  No device use. */
+hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
+                               int32_t leaf, double* Q1, double* Q2, int64_t* nrot);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,303 @@
+"""ctypes binding of libhqdwh.so (same names as the C ABI in include/hq.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libhqdwh.so")
+
+c_d = ctypes.c_double
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_vp = ctypes.c_void_p
+P = ctypes.POINTER
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class HQError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hq status {status}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("leaf", c_i32), ("tol", c_d), ("delta", c_d), ("max_rank", c_i32), ("max_iter", c_i32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("alpha", c_d), ("l0", c_d), ("a", c_d * 16), ("b", c_d * 16), ("c", c_d * 16),
+                ("max_rank_iter", c_i32 * 16), ("max_rank", c_i32), ("redo_count", c_i32), ("bytes", c_i64),
+                ("peak_bytes", c_i64), ("launches", c_i64), ("seconds", c_d), ("setup_seconds", c_d),
+                ("givens_seconds", c_d)]
+
+    def as_dict(self) -> dict:
+        K = self.iters
+        return {"iters": K, "alpha": self.alpha, "l0": self.l0, "a": list(self.a[:K]), "b": list(self.b[:K]),
+                "c": list(self.c[:K]), "max_rank_iter": list(self.max_rank_iter[:K]), "max_rank": self.max_rank,
+                "redo_count": self.redo_count, "bytes": self.bytes, "peak_bytes": self.peak_bytes,
+                "launches": self.launches, "seconds": self.seconds, "setup_seconds": self.setup_seconds,
+                "givens_seconds": self.givens_seconds}
+
+
+_lib = None
+
+_SIGS = {
+    "hq_default_opts": (c_i32, [P(Opts)]),
+    "hodlr_build": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, P(Opts), c_vp, P(c_vp)]),
+    "qdwh_sign": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, P(Opts), c_vp, P(c_vp), P(Info)]),
+    "spectral_projector": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, P(Opts), c_vp, P(c_vp), P(Info)]),
+    "apply_projector": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp]),
+    "hodlr_to_dense": (c_i32, [c_vp, c_vp, c_i64, c_vp]),
+    "hodlr_shape": (c_i32, [c_vp, P(c_i64), P(c_i32), P(c_i32), P(c_i32)]),
+    "hodlr_get_leaf": (c_i32, [c_vp, c_i32, c_vp, c_i64, P(c_i64), P(c_i64)]),
+    "hodlr_get_block": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp, c_i64, P(c_i32), P(c_i64), P(c_i64), P(c_i64)]),
+    "hq_shift_for_count": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, P(c_d), P(c_d)]),
+    "hodlr_destroy": (None, [c_vp]),
+    "hq_status_string": (ctypes.c_char_p, [c_i32]),
+    "hq_last_error": (ctypes.c_char_p, []),
+    "hq_test_gemm": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_d, c_d, c_vp]),
+    "hq_test_qr_r": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
+    "hq_test_recompress": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_i32, c_d, c_i32, c_vp, c_vp, P(c_i32), c_vp]),
+    "hq_test_from_dense": (c_i32, [c_vp, c_i64, c_i64, P(Opts), c_i32, c_vp, P(c_vp)]),
+    "hq_test_product": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_d, c_vp, c_i32, c_d, c_i32, c_i32, c_d, c_vp, P(c_vp)]),
+    "hq_test_cholesky_inverse": (c_i32, [c_vp, c_i32, c_d, c_vp, P(c_vp)]),
+    "hq_test_q_factors": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, P(c_vp), P(c_vp), P(c_i64)]),
+    "hq_test_q_dense_host": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, c_vp, P(c_i64)]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libhqdwh.so; raise LibraryMissing if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise LibraryMissing(f"{LIBPATH} not found: run __graft_entry__.build() or "
+                                 "python paper_1608_01164_amd/build.py")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        L = lib()
+        raise HQError(status, f"{L.hq_status_string(status).decode()}: {L.hq_last_error().decode()}")
+
+
+def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10) -> Opts:
+    o = Opts()
+    _check(lib().hq_default_opts(ctypes.byref(o)))
+    o.leaf, o.tol, o.delta, o.max_rank, o.max_iter = int(leaf), float(tol), float(delta), int(max_rank), int(max_iter)
+    return o
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return c_vp(torch.cuda.current_stream().cuda_stream)
+    return c_vp(int(stream))
+
+
+def _dev_f64(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+    return t
+
+
+def _band_args(band):
+    band = _dev_f64(band, "band")
+    if band.dim() != 2 or not band.is_contiguous():
+        raise ValueError("band must be a contiguous (n, ld) tensor in lower band storage")
+    n, ld = band.shape
+    return c_vp(band.data_ptr()), n, ld
+
+
+class HODLR:
+    """A HODLR matrix owned by the library (handle)."""
+
+    def __init__(self, handle: c_vp):
+        self._h = handle
+        n = c_i64()
+        lv = c_i32()
+        nl = c_i32()
+        _check(lib().hodlr_shape(self._h, ctypes.byref(n), ctypes.byref(lv), ctypes.byref(nl), None))
+        self.n, self.levels, self.nleaves = n.value, lv.value, nl.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def max_rank(self) -> int:
+        r = c_i32()
+        _check(lib().hodlr_shape(self._h, None, None, None, ctypes.byref(r)))
+        return r.value
+
+    def apply(self, X, out=None, stream=None):
+        """Y = H X for a device tensor X of shape (n,) or (n, k) (float64)."""
+        import torch
+        X = _dev_f64(X, "X")
+        vec = X.dim() == 1
+        Xm = X.reshape(self.n, -1)
+        # column-major n x k view: use the transpose of a contiguous (k, n) tensor
+        Xc = Xm.t().contiguous()
+        Y = torch.empty_like(Xc) if out is None else out
+        k = Xc.shape[0]
+        _check(lib().apply_projector(self._h, c_vp(Xc.data_ptr()), self.n, k, c_vp(Y.data_ptr()), self.n,
+                                     _stream(stream)))
+        Y = Y.t()
+        return Y.reshape(self.n) if vec else Y
+
+    def to_dense(self, stream=None):
+        import torch
+        out = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda")
+        _check(lib().hodlr_to_dense(self._h, c_vp(out.data_ptr()), self.n, _stream(stream)))
+        return out.t()  # column-major buffer -> row-major view
+
+    def export(self) -> dict:
+        """Host copy in the oracle's plain format {n, leaves, blocks}."""
+        L = lib()
+        leaves, blocks = [], []
+        for i in range(self.nleaves):
+            lo, m = c_i64(), c_i64()
+            _check(L.hodlr_get_leaf(self._h, i, None, 0, ctypes.byref(lo), ctypes.byref(m)))
+            buf = np.zeros((m.value, m.value))  # column-major fill through the transpose
+            bt = np.zeros((m.value, m.value), order="F")
+            _check(L.hodlr_get_leaf(self._h, i, bt.ctypes.data_as(c_vp), m.value, None, None))
+            buf[:] = bt
+            leaves.append((lo.value, lo.value + m.value, buf))
+        nint = (1 << self.levels) - 1
+        for p in range(nint):
+            fac = []
+            for s in (0, 1):
+                r, lo, mid, hi = c_i32(), c_i64(), c_i64(), c_i64()
+                _check(L.hodlr_get_block(self._h, p, s, None, None, 0, ctypes.byref(r), ctypes.byref(lo),
+                                         ctypes.byref(mid), ctypes.byref(hi)))
+                ld = max(mid.value - lo.value, hi.value - mid.value)
+                U = np.zeros((ld, max(r.value, 1)), order="F")
+                V = np.zeros((ld, max(r.value, 1)), order="F")
+                _check(L.hodlr_get_block(self._h, p, s, U.ctypes.data_as(c_vp), V.ctypes.data_as(c_vp), ld,
+                                         ctypes.byref(r), None, None, None))
+                ma, mb = mid.value - lo.value, hi.value - mid.value
+                ru, rv = (ma, mb) if s == 0 else (mb, ma)
+                fac += [np.ascontiguousarray(U[:ru, : r.value]), np.ascontiguousarray(V[:rv, : r.value])]
+            blocks.append((lo.value, mid.value, hi.value, *fac))
+        return {"n": self.n, "leaves": leaves, "blocks": blocks}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().hodlr_destroy(self._h)
+        self._h = c_vp(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hodlr_build(band, b: int, shift: float, scale: float, leaf: int = 256, stream=None) -> HODLR:
+    p, n, ld = _band_args(band)
+    h = c_vp()
+    _check(lib().hodlr_build(p, n, int(b), ld, float(shift), float(scale), ctypes.byref(_opts(leaf=leaf)),
+                             _stream(stream), ctypes.byref(h)))
+    return HODLR(h)
+
+
+def _solve(fn, band, b, mu, stream, **kw):
+    p, n, ld = _band_args(band)
+    h = c_vp()
+    info = Info()
+    _check(getattr(lib(), fn)(p, n, int(b), ld, float(mu), ctypes.byref(_opts(**kw)), _stream(stream),
+                              ctypes.byref(h), ctypes.byref(info)))
+    return HODLR(h), info.as_dict()
+
+
+def spectral_projector(band, b: int, mu: float, stream=None, **opts):
+    """(P, info): P ~ Pi_{<mu}(A) in HODLR format.  opts: leaf, tol, delta, max_rank, max_iter."""
+    return _solve("spectral_projector", band, b, mu, stream, **opts)
+
+
+def qdwh_sign(band, b: int, mu: float, stream=None, **opts):
+    return _solve("qdwh_sign", band, b, mu, stream, **opts)
+
+
+def shift_for_count(band_host: np.ndarray, b: int, nu: int):
+    """(mu, gap) with mu the midpoint of lambda_nu and lambda_{nu+1} (library's own inertia bisection)."""
+    ab = np.ascontiguousarray(band_host, dtype=np.float64)
+    n, ld = ab.shape
+    mu, gap = c_d(), c_d()
+    _check(lib().hq_shift_for_count(ab.ctypes.data_as(c_vp), n, int(b), ld, int(nu), ctypes.byref(mu),
+                                    ctypes.byref(gap)))
+    return mu.value, gap.value
+
+
+# ---- test hooks ---------------------------------------------------------------------------------
+def test_gemm(A, B, C, m, n, k, lda, ldb, ldc, opA, opB, alpha, beta, stream=None):
+    _check(lib().hq_test_gemm(c_vp(A.data_ptr()), c_vp(B.data_ptr()), c_vp(C.data_ptr()), m, n, k, lda, ldb, ldc,
+                              opA, opB, alpha, beta, _stream(stream)))
+
+
+def test_qr_r(M, rows, r, ldm, R, stream=None):
+    _check(lib().hq_test_qr_r(c_vp(M.data_ptr()), rows, r, ldm, c_vp(R.data_ptr()), _stream(stream)))
+
+
+def test_recompress(Us, m, Vs, n, r, tol, kcap, U, V, stream=None) -> int:
+    k = c_i32()
+    _check(lib().hq_test_recompress(c_vp(Us.data_ptr()), m, c_vp(Vs.data_ptr()), n, r, tol, kcap,
+                                    c_vp(U.data_ptr()), c_vp(V.data_ptr()), ctypes.byref(k), _stream(stream)))
+    return k.value
+
+
+def test_from_dense(dense_colmajor, n, leaf, tol, cap, stream=None) -> HODLR:
+    h = c_vp()
+    _check(lib().hq_test_from_dense(c_vp(dense_colmajor.data_ptr()), n, n, ctypes.byref(_opts(leaf=leaf, tol=tol)),
+                                    cap, _stream(stream), ctypes.byref(h)))
+    return HODLR(h)
+
+
+def test_product(A: HODLR, tA, B: HODLR, tB, alpha, D: HODLR | None, d_identity, delta, lower_only, cap, tol,
+                 stream=None) -> HODLR:
+    h = c_vp()
+    _check(lib().hq_test_product(A.handle, tA, B.handle, tB, alpha, D.handle if D else None, d_identity, delta,
+                                 lower_only, cap, tol, _stream(stream), ctypes.byref(h)))
+    return HODLR(h)
+
+
+def test_cholesky_inverse(Z: HODLR, cap, tol, stream=None) -> HODLR:
+    h = c_vp()
+    _check(lib().hq_test_cholesky_inverse(Z.handle, cap, tol, _stream(stream), ctypes.byref(h)))
+    return HODLR(h)
+
+
+def test_q_factors(band_host: np.ndarray, b, shift, scale, leaf, stream=None):
+    ab = np.ascontiguousarray(band_host, dtype=np.float64)
+    n, ld = ab.shape
+    h1, h2, nr = c_vp(), c_vp(), c_i64()
+    _check(lib().hq_test_q_factors(ab.ctypes.data_as(c_vp), n, b, ld, shift, scale, leaf, _stream(stream),
+                                   ctypes.byref(h1), ctypes.byref(h2), ctypes.byref(nr)))
+    return HODLR(h1), HODLR(h2), nr.value
+
+
+def test_q_dense_host(band_host: np.ndarray, b, shift, scale, leaf):
+    ab = np.ascontiguousarray(band_host, dtype=np.float64)
+    n, ld = ab.shape
+    Q1 = np.zeros((n, n), order="F")
+    Q2 = np.zeros((n, n), order="F")
+    nr = c_i64()
+    _check(lib().hq_test_q_dense_host(ab.ctypes.data_as(c_vp), n, b, ld, shift, scale, leaf,
+                                      Q1.ctypes.data_as(c_vp), Q2.ctypes.data_as(c_vp), ctypes.byref(nr)))
+    return Q1, Q2, nr.value

@@ -1,0 +1,906 @@
+// C ABI of the library and the hQDWH driver (Algorithm 3 of the paper).
+#include "../../include/hq.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "givens.h"
+
+struct hq_hodlr_s {
+  hq::Tree t;
+  std::unique_ptr<hq::Engine> e;
+  hq::HMat H;
+  int* d_w = nullptr;     // device int: width of the current apply
+  hipEvent_t done = nullptr;
+  ~hq_hodlr_s() {
+    if (done) (void)hipEventDestroy(done);
+    e.reset();
+  }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+hq_status fail(hq_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+template <class F>
+hq_status guard(F&& f) {
+  try {
+    return f();
+  } catch (const hq::HipError& e) {
+    return fail(HQ_ERR_DEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(HQ_ERR_ALLOC, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HQ_ERR_DEVICE, e.what());
+  }
+}
+
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a) { return std::chrono::duration<double>(clk::now() - a).count(); }
+
+// ---- host setup: alpha, l0, weights ---------------------------------------------------------
+
+// Number of eigenvalues below sigma: negative pivots of the symmetric elimination of A - sigma I,
+// carried as a sliding (b+1) x (b+1) trailing block (Sylvester's law of inertia).
+int64_t inertia_below(const double* ab, int64_t n, int b, int64_t ld, double sigma, double pivmin,
+                      std::vector<double>& S) {
+  int64_t neg = 0;
+  if (b > 63) throw std::runtime_error("inertia count supports b <= 63");
+  if (b == 1) {
+    double q = 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double e = i > 0 ? ab[1 + (i - 1) * ld] : 0.0;
+      q = (ab[i * ld] - sigma) - (i > 0 ? e * e / q : 0.0);
+      if (std::fabs(q) < pivmin) q = -pivmin;
+      neg += q < 0.0;
+    }
+    return neg;
+  }
+  const int w = b + 1;
+  S.assign((size_t)w * w, 0.0);  // S(r, c), r, c in window rows j..j+b (symmetric, lower used)
+  auto A = [&](int64_t i, int64_t j) -> double {  // i >= j, i - j <= b
+    return ab[(i - j) + j * ld] - (i == j ? sigma : 0.0);
+  };
+  for (int r = 0; r < w && r < n; ++r)
+    for (int c = 0; c <= r; ++c) S[r + (size_t)c * w] = A(r, c);
+  for (int64_t j = 0; j < n; ++j) {
+    double d = S[0];
+    if (std::fabs(d) < pivmin) d = -pivmin;
+    neg += d < 0.0;
+    const int act = (int)std::min<int64_t>(b, n - 1 - j);  // live rows below the pivot
+    // Schur update of the trailing block, shifted up-left by one
+    double col[64];
+    for (int r = 0; r < act; ++r) col[r] = S[r + 1];
+    for (int c = 0; c < act; ++c) {
+      const double lc = col[c] / d;
+      for (int r = c; r < act; ++r) S[r + (size_t)c * w] = S[(r + 1) + (size_t)(c + 1) * w] - col[r] * lc;
+    }
+    // new last row/col from A
+    if (j + 1 + b < n) {
+      const int64_t ni = j + 1 + b;
+      for (int c = 0; c <= b; ++c) S[b + (size_t)c * w] = (ni - (j + 1 + c) <= b) ? A(ni, j + 1 + c) : 0.0;
+    }
+  }
+  return neg;
+}
+
+double pivmin_of(const double* ab, int64_t n, int b, int64_t ld) {
+  double m = 1.0;
+  for (int64_t j = 0; j < n; ++j)
+    for (int i = 1; i <= b && j + i < n; ++i) m = std::max(m, ab[i + j * ld] * ab[i + j * ld]);
+  return 2.2250738585072014e-308 * m;
+}
+
+double norm_inf_shifted(const double* ab, int64_t n, int b, int64_t ld, double mu) {
+  std::vector<double> rs(n, 0.0);
+  for (int64_t j = 0; j < n; ++j) {
+    rs[j] += std::fabs(ab[j * ld] - mu);
+    for (int i = 1; i <= b && j + i < n; ++i) {
+      const double v = std::fabs(ab[i + j * ld]);
+      rs[j] += v;
+      rs[j + i] += v;
+    }
+  }
+  double m = 0.0;
+  for (double v : rs) m = std::max(m, v);
+  return m;
+}
+
+// Largest delta = alpha 2^-k with no eigenvalue in [mu - delta, mu + delta): a certified lower bound
+// of dist(mu, spectrum) within a factor of two.  Returns 0 if none down to 1e-15 alpha.
+double certified_distance(const double* ab, int64_t n, int b, int64_t ld, double mu, double alpha) {
+  const double pm = pivmin_of(ab, n, b, ld);
+  std::vector<double> S;
+  const int64_t nu = inertia_below(ab, n, b, ld, mu, pm, S);
+  const int K = 52;
+  std::vector<int> ok(K + 1, 0);
+  int found = -1;
+  for (int k0 = 1; k0 <= K && found < 0; k0 += 8) {
+    const int k1 = std::min(K, k0 + 7);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = k0; k <= k1; ++k) {
+      std::vector<double> SS;
+      const double d = std::ldexp(alpha, -k);
+      ok[k] = inertia_below(ab, n, b, ld, mu - d, pm, SS) == nu && inertia_below(ab, n, b, ld, mu + d, pm, SS) == nu;
+    }
+    for (int k = k0; k <= k1; ++k)
+      if (ok[k]) {
+        found = k;
+        break;
+      }
+  }
+  if (found < 0) return 0.0;
+  return std::ldexp(alpha, -found);
+}
+
+double h_of(double l) {
+  const double l2 = l * l;
+  const double g = std::cbrt(4.0 * (1.0 - l2) / (l2 * l2));
+  const double sg = std::sqrt(1.0 + g);
+  return sg + 0.5 * std::sqrt(8.0 - 4.0 * g + 8.0 * (2.0 - l2) / (l2 * sg));
+}
+
+struct Weights {
+  std::vector<double> a, b, c;
+  double lK;
+};
+Weights schedule(double l0, double delta, int max_iter) {
+  Weights w;
+  double l = l0;
+  while (std::fabs(1.0 - l) > delta && (int)w.a.size() < max_iter) {
+    const double a = h_of(l), b = (a - 1.0) * (a - 1.0) / 4.0, c = a + b - 1.0;
+    w.a.push_back(a);
+    w.b.push_back(b);
+    w.c.push_back(c);
+    l = l * (a + b * l * l) / (1.0 + c * l * l);
+    if (l > 1.0) l = 1.0;
+  }
+  w.lK = l;
+  return w;
+}
+
+// ---- helpers --------------------------------------------------------------------------------
+
+std::vector<int> caps_from(const hq::Tree& t, int v, int maxr) {
+  std::vector<int> c(t.L);
+  for (int l = 0; l < t.L; ++l) c[l] = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)v, (int64_t)maxr, t.ldf[l]}));
+  return c;
+}
+
+std::vector<int> caps_grow(const hq::Tree& t, const std::vector<int>& ranks, int maxr, int mult, int add) {
+  std::vector<int> c(t.L, 1);
+  for (int p = 0; p < t.ninternal; ++p) {
+    const int l = hq::Tree::level(p);
+    c[l] = std::max(c[l], std::max(ranks[2 * p], ranks[2 * p + 1]));
+  }
+  for (int l = 0; l < t.L; ++l)
+    c[l] = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)c[l] * mult + add, (int64_t)maxr, t.ldf[l]}));
+  return c;
+}
+
+int max_of(const std::vector<int>& v) {
+  int m = 0;
+  for (int x : v) m = std::max(m, x);
+  return m;
+}
+
+void upload_host(hq::Engine& e, const hq::HostHodlr& h, hq::HMat& H) {
+  const hq::Tree& t = *e.t;
+  HQ_CHECK(hipMemcpyAsync(H.leaves, h.leaves.data(), sizeof(double) * h.leaves.size(), hipMemcpyHostToDevice, e.st));
+  for (int l = 0; l < t.L; ++l) {
+    HQ_CHECK(hipMemcpyAsync(H.Ubase[l], h.U[l].data(), sizeof(double) * h.U[l].size(), hipMemcpyHostToDevice, e.st));
+    HQ_CHECK(hipMemcpyAsync(H.Vbase[l], h.V[l].data(), sizeof(double) * h.V[l].size(), hipMemcpyHostToDevice, e.st));
+  }
+  if (t.ninternal > 0)
+    HQ_CHECK(hipMemcpyAsync(H.rank, h.rank.data(), sizeof(int) * 2 * t.ninternal, hipMemcpyHostToDevice, e.st));
+  HQ_CHECK(hipStreamSynchronize(e.st));  // host buffers go out of scope
+}
+
+// X0 = (A - shift I) * inv_scale directly from the device band.
+void build_x0(hq::Engine& e, const double* band, int64_t n, int b, int64_t ldab, double shift, double inv_scale,
+              hq::HMat& X) {
+  const hq::Tree& t = *e.t;
+  hq::BandDesc bd{band, n, ldab, b, shift, inv_scale};
+  std::vector<int64_t> lo(t.nleaves);
+  std::vector<int> ms(t.nleaves);
+  for (int i = 0; i < t.nleaves; ++i) {
+    lo[i] = t.lo[t.ninternal + i];
+    ms[i] = (int)t.size(t.ninternal + i);
+  }
+  hq::launch_band_leaves(bd, X.leaves, X.ldl, e.stage.upload(lo, e.st), e.stage.upload(ms, e.st), t.nleaves, e.st);
+  std::vector<hq::BandBlockTask> bt;
+  int maxrows = 1;
+  for (int p = 0; p < t.ninternal; ++p) {
+    hq::BandBlockTask k{};
+    k.Ul = X.U(p, 1);
+    k.Vl = X.V(p, 1);
+    k.Uu = X.U(p, 0);
+    k.Vu = X.V(p, 0);
+    k.rank_l = X.rk(p, 1);
+    k.rank_u = X.rk(p, 0);
+    k.mid = t.mid(p);
+    k.rows_a = (int)t.size(2 * p + 1);
+    k.rows_b = (int)t.size(2 * p + 2);
+    k.ldf = X.ld(p);
+    maxrows = std::max({maxrows, k.rows_a, k.rows_b});
+    bt.push_back(k);
+  }
+  hq::launch_band_blocks(bd, e.stage.upload(bt, e.st), (int)bt.size(), maxrows, e.st);
+}
+
+// Copy H (engine E) into a fresh handle whose capacities equal the realised ranks.
+hq_hodlr_t compact_copy(hq::Engine& E, const hq::HMat& H, hipStream_t st, int leaf) {
+  std::unique_ptr<hq_hodlr_s> h(new hq_hodlr_s());
+  h->t.build(E.t->n, leaf);
+  const hq::Tree& t = h->t;
+  const std::vector<int> r = E.read_ranks(H);
+  std::vector<int> cap(t.L, 1);
+  for (int p = 0; p < t.ninternal; ++p) {
+    const int l = hq::Tree::level(p);
+    cap[l] = std::max(cap[l], std::max(r[2 * p], r[2 * p + 1]));
+  }
+  h->e.reset(new hq::Engine(st, &h->t));
+  h->e->tol = E.tol;
+  h->e->persist.chunk_bytes = std::max<size_t>(size_t(1) << 20, H.bytes() + (size_t(4) << 20));
+  h->H = h->e->alloc_hmat(cap, H.lower_only);
+  HQ_CHECK(hipMemcpy2DAsync(h->H.leaves, sizeof(double) * h->H.ldl, H.leaves, sizeof(double) * H.ldl,
+                            sizeof(double) * H.ldl, (size_t)t.nleaves * H.ldl, hipMemcpyDeviceToDevice, st));
+  std::vector<hq::StackTask> cp;
+  int maxrows = 1;
+  for (int p = 0; p < t.ninternal; ++p)
+    for (int s = 0; s < 2; ++s)
+      for (int uv = 0; uv < 2; ++uv) {
+        const int rows = (int)((uv == 0) == (s == 0) ? t.size(2 * p + 1) : t.size(2 * p + 2));
+        hq::StackTask k{};
+        k.dst = uv == 0 ? h->H.U(p, s) : h->H.V(p, s);
+        k.ld = h->H.ld(p);
+        k.rows = rows;
+        k.wcap = h->H.capof(p);
+        k.wout = uv == 0 ? h->H.rk(p, s) : nullptr;
+        k.nsrc = 1;
+        k.src[0] = {uv == 0 ? H.U(p, s) : H.V(p, s), H.rk(p, s), H.ld(p), H.capof(p), 1.0};
+        cp.push_back(k);
+        maxrows = std::max(maxrows, rows);
+      }
+  if (!cp.empty()) h->e->stack(cp, maxrows);
+  HQ_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
+  h->d_w = h->e->persist.get<int>(1);
+  HQ_CHECK(hipStreamSynchronize(st));
+  h->e->stage.reset();
+  return h.release();
+}
+
+hq_status check_opts(const hq_opts* o, hq_opts& out) {
+  hq_default_opts(&out);
+  if (o) out = *o;
+  if (out.leaf < 2) return fail(HQ_ERR_ARG, "opts.leaf must be >= 2");
+  if (!(out.tol > 0.0)) return fail(HQ_ERR_ARG, "opts.tol must be > 0");
+  if (!(out.delta > 0.0)) return fail(HQ_ERR_ARG, "opts.delta must be > 0");
+  if (out.max_rank < 1) return fail(HQ_ERR_ARG, "opts.max_rank must be >= 1");
+  if (out.max_iter < 1 || out.max_iter > 16) return fail(HQ_ERR_ARG, "opts.max_iter must be in [1, 16]");
+  return HQ_OK;
+}
+
+hq_status check_band(const double* band, int64_t n, int32_t b, int64_t ldab) {
+  if (!band) return fail(HQ_ERR_ARG, "band is NULL");
+  if (n < 1) return fail(HQ_ERR_ARG, "n must be >= 1");
+  if (b < 1) return fail(HQ_ERR_ARG, "b must be >= 1");
+  if (ldab < b + 1) return fail(HQ_ERR_ARG, "ldab must be >= b+1");
+  return HQ_OK;
+}
+
+// ---- the hQDWH driver -----------------------------------------------------------------------
+hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu, const hq_opts& o, hipStream_t st,
+                   bool projector, hq_hodlr_t* out, hq_info* info) {
+  const auto t0 = clk::now();
+  hq_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  hq::Tree t;
+  t.build(n, o.leaf);
+  if (t.L > 0 && (int64_t)b > n / (int64_t(1) << t.L))
+    return fail(HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block; raise opts.leaf");
+  const int beff = (int)std::min<int64_t>(b, std::max<int64_t>(1, n - 1));
+  // host copy of the band for the scalar setup and the Givens sweep
+  std::vector<double> ab((size_t)n * ldab);
+  HQ_CHECK(hipMemcpyAsync(ab.data(), band, sizeof(double) * ab.size(), hipMemcpyDeviceToHost, st));
+  HQ_CHECK(hipStreamSynchronize(st));
+  // Alg. 3 line 1: alpha >= ||A - mu I||_2 and l0 <= sigma_min(X0)
+  const double alpha = norm_inf_shifted(ab.data(), n, beff, ldab, mu);
+  if (!(alpha > 0.0)) return fail(HQ_ERR_SINGULAR_SHIFT, "A - mu I is zero");
+  const double dist = certified_distance(ab.data(), n, beff, ldab, mu, alpha);
+  if (!(dist > 0.0)) return fail(HQ_ERR_SINGULAR_SHIFT, "mu is numerically an eigenvalue of A");
+  const double l0 = dist / alpha;
+  const Weights w = schedule(l0, o.delta, o.max_iter);
+  if (std::fabs(1.0 - w.lK) > o.delta) return fail(HQ_ERR_NO_CONVERGENCE, "weight recurrence did not reach 1 - delta");
+  const int K = (int)w.a.size();
+  inf.alpha = alpha;
+  inf.l0 = l0;
+  inf.iters = K;
+  for (int k = 0; k < K && k < 16; ++k) {
+    inf.a[k] = w.a[k];
+    inf.b[k] = w.b[k];
+    inf.c[k] = w.c[k];
+  }
+  inf.setup_seconds = secs(t0);
+
+  hq::Engine E(st, &t);
+  E.tol = o.tol;
+  hq::DevArena xa[2], it;
+  auto alloc = [&](hq::DevArena& ar, const std::vector<int>& cap, bool lower) {
+    std::swap(E.persist, ar);
+    hq::HMat h = E.alloc_hmat(cap, lower);
+    std::swap(E.persist, ar);
+    return h;
+  };
+  // X0
+  hq::HMat X = alloc(xa[0], caps_from(t, beff, o.max_rank), false);
+  build_x0(E, band, n, beff, ldab, mu, 1.0 / alpha, X);
+  int cur = 0;
+  size_t peak = 0;
+  for (int k = 0; k < K; ++k) {
+    const double a = w.a[k], bb = w.b[k], c = w.c[k];
+    std::vector<int> capX;
+    if (k == 0) {
+      capX = caps_from(t, 3 * beff + 8, o.max_rank);
+    } else {
+      capX = caps_grow(t, E.read_ranks(X), o.max_rank, 2, 16);
+    }
+    for (int attempt = 0;; ++attempt) {
+      E.stage.reset();
+      E.scratch.reset();
+      xa[cur ^ 1].reset();
+      it.reset();
+      hq::HMat Xn = alloc(xa[cur ^ 1], capX, false);
+      E.clear_flag();
+      if (k == 0) {
+        // Alg. 3 lines 7-9: structured QR of [sqrt(c0) X0; I], Q1/Q2 in HODLR, X1
+        const auto tg = clk::now();
+        const hq::GivensSweep gs = hq::structured_qr(ab.data(), n, beff, ldab, mu, std::sqrt(c) / alpha);
+        const std::vector<int> capQ(t.L, 2 * beff);
+        hq::HostHodlr h1, h2;
+        hq::q_factors_hodlr(gs, t, beff, capQ, (int)t.maxleaf, h1, h2);
+        hq::HMat Q1 = alloc(it, capQ, false), Q2 = alloc(it, capQ, false);
+        upload_host(E, h1, Q1);
+        upload_host(E, h2, Q2);
+        inf.givens_seconds = secs(tg);
+        const hq::HView Xv = E.view(X);
+        E.product(E.view(Q1), E.view(Q2, true), &Xv, false, (a - bb / c) / std::sqrt(c), bb / c, Xn);
+      } else {
+        // Alg. 3 lines 11-14: W = chol(I + c X^T X); Y W = X; V W^T = Y; X+ = b/c X + (a - b/c) V
+        hq::HMat Z = alloc(it, capX, true), Linv = alloc(it, capX, false), Lf = alloc(it, capX, false);
+        hq::HMat Y = alloc(it, capX, false);
+        E.product(E.view(X, true), E.view(X), nullptr, true, c, 1.0, Z);
+        E.scratch.reset();
+        E.cholesky_inverse(Z, Linv, Lf, 2 * max_of(capX) + 16);
+        E.scratch.reset();
+        E.product(E.view(X), E.view(Linv, true), nullptr, false, 1.0, 0.0, Y);  // Y = X L^{-T} = X W^{-1}
+        E.scratch.reset();
+        const hq::HView Xv = E.view(X);
+        E.product(E.view(Y), E.view(Linv), &Xv, false, a - bb / c, bb / c, Xn);  // V = Y L^{-1} = Y W^{-T}
+      }
+      peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + xa[0].high_water() +
+                                xa[1].high_water() + it.high_water());
+      const int f = E.read_flag();
+      if (f & 2) return fail(HQ_ERR_NOT_POSDEF, "a leaf of I + c X^T X is not positive definite");
+      if (f & 5) {
+        bool grown = false;
+        for (int l = 0; l < t.L; ++l) {
+          const int nc = (int)std::min<int64_t>({(int64_t)capX[l] * 2, (int64_t)o.max_rank, t.ldf[l]});
+          grown |= nc > capX[l];
+          capX[l] = nc;
+        }
+        if (!grown || attempt > 6) return fail(HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
+        ++inf.redo_count;
+        continue;
+      }
+      X = Xn;
+      cur ^= 1;
+      break;
+    }
+    if (k < 16) inf.max_rank_iter[k] = max_of(E.read_ranks(X));
+  }
+  // Alg. 3 lines 17-18: U = X_K (symmetrised), P = (I - U)/2
+  E.stage.reset();
+  E.scratch.reset();
+  it.reset();
+  const std::vector<int> capP = caps_grow(t, E.read_ranks(X), o.max_rank, 1, 0);
+  hq::HMat P = alloc(it, capP, false);
+  E.sym_affine(X, P, projector ? -0.5 : 1.0, projector ? 0.5 : 0.0);
+  E.clear_flag();
+  const int f = E.read_flag();
+  (void)f;
+  hq_hodlr_t h = compact_copy(E, P, st, o.leaf);
+  inf.max_rank = max_of(E.read_ranks(P));
+  inf.bytes = (int64_t)h->H.bytes();
+  inf.peak_bytes = (int64_t)peak;
+  inf.launches = E.launches;
+  inf.seconds = secs(t0);
+  *out = h;
+  if (info) *info = inf;
+  return HQ_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+hq_status hq_default_opts(hq_opts* o) {
+  if (!o) return fail(HQ_ERR_ARG, "opts is NULL");
+  o->leaf = 256;
+  o->tol = 1e-10;
+  o->delta = 1e-15;
+  o->max_rank = 512;
+  o->max_iter = 10;
+  return HQ_OK;
+}
+
+const char* hq_last_error(void) { return g_err.c_str(); }
+
+const char* hq_status_string(hq_status s) {
+  switch (s) {
+    case HQ_OK: return "ok";
+    case HQ_ERR_ARG: return "invalid argument";
+    case HQ_ERR_ALLOC: return "allocation failed";
+    case HQ_ERR_DEVICE: return "device error";
+    case HQ_ERR_UNSUPPORTED: return "unsupported";
+    case HQ_ERR_SINGULAR_SHIFT: return "shift is an eigenvalue";
+    case HQ_ERR_NOT_POSDEF: return "not positive definite";
+    case HQ_ERR_NO_CONVERGENCE: return "no convergence";
+    case HQ_ERR_RANK_OVERFLOW: return "rank overflow";
+  }
+  return "unknown status";
+}
+
+hq_status hodlr_build(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
+                      const hq_opts* opts, void* stream, hq_hodlr_t* out) {
+  if (!out) return fail(HQ_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  hq_opts o;
+  hq_status s = check_opts(opts, o);
+  if (s) return s;
+  if ((s = check_band(band, n, b, ldab))) return s;
+  if (!(scale != 0.0)) return fail(HQ_ERR_ARG, "scale must be nonzero");
+  return guard([&]() -> hq_status {
+    std::unique_ptr<hq_hodlr_s> h(new hq_hodlr_s());
+    h->t.build(n, o.leaf);
+    if (h->t.L > 0 && (int64_t)b > n / (int64_t(1) << h->t.L))
+      return fail(HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block");
+    hipStream_t st = (hipStream_t)stream;
+    h->e.reset(new hq::Engine(st, &h->t));
+    h->H = h->e->alloc_hmat(caps_from(h->t, b, 1 << 30), false);
+    build_x0(*h->e, band, n, b, ldab, shift, 1.0 / scale, h->H);
+    HQ_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
+    h->d_w = h->e->persist.get<int>(1);
+    HQ_CHECK(hipEventRecord(h->done, st));
+    *out = h.release();
+    return HQ_OK;
+  });
+}
+
+hq_status qdwh_sign(const double* band, int64_t n, int32_t b, int64_t ldab, double mu, const hq_opts* opts,
+                    void* stream, hq_hodlr_t* sign_out, hq_info* info) {
+  if (!sign_out) return fail(HQ_ERR_ARG, "sign_out is NULL");
+  *sign_out = nullptr;
+  hq_opts o;
+  hq_status s = check_opts(opts, o);
+  if (s) return s;
+  if ((s = check_band(band, n, b, ldab))) return s;
+  return guard([&] { return run_qdwh(band, n, b, ldab, mu, o, (hipStream_t)stream, false, sign_out, info); });
+}
+
+hq_status spectral_projector(const double* band, int64_t n, int32_t b, int64_t ldab, double mu,
+                             const hq_opts* opts, void* stream, hq_hodlr_t* P_out, hq_info* info) {
+  if (!P_out) return fail(HQ_ERR_ARG, "P_out is NULL");
+  *P_out = nullptr;
+  hq_opts o;
+  hq_status s = check_opts(opts, o);
+  if (s) return s;
+  if ((s = check_band(band, n, b, ldab))) return s;
+  return guard([&] { return run_qdwh(band, n, b, ldab, mu, o, (hipStream_t)stream, true, P_out, info); });
+}
+
+hq_status apply_projector(hq_hodlr_t P, const double* X, int64_t ldx, int32_t ncols, double* Y, int64_t ldy,
+                          void* stream) {
+  if (!P) return fail(HQ_ERR_ARG, "P is NULL");
+  if (ncols < 0) return fail(HQ_ERR_ARG, "ncols < 0");
+  if (ncols == 0) return HQ_OK;
+  if (!X || !Y) return fail(HQ_ERR_ARG, "X or Y is NULL");
+  if (ldx < P->t.n || ldy < P->t.n) return fail(HQ_ERR_ARG, "ldx/ldy < n");
+  return guard([&]() -> hq_status {
+    hq::Engine& e = *P->e;
+    HQ_CHECK(hipEventSynchronize(P->done));  // previous call's staging buffers are free again
+    e.st = (hipStream_t)stream;
+    e.stage.reset();
+    e.scratch.reset();
+    hq::launch_fill_int(P->d_w, ncols, 1, e.st);
+    e.mm_thin({hq::Engine::ThinTask{e.view(P->H), 0, X, (int)ldx, Y, (int)ldy, P->d_w, ncols, 1.0, 0.0}});
+    HQ_CHECK(hipEventRecord(P->done, e.st));
+    return HQ_OK;
+  });
+}
+
+hq_status hodlr_to_dense(hq_hodlr_t H, double* out, int64_t ld, void* stream) {
+  if (!H || !out) return fail(HQ_ERR_ARG, "NULL argument");
+  const int64_t n = H->t.n;
+  if (ld < n) return fail(HQ_ERR_ARG, "ld < n");
+  return guard([&]() -> hq_status {
+    hq::Engine& e = *H->e;
+    HQ_CHECK(hipEventSynchronize(H->done));
+    e.st = (hipStream_t)stream;
+    e.stage.reset();
+    e.scratch.reset();
+    double* I = e.scratch.get<double>((size_t)n * n);
+    std::vector<hq::LeafAxpy> id(1);
+    // identity via the leaf kernel over one n x n tile
+    id[0] = hq::LeafAxpy{};
+    id[0].out = I; id[0].ldo = (int)n; id[0].m = (int)n; id[0].gamma = 1.0; id[0].X = I; id[0].ldx = (int)n;
+    hq::launch_leaf_axpy(e.stage.upload(id, e.st), 1, (int)n, e.st);
+    hq::launch_fill_int(H->d_w, (int)n, 1, e.st);
+    e.mm_thin({hq::Engine::ThinTask{e.view(H->H), 0, I, (int)n, out, (int)ld, H->d_w, (int)n, 1.0, 0.0}});
+    HQ_CHECK(hipEventRecord(H->done, e.st));
+    HQ_CHECK(hipStreamSynchronize(e.st));
+    return HQ_OK;
+  });
+}
+
+hq_status hodlr_shape(hq_hodlr_t H, int64_t* n, int32_t* levels, int32_t* nleaves, int32_t* max_rank) {
+  if (!H) return fail(HQ_ERR_ARG, "H is NULL");
+  return guard([&]() -> hq_status {
+    if (n) *n = H->t.n;
+    if (levels) *levels = H->t.L;
+    if (nleaves) *nleaves = H->t.nleaves;
+    if (max_rank) {
+      HQ_CHECK(hipEventSynchronize(H->done));
+      *max_rank = max_of(H->e->read_ranks(H->H));
+    }
+    return HQ_OK;
+  });
+}
+
+hq_status hodlr_get_leaf(hq_hodlr_t H, int32_t i, double* out, int64_t ld, int64_t* lo, int64_t* m) {
+  if (!H) return fail(HQ_ERR_ARG, "H is NULL");
+  if (i < 0 || i >= H->t.nleaves) return fail(HQ_ERR_ARG, "leaf index out of range");
+  return guard([&]() -> hq_status {
+    const int p = H->t.ninternal + i;
+    const int64_t mm = H->t.size(p);
+    if (lo) *lo = H->t.lo[p];
+    if (m) *m = mm;
+    if (out) {
+      if (ld < mm) return fail(HQ_ERR_ARG, "ld < m");
+      HQ_CHECK(hipEventSynchronize(H->done));
+      HQ_CHECK(hipMemcpy2D(out, sizeof(double) * ld, H->H.leaf(i), sizeof(double) * H->H.ldl, sizeof(double) * mm, mm,
+                           hipMemcpyDeviceToHost));
+    }
+    return HQ_OK;
+  });
+}
+
+hq_status hodlr_get_block(hq_hodlr_t H, int32_t node, int32_t which, double* U, double* V, int64_t ld,
+                          int32_t* rank, int64_t* lo, int64_t* mid, int64_t* hi) {
+  if (!H) return fail(HQ_ERR_ARG, "H is NULL");
+  if (node < 0 || node >= H->t.ninternal) return fail(HQ_ERR_ARG, "node out of range");
+  if (which != 0 && which != 1) return fail(HQ_ERR_ARG, "which must be 0 or 1");
+  return guard([&]() -> hq_status {
+    const hq::Tree& t = H->t;
+    if (lo) *lo = t.lo[node];
+    if (mid) *mid = t.mid(node);
+    if (hi) *hi = t.hi[node];
+    HQ_CHECK(hipEventSynchronize(H->done));
+    int r = 0;
+    HQ_CHECK(hipMemcpy(&r, H->H.rk(node, which), sizeof(int), hipMemcpyDeviceToHost));
+    if (rank) *rank = r;
+    const int64_t ma = t.size(2 * node + 1), mb = t.size(2 * node + 2);
+    const int64_t ru = which == 0 ? ma : mb, rv = which == 0 ? mb : ma;
+    if ((U || V) && ld < std::max(ru, rv)) return fail(HQ_ERR_ARG, "ld too small");
+    if (U && r > 0)
+      HQ_CHECK(hipMemcpy2D(U, sizeof(double) * ld, H->H.U(node, which), sizeof(double) * H->H.ld(node),
+                           sizeof(double) * ru, r, hipMemcpyDeviceToHost));
+    if (V && r > 0)
+      HQ_CHECK(hipMemcpy2D(V, sizeof(double) * ld, H->H.V(node, which), sizeof(double) * H->H.ld(node),
+                           sizeof(double) * rv, r, hipMemcpyDeviceToHost));
+    return HQ_OK;
+  });
+}
+
+hq_status hq_shift_for_count(const double* band, int64_t n, int32_t b, int64_t ldab, int64_t nu, double* mu,
+                             double* gap) {
+  hq_status s = check_band(band, n, b, ldab);
+  if (s) return s;
+  if (nu < 1 || nu >= n) return fail(HQ_ERR_ARG, "nu must satisfy 1 <= nu < n");
+  if (!mu) return fail(HQ_ERR_ARG, "mu is NULL");
+  return guard([&]() -> hq_status {
+    const double an = norm_inf_shifted(band, n, b, ldab, 0.0);
+    const double pm = pivmin_of(band, n, b, ldab);
+    double lam[2];
+#pragma omp parallel for
+    for (int j = 0; j < 2; ++j) {
+      std::vector<double> S;
+      double lo = -an - 1.0, hi = an + 1.0;
+      const int64_t k = nu + j;  // lambda_k, 1-based
+      for (int it = 0; it < 200; ++it) {
+        const double m = 0.5 * (lo + hi);
+        if (m <= lo || m >= hi) break;
+        if (inertia_below(band, n, b, ldab, m, pm, S) >= k) hi = m;
+        else lo = m;
+      }
+      lam[j] = 0.5 * (lo + hi);
+    }
+    *mu = 0.5 * (lam[0] + lam[1]);
+    if (gap) *gap = lam[1] - lam[0];
+    return HQ_OK;
+  });
+}
+
+void hodlr_destroy(hq_hodlr_t H) {
+  if (!H) return;
+  if (H->done) (void)hipEventSynchronize(H->done);
+  delete H;
+}
+
+// ---- test hooks -------------------------------------------------------------------------------
+hq_status hq_test_gemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k, int32_t lda,
+                       int32_t ldb, int32_t ldc, int32_t opA, int32_t opB, double alpha, double beta, void* stream) {
+  if (!A || !B || !C || m < 0 || n < 0 || k < 0) return fail(HQ_ERR_ARG, "bad gemm arguments");
+  return guard([&]() -> hq_status {
+    hq::Tree t;
+    t.build(1, 2);
+    hq::Engine e((hipStream_t)stream, &t);
+    hq::GemmTask g{};
+    g.A = A; g.B = B; g.C = C; g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.opA = opA; g.opB = opB; g.alpha = alpha; g.beta = beta;
+    e.gemm({g}, m, n);
+    HQ_CHECK(hipStreamSynchronize(e.st));
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, double* R, void* stream) {
+  if (!M || !R || rows < 1 || r < 1 || ldm < rows) return fail(HQ_ERR_ARG, "bad qr arguments");
+  return guard([&]() -> hq_status {
+    hq::Tree t;
+    t.build(1, 2);
+    hq::Engine e((hipStream_t)stream, &t);
+    int* dr = e.scratch.get<int>(1);
+    hq::launch_fill_int(dr, r, 1, e.st);
+    // reuse compress_sym's QR stage through a recompress with V = nothing: run QR directly
+    double* out = e.scratch.get<double>((size_t)rows * r);
+    int* kk = e.scratch.get<int>(1);
+    (void)out;
+    (void)kk;
+    // R-only TSQR via the same plan as recompress
+    const int rc = r;
+    const int hmin = std::max(256, 2 * rc);
+    hq::QrTask q{};
+    q.M = M; q.ldm = ldm; q.rows = rows; q.rp = dr; q.rcap = rc; q.R = R; q.ldr = rc;
+    if (rows <= hmin) { q.h0 = q.hs = rows; q.ntiles = 1; }
+    else { q.h0 = q.hs = (hmin + 63) / 64 * 64; q.ntiles = (rows + q.h0 - 1) / q.h0; }
+    q.work = e.scratch.get<double>((size_t)q.ntiles * q.hs * rc);
+    hq::QrTask* dq = e.stage.upload(std::vector<hq::QrTask>{q}, e.st);
+    int nst = 0;
+    while ((1 << nst) < q.ntiles) ++nst;
+    for (int s = 0; s <= nst; ++s) hq::launch_qr_stage(dq, 1, s, (q.ntiles + (1 << s) - 1) >> s, q.hs, rc, e.st);
+    hq::launch_qr_final(dq, 1, rc, e.st);
+    HQ_CHECK(hipStreamSynchronize(e.st));
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_recompress(const double* Us, int32_t m, const double* Vs, int32_t n, int32_t r, double tol,
+                             int32_t kcap, double* U, double* V, int32_t* k, void* stream) {
+  if (!Us || !Vs || !U || !V || !k || m < 1 || n < 1 || r < 0 || kcap < 1) return fail(HQ_ERR_ARG, "bad arguments");
+  return guard([&]() -> hq_status {
+    hq::Tree t;
+    t.build(1, 2);
+    hq::Engine e((hipStream_t)stream, &t);
+    e.tol = tol;
+    int* dr = e.scratch.get<int>(2);
+    hq::launch_fill_int(dr, r, 1, e.st);
+    hq::Engine::RecTask rt{};
+    rt.Us = Us; rt.ldus = m; rt.m = m; rt.Vs = Vs; rt.ldvs = n; rt.n = n; rt.r = dr; rt.rcap = std::max(r, 1);
+    rt.U = U; rt.V = V; rt.ldu = m; rt.ldv = n; rt.rank = dr + 1; rt.kcap = kcap; rt.thresh = tol;
+    e.recompress({rt});
+    HQ_CHECK(hipMemcpyAsync(k, dr + 1, sizeof(int), hipMemcpyDeviceToHost, e.st));
+    HQ_CHECK(hipStreamSynchronize(e.st));
+    return (e.read_flag() & 1) ? fail(HQ_ERR_RANK_OVERFLOW, "rank above kcap") : HQ_OK;
+  });
+}
+
+hq_status hq_test_from_dense(const double* dense, int64_t n, int64_t ld, const hq_opts* opts, int32_t cap,
+                             void* stream, hq_hodlr_t* out) {
+  if (!out) return fail(HQ_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  hq_opts o;
+  hq_status s = check_opts(opts, o);
+  if (s) return s;
+  if (!dense || n < 1 || ld < n || cap < 1) return fail(HQ_ERR_ARG, "bad arguments");
+  return guard([&]() -> hq_status {
+    std::unique_ptr<hq_hodlr_s> h(new hq_hodlr_s());
+    h->t.build(n, o.leaf);
+    const hq::Tree& t = h->t;
+    if (t.L > 0 && t.ldf[0] > 2048) return fail(HQ_ERR_UNSUPPORTED, "test compression limited to n <= 4096");
+    hipStream_t st = (hipStream_t)stream;
+    h->e.reset(new hq::Engine(st, &t));
+    hq::Engine& e = *h->e;
+    e.tol = o.tol;
+    h->H = e.alloc_hmat(caps_from(t, cap, 1 << 30), false);
+    // leaves
+    for (int i = 0; i < t.nleaves; ++i) {
+      const int p = t.ninternal + i;
+      const int64_t lo = t.lo[p], m = t.size(p);
+      HQ_CHECK(hipMemcpy2DAsync(h->H.leaf(i), sizeof(double) * h->H.ldl, dense + lo + lo * ld, sizeof(double) * ld,
+                                sizeof(double) * m, m, hipMemcpyDeviceToDevice, st));
+    }
+    // off-diagonal blocks: Us = block (rows x cols), Vs = I (cols x cols)
+    std::vector<hq::Engine::RecTask> rec;
+    int64_t maxc = 1;
+    for (int p = 0; p < t.ninternal; ++p) maxc = std::max(maxc, std::max(t.size(2 * p + 1), t.size(2 * p + 2)));
+    double* I = e.scratch.get<double>((size_t)maxc * maxc);
+    std::vector<hq::LeafAxpy> id(1);
+    id[0] = hq::LeafAxpy{};
+    id[0].out = I; id[0].ldo = (int)maxc; id[0].m = (int)maxc; id[0].gamma = 1.0; id[0].X = I; id[0].ldx = (int)maxc;
+    hq::launch_leaf_axpy(e.stage.upload(id, st), 1, (int)maxc, st);
+    std::vector<int> widths;
+    int* dw = e.scratch.get<int>(2 * std::max(1, t.ninternal));
+    std::vector<int> hw(2 * std::max(1, t.ninternal));
+    for (int p = 0; p < t.ninternal; ++p)
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int a = 2 * p + 1, b = 2 * p + 2;
+        const int64_t r0 = s2 == 0 ? t.lo[a] : t.lo[b], c0 = s2 == 0 ? t.lo[b] : t.lo[a];
+        const int64_t mr = s2 == 0 ? t.size(a) : t.size(b), mc = s2 == 0 ? t.size(b) : t.size(a);
+        hw[2 * p + s2] = (int)mc;
+        hq::Engine::RecTask rt{};
+        rt.Us = dense + r0 + c0 * ld; rt.ldus = (int)ld; rt.m = (int)mr;
+        rt.Vs = I; rt.ldvs = (int)maxc; rt.n = (int)mc;
+        rt.r = dw + 2 * p + s2; rt.rcap = (int)mc;
+        rt.U = h->H.U(p, s2); rt.V = h->H.V(p, s2); rt.ldu = rt.ldv = h->H.ld(p);
+        rt.rank = h->H.rk(p, s2); rt.kcap = h->H.capof(p); rt.thresh = o.tol;
+        rec.push_back(rt);
+      }
+    HQ_CHECK(hipMemcpyAsync(dw, hw.data(), sizeof(int) * hw.size(), hipMemcpyHostToDevice, st));
+    e.recompress(rec);
+    HQ_CHECK(hipStreamSynchronize(st));
+    if (e.read_flag() & 1) return fail(HQ_ERR_RANK_OVERFLOW, "rank above cap");
+    HQ_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
+    h->d_w = e.persist.get<int>(1);
+    e.stage.reset();
+    *out = h.release();
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_product(hq_hodlr_t A, int32_t transA, hq_hodlr_t B, int32_t transB, double alpha, hq_hodlr_t D,
+                          int32_t d_identity, double delta, int32_t lower_only, int32_t cap, double tol, void* stream,
+                          hq_hodlr_t* out) {
+  if (!out) return fail(HQ_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!A || !B) return fail(HQ_ERR_ARG, "A or B is NULL");
+  if (A->t.n != B->t.n || A->t.leaf != B->t.leaf) return fail(HQ_ERR_ARG, "A and B differ in structure");
+  if (D && (D->t.n != A->t.n || D->t.leaf != A->t.leaf)) return fail(HQ_ERR_ARG, "D differs in structure");
+  return guard([&]() -> hq_status {
+    hipStream_t st = (hipStream_t)stream;
+    HQ_CHECK(hipEventSynchronize(A->done));
+    HQ_CHECK(hipEventSynchronize(B->done));
+    hq::Engine E(st, &A->t);
+    E.tol = tol;
+    hq::HMat C = E.alloc_hmat(caps_from(A->t, cap, 1 << 30), lower_only != 0);
+    hq::HView dv;
+    if (D) dv = E.view(D->H);
+    E.product(E.view(A->H, transA != 0), E.view(B->H, transB != 0), D ? &dv : nullptr, d_identity != 0, alpha,
+              delta, C);
+    if (E.read_flag() & 5) return fail(HQ_ERR_RANK_OVERFLOW, "rank above cap");
+    *out = compact_copy(E, C, st, A->t.leaf);
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_cholesky_inverse(hq_hodlr_t Z, int32_t cap, double tol, void* stream, hq_hodlr_t* out) {
+  if (!out) return fail(HQ_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!Z) return fail(HQ_ERR_ARG, "Z is NULL");
+  return guard([&]() -> hq_status {
+    hipStream_t st = (hipStream_t)stream;
+    HQ_CHECK(hipEventSynchronize(Z->done));
+    hq::Engine E(st, &Z->t);
+    E.tol = tol;
+    const std::vector<int> c = caps_from(Z->t, cap, 1 << 30);
+    hq::HMat Linv = E.alloc_hmat(c, false), Lf = E.alloc_hmat(c, false);
+    hq::HMat Zs = Z->H;
+    Zs.lower_only = true;
+    E.cholesky_inverse(Zs, Linv, Lf, 2 * cap + 16);
+    const int f = E.read_flag();
+    if (f & 2) return fail(HQ_ERR_NOT_POSDEF, "not positive definite");
+    if (f & 5) return fail(HQ_ERR_RANK_OVERFLOW, "rank above cap");
+    *out = compact_copy(E, Linv, st, Z->t.leaf);
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
+                            int32_t leaf, void* stream, hq_hodlr_t* q1, hq_hodlr_t* q2, int64_t* nrot) {
+  if (!q1 || !q2) return fail(HQ_ERR_ARG, "output NULL");
+  *q1 = *q2 = nullptr;
+  hq_status s = check_band(band, n, b, ldab);
+  if (s) return s;
+  if (leaf < 2) return fail(HQ_ERR_ARG, "leaf < 2");
+  return guard([&]() -> hq_status {
+    hipStream_t st = (hipStream_t)stream;
+    hq::Tree t;
+    t.build(n, leaf);
+    if (t.L > 0 && (int64_t)b > n / (int64_t(1) << t.L)) return fail(HQ_ERR_UNSUPPORTED, "b > smallest leaf");
+    const hq::GivensSweep gs = hq::structured_qr(band, n, b, ldab, shift, scale);
+    if (nrot) *nrot = (int64_t)gs.rots.size();
+    const std::vector<int> capQ(t.L, 2 * b);
+    hq::HostHodlr h1, h2;
+    hq::q_factors_hodlr(gs, t, b, capQ, (int)t.maxleaf, h1, h2);
+    hq::Engine E(st, &t);
+    hq::HMat Q1 = E.alloc_hmat(capQ, false), Q2 = E.alloc_hmat(capQ, false);
+    upload_host(E, h1, Q1);
+    upload_host(E, h2, Q2);
+    *q1 = compact_copy(E, Q1, st, leaf);
+    *q2 = compact_copy(E, Q2, st, leaf);
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
+                               int32_t leaf, double* Q1, double* Q2, int64_t* nrot) {
+  hq_status s = check_band(band, n, b, ldab);
+  if (s) return s;
+  if (!Q1 || !Q2 || leaf < 2) return fail(HQ_ERR_ARG, "bad arguments");
+  return guard([&]() -> hq_status {
+    hq::Tree t;
+    t.build(n, leaf);
+    if (t.L > 0 && (int64_t)b > n / (int64_t(1) << t.L)) return fail(HQ_ERR_UNSUPPORTED, "b > smallest leaf");
+    const hq::GivensSweep gs = hq::structured_qr(band, n, b, ldab, shift, scale);
+    if (nrot) *nrot = (int64_t)gs.rots.size();
+    const std::vector<int> cap(t.L, 2 * b);
+    hq::HostHodlr h[2];
+    const int ldl = (int)t.maxleaf;
+    hq::q_factors_hodlr(gs, t, b, cap, ldl, h[0], h[1]);
+    for (int w = 0; w < 2; ++w) {
+      double* Q = w == 0 ? Q1 : Q2;
+      std::fill(Q, Q + n * n, 0.0);
+      for (int i = 0; i < t.nleaves; ++i) {
+        const int p = t.ninternal + i;
+        const int64_t lo = t.lo[p], m = t.size(p);
+        for (int64_t c = 0; c < m; ++c)
+          for (int64_t r = 0; r < m; ++r) Q[(lo + r) + (lo + c) * n] = h[w].leaves[(size_t)i * ldl * ldl + r + c * ldl];
+      }
+      for (int p = 0; p < t.ninternal; ++p) {
+        const int l = hq::Tree::level(p), i = p - ((1 << l) - 1);
+        const int64_t ld = t.ldf[l];
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int a = 2 * p + 1, bb = 2 * p + 2;
+          const int64_t r0 = s2 == 0 ? t.lo[a] : t.lo[bb], c0 = s2 == 0 ? t.lo[bb] : t.lo[a];
+          const int64_t mr = s2 == 0 ? t.size(a) : t.size(bb), mc = s2 == 0 ? t.size(bb) : t.size(a);
+          const double* U = h[w].U[l].data() + (size_t)(2 * i + s2) * ld * cap[l];
+          const double* V = h[w].V[l].data() + (size_t)(2 * i + s2) * ld * cap[l];
+          const int rk = h[w].rank[2 * p + s2];
+          for (int64_t c = 0; c < mc; ++c)
+            for (int64_t r = 0; r < mr; ++r) {
+              double v = 0.0;
+              for (int k = 0; k < rk; ++k) v += U[r + k * ld] * V[c + k * ld];
+              Q[(r0 + r) + (c0 + c) * n] = v;
+            }
+        }
+      }
+    }
+    return HQ_OK;
+  });
+}
+
+}  // extern "C"

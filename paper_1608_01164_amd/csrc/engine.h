@@ -1,0 +1,177 @@
+// HODLR engine: cluster tree, device storage of HODLR matrices, and the formatted operations of
+// the QDWH iteration (Sec. 3.1.1 of the paper: products with recompression, Cholesky, triangular
+// solves), issued as batched kernel launches on one HIP stream.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace hq {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+#define HQ_CHECK(x)                                                                              \
+  do {                                                                                           \
+    hipError_t e_ = (x);                                                                         \
+    if (e_ != hipSuccess) throw ::hq::HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Binary cluster tree in heap order: node 0 is [0, n); node p splits [lo, hi) at
+// lo + ceil((hi - lo)/2) into children 2p+1, 2p+2.  All leaves sit at level L, the smallest
+// level whose blocks have at most `leaf` rows (Sec. 3.1.1: stop once n/2^l <= n_min).
+struct Tree {
+  int64_t n = 0;
+  int leaf = 0, L = 0;
+  int nnodes = 0, ninternal = 0, nleaves = 0;
+  int64_t maxleaf = 0;
+  std::vector<int64_t> lo, hi;
+  std::vector<int64_t> ldf;  // per level l < L: largest child size (leading dim of factors)
+  void build(int64_t n_, int leaf_);
+  int64_t size(int p) const { return hi[p] - lo[p]; }
+  int64_t mid(int p) const { return lo[p] + (hi[p] - lo[p] + 1) / 2; }
+  static int level(int p) {
+    int l = 0;
+    while ((2 << l) - 1 <= p) ++l;
+    return l;
+  }
+  bool is_leaf(int p) const { return p >= ninternal; }
+  int leaf_index(int p) const { return p - ninternal; }
+};
+
+// Device bump allocator over large chunks (256-byte aligned).
+class DevArena {
+ public:
+  ~DevArena();
+  void* alloc(size_t bytes);
+  template <class T>
+  T* get(size_t count) { return static_cast<T*>(alloc(sizeof(T) * (count ? count : 1))); }
+  void reset();  // keeps chunks, rewinds
+  struct Mark { size_t cur, used, inuse; };
+  Mark mark() const { return Mark{cur_, cur_ < chunks_.size() ? chunks_[cur_].used : 0, inuse_}; }
+  void rewind(const Mark& m);  // memory handed out after m may be reused (stream order keeps it safe)
+  size_t high_water() const { return high_; }
+  size_t chunk_bytes = size_t(256) << 20;
+
+ private:
+  struct Chunk { char* p; size_t cap, used; };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, inuse_ = 0, high_ = 0;
+};
+
+// Host-pinned staging + device copies for task descriptors.
+class DescStage {
+ public:
+  ~DescStage();
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t s) { return static_cast<T*>(up(v.data(), sizeof(T) * v.size(), s)); }
+  void reset();  // only after the stream has drained
+ private:
+  void* up(const void* src, size_t bytes, hipStream_t s);
+  struct Chunk { char* h; char* d; size_t cap, used; };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+};
+
+// A HODLR matrix on the device.  Block s of internal node p: s = 0 upper (rows = left child a,
+// cols = right child b), s = 1 lower (rows b, cols a); stored as U (rows x cap) V (cols x cap)
+// with leading dimension ldf[level] and a device rank.
+struct HMat {
+  const Tree* t = nullptr;
+  std::vector<int> cap;           // per level
+  int ldl = 0;
+  double* leaves = nullptr;
+  std::vector<double*> Ubase, Vbase;
+  int* rank = nullptr;            // 2 * ninternal
+  bool lower_only = false;        // symmetric storage: upper blocks implied by transposition
+  double* leaf(int li) const { return leaves + (size_t)li * ldl * ldl; }
+  double* U(int p, int s) const {
+    const int l = Tree::level(p), i = p - ((1 << l) - 1);
+    return Ubase[l] + (size_t)(2 * i + s) * t->ldf[l] * cap[l];
+  }
+  double* V(int p, int s) const {
+    const int l = Tree::level(p), i = p - ((1 << l) - 1);
+    return Vbase[l] + (size_t)(2 * i + s) * t->ldf[l] * cap[l];
+  }
+  int* rk(int p, int s) const { return rank + 2 * p + s; }
+  int ld(int p) const { return (int)t->ldf[Tree::level(p)]; }
+  int capof(int p) const { return cap[Tree::level(p)]; }
+  size_t bytes() const;
+};
+
+// op(H) as seen by an operation: trans swaps the roles of the two blocks and of U and V.
+struct HView {
+  const HMat* h = nullptr;
+  bool trans = false;
+  const int* zero = nullptr;  // device int holding 0 (used for blocks known to vanish)
+  struct Blk { const double* U; const double* V; const int* r; int ld, cap; };
+  Blk upper(int p) const;  // rows a, cols b of op(H)
+  Blk lower(int p) const;  // rows b, cols a of op(H)
+  HView T() const { HView v = *this; v.trans = !trans; return v; }
+};
+
+struct Thin {            // dense n_sub x w block (column-major) with a device width
+  double* p; int ld; const int* w; int wcap;
+};
+
+class Engine {
+ public:
+  Engine(hipStream_t s, const Tree* t);
+  ~Engine();
+  hipStream_t st;
+  const Tree* t;
+  DevArena persist, scratch;
+  DescStage stage;
+  int* d_flag = nullptr;   // bit 0: rank overflow, bit 1: not positive definite, bit 2: stack overflow
+  int* d_zero = nullptr;
+  double tol = 1e-10;
+  int64_t launches = 0;
+
+  HMat alloc_hmat(const std::vector<int>& cap, bool lower_only = false);
+  HView view(const HMat& h, bool trans = false) const { HView v; v.h = &h; v.trans = trans; v.zero = d_zero; return v; }
+  void zero_ranks(HMat& h);
+
+  // Y[rows of root] = alpha * op(H)|root * X + beta * Y for a list of subtree tasks.
+  struct ThinTask {
+    HView H; int root; const double* X; int ldx; double* Y; int ldy; const int* w; int wcap; double alpha, beta;
+  };
+  void mm_thin(const std::vector<ThinTask>& tasks);
+
+  // Truncated recompression of stacked factors Us (m x r) Vs (n x r) into (U, V, rank):
+  // U' = Us Rv^T J_k (scaled by sigma), V' = Vs Ru^T (B J)_k / sigma^2 (orthonormal columns).
+  struct RecTask {
+    const double* Us; int ldus; int m;
+    const double* Vs; int ldvs; int n;
+    const int* r; int rcap;
+    double* U; double* V; int ldu, ldv; int* rank; int kcap;
+    double thresh;
+  };
+  void recompress(const std::vector<RecTask>& tasks);
+  // Symmetric factor compression: S (m x r) -> S J_k with S S^T ~ S' S'^T, drop sigma(S) <= thresh.
+  struct SymTask { const double* S; int lds; int m; const int* r; int rcap; double* out; int ldo; int* rank; int kcap; double thresh; };
+  void compress_sym(const std::vector<SymTask>& tasks);
+
+  // C = alpha op(A) op(B) + delta op(D)  (D may be null, or the identity when d_identity)
+  void product(HView A, HView B, const HView* D, bool d_identity, double alpha, double delta, HMat& C);
+  // Cholesky Z = L L^T of a symmetric HODLR (lower blocks + leaves); returns L^{-1} in Linv.
+  void cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS);
+  // out = sid * I + sx * (X + X^T) / 2 as a full HODLR (sign: sx = 1, sid = 0; projector: -1/2, 1/2)
+  void sym_affine(const HMat& X, HMat& P, double sx, double sid);
+  void copy_hmat(const HMat& src, HMat& dst);
+
+  int read_flag();
+  void clear_flag();
+  std::vector<int> read_ranks(const HMat& h);
+
+  // helpers
+  void gemm(const std::vector<GemmTask>& v, int max_m, int max_n);
+  void stack(const std::vector<StackTask>& v, int max_rows);
+};
+
+}  // namespace hq

@@ -1,0 +1,757 @@
+// HODLR engine: storage and formatted arithmetic (Sec. 3.1.1 of the paper, Table complexity_HODLR)
+// mapped onto batched kernels.  Everything is issued on one stream; sizes that depend on ranks are
+// read by the kernels from device memory.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+
+namespace hq {
+
+// ---------------------------------------------------------------------------------------------
+void Tree::build(int64_t n_, int leaf_) {
+  n = n_;
+  leaf = leaf_;
+  L = 0;
+  while (((n + (int64_t(1) << L) - 1) >> L) > leaf) ++L;
+  nnodes = (2 << L) - 1;
+  ninternal = (1 << L) - 1;
+  nleaves = 1 << L;
+  lo.assign(nnodes, 0);
+  hi.assign(nnodes, 0);
+  hi[0] = n;
+  for (int p = 0; p < ninternal; ++p) {
+    const int64_t m = mid(p);
+    lo[2 * p + 1] = lo[p];
+    hi[2 * p + 1] = m;
+    lo[2 * p + 2] = m;
+    hi[2 * p + 2] = hi[p];
+  }
+  maxleaf = 0;
+  for (int p = ninternal; p < nnodes; ++p) maxleaf = std::max(maxleaf, size(p));
+  ldf.assign(L, 0);
+  for (int l = 0; l < L; ++l) ldf[l] = (n + (int64_t(2) << l) - 1) >> (l + 1);
+}
+
+// ---------------------------------------------------------------------------------------------
+DevArena::~DevArena() {
+  for (auto& c : chunks_) (void)hipFree(c.p);
+}
+void* DevArena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  while (cur_ < chunks_.size()) {
+    Chunk& c = chunks_[cur_];
+    if (c.used + bytes <= c.cap) {
+      void* p = c.p + c.used;
+      c.used += bytes;
+      inuse_ += bytes;
+      high_ = std::max(high_, inuse_);
+      return p;
+    }
+    ++cur_;
+  }
+  Chunk c;
+  c.cap = std::max(chunk_bytes, bytes);
+  HQ_CHECK(hipMalloc(&c.p, c.cap));
+  c.used = bytes;
+  chunks_.push_back(c);
+  cur_ = chunks_.size() - 1;
+  inuse_ += bytes;
+  high_ = std::max(high_, inuse_);
+  return c.p;
+}
+void DevArena::rewind(const Mark& m) {
+  for (size_t i = m.cur + 1; i < chunks_.size(); ++i) chunks_[i].used = 0;
+  if (m.cur < chunks_.size()) chunks_[m.cur].used = m.used;
+  cur_ = m.cur;
+  inuse_ = m.inuse;
+}
+void DevArena::reset() {
+  for (auto& c : chunks_) c.used = 0;
+  cur_ = 0;
+  inuse_ = 0;
+}
+
+DescStage::~DescStage() {
+  for (auto& c : chunks_) {
+    (void)hipHostFree(c.h);
+    (void)hipFree(c.d);
+  }
+}
+void* DescStage::up(const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return nullptr;
+  const size_t need = (bytes + 255) & ~size_t(255);
+  while (cur_ < chunks_.size() && chunks_[cur_].used + need > chunks_[cur_].cap) ++cur_;
+  if (cur_ == chunks_.size()) {
+    Chunk c;
+    c.cap = std::max(need, size_t(32) << 20);
+    HQ_CHECK(hipHostMalloc((void**)&c.h, c.cap, hipHostMallocDefault));
+    HQ_CHECK(hipMalloc((void**)&c.d, c.cap));
+    c.used = 0;
+    chunks_.push_back(c);
+  }
+  Chunk& c = chunks_[cur_];
+  std::memcpy(c.h + c.used, src, bytes);
+  HQ_CHECK(hipMemcpyAsync(c.d + c.used, c.h + c.used, bytes, hipMemcpyHostToDevice, s));
+  void* d = c.d + c.used;
+  c.used += need;
+  return d;
+}
+void DescStage::reset() {
+  for (auto& c : chunks_) c.used = 0;
+  cur_ = 0;
+}
+
+size_t HMat::bytes() const {
+  size_t b = (size_t)t->nleaves * ldl * ldl * sizeof(double);
+  for (int l = 0; l < t->L; ++l) b += (size_t)2 * (2 << l) * t->ldf[l] * cap[l] * sizeof(double);
+  return b;
+}
+
+HView::Blk HView::upper(int p) const {
+  const HMat& H = *h;
+  if (H.lower_only || trans) return {H.V(p, 1), H.U(p, 1), H.rk(p, 1), H.ld(p), H.capof(p)};
+  return {H.U(p, 0), H.V(p, 0), H.rk(p, 0), H.ld(p), H.capof(p)};
+}
+HView::Blk HView::lower(int p) const {
+  const HMat& H = *h;
+  if (H.lower_only || !trans) return {H.U(p, 1), H.V(p, 1), H.rk(p, 1), H.ld(p), H.capof(p)};
+  return {H.V(p, 0), H.U(p, 0), H.rk(p, 0), H.ld(p), H.capof(p)};
+}
+
+// ---------------------------------------------------------------------------------------------
+Engine::Engine(hipStream_t s, const Tree* t_) : st(s), t(t_) {
+  HQ_CHECK(hipMalloc(&d_flag, 256));
+  d_zero = d_flag + 32;
+  HQ_CHECK(hipMemsetAsync(d_flag, 0, 256, st));
+}
+Engine::~Engine() {
+  if (d_flag) (void)hipFree(d_flag);
+}
+
+HMat Engine::alloc_hmat(const std::vector<int>& cap, bool lower_only) {
+  HMat h;
+  h.t = t;
+  h.cap = cap;
+  h.lower_only = lower_only;
+  h.ldl = (int)t->maxleaf;
+  h.leaves = persist.get<double>((size_t)t->nleaves * h.ldl * h.ldl);
+  h.Ubase.resize(t->L);
+  h.Vbase.resize(t->L);
+  for (int l = 0; l < t->L; ++l) {
+    const size_t per = (size_t)(2 << l) * t->ldf[l] * cap[l];
+    h.Ubase[l] = persist.get<double>(per);
+    h.Vbase[l] = persist.get<double>(per);
+  }
+  h.rank = persist.get<int>(std::max(1, 2 * t->ninternal));
+  zero_ranks(h);
+  return h;
+}
+void Engine::zero_ranks(HMat& h) { launch_fill_int(h.rank, 0, 2 * t->ninternal, st); }
+
+void Engine::gemm(const std::vector<GemmTask>& v, int max_m, int max_n) {
+  if (v.empty()) return;
+  launch_gemm(stage.upload(v, st), (int)v.size(), max_m, max_n, st);
+  ++launches;
+}
+void Engine::stack(const std::vector<StackTask>& v, int max_rows) {
+  if (v.empty()) return;
+  launch_stack(stage.upload(v, st), (int)v.size(), max_rows, d_flag, st);
+  ++launches;
+}
+
+int Engine::read_flag() {
+  int f = 0;
+  HQ_CHECK(hipMemcpyAsync(&f, d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HQ_CHECK(hipStreamSynchronize(st));
+  return f;
+}
+void Engine::clear_flag() { launch_fill_int(d_flag, 0, 1, st); }
+
+std::vector<int> Engine::read_ranks(const HMat& h) {
+  std::vector<int> r(std::max(1, 2 * t->ninternal));
+  HQ_CHECK(hipMemcpyAsync(r.data(), h.rank, sizeof(int) * r.size(), hipMemcpyDeviceToHost, st));
+  HQ_CHECK(hipStreamSynchronize(st));
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------------
+// HODLR (subtree) x thin dense: leaves, then per internal node V^T X (all at once), then U (V^T X)
+// per level so that updates of one launch never overlap.
+void Engine::mm_thin(const std::vector<ThinTask>& tasks) {
+  if (tasks.empty()) return;
+  const int L = t->L;
+  std::vector<GemmTask> leafv, tv;
+  std::vector<std::vector<GemmTask>> upd(L);
+  int wmax = 1, capmax = 1;
+  int64_t rowmax = 1;
+  for (const ThinTask& T : tasks) {
+    wmax = std::max(wmax, T.wcap);
+    const int lr = Tree::level(T.root);
+    const int64_t r0 = t->lo[T.root];
+    // leaves
+    const int nl = 1 << (L - lr);
+    const int first = ((T.root + 1) << (L - lr)) - 1;
+    for (int q = first; q < first + nl; ++q) {
+      const int64_t off = t->lo[q] - r0, m = t->size(q);
+      GemmTask g{};
+      g.A = T.H.h->leaf(t->leaf_index(q));
+      g.opA = (T.H.trans && !T.H.h->lower_only) ? 1 : 0;
+      g.lda = T.H.h->ldl;
+      g.B = T.X + off;
+      g.ldb = T.ldx;
+      g.C = T.Y + off;
+      g.ldc = T.ldy;
+      g.m = (int)m;
+      g.k = (int)m;
+      g.n = T.wcap;
+      g.np = T.w;
+      g.alpha = T.alpha;
+      g.beta = T.beta;
+      leafv.push_back(g);
+    }
+    // internal nodes of the subtree
+    for (int l = lr; l < L; ++l) {
+      const int cnt = 1 << (l - lr);
+      const int f0 = ((T.root + 1) << (l - lr)) - 1;
+      for (int q = f0; q < f0 + cnt; ++q) {
+        const int a = 2 * q + 1, b = 2 * q + 2;
+        const int64_t oa = t->lo[a] - r0, ob = t->lo[b] - r0;
+        for (int s = 0; s < 2; ++s) {
+          const HView::Blk B = s == 0 ? T.H.upper(q) : T.H.lower(q);
+          // s = 0: rows a, cols b;  s = 1: rows b, cols a
+          const int64_t orow = s == 0 ? oa : ob, ocol = s == 0 ? ob : oa;
+          const int64_t mrow = s == 0 ? t->size(a) : t->size(b), mcol = s == 0 ? t->size(b) : t->size(a);
+          double* tmp = scratch.get<double>((size_t)B.cap * T.wcap);
+          capmax = std::max(capmax, B.cap);
+          rowmax = std::max(rowmax, mrow);
+          GemmTask g{};
+          g.A = B.V;
+          g.opA = 1;
+          g.lda = B.ld;
+          g.B = T.X + ocol;
+          g.ldb = T.ldx;
+          g.C = tmp;
+          g.ldc = B.cap;
+          g.m = B.cap;
+          g.mp = B.r;
+          g.n = T.wcap;
+          g.np = T.w;
+          g.k = (int)mcol;
+          g.alpha = 1.0;
+          g.beta = 0.0;
+          tv.push_back(g);
+          GemmTask u{};
+          u.A = B.U;
+          u.lda = B.ld;
+          u.B = tmp;
+          u.ldb = B.cap;
+          u.C = T.Y + orow;
+          u.ldc = T.ldy;
+          u.m = (int)mrow;
+          u.n = T.wcap;
+          u.np = T.w;
+          u.k = B.cap;
+          u.kp = B.r;
+          u.alpha = T.alpha;
+          u.beta = 1.0;
+          upd[l].push_back(u);
+        }
+      }
+    }
+  }
+  gemm(leafv, (int)t->maxleaf, wmax);
+  gemm(tv, capmax, wmax);
+  for (int l = 0; l < L; ++l) gemm(upd[l], (int)rowmax, wmax);
+}
+
+// ---------------------------------------------------------------------------------------------
+// R-only TSQR of each stack, SVD of the small core, and two thin GEMMs per factor.
+namespace {
+struct QrPlan { int h0, hs, ntiles; };
+QrPlan plan_qr(int m, int rcap) {
+  QrPlan p;
+  const int hmin = std::max(256, 2 * rcap);
+  if (m <= hmin) {
+    p.h0 = p.hs = std::max(m, 1);
+    p.ntiles = 1;
+  } else {
+    p.h0 = p.hs = (hmin + 63) / 64 * 64;
+    p.ntiles = (m + p.h0 - 1) / p.h0;
+  }
+  return p;
+}
+}  // namespace
+
+void Engine::recompress(const std::vector<RecTask>& tasks) {
+  if (tasks.empty()) return;
+  const int nt = (int)tasks.size();
+  std::vector<QrTask> qv;
+  std::vector<GemmTask> gB, gP, gUV;
+  std::vector<SvdTask> sv;
+  int maxtiles = 1, hsmax = 1, rmax = 1, kmax = 1, mmax = 1;
+  struct Bufs { double *Ru, *Rv, *B, *J, *Wk, *Jk, *Pu, *Pv; };
+  std::vector<Bufs> bufs(nt);
+  for (int i = 0; i < nt; ++i) {
+    const RecTask& T = tasks[i];
+    const int rc = std::max(T.rcap, 1);
+    if (rc > 2048) throw std::runtime_error("recompress: stacked rank capacity above 2048");
+    Bufs& b = bufs[i];
+    const size_t rr = (size_t)rc * rc;
+    b.Ru = scratch.get<double>(rr);
+    b.Rv = scratch.get<double>(rr);
+    b.B = scratch.get<double>(rr);
+    b.J = scratch.get<double>(rr);
+    b.Wk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    b.Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    b.Pu = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    b.Pv = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    for (int side = 0; side < 2; ++side) {
+      const int m = side == 0 ? T.m : T.n;
+      const QrPlan pl = plan_qr(m, rc);
+      QrTask q{};
+      q.M = side == 0 ? T.Us : T.Vs;
+      q.ldm = side == 0 ? T.ldus : T.ldvs;
+      q.rows = m;
+      q.rp = T.r;
+      q.rcap = rc;
+      q.hs = pl.hs;
+      q.h0 = pl.h0;
+      q.ntiles = pl.ntiles;
+      q.work = scratch.get<double>((size_t)pl.ntiles * pl.hs * rc);
+      q.R = side == 0 ? b.Ru : b.Rv;
+      q.ldr = rc;
+      qv.push_back(q);
+      maxtiles = std::max(maxtiles, pl.ntiles);
+      hsmax = std::max(hsmax, pl.hs);
+    }
+    rmax = std::max(rmax, rc);
+    kmax = std::max(kmax, T.kcap);
+    mmax = std::max(mmax, std::max(T.m, T.n));
+    GemmTask g{};  // B = Ru Rv^T
+    g.A = b.Ru; g.lda = rc; g.B = b.Rv; g.ldb = rc; g.opB = 1; g.C = b.B; g.ldc = rc;
+    g.m = g.n = g.k = rc; g.mp = g.np = g.kp = T.r; g.alpha = 1.0; g.beta = 0.0;
+    gB.push_back(g);
+    SvdTask s{};
+    s.B = b.B; s.J = b.J; s.Wk = b.Wk; s.Jk = b.Jk; s.sig = nullptr; s.rp = T.r; s.kout = T.rank;
+    s.ld = rc; s.kcap = T.kcap; s.thresh = T.thresh;
+    sv.push_back(s);
+    GemmTask pu{};  // Pu = Rv^T Jk
+    pu.A = b.Rv; pu.opA = 1; pu.lda = rc; pu.B = b.Jk; pu.ldb = rc; pu.C = b.Pu; pu.ldc = rc;
+    pu.m = rc; pu.mp = T.r; pu.n = T.kcap; pu.np = T.rank; pu.k = rc; pu.kp = T.r; pu.alpha = 1.0; pu.beta = 0.0;
+    gP.push_back(pu);
+    GemmTask pv = pu;  // Pv = Ru^T Wk
+    pv.A = b.Ru; pv.B = b.Wk; pv.C = b.Pv;
+    gP.push_back(pv);
+    GemmTask gu{};  // U = Us Pu
+    gu.A = T.Us; gu.lda = T.ldus; gu.B = b.Pu; gu.ldb = rc; gu.C = T.U; gu.ldc = T.ldu;
+    gu.m = T.m; gu.n = T.kcap; gu.np = T.rank; gu.k = rc; gu.kp = T.r; gu.alpha = 1.0; gu.beta = 0.0;
+    gUV.push_back(gu);
+    GemmTask gv = gu;  // V = Vs Pv
+    gv.A = T.Vs; gv.lda = T.ldvs; gv.B = b.Pv; gv.C = T.V; gv.ldc = T.ldv; gv.m = T.n;
+    gUV.push_back(gv);
+  }
+  QrTask* dq = stage.upload(qv, st);
+  int nst = 0;
+  while ((1 << nst) < maxtiles) ++nst;
+  for (int s = 0; s <= nst; ++s) {
+    const int pairs = (maxtiles + (1 << s) - 1) >> s;
+    launch_qr_stage(dq, (int)qv.size(), s, pairs, hsmax, rmax, st);
+    ++launches;
+  }
+  launch_qr_final(dq, (int)qv.size(), rmax, st);
+  gemm(gB, rmax, rmax);
+  launch_svd(stage.upload(sv, st), nt, d_flag, st);
+  launches += 2;
+  gemm(gP, rmax, kmax);
+  gemm(gUV, mmax, kmax);
+}
+
+void Engine::compress_sym(const std::vector<SymTask>& tasks) {
+  if (tasks.empty()) return;
+  const int nt = (int)tasks.size();
+  std::vector<QrTask> qv;
+  std::vector<SvdTask> sv;
+  std::vector<GemmTask> go;
+  int maxtiles = 1, hsmax = 1, rmax = 1, kmax = 1, mmax = 1;
+  for (int i = 0; i < nt; ++i) {
+    const SymTask& T = tasks[i];
+    const int rc = std::max(T.rcap, 1);
+    const QrPlan pl = plan_qr(T.m, rc);
+    double* R = scratch.get<double>((size_t)rc * rc);
+    double* J = scratch.get<double>((size_t)rc * rc);
+    double* Wk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    double* Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    QrTask q{};
+    q.M = T.S; q.ldm = T.lds; q.rows = T.m; q.rp = T.r; q.rcap = rc; q.hs = pl.hs; q.h0 = pl.h0;
+    q.ntiles = pl.ntiles; q.work = scratch.get<double>((size_t)pl.ntiles * pl.hs * rc); q.R = R; q.ldr = rc;
+    qv.push_back(q);
+    maxtiles = std::max(maxtiles, pl.ntiles);
+    hsmax = std::max(hsmax, pl.hs);
+    rmax = std::max(rmax, rc);
+    kmax = std::max(kmax, T.kcap);
+    mmax = std::max(mmax, T.m);
+    SvdTask s{};
+    s.B = R; s.J = J; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc; s.kcap = T.kcap;
+    s.thresh = T.thresh;
+    sv.push_back(s);
+    GemmTask g{};  // out = S Jk
+    g.A = T.S; g.lda = T.lds; g.B = Jk; g.ldb = rc; g.C = T.out; g.ldc = T.ldo;
+    g.m = T.m; g.n = T.kcap; g.np = T.rank; g.k = rc; g.kp = T.r; g.alpha = 1.0; g.beta = 0.0;
+    go.push_back(g);
+  }
+  QrTask* dq = stage.upload(qv, st);
+  int nst = 0;
+  while ((1 << nst) < maxtiles) ++nst;
+  for (int s = 0; s <= nst; ++s) {
+    const int pairs = (maxtiles + (1 << s) - 1) >> s;
+    launch_qr_stage(dq, nt, s, pairs, hsmax, rmax, st);
+    ++launches;
+  }
+  launch_qr_final(dq, nt, rmax, st);
+  launch_svd(stage.upload(sv, st), nt, d_flag, st);
+  launches += 2;
+  gemm(go, mmax, kmax);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Formatted product.  For node p with children a, b:
+//   C_ab = A_aa B_ab + A_ab B_bb + T_p|ab,   C_ba = A_ba B_aa + A_bb B_ba + T_p|ba,
+// where T_p collects the low-rank products that ancestors of p contribute inside p x p:
+//   T_a = T_p|aa + A_ab B_ba,   T_b = T_p|bb + A_ba B_ab,
+// carried top-down in factored, recompressed form.  Leaves: C_i = A_i B_i + T_i.
+void Engine::product(HView A, HView B, const HView* D, bool d_identity, double alpha, double delta, HMat& C) {
+  const int L = t->L;
+  const bool full = !C.lower_only;
+  const double tolT = 0.25 * tol;
+  struct NodeBufs {
+    double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *P4 = nullptr;
+    int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+  };
+  std::vector<NodeBufs> nb(std::max(1, t->ninternal));
+  // 1) thin products for every internal node
+  std::vector<ThinTask> thin;
+  for (int p = 0; p < t->ninternal; ++p) {
+    const int a = 2 * p + 1, b = 2 * p + 2, ld = (int)t->ldf[Tree::level(p)];
+    const HView::Blk Au = A.upper(p), Al = A.lower(p), Bu = B.upper(p), Bl = B.lower(p);
+    NodeBufs& q = nb[p];
+    if (full) {
+      q.c1 = Bu.cap;
+      q.P1 = scratch.get<double>((size_t)ld * q.c1);
+      thin.push_back({A, a, Bu.U, Bu.ld, q.P1, ld, Bu.r, Bu.cap, 1.0, 0.0});  // A_aa Uu_B
+      q.c2 = Au.cap;
+      q.P2 = scratch.get<double>((size_t)ld * q.c2);
+      thin.push_back({B.T(), b, Au.V, Au.ld, q.P2, ld, Au.r, Au.cap, 1.0, 0.0});  // B_bb^T Vu_A
+    }
+    q.c3 = Bl.cap;
+    q.P3 = scratch.get<double>((size_t)ld * q.c3);
+    thin.push_back({A, b, Bl.U, Bl.ld, q.P3, ld, Bl.r, Bl.cap, 1.0, 0.0});  // A_bb Ul_B
+    q.c4 = Al.cap;
+    q.P4 = scratch.get<double>((size_t)ld * q.c4);
+    thin.push_back({B.T(), a, Al.V, Al.ld, q.P4, ld, Al.r, Al.cap, 1.0, 0.0});  // B_aa^T Vl_A
+  }
+  mm_thin(thin);
+
+  // 2) level sweep: C blocks of level l and the accumulated terms of level l+1
+  struct TermF { double* E; double* F; int ld; const int* r; int cap; };
+  std::vector<TermF> term(t->nnodes, TermF{nullptr, nullptr, 1, d_zero, 0});
+  for (int l = 0; l < L; ++l) {
+    const int f0 = (1 << l) - 1, cnt = 1 << l;
+    const int ldc = (int)t->ldf[l];
+    // core products M and G for the children's terms
+    std::vector<GemmTask> gm, gg;
+    std::vector<StackTask> stk;
+    std::vector<RecTask> rec;
+    int maxrows = 1, mcapA = 1, mcapB = 1;
+    for (int p = f0; p < f0 + cnt; ++p) {
+      const int a = 2 * p + 1, b = 2 * p + 2;
+      const int64_t sa = t->size(a), sb = t->size(b), ofa = t->lo[a] - t->lo[p], ofb = t->lo[b] - t->lo[p];
+      maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
+      const HView::Blk Au = A.upper(p), Al = A.lower(p), Bu = B.upper(p), Bl = B.lower(p);
+      const TermF& Tp = term[p];
+      mcapA = std::max(mcapA, std::max(Au.cap, Al.cap));
+      mcapB = std::max(mcapB, std::max(Bu.cap, Bl.cap));
+      const int capT = std::min<int>((int)std::max(sa, sb), std::max(C.cap[l], std::max(Au.cap, Bu.cap)) * 2);
+      // --- C blocks
+      for (int s = 0; s < 2; ++s) {
+        if (s == 0 && !full) continue;
+        const int64_t mr = s == 0 ? sa : sb, mc = s == 0 ? sb : sa;
+        const int64_t ofr = s == 0 ? ofa : ofb, ofc = s == 0 ? ofb : ofa;
+        const HView::Blk Ax = s == 0 ? Au : Al, Bx = s == 0 ? Bu : Bl;
+        const NodeBufs& q = nb[p];
+        double* P_left = s == 0 ? q.P1 : q.P3;   // A_xx U_B  (rows r)
+        double* P_right = s == 0 ? q.P2 : q.P4;  // B_yy^T V_A (rows c)
+        HView::Blk Dx{nullptr, nullptr, d_zero, 1, 0};
+        if (D && !d_identity) Dx = s == 0 ? D->upper(p) : D->lower(p);
+        const int rcap = Bx.cap + Ax.cap + Tp.cap + Dx.cap;
+        double* Us = scratch.get<double>((size_t)ldc * rcap);
+        double* Vs = scratch.get<double>((size_t)ldc * rcap);
+        int* rs = scratch.get<int>(1);
+        StackTask su{};
+        su.dst = Us; su.ld = ldc; su.rows = (int)mr; su.wcap = rcap; su.wout = rs; su.nsrc = 4;
+        su.src[0] = {P_left, Bx.r, ldc, Bx.cap, alpha};
+        su.src[1] = {Ax.U, Ax.r, Ax.ld, Ax.cap, alpha};
+        su.src[2] = {Tp.E ? Tp.E + ofr : nullptr, Tp.r, Tp.ld, Tp.cap, alpha};
+        su.src[3] = {Dx.U, Dx.r, Dx.ld, Dx.cap, delta};
+        StackTask sv = su;
+        sv.dst = Vs; sv.rows = (int)mc; sv.wout = nullptr;
+        sv.src[0] = {Bx.V, Bx.r, Bx.ld, Bx.cap, 1.0};
+        sv.src[1] = {P_right, Ax.r, ldc, Ax.cap, 1.0};
+        sv.src[2] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
+        sv.src[3] = {Dx.V, Dx.r, Dx.ld, Dx.cap, 1.0};
+        stk.push_back(su);
+        stk.push_back(sv);
+        RecTask r{};
+        r.Us = Us; r.ldus = ldc; r.m = (int)mr; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mc; r.r = rs; r.rcap = rcap;
+        r.U = C.U(p, s); r.V = C.V(p, s); r.ldu = r.ldv = ldc; r.rank = C.rk(p, s); r.kcap = C.cap[l];
+        r.thresh = tol;
+        rec.push_back(r);
+      }
+      // --- terms for the children: T_a = T_p|aa + Uu_A (Vu_A^T Ul_B) Vl_B^T, T_b = T_p|bb + Ul_A (Vl_A^T Uu_B) Vu_B^T
+      for (int s = 0; s < 2; ++s) {
+        const int c = s == 0 ? a : b;
+        const int64_t mrow = s == 0 ? sa : sb, inner = s == 0 ? sb : sa, ofc = s == 0 ? ofa : ofb;
+        const HView::Blk Ax = s == 0 ? Au : Al, By = s == 0 ? Bl : Bu;
+        double* M = scratch.get<double>((size_t)std::max(Ax.cap, 1) * std::max(By.cap, 1));
+        double* G = scratch.get<double>((size_t)ldc * std::max(By.cap, 1));
+        GemmTask g1{};
+        g1.A = Ax.V; g1.opA = 1; g1.lda = Ax.ld; g1.B = By.U; g1.ldb = By.ld; g1.C = M; g1.ldc = std::max(Ax.cap, 1);
+        g1.m = Ax.cap; g1.mp = Ax.r; g1.n = By.cap; g1.np = By.r; g1.k = (int)inner; g1.alpha = 1.0; g1.beta = 0.0;
+        gm.push_back(g1);
+        GemmTask g2{};
+        g2.A = Ax.U; g2.lda = Ax.ld; g2.B = M; g2.ldb = std::max(Ax.cap, 1); g2.C = G; g2.ldc = ldc;
+        g2.m = (int)mrow; g2.n = By.cap; g2.np = By.r; g2.k = Ax.cap; g2.kp = Ax.r; g2.alpha = 1.0; g2.beta = 0.0;
+        gg.push_back(g2);
+        const int rcap = Tp.cap + By.cap;
+        double* Us = scratch.get<double>((size_t)ldc * rcap);
+        double* Vs = scratch.get<double>((size_t)ldc * rcap);
+        int* rs = scratch.get<int>(1);
+        StackTask su{};
+        su.dst = Us; su.ld = ldc; su.rows = (int)mrow; su.wcap = rcap; su.wout = rs; su.nsrc = 2;
+        su.src[0] = {Tp.E ? Tp.E + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
+        su.src[1] = {G, By.r, ldc, By.cap, 1.0};
+        StackTask sv = su;
+        sv.dst = Vs; sv.wout = nullptr;
+        sv.src[0] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
+        sv.src[1] = {By.V, By.r, By.ld, By.cap, 1.0};
+        stk.push_back(su);
+        stk.push_back(sv);
+        TermF nt;
+        nt.ld = ldc;
+        nt.cap = capT;
+        nt.E = scratch.get<double>((size_t)nt.ld * capT);
+        nt.F = scratch.get<double>((size_t)nt.ld * capT);
+        int* rr = scratch.get<int>(1);
+        nt.r = rr;
+        term[c] = nt;
+        RecTask r{};
+        r.Us = Us; r.ldus = ldc; r.m = (int)mrow; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mrow; r.r = rs; r.rcap = rcap;
+        r.U = nt.E; r.V = nt.F; r.ldu = r.ldv = nt.ld; r.rank = rr; r.kcap = capT; r.thresh = tolT;
+        rec.push_back(r);
+      }
+    }
+    gemm(gm, mcapA, mcapB);
+    gemm(gg, maxrows, mcapB);
+    stack(stk, maxrows);
+    recompress(rec);
+  }
+  // 3) leaves
+  std::vector<GemmTask> g1, g2;
+  std::vector<LeafAxpy> ax;
+  const int ldl = (int)t->maxleaf;
+  double* tmp = scratch.get<double>((size_t)t->nleaves * ldl * ldl);
+  int capTmax = 1;
+  for (int q = t->ninternal; q < t->nnodes; ++q) {
+    const int li = t->leaf_index(q), m = (int)t->size(q);
+    double* Ti = tmp + (size_t)li * ldl * ldl;
+    GemmTask g{};
+    g.A = A.h->leaf(li); g.opA = (A.trans && !A.h->lower_only) ? 1 : 0; g.lda = A.h->ldl;
+    g.B = B.h->leaf(li); g.opB = (B.trans && !B.h->lower_only) ? 1 : 0; g.ldb = B.h->ldl;
+    g.C = Ti; g.ldc = ldl; g.m = g.n = g.k = m; g.alpha = 1.0; g.beta = 0.0;
+    g1.push_back(g);
+    const TermF& Tq = term[q];
+    if (Tq.E) {
+      GemmTask e{};
+      e.A = Tq.E; e.lda = Tq.ld; e.B = Tq.F; e.ldb = Tq.ld; e.opB = 1; e.C = Ti; e.ldc = ldl;
+      e.m = e.n = m; e.k = Tq.cap; e.kp = Tq.r; e.alpha = 1.0; e.beta = 1.0;
+      g2.push_back(e);
+      capTmax = std::max(capTmax, Tq.cap);
+    }
+    LeafAxpy x{};
+    x.out = C.leaf(li); x.ldo = C.ldl; x.m = m; x.X = Ti; x.ldx = ldl;
+    if (C.lower_only) {
+      x.Y = Ti; x.ldy = ldl; x.transY = 1; x.alpha = 0.5 * alpha; x.beta = 0.5 * alpha;
+      x.gamma = d_identity ? delta : 0.0;
+    } else {
+      x.alpha = alpha;
+      if (d_identity) {
+        x.gamma = delta;
+      } else if (D) {
+        x.Y = D->h->leaf(li); x.ldy = D->h->ldl; x.transY = (D->trans && !D->h->lower_only) ? 1 : 0; x.beta = delta;
+      }
+    }
+    ax.push_back(x);
+  }
+  gemm(g1, ldl, ldl);
+  gemm(g2, ldl, ldl);
+  launch_leaf_axpy(stage.upload(ax, st), (int)ax.size(), ldl, st);
+  ++launches;
+  if (!full)  // lower_only result: upper blocks are implied, keep their ranks at zero
+    for (int p = 0; p < t->ninternal; ++p) launch_fill_int(C.rk(p, 0), 0, 1, st);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Recursive Cholesky (left subtree, off-diagonal factor, Schur update, right subtree).  The
+// Schur complement updates from all ancestors are carried lazily as one symmetric low-rank
+// factor S (Z_bb - L_ba L_ba^T restricted = Z_bb - S S^T), compressed at every right turn.
+// Alongside, the inverse factor is assembled bottom-up:
+//   [L^-1]_aa = L_aa^-1, [L^-1]_bb = L_bb^-1, [L^-1]_ba = -(L_bb^-1 U)(L_aa^-T V)^T for L_ba = U V^T.
+void Engine::cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) {
+  zero_ranks(Linv);
+  zero_ranks(Lf);
+  struct SF { double* p; int ld; const int* r; int cap; };
+  const double thS = std::sqrt(0.1 * tol);
+  const HView Lv = view(Linv), LvT = view(Linv, true);
+  std::function<void(int, SF)> dfs = [&](int c, SF S) {
+    if (t->is_leaf(c)) {
+      const int li = t->leaf_index(c), m = (int)t->size(c);
+      std::vector<LeafAxpy> cp(1);
+      cp[0] = LeafAxpy{};
+      cp[0].out = Lf.leaf(li); cp[0].ldo = Lf.ldl; cp[0].X = Z.leaf(li); cp[0].ldx = Z.ldl; cp[0].m = m; cp[0].alpha = 1.0;
+      launch_leaf_axpy(stage.upload(cp, st), 1, m, st);
+      if (S.cap > 0) {
+        GemmTask g{};
+        g.A = S.p; g.lda = S.ld; g.B = S.p; g.ldb = S.ld; g.opB = 1; g.C = Lf.leaf(li); g.ldc = Lf.ldl;
+        g.m = g.n = m; g.k = S.cap; g.kp = S.r; g.alpha = -1.0; g.beta = 1.0;
+        gemm({g}, m, m);
+      }
+      std::vector<LeafTask> lt(1);
+      lt[0] = LeafTask{Lf.leaf(li), Linv.leaf(li), m, Lf.ldl, Linv.ldl};
+      LeafTask* d = stage.upload(lt, st);
+      launch_potrf(d, 1, d_flag, st);
+      launch_trtri(d, 1, st);
+      launches += 3;
+      return;
+    }
+    const int p = c, a = 2 * p + 1, b = 2 * p + 2, l = Tree::level(p);
+    const int64_t sa = t->size(a), sb = t->size(b), la = t->lo[a] - t->lo[p], lb = t->lo[b] - t->lo[p];
+    const int ldc = (int)t->ldf[l];
+    dfs(a, SF{S.p ? S.p + la : nullptr, S.ld, S.r, S.cap});
+    const int capSb = std::min<int>((int)sb, capS);
+    double* Snew = scratch.get<double>((size_t)sb * capSb);
+    int* rnew = scratch.get<int>(1);
+    const DevArena::Mark mk = scratch.mark();
+    const int rcap = Z.cap[l] + S.cap;
+    double* Us = scratch.get<double>((size_t)ldc * rcap);
+    double* Vs0 = scratch.get<double>((size_t)ldc * rcap);
+    double* Vs = scratch.get<double>((size_t)ldc * rcap);
+    int* rs = scratch.get<int>(1);
+    StackTask su{};
+    su.dst = Us; su.ld = ldc; su.rows = (int)sb; su.wcap = rcap; su.wout = rs; su.nsrc = 2;
+    su.src[0] = {Z.U(p, 1), Z.rk(p, 1), ldc, Z.cap[l], 1.0};
+    su.src[1] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
+    StackTask sv = su;
+    sv.dst = Vs0; sv.rows = (int)sa; sv.wout = nullptr;
+    sv.src[0] = {Z.V(p, 1), Z.rk(p, 1), ldc, Z.cap[l], 1.0};
+    sv.src[1] = {S.p ? S.p + la : nullptr, S.r, S.ld, S.cap, -1.0};
+    stack({su, sv}, (int)std::max(sa, sb));
+    mm_thin({ThinTask{Lv, a, Vs0, ldc, Vs, ldc, rs, rcap, 1.0, 0.0}});
+    RecTask r{};
+    r.Us = Us; r.ldus = ldc; r.m = (int)sb; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sa; r.r = rs; r.rcap = rcap;
+    r.U = Lf.U(p, 1); r.V = Lf.V(p, 1); r.ldu = r.ldv = ldc; r.rank = Lf.rk(p, 1); r.kcap = Lf.cap[l]; r.thresh = tol;
+    recompress({r});
+    // Schur factor of the right child
+    const int rcS = S.cap + Lf.cap[l];
+    double* Sraw = scratch.get<double>((size_t)sb * rcS);
+    int* rsb = scratch.get<int>(1);
+    StackTask ss{};
+    ss.dst = Sraw; ss.ld = (int)sb; ss.rows = (int)sb; ss.wcap = rcS; ss.wout = rsb; ss.nsrc = 2;
+    ss.src[0] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
+    ss.src[1] = {Lf.U(p, 1), Lf.rk(p, 1), ldc, Lf.cap[l], 1.0};
+    stack({ss}, (int)sb);
+    compress_sym({SymTask{Sraw, (int)sb, (int)sb, rsb, rcS, Snew, (int)sb, rnew, capSb, thS}});
+    scratch.rewind(mk);
+    dfs(b, SF{Snew, (int)sb, rnew, capSb});
+    const DevArena::Mark mk2 = scratch.mark();
+    // inverse block
+    mm_thin({ThinTask{Lv, b, Lf.U(p, 1), ldc, Linv.U(p, 1), ldc, Lf.rk(p, 1), Lf.cap[l], -1.0, 0.0},
+             ThinTask{LvT, a, Lf.V(p, 1), ldc, Linv.V(p, 1), ldc, Lf.rk(p, 1), Lf.cap[l], 1.0, 0.0}});
+    launch_copy_int(Linv.rk(p, 1), Lf.rk(p, 1), 1, st);
+    scratch.rewind(mk2);
+  };
+  dfs(0, SF{nullptr, 1, d_zero, 0});
+}
+
+// ---------------------------------------------------------------------------------------------
+void Engine::sym_affine(const HMat& X, HMat& P, double sx, double sid) {
+  zero_ranks(P);
+  std::vector<StackTask> stk;
+  std::vector<RecTask> rec;
+  int maxrows = 1;
+  const HView Xv = view(X);
+  for (int p = 0; p < t->ninternal; ++p) {
+    const int l = Tree::level(p), ldc = (int)t->ldf[l];
+    const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
+    maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
+    const HView::Blk u = Xv.upper(p), lo = Xv.lower(p);
+    const int rcap = u.cap + lo.cap;
+    double* Us = scratch.get<double>((size_t)ldc * rcap);
+    double* Vs = scratch.get<double>((size_t)ldc * rcap);
+    int* rs = scratch.get<int>(1);
+    StackTask su{};
+    su.dst = Us; su.ld = ldc; su.rows = (int)sa; su.wcap = rcap; su.wout = rs; su.nsrc = 2;
+    su.src[0] = {u.U, u.r, u.ld, u.cap, 0.5 * sx};
+    su.src[1] = {lo.V, lo.r, lo.ld, lo.cap, 0.5 * sx};
+    StackTask sv = su;
+    sv.dst = Vs; sv.rows = (int)sb; sv.wout = nullptr;
+    sv.src[0] = {u.V, u.r, u.ld, u.cap, 1.0};
+    sv.src[1] = {lo.U, lo.r, lo.ld, lo.cap, 1.0};
+    stk.push_back(su);
+    stk.push_back(sv);
+    RecTask r{};
+    r.Us = Us; r.ldus = ldc; r.m = (int)sa; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sb; r.r = rs; r.rcap = rcap;
+    r.U = P.U(p, 0); r.V = P.V(p, 0); r.ldu = r.ldv = ldc; r.rank = P.rk(p, 0); r.kcap = P.cap[l]; r.thresh = tol;
+    rec.push_back(r);
+  }
+  stack(stk, maxrows);
+  recompress(rec);
+  // lower block = transpose of the upper one
+  std::vector<StackTask> cp;
+  for (int p = 0; p < t->ninternal; ++p) {
+    const int l = Tree::level(p), ldc = (int)t->ldf[l];
+    const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
+    StackTask a{};
+    a.dst = P.U(p, 1); a.ld = ldc; a.rows = (int)sb; a.wcap = P.cap[l]; a.wout = P.rk(p, 1); a.nsrc = 1;
+    a.src[0] = {P.V(p, 0), P.rk(p, 0), ldc, P.cap[l], 1.0};
+    StackTask b = a;
+    b.dst = P.V(p, 1); b.rows = (int)sa; b.wout = nullptr;
+    b.src[0] = {P.U(p, 0), P.rk(p, 0), ldc, P.cap[l], 1.0};
+    cp.push_back(a);
+    cp.push_back(b);
+  }
+  stack(cp, maxrows);
+  std::vector<LeafAxpy> ax;
+  for (int q = t->ninternal; q < t->nnodes; ++q) {
+    const int li = t->leaf_index(q);
+    LeafAxpy x{};
+    x.out = P.leaf(li); x.ldo = P.ldl; x.X = X.leaf(li); x.ldx = X.ldl; x.Y = X.leaf(li); x.ldy = X.ldl;
+    x.transY = 1; x.m = (int)t->size(q); x.alpha = 0.5 * sx; x.beta = 0.5 * sx; x.gamma = sid;
+    ax.push_back(x);
+  }
+  launch_leaf_axpy(stage.upload(ax, st), (int)ax.size(), (int)t->maxleaf, st);
+}
+
+void Engine::copy_hmat(const HMat& src, HMat& dst) {
+  HQ_CHECK(hipMemcpyAsync(dst.leaves, src.leaves, sizeof(double) * (size_t)t->nleaves * src.ldl * src.ldl,
+                          hipMemcpyDeviceToDevice, st));
+  for (int l = 0; l < t->L; ++l) {
+    if (src.cap[l] != dst.cap[l]) throw std::runtime_error("copy_hmat: capacity mismatch");
+    const size_t per = (size_t)(2 << l) * t->ldf[l] * src.cap[l] * sizeof(double);
+    HQ_CHECK(hipMemcpyAsync(dst.Ubase[l], src.Ubase[l], per, hipMemcpyDeviceToDevice, st));
+    HQ_CHECK(hipMemcpyAsync(dst.Vbase[l], src.Vbase[l], per, hipMemcpyDeviceToDevice, st));
+  }
+  launch_copy_int(dst.rank, src.rank, 2 * t->ninternal, st);
+}
+
+}  // namespace hq

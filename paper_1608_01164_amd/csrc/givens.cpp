@@ -1,0 +1,322 @@
+// Structured Givens QR of [M; I] for a b-banded symmetric M (Sec. 4, Algorithms 1 and 2) and the
+// direct HODLR construction of the orthogonal factor (Remark construct_off and Theorems
+// ranks_tridiag / ranks_banded).
+//
+// The rotation sweep is inherently sequential and O(b^2 n); it runs on the host, as in the
+// paper.  The Q factors are then assembled block by block:
+//  * leaves: the rows [lo, hi) of Q1 and of Q2 are replayed densely from the first step that can
+//    touch them (lo - b) to the last step of the leaf (hi - 1);
+//  * after step k, the rows 0..k of Q live, outside the finished columns, in the span of the 2b
+//    "active" columns {k+1..k+b, n, n+k+1..n+k+b-1} (proof of Theorem ranks_banded), so the
+//    upper block of node [lo, hi) = (a, b) is U V^T with U = those active columns restricted to
+//    the rows of a at step mid-1, and V the coefficients of the columns of b in that basis,
+//    obtained by replaying only the rotations of steps mid..hi-1 on 2b-vectors;
+//  * the basis of a parent is the children's bases glued together ([U_a C; U_b]), so nothing of
+//    size larger than the block itself is ever formed.
+#include "givens.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+#include "engine.h"
+
+namespace hq {
+
+namespace {
+
+// A row of R kept as a short window of columns [c0, c0 + W).
+struct RowStore {
+  int W;
+  std::vector<int64_t> c0;
+  std::vector<double> v;
+  double* row(int64_t r) { return v.data() + (size_t)r * W; }
+  double get(int64_t r, int64_t col) {
+    const int64_t k = col - c0[r];
+    return (k >= 0 && k < W) ? v[(size_t)r * W + k] : 0.0;
+  }
+};
+
+inline void make_rot(double f, double g, double& c, double& s) {
+  const double r = std::hypot(f, g);
+  if (r == 0.0) {
+    c = 1.0;
+    s = 0.0;
+  } else {
+    c = f / r;
+    s = g / r;
+  }
+}
+
+}  // namespace
+
+GivensSweep structured_qr(const double* ab, int64_t n, int b, int64_t ldab, double shift, double scale) {
+  GivensSweep g;
+  RowStore R;
+  R.W = 4 * b + 8;
+  const int W = R.W;
+  R.c0.assign(2 * n, 0);
+  R.v.assign((size_t)2 * n * W, 0.0);
+  // rows 0..n-1: scale * (A - shift I); window starts at column i - b
+  for (int64_t i = 0; i < n; ++i) {
+    R.c0[i] = i - b;
+    double* r = R.row(i);
+    for (int64_t j = std::max<int64_t>(0, i - b); j <= std::min<int64_t>(n - 1, i + b); ++j) {
+      const int64_t d = i >= j ? i - j : j - i, col = std::min(i, j);
+      double v = ab[d + col * ldab];
+      if (i == j) v -= shift;
+      r[j - (i - b)] = scale * v;
+    }
+  }
+  // rows n..2n-1: identity rows; row n is the one all beta rotations act on
+  for (int64_t i = 0; i < n; ++i) {
+    R.c0[n + i] = i;
+    R.row(n + i)[0] = 1.0;
+  }
+  std::vector<double> tp(2 * W), tq(2 * W);
+  auto store = [&](int64_t r, const double* t, int64_t lo, int64_t span) {
+    int64_t first = -1, last = -1;
+    for (int64_t k = 0; k < span; ++k)
+      if (t[k] != 0.0) {
+        if (first < 0) first = k;
+        last = k;
+      }
+    double* out = R.row(r);
+    std::fill(out, out + W, 0.0);
+    if (first < 0) return;
+    if (last - first >= W) throw std::runtime_error("structured_qr: row window overflow");
+    for (int64_t k = first; k <= last; ++k) out[k - first] = t[k];
+    R.c0[r] = lo + first;
+  };
+  // rotation in rows (P, Q) chosen so that R(Q, col) becomes zero
+  auto rot = [&](int64_t P, int64_t Q, int64_t col) {
+    double c, s;
+    make_rot(R.get(P, col), R.get(Q, col), c, s);
+    g.rots.push_back({P, Q, c, s});
+    const int64_t lo = std::min(R.c0[P], R.c0[Q]);
+    const int64_t span = std::max(R.c0[P], R.c0[Q]) + W - lo;
+    for (int64_t k = 0; k < span; ++k) {
+      const double x = R.get(P, lo + k), y = R.get(Q, lo + k);
+      tp[k] = c * x + s * y;
+      tq[k] = -s * x + c * y;
+    }
+    tq[col - lo] = 0.0;
+    store(P, tp.data(), lo, span);
+    store(Q, tq.data(), lo, span);
+  };
+  g.step.reserve(n + 1);
+  for (int64_t i = 0; i < n; ++i) {
+    g.step.push_back((int64_t)g.rots.size());
+    if (i == 0) {
+      rot(0, n, 0);                                                  // beta_1
+      for (int64_t j = 1; j <= std::min<int64_t>(n - 1, b); ++j) rot(0, j, 0);  // gamma_{1,j}
+      continue;
+    }
+    rot(n, n + i, i);                                                // alpha_{i,i}
+    for (int64_t j = i + 1; j <= std::min<int64_t>(n - 1, b + i - 1); ++j) rot(n + j, n + i, j);  // alpha_{i,j}
+    rot(i, n, i);                                                    // beta_i
+    if (i < n - 1)
+      for (int64_t j = i + 1; j <= std::min<int64_t>(n - 1, b + i); ++j) rot(i, j, i);  // gamma_{i,j}
+  }
+  g.step.push_back((int64_t)g.rots.size());
+  return g;
+}
+
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+// Active column set after 0-based step k: {k+1..k+b, n, n+k+1..n+k+b-1}; -1 marks a column
+// beyond the matrix (its coefficient stays zero).
+std::vector<int64_t> active_set(int64_t k, int64_t n, int b) {
+  std::vector<int64_t> a;
+  for (int j = 1; j <= b; ++j) a.push_back(k + j < n ? k + j : -1);
+  a.push_back(n);
+  for (int j = 1; j <= b - 1; ++j) a.push_back(k + j < n ? n + k + j : -1);
+  return a;
+}
+
+// column map for a window [lo0, hi0) of the first n columns, column n, and n + [lo0, hi0)
+struct ColMap {
+  int64_t n, lo0, w;
+  int size() const { return (int)(2 * w + 1); }
+  int operator()(int64_t col) const {
+    if (col < n) {
+      const int64_t k = col - lo0;
+      return (k >= 0 && k < w) ? (int)k : -1;
+    }
+    if (col == n) return (int)w;
+    const int64_t k = col - n - lo0;
+    return (k >= 0 && k < w) ? (int)(w + 1 + k) : -1;
+  }
+};
+
+}  // namespace
+
+void q_factors_hodlr(const GivensSweep& g, const Tree& t, int b, const std::vector<int>& cap, int ldl,
+                     HostHodlr& q1, HostHodlr& q2) {
+  const int64_t n = t.n;
+  const int L = t.L, B2 = 2 * b;
+  for (int l = 0; l < L; ++l)
+    if (cap[l] < B2) throw std::runtime_error("q_factors_hodlr: capacity below 2b");
+  for (HostHodlr* h : {&q1, &q2}) {
+    h->leaves.assign((size_t)t.nleaves * ldl * ldl, 0.0);
+    h->U.assign(L, {});
+    h->V.assign(L, {});
+    for (int l = 0; l < L; ++l) {
+      h->U[l].assign((size_t)(2 << l) * t.ldf[l] * cap[l], 0.0);
+      h->V[l].assign((size_t)(2 << l) * t.ldf[l] * cap[l], 0.0);
+    }
+    h->rank.assign(std::max(1, 2 * t.ninternal), 0);
+  }
+  // basis of each node's rows (Q1 rows then Q2 rows) x 2b, at the end of the node's last step
+  std::vector<std::vector<double>> basis(t.nnodes);
+  // lower-left corner of Q1 next to the first leaf of every right subtree: rows lo..lo+b-1, cols lo-b..lo-1
+  std::vector<std::vector<double>> corner(t.nleaves);
+
+  auto stepbeg = [&](int64_t i) { return g.step[std::max<int64_t>(0, std::min<int64_t>(i, n))]; };
+
+  // ---- leaves
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int li = 0; li < t.nleaves; ++li) {
+    const int p = t.ninternal + li;
+    const int64_t lo = t.lo[p], hi = t.hi[p], m = hi - lo;
+    ColMap cm{n, lo - b, m + 2 * b};
+    const int nc = cm.size();
+    const int64_t rows = 2 * m;
+    std::vector<double> D((size_t)rows * nc, 0.0);  // column-major rows x nc
+    auto at = [&](int64_t r, int c) -> double& { return D[(size_t)c * rows + r]; };
+    for (int64_t r = 0; r < m; ++r) {
+      at(r, cm(lo + r)) = 1.0;
+      at(m + r, cm(n + lo + r)) = 1.0;
+    }
+    for (int64_t k = stepbeg(lo - b); k < stepbeg(hi); ++k) {
+      const Rot& R = g.rots[k];
+      const int ip = cm(R.p), iq = cm(R.q);
+      if (ip < 0 || iq < 0) throw std::runtime_error("q_factors_hodlr: leaf window");
+      double* x = &D[(size_t)ip * rows];
+      double* y = &D[(size_t)iq * rows];
+      for (int64_t r = 0; r < rows; ++r) {
+        const double u = x[r], w = y[r];
+        x[r] = R.c * u + R.s * w;
+        y[r] = -R.s * u + R.c * w;
+      }
+    }
+    double* L1 = q1.leaves.data() + (size_t)li * ldl * ldl;
+    double* L2 = q2.leaves.data() + (size_t)li * ldl * ldl;
+    for (int64_t c = 0; c < m; ++c)
+      for (int64_t r = 0; r < m; ++r) {
+        L1[r + c * ldl] = at(r, cm(lo + c));
+        L2[r + c * ldl] = at(m + r, cm(lo + c));
+      }
+    if (lo > 0) {
+      corner[li].assign((size_t)b * b, 0.0);
+      for (int tr = 0; tr < b; ++tr)
+        for (int j = 0; j < b; ++j) corner[li][tr + (size_t)j * b] = at(tr, cm(lo - b + j));
+    }
+    std::vector<double>& Bs = basis[p];
+    Bs.assign((size_t)rows * B2, 0.0);
+    const std::vector<int64_t> act = active_set(hi - 1, n, b);
+    for (int k = 0; k < B2; ++k) {
+      if (act[k] < 0) continue;
+      const int ic = cm(act[k]);
+      if (ic < 0) throw std::runtime_error("q_factors_hodlr: active column outside leaf window");
+      for (int64_t r = 0; r < rows; ++r) Bs[(size_t)k * rows + r] = at(r, ic);
+    }
+  }
+
+  // ---- internal nodes, bottom-up
+  for (int l = L - 1; l >= 0; --l) {
+    const int f0 = (1 << l) - 1, cnt = 1 << l;
+    const int64_t ldf = t.ldf[l];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = f0; p < f0 + cnt; ++p) {
+      const int a = 2 * p + 1, bb = 2 * p + 2, i = p - f0;
+      const int64_t lo = t.lo[p], mid = t.mid(p), hi = t.hi[p];
+      const int64_t ma = mid - lo, mb = hi - mid;
+      // coefficient replay over steps mid..hi-1
+      ColMap cm{n, mid, (hi - mid) + b + 1};
+      const int nc = cm.size();
+      std::vector<double> Cf((size_t)B2 * nc, 0.0);  // column c of Q -> 2b coefficients
+      const std::vector<int64_t> act0 = active_set(mid - 1, n, b);
+      for (int k = 0; k < B2; ++k)
+        if (act0[k] >= 0) {
+          const int ic = cm(act0[k]);
+          if (ic < 0) throw std::runtime_error("q_factors_hodlr: start basis outside window");
+          Cf[(size_t)ic * B2 + k] = 1.0;
+        }
+      for (int64_t k = stepbeg(mid); k < stepbeg(hi); ++k) {
+        const Rot& R = g.rots[k];
+        const int ip = cm(R.p), iq = cm(R.q);
+        if (ip < 0 || iq < 0) throw std::runtime_error("q_factors_hodlr: node window");
+        double* x = &Cf[(size_t)ip * B2];
+        double* y = &Cf[(size_t)iq * B2];
+        for (int r = 0; r < B2; ++r) {
+          const double u = x[r], w = y[r];
+          x[r] = R.c * u + R.s * w;
+          y[r] = -R.s * u + R.c * w;
+        }
+      }
+      const std::vector<double>& Ba = basis[a];  // (2 ma) x 2b
+      const int cp = cap[l];
+      const size_t off0 = (size_t)(2 * i) * ldf * cp, off1 = (size_t)(2 * i + 1) * ldf * cp;
+      // upper blocks: U = basis rows of a (Q1 part / Q2 part), V(j - mid, :) = coefficients of column j
+      for (int k = 0; k < B2; ++k) {
+        for (int64_t r = 0; r < ma; ++r) {
+          q1.U[l][off0 + r + (size_t)k * ldf] = Ba[(size_t)k * 2 * ma + r];
+          q2.U[l][off0 + r + (size_t)k * ldf] = Ba[(size_t)k * 2 * ma + ma + r];
+        }
+        for (int64_t j = 0; j < mb; ++j) {
+          const double v = Cf[(size_t)cm(mid + j) * B2 + k];
+          q1.V[l][off0 + j + (size_t)k * ldf] = v;
+          q2.V[l][off0 + j + (size_t)k * ldf] = v;
+        }
+      }
+      q1.rank[2 * p] = B2;
+      q2.rank[2 * p] = B2;
+      // lower block of Q1: the b x b corner rows mid..mid+b-1, cols mid-b..mid-1
+      const int lf = (int)(((int64_t)(bb + 1) << (L - l - 1)) - 1) - t.ninternal;  // first leaf under bb
+      const std::vector<double>& cr = corner[lf];
+      for (int tr = 0; tr < b; ++tr) {
+        q1.U[l][off1 + tr + (size_t)tr * ldf] = 1.0;
+        for (int j = 0; j < b; ++j) q1.V[l][off1 + (ma - b + j) + (size_t)tr * ldf] = cr[tr + (size_t)j * b];
+      }
+      q1.rank[2 * p + 1] = b;
+      q2.rank[2 * p + 1] = 0;
+      // basis of p at the end of step hi-1
+      if (p > 0) {
+        const std::vector<int64_t> act1 = active_set(hi - 1, n, b);
+        std::vector<double> Cend((size_t)B2 * B2, 0.0);
+        for (int k = 0; k < B2; ++k)
+          if (act1[k] >= 0) {
+            const int ic = cm(act1[k]);
+            if (ic < 0) throw std::runtime_error("q_factors_hodlr: end basis outside window");
+            for (int r = 0; r < B2; ++r) Cend[(size_t)k * B2 + r] = Cf[(size_t)ic * B2 + r];
+          }
+        const std::vector<double>& Bb = basis[bb];  // (2 mb) x 2b
+        const int64_t rows = 2 * (ma + mb);
+        std::vector<double>& Bp = basis[p];
+        Bp.assign((size_t)rows * B2, 0.0);
+        for (int k = 0; k < B2; ++k) {
+          for (int part = 0; part < 2; ++part) {
+            // rows of a in this part
+            for (int64_t r = 0; r < ma; ++r) {
+              double s = 0.0;
+              for (int q = 0; q < B2; ++q) s += Ba[(size_t)q * 2 * ma + part * ma + r] * Cend[(size_t)k * B2 + q];
+              Bp[(size_t)k * rows + part * (ma + mb) + r] = s;
+            }
+            for (int64_t r = 0; r < mb; ++r)
+              Bp[(size_t)k * rows + part * (ma + mb) + ma + r] = Bb[(size_t)k * 2 * mb + part * mb + r];
+          }
+        }
+      }
+    }
+    // children bases are no longer needed
+    for (int p = f0; p < f0 + cnt; ++p) {
+      std::vector<double>().swap(basis[2 * p + 1]);
+      std::vector<double>().swap(basis[2 * p + 2]);
+    }
+  }
+}
+
+}  // namespace hq

@@ -1,0 +1,119 @@
+// Device kernels of the HODLR-QDWH path (gfx950).  Host-side launch wrappers.
+//
+// Every batched kernel takes an array of task descriptors in device memory.  Sizes that are
+// only known on the device (off-diagonal ranks, stacked widths) are read through `const int*`
+// fields; the matching static field is then an upper bound used to size the grid, and tiles
+// beyond the live size exit at once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hq {
+
+// C = alpha * op(A) * op(B) + beta * C, column-major, op = N (0) or T (1).
+struct GemmTask {
+  const double* A;
+  const double* B;
+  double* C;
+  const int* mp;  // if non-null, m = *mp (else m)
+  const int* np;
+  const int* kp;
+  int m, n, k;    // static sizes (upper bounds when the pointer is set)
+  int lda, ldb, ldc;
+  int opA, opB;
+  double alpha, beta;
+};
+
+// dst[:, off_s : off_s + w_s] = scale_s * src_s[:, 0 : w_s] for s = 0..nsrc-1, off_s = sum of previous widths.
+struct StackSrc {
+  const double* p;
+  const int* wp;  // dynamic width (or null -> w)
+  int ld, w;
+  double scale;
+};
+struct StackTask {
+  double* dst;
+  int* wout;      // receives the total width (may be null)
+  int ld, rows, nsrc, wcap;  // wcap: capacity of dst in columns (overflow -> flag)
+  StackSrc src[4];
+};
+
+// R-only Householder QR of a tall matrix, tree-reduced (TSQR).  Stage 0 copies a row tile of
+// the source into a workspace slot and triangularises it; stage s >= 1 stacks the triangle of
+// slot i + 2^(s-1) under that of slot i and triangularises again.  After the last stage slot 0
+// holds R (min(rows, r) x r, upper trapezoidal), copied to R (ldr) with zero padding to r x r.
+struct QrTask {
+  const double* M;   // source (rows x r), ld = ldm
+  const int* rp;     // live column count r
+  double* work;      // ntiles slots of (hs x rcap)
+  double* R;         // output r x r
+  int ldm, rows, rcap, hs, h0, ntiles, ldr;
+};
+
+// One-sided Jacobi SVD of B (r x r) with accumulated right rotations J, sorted by singular
+// value, truncated at sigma > thresh (and capped at kcap; overflow -> flag).
+//   Jk[:, i] = J[:, perm(i)],  Wk[:, i] = (B J)[:, perm(i)] / sigma_i^2  (i < k')
+struct SvdTask {
+  double* B;         // r x r, overwritten by B J
+  double* J;         // r x r accumulator
+  double* Wk;        // r x k' output: (B J)[:, perm] / sigma^2
+  double* Jk;        // r x k' output: J[:, perm]
+  double* sig;       // r sorted singular values (may be null)
+  const int* rp;
+  int* kout;         // receives k'
+  int ld, kcap;
+  double thresh;
+};
+
+// Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.
+struct LeafTask {
+  double* A;
+  double* B;    // second operand (trtri output)
+  int m, lda, ldb;
+};
+
+// Band -> HODLR of X0 = (A - shift I) / scale.
+struct BandDesc {
+  const double* ab;
+  int64_t n, ldab;
+  int b;
+  double shift, inv_scale;
+};
+
+void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, hipStream_t s);
+void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s);
+void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int hs_max, int rcap_max,
+                     hipStream_t s);
+void launch_qr_final(const QrTask* d_tasks, int ntasks, int rcap_max, hipStream_t s);
+void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s);
+void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s);
+void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s);
+// leaves: out = alpha*X + beta*op(X)^T + gamma*I over m x m tiles (symmetrise / identity shifts)
+struct LeafAxpy {
+  double* out;
+  const double* X;
+  const double* Y;
+  int m, ldo, ldx, ldy;
+  int transY;
+  double alpha, beta, gamma;
+};
+void launch_leaf_axpy(const LeafAxpy* d_tasks, int ntasks, int max_m, hipStream_t s);
+void launch_fill_int(int* p, int value, int count, hipStream_t s);
+void launch_copy_int(int* dst, const int* src, int count, hipStream_t s);
+void launch_band_leaves(BandDesc bd, double* leaves, int ldl, const int64_t* d_leaf_lo, const int* d_leaf_m,
+                        int nleaves, hipStream_t s);
+struct BandBlockTask {
+  double* Ul;     // rows b (lower block), ld ldu
+  double* Vl;
+  double* Uu;
+  double* Vu;
+  int* rank_l;
+  int* rank_u;
+  int64_t mid;
+  int rows_b, rows_a, ldf;
+};
+void launch_band_blocks(BandDesc bd, const BandBlockTask* d_tasks, int ntasks, int max_rows, hipStream_t s);
+// max over per-task ints (stats)
+void launch_scale_cols(double* p, int ld, int rows, const int* wp, double scale, hipStream_t s);
+
+}  // namespace hq

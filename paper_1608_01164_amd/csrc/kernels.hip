@@ -1,0 +1,557 @@
+// Device kernels of the HODLR-QDWH path, written for CDNA4 (gfx950): 64-wide wavefronts,
+// FP64 MFMA (v_mfma_f64_16x16x4f64), LDS staging.  All kernels are batched over a task array and
+// read live sizes (ranks) from device memory, so a whole QDWH iteration can be issued without a
+// device-to-host synchronisation.
+#include "kernels.h"
+
+#include <cfloat>
+#include <cmath>
+
+namespace hq {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+static __device__ __forceinline__ int live(const int* p, int v) {
+  if (!p) return v;
+  int x = *p;
+  return x < v ? x : v;
+}
+
+static __device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Batched GEMM, 64x64 output tile per workgroup (4 waves, 32x32 each = 2x2 MFMA 16x16 tiles),
+// K staged through LDS in chunks of 16.
+// ----------------------------------------------------------------------------------------------
+constexpr int GT = 64, GK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks, int tiles_n) {
+  const GemmTask T = tasks[blockIdx.y];
+  const int m = live(T.mp, T.m), n = live(T.np, T.n), k = live(T.kp, T.k);
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int row0 = tm * GT, col0 = tn * GT;
+  if (row0 >= m || col0 >= n) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+
+  for (int k0 = 0; k0 < k; k0 += GK) {
+    // stage A tile (rows row0.., k cols k0..)
+    if (T.opA == 0) {
+      const int i = tid & 63, kk0 = tid >> 6;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = kk0 + 4 * q, gi = row0 + i, gk = k0 + kk;
+        As[kk][i] = (gi < m && gk < k) ? T.A[gi + (size_t)gk * T.lda] : 0.0;
+      }
+    } else {
+      const int kk = tid & 15, i0 = tid >> 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 16 * q, gi = row0 + i, gk = k0 + kk;
+        As[kk][i] = (gi < m && gk < k) ? T.A[gk + (size_t)gi * T.lda] : 0.0;
+      }
+    }
+    if (T.opB == 0) {
+      const int kk = tid & 15, j0 = tid >> 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + 16 * q, gj = col0 + j, gk = k0 + kk;
+        Bs[kk][j] = (gj < n && gk < k) ? T.B[gk + (size_t)gj * T.ldb] : 0.0;
+      }
+    } else {
+      const int j = tid & 63, kk0 = tid >> 6;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = kk0 + 4 * q, gj = col0 + j, gk = k0 + kk;
+        Bs[kk][j] = (gj < n && gk < k) ? T.B[gj + (size_t)gk * T.ldb] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const double a0 = As[kk + lk][wr + li], a1 = As[kk + lk][wr + 16 + li];
+      const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D(i, j) of a 16x16 block sits in lane j + 16*(i/4), element i%4
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = row0 + wr + 16 * x + 4 * lk + e;
+        const int gj = col0 + wc + 16 * y + li;
+        if (gi < m && gj < n) {
+          double* c = T.C + gi + (size_t)gj * T.ldc;
+          const double v = T.alpha * acc[x][y][e];
+          *c = (T.beta == 0.0) ? v : v + T.beta * *c;
+        }
+      }
+}
+
+void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, hipStream_t s) {
+  if (ntasks <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tm = (max_m + GT - 1) / GT, tn = (max_n + GT - 1) / GT;
+  for (int t0 = 0; t0 < ntasks; t0 += 65535) {
+    const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+    hipLaunchKernelGGL(k_gemm, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn);
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Column stacking with scaling at device-determined offsets.
+// ----------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stack(const StackTask* __restrict__ tasks, int* flag) {
+  const StackTask T = tasks[blockIdx.y];
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  int off = 0;
+  for (int s = 0; s < T.nsrc; ++s) {
+    const StackSrc& S = T.src[s];
+    int w = S.wp ? *S.wp : S.w;
+    if (off + w > T.wcap) {
+      w = T.wcap - off;
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 4);
+    }
+    if (row < T.rows)
+      for (int c = 0; c < w; ++c) T.dst[row + (size_t)(off + c) * T.ld] = S.scale * S.p[row + (size_t)c * S.ld];
+    off += w;
+  }
+  if (T.wout && blockIdx.x == 0 && threadIdx.x == 0) *T.wout = off;
+}
+
+void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int bx = max_rows > 0 ? (max_rows + 255) / 256 : 1;
+  for (int t0 = 0; t0 < ntasks; t0 += 65535) {
+    const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+    hipLaunchKernelGGL(k_stack, dim3(bx, nt), dim3(256), 0, s, d_tasks + t0, flag);
+  }
+}
+
+__global__ void k_scale_cols(double* p, int ld, int rows, const int* wp, double scale) {
+  const int w = *wp;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < rows * w; idx += gridDim.x * blockDim.x)
+    p[(idx % rows) + (size_t)(idx / rows) * ld] *= scale;
+}
+void launch_scale_cols(double* p, int ld, int rows, const int* wp, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_cols, dim3(64), dim3(256), 0, s, p, ld, rows, wp, scale);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Householder triangularisation of an h x r panel held in global memory (one workgroup).
+// ----------------------------------------------------------------------------------------------
+constexpr int QR_THREADS = 512;
+constexpr int QR_WAVES = QR_THREADS / 64;
+
+static __device__ void householder_rows(double* X, int ld, int h, int r, double* v) {
+  __shared__ double red[QR_WAVES];
+  __shared__ double sh_beta, sh_tau;
+  __shared__ int sh_skip;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jend = (h - 1 < r) ? h - 1 : r;
+  for (int j = 0; j < jend; ++j) {
+    double s = 0.0;
+    for (int i = j + 1 + tid; i < h; i += QR_THREADS) {
+      const double x = X[i + (size_t)j * ld];
+      s += x * x;
+    }
+    s = wave_sum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < QR_WAVES; ++w) t += red[w];
+      const double x0 = X[j + (size_t)j * ld];
+      if (t == 0.0) {
+        sh_skip = 1;
+      } else {
+        sh_skip = 0;
+        const double nrm = sqrt(x0 * x0 + t);
+        const double beta = x0 >= 0.0 ? -nrm : nrm;
+        const double v0 = x0 - beta;
+        sh_beta = beta;
+        sh_tau = 2.0 / (v0 * v0 + t);
+        v[0] = v0;
+      }
+    }
+    __syncthreads();
+    if (sh_skip) continue;
+    for (int i = j + 1 + tid; i < h; i += QR_THREADS) v[i - j] = X[i + (size_t)j * ld];
+    __syncthreads();
+    const double tau = sh_tau;
+    for (int c = j + 1 + wave; c < r; c += QR_WAVES) {
+      double* col = X + (size_t)c * ld;
+      double w = 0.0;
+      for (int i = j + lane; i < h; i += 64) w += v[i - j] * col[i];
+      w = wave_sum(w) * tau;
+      for (int i = j + lane; i < h; i += 64) col[i] -= w * v[i - j];
+    }
+    __syncthreads();
+    if (tid == 0) X[j + (size_t)j * ld] = sh_beta;
+    for (int i = j + 1 + tid; i < h; i += QR_THREADS) X[i + (size_t)j * ld] = 0.0;
+    __syncthreads();
+  }
+}
+
+// rows covered by slot a after stage s, capped at r
+static __device__ __forceinline__ int slot_live_rows(int a, int s, int h0, int rows, int r) {
+  long long end = (long long)(a + (1 << s)) * h0;
+  if (end > rows) end = rows;
+  long long cov = end - (long long)a * h0;
+  if (cov < 0) cov = 0;
+  return cov < r ? (int)cov : r;
+}
+
+__global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restrict__ tasks, int stage) {
+  extern __shared__ double vbuf[];
+  const QrTask T = tasks[blockIdx.y];
+  const int r = live(T.rp, T.rcap);
+  if (r <= 0) return;
+  const int tid = threadIdx.x;
+  if (stage == 0) {
+    const int t = blockIdx.x;
+    if (t >= T.ntiles) return;
+    const int r0 = t * T.h0;
+    int h = T.rows - r0;
+    if (h > T.h0) h = T.h0;
+    double* X = T.work + (size_t)t * T.hs * T.rcap;
+    for (int idx = tid; idx < h * r; idx += QR_THREADS) {
+      const int i = idx % h, c = idx / h;
+      X[i + (size_t)c * T.hs] = T.M[(r0 + i) + (size_t)c * T.ldm];
+    }
+    __syncthreads();
+    householder_rows(X, T.hs, h, r, vbuf);
+  } else {
+    const int half = 1 << (stage - 1);
+    const int a = blockIdx.x << stage, b = a + half;
+    if (b >= T.ntiles) return;
+    const int ra = slot_live_rows(a, stage - 1, T.h0, T.rows, r);
+    const int rb = slot_live_rows(b, stage - 1, T.h0, T.rows, r);
+    double* Xa = T.work + (size_t)a * T.hs * T.rcap;
+    const double* Xb = T.work + (size_t)b * T.hs * T.rcap;
+    for (int idx = tid; idx < rb * r; idx += QR_THREADS) {
+      const int i = idx % rb, c = idx / rb;
+      Xa[(ra + i) + (size_t)c * T.hs] = (i <= c) ? Xb[i + (size_t)c * T.hs] : 0.0;
+    }
+    __syncthreads();
+    householder_rows(Xa, T.hs, ra + rb, r, vbuf);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tasks) {
+  const QrTask T = tasks[blockIdx.x];
+  const int r = live(T.rp, T.rcap);
+  const int rr = T.rows < r ? T.rows : r;
+  for (int idx = threadIdx.x; idx < r * r; idx += 256) {
+    const int i = idx % r, c = idx / r;
+    T.R[i + (size_t)c * T.ldr] = (i < rr && i <= c) ? T.work[i + (size_t)c * T.hs] : 0.0;
+  }
+}
+
+void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int hs_max, int, hipStream_t s) {
+  if (ntasks <= 0 || max_pairs <= 0) return;
+  const size_t lds = sizeof(double) * (size_t)hs_max;
+  for (int t0 = 0; t0 < ntasks; t0 += 65535) {
+    const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+    hipLaunchKernelGGL(k_qr_stage, dim3(max_pairs, nt), dim3(QR_THREADS), lds, s, d_tasks + t0, stage);
+  }
+}
+void launch_qr_final(const QrTask* d_tasks, int ntasks, int, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_qr_final, dim3(ntasks), dim3(256), 0, s, d_tasks);
+}
+
+// ----------------------------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD with round-robin pair ordering; one wave per column pair.
+// ----------------------------------------------------------------------------------------------
+constexpr int SVD_THREADS = 1024;
+constexpr int SVD_WAVES = SVD_THREADS / 64;
+constexpr int SVD_RMAX = 2048;
+
+__global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__ tasks, int* flag) {
+  const SvdTask T = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int r = *T.rp;
+  if (r > SVD_RMAX) r = SVD_RMAX;
+  if (r <= 0) {
+    if (tid == 0) *T.kout = 0;
+    return;
+  }
+  double* B = T.B;
+  double* J = T.J;
+  const int ld = T.ld;
+  __shared__ int rotated;
+  __shared__ double sig2[SVD_RMAX];
+  __shared__ int perm[SVD_RMAX];
+  for (int idx = tid; idx < r * r; idx += SVD_THREADS) {
+    const int i = idx % r, c = idx / r;
+    J[i + (size_t)c * ld] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int rp = r + (r & 1);
+  const double tol = 4.0 * DBL_EPSILON * sqrt((double)r);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < rp - 1; ++round) {
+      for (int pi = wave; pi < rp / 2; pi += SVD_WAVES) {
+        const int x = pi, y = rp - 1 - pi;
+        int p = (x == 0) ? 0 : 1 + ((x - 1 + round) % (rp - 1));
+        int q = (y == 0) ? 0 : 1 + ((y - 1 + round) % (rp - 1));
+        if (p >= r || q >= r) continue;
+        if (p > q) { const int t = p; p = q; q = t; }
+        double* bp = B + (size_t)p * ld;
+        double* bq = B + (size_t)q * ld;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = lane; i < r; i += 64) {
+          const double u = bp[i], w = bq[i];
+          a += u * u;
+          b += w * w;
+          g += u * w;
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        g = wave_sum(g);
+        if (a > DBL_MIN && b > DBL_MIN && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+          const double zeta = (b - a) / (2.0 * g);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int i = lane; i < r; i += 64) {
+            const double u = bp[i], w = bq[i];
+            bp[i] = cs * u - sn * w;
+            bq[i] = sn * u + cs * w;
+          }
+          double* jp = J + (size_t)p * ld;
+          double* jq = J + (size_t)q * ld;
+          for (int i = lane; i < r; i += 64) {
+            const double u = jp[i], w = jq[i];
+            jp[i] = cs * u - sn * w;
+            jq[i] = sn * u + cs * w;
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  // singular values = column norms
+  for (int c = wave; c < r; c += SVD_WAVES) {
+    double s = 0.0;
+    for (int i = lane; i < r; i += 64) s += B[i + (size_t)c * ld] * B[i + (size_t)c * ld];
+    s = wave_sum(s);
+    if (lane == 0) sig2[c] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += SVD_THREADS) {
+    int pos = 0;
+    const double si = sig2[i];
+    for (int j = 0; j < r; ++j) pos += (sig2[j] > si) || (sig2[j] == si && j < i);
+    perm[pos] = i;
+  }
+  __syncthreads();
+  const double th2 = T.thresh * T.thresh;
+  int kk = 0;
+  for (int i = 0; i < r; ++i) kk += sig2[i] > th2;
+  if (kk > T.kcap) {
+    if (tid == 0) atomicOr(flag, 1);
+    kk = T.kcap;
+  }
+  if (tid == 0) *T.kout = kk;
+  if (T.sig)
+    for (int i = tid; i < r; i += SVD_THREADS) T.sig[i] = sqrt(sig2[perm[i]]);
+  double* Jk = T.Jk;
+  for (int idx = tid; idx < r * kk; idx += SVD_THREADS) {
+    const int i = idx % r, o = idx / r, c = perm[o];
+    Jk[i + (size_t)o * ld] = J[i + (size_t)c * ld];
+    T.Wk[i + (size_t)o * ld] = B[i + (size_t)c * ld] / sig2[c];
+  }
+}
+
+void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(SVD_THREADS), 0, s, d_tasks, flag);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Leaf Cholesky (lower, right-looking, in place) and lower-triangular inverse.
+// ----------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_potrf(const LeafTask* __restrict__ tasks, int* flag) {
+  const LeafTask T = tasks[blockIdx.x];
+  double* A = T.A;
+  const int m = T.m, ld = T.lda, tid = threadIdx.x;
+  __shared__ double piv;
+  for (int j = 0; j < m; ++j) {
+    if (tid == 0) {
+      double d = A[j + (size_t)j * ld];
+      if (!(d > 0.0)) {
+        atomicOr(flag, 2);
+        d = fabs(d) + DBL_MIN;
+      }
+      d = sqrt(d);
+      A[j + (size_t)j * ld] = d;
+      piv = d;
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int i = j + 1 + tid; i < m; i += 256) A[i + (size_t)j * ld] *= inv;
+    __syncthreads();
+    const int w = m - j - 1;
+    for (int idx = tid; idx < w * w; idx += 256) {
+      const int i = j + 1 + idx % w, c = j + 1 + idx / w;
+      if (c <= i) A[i + (size_t)c * ld] -= A[i + (size_t)j * ld] * A[c + (size_t)j * ld];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * m; idx += 256) {
+    const int i = idx % m, c = idx / m;
+    if (i < c) A[i + (size_t)c * ld] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ tasks) {
+  const LeafTask T = tasks[blockIdx.x];
+  const double* L = T.A;
+  double* X = T.B;
+  const int m = T.m, tid = threadIdx.x;
+  for (int idx = tid; idx < m * m; idx += 256) {
+    const int i = idx % m, c = idx / m;
+    X[i + (size_t)c * T.ldb] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    const double inv = 1.0 / L[k + (size_t)k * T.lda];
+    for (int c = tid; c <= k; c += 256) X[k + (size_t)c * T.ldb] *= inv;
+    __syncthreads();
+    const int rows = m - k - 1, cols = k + 1;
+    for (int idx = tid; idx < rows * cols; idx += 256) {
+      const int i = k + 1 + idx % rows, c = idx / rows;
+      X[i + (size_t)c * T.ldb] -= L[i + (size_t)k * T.lda] * X[k + (size_t)c * T.ldb];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_potrf, dim3(ntasks), dim3(256), 0, s, d_tasks, flag);
+}
+void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_trtri, dim3(ntasks), dim3(256), 0, s, d_tasks);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Leaf-level elementwise: out = alpha*X + beta*op(Y) + gamma*I.
+// ----------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_leaf_axpy(const LeafAxpy* __restrict__ tasks) {
+  const LeafAxpy T = tasks[blockIdx.y];
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= T.m * T.m) return;
+  const int i = idx % T.m, c = idx / T.m;
+  double v = T.gamma * (i == c ? 1.0 : 0.0);
+  if (T.alpha != 0.0) v += T.alpha * T.X[i + (size_t)c * T.ldx];
+  if (T.beta != 0.0) v += T.beta * (T.transY ? T.Y[c + (size_t)i * T.ldy] : T.Y[i + (size_t)c * T.ldy]);
+  T.out[i + (size_t)c * T.ldo] = v;
+}
+void launch_leaf_axpy(const LeafAxpy* d_tasks, int ntasks, int max_m, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int bx = (max_m * max_m + 255) / 256;
+  for (int t0 = 0; t0 < ntasks; t0 += 65535) {
+    const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+    hipLaunchKernelGGL(k_leaf_axpy, dim3(bx, nt), dim3(256), 0, s, d_tasks + t0);
+  }
+}
+
+__global__ void k_fill_int(int* p, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_copy_int(int* d, const int* s, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+void launch_fill_int(int* p, int value, int count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, s, p, value, count);
+}
+void launch_copy_int(int* dst, const int* src, int count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_copy_int, dim3((count + 255) / 256), dim3(256), 0, s, dst, src, count);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Band -> HODLR of X0 = (A - shift I) * inv_scale.  Exact: leaves are the dense band pieces and
+// every off-diagonal block is the b x b corner next to the diagonal, stored with rank b.
+// ----------------------------------------------------------------------------------------------
+static __device__ __forceinline__ double band_at(const BandDesc& bd, int64_t i, int64_t j) {
+  int64_t d = i - j;
+  if (d < 0) { d = -d; const int64_t t = i; i = j; j = t; }
+  if (d > bd.b) return 0.0;
+  return bd.ab[d + j * bd.ldab];
+}
+
+__global__ __launch_bounds__(256) void k_band_leaves(BandDesc bd, double* leaves, int ldl, const int64_t* lo,
+                                                     const int* ms) {
+  const int leaf = blockIdx.y, m = ms[leaf];
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= m * m) return;
+  const int i = idx % m, c = idx / m;
+  const int64_t g0 = lo[leaf];
+  double v = band_at(bd, g0 + i, g0 + c) * bd.inv_scale;
+  if (i == c) v -= bd.shift * bd.inv_scale;
+  leaves[(size_t)leaf * ldl * ldl + i + (size_t)c * ldl] = v;
+}
+void launch_band_leaves(BandDesc bd, double* leaves, int ldl, const int64_t* d_leaf_lo, const int* d_leaf_m,
+                        int nleaves, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_leaves, dim3((ldl * ldl + 255) / 256, nleaves), dim3(256), 0, s, bd, leaves, ldl,
+                     d_leaf_lo, d_leaf_m);
+}
+
+__global__ __launch_bounds__(256) void k_band_blocks(BandDesc bd, const BandBlockTask* __restrict__ tasks) {
+  const BandBlockTask T = tasks[blockIdx.y];
+  const int b = bd.b, tid = blockIdx.x * 256 + threadIdx.x;
+  // lower block rows [mid, mid+rows_b) x cols [mid-rows_a, mid): Ul = [I_b; 0], Vl = corner^T
+  if (tid < T.rows_b * b) {
+    const int i = tid % T.rows_b, t = tid / T.rows_b;
+    const double u = (i == t) ? 1.0 : 0.0;
+    T.Ul[i + (size_t)t * T.ldf] = u;
+    T.Vu[i + (size_t)t * T.ldf] = u;
+  }
+  if (tid < T.rows_a * b) {
+    const int jj = tid % T.rows_a, t = tid / T.rows_a;
+    const int64_t gi = T.mid + t, gj = T.mid - T.rows_a + jj;
+    const double v = (gj >= T.mid - b) ? band_at(bd, gi, gj) * bd.inv_scale : 0.0;
+    T.Vl[jj + (size_t)t * T.ldf] = v;
+    T.Uu[jj + (size_t)t * T.ldf] = v;
+  }
+  if (tid == 0) {
+    *T.rank_l = b;
+    *T.rank_u = b;
+  }
+}
+void launch_band_blocks(BandDesc bd, const BandBlockTask* d_tasks, int ntasks, int max_rows, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int bx = (max_rows * bd.b + 255) / 256;
+  hipLaunchKernelGGL(k_band_blocks, dim3(bx, ntasks), dim3(256), 0, s, bd, d_tasks);
+}
+
+}  // namespace hq

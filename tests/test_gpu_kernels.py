@@ -1,0 +1,132 @@
+"""Each building block of the HIP path through the C ABI, against numpy FP64 references."""
+import numpy as np
+import pytest
+
+import paper_1608_01164_amd as hq
+from oracle import hodlr as oh
+from tests.gpu_util import dev, empty, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("m,n,k,opA,opB", [
+    (1, 1, 1, 0, 0), (64, 64, 16, 0, 0), (65, 63, 17, 0, 1), (130, 7, 300, 1, 0), (33, 129, 5, 1, 1),
+    (1000, 40, 40, 0, 0), (40, 40, 3000, 1, 0), (7, 3, 0, 0, 0)])
+def test_gemm(m, n, k, opA, opB):
+    rng = np.random.default_rng(m * 7 + n)
+    A = rng.standard_normal((k, m) if opA else (m, k))
+    B = rng.standard_normal((n, k) if opB else (k, n))
+    C = rng.standard_normal((m, n))
+    dA, dB, dC = dev(A), dev(B), dev(C)
+    hq.test_gemm(dA, dB, dC, m, n, k, A.shape[0], B.shape[0], m, opA, opB, 1.5, -0.5)
+    ref = 1.5 * (A.T if opA else A) @ (B.T if opB else B) - 0.5 * C
+    got = host(dC, m, n)
+    assert np.abs(got - ref).max() <= 1e-13 * max(1.0, k) ** 0.5 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("rows,r", [(1, 1), (5, 9), (64, 64), (300, 20), (2000, 37), (9000, 64), (700, 200)])
+def test_qr_r(rows, r):
+    rng = np.random.default_rng(rows + r)
+    M = rng.standard_normal((rows, r)) * np.logspace(0, -12, r)[None, :]
+    dM = dev(M)
+    dR = empty(r, r)
+    hq.test_qr_r(dM, rows, r, rows, dR)
+    R = host(dR, r, r)
+    assert np.abs(np.tril(R, -1)).max() == 0.0
+    Rn = np.linalg.qr(M, mode="r")
+    kk = min(rows, r)
+    # R is unique up to row signs
+    assert np.abs(np.abs(R[:kk]) - np.abs(Rn[:kk])).max() < 1e-12 * np.abs(Rn).max()
+    if rows < r:
+        assert np.abs(R[kk:]).max() == 0.0
+
+
+@pytest.mark.parametrize("m,n,r,decay", [(50, 60, 10, 1.0), (300, 200, 40, 0.6), (1200, 900, 90, 0.8),
+                                         (64, 64, 64, 0.5), (10, 400, 30, 0.3)])
+def test_recompress(m, n, r, decay):
+    rng = np.random.default_rng(m + n + r)
+    s = decay ** np.arange(r)
+    Uq, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    kk = min(m, n, r)
+    Us = Uq[:, :kk] * s[:kk]
+    Vs = Vq[:, :kk]
+    # stack redundant copies so that recompression has something to remove
+    Us2 = np.hstack([Us, 0.5 * Us[:, : kk // 2]])
+    Vs2 = np.hstack([Vs, Vs[:, : kk // 2]])
+    rr = Us2.shape[1]
+    M = Us2 @ Vs2.T
+    tol = 1e-10
+    U, V = empty(m, rr), empty(n, rr)
+    k = hq.test_recompress(dev(Us2), m, dev(Vs2), n, rr, tol, rr, U, V)
+    sv = np.linalg.svd(M, compute_uv=False)
+    assert k == int(np.sum(sv > tol))
+    Uh, Vh = host(U, m, k), host(V, n, k)
+    assert np.linalg.norm(Uh @ Vh.T - M, 2) <= tol + 1e-13 * sv[0]
+    assert np.abs(Vh.T @ Vh - np.eye(k)).max() < 1e-10
+
+
+def _kernel_matrix(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.uniform(0, 1, n))
+    return 1.0 / (1.0 + 30 * np.abs(x[:, None] - x[None, :])) + 0.1 * np.eye(n)
+
+
+@pytest.mark.parametrize("n,leaf", [(100, 16), (257, 32), (512, 64)])
+def test_from_dense_roundtrip(n, leaf):
+    K = _kernel_matrix(n, n)
+    H = hq.test_from_dense(dev(K), n, leaf, 1e-12, 128)
+    D = H.to_dense().cpu().numpy()
+    assert np.abs(D - K).max() < 1e-10
+    E = H.export()
+    assert np.abs(oh.to_dense(E) - K).max() < 1e-10
+    X = np.random.default_rng(1).standard_normal((n, 5))
+    import torch
+    Y = H.apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.abs(Y - K @ X).max() < 1e-9
+
+
+@pytest.mark.parametrize("n,leaf,tA,tB", [(200, 25, 0, 0), (333, 40, 1, 0), (256, 32, 0, 1), (512, 64, 1, 1)])
+def test_product(n, leaf, tA, tB):
+    A = _kernel_matrix(n, 1)
+    B = _kernel_matrix(n, 2) + 0.3 * np.triu(_kernel_matrix(n, 3), 1)
+    D = _kernel_matrix(n, 4)
+    tol = 1e-11
+    hA = hq.test_from_dense(dev(A), n, leaf, 1e-13, 200)
+    hB = hq.test_from_dense(dev(B), n, leaf, 1e-13, 200)
+    hD = hq.test_from_dense(dev(D), n, leaf, 1e-13, 200)
+    C = hq.test_product(hA, tA, hB, tB, 0.7, hD, 0, -1.3, 0, 200, tol)
+    ref = 0.7 * (A.T if tA else A) @ (B.T if tB else B) - 1.3 * D
+    got = C.to_dense().cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-9
+    # symmetric Z = I + c X^T X in lower storage
+    Z = hq.test_product(hA, 1, hA, 0, 2.0, None, 1, 1.0, 1, 200, tol)
+    Zd = oh.to_dense(Z.export())
+    Zref = np.eye(n) + 2.0 * A.T @ A
+    assert np.abs(np.tril(Zd) - np.tril(Zref)).max() < 1e-9
+
+
+@pytest.mark.parametrize("n,leaf", [(64, 64), (200, 25), (300, 37), (512, 64)])
+def test_cholesky_inverse(n, leaf):
+    A = _kernel_matrix(n, 5)
+    Z = np.eye(n) + 3.0 * A.T @ A
+    hZ = hq.test_from_dense(dev(Z), n, leaf, 1e-13, 200)
+    Li = hq.test_cholesky_inverse(hZ, 200, 1e-12)
+    G = oh.to_dense(Li.export())
+    Lref = np.linalg.cholesky(Z)
+    assert np.abs(np.triu(G, 1)).max() == 0.0
+    assert np.abs(G @ Z @ G.T - np.eye(n)).max() < 1e-9
+    assert np.abs(G - np.linalg.inv(Lref)).max() < 1e-9
+
+
+@pytest.mark.parametrize("n,b,leaf", [(64, 1, 8), (300, 1, 64), (257, 5, 40), (512, 8, 64)])
+def test_q_factors_device(n, b, leaf):
+    import workloads as w
+    from oracle import givens_qr as g
+    ab = w.tridiag_uniform(n, 2) if b == 1 else w.banded_normal(n, b, 2)
+    A = w.band_to_dense(ab)
+    Q, R, rots = g.fast_qr(1.7 * (A - 0.05 * np.eye(n)), b)
+    h1, h2, nr = hq.test_q_factors(ab, b, 0.05, 1.7, leaf)
+    assert nr == len(rots)
+    assert np.abs(oh.to_dense(h1.export()) - Q[:n, :n]).max() < 1e-13
+    assert np.abs(h2.to_dense().cpu().numpy() - Q[n:, :n]).max() < 1e-13
