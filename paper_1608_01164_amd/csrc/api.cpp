@@ -340,10 +340,7 @@ hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu
   E.tol = o.tol;
   hq::DevArena xa[2], it;
   auto alloc = [&](hq::DevArena& ar, const std::vector<int>& cap, bool lower) {
-    std::swap(E.persist, ar);
-    hq::HMat h = E.alloc_hmat(cap, lower);
-    std::swap(E.persist, ar);
-    return h;
+    return E.alloc_hmat_in(ar, cap, lower);
   };
   // X0
   hq::HMat X = alloc(xa[0], caps_from(t, beff, o.max_rank), false);

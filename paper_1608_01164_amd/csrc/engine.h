@@ -48,6 +48,9 @@ struct Tree {
 // Device bump allocator over large chunks (256-byte aligned).
 class DevArena {
  public:
+  DevArena() = default;
+  DevArena(const DevArena&) = delete;
+  DevArena& operator=(const DevArena&) = delete;
   ~DevArena();
   void* alloc(size_t bytes);
   template <class T>
@@ -68,6 +71,9 @@ class DevArena {
 // Host-pinned staging + device copies for task descriptors.
 class DescStage {
  public:
+  DescStage() = default;
+  DescStage(const DescStage&) = delete;
+  DescStage& operator=(const DescStage&) = delete;
   ~DescStage();
   template <class T>
   T* upload(const std::vector<T>& v, hipStream_t s) { return static_cast<T*>(up(v.data(), sizeof(T) * v.size(), s)); }
@@ -123,6 +129,8 @@ struct Thin {            // dense n_sub x w block (column-major) with a device w
 class Engine {
  public:
   Engine(hipStream_t s, const Tree* t);
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
   ~Engine();
   hipStream_t st;
   const Tree* t;
@@ -133,7 +141,8 @@ class Engine {
   double tol = 1e-10;
   int64_t launches = 0;
 
-  HMat alloc_hmat(const std::vector<int>& cap, bool lower_only = false);
+  HMat alloc_hmat(const std::vector<int>& cap, bool lower_only = false) { return alloc_hmat_in(persist, cap, lower_only); }
+  HMat alloc_hmat_in(DevArena& ar, const std::vector<int>& cap, bool lower_only = false);
   HView view(const HMat& h, bool trans = false) const { HView v; v.h = &h; v.trans = trans; v.zero = d_zero; return v; }
   void zero_ranks(HMat& h);
 

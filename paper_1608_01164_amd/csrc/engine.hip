@@ -130,21 +130,21 @@ Engine::~Engine() {
   if (d_flag) (void)hipFree(d_flag);
 }
 
-HMat Engine::alloc_hmat(const std::vector<int>& cap, bool lower_only) {
+HMat Engine::alloc_hmat_in(DevArena& ar, const std::vector<int>& cap, bool lower_only) {
   HMat h;
   h.t = t;
   h.cap = cap;
   h.lower_only = lower_only;
   h.ldl = (int)t->maxleaf;
-  h.leaves = persist.get<double>((size_t)t->nleaves * h.ldl * h.ldl);
+  h.leaves = ar.get<double>((size_t)t->nleaves * h.ldl * h.ldl);
   h.Ubase.resize(t->L);
   h.Vbase.resize(t->L);
   for (int l = 0; l < t->L; ++l) {
     const size_t per = (size_t)(2 << l) * t->ldf[l] * cap[l];
-    h.Ubase[l] = persist.get<double>(per);
-    h.Vbase[l] = persist.get<double>(per);
+    h.Ubase[l] = ar.get<double>(per);
+    h.Vbase[l] = ar.get<double>(per);
   }
-  h.rank = persist.get<int>(std::max(1, 2 * t->ninternal));
+  h.rank = ar.get<int>(std::max(1, 2 * t->ninternal));
   zero_ranks(h);
   return h;
 }

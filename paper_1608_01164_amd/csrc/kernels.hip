@@ -93,14 +93,14 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
     }
     __syncthreads();
   }
-  // D(i, j) of a 16x16 block sits in lane j + 16*(i/4), element i%4
+  // D(i, j) of a 16x16 block sits in lane j + 16*(i%4), element i/4
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gi = row0 + wr + 16 * x + 4 * lk + e;
+        const int gi = row0 + wr + 16 * x + lk + 4 * e;
         const int gj = col0 + wc + 16 * y + li;
         if (gi < m && gj < n) {
           double* c = T.C + gi + (size_t)gj * T.ldc;

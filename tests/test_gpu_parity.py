@@ -62,7 +62,8 @@ def test_sign_and_projector_consistent():
     S, _ = hq.qdwh_sign(_dev_band(ab), 1, ref.mu, leaf=50)
     P, _ = hq.spectral_projector(_dev_band(ab), 1, ref.mu, leaf=50)
     Sd, Pd = oh.to_dense(S.export()), oh.to_dense(P.export())
-    assert np.abs(Pd - 0.5 * (np.eye(400) - Sd)).max() < 1e-12
+    # both outputs are truncated independently at tol = 1e-10
+    assert np.abs(Pd - 0.5 * (np.eye(400) - Sd)).max() < 1e-9
     assert np.linalg.norm(Sd @ Sd - np.eye(400), 2) < 1e-8
 
 
