@@ -728,7 +728,7 @@ hq_status hq_test_from_dense(const double* dense, int64_t n, int64_t ld, const h
     std::unique_ptr<hq_hodlr_s> h(new hq_hodlr_s());
     h->t.build(n, o.leaf);
     const hq::Tree& t = h->t;
-    if (t.L > 0 && t.ldf[0] > 2048) return fail(HQ_ERR_UNSUPPORTED, "test compression limited to n <= 4096");
+    if (t.L > 0 && t.ldf[0] > 1024) return fail(HQ_ERR_UNSUPPORTED, "test compression limited to n <= 2048");
     hipStream_t st = (hipStream_t)stream;
     h->e.reset(new hq::Engine(st, &t));
     hq::Engine& e = *h->e;

@@ -291,18 +291,20 @@ void Engine::recompress(const std::vector<RecTask>& tasks) {
   std::vector<GemmTask> gB, gP, gUV;
   std::vector<SvdTask> sv;
   int maxtiles = 1, hsmax = 1, rmax = 1, kmax = 1, mmax = 1;
-  struct Bufs { double *Ru, *Rv, *B, *J, *Wk, *Jk, *Pu, *Pv; };
+  struct Bufs { double *Ru, *Rv, *B, *J, *Jw, *aux, *Wk, *Jk, *Pu, *Pv; };
   std::vector<Bufs> bufs(nt);
   for (int i = 0; i < nt; ++i) {
     const RecTask& T = tasks[i];
     const int rc = std::max(T.rcap, 1);
-    if (rc > 2048) throw std::runtime_error("recompress: stacked rank capacity above 2048");
+    if (rc > 1024) throw std::runtime_error("recompress: stacked rank capacity above 1024");
     Bufs& b = bufs[i];
     const size_t rr = (size_t)rc * rc;
     b.Ru = scratch.get<double>(rr);
     b.Rv = scratch.get<double>(rr);
     b.B = scratch.get<double>(rr);
     b.J = scratch.get<double>(rr);
+    b.Jw = scratch.get<double>(rr);
+    b.aux = scratch.get<double>(2 * (size_t)rc);
     b.Wk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     b.Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     b.Pu = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
@@ -334,8 +336,8 @@ void Engine::recompress(const std::vector<RecTask>& tasks) {
     g.m = g.n = g.k = rc; g.mp = g.np = g.kp = T.r; g.alpha = 1.0; g.beta = 0.0;
     gB.push_back(g);
     SvdTask s{};
-    s.B = b.B; s.J = b.J; s.Wk = b.Wk; s.Jk = b.Jk; s.sig = nullptr; s.rp = T.r; s.kout = T.rank;
-    s.ld = rc; s.kcap = T.kcap; s.thresh = T.thresh;
+    s.B = b.B; s.C = b.J; s.Jw = b.Jw; s.aux = b.aux; s.Wk = b.Wk; s.Jk = b.Jk; s.sig = nullptr; s.rp = T.r;
+    s.kout = T.rank; s.ld = rc; s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
     sv.push_back(s);
     GemmTask pu{};  // Pu = Rv^T Jk
     pu.A = b.Rv; pu.opA = 1; pu.lda = rc; pu.B = b.Jk; pu.ldb = rc; pu.C = b.Pu; pu.ldc = rc;
@@ -378,9 +380,12 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
   for (int i = 0; i < nt; ++i) {
     const SymTask& T = tasks[i];
     const int rc = std::max(T.rcap, 1);
+    if (rc > 1024) throw std::runtime_error("compress_sym: factor capacity above 1024");
     const QrPlan pl = plan_qr(T.m, rc);
     double* R = scratch.get<double>((size_t)rc * rc);
     double* J = scratch.get<double>((size_t)rc * rc);
+    double* Jw = scratch.get<double>((size_t)rc * rc);
+    double* aux = scratch.get<double>(2 * (size_t)rc);
     double* Wk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     double* Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     QrTask q{};
@@ -393,8 +398,8 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
     kmax = std::max(kmax, T.kcap);
     mmax = std::max(mmax, T.m);
     SvdTask s{};
-    s.B = R; s.J = J; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc; s.kcap = T.kcap;
-    s.thresh = T.thresh;
+    s.B = R; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc;
+    s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
     sv.push_back(s);
     GemmTask g{};  // out = S Jk
     g.A = T.S; g.lda = T.lds; g.B = Jk; g.ldb = rc; g.C = T.out; g.ldc = T.ldo;

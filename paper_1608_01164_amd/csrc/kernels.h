@@ -50,19 +50,23 @@ struct QrTask {
   int ldm, rows, rcap, hs, h0, ntiles, ldr;
 };
 
-// One-sided Jacobi SVD of B (r x r) with accumulated right rotations J, sorted by singular
-// value, truncated at sigma > thresh (and capped at kcap; overflow -> flag).
-//   Jk[:, i] = J[:, perm(i)],  Wk[:, i] = (B J)[:, perm(i)] / sigma_i^2  (i < k')
+// Truncated SVD of the small core B (r x r): Householder QR with column pivoting of B, stopped
+// once the trailing block's Frobenius norm is below qr_thresh (B Pi ~ Q_t R_t), then one-sided
+// Jacobi on R_t^T (r x t) with accumulated rotations J (t x t), sorted, truncated at
+// sigma > thresh and capped at kcap (overflow -> flag bit 0).  With B ~ U S V^T:
+//   Jk = V_k (r x k'),   Wk = U_k S_k^{-1} (r x k').
 struct SvdTask {
-  double* B;         // r x r, overwritten by B J
-  double* J;         // r x r accumulator
-  double* Wk;        // r x k' output: (B J)[:, perm] / sigma^2
-  double* Jk;        // r x k' output: J[:, perm]
+  double* B;         // r x r, destroyed
+  double* C;         // r x r workspace
+  double* Jw;        // r x r workspace (rotations when t exceeds the LDS copy)
+  double* aux;       // 2r workspace
+  double* Wk;        // r x kcap output
+  double* Jk;        // r x kcap output
   double* sig;       // r sorted singular values (may be null)
   const int* rp;
   int* kout;         // receives k'
   int ld, kcap;
-  double thresh;
+  double thresh, qr_thresh;
 };
 
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.

@@ -283,49 +283,176 @@ void launch_qr_final(const QrTask* d_tasks, int ntasks, int, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi SVD with round-robin pair ordering; one wave per column pair.
+// Core SVD: pivoted Householder QR (rank-revealing, early stop) + one-sided Jacobi on R_t^T.
+// One workgroup per core; columns are handled one per wave with lanes over rows.
 // ----------------------------------------------------------------------------------------------
 constexpr int SVD_THREADS = 1024;
 constexpr int SVD_WAVES = SVD_THREADS / 64;
-constexpr int SVD_RMAX = 2048;
+constexpr int SVD_RMAX = 2048;  // pivot bookkeeping; cores are limited to r <= SVD_RMAX / 2
+constexpr int SVD_JLDS = 96;  // rotations kept in LDS up to t = 96
+
+struct ArgMax { double v; int i; };
+
+static __device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v = __shfl_xor(a.v, o, 64);
+    const int i = __shfl_xor(a.i, o, 64);
+    if (v > a.v || (v == a.v && i < a.i)) { a.v = v; a.i = i; }
+  }
+  return a;
+}
 
 __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__ tasks, int* flag) {
   const SvdTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int r = *T.rp;
-  if (r > SVD_RMAX) r = SVD_RMAX;
+  if (r > SVD_RMAX / 2) r = SVD_RMAX / 2;
   if (r <= 0) {
     if (tid == 0) *T.kout = 0;
     return;
   }
   double* B = T.B;
-  double* J = T.J;
+  double* C = T.C;
+  double* tau = T.aux;
+  double* vhead = T.aux + r;
   const int ld = T.ld;
-  __shared__ int rotated;
-  __shared__ double sig2[SVD_RMAX];
+  __shared__ double cn[SVD_RMAX];     // squared norms of the trailing parts of the columns
   __shared__ int perm[SVD_RMAX];
-  for (int idx = tid; idx < r * r; idx += SVD_THREADS) {
-    const int i = idx % r, c = idx / r;
-    J[i + (size_t)c * ld] = (i == c) ? 1.0 : 0.0;
+  __shared__ double Jl[SVD_JLDS * SVD_JLDS];
+  __shared__ double redv[SVD_WAVES];
+  __shared__ ArgMax reda[SVD_WAVES];
+  __shared__ int sh_t, sh_p, rotated;
+  __shared__ double sh_beta, sh_tau;
+
+  // ---- phase 1: QR with column pivoting, stopped at trailing norm <= qr_thresh
+  for (int c = wave; c < r; c += SVD_WAVES) {
+    double s = 0.0;
+    for (int i = lane; i < r; i += 64) s += B[i + (size_t)c * ld] * B[i + (size_t)c * ld];
+    s = wave_sum(s);
+    if (lane == 0) { cn[c] = s; perm[c] = c; }
+  }
+  if (tid == 0) sh_t = r;
+  __syncthreads();
+  const double qth2 = T.qr_thresh * T.qr_thresh;
+  for (int j = 0; j < r; ++j) {
+    // trailing Frobenius norm and pivot
+    double s = 0.0;
+    ArgMax am{-1.0, 0x7fffffff};
+    for (int c = j + tid; c < r; c += SVD_THREADS) {
+      s += cn[c];
+      if (cn[c] > am.v) { am.v = cn[c]; am.i = c; }
+    }
+    s = wave_sum(s);
+    am = wave_argmax(am);
+    if (lane == 0) { redv[wave] = s; reda[wave] = am; }
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      ArgMax best = reda[0];
+      for (int w = 0; w < SVD_WAVES; ++w) {
+        tot += redv[w];
+        const ArgMax x = reda[w];
+        if (x.v > best.v || (x.v == best.v && x.i < best.i)) best = x;
+      }
+      sh_p = (tot <= qth2) ? -1 : best.i;
+      if (sh_p < 0) sh_t = j;
+    }
+    __syncthreads();
+    const int p = sh_p;
+    if (p < 0) break;
+    if (p != j) {  // swap columns j and p
+      for (int i = tid; i < r; i += SVD_THREADS) {
+        const double x = B[i + (size_t)j * ld];
+        B[i + (size_t)j * ld] = B[i + (size_t)p * ld];
+        B[i + (size_t)p * ld] = x;
+      }
+      if (tid == 0) {
+        const double x = cn[j]; cn[j] = cn[p]; cn[p] = x;
+        const int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
+      }
+    }
+    __syncthreads();
+    // Householder vector of column j (rows j..r-1)
+    double s2 = 0.0;
+    for (int i = j + 1 + tid; i < r; i += SVD_THREADS) s2 += B[i + (size_t)j * ld] * B[i + (size_t)j * ld];
+    s2 = wave_sum(s2);
+    if (lane == 0) redv[wave] = s2;
+    __syncthreads();
+    if (tid == 0) {
+      double t2 = 0.0;
+      for (int w = 0; w < SVD_WAVES; ++w) t2 += redv[w];
+      const double x0 = B[j + (size_t)j * ld];
+      if (t2 == 0.0) {
+        sh_beta = x0; sh_tau = 0.0; vhead[j] = 1.0; tau[j] = 0.0;
+      } else {
+        const double nrm = sqrt(x0 * x0 + t2);
+        const double beta = x0 >= 0.0 ? -nrm : nrm;
+        const double v0 = x0 - beta;
+        sh_beta = beta;
+        sh_tau = 2.0 / (v0 * v0 + t2);
+        vhead[j] = v0;
+        tau[j] = sh_tau;
+      }
+    }
+    __syncthreads();
+    const double tj = sh_tau, vj = vhead[j];
+    const double* vcol = B + (size_t)j * ld;  // v_i = B[i, j] for i > j, v_j = vj
+    for (int c = j + 1 + wave; c < r; c += SVD_WAVES) {
+      double* col = B + (size_t)c * ld;
+      double w = (lane == 0) ? vj * col[j] : 0.0;
+      for (int i = j + 1 + lane; i < r; i += 64) w += vcol[i] * col[i];
+      w = wave_sum(w) * tj;
+      double nn = 0.0;
+      if (lane == 0) col[j] -= w * vj;
+      for (int i = j + 1 + lane; i < r; i += 64) {
+        const double x = col[i] - w * vcol[i];
+        col[i] = x;
+        nn += x * x;
+      }
+      nn = wave_sum(nn);
+      if (lane == 0) cn[c] = nn;  // exact norm of the new trailing part
+    }
+    __syncthreads();
+    if (tid == 0) B[j + (size_t)j * ld] = sh_beta;
+    __syncthreads();
   }
   __syncthreads();
-  const int rp = r + (r & 1);
+  const int t = sh_t;
+  if (t == 0) {
+    if (tid == 0) *T.kout = 0;
+    return;
+  }
+  // ---- phase 2: one-sided Jacobi on C = R_t^T (r x t), rotations accumulated in J (t x t)
+  for (int idx = tid; idx < r * t; idx += SVD_THREADS) {
+    const int c = idx % r, i = idx / r;  // C[c, i] = R[i, c]
+    C[c + (size_t)i * ld] = (c >= i) ? B[i + (size_t)c * ld] : 0.0;
+  }
+  const bool jl = t <= SVD_JLDS;
+  double* J = jl ? Jl : T.Jw;  // t x t
+  const int ldj = jl ? SVD_JLDS : ld;
+  for (int idx = tid; idx < t * t; idx += SVD_THREADS) {
+    const int i = idx % t, c = idx / t;
+    J[i + c * ldj] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int tp = t + (t & 1);
   const double tol = 4.0 * DBL_EPSILON * sqrt((double)r);
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  for (int sweep = 0; sweep < 40 && t > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
-    for (int round = 0; round < rp - 1; ++round) {
-      for (int pi = wave; pi < rp / 2; pi += SVD_WAVES) {
-        const int x = pi, y = rp - 1 - pi;
-        int p = (x == 0) ? 0 : 1 + ((x - 1 + round) % (rp - 1));
-        int q = (y == 0) ? 0 : 1 + ((y - 1 + round) % (rp - 1));
-        if (p >= r || q >= r) continue;
-        if (p > q) { const int t = p; p = q; q = t; }
-        double* bp = B + (size_t)p * ld;
-        double* bq = B + (size_t)q * ld;
+    for (int round = 0; round < tp - 1; ++round) {
+      for (int pi = wave; pi < tp / 2; pi += SVD_WAVES) {
+        const int x = pi, y = tp - 1 - pi;
+        int p = (x == 0) ? 0 : 1 + ((x - 1 + round) % (tp - 1));
+        int q = (y == 0) ? 0 : 1 + ((y - 1 + round) % (tp - 1));
+        if (p >= t || q >= t) continue;
+        if (p > q) { const int tt = p; p = q; q = tt; }
+        double* cp = C + (size_t)p * ld;
+        double* cq = C + (size_t)q * ld;
         double a = 0.0, b = 0.0, g = 0.0;
         for (int i = lane; i < r; i += 64) {
-          const double u = bp[i], w = bq[i];
+          const double u = cp[i], w = cq[i];
           a += u * u;
           b += w * w;
           g += u * w;
@@ -335,16 +462,16 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
         g = wave_sum(g);
         if (a > DBL_MIN && b > DBL_MIN && fabs(g) > tol * sqrt(a) * sqrt(b)) {
           const double zeta = (b - a) / (2.0 * g);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
           for (int i = lane; i < r; i += 64) {
-            const double u = bp[i], w = bq[i];
-            bp[i] = cs * u - sn * w;
-            bq[i] = sn * u + cs * w;
+            const double u = cp[i], w = cq[i];
+            cp[i] = cs * u - sn * w;
+            cq[i] = sn * u + cs * w;
           }
-          double* jp = J + (size_t)p * ld;
-          double* jq = J + (size_t)q * ld;
-          for (int i = lane; i < r; i += 64) {
+          double* jp = J + (size_t)p * ldj;
+          double* jq = J + (size_t)q * ldj;
+          for (int i = lane; i < t; i += 64) {
             const double u = jp[i], w = jq[i];
             jp[i] = cs * u - sn * w;
             jq[i] = sn * u + cs * w;
@@ -357,36 +484,56 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     if (!rotated) break;
     __syncthreads();
   }
-  // singular values = column norms
-  for (int c = wave; c < r; c += SVD_WAVES) {
+  // ---- phase 3: singular values (column norms of C J), order, truncation
+  double* sig2 = cn;       // the pivot norms are no longer needed
+  int* ordr = perm + SVD_RMAX / 2;  // perm[0 .. r) stays intact (r <= SVD_RMAX / 2 checked on the host)
+  for (int c = wave; c < t; c += SVD_WAVES) {
     double s = 0.0;
-    for (int i = lane; i < r; i += 64) s += B[i + (size_t)c * ld] * B[i + (size_t)c * ld];
+    for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ld] * C[i + (size_t)c * ld];
     s = wave_sum(s);
     if (lane == 0) sig2[c] = s;
   }
   __syncthreads();
-  for (int i = tid; i < r; i += SVD_THREADS) {
+  for (int i = tid; i < t; i += SVD_THREADS) {
     int pos = 0;
     const double si = sig2[i];
-    for (int j = 0; j < r; ++j) pos += (sig2[j] > si) || (sig2[j] == si && j < i);
-    perm[pos] = i;
+    for (int j = 0; j < t; ++j) pos += (sig2[j] > si) || (sig2[j] == si && j < i);
+    ordr[pos] = i;
   }
   __syncthreads();
   const double th2 = T.thresh * T.thresh;
   int kk = 0;
-  for (int i = 0; i < r; ++i) kk += sig2[i] > th2;
+  for (int i = 0; i < t; ++i) kk += sig2[i] > th2;
   if (kk > T.kcap) {
     if (tid == 0) atomicOr(flag, 1);
     kk = T.kcap;
   }
   if (tid == 0) *T.kout = kk;
   if (T.sig)
-    for (int i = tid; i < r; i += SVD_THREADS) T.sig[i] = sqrt(sig2[perm[i]]);
-  double* Jk = T.Jk;
+    for (int i = tid; i < t; i += SVD_THREADS) T.sig[i] = sqrt(sig2[ordr[i]]);
+  // ---- phase 4: B ~ Q_t J S (Pi W S^{-1})^T with W = C J
+  //   Jk[perm[c], o] = W[c, ord(o)] / sigma      (right singular vectors)
+  //   Wk = Q_t [J[:, ord(o)] / sigma ; 0]         (left singular vectors over sigma)
   for (int idx = tid; idx < r * kk; idx += SVD_THREADS) {
-    const int i = idx % r, o = idx / r, c = perm[o];
-    Jk[i + (size_t)o * ld] = J[i + (size_t)c * ld];
-    T.Wk[i + (size_t)o * ld] = B[i + (size_t)c * ld] / sig2[c];
+    const int c = idx % r, o = idx / r, src = ordr[o];
+    T.Jk[perm[c] + (size_t)o * ld] = C[c + (size_t)src * ld] / sqrt(sig2[src]);
+    T.Wk[c + (size_t)o * ld] = (c < t) ? J[c + (size_t)src * ldj] / sqrt(sig2[src]) : 0.0;
+  }
+  __syncthreads();
+  for (int j = t - 1; j >= 0; --j) {
+    const double tj = tau[j], vj = vhead[j];
+    if (tj != 0.0) {
+      const double* vcol = B + (size_t)j * ld;
+      for (int o = wave; o < kk; o += SVD_WAVES) {
+        double* col = T.Wk + (size_t)o * ld;
+        double w = (lane == 0) ? vj * col[j] : 0.0;
+        for (int i = j + 1 + lane; i < r; i += 64) w += vcol[i] * col[i];
+        w = wave_sum(w) * tj;
+        if (lane == 0) col[j] -= w * vj;
+        for (int i = j + 1 + lane; i < r; i += 64) col[i] -= w * vcol[i];
+      }
+    }
+    __syncthreads();
   }
 }
 
