@@ -149,6 +149,15 @@ hq_status hq_test_cholesky_inverse(hq_hodlr_t Z, int32_t cap, double tol, void* 
 hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
                             int32_t leaf, void* stream, hq_hodlr_t* q1, hq_hodlr_t* q2, int64_t* nrot);
 
+/* Built-in kernel timers: when enabled, every launch of the library is bracketed by HIP events on
+ * its own stream and the kernels count their algorithmic work (flops, operand bytes).
+ * hq_profile_read synchronises the device and returns, per kernel class (0 gemm, 1 tsqr, 2 core svd,
+ * 3 leaf cholesky, 4 leaf inverse, 5 stack, 6 leaf elementwise, 7 other), the number of launches,
+ * total milliseconds, flops and bytes since the last reset; reset != 0 clears them. */
+typedef struct { int64_t launches; double ms, flops, bytes; } hq_kstat;
+hq_status hq_profile_enable(int32_t on);
+hq_status hq_profile_read(hq_kstat* out /* [8] */, int32_t reset);
+
 /* Host-only: the same Q1, Q2 assembled densely (Q1, Q2: host, n x n, ld n).  No device use. */
 hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
                                int32_t leaf, double* Q1, double* Q2, int64_t* nrot);

@@ -70,7 +70,29 @@ _SIGS = {
     "hq_test_cholesky_inverse": (c_i32, [c_vp, c_i32, c_d, c_vp, P(c_vp)]),
     "hq_test_q_factors": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, P(c_vp), P(c_vp), P(c_i64)]),
     "hq_test_q_dense_host": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, c_vp, P(c_i64)]),
+    "hq_profile_enable": (c_i32, [c_i32]),
+    "hq_profile_read": (c_i32, [c_vp, c_i32]),
 }
+
+KCLASSES = ("gemm", "tsqr", "core_svd", "leaf_cholesky", "leaf_inverse", "stack", "leaf_elementwise", "other")
+
+
+class KStat(ctypes.Structure):
+    _fields_ = [("launches", c_i64), ("ms", c_d), ("flops", c_d), ("bytes", c_d)]
+
+
+def profile(on: bool):
+    """Enable/disable the library's kernel timers (and clear them when enabling)."""
+    if on:
+        profile_read(reset=True)
+    _check(lib().hq_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    arr = (KStat * 8)()
+    _check(lib().hq_profile_read(ctypes.cast(arr, c_vp), 1 if reset else 0))
+    return {KCLASSES[i]: {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops,
+                          "bytes": arr[i].bytes} for i in range(8)}
 
 EXPORTED = tuple(_SIGS)
 

@@ -853,6 +853,23 @@ hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ld
   });
 }
 
+hq_status hq_profile_enable(int32_t on) {
+  return guard([&]() -> hq_status {
+    hq::prof_enable(on != 0);
+    return HQ_OK;
+  });
+}
+
+hq_status hq_profile_read(hq_kstat* out, int32_t reset) {
+  if (!out) return fail(HQ_ERR_ARG, "out is NULL");
+  return guard([&]() -> hq_status {
+    hq::ProfStat st[hq::K_NCLASS];
+    hq::prof_read(st, reset != 0);
+    for (int c = 0; c < hq::K_NCLASS; ++c) out[c] = hq_kstat{st[c].launches, st[c].ms, st[c].flops, st[c].bytes};
+    return HQ_OK;
+  });
+}
+
 hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
                                int32_t leaf, double* Q1, double* Q2, int64_t* nrot) {
   hq_status s = check_band(band, n, b, ldab);

@@ -634,8 +634,12 @@ void Engine::cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) {
       std::vector<LeafTask> lt(1);
       lt[0] = LeafTask{Lf.leaf(li), Linv.leaf(li), m, Lf.ldl, Linv.ldl};
       LeafTask* d = stage.upload(lt, st);
-      launch_potrf(d, 1, d_flag, st);
-      launch_trtri(d, 1, st);
+      if (m <= 128) {
+        launch_chol_inv(d, 1, m, d_flag, st);
+      } else {
+        launch_potrf(d, 1, d_flag, st);
+        launch_trtri(d, 1, st);
+      }
       launches += 3;
       return;
     }

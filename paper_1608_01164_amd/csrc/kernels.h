@@ -10,6 +10,19 @@
 
 namespace hq {
 
+// Kernel classes for the built-in timers (HIP events around each launch, on the launch stream)
+// and the device-side counters of algorithmic work (flops and operand bytes per launch).
+enum KClass { K_GEMM = 0, K_QR, K_SVD, K_POTRF, K_TRTRI, K_STACK, K_LEAF, K_OTHER, K_NCLASS };
+struct ProfStat {
+  long long launches;
+  double ms, flops, bytes;
+};
+void prof_enable(bool on);
+bool prof_enabled();
+void prof_read(ProfStat out[K_NCLASS], bool reset);
+int prof_begin(hipStream_t s);             // returns a record slot or -1 when profiling is off
+void prof_end(int slot, int cls, hipStream_t s);
+
 // C = alpha * op(A) * op(B) + beta * C, column-major, op = N (0) or T (1).
 struct GemmTask {
   const double* A;
@@ -92,6 +105,8 @@ void launch_qr_final(const QrTask* d_tasks, int ntasks, int rcap_max, hipStream_
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s);
+// fused: A (m <= 128) -> Cholesky factor, B = its inverse; whole tile in LDS
+void launch_chol_inv(const LeafTask* d_tasks, int ntasks, int max_m, int* flag, hipStream_t s);
 // leaves: out = alpha*X + beta*op(X)^T + gamma*I over m x m tiles (symmetrise / identity shifts)
 struct LeafAxpy {
   double* out;

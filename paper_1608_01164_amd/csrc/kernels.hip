@@ -6,8 +6,96 @@
 
 #include <cfloat>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 namespace hq {
+
+// ---------------------------------------------------------------------------------------------
+// Timers and work counters
+// ---------------------------------------------------------------------------------------------
+__device__ unsigned long long g_prof[2 * K_NCLASS];  // [flops..., bytes...]
+__device__ int g_prof_on;
+
+namespace {
+struct Rec { hipEvent_t a, b; int cls; };
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  (void)hipEventCreate(&e);
+  return e;
+}
+}  // namespace
+
+void prof_enable(bool on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_on = on;
+  const int v = on ? 1 : 0;
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(g_prof_on), &v, sizeof(int));
+}
+bool prof_enabled() { return g_on; }
+int prof_begin(hipStream_t s) {
+  if (!g_on) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Rec r{take_event(), take_event(), 0};
+  (void)hipEventRecord(r.a, s);
+  g_recs.push_back(r);
+  return (int)g_recs.size() - 1;
+}
+void prof_end(int slot, int cls, hipStream_t s) {
+  if (slot < 0) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_recs[slot].cls = cls;
+  (void)hipEventRecord(g_recs[slot].b, s);
+}
+void prof_read(ProfStat out[K_NCLASS], bool reset) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  (void)hipDeviceSynchronize();
+  for (int c = 0; c < K_NCLASS; ++c) out[c] = ProfStat{0, 0.0, 0.0, 0.0};
+  for (Rec& r : g_recs) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    out[r.cls].launches += 1;
+    out[r.cls].ms += ms;
+  }
+  unsigned long long h[2 * K_NCLASS];
+  (void)hipMemcpyFromSymbol(h, HIP_SYMBOL(g_prof), sizeof(h));
+  for (int c = 0; c < K_NCLASS; ++c) {
+    out[c].flops = (double)h[c];
+    out[c].bytes = (double)h[K_NCLASS + c];
+  }
+  if (reset) {
+    for (Rec& r : g_recs) {
+      g_pool.push_back(r.a);
+      g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    unsigned long long z[2 * K_NCLASS] = {};
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(g_prof), z, sizeof(z));
+  }
+}
+
+static __device__ __forceinline__ void count_work(int cls, unsigned long long flops, unsigned long long bytes) {
+  if (g_prof_on) {
+    atomicAdd(&g_prof[cls], flops);
+    if (bytes) atomicAdd(&g_prof[K_NCLASS + cls], bytes);
+  }
+}
+
+#define HQ_TIMED(cls, stream, ...)            \
+  do {                                        \
+    const int slot_ = prof_begin(stream);     \
+    __VA_ARGS__;                              \
+    prof_end(slot_, cls, stream);             \
+  } while (0)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -36,6 +124,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
   const int row0 = tm * GT, col0 = tn * GT;
   if (row0 >= m || col0 >= n) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (blockIdx.x == 0 && tid == 0)
+    count_work(K_GEMM, 2ull * m * n * k,
+               8ull * ((unsigned long long)m * k + (unsigned long long)k * n + (T.beta != 0.0 ? 2ull : 1ull) * m * n));
 
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
@@ -115,7 +206,7 @@ void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, hipS
   const int tm = (max_m + GT - 1) / GT, tn = (max_n + GT - 1) / GT;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    hipLaunchKernelGGL(k_gemm, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn);
+    HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn));
   }
 }
 
@@ -145,7 +236,7 @@ void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag,
   const int bx = max_rows > 0 ? (max_rows + 255) / 256 : 1;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    hipLaunchKernelGGL(k_stack, dim3(bx, nt), dim3(256), 0, s, d_tasks + t0, flag);
+    HQ_TIMED(K_STACK, s, hipLaunchKernelGGL(k_stack, dim3(bx, nt), dim3(256), 0, s, d_tasks + t0, flag));
   }
 }
 
@@ -161,7 +252,7 @@ void launch_scale_cols(double* p, int ld, int rows, const int* wp, double scale,
 // ----------------------------------------------------------------------------------------------
 // Householder triangularisation of an h x r panel held in global memory (one workgroup).
 // ----------------------------------------------------------------------------------------------
-constexpr int QR_THREADS = 512;
+constexpr int QR_THREADS = 1024;
 constexpr int QR_WAVES = QR_THREADS / 64;
 
 static __device__ void householder_rows(double* X, int ld, int h, int r, double* v) {
@@ -200,17 +291,36 @@ static __device__ void householder_rows(double* X, int ld, int h, int r, double*
     for (int i = j + 1 + tid; i < h; i += QR_THREADS) v[i - j] = X[i + (size_t)j * ld];
     __syncthreads();
     const double tau = sh_tau;
-    for (int c = j + 1 + wave; c < r; c += QR_WAVES) {
-      double* col = X + (size_t)c * ld;
-      double w = 0.0;
-      for (int i = j + lane; i < h; i += 64) w += v[i - j] * col[i];
-      w = wave_sum(w) * tau;
-      for (int i = j + lane; i < h; i += 64) col[i] -= w * v[i - j];
+    // four trailing columns per wave at a time: independent reductions overlap their latency
+    for (int c0 = j + 1 + 4 * wave; c0 < r; c0 += 4 * QR_WAVES) {
+      const int nc = r - c0 < 4 ? r - c0 : 4;
+      double* col[4];
+      double w[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) col[q] = X + (size_t)(q < nc ? c0 + q : c0) * ld;
+      for (int i = j + lane; i < h; i += 64) {
+        const double vi = v[i - j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = wave_sum(w[q]) * tau;
+      for (int i = j + lane; i < h; i += 64) {
+        const double vi = v[i - j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < nc) col[q][i] -= w[q] * vi;
+      }
     }
     __syncthreads();
     if (tid == 0) X[j + (size_t)j * ld] = sh_beta;
     for (int i = j + 1 + tid; i < h; i += QR_THREADS) X[i + (size_t)j * ld] = 0.0;
     __syncthreads();
+  }
+  if (tid == 0) {
+    unsigned long long f = 0;
+    for (int j = 0; j < jend; ++j) f += 2ull * (h - j) + 4ull * (unsigned long long)(h - j) * (r - j - 1);
+    count_work(K_QR, f, 0);
   }
 }
 
@@ -274,12 +384,12 @@ void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs
   const size_t lds = sizeof(double) * (size_t)hs_max;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    hipLaunchKernelGGL(k_qr_stage, dim3(max_pairs, nt), dim3(QR_THREADS), lds, s, d_tasks + t0, stage);
+    HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage, dim3(max_pairs, nt), dim3(QR_THREADS), lds, s, d_tasks + t0, stage));
   }
 }
 void launch_qr_final(const QrTask* d_tasks, int ntasks, int, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_qr_final, dim3(ntasks), dim3(256), 0, s, d_tasks);
+  HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final, dim3(ntasks), dim3(256), 0, s, d_tasks));
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -318,12 +428,15 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   double* vhead = T.aux + r;
   const int ld = T.ld;
   __shared__ double cn[SVD_RMAX];     // squared norms of the trailing parts of the columns
+  __shared__ double vl[SVD_RMAX / 2]; // current reflector
   __shared__ int perm[SVD_RMAX];
   __shared__ double Jl[SVD_JLDS * SVD_JLDS];
   __shared__ double redv[SVD_WAVES];
   __shared__ ArgMax reda[SVD_WAVES];
   __shared__ int sh_t, sh_p, rotated;
   __shared__ double sh_beta, sh_tau;
+  __shared__ unsigned long long sh_pairs, sh_rots;
+  if (tid == 0) { sh_pairs = 0; sh_rots = 0; }
 
   // ---- phase 1: QR with column pivoting, stopped at trailing norm <= qr_thresh
   for (int c = wave; c < r; c += SVD_WAVES) {
@@ -397,21 +510,37 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     }
     __syncthreads();
     const double tj = sh_tau, vj = vhead[j];
-    const double* vcol = B + (size_t)j * ld;  // v_i = B[i, j] for i > j, v_j = vj
-    for (int c = j + 1 + wave; c < r; c += SVD_WAVES) {
-      double* col = B + (size_t)c * ld;
-      double w = (lane == 0) ? vj * col[j] : 0.0;
-      for (int i = j + 1 + lane; i < r; i += 64) w += vcol[i] * col[i];
-      w = wave_sum(w) * tj;
-      double nn = 0.0;
-      if (lane == 0) col[j] -= w * vj;
-      for (int i = j + 1 + lane; i < r; i += 64) {
-        const double x = col[i] - w * vcol[i];
-        col[i] = x;
-        nn += x * x;
+    // reflector v (v_j = vj, v_i = B[i, j] for i > j) staged in LDS
+    for (int i = j + tid; i < r; i += SVD_THREADS) vl[i] = (i == j) ? vj : B[i + (size_t)j * ld];
+    __syncthreads();
+    for (int c0 = j + 1 + 4 * wave; c0 < r; c0 += 4 * SVD_WAVES) {
+      const int nc = r - c0 < 4 ? r - c0 : 4;
+      double* col[4];
+      double w[4] = {0.0, 0.0, 0.0, 0.0}, nn[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) col[q] = B + (size_t)(q < nc ? c0 + q : c0) * ld;
+      for (int i = j + lane; i < r; i += 64) {
+        const double vi = vl[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
       }
-      nn = wave_sum(nn);
-      if (lane == 0) cn[c] = nn;  // exact norm of the new trailing part
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = wave_sum(w[q]) * tj;
+      for (int i = j + lane; i < r; i += 64) {
+        const double vi = vl[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < nc) {
+            const double x = col[q][i] - w[q] * vi;
+            col[q][i] = x;
+            if (i > j) nn[q] += x * x;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nn[q] = wave_sum(nn[q]);
+      if (lane == 0)
+        for (int q = 0; q < nc; ++q) cn[c0 + q] = nn[q];  // exact norm of the new trailing part
     }
     __syncthreads();
     if (tid == 0) B[j + (size_t)j * ld] = sh_beta;
@@ -460,7 +589,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
         a = wave_sum(a);
         b = wave_sum(b);
         g = wave_sum(g);
+        if (lane == 0) atomicAdd(&sh_pairs, 1ull);
         if (a > DBL_MIN && b > DBL_MIN && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+          if (lane == 0) atomicAdd(&sh_rots, 1ull);
           const double zeta = (b - a) / (2.0 * g);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -535,11 +666,18 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     }
     __syncthreads();
   }
+  if (tid == 0) {
+    unsigned long long f = 0;
+    for (int j = 0; j < t; ++j)
+      f += 2ull * (r - j) + 6ull * (unsigned long long)(r - j) * (r - j - 1) + 4ull * (r - j) * kk;
+    f += sh_pairs * 6ull * r + sh_rots * (6ull * r + 6ull * t) + 2ull * r * t;
+    count_work(K_SVD, f, 0);
+  }
 }
 
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(SVD_THREADS), 0, s, d_tasks, flag);
+  HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(SVD_THREADS), 0, s, d_tasks, flag));
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -576,6 +714,7 @@ __global__ __launch_bounds__(256) void k_potrf(const LeafTask* __restrict__ task
     const int i = idx % m, c = idx / m;
     if (i < c) A[i + (size_t)c * ld] = 0.0;
   }
+  if (tid == 0) count_work(K_POTRF, (unsigned long long)m * m * m / 3, 0);
 }
 
 __global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ tasks) {
@@ -599,13 +738,76 @@ __global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ task
     }
     __syncthreads();
   }
+  if (tid == 0) count_work(K_TRTRI, (unsigned long long)m * m * m / 3, 0);
+}
+
+// Leaf Cholesky and in-place triangular inverse with the whole leaf in LDS (m <= 128):
+// A (lower part of an SPD tile) -> A = L L^T, then L -> L^{-1} written to B.
+constexpr int CI_MAX = 128;
+__global__ __launch_bounds__(512) void k_chol_inv(const LeafTask* __restrict__ tasks, int* flag) {
+  const LeafTask T = tasks[blockIdx.x];
+  const int m = T.m, tid = threadIdx.x;
+  extern __shared__ double S[];  // m x m, ld = m
+  for (int idx = tid; idx < m * m; idx += 512) {
+    const int i = idx % m, c = idx / m;
+    S[i + c * m] = (i >= c) ? T.A[i + (size_t)c * T.lda] : 0.0;
+  }
+  __syncthreads();
+  __shared__ double piv;
+  for (int j = 0; j < m; ++j) {
+    if (tid == 0) {
+      double d = S[j + j * m];
+      if (!(d > 0.0)) {
+        atomicOr(flag, 2);
+        d = fabs(d) + DBL_MIN;
+      }
+      piv = sqrt(d);
+      S[j + j * m] = piv;
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int i = j + 1 + tid; i < m; i += 512) S[i + j * m] *= inv;
+    __syncthreads();
+    const int w = m - j - 1;
+    for (int idx = tid; idx < w * w; idx += 512) {
+      const int i = j + 1 + idx % w, c = j + 1 + idx / w;
+      if (c <= i) S[i + c * m] -= S[i + j * m] * S[c + j * m];
+    }
+    __syncthreads();
+  }
+  // in-place inverse of the lower triangle, columns from the right:
+  // X_jj = 1/L_jj;  X_{j+1:, j} = -X_jj * X_{j+1:, j+1:} L_{j+1:, j}
+  __shared__ double col[CI_MAX];
+  for (int j = m - 1; j >= 0; --j) {
+    const double xjj = 1.0 / S[j + j * m];
+    for (int i = j + 1 + tid; i < m; i += 512) {
+      double acc = 0.0;
+      for (int k = j + 1; k <= i; ++k) acc += S[i + k * m] * S[k + j * m];
+      col[i] = -xjj * acc;
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < m; i += 512) S[i + j * m] = col[i];
+    if (tid == 0) S[j + j * m] = xjj;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * m; idx += 512) {
+    const int i = idx % m, c = idx / m;
+    T.B[i + (size_t)c * T.ldb] = (i >= c) ? S[i + c * m] : 0.0;
+  }
+  if (tid == 0) count_work(K_POTRF, 2ull * m * m * m / 3, 0);
+}
+
+void launch_chol_inv(const LeafTask* d_tasks, int ntasks, int max_m, int* flag, hipStream_t s) {
+  if (ntasks <= 0) return;
+  HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(512), sizeof(double) * max_m * max_m, s,
+                                          d_tasks, flag));
 }
 
 void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
-  if (ntasks > 0) hipLaunchKernelGGL(k_potrf, dim3(ntasks), dim3(256), 0, s, d_tasks, flag);
+  if (ntasks > 0) HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_potrf, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
 }
 void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s) {
-  if (ntasks > 0) hipLaunchKernelGGL(k_trtri, dim3(ntasks), dim3(256), 0, s, d_tasks);
+  if (ntasks > 0) HQ_TIMED(K_TRTRI, s, hipLaunchKernelGGL(k_trtri, dim3(ntasks), dim3(256), 0, s, d_tasks));
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -626,7 +828,7 @@ void launch_leaf_axpy(const LeafAxpy* d_tasks, int ntasks, int max_m, hipStream_
   const int bx = (max_m * max_m + 255) / 256;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    hipLaunchKernelGGL(k_leaf_axpy, dim3(bx, nt), dim3(256), 0, s, d_tasks + t0);
+    HQ_TIMED(K_LEAF, s, hipLaunchKernelGGL(k_leaf_axpy, dim3(bx, nt), dim3(256), 0, s, d_tasks + t0));
   }
 }
 
