@@ -159,6 +159,7 @@ def main():
         print(f"# step {i}: {info['seconds']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    svd_stats = hq.binding.profile_svd() if not args.no_profile else None
     prof = hq.profile_read() if not args.no_profile else None
     if not args.no_profile:
         hq.profile(False)
@@ -177,6 +178,7 @@ def main():
     }
     if prof is not None:
         out["roofline"], out["kernels"] = roofline(prof)
+        out["core_svd_phases"] = svd_stats
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ab, b, nu)
     print(json.dumps(out), flush=True)

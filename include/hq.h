@@ -157,6 +157,9 @@ hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ld
 typedef struct { int64_t launches; double ms, flops, bytes; } hq_kstat;
 hq_status hq_profile_enable(int32_t on);
 hq_status hq_profile_read(hq_kstat* out /* [8] */, int32_t reset);
+/* Core-SVD internals since the last reset: [0..2] cycles of the pivoted-QR, Jacobi and output phases
+ * (wall clock at 100 MHz), [3] sum of r, [4] sum of t, [5] sum of sweeps, [6] cores. */
+hq_status hq_profile_svd(int64_t* out /* [8] */);
 
 /* Host-only: the same Q1, Q2 assembled densely (Q1, Q2: host, n x n, ld n).  No device use. */
 hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,

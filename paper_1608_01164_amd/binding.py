@@ -72,6 +72,7 @@ _SIGS = {
     "hq_test_q_dense_host": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, c_vp, P(c_i64)]),
     "hq_profile_enable": (c_i32, [c_i32]),
     "hq_profile_read": (c_i32, [c_vp, c_i32]),
+    "hq_profile_svd": (c_i32, [c_vp]),
 }
 
 KCLASSES = ("gemm", "tsqr", "core_svd", "leaf_cholesky", "leaf_inverse", "stack", "leaf_elementwise", "other")
@@ -86,6 +87,14 @@ def profile(on: bool):
     if on:
         profile_read(reset=True)
     _check(lib().hq_profile_enable(1 if on else 0))
+
+
+def profile_svd() -> dict:
+    a = (c_i64 * 8)()
+    _check(lib().hq_profile_svd(ctypes.cast(a, c_vp)))
+    n = max(a[6], 1)
+    return {"cores": a[6], "qr_us": a[0] / 100.0, "jacobi_us": a[1] / 100.0, "out_us": a[2] / 100.0,
+            "mean_r": a[3] / n, "mean_t": a[4] / n, "mean_sweeps": a[5] / n}
 
 
 def profile_read(reset: bool = True) -> dict:

@@ -870,6 +870,16 @@ hq_status hq_profile_read(hq_kstat* out, int32_t reset) {
   });
 }
 
+hq_status hq_profile_svd(int64_t* out) {
+  if (!out) return fail(HQ_ERR_ARG, "out is NULL");
+  return guard([&]() -> hq_status {
+    unsigned long long v[8];
+    hq::prof_svd_stats(v);
+    for (int i = 0; i < 8; ++i) out[i] = (int64_t)v[i];
+    return HQ_OK;
+  });
+}
+
 hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
                                int32_t leaf, double* Q1, double* Q2, int64_t* nrot) {
   hq_status s = check_band(band, n, b, ldab);

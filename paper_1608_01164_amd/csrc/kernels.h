@@ -20,6 +20,7 @@ struct ProfStat {
 void prof_enable(bool on);
 bool prof_enabled();
 void prof_read(ProfStat out[K_NCLASS], bool reset);
+void prof_svd_stats(unsigned long long out[8]);  // core-SVD phase cycles and sizes (test/bench aid)
 int prof_begin(hipStream_t s);             // returns a record slot or -1 when profiling is off
 void prof_end(int slot, int cls, hipStream_t s);
 

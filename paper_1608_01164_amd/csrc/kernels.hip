@@ -15,6 +15,7 @@ namespace hq {
 // Timers and work counters
 // ---------------------------------------------------------------------------------------------
 __device__ unsigned long long g_prof[2 * K_NCLASS];  // [flops..., bytes...]
+__device__ unsigned long long g_svdstat[8];  // phase cycles (qr, jacobi, out), sum r, sum t, sum sweeps, calls
 __device__ int g_prof_on;
 
 namespace {
@@ -56,6 +57,10 @@ void prof_end(int slot, int cls, hipStream_t s) {
   g_recs[slot].cls = cls;
   (void)hipEventRecord(g_recs[slot].b, s);
 }
+void prof_svd_stats(unsigned long long out[8]) {
+  (void)hipDeviceSynchronize();
+  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_svdstat), sizeof(unsigned long long) * 8);
+}
 void prof_read(ProfStat out[K_NCLASS], bool reset) {
   std::lock_guard<std::mutex> lk(g_mu);
   (void)hipDeviceSynchronize();
@@ -80,6 +85,7 @@ void prof_read(ProfStat out[K_NCLASS], bool reset) {
     g_recs.clear();
     unsigned long long z[2 * K_NCLASS] = {};
     (void)hipMemcpyToSymbol(HIP_SYMBOL(g_prof), z, sizeof(z));
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(g_svdstat), z, sizeof(unsigned long long) * 8);
   }
 }
 
@@ -105,10 +111,26 @@ static __device__ __forceinline__ int live(const int* p, int v) {
   return x < v ? x : v;
 }
 
+// Data-parallel-primitive move of a double (two 32-bit DPP moves); rows/banks masked off read 0.
+template <int CTRL, int ROWS = 0xF>
+static __device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Quad swaps, then rotations inside each
+// 16-lane row give every lane its row sum; row broadcasts 15 and 31 fold the rows into lane 63.
 static __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);       // row_ror:4
+  v += dpp_move<0x128>(v);       // row_ror:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -214,21 +236,26 @@ void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, hipS
 // Column stacking with scaling at device-determined offsets.
 // ----------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_stack(const StackTask* __restrict__ tasks, int* flag) {
-  const StackTask T = tasks[blockIdx.y];
+  const StackTask* T = tasks + blockIdx.y;
   const int row = blockIdx.x * 256 + threadIdx.x;
+  const int rows = T->rows, ld = T->ld, nsrc = T->nsrc, wcap = T->wcap;
+  double* dst = T->dst;
   int off = 0;
-  for (int s = 0; s < T.nsrc; ++s) {
-    const StackSrc& S = T.src[s];
-    int w = S.wp ? *S.wp : S.w;
-    if (off + w > T.wcap) {
-      w = T.wcap - off;
+  for (int s = 0; s < nsrc; ++s) {
+    const double* p = T->src[s].p;
+    const int* wp = T->src[s].wp;
+    const int lds = T->src[s].ld;
+    const double sc = T->src[s].scale;
+    int w = wp ? *wp : T->src[s].w;
+    if (off + w > wcap) {
+      w = wcap - off;
       if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 4);
     }
-    if (row < T.rows)
-      for (int c = 0; c < w; ++c) T.dst[row + (size_t)(off + c) * T.ld] = S.scale * S.p[row + (size_t)c * S.ld];
+    if (row < rows)
+      for (int c = 0; c < w; ++c) dst[row + (size_t)(off + c) * ld] = sc * p[row + (size_t)c * lds];
     off += w;
   }
-  if (T.wout && blockIdx.x == 0 && threadIdx.x == 0) *T.wout = off;
+  if (T->wout && blockIdx.x == 0 && threadIdx.x == 0) *T->wout = off;
 }
 
 void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s) {
@@ -250,78 +277,87 @@ void launch_scale_cols(double* p, int ld, int rows, const int* wp, double scale,
 }
 
 // ----------------------------------------------------------------------------------------------
-// Householder triangularisation of an h x r panel held in global memory (one workgroup).
+// Householder triangularisation of an h x r panel (one workgroup).  The panel lives in LDS when it
+// fits (QR_LDS doubles), else in its global workspace slot.  Each step needs two barriers: the
+// norm of the next pivot column below the diagonal is accumulated while that column is updated.
 // ----------------------------------------------------------------------------------------------
 constexpr int QR_THREADS = 1024;
 constexpr int QR_WAVES = QR_THREADS / 64;
+constexpr int QR_RMAX = 1024;
+constexpr int QR_LDS = 16384;  // doubles of dynamic LDS (128 KiB)
 
-static __device__ void householder_rows(double* X, int ld, int h, int r, double* v) {
-  __shared__ double red[QR_WAVES];
-  __shared__ double sh_beta, sh_tau;
-  __shared__ int sh_skip;
+static __device__ void householder_rows(double* X, int ld, int h, int r) {
+  __shared__ double cn[QR_RMAX];  // squared norm of column c below row j, for the next pivot
+  __shared__ double sh_v0, sh_tau;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jend = (h - 1 < r) ? h - 1 : r;
-  for (int j = 0; j < jend; ++j) {
+  if (jend <= 0) return;
+  if (wave == 0) {
     double s = 0.0;
-    for (int i = j + 1 + tid; i < h; i += QR_THREADS) {
-      const double x = X[i + (size_t)j * ld];
-      s += x * x;
-    }
+    for (int i = 1 + lane; i < h; i += 64) s += X[i] * X[i];
     s = wave_sum(s);
-    if (lane == 0) red[wave] = s;
-    __syncthreads();
+    if (lane == 0) cn[0] = s;
+  }
+  __syncthreads();
+  unsigned long long flops = 0;
+  for (int j = 0; j < jend; ++j) {
     if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < QR_WAVES; ++w) t += red[w];
-      const double x0 = X[j + (size_t)j * ld];
-      if (t == 0.0) {
-        sh_skip = 1;
+      const double s = cn[j], x0 = X[j + (size_t)j * ld];
+      if (s == 0.0) {
+        sh_tau = 0.0;
+        sh_v0 = 0.0;
       } else {
-        sh_skip = 0;
-        const double nrm = sqrt(x0 * x0 + t);
+        const double nrm = sqrt(x0 * x0 + s);
         const double beta = x0 >= 0.0 ? -nrm : nrm;
-        const double v0 = x0 - beta;
-        sh_beta = beta;
-        sh_tau = 2.0 / (v0 * v0 + t);
-        v[0] = v0;
+        sh_v0 = x0 - beta;
+        sh_tau = 1.0 / (nrm * (nrm + fabs(x0)));
+        X[j + (size_t)j * ld] = beta;
       }
     }
     __syncthreads();
-    if (sh_skip) continue;
-    for (int i = j + 1 + tid; i < h; i += QR_THREADS) v[i - j] = X[i + (size_t)j * ld];
-    __syncthreads();
-    const double tau = sh_tau;
-    // four trailing columns per wave at a time: independent reductions overlap their latency
+    const double tau = sh_tau, v0 = sh_v0;
+    const double* vj = X + (size_t)j * ld;  // reflector: v0 at row j, X[i, j] below
+    // four trailing columns per wave; the norm below row j+1 of each updated column is recorded
     for (int c0 = j + 1 + 4 * wave; c0 < r; c0 += 4 * QR_WAVES) {
       const int nc = r - c0 < 4 ? r - c0 : 4;
       double* col[4];
       double w[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < 4; ++q) col[q] = X + (size_t)(q < nc ? c0 + q : c0) * ld;
-      for (int i = j + lane; i < h; i += 64) {
-        const double vi = v[i - j];
+      if (tau != 0.0) {
+        for (int i = j + 1 + lane; i < h; i += 64) {
+          const double vi = vj[i];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
+          for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (wave_sum(w[q]) + v0 * col[q][j]) * tau;
+      }
+      double nn[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = j + 1 + lane; i < h; i += 64) {
+        const double vi = vj[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double x = col[q][i] - w[q] * vi;
+          if (q < nc && tau != 0.0) col[q][i] = x;
+          if (i > j + 1) nn[q] += x * x;
+        }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = wave_sum(w[q]) * tau;
-      for (int i = j + lane; i < h; i += 64) {
-        const double vi = v[i - j];
+      for (int q = 0; q < 4; ++q) nn[q] = wave_sum(nn[q]);
+      if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (q < nc) col[q][i] -= w[q] * vi;
+          if (q < nc) {
+            if (tau != 0.0) col[q][j] -= w[q] * v0;
+            cn[c0 + q] = nn[q];
+          }
       }
     }
-    __syncthreads();
-    if (tid == 0) X[j + (size_t)j * ld] = sh_beta;
-    for (int i = j + 1 + tid; i < h; i += QR_THREADS) X[i + (size_t)j * ld] = 0.0;
+    if (tid == 0) flops += 2ull * (h - j) + 4ull * (unsigned long long)(h - j) * (r - j - 1);
     __syncthreads();
   }
-  if (tid == 0) {
-    unsigned long long f = 0;
-    for (int j = 0; j < jend; ++j) f += 2ull * (h - j) + 4ull * (unsigned long long)(h - j) * (r - j - 1);
-    count_work(K_QR, f, 0);
-  }
+  if (tid == 0) count_work(K_QR, flops, 0);
 }
 
 // rows covered by slot a after stage s, capped at r
@@ -334,38 +370,69 @@ static __device__ __forceinline__ int slot_live_rows(int a, int s, int h0, int r
 }
 
 __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restrict__ tasks, int stage) {
-  extern __shared__ double vbuf[];
+  extern __shared__ double qlds[];
   const QrTask T = tasks[blockIdx.y];
   const int r = live(T.rp, T.rcap);
   if (r <= 0) return;
   const int tid = threadIdx.x;
+  double* slot;
+  int h, ra = 0;
+  const double* src0;
+  int ld0, rows0;
+  const double* src1 = nullptr;
+  int rb = 0;
   if (stage == 0) {
     const int t = blockIdx.x;
     if (t >= T.ntiles) return;
     const int r0 = t * T.h0;
-    int h = T.rows - r0;
+    h = T.rows - r0;
     if (h > T.h0) h = T.h0;
-    double* X = T.work + (size_t)t * T.hs * T.rcap;
-    for (int idx = tid; idx < h * r; idx += QR_THREADS) {
-      const int i = idx % h, c = idx / h;
-      X[i + (size_t)c * T.hs] = T.M[(r0 + i) + (size_t)c * T.ldm];
-    }
-    __syncthreads();
-    householder_rows(X, T.hs, h, r, vbuf);
+    slot = T.work + (size_t)t * T.hs * T.rcap;
+    src0 = T.M + r0;
+    ld0 = T.ldm;
+    rows0 = h;
   } else {
     const int half = 1 << (stage - 1);
     const int a = blockIdx.x << stage, b = a + half;
     if (b >= T.ntiles) return;
-    const int ra = slot_live_rows(a, stage - 1, T.h0, T.rows, r);
-    const int rb = slot_live_rows(b, stage - 1, T.h0, T.rows, r);
-    double* Xa = T.work + (size_t)a * T.hs * T.rcap;
-    const double* Xb = T.work + (size_t)b * T.hs * T.rcap;
+    ra = slot_live_rows(a, stage - 1, T.h0, T.rows, r);
+    rb = slot_live_rows(b, stage - 1, T.h0, T.rows, r);
+    slot = T.work + (size_t)a * T.hs * T.rcap;
+    src0 = slot;
+    ld0 = T.hs;
+    rows0 = ra;
+    src1 = T.work + (size_t)b * T.hs * T.rcap;
+    h = ra + rb;
+  }
+  const bool inl = h * r <= QR_LDS;
+  double* X = inl ? qlds : slot;
+  const int ldx = inl ? h : T.hs;
+  // gather the panel (stage 0: a row tile of M; stage s: triangle of slot a over triangle of slot b)
+  if (inl || stage == 0) {
+    for (int idx = tid; idx < rows0 * r; idx += QR_THREADS) {
+      const int i = idx % rows0, c = idx / rows0;
+      const double v = src0[i + (size_t)c * ld0];
+      X[i + (size_t)c * ldx] = (stage == 0 || i <= c) ? v : 0.0;
+    }
+  } else {  // in place: clear the reflector entries left below the triangle of slot a
+    for (int idx = tid; idx < rows0 * r; idx += QR_THREADS) {
+      const int i = idx % rows0, c = idx / rows0;
+      if (i > c) X[i + (size_t)c * ldx] = 0.0;
+    }
+  }
+  if (stage > 0)
     for (int idx = tid; idx < rb * r; idx += QR_THREADS) {
       const int i = idx % rb, c = idx / rb;
-      Xa[(ra + i) + (size_t)c * T.hs] = (i <= c) ? Xb[i + (size_t)c * T.hs] : 0.0;
+      X[(ra + i) + (size_t)c * ldx] = (i <= c) ? src1[i + (size_t)c * T.hs] : 0.0;
     }
-    __syncthreads();
-    householder_rows(Xa, T.hs, ra + rb, r, vbuf);
+  __syncthreads();
+  householder_rows(X, ldx, h, r);
+  if (inl) {  // the triangle goes back to the slot
+    const int rr = h < r ? h : r;
+    for (int idx = tid; idx < rr * r; idx += QR_THREADS) {
+      const int i = idx % rr, c = idx / rr;
+      slot[i + (size_t)c * T.hs] = X[i + (size_t)c * ldx];
+    }
   }
 }
 
@@ -379,9 +446,9 @@ __global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tas
   }
 }
 
-void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int hs_max, int, hipStream_t s) {
+void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int, int, hipStream_t s) {
   if (ntasks <= 0 || max_pairs <= 0) return;
-  const size_t lds = sizeof(double) * (size_t)hs_max;
+  const size_t lds = sizeof(double) * (size_t)QR_LDS;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
     HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage, dim3(max_pairs, nt), dim3(QR_THREADS), lds, s, d_tasks + t0, stage));
@@ -398,8 +465,8 @@ void launch_qr_final(const QrTask* d_tasks, int ntasks, int, hipStream_t s) {
 // ----------------------------------------------------------------------------------------------
 constexpr int SVD_THREADS = 1024;
 constexpr int SVD_WAVES = SVD_THREADS / 64;
-constexpr int SVD_RMAX = 2048;  // pivot bookkeeping; cores are limited to r <= SVD_RMAX / 2
-constexpr int SVD_JLDS = 96;  // rotations kept in LDS up to t = 96
+constexpr int SVD_RMAX = 1024;   // largest core handled
+constexpr int SVD_LDS = 16384;   // doubles of dynamic LDS (128 KiB) for B, C and J when they fit
 
 struct ArgMax { double v; int i; };
 
@@ -414,42 +481,47 @@ static __device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {
 }
 
 __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__ tasks, int* flag) {
+  extern __shared__ double slds[];
   const SvdTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int r = *T.rp;
-  if (r > SVD_RMAX / 2) r = SVD_RMAX / 2;
+  if (r > SVD_RMAX) r = SVD_RMAX;
   if (r <= 0) {
     if (tid == 0) *T.kout = 0;
     return;
   }
-  double* B = T.B;
-  double* C = T.C;
   double* tau = T.aux;
   double* vhead = T.aux + r;
-  const int ld = T.ld;
-  __shared__ double cn[SVD_RMAX];     // squared norms of the trailing parts of the columns
-  __shared__ double vl[SVD_RMAX / 2]; // current reflector
+  __shared__ double cn[SVD_RMAX];   // trailing squared column norms; later sigma^2
+  __shared__ double vl[SVD_RMAX];   // current reflector when B is in global memory
   __shared__ int perm[SVD_RMAX];
-  __shared__ double Jl[SVD_JLDS * SVD_JLDS];
+  __shared__ int ordr[SVD_RMAX];
   __shared__ double redv[SVD_WAVES];
   __shared__ ArgMax reda[SVD_WAVES];
-  __shared__ int sh_t, sh_p, rotated;
-  __shared__ double sh_beta, sh_tau;
+  __shared__ int rotated;
   __shared__ unsigned long long sh_pairs, sh_rots;
   if (tid == 0) { sh_pairs = 0; sh_rots = 0; }
+  const unsigned long long c0 = wall_clock64();
+  unsigned long long c1 = c0, c2 = c0;
+  int nsweeps = 0;
 
-  // ---- phase 1: QR with column pivoting, stopped at trailing norm <= qr_thresh
+  // ---- phase 1: QR with column pivoting, stopped at trailing Frobenius norm <= qr_thresh
+  const bool bl = r * r <= SVD_LDS;
+  double* Bm = bl ? slds : T.B;
+  int ldb = bl ? r : T.ld;
+  if (bl)
+    for (int idx = tid; idx < r * r; idx += SVD_THREADS) slds[idx] = T.B[(idx % r) + (size_t)(idx / r) * T.ld];
+  __syncthreads();
   for (int c = wave; c < r; c += SVD_WAVES) {
     double s = 0.0;
-    for (int i = lane; i < r; i += 64) s += B[i + (size_t)c * ld] * B[i + (size_t)c * ld];
+    for (int i = lane; i < r; i += 64) s += Bm[i + (size_t)c * ldb] * Bm[i + (size_t)c * ldb];
     s = wave_sum(s);
     if (lane == 0) { cn[c] = s; perm[c] = c; }
   }
-  if (tid == 0) sh_t = r;
   __syncthreads();
   const double qth2 = T.qr_thresh * T.qr_thresh;
+  int t = r;
   for (int j = 0; j < r; ++j) {
-    // trailing Frobenius norm and pivot
     double s = 0.0;
     ArgMax am{-1.0, 0x7fffffff};
     for (int c = j + tid; c < r; c += SVD_THREADS) {
@@ -460,114 +532,129 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     am = wave_argmax(am);
     if (lane == 0) { redv[wave] = s; reda[wave] = am; }
     __syncthreads();
-    if (tid == 0) {
-      double tot = 0.0;
-      ArgMax best = reda[0];
-      for (int w = 0; w < SVD_WAVES; ++w) {
-        tot += redv[w];
-        const ArgMax x = reda[w];
-        if (x.v > best.v || (x.v == best.v && x.i < best.i)) best = x;
-      }
-      sh_p = (tot <= qth2) ? -1 : best.i;
-      if (sh_p < 0) sh_t = j;
+    double tot = 0.0;
+    ArgMax best = reda[0];
+    for (int w = 0; w < SVD_WAVES; ++w) {
+      tot += redv[w];
+      const ArgMax x = reda[w];
+      if (x.v > best.v || (x.v == best.v && x.i < best.i)) best = x;
     }
-    __syncthreads();
-    const int p = sh_p;
-    if (p < 0) break;
-    if (p != j) {  // swap columns j and p
+    if (tot <= qth2) { t = j; break; }
+    const int p = best.i;
+    if (p != j) {
       for (int i = tid; i < r; i += SVD_THREADS) {
-        const double x = B[i + (size_t)j * ld];
-        B[i + (size_t)j * ld] = B[i + (size_t)p * ld];
-        B[i + (size_t)p * ld] = x;
+        const double x = Bm[i + (size_t)j * ldb];
+        Bm[i + (size_t)j * ldb] = Bm[i + (size_t)p * ldb];
+        Bm[i + (size_t)p * ldb] = x;
       }
+      __syncthreads();
       if (tid == 0) {
         const double x = cn[j]; cn[j] = cn[p]; cn[p] = x;
         const int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    // Householder vector of column j (rows j..r-1)
-    double s2 = 0.0;
-    for (int i = j + 1 + tid; i < r; i += SVD_THREADS) s2 += B[i + (size_t)j * ld] * B[i + (size_t)j * ld];
-    s2 = wave_sum(s2);
-    if (lane == 0) redv[wave] = s2;
-    __syncthreads();
-    if (tid == 0) {
-      double t2 = 0.0;
-      for (int w = 0; w < SVD_WAVES; ++w) t2 += redv[w];
-      const double x0 = B[j + (size_t)j * ld];
-      if (t2 == 0.0) {
-        sh_beta = x0; sh_tau = 0.0; vhead[j] = 1.0; tau[j] = 0.0;
-      } else {
-        const double nrm = sqrt(x0 * x0 + t2);
-        const double beta = x0 >= 0.0 ? -nrm : nrm;
-        const double v0 = x0 - beta;
-        sh_beta = beta;
-        sh_tau = 2.0 / (v0 * v0 + t2);
-        vhead[j] = v0;
-        tau[j] = sh_tau;
-      }
+    // reflector from the trailing norm of the pivot column (rows j..r-1)
+    const double nrm = sqrt(cn[j]), x0 = Bm[j + (size_t)j * ldb];
+    const double beta = x0 >= 0.0 ? -nrm : nrm;
+    const double vj = x0 - beta;
+    const double tj = nrm > 0.0 ? 1.0 / (nrm * (nrm + fabs(x0))) : 0.0;
+    const double* vcol = Bm + (size_t)j * ldb;
+    if (!bl) {
+      for (int i = j + 1 + tid; i < r; i += SVD_THREADS) vl[i] = vcol[i];
+      __syncthreads();
+      vcol = vl;
     }
-    __syncthreads();
-    const double tj = sh_tau, vj = vhead[j];
-    // reflector v (v_j = vj, v_i = B[i, j] for i > j) staged in LDS
-    for (int i = j + tid; i < r; i += SVD_THREADS) vl[i] = (i == j) ? vj : B[i + (size_t)j * ld];
-    __syncthreads();
-    for (int c0 = j + 1 + 4 * wave; c0 < r; c0 += 4 * SVD_WAVES) {
-      const int nc = r - c0 < 4 ? r - c0 : 4;
+    for (int cc = j + 1 + 4 * wave; cc < r; cc += 4 * SVD_WAVES) {
+      const int nc = r - cc < 4 ? r - cc : 4;
       double* col[4];
       double w[4] = {0.0, 0.0, 0.0, 0.0}, nn[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) col[q] = B + (size_t)(q < nc ? c0 + q : c0) * ld;
-      for (int i = j + lane; i < r; i += 64) {
-        const double vi = vl[i];
+      for (int q = 0; q < 4; ++q) col[q] = Bm + (size_t)(q < nc ? cc + q : cc) * ldb;
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = vj * col[q][j];
+      }
+      for (int i = j + 1 + lane; i < r; i += 64) {
+        const double vi = vcol[i];
 #pragma unroll
         for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) w[q] = wave_sum(w[q]) * tj;
-      for (int i = j + lane; i < r; i += 64) {
-        const double vi = vl[i];
+      if (lane == 0)
+        for (int q = 0; q < nc; ++q) col[q][j] -= w[q] * vj;
+      for (int i = j + 1 + lane; i < r; i += 64) {
+        const double vi = vcol[i];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (q < nc) {
             const double x = col[q][i] - w[q] * vi;
             col[q][i] = x;
-            if (i > j) nn[q] += x * x;
+            nn[q] += x * x;
           }
         }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) nn[q] = wave_sum(nn[q]);
       if (lane == 0)
-        for (int q = 0; q < nc; ++q) cn[c0 + q] = nn[q];  // exact norm of the new trailing part
+        for (int q = 0; q < nc; ++q) cn[cc + q] = nn[q];  // exact trailing norm for the next step
     }
     __syncthreads();
-    if (tid == 0) B[j + (size_t)j * ld] = sh_beta;
-    __syncthreads();
+    if (tid == 0) {
+      Bm[j + (size_t)j * ldb] = beta;
+      tau[j] = tj;
+      vhead[j] = vj;
+    }
   }
   __syncthreads();
-  const int t = sh_t;
+  c1 = wall_clock64();
   if (t == 0) {
     if (tid == 0) *T.kout = 0;
     return;
   }
   // ---- phase 2: one-sided Jacobi on C = R_t^T (r x t), rotations accumulated in J (t x t)
+  double *C, *J;
+  int ldc, ldj;
+  if (bl && r * r + r * t + t * t <= SVD_LDS) {
+    C = slds + r * r; ldc = r;
+    J = C + r * t; ldj = t;
+  } else {
+    if (bl) {  // free the LDS: reflectors back to global
+      for (int idx = tid; idx < r * r; idx += SVD_THREADS) T.B[(idx % r) + (size_t)(idx / r) * T.ld] = slds[idx];
+      __syncthreads();
+      Bm = T.B;
+      ldb = T.ld;
+    }
+    if (r * t + t * t <= SVD_LDS) {
+      C = slds; ldc = r;
+      J = slds + r * t; ldj = t;
+    } else {
+      C = T.C; ldc = T.ld;
+      if (t * t <= SVD_LDS) { J = slds; ldj = t; }
+      else { J = T.Jw; ldj = T.ld; }
+    }
+  }
   for (int idx = tid; idx < r * t; idx += SVD_THREADS) {
     const int c = idx % r, i = idx / r;  // C[c, i] = R[i, c]
-    C[c + (size_t)i * ld] = (c >= i) ? B[i + (size_t)c * ld] : 0.0;
+    C[c + (size_t)i * ldc] = (c >= i) ? Bm[i + (size_t)c * ldb] : 0.0;
   }
-  const bool jl = t <= SVD_JLDS;
-  double* J = jl ? Jl : T.Jw;  // t x t
-  const int ldj = jl ? SVD_JLDS : ld;
   for (int idx = tid; idx < t * t; idx += SVD_THREADS) {
     const int i = idx % t, c = idx / t;
-    J[i + c * ldj] = (i == c) ? 1.0 : 0.0;
+    J[i + (size_t)c * ldj] = (i == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int tp = t + (t & 1);
   const double tol = 4.0 * DBL_EPSILON * sqrt((double)r);
+  double* nrm2 = cn;  // squared column norms of C, tracked through the rotations
   for (int sweep = 0; sweep < 40 && t > 1; ++sweep) {
+    // exact norms at the start of every sweep
+    for (int c = wave; c < t; c += SVD_WAVES) {
+      double s = 0.0;
+      for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ldc] * C[i + (size_t)c * ldc];
+      s = wave_sum(s);
+      if (lane == 0) nrm2[c] = s;
+    }
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < tp - 1; ++round) {
@@ -577,28 +664,31 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
         int q = (y == 0) ? 0 : 1 + ((y - 1 + round) % (tp - 1));
         if (p >= t || q >= t) continue;
         if (p > q) { const int tt = p; p = q; q = tt; }
-        double* cp = C + (size_t)p * ld;
-        double* cq = C + (size_t)q * ld;
-        double a = 0.0, b = 0.0, g = 0.0;
-        for (int i = lane; i < r; i += 64) {
-          const double u = cp[i], w = cq[i];
-          a += u * u;
-          b += w * w;
-          g += u * w;
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
+        double* cp = C + (size_t)p * ldc;
+        double* cq = C + (size_t)q * ldc;
+        double g = 0.0;
+        for (int i = lane; i < r; i += 64) g += cp[i] * cq[i];
         g = wave_sum(g);
+        const double a = nrm2[p], b = nrm2[q];
         if (lane == 0) atomicAdd(&sh_pairs, 1ull);
         if (a > DBL_MIN && b > DBL_MIN && fabs(g) > tol * sqrt(a) * sqrt(b)) {
           if (lane == 0) atomicAdd(&sh_rots, 1ull);
           const double zeta = (b - a) / (2.0 * g);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          double na = 0.0, nb = 0.0;
           for (int i = lane; i < r; i += 64) {
             const double u = cp[i], w = cq[i];
-            cp[i] = cs * u - sn * w;
-            cq[i] = sn * u + cs * w;
+            const double u2 = cs * u - sn * w, w2 = sn * u + cs * w;
+            cp[i] = u2;
+            cq[i] = w2;
+            na += u2 * u2;
+            nb += w2 * w2;
+          }
+          double ea = a - tt * g, eb = b + tt * g;  // exact-arithmetic norms after the rotation
+          if (!(ea > 0.25 * a) || !(eb > 0.25 * b)) {  // cancellation: take the computed ones
+            ea = wave_sum(na);
+            eb = wave_sum(nb);
           }
           double* jp = J + (size_t)p * ldj;
           double* jq = J + (size_t)q * ldj;
@@ -607,20 +697,25 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
             jp[i] = cs * u - sn * w;
             jq[i] = sn * u + cs * w;
           }
-          if (lane == 0) rotated = 1;
+          if (lane == 0) {
+            nrm2[p] = ea;
+            nrm2[q] = eb;
+            rotated = 1;
+          }
         }
       }
       __syncthreads();
     }
+    ++nsweeps;
     if (!rotated) break;
     __syncthreads();
   }
+  c2 = wall_clock64();
   // ---- phase 3: singular values (column norms of C J), order, truncation
-  double* sig2 = cn;       // the pivot norms are no longer needed
-  int* ordr = perm + SVD_RMAX / 2;  // perm[0 .. r) stays intact (r <= SVD_RMAX / 2 checked on the host)
+  double* sig2 = cn;
   for (int c = wave; c < t; c += SVD_WAVES) {
     double s = 0.0;
-    for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ld] * C[i + (size_t)c * ld];
+    for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ldc] * C[i + (size_t)c * ldc];
     s = wave_sum(s);
     if (lane == 0) sig2[c] = s;
   }
@@ -647,16 +742,17 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   //   Wk = Q_t [J[:, ord(o)] / sigma ; 0]         (left singular vectors over sigma)
   for (int idx = tid; idx < r * kk; idx += SVD_THREADS) {
     const int c = idx % r, o = idx / r, src = ordr[o];
-    T.Jk[perm[c] + (size_t)o * ld] = C[c + (size_t)src * ld] / sqrt(sig2[src]);
-    T.Wk[c + (size_t)o * ld] = (c < t) ? J[c + (size_t)src * ldj] / sqrt(sig2[src]) : 0.0;
+    const double is = 1.0 / sqrt(sig2[src]);
+    T.Jk[perm[c] + (size_t)o * T.ld] = C[c + (size_t)src * ldc] * is;
+    T.Wk[c + (size_t)o * T.ld] = (c < t) ? J[c + (size_t)src * ldj] * is : 0.0;
   }
   __syncthreads();
   for (int j = t - 1; j >= 0; --j) {
     const double tj = tau[j], vj = vhead[j];
     if (tj != 0.0) {
-      const double* vcol = B + (size_t)j * ld;
+      const double* vcol = Bm + (size_t)j * ldb;
       for (int o = wave; o < kk; o += SVD_WAVES) {
-        double* col = T.Wk + (size_t)o * ld;
+        double* col = T.Wk + (size_t)o * T.ld;
         double w = (lane == 0) ? vj * col[j] : 0.0;
         for (int i = j + 1 + lane; i < r; i += 64) w += vcol[i] * col[i];
         w = wave_sum(w) * tj;
@@ -672,12 +768,23 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
       f += 2ull * (r - j) + 6ull * (unsigned long long)(r - j) * (r - j - 1) + 4ull * (r - j) * kk;
     f += sh_pairs * 6ull * r + sh_rots * (6ull * r + 6ull * t) + 2ull * r * t;
     count_work(K_SVD, f, 0);
+    if (g_prof_on) {
+      const unsigned long long c3 = wall_clock64();
+      atomicAdd(&g_svdstat[0], c1 - c0);
+      atomicAdd(&g_svdstat[1], c2 - c1);
+      atomicAdd(&g_svdstat[2], c3 - c2);
+      atomicAdd(&g_svdstat[3], (unsigned long long)r);
+      atomicAdd(&g_svdstat[4], (unsigned long long)t);
+      atomicAdd(&g_svdstat[5], (unsigned long long)nsweeps);
+      atomicAdd(&g_svdstat[6], 1ull);
+    }
   }
 }
 
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
-  HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(SVD_THREADS), 0, s, d_tasks, flag));
+  HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(SVD_THREADS), sizeof(double) * SVD_LDS, s,
+                                      d_tasks, flag));
 }
 
 // ----------------------------------------------------------------------------------------------
