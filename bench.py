@@ -26,6 +26,8 @@ WORKLOADS = {
     "metallic-n32768": (lambda: __import__("workloads").tridiag_metallic(32768, 0), 1, 256, 1e-10),
     "tridiag-n100000": (lambda: __import__("workloads").tridiag_uniform(100000, 0), 1, 256, 1e-8),
 }
+# batched: count independent banded matrices, n_i ~ U{2048..16384}, b_i ~ U{1..16}, leaf 128, tol 1e-10
+BATCHED = {"batched-256": 256, "batched-64": 64, "batched-16": 16}
 DEFAULT = "banded-n16384-b8"
 METRIC = "HODLR-QDWH Π/s at ‖Π−Π_oracle‖₂≤1e-8: mixed+batched vs FP64; MFMA util %"
 
@@ -119,7 +121,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="disable the library's per-launch kernel timers")
     args = ap.parse_args()
@@ -130,6 +132,8 @@ def main():
     import torch
     import paper_1608_01164_amd as hq
 
+    if args.workload in BATCHED:
+        return main_batched(args, BATCHED[args.workload])
     maker, b, leaf, tol = WORKLOADS[args.workload]
     ab = maker()
     n = ab.shape[0]
@@ -173,7 +177,8 @@ def main():
         "config": {"workload": args.workload, "n": n, "b": b, "leaf": leaf, "tol": tol, "nu": nu, "mu": mu,
                    "gap": gap, "precision": "fp64", "parallelism": "single-gpu"},
         "iters": info["iters"], "max_rank": info["max_rank"], "launches": info["launches"],
-        "setup_s": info["setup_seconds"], "givens_s": info["givens_seconds"],
+        "setup_s": info["setup_seconds"], "givens_s": info["givens_seconds"], "peak_bytes": info["peak_bytes"],
+        "redo_count": info["redo_count"],
         "checks": props,
     }
     if prof is not None:
@@ -181,6 +186,79 @@ def main():
         out["core_svd_phases"] = svd_stats
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ab, b, nu)
+    print(json.dumps(out), flush=True)
+
+
+def main_batched(args, count, leaf=128, tol=1e-10):
+    """One step = one spectral_projector_batched call over all `count` matrices."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_1608_01164_amd as hq
+    import workloads as wl
+
+    mats = wl.batched_banded(count, seed=0)
+    bs = [m.shape[1] - 1 for m in mats]
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        mg = list(ex.map(lambda i: hq.shift_for_count(mats[i], bs[i], mats[i].shape[0] // 2), range(count)))
+    mus = [x[0] for x in mg]
+    bands = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats]
+    torch.cuda.synchronize()
+    nsum = sum(m.shape[0] for m in mats)
+    print(f"# workload {args.workload}: {count} matrices, sum n = {nsum}, b in [{min(bs)}, {max(bs)}], leaf={leaf}, "
+          f"tol={tol}, min gap={min(x[1] for x in mg):.3e}", file=sys.stderr, flush=True)
+
+    def step():
+        Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol)
+        if st != 0:
+            bad = [(i, mats[i].shape[0], bs[i], mg[i][1]) for i, P in enumerate(Ps) if P is None]
+            print(f"# failed members (index, n, b, gap): {bad}; {hq.lib().hq_last_error().decode()}",
+                  file=sys.stderr, flush=True)
+            raise RuntimeError(f"batched solve: status {st}")
+        return Ps, infos
+
+    for i in range(args.warmup):
+        Ps, infos = step()
+        for P in Ps:
+            P.close()
+        for j, inf in enumerate(infos):
+            print(f"#   member {j}: n={mats[j].shape[0]} b={bs[j]} K={inf['iters']} ranks/iter={inf['max_rank_iter']} "
+                  f"redo={inf['redo_count']}", file=sys.stderr, flush=True)
+        print(f"# warmup {i}: {infos[0]['seconds']:.3f} s, peak {infos[0]['peak_bytes'] / 2**30:.2f} GiB, "
+              f"launches {infos[0]['launches']}", file=sys.stderr, flush=True)
+    if not args.no_profile:
+        hq.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ps = None
+    for i in range(args.steps):
+        if Ps is not None:
+            for P in Ps:
+                P.close()
+        Ps, infos = step()
+        print(f"# step {i}: {infos[0]['seconds']:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = hq.profile_read() if not args.no_profile else None
+    if not args.no_profile:
+        hq.profile(False)
+    ms = 1e3 * (t1 - t0) / args.steps
+    # at-any-size checks on the largest and the widest-band member
+    chk = {}
+    for j in sorted({int(np.argmax([m.shape[0] for m in mats])), int(np.argmax(bs))}):
+        pr = properties(Ps[j], bands[j], mus[j], mats[j].shape[0] // 2)
+        chk[f"member{j}_n{mats[j].shape[0]}_b{bs[j]}"] = {k: v for k, v in pr.items() if v is not None}
+    out = {
+        "metric": METRIC, "value": count * args.steps / (t1 - t0), "unit": "Π/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "count": count, "sum_n": nsum, "leaf": leaf, "tol": tol,
+                   "precision": "fp64", "parallelism": "single-gpu, batched"},
+        "iters_max": max(i["iters"] for i in infos), "max_rank": max(i["max_rank"] for i in infos),
+        "redo_count": sum(i["redo_count"] for i in infos), "launches": infos[0]["launches"],
+        "peak_bytes": infos[0]["peak_bytes"], "checks": chk,
+    }
+    if prof is not None:
+        out["roofline"], out["kernels"] = roofline(prof)
     print(json.dumps(out), flush=True)
 
 

@@ -38,7 +38,8 @@ typedef enum {
   HQ_ERR_SINGULAR_SHIFT = 1,  /* mu is (numerically) an eigenvalue: no positive lower bound l0 */
   HQ_ERR_NOT_POSDEF = 2,      /* a leaf of Z = I + c X^T X lost positive definiteness */
   HQ_ERR_NO_CONVERGENCE = 3,  /* |1 - l_k| > delta after max_iter steps of the weight recurrence */
-  HQ_ERR_RANK_OVERFLOW = 4    /* an off-diagonal rank exceeded opts.max_rank even after regrowth */
+  HQ_ERR_RANK_OVERFLOW = 4,   /* an off-diagonal rank exceeded opts.max_rank even after regrowth */
+  HQ_ERR_NONFINITE = 5        /* a non-finite value appeared in a recompression (result discarded) */
 } hq_status;
 
 typedef struct hq_hodlr_s* hq_hodlr_t; /* opaque HODLR matrix on the device */
@@ -91,6 +92,20 @@ hq_status qdwh_sign(const double* band, int64_t n, int32_t b, int64_t ldab, doub
  */
 hq_status spectral_projector(const double* band, int64_t n, int32_t b, int64_t ldab, double mu,
                              const hq_opts* opts, void* stream, hq_hodlr_t* P_out, hq_info* info);
+
+/*
+ * Batched form of spectral_projector for `count` independent problems (Alg. 3 for each member),
+ * 1 <= count <= 1024.  bands[i]: device band of member i; n, b, ldab, mu: host arrays of `count`
+ * entries.  The members advance together: every kernel launch of a step serves all members still
+ * iterating, so many small or uneven problems fill the device.  P_out[i] receives member i's
+ * projector (NULL if that member failed); info (may be NULL) receives `count` records whose
+ * seconds, launches and peak_bytes describe the whole batch.  Returns HQ_OK when every member
+ * succeeded, otherwise the status of the first member that failed (the others are still
+ * computed and returned).  Blocks until done.
+ */
+hq_status spectral_projector_batched(int32_t count, const double* const* bands, const int64_t* n, const int32_t* b,
+                                     const int64_t* ldab, const double* mu, const hq_opts* opts, void* stream,
+                                     hq_hodlr_t* P_out, hq_info* info);
 
 /*
  * Y = P X for a HODLR matrix P (Table complexity_HODLR, matrix-vector product, O(k n log n) per

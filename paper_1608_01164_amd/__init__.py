@@ -7,6 +7,7 @@ library; the first call does, and raises if the library has not been built.
 """
 from .binding import (  # noqa: F401
     HODLR, Info, Opts, LibraryMissing, HQError, lib, hodlr_build, qdwh_sign, spectral_projector,
+    spectral_projector_batched,
     shift_for_count, test_gemm, test_qr_r, test_recompress, test_from_dense, test_product,
     test_cholesky_inverse, test_q_factors, test_q_dense_host, profile, profile_read, KCLASSES,
 )

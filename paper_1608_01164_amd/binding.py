@@ -53,6 +53,8 @@ _SIGS = {
     "hodlr_build": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, P(Opts), c_vp, P(c_vp)]),
     "qdwh_sign": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, P(Opts), c_vp, P(c_vp), P(Info)]),
     "spectral_projector": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, P(Opts), c_vp, P(c_vp), P(Info)]),
+    "spectral_projector_batched": (c_i32, [c_i32, P(c_vp), P(c_i64), P(c_i32), P(c_i64), P(c_d), P(Opts), c_vp,
+                                           P(c_vp), P(Info)]),
     "apply_projector": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp]),
     "hodlr_to_dense": (c_i32, [c_vp, c_vp, c_i64, c_vp]),
     "hodlr_shape": (c_i32, [c_vp, P(c_i64), P(c_i32), P(c_i32), P(c_i32)]),
@@ -260,6 +262,30 @@ def _solve(fn, band, b, mu, stream, **kw):
 def spectral_projector(band, b: int, mu: float, stream=None, **opts):
     """(P, info): P ~ Pi_{<mu}(A) in HODLR format.  opts: leaf, tol, delta, max_rank, max_iter."""
     return _solve("spectral_projector", band, b, mu, stream, **opts)
+
+
+def spectral_projector_batched(bands, bs, mus, stream=None, **opts):
+    """([P_i], [info_i], status) for independent problems advanced together (one launch per step
+    for all members).  bands: device band tensors.  A failed member gives None and its status is
+    returned (the first failure); the call raises only for argument errors."""
+    cnt = len(bands)
+    ptrs = (c_vp * cnt)()
+    ns = (c_i64 * cnt)()
+    lds = (c_i64 * cnt)()
+    bb = (c_i32 * cnt)(*[int(x) for x in bs])
+    mm = (c_d * cnt)(*[float(x) for x in mus])
+    for i, band in enumerate(bands):
+        p, n, ld = _band_args(band)
+        ptrs[i] = p.value
+        ns[i] = n
+        lds[i] = ld
+    hs = (c_vp * cnt)()
+    infos = (Info * cnt)()
+    st = lib().spectral_projector_batched(cnt, ptrs, ns, bb, lds, mm, ctypes.byref(_opts(**opts)), _stream(stream),
+                                          hs, infos)
+    if st < 0:
+        _check(st)
+    return [HODLR(c_vp(h)) if h else None for h in hs], [i.as_dict() for i in infos], st
 
 
 def qdwh_sign(band, b: int, mu: float, stream=None, **opts):

@@ -26,7 +26,8 @@ def build(force: bool = True, jobs: int = 4) -> str:
             continue
         cmd = ["hipcc", *FLAGS, "-c", s, "-o", obj]
         if src.endswith(".cpp"):
-            cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "-c", s, "-o", obj]
+            # host-only translation units: no device code, so no offload target
+            cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "--offload-arch=" + ARCH, "-c", s, "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True)))
         if len(procs) >= jobs:
             _wait(procs.pop(0))

@@ -197,8 +197,8 @@ int max_of(const std::vector<int>& v) {
   return m;
 }
 
-void upload_host(hq::Engine& e, const hq::HostHodlr& h, hq::HMat& H) {
-  const hq::Tree& t = *e.t;
+void upload_host(hq::Engine& e, const hq::HostHodlr& h, hq::HMat& H, bool sync = true) {
+  const hq::Tree& t = *H.t;
   HQ_CHECK(hipMemcpyAsync(H.leaves, h.leaves.data(), sizeof(double) * h.leaves.size(), hipMemcpyHostToDevice, e.st));
   for (int l = 0; l < t.L; ++l) {
     HQ_CHECK(hipMemcpyAsync(H.Ubase[l], h.U[l].data(), sizeof(double) * h.U[l].size(), hipMemcpyHostToDevice, e.st));
@@ -206,13 +206,13 @@ void upload_host(hq::Engine& e, const hq::HostHodlr& h, hq::HMat& H) {
   }
   if (t.ninternal > 0)
     HQ_CHECK(hipMemcpyAsync(H.rank, h.rank.data(), sizeof(int) * 2 * t.ninternal, hipMemcpyHostToDevice, e.st));
-  HQ_CHECK(hipStreamSynchronize(e.st));  // host buffers go out of scope
+  if (sync) HQ_CHECK(hipStreamSynchronize(e.st));  // host buffers go out of scope
 }
 
 // X0 = (A - shift I) * inv_scale directly from the device band.
 void build_x0(hq::Engine& e, const double* band, int64_t n, int b, int64_t ldab, double shift, double inv_scale,
               hq::HMat& X) {
-  const hq::Tree& t = *e.t;
+  const hq::Tree& t = *X.t;
   hq::BandDesc bd{band, n, ldab, b, shift, inv_scale};
   std::vector<int64_t> lo(t.nleaves);
   std::vector<int> ms(t.nleaves);
@@ -244,7 +244,7 @@ void build_x0(hq::Engine& e, const double* band, int64_t n, int b, int64_t ldab,
 // Copy H (engine E) into a fresh handle whose capacities equal the realised ranks.
 hq_hodlr_t compact_copy(hq::Engine& E, const hq::HMat& H, hipStream_t st, int leaf) {
   std::unique_ptr<hq_hodlr_s> h(new hq_hodlr_s());
-  h->t.build(E.t->n, leaf);
+  h->t.build(H.t->n, leaf);
   const hq::Tree& t = h->t;
   const std::vector<int> r = E.read_ranks(H);
   std::vector<int> cap(t.L, 1);
@@ -252,10 +252,10 @@ hq_hodlr_t compact_copy(hq::Engine& E, const hq::HMat& H, hipStream_t st, int le
     const int l = hq::Tree::level(p);
     cap[l] = std::max(cap[l], std::max(r[2 * p], r[2 * p + 1]));
   }
-  h->e.reset(new hq::Engine(st, &h->t));
+  h->e.reset(new hq::Engine(st));
   h->e->tol = E.tol;
   h->e->persist.chunk_bytes = std::max<size_t>(size_t(1) << 20, H.bytes() + (size_t(4) << 20));
-  h->H = h->e->alloc_hmat(cap, H.lower_only);
+  h->H = h->e->alloc_hmat(&h->t, cap, H.lower_only);
   HQ_CHECK(hipMemcpy2DAsync(h->H.leaves, sizeof(double) * h->H.ldl, H.leaves, sizeof(double) * H.ldl,
                             sizeof(double) * H.ldl, (size_t)t.nleaves * H.ldl, hipMemcpyDeviceToDevice, st));
   std::vector<hq::StackTask> cp;
@@ -303,130 +303,350 @@ hq_status check_band(const double* band, int64_t n, int32_t b, int64_t ldab) {
 }
 
 // ---- the hQDWH driver -----------------------------------------------------------------------
-hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu, const hq_opts& o, hipStream_t st,
-                   bool projector, hq_hodlr_t* out, hq_info* info) {
-  const auto t0 = clk::now();
-  hq_info inf;
-  std::memset(&inf, 0, sizeof(inf));
+// One member of a (possibly singleton) batch of independent problems.  All members share the
+// engine, the stream and every kernel launch; each keeps its own tree, weights and capacities.
+struct Member {
+  const double* band = nullptr;
+  int64_t n = 0, ldab = 0;
+  int b = 0, beff = 0;
+  double mu = 0.0;
+  hq_status status = HQ_OK;
+  std::string err;
   hq::Tree t;
-  t.build(n, o.leaf);
-  if (t.L > 0 && (int64_t)b > n / (int64_t(1) << t.L))
-    return fail(HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block; raise opts.leaf");
-  const int beff = (int)std::min<int64_t>(b, std::max<int64_t>(1, n - 1));
-  // host copy of the band for the scalar setup and the Givens sweep
-  std::vector<double> ab((size_t)n * ldab);
-  HQ_CHECK(hipMemcpyAsync(ab.data(), band, sizeof(double) * ab.size(), hipMemcpyDeviceToHost, st));
-  HQ_CHECK(hipStreamSynchronize(st));
-  // Alg. 3 line 1: alpha >= ||A - mu I||_2 and l0 <= sigma_min(X0)
-  const double alpha = norm_inf_shifted(ab.data(), n, beff, ldab, mu);
-  if (!(alpha > 0.0)) return fail(HQ_ERR_SINGULAR_SHIFT, "A - mu I is zero");
-  const double dist = certified_distance(ab.data(), n, beff, ldab, mu, alpha);
-  if (!(dist > 0.0)) return fail(HQ_ERR_SINGULAR_SHIFT, "mu is numerically an eigenvalue of A");
-  const double l0 = dist / alpha;
-  const Weights w = schedule(l0, o.delta, o.max_iter);
-  if (std::fabs(1.0 - w.lK) > o.delta) return fail(HQ_ERR_NO_CONVERGENCE, "weight recurrence did not reach 1 - delta");
-  const int K = (int)w.a.size();
-  inf.alpha = alpha;
-  inf.l0 = l0;
-  inf.iters = K;
-  for (int k = 0; k < K && k < 16; ++k) {
-    inf.a[k] = w.a[k];
-    inf.b[k] = w.b[k];
-    inf.c[k] = w.c[k];
-  }
-  inf.setup_seconds = secs(t0);
+  std::vector<double> ab;  // host copy of the band
+  Weights w;
+  int K = 0;
+  hq_info inf;
+  hq::HMat X, Xn, Z, Linv, Lf, Y, Q1, Q2, P;
+  std::vector<int> capX;
+  hq_hodlr_t out = nullptr;
+};
 
-  hq::Engine E(st, &t);
-  E.tol = o.tol;
-  hq::DevArena xa[2], it;
-  auto alloc = [&](hq::DevArena& ar, const std::vector<int>& cap, bool lower) {
-    return E.alloc_hmat_in(ar, cap, lower);
-  };
-  // X0
-  hq::HMat X = alloc(xa[0], caps_from(t, beff, o.max_rank), false);
-  build_x0(E, band, n, beff, ldab, mu, 1.0 / alpha, X);
-  int cur = 0;
-  size_t peak = 0;
-  for (int k = 0; k < K; ++k) {
-    const double a = w.a[k], bb = w.b[k], c = w.c[k];
-    std::vector<int> capX;
-    if (k == 0) {
-      capX = caps_from(t, 3 * beff + 8, o.max_rank);
-    } else {
-      capX = caps_grow(t, E.read_ranks(X), o.max_rank, 2, 16);
+void set_fail(Member& m, hq_status s, const char* msg) {
+  m.status = s;
+  m.err = msg;
+}
+
+std::vector<std::vector<int>> read_ranks_many(hq::Engine& E, const std::vector<const hq::HMat*>& hs) {
+  std::vector<std::vector<int>> r(hs.size());
+  for (size_t i = 0; i < hs.size(); ++i) {
+    r[i].assign(std::max(1, 2 * hs[i]->t->ninternal), 0);
+    HQ_CHECK(hipMemcpyAsync(r[i].data(), hs[i]->rank, sizeof(int) * r[i].size(), hipMemcpyDeviceToHost, E.st));
+  }
+  HQ_CHECK(hipStreamSynchronize(E.st));
+  return r;
+}
+
+// Algorithm 3 for every member: setup (line 1), X0, the structured QR step (k = 0), Cholesky
+// steps (k >= 1) and the symmetrised result.  Members leave the batch when their own weight
+// schedule ends; a capacity overflow repeats the step for the members it hit.
+void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool projector) {
+  const auto t0 = clk::now();
+  const int nm = (int)ms.size();
+  if (nm > hq::Engine::kFlagSlots) throw std::runtime_error("batch larger than the engine's status slots");
+  // host copies of the bands
+  for (Member& m : ms) {
+    m.ab.resize((size_t)m.n * m.ldab);
+    HQ_CHECK(hipMemcpyAsync(m.ab.data(), m.band, sizeof(double) * m.ab.size(), hipMemcpyDeviceToHost, st));
+  }
+  HQ_CHECK(hipStreamSynchronize(st));
+  // Alg. 3 line 1: alpha >= ||A - mu I||_2, l0 <= sigma_min(X0), the weight schedule
+#pragma omp parallel for schedule(dynamic, 1) if (nm > 1)
+  for (int i = 0; i < nm; ++i) {
+    Member& m = ms[i];
+    const auto ts = clk::now();
+    std::memset(&m.inf, 0, sizeof(m.inf));
+    m.t.build(m.n, o.leaf);
+    if (m.t.L > 0 && (int64_t)m.b > m.n / (int64_t(1) << m.t.L)) {
+      set_fail(m, HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block; raise opts.leaf");
+      continue;
     }
-    for (int attempt = 0;; ++attempt) {
+    m.beff = (int)std::min<int64_t>(m.b, std::max<int64_t>(1, m.n - 1));
+    const double alpha = norm_inf_shifted(m.ab.data(), m.n, m.beff, m.ldab, m.mu);
+    if (!(alpha > 0.0)) {
+      set_fail(m, HQ_ERR_SINGULAR_SHIFT, "A - mu I is zero");
+      continue;
+    }
+    const double dist = certified_distance(m.ab.data(), m.n, m.beff, m.ldab, m.mu, alpha);
+    if (!(dist > 0.0)) {
+      set_fail(m, HQ_ERR_SINGULAR_SHIFT, "mu is numerically an eigenvalue of A");
+      continue;
+    }
+    m.w = schedule(dist / alpha, o.delta, o.max_iter);
+    if (std::fabs(1.0 - m.w.lK) > o.delta) {
+      set_fail(m, HQ_ERR_NO_CONVERGENCE, "weight recurrence did not reach 1 - delta");
+      continue;
+    }
+    m.K = (int)m.w.a.size();
+    m.inf.alpha = alpha;
+    m.inf.l0 = dist / alpha;
+    m.inf.iters = m.K;
+    for (int k = 0; k < m.K && k < 16; ++k) {
+      m.inf.a[k] = m.w.a[k];
+      m.inf.b[k] = m.w.b[k];
+      m.inf.c[k] = m.w.c[k];
+    }
+    m.inf.setup_seconds = secs(ts);
+  }
+  int Kmax = 0;
+  for (Member& m : ms)
+    if (m.status == HQ_OK) Kmax = std::max(Kmax, m.K);
+
+  hq::Engine E(st);
+  E.tol = o.tol;
+  hq::DevArena xa[2], it, qa, pa;
+  struct Drain {  // destroyed first: on an early exit the stream drains before any buffer is freed
+    hipStream_t s;
+    ~Drain() { (void)hipStreamSynchronize(s); }
+  } drain{st};
+  size_t peak = 0;
+  auto note_peak = [&] {
+    peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + xa[0].high_water() +
+                              xa[1].high_water() + it.high_water() + qa.high_water() + pa.high_water());
+  };
+  int cur = 0;
+  for (Member& m : ms) {
+    if (m.status != HQ_OK) continue;
+    m.X = E.alloc_hmat_in(xa[cur], &m.t, caps_from(m.t, m.beff, o.max_rank), false);
+    build_x0(E, m.band, m.n, m.beff, m.ldab, m.mu, 1.0 / m.inf.alpha, m.X);
+  }
+  std::vector<Member*> done;
+  for (int k = 0; k < Kmax; ++k) {
+    std::vector<int> act;
+    for (int i = 0; i < nm; ++i)
+      if (ms[i].status == HQ_OK && k < ms[i].K) act.push_back(i);
+    if (act.empty()) break;
+    if (k == 0) {
+      for (int i : act) ms[i].capX = caps_from(ms[i].t, 3 * ms[i].beff + 8, o.max_rank);
+      // Alg. 3 lines 7-8: structured QR of [sqrt(c0) X0; I] (Algorithms 1/2) and Q1, Q2 in HODLR
+      const auto tg = clk::now();
+      std::vector<hq::HostHodlr> h1(act.size()), h2(act.size());
+#pragma omp parallel for schedule(dynamic, 1) if (act.size() > 1)
+      for (int j = 0; j < (int)act.size(); ++j) {
+        Member& m = ms[act[j]];
+        const auto tj = clk::now();
+        const hq::GivensSweep gs = hq::structured_qr(m.ab.data(), m.n, m.beff, m.ldab, m.mu,
+                                                     std::sqrt(m.w.c[0]) / m.inf.alpha);
+        const std::vector<int> capQ(m.t.L, 2 * m.beff);
+        hq::q_factors_hodlr(gs, m.t, m.beff, capQ, (int)m.t.maxleaf, h1[j], h2[j]);
+        m.inf.givens_seconds = secs(tj);
+      }
+      for (size_t j = 0; j < act.size(); ++j) {
+        Member& m = ms[act[j]];
+        const std::vector<int> capQ(m.t.L, 2 * m.beff);
+        m.Q1 = E.alloc_hmat_in(qa, &m.t, capQ, false);
+        m.Q2 = E.alloc_hmat_in(qa, &m.t, capQ, false);
+        upload_host(E, h1[j], m.Q1, false);
+        upload_host(E, h2[j], m.Q2, false);
+      }
+      HQ_CHECK(hipStreamSynchronize(st));  // the host copies go out of scope
+      if (act.size() > 1)
+        for (int i : act) ms[i].inf.givens_seconds = secs(tg);
+    } else {
+      std::vector<const hq::HMat*> xs;
+      for (int i : act) xs.push_back(&ms[i].X);
+      const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+      for (size_t j = 0; j < act.size(); ++j) ms[act[j]].capX = caps_grow(ms[act[j]].t, rk[j], o.max_rank, 2, 16);
+    }
+    std::vector<int> pend = act;
+    xa[cur ^ 1].reset();
+    for (int attempt = 0; !pend.empty(); ++attempt) {
       E.stage.reset();
       E.scratch.reset();
-      xa[cur ^ 1].reset();
       it.reset();
-      hq::HMat Xn = alloc(xa[cur ^ 1], capX, false);
-      E.clear_flag();
+      for (int i : pend) ms[i].Xn = E.alloc_hmat_in(xa[cur ^ 1], &ms[i].t, ms[i].capX, false);
+      E.clear_flags(nm);
       if (k == 0) {
-        // Alg. 3 lines 7-9: structured QR of [sqrt(c0) X0; I], Q1/Q2 in HODLR, X1
-        const auto tg = clk::now();
-        const hq::GivensSweep gs = hq::structured_qr(ab.data(), n, beff, ldab, mu, std::sqrt(c) / alpha);
-        const std::vector<int> capQ(t.L, 2 * beff);
-        hq::HostHodlr h1, h2;
-        hq::q_factors_hodlr(gs, t, beff, capQ, (int)t.maxleaf, h1, h2);
-        hq::HMat Q1 = alloc(it, capQ, false), Q2 = alloc(it, capQ, false);
-        upload_host(E, h1, Q1);
-        upload_host(E, h2, Q2);
-        inf.givens_seconds = secs(tg);
-        const hq::HView Xv = E.view(X);
-        E.product(E.view(Q1), E.view(Q2, true), &Xv, false, (a - bb / c) / std::sqrt(c), bb / c, Xn);
+        // Alg. 3 line 9: X1 = b0/c0 X0 + (a0 - b0/c0)/sqrt(c0) Q1 Q2^T
+        std::vector<hq::Engine::ProdTask> pv;
+        for (int i : pend) {
+          Member& m = ms[i];
+          const double a = m.w.a[0], bb = m.w.b[0], c = m.w.c[0];
+          hq::Engine::ProdTask q;
+          q.A = E.view(m.Q1);
+          q.B = E.view(m.Q2, true);
+          q.D = E.view(m.X);
+          q.alpha = (a - bb / c) / std::sqrt(c);
+          q.delta = bb / c;
+          q.C = &m.Xn;
+          q.fidx = i;
+          pv.push_back(q);
+        }
+        E.product(pv);
       } else {
         // Alg. 3 lines 11-14: W = chol(I + c X^T X); Y W = X; V W^T = Y; X+ = b/c X + (a - b/c) V
-        hq::HMat Z = alloc(it, capX, true), Linv = alloc(it, capX, false), Lf = alloc(it, capX, false);
-        hq::HMat Y = alloc(it, capX, false);
-        E.product(E.view(X, true), E.view(X), nullptr, true, c, 1.0, Z);
-        E.scratch.reset();
-        E.cholesky_inverse(Z, Linv, Lf, 2 * max_of(capX) + 16);
-        E.scratch.reset();
-        E.product(E.view(X), E.view(Linv, true), nullptr, false, 1.0, 0.0, Y);  // Y = X L^{-T} = X W^{-1}
-        E.scratch.reset();
-        const hq::HView Xv = E.view(X);
-        E.product(E.view(Y), E.view(Linv), &Xv, false, a - bb / c, bb / c, Xn);  // V = Y L^{-1} = Y W^{-T}
-      }
-      peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + xa[0].high_water() +
-                                xa[1].high_water() + it.high_water());
-      const int f = E.read_flag();
-      if (f & 2) return fail(HQ_ERR_NOT_POSDEF, "a leaf of I + c X^T X is not positive definite");
-      if (f & 5) {
-        bool grown = false;
-        for (int l = 0; l < t.L; ++l) {
-          const int nc = (int)std::min<int64_t>({(int64_t)capX[l] * 2, (int64_t)o.max_rank, t.ldf[l]});
-          grown |= nc > capX[l];
-          capX[l] = nc;
+        std::vector<hq::Engine::ProdTask> pz, py, px;
+        std::vector<hq::Engine::CholTask> pc;
+        for (int i : pend) {
+          Member& m = ms[i];
+          m.Z = E.alloc_hmat_in(it, &m.t, m.capX, true);
+          m.Linv = E.alloc_hmat_in(it, &m.t, m.capX, false);
+          m.Lf = E.alloc_hmat_in(it, &m.t, m.capX, false);
+          m.Y = E.alloc_hmat_in(it, &m.t, m.capX, false);
+          const double a = m.w.a[k], bb = m.w.b[k], c = m.w.c[k];
+          hq::Engine::ProdTask q;
+          q.A = E.view(m.X, true);
+          q.B = E.view(m.X);
+          q.d_identity = true;
+          q.alpha = c;
+          q.delta = 1.0;
+          q.C = &m.Z;
+          q.fidx = i;
+          pz.push_back(q);
+          pc.push_back(hq::Engine::CholTask{&m.Z, &m.Linv, &m.Lf, 2 * max_of(m.capX) + 16, i});
+          q = hq::Engine::ProdTask{};
+          q.A = E.view(m.X);
+          q.B = E.view(m.Linv, true);  // Y = X L^{-T} = X W^{-1}
+          q.C = &m.Y;
+          q.fidx = i;
+          py.push_back(q);
+          q = hq::Engine::ProdTask{};
+          q.A = E.view(m.Y);
+          q.B = E.view(m.Linv);  // V = Y L^{-1} = Y W^{-T}
+          q.D = E.view(m.X);
+          q.alpha = a - bb / c;
+          q.delta = bb / c;
+          q.C = &m.Xn;
+          q.fidx = i;
+          px.push_back(q);
         }
-        if (!grown || attempt > 6) return fail(HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
-        ++inf.redo_count;
-        continue;
+        E.product(pz);
+        E.scratch.reset();
+        E.cholesky_inverse(pc);
+        E.scratch.reset();
+        E.product(py);
+        E.scratch.reset();
+        E.product(px);
       }
-      X = Xn;
-      cur ^= 1;
-      break;
+      note_peak();
+      const std::vector<int> f = E.read_flags(nm);
+      std::vector<int> again;
+      for (int i : pend) {
+        Member& m = ms[i];
+        if (f[i] & 2) {
+          set_fail(m, HQ_ERR_NOT_POSDEF, "a leaf of I + c X^T X is not positive definite");
+          continue;
+        }
+        if (f[i] & (8 | 16 | 32)) {
+          set_fail(m, HQ_ERR_NONFINITE, (f[i] & 16)   ? "non-finite factors entering a recompression"
+                                        : (f[i] & 32) ? "non-finite triangular factor in a recompression"
+                                                      : "non-finite singular values in a recompression");
+          continue;
+        }
+        if (f[i] & 4) {
+          set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
+          continue;
+        }
+        if (f[i] & 1) {
+          bool grown = false;
+          for (int l = 0; l < m.t.L; ++l) {
+            const int nc = (int)std::min<int64_t>({(int64_t)m.capX[l] * 2, (int64_t)o.max_rank, m.t.ldf[l]});
+            grown |= nc > m.capX[l];
+            m.capX[l] = nc;
+          }
+          if (!grown || attempt > 6) {
+            set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
+            continue;
+          }
+          ++m.inf.redo_count;
+          again.push_back(i);
+          continue;
+        }
+        m.X = m.Xn;
+      }
+      pend.swap(again);
     }
-    if (k < 16) inf.max_rank_iter[k] = max_of(E.read_ranks(X));
+    cur ^= 1;
+    // per-iteration ranks; members whose schedule ends here are finished now, before their
+    // iterate's arena is recycled
+    std::vector<const hq::HMat*> xs;
+    std::vector<int> ok;
+    for (int i : act)
+      if (ms[i].status == HQ_OK) {
+        xs.push_back(&ms[i].X);
+        ok.push_back(i);
+      }
+    const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+    std::vector<hq::Engine::AffTask> fin;
+    pa.reset();
+    E.stage.reset();
+    E.scratch.reset();
+    for (size_t j = 0; j < ok.size(); ++j) {
+      Member& m = ms[ok[j]];
+      if (k < 16) m.inf.max_rank_iter[k] = max_of(rk[j]);
+      if (k + 1 == m.K) {
+        // Alg. 3 lines 17-18: U = X_K (symmetrised), P = (I - U)/2
+        m.P = E.alloc_hmat_in(pa, &m.t, caps_grow(m.t, rk[j], o.max_rank, 1, 0), false);
+        fin.push_back(hq::Engine::AffTask{&m.X, &m.P, projector ? -0.5 : 1.0, projector ? 0.5 : 0.0, ok[j]});
+      }
+    }
+    for (int attempt = 0; !fin.empty(); ++attempt) {
+      E.clear_flags(nm);
+      E.sym_affine(fin);
+      note_peak();
+      const std::vector<int> f = E.read_flags(nm);
+      std::vector<hq::Engine::AffTask> again;
+      for (const auto& a : fin) {
+        Member& m = ms[a.fidx];
+        if (f[a.fidx] & (8 | 16 | 32)) {
+          set_fail(m, HQ_ERR_NONFINITE, "non-finite values in the symmetrisation");
+        } else if (f[a.fidx] & 4) {
+          set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
+        } else if (f[a.fidx] & 1) {  // the symmetric part needs more columns than X_K had
+          std::vector<int> cp = m.P.cap;
+          bool grown = false;
+          for (int l = 0; l < m.t.L; ++l) {
+            const int nc = (int)std::min<int64_t>({(int64_t)cp[l] * 2, (int64_t)o.max_rank, m.t.ldf[l]});
+            grown |= nc > cp[l];
+            cp[l] = nc;
+          }
+          if (!grown || attempt > 6) {
+            set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
+          } else {
+            m.P = E.alloc_hmat_in(pa, &m.t, cp, false);
+            again.push_back(a);
+          }
+        }
+      }
+      for (const auto& a : fin) {
+        Member& m = ms[a.fidx];
+        if (m.status != HQ_OK || std::any_of(again.begin(), again.end(), [&](const hq::Engine::AffTask& x) {
+              return x.fidx == a.fidx;
+            }))
+          continue;
+        m.out = compact_copy(E, m.P, st, o.leaf);
+        m.inf.max_rank = m.out ? max_of(E.read_ranks(m.out->H)) : 0;
+        m.inf.bytes = (int64_t)m.out->H.bytes();
+      }
+      E.stage.reset();
+      E.scratch.reset();
+      fin.swap(again);
+    }
   }
-  // Alg. 3 lines 17-18: U = X_K (symmetrised), P = (I - U)/2
-  E.stage.reset();
-  E.scratch.reset();
-  it.reset();
-  const std::vector<int> capP = caps_grow(t, E.read_ranks(X), o.max_rank, 1, 0);
-  hq::HMat P = alloc(it, capP, false);
-  E.sym_affine(X, P, projector ? -0.5 : 1.0, projector ? 0.5 : 0.0);
-  E.clear_flag();
-  const int f = E.read_flag();
-  (void)f;
-  hq_hodlr_t h = compact_copy(E, P, st, o.leaf);
-  inf.max_rank = max_of(E.read_ranks(P));
-  inf.bytes = (int64_t)h->H.bytes();
-  inf.peak_bytes = (int64_t)peak;
-  inf.launches = E.launches;
-  inf.seconds = secs(t0);
-  *out = h;
-  if (info) *info = inf;
+  const double total = secs(t0);
+  for (Member& m : ms) {
+    m.inf.peak_bytes = (int64_t)peak;
+    m.inf.launches = E.launches;
+    m.inf.seconds = total;
+  }
+}
+
+hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu, const hq_opts& o, hipStream_t st,
+                   bool projector, hq_hodlr_t* out, hq_info* info) {
+  std::vector<Member> ms(1);
+  ms[0].band = band;
+  ms[0].n = n;
+  ms[0].b = b;
+  ms[0].ldab = ldab;
+  ms[0].mu = mu;
+  run_batch(ms, o, st, projector);
+  Member& m = ms[0];
+  if (m.status != HQ_OK) {
+    if (m.out) hodlr_destroy(m.out);
+    return fail(m.status, m.err);
+  }
+  *out = m.out;
+  if (info) *info = m.inf;
   return HQ_OK;
 }
 
@@ -458,6 +678,7 @@ const char* hq_status_string(hq_status s) {
     case HQ_ERR_NOT_POSDEF: return "not positive definite";
     case HQ_ERR_NO_CONVERGENCE: return "no convergence";
     case HQ_ERR_RANK_OVERFLOW: return "rank overflow";
+    case HQ_ERR_NONFINITE: return "non-finite values";
   }
   return "unknown status";
 }
@@ -477,8 +698,8 @@ hq_status hodlr_build(const double* band, int64_t n, int32_t b, int64_t ldab, do
     if (h->t.L > 0 && (int64_t)b > n / (int64_t(1) << h->t.L))
       return fail(HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block");
     hipStream_t st = (hipStream_t)stream;
-    h->e.reset(new hq::Engine(st, &h->t));
-    h->H = h->e->alloc_hmat(caps_from(h->t, b, 1 << 30), false);
+    h->e.reset(new hq::Engine(st));
+    h->H = h->e->alloc_hmat(&h->t, caps_from(h->t, b, 1 << 30), false);
     build_x0(*h->e, band, n, b, ldab, shift, 1.0 / scale, h->H);
     HQ_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
     h->d_w = h->e->persist.get<int>(1);
@@ -508,6 +729,46 @@ hq_status spectral_projector(const double* band, int64_t n, int32_t b, int64_t l
   if (s) return s;
   if ((s = check_band(band, n, b, ldab))) return s;
   return guard([&] { return run_qdwh(band, n, b, ldab, mu, o, (hipStream_t)stream, true, P_out, info); });
+}
+
+hq_status spectral_projector_batched(int32_t count, const double* const* bands, const int64_t* n, const int32_t* b,
+                                     const int64_t* ldab, const double* mu, const hq_opts* opts, void* stream,
+                                     hq_hodlr_t* P_out, hq_info* info) {
+  if (!P_out) return fail(HQ_ERR_ARG, "P_out is NULL");
+  if (count < 1 || count > hq::Engine::kFlagSlots) return fail(HQ_ERR_ARG, "count must be in [1, 1024]");
+  for (int i = 0; i < count; ++i) P_out[i] = nullptr;
+  if (!bands || !n || !b || !ldab || !mu) return fail(HQ_ERR_ARG, "bands, n, b, ldab or mu is NULL");
+  hq_opts o;
+  hq_status s = check_opts(opts, o);
+  if (s) return s;
+  for (int i = 0; i < count; ++i)
+    if ((s = check_band(bands[i], n[i], b[i], ldab[i]))) return fail(s, "member " + std::to_string(i) + ": " + g_err);
+  return guard([&]() -> hq_status {
+    std::vector<Member> ms(count);
+    for (int i = 0; i < count; ++i) {
+      ms[i].band = bands[i];
+      ms[i].n = n[i];
+      ms[i].b = b[i];
+      ms[i].ldab = ldab[i];
+      ms[i].mu = mu[i];
+    }
+    run_batch(ms, o, (hipStream_t)stream, true);
+    hq_status first = HQ_OK;
+    for (int i = 0; i < count; ++i) {
+      Member& m = ms[i];
+      if (m.status != HQ_OK) {
+        if (m.out) hodlr_destroy(m.out);
+        m.out = nullptr;
+        if (first == HQ_OK) {
+          first = m.status;
+          g_err = "member " + std::to_string(i) + ": " + m.err;
+        }
+      }
+      P_out[i] = m.out;
+      if (info) info[i] = m.inf;
+    }
+    return first;
+  });
 }
 
 hq_status apply_projector(hq_hodlr_t P, const double* X, int64_t ldx, int32_t ncols, double* Y, int64_t ldy,
@@ -655,7 +916,7 @@ hq_status hq_test_gemm(const double* A, const double* B, double* C, int32_t m, i
   return guard([&]() -> hq_status {
     hq::Tree t;
     t.build(1, 2);
-    hq::Engine e((hipStream_t)stream, &t);
+    hq::Engine e((hipStream_t)stream);
     hq::GemmTask g{};
     g.A = A; g.B = B; g.C = C; g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.opA = opA; g.opB = opB; g.alpha = alpha; g.beta = beta;
@@ -670,7 +931,7 @@ hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, do
   return guard([&]() -> hq_status {
     hq::Tree t;
     t.build(1, 2);
-    hq::Engine e((hipStream_t)stream, &t);
+    hq::Engine e((hipStream_t)stream);
     int* dr = e.scratch.get<int>(1);
     hq::launch_fill_int(dr, r, 1, e.st);
     // reuse compress_sym's QR stage through a recompress with V = nothing: run QR directly
@@ -689,8 +950,8 @@ hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, do
     hq::QrTask* dq = e.stage.upload(std::vector<hq::QrTask>{q}, e.st);
     int nst = 0;
     while ((1 << nst) < q.ntiles) ++nst;
-    for (int s = 0; s <= nst; ++s) hq::launch_qr_stage(dq, 1, s, (q.ntiles + (1 << s) - 1) >> s, q.hs, rc, e.st);
-    hq::launch_qr_final(dq, 1, rc, e.st);
+    for (int s = 0; s <= nst; ++s) hq::launch_qr_stage(dq, 1, s, (q.ntiles + (1 << s) - 1) >> s, e.d_flag, e.st);
+    hq::launch_qr_final(dq, 1, e.d_flag, e.st);
     HQ_CHECK(hipStreamSynchronize(e.st));
     return HQ_OK;
   });
@@ -702,7 +963,7 @@ hq_status hq_test_recompress(const double* Us, int32_t m, const double* Vs, int3
   return guard([&]() -> hq_status {
     hq::Tree t;
     t.build(1, 2);
-    hq::Engine e((hipStream_t)stream, &t);
+    hq::Engine e((hipStream_t)stream);
     e.tol = tol;
     int* dr = e.scratch.get<int>(2);
     hq::launch_fill_int(dr, r, 1, e.st);
@@ -712,7 +973,9 @@ hq_status hq_test_recompress(const double* Us, int32_t m, const double* Vs, int3
     e.recompress({rt});
     HQ_CHECK(hipMemcpyAsync(k, dr + 1, sizeof(int), hipMemcpyDeviceToHost, e.st));
     HQ_CHECK(hipStreamSynchronize(e.st));
-    return (e.read_flag() & 1) ? fail(HQ_ERR_RANK_OVERFLOW, "rank above kcap") : HQ_OK;
+    const int f = e.read_flag();
+    if (f & (8 | 16 | 32)) return fail(HQ_ERR_NONFINITE, "non-finite values in the stacked factors");
+    return (f & 1) ? fail(HQ_ERR_RANK_OVERFLOW, "rank above kcap") : HQ_OK;
   });
 }
 
@@ -730,10 +993,10 @@ hq_status hq_test_from_dense(const double* dense, int64_t n, int64_t ld, const h
     const hq::Tree& t = h->t;
     if (t.L > 0 && t.ldf[0] > 1024) return fail(HQ_ERR_UNSUPPORTED, "test compression limited to n <= 2048");
     hipStream_t st = (hipStream_t)stream;
-    h->e.reset(new hq::Engine(st, &t));
+    h->e.reset(new hq::Engine(st));
     hq::Engine& e = *h->e;
     e.tol = o.tol;
-    h->H = e.alloc_hmat(caps_from(t, cap, 1 << 30), false);
+    h->H = e.alloc_hmat(&t, caps_from(t, cap, 1 << 30), false);
     // leaves
     for (int i = 0; i < t.nleaves; ++i) {
       const int p = t.ninternal + i;
@@ -791,9 +1054,9 @@ hq_status hq_test_product(hq_hodlr_t A, int32_t transA, hq_hodlr_t B, int32_t tr
     hipStream_t st = (hipStream_t)stream;
     HQ_CHECK(hipEventSynchronize(A->done));
     HQ_CHECK(hipEventSynchronize(B->done));
-    hq::Engine E(st, &A->t);
+    hq::Engine E(st);
     E.tol = tol;
-    hq::HMat C = E.alloc_hmat(caps_from(A->t, cap, 1 << 30), lower_only != 0);
+    hq::HMat C = E.alloc_hmat(&A->t, caps_from(A->t, cap, 1 << 30), lower_only != 0);
     hq::HView dv;
     if (D) dv = E.view(D->H);
     E.product(E.view(A->H, transA != 0), E.view(B->H, transB != 0), D ? &dv : nullptr, d_identity != 0, alpha,
@@ -811,10 +1074,10 @@ hq_status hq_test_cholesky_inverse(hq_hodlr_t Z, int32_t cap, double tol, void* 
   return guard([&]() -> hq_status {
     hipStream_t st = (hipStream_t)stream;
     HQ_CHECK(hipEventSynchronize(Z->done));
-    hq::Engine E(st, &Z->t);
+    hq::Engine E(st);
     E.tol = tol;
     const std::vector<int> c = caps_from(Z->t, cap, 1 << 30);
-    hq::HMat Linv = E.alloc_hmat(c, false), Lf = E.alloc_hmat(c, false);
+    hq::HMat Linv = E.alloc_hmat(&Z->t, c, false), Lf = E.alloc_hmat(&Z->t, c, false);
     hq::HMat Zs = Z->H;
     Zs.lower_only = true;
     E.cholesky_inverse(Zs, Linv, Lf, 2 * cap + 16);
@@ -843,8 +1106,8 @@ hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ld
     const std::vector<int> capQ(t.L, 2 * b);
     hq::HostHodlr h1, h2;
     hq::q_factors_hodlr(gs, t, b, capQ, (int)t.maxleaf, h1, h2);
-    hq::Engine E(st, &t);
-    hq::HMat Q1 = E.alloc_hmat(capQ, false), Q2 = E.alloc_hmat(capQ, false);
+    hq::Engine E(st);
+    hq::HMat Q1 = E.alloc_hmat(&t, capQ, false), Q2 = E.alloc_hmat(&t, capQ, false);
     upload_host(E, h1, Q1);
     upload_host(E, h2, Q2);
     *q1 = compact_copy(E, Q1, st, leaf);

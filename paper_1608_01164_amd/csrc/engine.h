@@ -128,21 +128,25 @@ struct Thin {            // dense n_sub x w block (column-major) with a device w
 
 class Engine {
  public:
-  Engine(hipStream_t s, const Tree* t);
+  static constexpr int kFlagSlots = 1024;  // one status word per matrix of a batch
+  explicit Engine(hipStream_t s);
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
   ~Engine();
   hipStream_t st;
-  const Tree* t;
   DevArena persist, scratch;
   DescStage stage;
-  int* d_flag = nullptr;   // bit 0: rank overflow, bit 1: not positive definite, bit 2: stack overflow
+  // d_flag[i], status of batch member i: bit 0 rank overflow, bit 1 not positive definite, bit 2 stack
+  // overflow, bit 3 non-finite singular values, bit 4 non-finite stacked factors, bit 5 non-finite R
+  int* d_flag = nullptr;
   int* d_zero = nullptr;
   double tol = 1e-10;
   int64_t launches = 0;
 
-  HMat alloc_hmat(const std::vector<int>& cap, bool lower_only = false) { return alloc_hmat_in(persist, cap, lower_only); }
-  HMat alloc_hmat_in(DevArena& ar, const std::vector<int>& cap, bool lower_only = false);
+  HMat alloc_hmat(const Tree* t, const std::vector<int>& cap, bool lower_only = false) {
+    return alloc_hmat_in(persist, t, cap, lower_only);
+  }
+  HMat alloc_hmat_in(DevArena& ar, const Tree* t, const std::vector<int>& cap, bool lower_only = false);
   HView view(const HMat& h, bool trans = false) const { HView v; v.h = &h; v.trans = trans; v.zero = d_zero; return v; }
   void zero_ranks(HMat& h);
 
@@ -160,22 +164,42 @@ class Engine {
     const int* r; int rcap;
     double* U; double* V; int ldu, ldv; int* rank; int kcap;
     double thresh;
+    int fidx;
   };
   void recompress(const std::vector<RecTask>& tasks);
   // Symmetric factor compression: S (m x r) -> S J_k with S S^T ~ S' S'^T, drop sigma(S) <= thresh.
-  struct SymTask { const double* S; int lds; int m; const int* r; int rcap; double* out; int ldo; int* rank; int kcap; double thresh; };
+  struct SymTask {
+    const double* S; int lds; int m; const int* r; int rcap; double* out; int ldo; int* rank; int kcap; double thresh;
+    int fidx;
+  };
   void compress_sym(const std::vector<SymTask>& tasks);
 
-  // C = alpha op(A) op(B) + delta op(D)  (D may be null, or the identity when d_identity)
+  // C = alpha op(A) op(B) + delta op(D)  (D absent, a HODLR, or the identity), for a batch of
+  // independent matrices: every launch covers all members.
+  struct ProdTask {
+    HView A, B, D;      // D.h == nullptr: no D term
+    bool d_identity = false;
+    double alpha = 1.0, delta = 0.0;
+    HMat* C = nullptr;
+    int fidx = 0;
+  };
+  void product(const std::vector<ProdTask>& v);
   void product(HView A, HView B, const HView* D, bool d_identity, double alpha, double delta, HMat& C);
-  // Cholesky Z = L L^T of a symmetric HODLR (lower blocks + leaves); returns L^{-1} in Linv.
-  void cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS);
+  // Cholesky Z = L L^T of symmetric HODLR matrices (lower blocks + leaves); L^{-1} in Linv.  The
+  // members' recursions advance in lockstep, one launch per step for all of them.
+  struct CholTask { const HMat* Z; HMat* Linv; HMat* Lf; int capS; int fidx; };
+  void cholesky_inverse(const std::vector<CholTask>& v);
+  void cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) { cholesky_inverse({CholTask{&Z, &Linv, &Lf, capS, 0}}); }
   // out = sid * I + sx * (X + X^T) / 2 as a full HODLR (sign: sx = 1, sid = 0; projector: -1/2, 1/2)
-  void sym_affine(const HMat& X, HMat& P, double sx, double sid);
+  struct AffTask { const HMat* X; HMat* P; double sx, sid; int fidx; };
+  void sym_affine(const std::vector<AffTask>& v);
+  void sym_affine(const HMat& X, HMat& P, double sx, double sid) { sym_affine({AffTask{&X, &P, sx, sid, 0}}); }
   void copy_hmat(const HMat& src, HMat& dst);
 
-  int read_flag();
-  void clear_flag();
+  int read_flag() { return read_flags(1)[0]; }
+  std::vector<int> read_flags(int count);
+  void clear_flag() { clear_flags(1); }
+  void clear_flags(int count);
   std::vector<int> read_ranks(const HMat& h);
 
   // helpers

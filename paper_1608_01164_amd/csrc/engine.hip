@@ -121,16 +121,16 @@ HView::Blk HView::lower(int p) const {
 }
 
 // ---------------------------------------------------------------------------------------------
-Engine::Engine(hipStream_t s, const Tree* t_) : st(s), t(t_) {
-  HQ_CHECK(hipMalloc(&d_flag, 256));
-  d_zero = d_flag + 32;
-  HQ_CHECK(hipMemsetAsync(d_flag, 0, 256, st));
+Engine::Engine(hipStream_t s) : st(s) {
+  HQ_CHECK(hipMalloc(&d_flag, sizeof(int) * (kFlagSlots + 64)));
+  d_zero = d_flag + kFlagSlots;
+  HQ_CHECK(hipMemsetAsync(d_flag, 0, sizeof(int) * (kFlagSlots + 64), st));
 }
 Engine::~Engine() {
   if (d_flag) (void)hipFree(d_flag);
 }
 
-HMat Engine::alloc_hmat_in(DevArena& ar, const std::vector<int>& cap, bool lower_only) {
+HMat Engine::alloc_hmat_in(DevArena& ar, const Tree* t, const std::vector<int>& cap, bool lower_only) {
   HMat h;
   h.t = t;
   h.cap = cap;
@@ -148,7 +148,7 @@ HMat Engine::alloc_hmat_in(DevArena& ar, const std::vector<int>& cap, bool lower
   zero_ranks(h);
   return h;
 }
-void Engine::zero_ranks(HMat& h) { launch_fill_int(h.rank, 0, 2 * t->ninternal, st); }
+void Engine::zero_ranks(HMat& h) { launch_fill_int(h.rank, 0, 2 * h.t->ninternal, st); }
 
 void Engine::gemm(const std::vector<GemmTask>& v, int max_m, int max_n) {
   if (v.empty()) return;
@@ -161,16 +161,20 @@ void Engine::stack(const std::vector<StackTask>& v, int max_rows) {
   ++launches;
 }
 
-int Engine::read_flag() {
-  int f = 0;
-  HQ_CHECK(hipMemcpyAsync(&f, d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+std::vector<int> Engine::read_flags(int count) {
+  if (count < 1 || count > kFlagSlots) throw std::runtime_error("read_flags: count out of range");
+  std::vector<int> f(count, 0);
+  HQ_CHECK(hipMemcpyAsync(f.data(), d_flag, sizeof(int) * count, hipMemcpyDeviceToHost, st));
   HQ_CHECK(hipStreamSynchronize(st));
   return f;
 }
-void Engine::clear_flag() { launch_fill_int(d_flag, 0, 1, st); }
+void Engine::clear_flags(int count) {
+  if (count < 1 || count > kFlagSlots) throw std::runtime_error("clear_flags: count out of range");
+  launch_fill_int(d_flag, 0, count, st);
+}
 
 std::vector<int> Engine::read_ranks(const HMat& h) {
-  std::vector<int> r(std::max(1, 2 * t->ninternal));
+  std::vector<int> r(std::max(1, 2 * h.t->ninternal));
   HQ_CHECK(hipMemcpyAsync(r.data(), h.rank, sizeof(int) * r.size(), hipMemcpyDeviceToHost, st));
   HQ_CHECK(hipStreamSynchronize(st));
   return r;
@@ -181,12 +185,18 @@ std::vector<int> Engine::read_ranks(const HMat& h) {
 // per level so that updates of one launch never overlap.
 void Engine::mm_thin(const std::vector<ThinTask>& tasks) {
   if (tasks.empty()) return;
-  const int L = t->L;
+  int Lmax = 0, maxleaf = 1;
+  for (const ThinTask& T : tasks) {
+    Lmax = std::max(Lmax, T.H.h->t->L);
+    maxleaf = std::max(maxleaf, (int)T.H.h->t->maxleaf);
+  }
   std::vector<GemmTask> leafv, tv;
-  std::vector<std::vector<GemmTask>> upd(L);
+  std::vector<std::vector<GemmTask>> upd(Lmax);
   int wmax = 1, capmax = 1;
   int64_t rowmax = 1;
   for (const ThinTask& T : tasks) {
+    const Tree* t = T.H.h->t;
+    const int L = t->L;
     wmax = std::max(wmax, T.wcap);
     const int lr = Tree::level(T.root);
     const int64_t r0 = t->lo[T.root];
@@ -261,9 +271,9 @@ void Engine::mm_thin(const std::vector<ThinTask>& tasks) {
       }
     }
   }
-  gemm(leafv, (int)t->maxleaf, wmax);
+  gemm(leafv, maxleaf, wmax);
   gemm(tv, capmax, wmax);
-  for (int l = 0; l < L; ++l) gemm(upd[l], (int)rowmax, wmax);
+  for (int l = 0; l < Lmax; ++l) gemm(upd[l], (int)rowmax, wmax);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -296,7 +306,7 @@ void Engine::recompress(const std::vector<RecTask>& tasks) {
   for (int i = 0; i < nt; ++i) {
     const RecTask& T = tasks[i];
     const int rc = std::max(T.rcap, 1);
-    if (rc > 1024) throw std::runtime_error("recompress: stacked rank capacity above 1024");
+    if (rc > kMaxStack) throw std::runtime_error("recompress: stacked rank capacity above the kernel limit");
     Bufs& b = bufs[i];
     const size_t rr = (size_t)rc * rc;
     b.Ru = scratch.get<double>(rr);
@@ -324,6 +334,7 @@ void Engine::recompress(const std::vector<RecTask>& tasks) {
       q.work = scratch.get<double>((size_t)pl.ntiles * pl.hs * rc);
       q.R = side == 0 ? b.Ru : b.Rv;
       q.ldr = rc;
+      q.fidx = T.fidx;
       qv.push_back(q);
       maxtiles = std::max(maxtiles, pl.ntiles);
       hsmax = std::max(hsmax, pl.hs);
@@ -338,6 +349,7 @@ void Engine::recompress(const std::vector<RecTask>& tasks) {
     SvdTask s{};
     s.B = b.B; s.C = b.J; s.Jw = b.Jw; s.aux = b.aux; s.Wk = b.Wk; s.Jk = b.Jk; s.sig = nullptr; s.rp = T.r;
     s.kout = T.rank; s.ld = rc; s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
+    s.fidx = T.fidx;
     sv.push_back(s);
     GemmTask pu{};  // Pu = Rv^T Jk
     pu.A = b.Rv; pu.opA = 1; pu.lda = rc; pu.B = b.Jk; pu.ldb = rc; pu.C = b.Pu; pu.ldc = rc;
@@ -359,10 +371,10 @@ void Engine::recompress(const std::vector<RecTask>& tasks) {
   while ((1 << nst) < maxtiles) ++nst;
   for (int s = 0; s <= nst; ++s) {
     const int pairs = (maxtiles + (1 << s) - 1) >> s;
-    launch_qr_stage(dq, (int)qv.size(), s, pairs, hsmax, rmax, st);
+    launch_qr_stage(dq, (int)qv.size(), s, pairs, d_flag, st);
     ++launches;
   }
-  launch_qr_final(dq, (int)qv.size(), rmax, st);
+  launch_qr_final(dq, (int)qv.size(), d_flag, st);
   gemm(gB, rmax, rmax);
   launch_svd(stage.upload(sv, st), nt, d_flag, st);
   launches += 2;
@@ -380,7 +392,7 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
   for (int i = 0; i < nt; ++i) {
     const SymTask& T = tasks[i];
     const int rc = std::max(T.rcap, 1);
-    if (rc > 1024) throw std::runtime_error("compress_sym: factor capacity above 1024");
+    if (rc > kMaxStack) throw std::runtime_error("compress_sym: factor capacity above the kernel limit");
     const QrPlan pl = plan_qr(T.m, rc);
     double* R = scratch.get<double>((size_t)rc * rc);
     double* J = scratch.get<double>((size_t)rc * rc);
@@ -390,7 +402,7 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
     double* Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     QrTask q{};
     q.M = T.S; q.ldm = T.lds; q.rows = T.m; q.rp = T.r; q.rcap = rc; q.hs = pl.hs; q.h0 = pl.h0;
-    q.ntiles = pl.ntiles; q.work = scratch.get<double>((size_t)pl.ntiles * pl.hs * rc); q.R = R; q.ldr = rc;
+    q.ntiles = pl.ntiles; q.work = scratch.get<double>((size_t)pl.ntiles * pl.hs * rc); q.R = R; q.ldr = rc; q.fidx = T.fidx;
     qv.push_back(q);
     maxtiles = std::max(maxtiles, pl.ntiles);
     hsmax = std::max(hsmax, pl.hs);
@@ -399,7 +411,7 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
     mmax = std::max(mmax, T.m);
     SvdTask s{};
     s.B = R; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc;
-    s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
+    s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh; s.fidx = T.fidx;
     sv.push_back(s);
     GemmTask g{};  // out = S Jk
     g.A = T.S; g.lda = T.lds; g.B = Jk; g.ldb = rc; g.C = T.out; g.ldc = T.ldo;
@@ -411,10 +423,10 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
   while ((1 << nst) < maxtiles) ++nst;
   for (int s = 0; s <= nst; ++s) {
     const int pairs = (maxtiles + (1 << s) - 1) >> s;
-    launch_qr_stage(dq, nt, s, pairs, hsmax, rmax, st);
+    launch_qr_stage(dq, nt, s, pairs, d_flag, st);
     ++launches;
   }
-  launch_qr_final(dq, nt, rmax, st);
+  launch_qr_final(dq, nt, d_flag, st);
   launch_svd(stage.upload(sv, st), nt, d_flag, st);
   launches += 2;
   gemm(go, mmax, kmax);
@@ -426,134 +438,166 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
 // where T_p collects the low-rank products that ancestors of p contribute inside p x p:
 //   T_a = T_p|aa + A_ab B_ba,   T_b = T_p|bb + A_ba B_ab,
 // carried top-down in factored, recompressed form.  Leaves: C_i = A_i B_i + T_i.
+// All members of the batch share every launch; a member takes part in level l if its tree has it.
 void Engine::product(HView A, HView B, const HView* D, bool d_identity, double alpha, double delta, HMat& C) {
-  const int L = t->L;
-  const bool full = !C.lower_only;
+  ProdTask q;
+  q.A = A;
+  q.B = B;
+  if (D) q.D = *D;
+  q.d_identity = d_identity;
+  q.alpha = alpha;
+  q.delta = delta;
+  q.C = &C;
+  product(std::vector<ProdTask>{q});
+}
+
+void Engine::product(const std::vector<ProdTask>& batch) {
+  if (batch.empty()) return;
   const double tolT = 0.25 * tol;
   struct NodeBufs {
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *P4 = nullptr;
     int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
   };
-  std::vector<NodeBufs> nb(std::max(1, t->ninternal));
-  // 1) thin products for every internal node
+  struct TermF { double* E; double* F; int ld; const int* r; int cap; };
+  const int nm = (int)batch.size();
+  std::vector<std::vector<NodeBufs>> nbm(nm);
+  std::vector<std::vector<TermF>> termm(nm);
+  int Lmax = 0;
+  // 1) thin products for every internal node of every member
   std::vector<ThinTask> thin;
-  for (int p = 0; p < t->ninternal; ++p) {
-    const int a = 2 * p + 1, b = 2 * p + 2, ld = (int)t->ldf[Tree::level(p)];
-    const HView::Blk Au = A.upper(p), Al = A.lower(p), Bu = B.upper(p), Bl = B.lower(p);
-    NodeBufs& q = nb[p];
-    if (full) {
-      q.c1 = Bu.cap;
-      q.P1 = scratch.get<double>((size_t)ld * q.c1);
-      thin.push_back({A, a, Bu.U, Bu.ld, q.P1, ld, Bu.r, Bu.cap, 1.0, 0.0});  // A_aa Uu_B
-      q.c2 = Au.cap;
-      q.P2 = scratch.get<double>((size_t)ld * q.c2);
-      thin.push_back({B.T(), b, Au.V, Au.ld, q.P2, ld, Au.r, Au.cap, 1.0, 0.0});  // B_bb^T Vu_A
+  for (int m = 0; m < nm; ++m) {
+    const ProdTask& P = batch[m];
+    const Tree* t = P.C->t;
+    const bool full = !P.C->lower_only;
+    Lmax = std::max(Lmax, t->L);
+    std::vector<NodeBufs>& nb = nbm[m];
+    nb.resize(std::max(1, t->ninternal));
+    termm[m].assign(t->nnodes, TermF{nullptr, nullptr, 1, d_zero, 0});
+    for (int p = 0; p < t->ninternal; ++p) {
+      const int a = 2 * p + 1, b = 2 * p + 2, ld = (int)t->ldf[Tree::level(p)];
+      const HView::Blk Au = P.A.upper(p), Al = P.A.lower(p), Bu = P.B.upper(p), Bl = P.B.lower(p);
+      NodeBufs& q = nb[p];
+      if (full) {
+        q.c1 = Bu.cap;
+        q.P1 = scratch.get<double>((size_t)ld * q.c1);
+        thin.push_back({P.A, a, Bu.U, Bu.ld, q.P1, ld, Bu.r, Bu.cap, 1.0, 0.0});  // A_aa Uu_B
+        q.c2 = Au.cap;
+        q.P2 = scratch.get<double>((size_t)ld * q.c2);
+        thin.push_back({P.B.T(), b, Au.V, Au.ld, q.P2, ld, Au.r, Au.cap, 1.0, 0.0});  // B_bb^T Vu_A
+      }
+      q.c3 = Bl.cap;
+      q.P3 = scratch.get<double>((size_t)ld * q.c3);
+      thin.push_back({P.A, b, Bl.U, Bl.ld, q.P3, ld, Bl.r, Bl.cap, 1.0, 0.0});  // A_bb Ul_B
+      q.c4 = Al.cap;
+      q.P4 = scratch.get<double>((size_t)ld * q.c4);
+      thin.push_back({P.B.T(), a, Al.V, Al.ld, q.P4, ld, Al.r, Al.cap, 1.0, 0.0});  // B_aa^T Vl_A
     }
-    q.c3 = Bl.cap;
-    q.P3 = scratch.get<double>((size_t)ld * q.c3);
-    thin.push_back({A, b, Bl.U, Bl.ld, q.P3, ld, Bl.r, Bl.cap, 1.0, 0.0});  // A_bb Ul_B
-    q.c4 = Al.cap;
-    q.P4 = scratch.get<double>((size_t)ld * q.c4);
-    thin.push_back({B.T(), a, Al.V, Al.ld, q.P4, ld, Al.r, Al.cap, 1.0, 0.0});  // B_aa^T Vl_A
   }
   mm_thin(thin);
 
   // 2) level sweep: C blocks of level l and the accumulated terms of level l+1
-  struct TermF { double* E; double* F; int ld; const int* r; int cap; };
-  std::vector<TermF> term(t->nnodes, TermF{nullptr, nullptr, 1, d_zero, 0});
-  for (int l = 0; l < L; ++l) {
-    const int f0 = (1 << l) - 1, cnt = 1 << l;
-    const int ldc = (int)t->ldf[l];
-    // core products M and G for the children's terms
+  for (int l = 0; l < Lmax; ++l) {
     std::vector<GemmTask> gm, gg;
     std::vector<StackTask> stk;
     std::vector<RecTask> rec;
     int maxrows = 1, mcapA = 1, mcapB = 1;
-    for (int p = f0; p < f0 + cnt; ++p) {
-      const int a = 2 * p + 1, b = 2 * p + 2;
-      const int64_t sa = t->size(a), sb = t->size(b), ofa = t->lo[a] - t->lo[p], ofb = t->lo[b] - t->lo[p];
-      maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
-      const HView::Blk Au = A.upper(p), Al = A.lower(p), Bu = B.upper(p), Bl = B.lower(p);
-      const TermF& Tp = term[p];
-      mcapA = std::max(mcapA, std::max(Au.cap, Al.cap));
-      mcapB = std::max(mcapB, std::max(Bu.cap, Bl.cap));
-      const int capT = std::min<int>((int)std::max(sa, sb), std::max(C.cap[l], std::max(Au.cap, Bu.cap)) * 2);
-      // --- C blocks
-      for (int s = 0; s < 2; ++s) {
-        if (s == 0 && !full) continue;
-        const int64_t mr = s == 0 ? sa : sb, mc = s == 0 ? sb : sa;
-        const int64_t ofr = s == 0 ? ofa : ofb, ofc = s == 0 ? ofb : ofa;
-        const HView::Blk Ax = s == 0 ? Au : Al, Bx = s == 0 ? Bu : Bl;
-        const NodeBufs& q = nb[p];
-        double* P_left = s == 0 ? q.P1 : q.P3;   // A_xx U_B  (rows r)
-        double* P_right = s == 0 ? q.P2 : q.P4;  // B_yy^T V_A (rows c)
-        HView::Blk Dx{nullptr, nullptr, d_zero, 1, 0};
-        if (D && !d_identity) Dx = s == 0 ? D->upper(p) : D->lower(p);
-        const int rcap = Bx.cap + Ax.cap + Tp.cap + Dx.cap;
-        double* Us = scratch.get<double>((size_t)ldc * rcap);
-        double* Vs = scratch.get<double>((size_t)ldc * rcap);
-        int* rs = scratch.get<int>(1);
-        StackTask su{};
-        su.dst = Us; su.ld = ldc; su.rows = (int)mr; su.wcap = rcap; su.wout = rs; su.nsrc = 4;
-        su.src[0] = {P_left, Bx.r, ldc, Bx.cap, alpha};
-        su.src[1] = {Ax.U, Ax.r, Ax.ld, Ax.cap, alpha};
-        su.src[2] = {Tp.E ? Tp.E + ofr : nullptr, Tp.r, Tp.ld, Tp.cap, alpha};
-        su.src[3] = {Dx.U, Dx.r, Dx.ld, Dx.cap, delta};
-        StackTask sv = su;
-        sv.dst = Vs; sv.rows = (int)mc; sv.wout = nullptr;
-        sv.src[0] = {Bx.V, Bx.r, Bx.ld, Bx.cap, 1.0};
-        sv.src[1] = {P_right, Ax.r, ldc, Ax.cap, 1.0};
-        sv.src[2] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
-        sv.src[3] = {Dx.V, Dx.r, Dx.ld, Dx.cap, 1.0};
-        stk.push_back(su);
-        stk.push_back(sv);
-        RecTask r{};
-        r.Us = Us; r.ldus = ldc; r.m = (int)mr; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mc; r.r = rs; r.rcap = rcap;
-        r.U = C.U(p, s); r.V = C.V(p, s); r.ldu = r.ldv = ldc; r.rank = C.rk(p, s); r.kcap = C.cap[l];
-        r.thresh = tol;
-        rec.push_back(r);
-      }
-      // --- terms for the children: T_a = T_p|aa + Uu_A (Vu_A^T Ul_B) Vl_B^T, T_b = T_p|bb + Ul_A (Vl_A^T Uu_B) Vu_B^T
-      for (int s = 0; s < 2; ++s) {
-        const int c = s == 0 ? a : b;
-        const int64_t mrow = s == 0 ? sa : sb, inner = s == 0 ? sb : sa, ofc = s == 0 ? ofa : ofb;
-        const HView::Blk Ax = s == 0 ? Au : Al, By = s == 0 ? Bl : Bu;
-        double* M = scratch.get<double>((size_t)std::max(Ax.cap, 1) * std::max(By.cap, 1));
-        double* G = scratch.get<double>((size_t)ldc * std::max(By.cap, 1));
-        GemmTask g1{};
-        g1.A = Ax.V; g1.opA = 1; g1.lda = Ax.ld; g1.B = By.U; g1.ldb = By.ld; g1.C = M; g1.ldc = std::max(Ax.cap, 1);
-        g1.m = Ax.cap; g1.mp = Ax.r; g1.n = By.cap; g1.np = By.r; g1.k = (int)inner; g1.alpha = 1.0; g1.beta = 0.0;
-        gm.push_back(g1);
-        GemmTask g2{};
-        g2.A = Ax.U; g2.lda = Ax.ld; g2.B = M; g2.ldb = std::max(Ax.cap, 1); g2.C = G; g2.ldc = ldc;
-        g2.m = (int)mrow; g2.n = By.cap; g2.np = By.r; g2.k = Ax.cap; g2.kp = Ax.r; g2.alpha = 1.0; g2.beta = 0.0;
-        gg.push_back(g2);
-        const int rcap = Tp.cap + By.cap;
-        double* Us = scratch.get<double>((size_t)ldc * rcap);
-        double* Vs = scratch.get<double>((size_t)ldc * rcap);
-        int* rs = scratch.get<int>(1);
-        StackTask su{};
-        su.dst = Us; su.ld = ldc; su.rows = (int)mrow; su.wcap = rcap; su.wout = rs; su.nsrc = 2;
-        su.src[0] = {Tp.E ? Tp.E + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
-        su.src[1] = {G, By.r, ldc, By.cap, 1.0};
-        StackTask sv = su;
-        sv.dst = Vs; sv.wout = nullptr;
-        sv.src[0] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
-        sv.src[1] = {By.V, By.r, By.ld, By.cap, 1.0};
-        stk.push_back(su);
-        stk.push_back(sv);
-        TermF nt;
-        nt.ld = ldc;
-        nt.cap = capT;
-        nt.E = scratch.get<double>((size_t)nt.ld * capT);
-        nt.F = scratch.get<double>((size_t)nt.ld * capT);
-        int* rr = scratch.get<int>(1);
-        nt.r = rr;
-        term[c] = nt;
-        RecTask r{};
-        r.Us = Us; r.ldus = ldc; r.m = (int)mrow; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mrow; r.r = rs; r.rcap = rcap;
-        r.U = nt.E; r.V = nt.F; r.ldu = r.ldv = nt.ld; r.rank = rr; r.kcap = capT; r.thresh = tolT;
-        rec.push_back(r);
+    for (int m = 0; m < nm; ++m) {
+      const ProdTask& P = batch[m];
+      const Tree* t = P.C->t;
+      if (l >= t->L) continue;
+      const bool full = !P.C->lower_only;
+      const HView* D = P.D.h ? &P.D : nullptr;
+      const double alpha = P.alpha, delta = P.delta;
+      HMat& C = *P.C;
+      std::vector<TermF>& term = termm[m];
+      const int f0 = (1 << l) - 1, cnt = 1 << l;
+      const int ldc = (int)t->ldf[l];
+      for (int p = f0; p < f0 + cnt; ++p) {
+        const int a = 2 * p + 1, b = 2 * p + 2;
+        const int64_t sa = t->size(a), sb = t->size(b), ofa = t->lo[a] - t->lo[p], ofb = t->lo[b] - t->lo[p];
+        maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
+        const HView::Blk Au = P.A.upper(p), Al = P.A.lower(p), Bu = P.B.upper(p), Bl = P.B.lower(p);
+        const TermF Tp = term[p];
+        mcapA = std::max(mcapA, std::max(Au.cap, Al.cap));
+        mcapB = std::max(mcapB, std::max(Bu.cap, Bl.cap));
+        const int capT = std::min<int>({(int)std::max(sa, sb), std::max(C.cap[l], std::max(Au.cap, Bu.cap)) * 2, kMaxStack});
+        // --- C blocks
+        for (int s = 0; s < 2; ++s) {
+          if (s == 0 && !full) continue;
+          const int64_t mr = s == 0 ? sa : sb, mc = s == 0 ? sb : sa;
+          const int64_t ofr = s == 0 ? ofa : ofb, ofc = s == 0 ? ofb : ofa;
+          const HView::Blk Ax = s == 0 ? Au : Al, Bx = s == 0 ? Bu : Bl;
+          const NodeBufs& q = nbm[m][p];
+          double* P_left = s == 0 ? q.P1 : q.P3;   // A_xx U_B  (rows r)
+          double* P_right = s == 0 ? q.P2 : q.P4;  // B_yy^T V_A (rows c)
+          HView::Blk Dx{nullptr, nullptr, d_zero, 1, 0};
+          if (D && !P.d_identity) Dx = s == 0 ? D->upper(p) : D->lower(p);
+          const int rcap = std::min(kMaxStack, Bx.cap + Ax.cap + Tp.cap + Dx.cap);  // wider: flagged by k_stack
+          double* Us = scratch.get<double>((size_t)ldc * rcap);
+          double* Vs = scratch.get<double>((size_t)ldc * rcap);
+          int* rs = scratch.get<int>(1);
+          StackTask su{};
+          su.dst = Us; su.ld = ldc; su.rows = (int)mr; su.wcap = rcap; su.wout = rs; su.nsrc = 4; su.fidx = P.fidx;
+          su.src[0] = {P_left, Bx.r, ldc, Bx.cap, alpha};
+          su.src[1] = {Ax.U, Ax.r, Ax.ld, Ax.cap, alpha};
+          su.src[2] = {Tp.E ? Tp.E + ofr : nullptr, Tp.r, Tp.ld, Tp.cap, alpha};
+          su.src[3] = {Dx.U, Dx.r, Dx.ld, Dx.cap, delta};
+          StackTask sv = su;
+          sv.dst = Vs; sv.rows = (int)mc; sv.wout = nullptr;
+          sv.src[0] = {Bx.V, Bx.r, Bx.ld, Bx.cap, 1.0};
+          sv.src[1] = {P_right, Ax.r, ldc, Ax.cap, 1.0};
+          sv.src[2] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
+          sv.src[3] = {Dx.V, Dx.r, Dx.ld, Dx.cap, 1.0};
+          stk.push_back(su);
+          stk.push_back(sv);
+          RecTask r{};
+          r.Us = Us; r.ldus = ldc; r.m = (int)mr; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mc; r.r = rs; r.rcap = rcap;
+          r.U = C.U(p, s); r.V = C.V(p, s); r.ldu = r.ldv = ldc; r.rank = C.rk(p, s); r.kcap = C.cap[l];
+          r.thresh = tol; r.fidx = P.fidx;
+          rec.push_back(r);
+        }
+        // --- terms for the children: T_a = T_p|aa + Uu_A (Vu_A^T Ul_B) Vl_B^T, T_b = T_p|bb + Ul_A (Vl_A^T Uu_B) Vu_B^T
+        for (int s = 0; s < 2; ++s) {
+          const int c = s == 0 ? a : b;
+          const int64_t mrow = s == 0 ? sa : sb, inner = s == 0 ? sb : sa, ofc = s == 0 ? ofa : ofb;
+          const HView::Blk Ax = s == 0 ? Au : Al, By = s == 0 ? Bl : Bu;
+          double* M = scratch.get<double>((size_t)std::max(Ax.cap, 1) * std::max(By.cap, 1));
+          double* G = scratch.get<double>((size_t)ldc * std::max(By.cap, 1));
+          GemmTask g1{};
+          g1.A = Ax.V; g1.opA = 1; g1.lda = Ax.ld; g1.B = By.U; g1.ldb = By.ld; g1.C = M; g1.ldc = std::max(Ax.cap, 1);
+          g1.m = Ax.cap; g1.mp = Ax.r; g1.n = By.cap; g1.np = By.r; g1.k = (int)inner; g1.alpha = 1.0; g1.beta = 0.0;
+          gm.push_back(g1);
+          GemmTask g2{};
+          g2.A = Ax.U; g2.lda = Ax.ld; g2.B = M; g2.ldb = std::max(Ax.cap, 1); g2.C = G; g2.ldc = ldc;
+          g2.m = (int)mrow; g2.n = By.cap; g2.np = By.r; g2.k = Ax.cap; g2.kp = Ax.r; g2.alpha = 1.0; g2.beta = 0.0;
+          gg.push_back(g2);
+          const int rcap = std::min(kMaxStack, Tp.cap + By.cap);
+          double* Us = scratch.get<double>((size_t)ldc * rcap);
+          double* Vs = scratch.get<double>((size_t)ldc * rcap);
+          int* rs = scratch.get<int>(1);
+          StackTask su{};
+          su.dst = Us; su.ld = ldc; su.rows = (int)mrow; su.wcap = rcap; su.wout = rs; su.nsrc = 2; su.fidx = P.fidx;
+          su.src[0] = {Tp.E ? Tp.E + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
+          su.src[1] = {G, By.r, ldc, By.cap, 1.0};
+          StackTask sv = su;
+          sv.dst = Vs; sv.wout = nullptr;
+          sv.src[0] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
+          sv.src[1] = {By.V, By.r, By.ld, By.cap, 1.0};
+          stk.push_back(su);
+          stk.push_back(sv);
+          TermF nt;
+          nt.ld = ldc;
+          nt.cap = capT;
+          nt.E = scratch.get<double>((size_t)nt.ld * capT);
+          nt.F = scratch.get<double>((size_t)nt.ld * capT);
+          int* rr = scratch.get<int>(1);
+          nt.r = rr;
+          term[c] = nt;
+          RecTask r{};
+          r.Us = Us; r.ldus = ldc; r.m = (int)mrow; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mrow; r.r = rs; r.rcap = rcap;
+          r.U = nt.E; r.V = nt.F; r.ldu = r.ldv = nt.ld; r.rank = rr; r.kcap = capT; r.thresh = tolT; r.fidx = P.fidx;
+          rec.push_back(r);
+        }
       }
     }
     gemm(gm, mcapA, mcapB);
@@ -564,46 +608,57 @@ void Engine::product(HView A, HView B, const HView* D, bool d_identity, double a
   // 3) leaves
   std::vector<GemmTask> g1, g2;
   std::vector<LeafAxpy> ax;
-  const int ldl = (int)t->maxleaf;
-  double* tmp = scratch.get<double>((size_t)t->nleaves * ldl * ldl);
-  int capTmax = 1;
-  for (int q = t->ninternal; q < t->nnodes; ++q) {
-    const int li = t->leaf_index(q), m = (int)t->size(q);
-    double* Ti = tmp + (size_t)li * ldl * ldl;
-    GemmTask g{};
-    g.A = A.h->leaf(li); g.opA = (A.trans && !A.h->lower_only) ? 1 : 0; g.lda = A.h->ldl;
-    g.B = B.h->leaf(li); g.opB = (B.trans && !B.h->lower_only) ? 1 : 0; g.ldb = B.h->ldl;
-    g.C = Ti; g.ldc = ldl; g.m = g.n = g.k = m; g.alpha = 1.0; g.beta = 0.0;
-    g1.push_back(g);
-    const TermF& Tq = term[q];
-    if (Tq.E) {
-      GemmTask e{};
-      e.A = Tq.E; e.lda = Tq.ld; e.B = Tq.F; e.ldb = Tq.ld; e.opB = 1; e.C = Ti; e.ldc = ldl;
-      e.m = e.n = m; e.k = Tq.cap; e.kp = Tq.r; e.alpha = 1.0; e.beta = 1.0;
-      g2.push_back(e);
-      capTmax = std::max(capTmax, Tq.cap);
-    }
-    LeafAxpy x{};
-    x.out = C.leaf(li); x.ldo = C.ldl; x.m = m; x.X = Ti; x.ldx = ldl;
-    if (C.lower_only) {
-      x.Y = Ti; x.ldy = ldl; x.transY = 1; x.alpha = 0.5 * alpha; x.beta = 0.5 * alpha;
-      x.gamma = d_identity ? delta : 0.0;
-    } else {
-      x.alpha = alpha;
-      if (d_identity) {
-        x.gamma = delta;
-      } else if (D) {
-        x.Y = D->h->leaf(li); x.ldy = D->h->ldl; x.transY = (D->trans && !D->h->lower_only) ? 1 : 0; x.beta = delta;
+  std::vector<IntCopy> zr;
+  int ldlmax = 1;
+  for (int m = 0; m < nm; ++m) {
+    const ProdTask& P = batch[m];
+    const Tree* t = P.C->t;
+    const HView* D = P.D.h ? &P.D : nullptr;
+    HMat& C = *P.C;
+    const int ldl = (int)t->maxleaf;
+    ldlmax = std::max(ldlmax, ldl);
+    double* tmp = scratch.get<double>((size_t)t->nleaves * ldl * ldl);
+    for (int q = t->ninternal; q < t->nnodes; ++q) {
+      const int li = t->leaf_index(q), mq = (int)t->size(q);
+      double* Ti = tmp + (size_t)li * ldl * ldl;
+      GemmTask g{};
+      g.A = P.A.h->leaf(li); g.opA = (P.A.trans && !P.A.h->lower_only) ? 1 : 0; g.lda = P.A.h->ldl;
+      g.B = P.B.h->leaf(li); g.opB = (P.B.trans && !P.B.h->lower_only) ? 1 : 0; g.ldb = P.B.h->ldl;
+      g.C = Ti; g.ldc = ldl; g.m = g.n = g.k = mq; g.alpha = 1.0; g.beta = 0.0;
+      g1.push_back(g);
+      const TermF& Tq = termm[m][q];
+      if (Tq.E) {
+        GemmTask e{};
+        e.A = Tq.E; e.lda = Tq.ld; e.B = Tq.F; e.ldb = Tq.ld; e.opB = 1; e.C = Ti; e.ldc = ldl;
+        e.m = e.n = mq; e.k = Tq.cap; e.kp = Tq.r; e.alpha = 1.0; e.beta = 1.0;
+        g2.push_back(e);
       }
+      LeafAxpy x{};
+      x.out = C.leaf(li); x.ldo = C.ldl; x.m = mq; x.X = Ti; x.ldx = ldl;
+      if (C.lower_only) {
+        x.Y = Ti; x.ldy = ldl; x.transY = 1; x.alpha = 0.5 * P.alpha; x.beta = 0.5 * P.alpha;
+        x.gamma = P.d_identity ? P.delta : 0.0;
+      } else {
+        x.alpha = P.alpha;
+        if (P.d_identity) {
+          x.gamma = P.delta;
+        } else if (D) {
+          x.Y = D->h->leaf(li); x.ldy = D->h->ldl; x.transY = (D->trans && !D->h->lower_only) ? 1 : 0; x.beta = P.delta;
+        }
+      }
+      ax.push_back(x);
     }
-    ax.push_back(x);
+    if (C.lower_only)  // lower_only result: upper blocks are implied, keep their ranks at zero
+      for (int p = 0; p < t->ninternal; ++p) zr.push_back(IntCopy{C.rk(p, 0), d_zero});
   }
-  gemm(g1, ldl, ldl);
-  gemm(g2, ldl, ldl);
-  launch_leaf_axpy(stage.upload(ax, st), (int)ax.size(), ldl, st);
+  gemm(g1, ldlmax, ldlmax);
+  gemm(g2, ldlmax, ldlmax);
+  launch_leaf_axpy(stage.upload(ax, st), (int)ax.size(), ldlmax, st);
   ++launches;
-  if (!full)  // lower_only result: upper blocks are implied, keep their ranks at zero
-    for (int p = 0; p < t->ninternal; ++p) launch_fill_int(C.rk(p, 0), 0, 1, st);
+  if (!zr.empty()) {
+    launch_copy_ints(stage.upload(zr, st), (int)zr.size(), st);
+    ++launches;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -612,146 +667,239 @@ void Engine::product(HView A, HView B, const HView* D, bool d_identity, double a
 // factor S (Z_bb - L_ba L_ba^T restricted = Z_bb - S S^T), compressed at every right turn.
 // Alongside, the inverse factor is assembled bottom-up:
 //   [L^-1]_aa = L_aa^-1, [L^-1]_bb = L_bb^-1, [L^-1]_ba = -(L_bb^-1 U)(L_aa^-T V)^T for L_ba = U V^T.
-void Engine::cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) {
-  zero_ranks(Linv);
-  zero_ranks(Lf);
+// A batch runs the recursions of all members in lockstep: a step handles the members' nodes at
+// the same position of the depth-first order together, leaves and internal nodes alike.
+void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
+  if (batch.empty()) return;
   struct SF { double* p; int ld; const int* r; int cap; };
+  struct Item { int m; int c; SF S; };
   const double thS = std::sqrt(0.1 * tol);
-  const HView Lv = view(Linv), LvT = view(Linv, true);
-  std::function<void(int, SF)> dfs = [&](int c, SF S) {
-    if (t->is_leaf(c)) {
-      const int li = t->leaf_index(c), m = (int)t->size(c);
-      std::vector<LeafAxpy> cp(1);
-      cp[0] = LeafAxpy{};
-      cp[0].out = Lf.leaf(li); cp[0].ldo = Lf.ldl; cp[0].X = Z.leaf(li); cp[0].ldx = Z.ldl; cp[0].m = m; cp[0].alpha = 1.0;
-      launch_leaf_axpy(stage.upload(cp, st), 1, m, st);
-      if (S.cap > 0) {
+  for (const CholTask& T : batch) {
+    zero_ranks(*T.Linv);
+    zero_ranks(*T.Lf);
+  }
+  std::function<void(const std::vector<Item>&)> dfs = [&](const std::vector<Item>& items) {
+    // leaves: Lf_i = chol(Z_i - S S^T), Linv_i = Lf_i^{-1}
+    std::vector<LeafAxpy> cp;
+    std::vector<GemmTask> gs;
+    std::vector<LeafTask> small, big;
+    std::vector<Item> inner;
+    int maxm = 1, maxsmall = 1;
+    for (const Item& it : items) {
+      const CholTask& T = batch[it.m];
+      const Tree* t = T.Z->t;
+      if (!t->is_leaf(it.c)) {
+        inner.push_back(it);
+        continue;
+      }
+      const int li = t->leaf_index(it.c), m = (int)t->size(it.c);
+      maxm = std::max(maxm, m);
+      LeafAxpy x{};
+      x.out = T.Lf->leaf(li); x.ldo = T.Lf->ldl; x.X = T.Z->leaf(li); x.ldx = T.Z->ldl; x.m = m; x.alpha = 1.0;
+      cp.push_back(x);
+      if (it.S.cap > 0) {
         GemmTask g{};
-        g.A = S.p; g.lda = S.ld; g.B = S.p; g.ldb = S.ld; g.opB = 1; g.C = Lf.leaf(li); g.ldc = Lf.ldl;
-        g.m = g.n = m; g.k = S.cap; g.kp = S.r; g.alpha = -1.0; g.beta = 1.0;
-        gemm({g}, m, m);
+        g.A = it.S.p; g.lda = it.S.ld; g.B = it.S.p; g.ldb = it.S.ld; g.opB = 1; g.C = T.Lf->leaf(li); g.ldc = T.Lf->ldl;
+        g.m = g.n = m; g.k = it.S.cap; g.kp = it.S.r; g.alpha = -1.0; g.beta = 1.0;
+        gs.push_back(g);
       }
-      std::vector<LeafTask> lt(1);
-      lt[0] = LeafTask{Lf.leaf(li), Linv.leaf(li), m, Lf.ldl, Linv.ldl};
-      LeafTask* d = stage.upload(lt, st);
+      const LeafTask lt{T.Lf->leaf(li), T.Linv->leaf(li), m, T.Lf->ldl, T.Linv->ldl, T.fidx};
       if (m <= 128) {
-        launch_chol_inv(d, 1, m, d_flag, st);
+        small.push_back(lt);
+        maxsmall = std::max(maxsmall, m);
       } else {
-        launch_potrf(d, 1, d_flag, st);
-        launch_trtri(d, 1, st);
+        big.push_back(lt);
       }
-      launches += 3;
-      return;
     }
-    const int p = c, a = 2 * p + 1, b = 2 * p + 2, l = Tree::level(p);
-    const int64_t sa = t->size(a), sb = t->size(b), la = t->lo[a] - t->lo[p], lb = t->lo[b] - t->lo[p];
-    const int ldc = (int)t->ldf[l];
-    dfs(a, SF{S.p ? S.p + la : nullptr, S.ld, S.r, S.cap});
-    const int capSb = std::min<int>((int)sb, capS);
-    double* Snew = scratch.get<double>((size_t)sb * capSb);
-    int* rnew = scratch.get<int>(1);
-    const DevArena::Mark mk = scratch.mark();
-    const int rcap = Z.cap[l] + S.cap;
-    double* Us = scratch.get<double>((size_t)ldc * rcap);
-    double* Vs0 = scratch.get<double>((size_t)ldc * rcap);
-    double* Vs = scratch.get<double>((size_t)ldc * rcap);
-    int* rs = scratch.get<int>(1);
-    StackTask su{};
-    su.dst = Us; su.ld = ldc; su.rows = (int)sb; su.wcap = rcap; su.wout = rs; su.nsrc = 2;
-    su.src[0] = {Z.U(p, 1), Z.rk(p, 1), ldc, Z.cap[l], 1.0};
-    su.src[1] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
-    StackTask sv = su;
-    sv.dst = Vs0; sv.rows = (int)sa; sv.wout = nullptr;
-    sv.src[0] = {Z.V(p, 1), Z.rk(p, 1), ldc, Z.cap[l], 1.0};
-    sv.src[1] = {S.p ? S.p + la : nullptr, S.r, S.ld, S.cap, -1.0};
-    stack({su, sv}, (int)std::max(sa, sb));
-    mm_thin({ThinTask{Lv, a, Vs0, ldc, Vs, ldc, rs, rcap, 1.0, 0.0}});
-    RecTask r{};
-    r.Us = Us; r.ldus = ldc; r.m = (int)sb; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sa; r.r = rs; r.rcap = rcap;
-    r.U = Lf.U(p, 1); r.V = Lf.V(p, 1); r.ldu = r.ldv = ldc; r.rank = Lf.rk(p, 1); r.kcap = Lf.cap[l]; r.thresh = tol;
-    recompress({r});
-    // Schur factor of the right child
-    const int rcS = S.cap + Lf.cap[l];
-    double* Sraw = scratch.get<double>((size_t)sb * rcS);
-    int* rsb = scratch.get<int>(1);
-    StackTask ss{};
-    ss.dst = Sraw; ss.ld = (int)sb; ss.rows = (int)sb; ss.wcap = rcS; ss.wout = rsb; ss.nsrc = 2;
-    ss.src[0] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
-    ss.src[1] = {Lf.U(p, 1), Lf.rk(p, 1), ldc, Lf.cap[l], 1.0};
-    stack({ss}, (int)sb);
-    compress_sym({SymTask{Sraw, (int)sb, (int)sb, rsb, rcS, Snew, (int)sb, rnew, capSb, thS}});
-    scratch.rewind(mk);
-    dfs(b, SF{Snew, (int)sb, rnew, capSb});
+    if (!cp.empty()) {
+      launch_leaf_axpy(stage.upload(cp, st), (int)cp.size(), maxm, st);
+      ++launches;
+      gemm(gs, maxm, maxm);
+      if (!small.empty()) {
+        launch_chol_inv(stage.upload(small, st), (int)small.size(), maxsmall, d_flag, st);
+        ++launches;
+      }
+      if (!big.empty()) {
+        LeafTask* d = stage.upload(big, st);
+        launch_potrf(d, (int)big.size(), d_flag, st);
+        launch_trtri(d, (int)big.size(), st);
+        launches += 2;
+      }
+    }
+    if (inner.empty()) return;
+    // left subtrees
+    std::vector<Item> left;
+    for (const Item& it : inner) {
+      const Tree* t = batch[it.m].Z->t;
+      const int a = 2 * it.c + 1;
+      const int64_t la = t->lo[a] - t->lo[it.c];
+      left.push_back(Item{it.m, a, SF{it.S.p ? it.S.p + la : nullptr, it.S.ld, it.S.r, it.S.cap}});
+    }
+    dfs(left);
+    // off-diagonal factor L_ba = (Z_ba - S_b S_a^T) L_aa^{-T}, and the Schur factor of the right child
+    const int ni = (int)inner.size();
+    std::vector<double*> Snew(ni);
+    std::vector<int*> rnew(ni);
+    std::vector<int> capSb(ni);
+    for (int i = 0; i < ni; ++i) {
+      const Item& it = inner[i];
+      const Tree* t = batch[it.m].Z->t;
+      const int64_t sb = t->size(2 * it.c + 2);
+      capSb[i] = std::min<int>({(int)sb, batch[it.m].capS, kMaxStack});
+      Snew[i] = scratch.get<double>((size_t)sb * capSb[i]);
+      rnew[i] = scratch.get<int>(1);
+    }
+    {
+      const DevArena::Mark mk = scratch.mark();
+      std::vector<StackTask> stk, stk2;
+      std::vector<ThinTask> th;
+      std::vector<RecTask> rec;
+      std::vector<SymTask> sym;
+      int maxrows = 1, maxsb = 1;
+      for (int i = 0; i < ni; ++i) {
+        const Item& it = inner[i];
+        const CholTask& T = batch[it.m];
+        const Tree* t = T.Z->t;
+        const int p = it.c, a = 2 * p + 1, b = 2 * p + 2, l = Tree::level(p);
+        const int64_t sa = t->size(a), sb = t->size(b), la = t->lo[a] - t->lo[p], lb = t->lo[b] - t->lo[p];
+        const int ldc = (int)t->ldf[l];
+        const SF& S = it.S;
+        maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
+        maxsb = std::max<int>(maxsb, (int)sb);
+        const int rcap = std::min(kMaxStack, T.Z->cap[l] + S.cap);
+        double* Us = scratch.get<double>((size_t)ldc * rcap);
+        double* Vs0 = scratch.get<double>((size_t)ldc * rcap);
+        double* Vs = scratch.get<double>((size_t)ldc * rcap);
+        int* rs = scratch.get<int>(1);
+        StackTask su{};
+        su.dst = Us; su.ld = ldc; su.rows = (int)sb; su.wcap = rcap; su.wout = rs; su.nsrc = 2; su.fidx = T.fidx;
+        su.src[0] = {T.Z->U(p, 1), T.Z->rk(p, 1), ldc, T.Z->cap[l], 1.0};
+        su.src[1] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
+        StackTask sv = su;
+        sv.dst = Vs0; sv.rows = (int)sa; sv.wout = nullptr;
+        sv.src[0] = {T.Z->V(p, 1), T.Z->rk(p, 1), ldc, T.Z->cap[l], 1.0};
+        sv.src[1] = {S.p ? S.p + la : nullptr, S.r, S.ld, S.cap, -1.0};
+        stk.push_back(su);
+        stk.push_back(sv);
+        th.push_back(ThinTask{view(*T.Linv), a, Vs0, ldc, Vs, ldc, rs, rcap, 1.0, 0.0});
+        RecTask r{};
+        r.Us = Us; r.ldus = ldc; r.m = (int)sb; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sa; r.r = rs; r.rcap = rcap;
+        r.U = T.Lf->U(p, 1); r.V = T.Lf->V(p, 1); r.ldu = r.ldv = ldc; r.rank = T.Lf->rk(p, 1); r.kcap = T.Lf->cap[l];
+        r.thresh = tol; r.fidx = T.fidx;
+        rec.push_back(r);
+        const int rcS = std::min(kMaxStack, S.cap + T.Lf->cap[l]);
+        double* Sraw = scratch.get<double>((size_t)sb * rcS);
+        int* rsb = scratch.get<int>(1);
+        StackTask ss{};
+        ss.dst = Sraw; ss.ld = (int)sb; ss.rows = (int)sb; ss.wcap = rcS; ss.wout = rsb; ss.nsrc = 2; ss.fidx = T.fidx;
+        ss.src[0] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
+        ss.src[1] = {T.Lf->U(p, 1), T.Lf->rk(p, 1), ldc, T.Lf->cap[l], 1.0};
+        stk2.push_back(ss);
+        sym.push_back(SymTask{Sraw, (int)sb, (int)sb, rsb, rcS, Snew[i], (int)sb, rnew[i], capSb[i], thS, T.fidx});
+      }
+      stack(stk, maxrows);
+      mm_thin(th);
+      recompress(rec);
+      stack(stk2, maxsb);
+      compress_sym(sym);
+      scratch.rewind(mk);
+    }
+    // right subtrees
+    std::vector<Item> right;
+    for (int i = 0; i < ni; ++i) {
+      const Item& it = inner[i];
+      const Tree* t = batch[it.m].Z->t;
+      right.push_back(Item{it.m, 2 * it.c + 2, SF{Snew[i], (int)t->size(2 * it.c + 2), rnew[i], capSb[i]}});
+    }
+    dfs(right);
+    // inverse blocks
     const DevArena::Mark mk2 = scratch.mark();
-    // inverse block
-    mm_thin({ThinTask{Lv, b, Lf.U(p, 1), ldc, Linv.U(p, 1), ldc, Lf.rk(p, 1), Lf.cap[l], -1.0, 0.0},
-             ThinTask{LvT, a, Lf.V(p, 1), ldc, Linv.V(p, 1), ldc, Lf.rk(p, 1), Lf.cap[l], 1.0, 0.0}});
-    launch_copy_int(Linv.rk(p, 1), Lf.rk(p, 1), 1, st);
+    std::vector<ThinTask> th;
+    std::vector<IntCopy> rk;
+    for (const Item& it : inner) {
+      const CholTask& T = batch[it.m];
+      const int p = it.c, a = 2 * p + 1, b = 2 * p + 2, l = Tree::level(p);
+      const int ldc = (int)T.Z->t->ldf[l];
+      th.push_back(ThinTask{view(*T.Linv), b, T.Lf->U(p, 1), ldc, T.Linv->U(p, 1), ldc, T.Lf->rk(p, 1), T.Lf->cap[l], -1.0, 0.0});
+      th.push_back(ThinTask{view(*T.Linv, true), a, T.Lf->V(p, 1), ldc, T.Linv->V(p, 1), ldc, T.Lf->rk(p, 1), T.Lf->cap[l], 1.0, 0.0});
+      rk.push_back(IntCopy{T.Linv->rk(p, 1), T.Lf->rk(p, 1)});
+    }
+    mm_thin(th);
+    launch_copy_ints(stage.upload(rk, st), (int)rk.size(), st);
+    ++launches;
     scratch.rewind(mk2);
   };
-  dfs(0, SF{nullptr, 1, d_zero, 0});
+  std::vector<Item> roots;
+  for (int m = 0; m < (int)batch.size(); ++m) roots.push_back(Item{m, 0, SF{nullptr, 1, d_zero, 0}});
+  dfs(roots);
 }
 
 // ---------------------------------------------------------------------------------------------
-void Engine::sym_affine(const HMat& X, HMat& P, double sx, double sid) {
-  zero_ranks(P);
-  std::vector<StackTask> stk;
+void Engine::sym_affine(const std::vector<AffTask>& batch) {
+  std::vector<StackTask> stk, cp;
   std::vector<RecTask> rec;
-  int maxrows = 1;
-  const HView Xv = view(X);
-  for (int p = 0; p < t->ninternal; ++p) {
-    const int l = Tree::level(p), ldc = (int)t->ldf[l];
-    const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
-    maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
-    const HView::Blk u = Xv.upper(p), lo = Xv.lower(p);
-    const int rcap = u.cap + lo.cap;
-    double* Us = scratch.get<double>((size_t)ldc * rcap);
-    double* Vs = scratch.get<double>((size_t)ldc * rcap);
-    int* rs = scratch.get<int>(1);
-    StackTask su{};
-    su.dst = Us; su.ld = ldc; su.rows = (int)sa; su.wcap = rcap; su.wout = rs; su.nsrc = 2;
-    su.src[0] = {u.U, u.r, u.ld, u.cap, 0.5 * sx};
-    su.src[1] = {lo.V, lo.r, lo.ld, lo.cap, 0.5 * sx};
-    StackTask sv = su;
-    sv.dst = Vs; sv.rows = (int)sb; sv.wout = nullptr;
-    sv.src[0] = {u.V, u.r, u.ld, u.cap, 1.0};
-    sv.src[1] = {lo.U, lo.r, lo.ld, lo.cap, 1.0};
-    stk.push_back(su);
-    stk.push_back(sv);
-    RecTask r{};
-    r.Us = Us; r.ldus = ldc; r.m = (int)sa; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sb; r.r = rs; r.rcap = rcap;
-    r.U = P.U(p, 0); r.V = P.V(p, 0); r.ldu = r.ldv = ldc; r.rank = P.rk(p, 0); r.kcap = P.cap[l]; r.thresh = tol;
-    rec.push_back(r);
+  std::vector<LeafAxpy> ax;
+  int maxrows = 1, maxleaf = 1;
+  for (const AffTask& A : batch) {
+    const Tree* t = A.X->t;
+    HMat& P = *A.P;
+    const double sx = A.sx;
+    zero_ranks(P);
+    const HView Xv = view(*A.X);
+    for (int p = 0; p < t->ninternal; ++p) {
+      const int l = Tree::level(p), ldc = (int)t->ldf[l];
+      const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
+      maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
+      const HView::Blk u = Xv.upper(p), lo = Xv.lower(p);
+      const int rcap = std::min(kMaxStack, u.cap + lo.cap);
+      double* Us = scratch.get<double>((size_t)ldc * rcap);
+      double* Vs = scratch.get<double>((size_t)ldc * rcap);
+      int* rs = scratch.get<int>(1);
+      StackTask su{};
+      su.dst = Us; su.ld = ldc; su.rows = (int)sa; su.wcap = rcap; su.wout = rs; su.nsrc = 2; su.fidx = A.fidx;
+      su.src[0] = {u.U, u.r, u.ld, u.cap, 0.5 * sx};
+      su.src[1] = {lo.V, lo.r, lo.ld, lo.cap, 0.5 * sx};
+      StackTask sv = su;
+      sv.dst = Vs; sv.rows = (int)sb; sv.wout = nullptr;
+      sv.src[0] = {u.V, u.r, u.ld, u.cap, 1.0};
+      sv.src[1] = {lo.U, lo.r, lo.ld, lo.cap, 1.0};
+      stk.push_back(su);
+      stk.push_back(sv);
+      RecTask r{};
+      r.Us = Us; r.ldus = ldc; r.m = (int)sa; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sb; r.r = rs; r.rcap = rcap;
+      r.U = P.U(p, 0); r.V = P.V(p, 0); r.ldu = r.ldv = ldc; r.rank = P.rk(p, 0); r.kcap = P.cap[l]; r.thresh = tol;
+      r.fidx = A.fidx;
+      rec.push_back(r);
+      // lower block = transpose of the upper one (issued after the recompression)
+      StackTask a{};
+      a.dst = P.U(p, 1); a.ld = ldc; a.rows = (int)sb; a.wcap = P.cap[l]; a.wout = P.rk(p, 1); a.nsrc = 1; a.fidx = A.fidx;
+      a.src[0] = {P.V(p, 0), P.rk(p, 0), ldc, P.cap[l], 1.0};
+      StackTask b = a;
+      b.dst = P.V(p, 1); b.rows = (int)sa; b.wout = nullptr;
+      b.src[0] = {P.U(p, 0), P.rk(p, 0), ldc, P.cap[l], 1.0};
+      cp.push_back(a);
+      cp.push_back(b);
+    }
+    for (int q = t->ninternal; q < t->nnodes; ++q) {
+      const int li = t->leaf_index(q);
+      LeafAxpy x{};
+      x.out = P.leaf(li); x.ldo = P.ldl; x.X = A.X->leaf(li); x.ldx = A.X->ldl; x.Y = A.X->leaf(li); x.ldy = A.X->ldl;
+      x.transY = 1; x.m = (int)t->size(q); x.alpha = 0.5 * sx; x.beta = 0.5 * sx; x.gamma = A.sid;
+      ax.push_back(x);
+    }
+    maxleaf = std::max(maxleaf, (int)t->maxleaf);
   }
   stack(stk, maxrows);
   recompress(rec);
-  // lower block = transpose of the upper one
-  std::vector<StackTask> cp;
-  for (int p = 0; p < t->ninternal; ++p) {
-    const int l = Tree::level(p), ldc = (int)t->ldf[l];
-    const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
-    StackTask a{};
-    a.dst = P.U(p, 1); a.ld = ldc; a.rows = (int)sb; a.wcap = P.cap[l]; a.wout = P.rk(p, 1); a.nsrc = 1;
-    a.src[0] = {P.V(p, 0), P.rk(p, 0), ldc, P.cap[l], 1.0};
-    StackTask b = a;
-    b.dst = P.V(p, 1); b.rows = (int)sa; b.wout = nullptr;
-    b.src[0] = {P.U(p, 0), P.rk(p, 0), ldc, P.cap[l], 1.0};
-    cp.push_back(a);
-    cp.push_back(b);
-  }
   stack(cp, maxrows);
-  std::vector<LeafAxpy> ax;
-  for (int q = t->ninternal; q < t->nnodes; ++q) {
-    const int li = t->leaf_index(q);
-    LeafAxpy x{};
-    x.out = P.leaf(li); x.ldo = P.ldl; x.X = X.leaf(li); x.ldx = X.ldl; x.Y = X.leaf(li); x.ldy = X.ldl;
-    x.transY = 1; x.m = (int)t->size(q); x.alpha = 0.5 * sx; x.beta = 0.5 * sx; x.gamma = sid;
-    ax.push_back(x);
+  if (!ax.empty()) {
+    launch_leaf_axpy(stage.upload(ax, st), (int)ax.size(), maxleaf, st);
+    ++launches;
   }
-  launch_leaf_axpy(stage.upload(ax, st), (int)ax.size(), (int)t->maxleaf, st);
 }
 
 void Engine::copy_hmat(const HMat& src, HMat& dst) {
+  const Tree* t = src.t;
   HQ_CHECK(hipMemcpyAsync(dst.leaves, src.leaves, sizeof(double) * (size_t)t->nleaves * src.ldl * src.ldl,
                           hipMemcpyDeviceToDevice, st));
   for (int l = 0; l < t->L; ++l) {

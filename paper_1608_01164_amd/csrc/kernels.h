@@ -39,6 +39,9 @@ struct GemmTask {
 };
 
 // dst[:, off_s : off_s + w_s] = scale_s * src_s[:, 0 : w_s] for s = 0..nsrc-1, off_s = sum of previous widths.
+// Widest stack of factor columns the recompression kernels take (TSQR and core SVD limits).
+constexpr int kMaxStack = 1024;
+
 struct StackSrc {
   const double* p;
   const int* wp;  // dynamic width (or null -> w)
@@ -48,7 +51,8 @@ struct StackSrc {
 struct StackTask {
   double* dst;
   int* wout;      // receives the total width (may be null)
-  int ld, rows, nsrc, wcap;  // wcap: capacity of dst in columns (overflow -> flag)
+  int ld, rows, nsrc, wcap;  // wcap: capacity of dst in columns (overflow -> flag[fidx])
+  int fidx;
   StackSrc src[4];
 };
 
@@ -62,6 +66,7 @@ struct QrTask {
   double* work;      // ntiles slots of (hs x rcap)
   double* R;         // output r x r
   int ldm, rows, rcap, hs, h0, ntiles, ldr;
+  int fidx;          // status word of the owning matrix (non-finite input 16, non-finite R 32)
 };
 
 // Truncated SVD of the small core B (r x r): Householder QR with column pivoting of B, stopped
@@ -81,6 +86,7 @@ struct SvdTask {
   int* kout;         // receives k'
   int ld, kcap;
   double thresh, qr_thresh;
+  int fidx;          // status word of the owning matrix (rank overflow sets bit 0)
 };
 
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.
@@ -88,7 +94,11 @@ struct LeafTask {
   double* A;
   double* B;    // second operand (trtri output)
   int m, lda, ldb;
+  int fidx;     // status word of the owning matrix
 };
+// d[i] = s[i] for a list of device ints
+struct IntCopy { int* d; const int* s; };
+void launch_copy_ints(const IntCopy* d_list, int n, hipStream_t s);
 
 // Band -> HODLR of X0 = (A - shift I) / scale.
 struct BandDesc {
@@ -100,9 +110,8 @@ struct BandDesc {
 
 void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, hipStream_t s);
 void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s);
-void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int hs_max, int rcap_max,
-                     hipStream_t s);
-void launch_qr_final(const QrTask* d_tasks, int ntasks, int rcap_max, hipStream_t s);
+void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, hipStream_t s);
+void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s);

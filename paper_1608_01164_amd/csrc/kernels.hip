@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_stack(const StackTask* __restrict__ tas
     int w = wp ? *wp : T->src[s].w;
     if (off + w > wcap) {
       w = wcap - off;
-      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 4);
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag + T->fidx, 4);
     }
     if (row < rows)
       for (int c = 0; c < w; ++c) dst[row + (size_t)(off + c) * ld] = sc * p[row + (size_t)c * lds];
@@ -286,8 +286,29 @@ constexpr int QR_WAVES = QR_THREADS / 64;
 constexpr int QR_RMAX = 1024;
 constexpr int QR_LDS = 16384;  // doubles of dynamic LDS (128 KiB)
 
+static __device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide reduction (all threads of a QR_THREADS block, uniform control flow); every thread
+// gets the result.
+template <bool MAX>
+static __device__ double block_reduce(double v, double* red) {
+  v = MAX ? wave_max(v) : wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int w = 1; w < QR_WAVES; ++w) t = MAX ? fmax(t, red[w]) : t + red[w];
+  __syncthreads();
+  return t;
+}
+
 static __device__ void householder_rows(double* X, int ld, int h, int r) {
   __shared__ double cn[QR_RMAX];  // squared norm of column c below row j, for the next pivot
+  __shared__ double red[QR_WAVES];
   __shared__ double sh_v0, sh_tau;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jend = (h - 1 < r) ? h - 1 : r;
@@ -301,17 +322,47 @@ static __device__ void householder_rows(double* X, int ld, int h, int r) {
   __syncthreads();
   unsigned long long flops = 0;
   for (int j = 0; j < jend; ++j) {
+    // cn[j] is final for this step (updates below write cn[c] for c > j only), so the branch is
+    // uniform over the block; X(j, j) is read by thread 0 alone on the fast path.
+    double s = cn[j], x0 = 0.0, unscale = 1.0;
+    if (s < 0x1p-800) {
+      // Tiny column (off-diagonal factors decay exponentially, so entries near the underflow
+      // threshold occur): its squared norm lost precision and 1/(nrm (nrm + |x0|)) could overflow.
+      // Rescale rows j.. of the column by a power of two (exact) and recompute the norm; the
+      // reflector is unchanged by the scaling, only the diagonal of R is scaled back.
+      double am = 0.0;
+      for (int i = j + tid; i < h; i += QR_THREADS) am = fmax(am, fabs(X[i + (size_t)j * ld]));
+      am = block_reduce<true>(am, red);
+      s = 0.0;
+      x0 = 0.0;
+      if (am > 0.0) {
+        // 2^-e can exceed the largest double when am is subnormal: apply it as two factors
+        const int e = ilogb(am);
+        const double sc1 = ldexp(1.0, -e > 1000 ? 1000 : -e), sc2 = ldexp(1.0, -e > 1000 ? -e - 1000 : 0);
+        unscale = ldexp(1.0, e);
+        double ss = 0.0;
+        for (int i = j + tid; i < h; i += QR_THREADS) {
+          const double x = (X[i + (size_t)j * ld] * sc1) * sc2;
+          X[i + (size_t)j * ld] = x;
+          if (i > j) ss += x * x;
+        }
+        s = block_reduce<false>(ss, red);  // its barriers also publish the scaled column
+        if (tid == 0) x0 = X[j + (size_t)j * ld];
+      }
+    } else if (tid == 0) {
+      x0 = X[j + (size_t)j * ld];
+    }
     if (tid == 0) {
-      const double s = cn[j], x0 = X[j + (size_t)j * ld];
       if (s == 0.0) {
         sh_tau = 0.0;
         sh_v0 = 0.0;
+        X[j + (size_t)j * ld] = x0 * unscale;
       } else {
         const double nrm = sqrt(x0 * x0 + s);
         const double beta = x0 >= 0.0 ? -nrm : nrm;
         sh_v0 = x0 - beta;
         sh_tau = 1.0 / (nrm * (nrm + fabs(x0)));
-        X[j + (size_t)j * ld] = beta;
+        X[j + (size_t)j * ld] = beta * unscale;
       }
     }
     __syncthreads();
@@ -369,7 +420,7 @@ static __device__ __forceinline__ int slot_live_rows(int a, int s, int h0, int r
   return cov < r ? (int)cov : r;
 }
 
-__global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restrict__ tasks, int stage) {
+__global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restrict__ tasks, int stage, int* flag) {
   extern __shared__ double qlds[];
   const QrTask T = tasks[blockIdx.y];
   const int r = live(T.rp, T.rcap);
@@ -420,6 +471,14 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
       if (i > c) X[i + (size_t)c * ldx] = 0.0;
     }
   }
+  if (stage == 0) {  // non-finite stacked input is reported (value 16) and traced to its source by the caller
+    bool bad = false;
+    for (int idx = tid; idx < rows0 * r; idx += QR_THREADS) {
+      const int i = idx % rows0, c = idx / rows0;
+      bad |= !(fabs(X[i + (size_t)c * ldx]) <= DBL_MAX);
+    }
+    if (bad) atomicOr(flag + T.fidx, 16);
+  }
   if (stage > 0)
     for (int idx = tid; idx < rb * r; idx += QR_THREADS) {
       const int i = idx % rb, c = idx / rb;
@@ -436,27 +495,32 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
   }
 }
 
-__global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tasks) {
+__global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tasks, int* flag) {
   const QrTask T = tasks[blockIdx.x];
   const int r = live(T.rp, T.rcap);
   const int rr = T.rows < r ? T.rows : r;
+  bool bad = false;
   for (int idx = threadIdx.x; idx < r * r; idx += 256) {
     const int i = idx % r, c = idx / r;
-    T.R[i + (size_t)c * T.ldr] = (i < rr && i <= c) ? T.work[i + (size_t)c * T.hs] : 0.0;
+    const double v = (i < rr && i <= c) ? T.work[i + (size_t)c * T.hs] : 0.0;
+    bad |= !(fabs(v) <= DBL_MAX);
+    T.R[i + (size_t)c * T.ldr] = v;
   }
+  if (bad) atomicOr(flag + T.fidx, 32);  // the triangular factor came out non-finite
 }
 
-void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int, int, hipStream_t s) {
+void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, hipStream_t s) {
   if (ntasks <= 0 || max_pairs <= 0) return;
   const size_t lds = sizeof(double) * (size_t)QR_LDS;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage, dim3(max_pairs, nt), dim3(QR_THREADS), lds, s, d_tasks + t0, stage));
+    HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage, dim3(max_pairs, nt), dim3(QR_THREADS), lds, s, d_tasks + t0, stage,
+                                         flag));
   }
 }
-void launch_qr_final(const QrTask* d_tasks, int ntasks, int, hipStream_t s) {
+void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
-  HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final, dim3(ntasks), dim3(256), 0, s, d_tasks));
+  HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -540,6 +604,12 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
       if (x.v > best.v || (x.v == best.v && x.i < best.i)) best = x;
     }
     if (tot <= qth2) { t = j; break; }
+    if (!(tot <= DBL_MAX) || best.i < j || best.i >= r) {
+      // non-finite trailing norms: no valid pivot exists; report and stop (the caller discards the result)
+      if (tid == 0) atomicOr(flag + T.fidx, 8);
+      t = j;
+      break;
+    }
     const int p = best.i;
     if (p != j) {
       for (int i = tid; i < r; i += SVD_THREADS) {
@@ -717,6 +787,10 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     double s = 0.0;
     for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ldc] * C[i + (size_t)c * ldc];
     s = wave_sum(s);
+    if (!(s <= DBL_MAX)) {  // NaN or Inf: flagged, and ranked last so that the ordering stays a permutation
+      if (lane == 0) atomicOr(flag + T.fidx, 8);
+      s = 0.0;
+    }
     if (lane == 0) sig2[c] = s;
   }
   __syncthreads();
@@ -731,7 +805,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   int kk = 0;
   for (int i = 0; i < t; ++i) kk += sig2[i] > th2;
   if (kk > T.kcap) {
-    if (tid == 0) atomicOr(flag, 1);
+    if (tid == 0) atomicOr(flag + T.fidx, 1);
     kk = T.kcap;
   }
   if (tid == 0) *T.kout = kk;
@@ -798,9 +872,9 @@ __global__ __launch_bounds__(256) void k_potrf(const LeafTask* __restrict__ task
   for (int j = 0; j < m; ++j) {
     if (tid == 0) {
       double d = A[j + (size_t)j * ld];
-      if (!(d > 0.0)) {
-        atomicOr(flag, 2);
-        d = fabs(d) + DBL_MIN;
+      if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
+        atomicOr(flag + T.fidx, 2);
+        d = 1.0;
       }
       d = sqrt(d);
       A[j + (size_t)j * ld] = d;
@@ -864,9 +938,9 @@ __global__ __launch_bounds__(512) void k_chol_inv(const LeafTask* __restrict__ t
   for (int j = 0; j < m; ++j) {
     if (tid == 0) {
       double d = S[j + j * m];
-      if (!(d > 0.0)) {
-        atomicOr(flag, 2);
-        d = fabs(d) + DBL_MIN;
+      if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
+        atomicOr(flag + T.fidx, 2);
+        d = 1.0;
       }
       piv = sqrt(d);
       S[j + j * m] = piv;
@@ -952,6 +1026,13 @@ void launch_fill_int(int* p, int value, int count, hipStream_t s) {
 }
 void launch_copy_int(int* dst, const int* src, int count, hipStream_t s) {
   if (count > 0) hipLaunchKernelGGL(k_copy_int, dim3((count + 255) / 256), dim3(256), 0, s, dst, src, count);
+}
+__global__ void k_copy_ints(const IntCopy* __restrict__ list, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *list[i].d = *list[i].s;
+}
+void launch_copy_ints(const IntCopy* d_list, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy_ints, dim3((n + 255) / 256), dim3(256), 0, s, d_list, n);
 }
 
 // ----------------------------------------------------------------------------------------------

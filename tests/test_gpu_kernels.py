@@ -44,6 +44,25 @@ def test_qr_r(rows, r):
         assert np.abs(R[kk:]).max() == 0.0
 
 
+@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (120, 90)])
+def test_qr_r_columns_near_underflow(rows, r):
+    """Columns scaled into the range where squared norms are denormal or underflow: the
+    triangular factor stays finite and matches LAPACK's column by column (relative to each
+    column's own size)."""
+    rng = np.random.default_rng(rows * r)
+    scales = np.array([10.0 ** -(140 + 20 * (c % 9)) if c % 3 else 1.0 for c in range(r)])
+    M = rng.standard_normal((rows, r)) * scales[None, :]
+    dR = empty(r, r)
+    hq.test_qr_r(dev(M), rows, r, rows, dR)
+    R = host(dR, r, r)
+    assert np.isfinite(R).all()
+    Rn = np.linalg.qr(M, mode="r")
+    kk = min(rows, r)
+    for c in range(r):
+        ref = np.abs(M[:, c]).max()  # a plain 2-norm of such a column underflows
+        assert np.abs(np.abs(R[:kk, c]) - np.abs(Rn[:kk, c])).max() <= 1e-12 * ref * np.sqrt(rows)
+
+
 @pytest.mark.parametrize("m,n,r,decay", [(50, 60, 10, 1.0), (300, 200, 40, 0.6), (1200, 900, 90, 0.8),
                                          (64, 64, 64, 0.5), (10, 400, 30, 0.3)])
 def test_recompress(m, n, r, decay):
@@ -68,6 +87,24 @@ def test_recompress(m, n, r, decay):
     assert np.linalg.norm(Uh @ Vh.T - M, 2) <= tol + 1e-13 * sv[0]
     # V is orthonormal where it matters: the Schur update U (V^T V) U^T equals U U^T to rounding
     assert np.abs(Uh @ (Vh.T @ Vh - np.eye(k)) @ Uh.T).max() < 1e-13 * max(1.0, sv[0] ** 2)
+
+
+@pytest.mark.parametrize("m,n,r", [(40, 50, 12), (600, 500, 200)])
+def test_recompress_nonfinite_is_reported(m, n, r):
+    """Regression: NaN stacks used to leave the core SVD's pivot search without a candidate; the
+    kernel now stops and the call reports non-finite values instead of touching memory."""
+    rng = np.random.default_rng(7)
+    Us = rng.standard_normal((m, r))
+    Vs = rng.standard_normal((n, r))
+    Us[:, :] = np.nan
+    U, V = empty(m, r), empty(n, r)
+    with pytest.raises(hq.HQError) as e:
+        hq.test_recompress(dev(Us), m, dev(Vs), n, r, 1e-10, r, U, V)
+    assert e.value.status == 5
+    # the library stays usable afterwards
+    Us = rng.standard_normal((m, 3)) @ rng.standard_normal((3, r))
+    k = hq.test_recompress(dev(Us), m, dev(Vs), n, r, 1e-10, r, U, V)
+    assert k == 3
 
 
 def _kernel_matrix(n, seed):

@@ -25,6 +25,8 @@ CASES = [
     ("metallic", lambda: w.tridiag_metallic(777, 2), 1, 64, 1e-10),
     ("tri-1024-leaf64", lambda: w.tridiag_uniform(1024, 0), 1, 64, 1e-10),
     ("band8-2048-leaf128", lambda: w.banded_normal(2048, 8, 0), 8, 128, 1e-10),
+    # off-diagonal factors decay to the underflow range (wide gap, 71-row leaves, depth 5)
+    ("tri-2284-leaf128-decay", lambda: w.banded_normal(2284, 1, rng=np.random.default_rng([0, 7])), 1, 128, 1e-10),
 ]
 
 
@@ -73,3 +75,48 @@ def test_singular_shift_is_reported():
     with pytest.raises(hq.HQError) as e:
         hq.spectral_projector(_dev_band(ab), 1, lam, leaf=16)
     assert e.value.status == 1
+
+
+BATCH = [
+    # band maker, b (one leaf size for the whole batch)
+    (lambda: w.tridiag_uniform(500, 11), 1),
+    (lambda: w.banded_normal(257, 3, 12), 3),
+    (lambda: w.laplacian(700), 1),
+    (lambda: w.tridiag_metallic(777, 13), 1),
+    (lambda: w.banded_normal(1024, 8, 14), 8),
+    (lambda: w.tridiag_uniform(64, 15), 1),  # a single leaf: dense QDWH
+]
+
+
+def test_batched_parity_and_equal_to_single_calls():
+    """Members of uneven size, bandwidth and tree depth advance together; each must meet the
+    oracle gate, and equal the single-matrix call bit for bit (the batch only groups launches)."""
+    bands, bs, mus, refs = [], [], [], []
+    for maker, b in BATCH:
+        ab = maker()
+        ref = eig.spectral_projector(ab, nu=ab.shape[0] // 2)
+        bands.append(_dev_band(ab))
+        bs.append(b)
+        mus.append(ref.mu)
+        refs.append(ref)
+    Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=64, tol=1e-10)
+    assert st == 0
+    for i, (P, info, ref) in enumerate(zip(Ps, infos, refs)):
+        n = ref.Pi.shape[0]
+        Pd = oh.to_dense(P.export())
+        err2 = norms.lanczos_norm(lambda x: (Pd - ref.Pi) @ x, n, steps=min(n, 80))
+        print(f"member {i}: n={n} b={bs[i]} K={info['iters']} maxrank={info['max_rank']} ||P-Pi||_2={err2:.3e}")
+        assert err2 <= GATE
+        P1, info1 = hq.spectral_projector(bands[i], bs[i], mus[i], leaf=64, tol=1e-10)
+        assert info1["iters"] == info["iters"]
+        assert np.array_equal(oh.to_dense(P1.export()), Pd)
+
+
+def test_batched_reports_failed_member():
+    good = w.tridiag_uniform(300, 16)
+    ref = eig.spectral_projector(good, nu=150)
+    lap = w.laplacian(65)  # 0 is an eigenvalue of the odd-order Laplacian
+    Ps, infos, st = hq.spectral_projector_batched([_dev_band(good), _dev_band(lap)], [1, 1], [ref.mu, 0.0], leaf=32)
+    assert st == 1 and Ps[1] is None and Ps[0] is not None
+    Pd = oh.to_dense(Ps[0].export())
+    assert np.linalg.norm(Pd - ref.Pi, 2) <= GATE
