@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="disable the library's per-launch kernel timers")
+    ap.add_argument("--no-predictor", action="store_true",
+                    help="capacities from the previous iterate's ranks instead of the trained rank predictor")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -135,6 +137,7 @@ def main():
     if args.workload in BATCHED:
         return main_batched(args, BATCHED[args.workload])
     maker, b, leaf, tol = WORKLOADS[args.workload]
+    pred = _predictor(args)
     ab = maker()
     n = ab.shape[0]
     nu = n // 2
@@ -145,7 +148,7 @@ def main():
           file=sys.stderr, flush=True)
     info = None
     for i in range(args.warmup):
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred)
         P.close()
         print(f"# warmup {i}: {info['seconds']:.3f} s, K={info['iters']}, max rank {info['max_rank']}",
               file=sys.stderr, flush=True)
@@ -158,7 +161,7 @@ def main():
     for i in range(args.steps):
         if P is not None:
             P.close()
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred)
         infos.append(info)
         print(f"# step {i}: {info['seconds']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -175,7 +178,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "b": b, "leaf": leaf, "tol": tol, "nu": nu, "mu": mu,
-                   "gap": gap, "precision": "fp64", "parallelism": "single-gpu"},
+                   "gap": gap, "precision": "fp64", "parallelism": "single-gpu",
+                   "capacities": "predictor" if pred is not None else "previous ranks"},
         "iters": info["iters"], "max_rank": info["max_rank"], "launches": info["launches"],
         "setup_s": info["setup_seconds"], "givens_s": info["givens_seconds"], "peak_bytes": info["peak_bytes"],
         "redo_count": info["redo_count"],
@@ -189,6 +193,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _predictor(args):
+    if args.no_predictor:
+        return None
+    from paper_1608_01164_amd import predictor as hp
+    return hp.load() if os.path.exists(hp.DEFAULT_PATH) else None
+
+
 def main_batched(args, count, leaf=128, tol=1e-10):
     """One step = one spectral_projector_batched call over all `count` matrices."""
     import torch
@@ -196,6 +207,7 @@ def main_batched(args, count, leaf=128, tol=1e-10):
     import paper_1608_01164_amd as hq
     import workloads as wl
 
+    pred = _predictor(args)
     mats = wl.batched_banded(count, seed=0)
     bs = [m.shape[1] - 1 for m in mats]
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
@@ -208,7 +220,7 @@ def main_batched(args, count, leaf=128, tol=1e-10):
           f"tol={tol}, min gap={min(x[1] for x in mg):.3e}", file=sys.stderr, flush=True)
 
     def step():
-        Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol)
+        Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol, predictor=pred)
         if st != 0:
             bad = [(i, mats[i].shape[0], bs[i], mg[i][1]) for i, P in enumerate(Ps) if P is None]
             print(f"# failed members (index, n, b, gap): {bad}; {hq.lib().hq_last_error().decode()}",
@@ -252,7 +264,8 @@ def main_batched(args, count, leaf=128, tol=1e-10):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "count": count, "sum_n": nsum, "leaf": leaf, "tol": tol,
-                   "precision": "fp64", "parallelism": "single-gpu, batched"},
+                   "precision": "fp64", "parallelism": "single-gpu, batched",
+                   "capacities": "predictor" if pred is not None else "previous ranks"},
         "iters_max": max(i["iters"] for i in infos), "max_rank": max(i["max_rank"] for i in infos),
         "redo_count": sum(i["redo_count"] for i in infos), "launches": infos[0]["launches"],
         "peak_bytes": infos[0]["peak_bytes"], "checks": chk,

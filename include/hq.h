@@ -42,7 +42,8 @@ typedef enum {
   HQ_ERR_NONFINITE = 5        /* a non-finite value appeared in a recompression (result discarded) */
 } hq_status;
 
-typedef struct hq_hodlr_s* hq_hodlr_t; /* opaque HODLR matrix on the device */
+typedef struct hq_hodlr_s* hq_hodlr_t;         /* opaque HODLR matrix on the device */
+typedef struct hq_predictor_s* hq_predictor_t; /* opaque rank predictor (see below) */
 
 typedef struct {
   int32_t leaf;      /* n_min: diagonal blocks have at most this many rows (Alg. 3 input), >= 2 */
@@ -50,6 +51,9 @@ typedef struct {
   double delta;      /* stopping tolerance |1 - l_k| <= delta (Alg. 3), default 1e-15 */
   int32_t max_rank;  /* largest off-diagonal rank a block may reach, default 512 */
   int32_t max_iter;  /* bound on QDWH iterations, default 10 */
+  int32_t record_ranks;      /* nonzero: fill hq_info.level_ranks (one extra readback per iteration) */
+  hq_predictor_t predictor;  /* NULL: capacities of iteration k from the ranks of X_k (2r + 16);
+                                else the predictor's ranks (no readback of ranks between iterations) */
 } hq_opts;
 
 typedef struct {
@@ -66,6 +70,11 @@ typedef struct {
   double seconds;            /* wall time of the call */
   double setup_seconds;      /* alpha, l0 and the weight schedule (host) */
   double givens_seconds;     /* Algorithms 1/2 and the Q factors (host) */
+  int32_t levels;            /* tree depth L */
+  /* opts.record_ranks: largest rank at level l (< 24) of the outputs of iteration k (< 16):
+   * [k][0] X_{k+1}, and for k >= 1 [k][1] Z_k = I + c X^T X, [k][2] L_k^{-1}, [k][3] Y_k */
+  int32_t level_ranks[16][4][24];
+  int64_t capacity_columns;  /* sum over iterations of the factor columns allocated for X_{k+1}, Z, L, Y */
 } hq_info;
 
 /* Fill *o with the defaults: leaf 256, tol 1e-10, delta 1e-15, max_rank 512, max_iter 10. */
@@ -163,6 +172,43 @@ hq_status hq_test_cholesky_inverse(hq_hodlr_t Z, int32_t cap, double tol, void* 
 /* Q1, Q2 of the structured QR of [scale*(A - shift I); I] (band: host) in HODLR format. */
 hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
                             int32_t leaf, void* stream, hq_hodlr_t* q1, hq_hodlr_t* q2, int64_t* nrot);
+
+/*
+ * Rank predictor: a perceptron (10 inputs, two tanh layers of 32, 4 linear outputs; FP32) that maps
+ * (level, block size, bandwidth, iteration, weights c_k and a_k, rank of X_k at the level, l0, n,
+ * tol) to the codes log2(1 + r)/10 of the largest ranks at that level of X_{k+1}, Z_k, L_k^{-1}
+ * and Y_k.  Used through opts.predictor, it sets every capacity before the iterations start;
+ * a rank above its capacity is caught by the kernels and the iteration is repeated with larger
+ * capacities, so results do not depend on the predictions.  Training and inference run in the
+ * library's own kernels.  Parameters: W1 (32x10), b1, W2 (32x32), b2, W3 (4x32), b3, row-major.
+ */
+#define HQ_PRED_FEATURES 10
+#define HQ_PRED_OUTPUTS 4
+/* New network with Glorot-uniform weights from `seed` (splitmix64), zero biases. */
+hq_status hq_predictor_create(uint64_t seed, hq_predictor_t* out);
+int64_t hq_predictor_nparams(void);
+/* Host copies of the parameters (nparams floats). */
+hq_status hq_predictor_get_params(hq_predictor_t p, float* params);
+hq_status hq_predictor_set_params(hq_predictor_t p, const float* params);
+/* Safety margins (4 floats in [0, 1], host), added to the predicted codes before they become
+ * capacities: capacity = 2^(10 (code + margin)) - 1 + 4.  Default 0.05 each. */
+hq_status hq_predictor_set_margin(hq_predictor_t p, const float* margin);
+hq_status hq_predictor_get_margin(hq_predictor_t p, float* margin);
+/* Y = net(X): X device rows x 10, Y device rows x 4, row-major.  Stream-ordered. */
+hq_status hq_predictor_forward(hq_predictor_t p, const float* X, int64_t rows, float* Y, void* stream);
+/* Loss sum w (y - t)^2 / sum w over rows (X, T, W device, row-major) and its gradient (device,
+ * nparams floats).  *loss: host.  Blocks until done. */
+hq_status hq_predictor_loss_grad(hq_predictor_t p, const float* X, const float* T, const float* W, int64_t rows,
+                                 float* loss, float* grad, void* stream);
+/* `epochs` full-batch Adam steps (learning rate lr); *loss: host, the loss before the last step. */
+hq_status hq_predictor_train(hq_predictor_t p, const float* X, const float* T, const float* W, int64_t rows,
+                             int32_t epochs, float lr, void* stream, float* loss);
+/* Training rows from a solve run with opts.record_ranks (host outputs, up to 16*24 rows each of
+ * X (10 floats), T and W (4 floats); W masks entries that do not exist).  The features are built
+ * by the same code the solver uses, with the recorded rank of X_k as the previous rank. */
+hq_status hq_predictor_rows(const hq_info* info, int64_t n, int32_t b, const hq_opts* opts, float* X, float* T,
+                            float* W, int32_t* rows);
+void hq_predictor_destroy(hq_predictor_t p);
 
 /* Built-in kernel timers: when enabled, every launch of the library is bracketed by HIP events on
  * its own stream and the kernels count their algorithmic work (flops, operand bytes).

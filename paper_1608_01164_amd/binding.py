@@ -28,14 +28,16 @@ class HQError(RuntimeError):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("leaf", c_i32), ("tol", c_d), ("delta", c_d), ("max_rank", c_i32), ("max_iter", c_i32)]
+    _fields_ = [("leaf", c_i32), ("tol", c_d), ("delta", c_d), ("max_rank", c_i32), ("max_iter", c_i32),
+                ("record_ranks", c_i32), ("predictor", c_vp)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("alpha", c_d), ("l0", c_d), ("a", c_d * 16), ("b", c_d * 16), ("c", c_d * 16),
                 ("max_rank_iter", c_i32 * 16), ("max_rank", c_i32), ("redo_count", c_i32), ("bytes", c_i64),
                 ("peak_bytes", c_i64), ("launches", c_i64), ("seconds", c_d), ("setup_seconds", c_d),
-                ("givens_seconds", c_d)]
+                ("givens_seconds", c_d), ("levels", c_i32), ("level_ranks", c_i32 * (16 * 4 * 24)),
+                ("capacity_columns", c_i64)]
 
     def as_dict(self) -> dict:
         K = self.iters
@@ -43,7 +45,12 @@ class Info(ctypes.Structure):
                 "c": list(self.c[:K]), "max_rank_iter": list(self.max_rank_iter[:K]), "max_rank": self.max_rank,
                 "redo_count": self.redo_count, "bytes": self.bytes, "peak_bytes": self.peak_bytes,
                 "launches": self.launches, "seconds": self.seconds, "setup_seconds": self.setup_seconds,
-                "givens_seconds": self.givens_seconds}
+                "givens_seconds": self.givens_seconds, "levels": self.levels,
+                "capacity_columns": self.capacity_columns}
+
+    def level_ranks_array(self) -> np.ndarray:
+        """[k][o][l]: o = 0 X_{k+1}, 1 Z_k, 2 L_k^{-1}, 3 Y_k (filled with opts record_ranks)."""
+        return np.ctypeslib.as_array(self.level_ranks).reshape(16, 4, 24)[: self.iters, :, : self.levels].copy()
 
 
 _lib = None
@@ -75,6 +82,18 @@ _SIGS = {
     "hq_profile_enable": (c_i32, [c_i32]),
     "hq_profile_read": (c_i32, [c_vp, c_i32]),
     "hq_profile_svd": (c_i32, [c_vp]),
+    "hq_predictor_create": (c_i32, [ctypes.c_uint64, P(c_vp)]),
+    "hq_predictor_nparams": (c_i64, []),
+    "hq_predictor_get_params": (c_i32, [c_vp, c_vp]),
+    "hq_predictor_set_params": (c_i32, [c_vp, c_vp]),
+    "hq_predictor_forward": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "hq_predictor_set_margin": (c_i32, [c_vp, c_vp]),
+    "hq_predictor_get_margin": (c_i32, [c_vp, c_vp]),
+    "hq_predictor_loss_grad": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, P(ctypes.c_float), c_vp, c_vp]),
+    "hq_predictor_train": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, ctypes.c_float, c_vp,
+                                   P(ctypes.c_float)]),
+    "hq_predictor_rows": (c_i32, [P(Info), c_i64, c_i32, P(Opts), c_vp, c_vp, c_vp, P(c_i32)]),
+    "hq_predictor_destroy": (None, [c_vp]),
 }
 
 KCLASSES = ("gemm", "tsqr", "core_svd", "leaf_cholesky", "leaf_inverse", "stack", "leaf_elementwise", "other")
@@ -130,10 +149,12 @@ def _check(status: int):
         raise HQError(status, f"{L.hq_status_string(status).decode()}: {L.hq_last_error().decode()}")
 
 
-def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10) -> Opts:
+def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10, record_ranks=False, predictor=None) -> Opts:
     o = Opts()
     _check(lib().hq_default_opts(ctypes.byref(o)))
     o.leaf, o.tol, o.delta, o.max_rank, o.max_iter = int(leaf), float(tol), float(delta), int(max_rank), int(max_iter)
+    o.record_ranks = 1 if record_ranks else 0
+    o.predictor = predictor._h if predictor is not None else None
     return o
 
 
@@ -250,13 +271,13 @@ def hodlr_build(band, b: int, shift: float, scale: float, leaf: int = 256, strea
     return HODLR(h)
 
 
-def _solve(fn, band, b, mu, stream, **kw):
+def _solve(fn, band, b, mu, stream, raw_info=False, **kw):
     p, n, ld = _band_args(band)
     h = c_vp()
     info = Info()
     _check(getattr(lib(), fn)(p, n, int(b), ld, float(mu), ctypes.byref(_opts(**kw)), _stream(stream),
                               ctypes.byref(h), ctypes.byref(info)))
-    return HODLR(h), info.as_dict()
+    return HODLR(h), (info if raw_info else info.as_dict())
 
 
 def spectral_projector(band, b: int, mu: float, stream=None, **opts):
@@ -358,3 +379,82 @@ def test_q_dense_host(band_host: np.ndarray, b, shift, scale, leaf):
     _check(lib().hq_test_q_dense_host(ab.ctypes.data_as(c_vp), n, b, ld, shift, scale, leaf,
                                       Q1.ctypes.data_as(c_vp), Q2.ctypes.data_as(c_vp), ctypes.byref(nr)))
     return Q1, Q2, nr.value
+
+
+# ---- rank predictor --------------------------------------------------------------------------
+NFEAT, NOUT = 10, 4
+
+
+class Predictor:
+    """The library's rank predictor network (device parameters); see hq.h."""
+
+    def __init__(self, seed: int = 0):
+        self._h = c_vp()
+        _check(lib().hq_predictor_create(ctypes.c_uint64(seed), ctypes.byref(self._h)))
+
+    @staticmethod
+    def nparams() -> int:
+        return int(lib().hq_predictor_nparams())
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.nparams(), dtype=np.float32)
+        _check(lib().hq_predictor_get_params(self._h, out.ctypes.data_as(c_vp)))
+        return out
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.nparams():
+            raise ValueError("wrong number of parameters")
+        _check(lib().hq_predictor_set_params(self._h, p.ctypes.data_as(c_vp)))
+
+    def margin(self) -> np.ndarray:
+        out = np.zeros(NOUT, dtype=np.float32)
+        _check(lib().hq_predictor_get_margin(self._h, out.ctypes.data_as(c_vp)))
+        return out
+
+    def set_margin(self, m) -> None:
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        _check(lib().hq_predictor_set_margin(self._h, m.ctypes.data_as(c_vp)))
+
+    def forward(self, X, Y, stream=None) -> None:
+        """Y (rows x 4) = net(X (rows x 10)); device float32 tensors."""
+        _check(lib().hq_predictor_forward(self._h, c_vp(X.data_ptr()), X.shape[0], c_vp(Y.data_ptr()),
+                                          _stream(stream)))
+
+    def loss_grad(self, X, T, W, grad, stream=None) -> float:
+        loss = ctypes.c_float()
+        _check(lib().hq_predictor_loss_grad(self._h, c_vp(X.data_ptr()), c_vp(T.data_ptr()), c_vp(W.data_ptr()),
+                                            X.shape[0], ctypes.byref(loss), c_vp(grad.data_ptr()), _stream(stream)))
+        return loss.value
+
+    def train(self, X, T, W, epochs: int, lr: float, stream=None) -> float:
+        loss = ctypes.c_float()
+        _check(lib().hq_predictor_train(self._h, c_vp(X.data_ptr()), c_vp(T.data_ptr()), c_vp(W.data_ptr()),
+                                        X.shape[0], int(epochs), ctypes.c_float(lr), _stream(stream),
+                                        ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().hq_predictor_destroy(self._h)
+        self._h = c_vp(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def predictor_rows(info: Info, n: int, b: int, **opts):
+    """(X, T, W) float32 host arrays: training rows of one solve run with record_ranks=True."""
+    cap = 16 * 24
+    X = np.zeros((cap, NFEAT), dtype=np.float32)
+    T = np.zeros((cap, NOUT), dtype=np.float32)
+    W = np.zeros((cap, NOUT), dtype=np.float32)
+    rows = c_i32()
+    _check(lib().hq_predictor_rows(ctypes.byref(info), int(n), int(b), ctypes.byref(_opts(**opts)),
+                                   X.ctypes.data_as(c_vp), T.ctypes.data_as(c_vp), W.ctypes.data_as(c_vp),
+                                   ctypes.byref(rows)))
+    r = rows.value
+    return X[:r], T[:r], W[:r]

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -13,6 +14,7 @@
 
 #include "engine.h"
 #include "givens.h"
+#include "predictor.h"
 
 struct hq_hodlr_s {
   hq::Tree t;
@@ -34,6 +36,11 @@ hq_status fail(hq_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+}  // namespace
+
+void hq::set_last_error(const std::string& m) { g_err = m; }
+
+namespace {
 
 template <class F>
 hq_status guard(F&& f) {
@@ -318,9 +325,73 @@ struct Member {
   int K = 0;
   hq_info inf;
   hq::HMat X, Xn, Z, Linv, Lf, Y, Q1, Q2, P;
-  std::vector<int> capX;
+  std::vector<int> capX, capZ, capL, capY;  // capacities of X_{k+1}, Z, L and L^{-1}, Y
+  std::vector<std::array<std::vector<int>, 4>> pcap;  // predicted capacities per iteration
   hq_hodlr_t out = nullptr;
 };
+
+std::vector<int> level_max(const hq::Tree& t, const std::vector<int>& r) {
+  std::vector<int> m(t.L, 0);
+  for (int p = 0; p < t.ninternal; ++p) {
+    const int l = hq::Tree::level(p);
+    m[l] = std::max(m[l], std::max(r[2 * p], r[2 * p + 1]));
+  }
+  return m;
+}
+
+int64_t capacity_columns(const hq::Tree& t, const std::vector<int>& cap) {
+  int64_t c = 0;
+  for (int l = 0; l < t.L; ++l) c += (int64_t)(2 << l) * cap[l];
+  return c;
+}
+
+// Capacities of every iteration from the predictor: rows (k, member, level) on a full grid, one
+// forward launch per iteration (the previous-rank feature of iteration k is read on the device from
+// iteration k-1's output), and a single readback.
+void predict_capacities(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, hq::Engine& E) {
+  const int nm = (int)ms.size();
+  int Kmax = 0, Lmax = 0;
+  for (Member& m : ms)
+    if (m.status == HQ_OK) {
+      Kmax = std::max(Kmax, m.K);
+      Lmax = std::max(Lmax, m.t.L);
+    }
+  for (Member& m : ms)
+    if (m.status == HQ_OK) m.pcap.assign(m.K, {});  // members without levels keep empty capacities
+  if (Kmax == 0 || Lmax == 0) return;
+  const int64_t R = (int64_t)nm * Lmax;
+  constexpr int F = hq::kMlpFeatures, O = hq::kMlpOutputs;
+  std::vector<float> X((size_t)Kmax * R * F, 0.0f);
+  for (int k = 0; k < Kmax; ++k)
+    for (int i = 0; i < nm; ++i) {
+      const Member& m = ms[i];
+      if (m.status != HQ_OK || k >= m.K) continue;
+      for (int l = 0; l < m.t.L; ++l)
+        hq::predictor_features(&X[((size_t)k * R + (size_t)i * Lmax + l) * F], m.n, m.beff, l, m.t.ldf[l], k,
+                               m.w.a[k], m.w.c[k], m.beff, m.inf.l0, o.tol);
+    }
+  float* dX = E.scratch.get<float>(X.size());
+  float* dY = E.scratch.get<float>((size_t)Kmax * R * O);
+  HQ_CHECK(hipMemcpyAsync(dX, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice, st));
+  for (int k = 0; k < Kmax; ++k)
+    hq::launch_mlp_forward(o.predictor->d_params, dX + (size_t)k * R * F, k == 0 ? nullptr : dY + (size_t)(k - 1) * R * O,
+                           dY + (size_t)k * R * O, R, st);
+  std::vector<float> Y((size_t)Kmax * R * O);
+  HQ_CHECK(hipMemcpyAsync(Y.data(), dY, sizeof(float) * Y.size(), hipMemcpyDeviceToHost, st));
+  HQ_CHECK(hipStreamSynchronize(st));
+  for (int i = 0; i < nm; ++i) {
+    Member& m = ms[i];
+    if (m.status != HQ_OK) continue;
+    for (int k = 1; k < m.K; ++k)
+      for (int q = 0; q < O; ++q) {
+        std::vector<int>& c = m.pcap[k][q];
+        c.resize(m.t.L);
+        for (int l = 0; l < m.t.L; ++l)
+          c[l] = hq::predictor_capacity(Y[((size_t)k * R + (size_t)i * Lmax + l) * O + q], o.predictor->margin[q],
+                                        std::min<int64_t>(o.max_rank, m.t.ldf[l]));
+      }
+  }
+}
 
 void set_fail(Member& m, hq_status s, const char* msg) {
   m.status = s;
@@ -390,7 +461,10 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
   }
   int Kmax = 0;
   for (Member& m : ms)
-    if (m.status == HQ_OK) Kmax = std::max(Kmax, m.K);
+    if (m.status == HQ_OK) {
+      Kmax = std::max(Kmax, m.K);
+      m.inf.levels = m.t.L;
+    }
 
   hq::Engine E(st);
   E.tol = o.tol;
@@ -404,6 +478,10 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
     peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + xa[0].high_water() +
                               xa[1].high_water() + it.high_water() + qa.high_water() + pa.high_water());
   };
+  if (o.predictor) {
+    predict_capacities(ms, o, st, E);
+    E.scratch.reset();
+  }
   int cur = 0;
   for (Member& m : ms) {
     if (m.status != HQ_OK) continue;
@@ -442,11 +520,22 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
       HQ_CHECK(hipStreamSynchronize(st));  // the host copies go out of scope
       if (act.size() > 1)
         for (int i : act) ms[i].inf.givens_seconds = secs(tg);
+    } else if (o.predictor) {
+      for (int i : act) {
+        Member& m = ms[i];
+        m.capX = m.pcap[k][0];
+        m.capZ = m.pcap[k][1];
+        m.capL = m.pcap[k][2];
+        m.capY = m.pcap[k][3];
+      }
     } else {
       std::vector<const hq::HMat*> xs;
       for (int i : act) xs.push_back(&ms[i].X);
       const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
-      for (size_t j = 0; j < act.size(); ++j) ms[act[j]].capX = caps_grow(ms[act[j]].t, rk[j], o.max_rank, 2, 16);
+      for (size_t j = 0; j < act.size(); ++j) {
+        Member& m = ms[act[j]];
+        m.capX = m.capZ = m.capL = m.capY = caps_grow(m.t, rk[j], o.max_rank, 2, 16);
+      }
     }
     std::vector<int> pend = act;
     xa[cur ^ 1].reset();
@@ -454,7 +543,10 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
       E.stage.reset();
       E.scratch.reset();
       it.reset();
-      for (int i : pend) ms[i].Xn = E.alloc_hmat_in(xa[cur ^ 1], &ms[i].t, ms[i].capX, false);
+      for (int i : pend) {
+        ms[i].Xn = E.alloc_hmat_in(xa[cur ^ 1], &ms[i].t, ms[i].capX, false);
+        ms[i].inf.capacity_columns += capacity_columns(ms[i].t, ms[i].capX);
+      }
       E.clear_flags(nm);
       if (k == 0) {
         // Alg. 3 line 9: X1 = b0/c0 X0 + (a0 - b0/c0)/sqrt(c0) Q1 Q2^T
@@ -479,10 +571,12 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         std::vector<hq::Engine::CholTask> pc;
         for (int i : pend) {
           Member& m = ms[i];
-          m.Z = E.alloc_hmat_in(it, &m.t, m.capX, true);
-          m.Linv = E.alloc_hmat_in(it, &m.t, m.capX, false);
-          m.Lf = E.alloc_hmat_in(it, &m.t, m.capX, false);
-          m.Y = E.alloc_hmat_in(it, &m.t, m.capX, false);
+          m.Z = E.alloc_hmat_in(it, &m.t, m.capZ, true);
+          m.Linv = E.alloc_hmat_in(it, &m.t, m.capL, false);
+          m.Lf = E.alloc_hmat_in(it, &m.t, m.capL, false);
+          m.Y = E.alloc_hmat_in(it, &m.t, m.capY, false);
+          m.inf.capacity_columns += capacity_columns(m.t, m.capZ) / 2 + 2 * capacity_columns(m.t, m.capL) +
+                                    capacity_columns(m.t, m.capY);
           const double a = m.w.a[k], bb = m.w.b[k], c = m.w.c[k];
           hq::Engine::ProdTask q;
           q.A = E.view(m.X, true);
@@ -493,7 +587,7 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
           q.C = &m.Z;
           q.fidx = i;
           pz.push_back(q);
-          pc.push_back(hq::Engine::CholTask{&m.Z, &m.Linv, &m.Lf, 2 * max_of(m.capX) + 16, i});
+          pc.push_back(hq::Engine::CholTask{&m.Z, &m.Linv, &m.Lf, 2 * max_of(m.capL) + 16, i});
           q = hq::Engine::ProdTask{};
           q.A = E.view(m.X);
           q.B = E.view(m.Linv, true);  // Y = X L^{-T} = X W^{-1}
@@ -539,11 +633,12 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         }
         if (f[i] & 1) {
           bool grown = false;
-          for (int l = 0; l < m.t.L; ++l) {
-            const int nc = (int)std::min<int64_t>({(int64_t)m.capX[l] * 2, (int64_t)o.max_rank, m.t.ldf[l]});
-            grown |= nc > m.capX[l];
-            m.capX[l] = nc;
-          }
+          for (std::vector<int>* cv : {&m.capX, &m.capZ, &m.capL, &m.capY})
+            for (int l = 0; l < m.t.L && l < (int)cv->size(); ++l) {
+              const int nc = (int)std::min<int64_t>({(int64_t)(*cv)[l] * 2, (int64_t)o.max_rank, m.t.ldf[l]});
+              grown |= nc > (*cv)[l];
+              (*cv)[l] = nc;
+            }
           if (!grown || attempt > 6) {
             set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
             continue;
@@ -566,7 +661,22 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         xs.push_back(&ms[i].X);
         ok.push_back(i);
       }
+    if (o.record_ranks && k >= 1)
+      for (int i : ok) {
+        xs.push_back(&ms[i].Z);
+        xs.push_back(&ms[i].Linv);
+        xs.push_back(&ms[i].Y);
+      }
     const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+    if (o.record_ranks && k < 16)
+      for (size_t j = 0; j < ok.size(); ++j) {
+        Member& m = ms[ok[j]];
+        for (int q = 0; q < 4; ++q) {
+          if (q > 0 && k == 0) break;
+          const std::vector<int> lm = level_max(m.t, rk[q == 0 ? j : ok.size() + 3 * j + (q - 1)]);
+          for (int l = 0; l < m.t.L && l < 24; ++l) m.inf.level_ranks[k][q][l] = lm[l];
+        }
+      }
     std::vector<hq::Engine::AffTask> fin;
     pa.reset();
     E.stage.reset();
@@ -662,6 +772,8 @@ hq_status hq_default_opts(hq_opts* o) {
   o->delta = 1e-15;
   o->max_rank = 512;
   o->max_iter = 10;
+  o->record_ranks = 0;
+  o->predictor = nullptr;
   return HQ_OK;
 }
 
@@ -744,6 +856,12 @@ hq_status spectral_projector_batched(int32_t count, const double* const* bands, 
   for (int i = 0; i < count; ++i)
     if ((s = check_band(bands[i], n[i], b[i], ldab[i]))) return fail(s, "member " + std::to_string(i) + ": " + g_err);
   return guard([&]() -> hq_status {
+    // Members run in consecutive chunks whose estimated working set fits 60% of the free device
+    // memory: about 8.5 KB per n (b + 1) L, L the tree depth (measured on banded workloads with
+    // capacities of twice the previous ranks).
+    size_t free_b = 0, total_b = 0;
+    HQ_CHECK(hipMemGetInfo(&free_b, &total_b));
+    const double budget = 0.6 * (double)free_b;
     std::vector<Member> ms(count);
     for (int i = 0; i < count; ++i) {
       ms[i].band = bands[i];
@@ -752,7 +870,36 @@ hq_status spectral_projector_batched(int32_t count, const double* const* bands, 
       ms[i].ldab = ldab[i];
       ms[i].mu = mu[i];
     }
-    run_batch(ms, o, (hipStream_t)stream, true);
+    int i0 = 0;
+    while (i0 < count) {
+      int i1 = i0;
+      double sum = 0.0;
+      while (i1 < count) {
+        hq::Tree t;
+        t.build(n[i1], o.leaf);
+        const double est = 8.5e3 * (double)n[i1] * (b[i1] + 1) * std::max(1, t.L) + 64e6;
+        if (i1 > i0 && sum + est > budget) break;
+        sum += est;
+        ++i1;
+      }
+      std::vector<Member> chunk(i1 - i0);
+      for (int i = i0; i < i1; ++i) {
+        chunk[i - i0].band = ms[i].band;
+        chunk[i - i0].n = ms[i].n;
+        chunk[i - i0].b = ms[i].b;
+        chunk[i - i0].ldab = ms[i].ldab;
+        chunk[i - i0].mu = ms[i].mu;
+      }
+      run_batch(chunk, o, (hipStream_t)stream, true);
+      for (int i = i0; i < i1; ++i) {
+        Member& c = chunk[i - i0];
+        ms[i].status = c.status;
+        ms[i].err = c.err;
+        ms[i].inf = c.inf;
+        ms[i].out = c.out;
+      }
+      i0 = i1;
+    }
     hq_status first = HQ_OK;
     for (int i = 0; i < count; ++i) {
       Member& m = ms[i];
@@ -934,18 +1081,12 @@ hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, do
     hq::Engine e((hipStream_t)stream);
     int* dr = e.scratch.get<int>(1);
     hq::launch_fill_int(dr, r, 1, e.st);
-    // reuse compress_sym's QR stage through a recompress with V = nothing: run QR directly
-    double* out = e.scratch.get<double>((size_t)rows * r);
-    int* kk = e.scratch.get<int>(1);
-    (void)out;
-    (void)kk;
-    // R-only TSQR via the same plan as recompress
+    // R-only TSQR with the plan the recompressions use
     const int rc = r;
-    const int hmin = std::max(256, 2 * rc);
+    const hq::QrPlan pl = hq::plan_qr(rows, rc);
     hq::QrTask q{};
     q.M = M; q.ldm = ldm; q.rows = rows; q.rp = dr; q.rcap = rc; q.R = R; q.ldr = rc;
-    if (rows <= hmin) { q.h0 = q.hs = rows; q.ntiles = 1; }
-    else { q.h0 = q.hs = (hmin + 63) / 64 * 64; q.ntiles = (rows + q.h0 - 1) / q.h0; }
+    q.h0 = pl.h0; q.hs = pl.hs; q.ntiles = pl.ntiles;
     q.work = e.scratch.get<double>((size_t)q.ntiles * q.hs * rc);
     hq::QrTask* dq = e.stage.upload(std::vector<hq::QrTask>{q}, e.st);
     int nst = 0;

@@ -122,6 +122,10 @@ struct HView {
   HView T() const { HView v = *this; v.trans = !trans; return v; }
 };
 
+// Row tiling of the R-only TSQR of an m-row stack with rcap columns of capacity.
+struct QrPlan { int h0, hs, ntiles; };
+QrPlan plan_qr(int m, int rcap);
+
 struct Thin {            // dense n_sub x w block (column-major) with a device width
   double* p; int ld; const int* w; int wcap;
 };
@@ -167,12 +171,15 @@ class Engine {
     int fidx;
   };
   void recompress(const std::vector<RecTask>& tasks);
+  size_t rec_budget = size_t(3) << 30;  // device workspace of one group of recompressions
   // Symmetric factor compression: S (m x r) -> S J_k with S S^T ~ S' S'^T, drop sigma(S) <= thresh.
   struct SymTask {
     const double* S; int lds; int m; const int* r; int rcap; double* out; int ldo; int* rank; int kcap; double thresh;
     int fidx;
   };
   void compress_sym(const std::vector<SymTask>& tasks);
+  void recompress_group(const std::vector<RecTask>& tasks);
+  void compress_sym_group(const std::vector<SymTask>& tasks);
 
   // C = alpha op(A) op(B) + delta op(D)  (D absent, a HODLR, or the identity), for a batch of
   // independent matrices: every launch covers all members.

@@ -122,6 +122,8 @@ HView::Blk HView::lower(int p) const {
 
 // ---------------------------------------------------------------------------------------------
 Engine::Engine(hipStream_t s) : st(s) {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) rec_budget = std::max(rec_budget, free_b / 4);
   HQ_CHECK(hipMalloc(&d_flag, sizeof(int) * (kFlagSlots + 64)));
   d_zero = d_flag + kFlagSlots;
   HQ_CHECK(hipMemsetAsync(d_flag, 0, sizeof(int) * (kFlagSlots + 64), st));
@@ -278,23 +280,68 @@ void Engine::mm_thin(const std::vector<ThinTask>& tasks) {
 
 // ---------------------------------------------------------------------------------------------
 // R-only TSQR of each stack, SVD of the small core, and two thin GEMMs per factor.
-namespace {
-struct QrPlan { int h0, hs, ntiles; };
 QrPlan plan_qr(int m, int rcap) {
+  // Row tiles depend on m alone (never on capacities), so a result does not change when a
+  // capacity does; slots hold a tile or two stacked triangles, whichever is taller.
+  constexpr int kTile = 1024;
   QrPlan p;
-  const int hmin = std::max(256, 2 * rcap);
-  if (m <= hmin) {
-    p.h0 = p.hs = std::max(m, 1);
-    p.ntiles = 1;
-  } else {
-    p.h0 = p.hs = (hmin + 63) / 64 * 64;
-    p.ntiles = (m + p.h0 - 1) / p.h0;
-  }
+  p.h0 = m <= kTile ? std::max(m, 1) : kTile;
+  p.ntiles = (m + p.h0 - 1) / p.h0;
+  p.hs = p.ntiles == 1 ? p.h0 : std::max(p.h0, 2 * rcap);
   return p;
+}
+
+namespace {
+// Device workspace of one recompression task (TSQR slots of both sides, cores, outputs).
+size_t rec_bytes(int m, int n, int rcap, int kcap) {
+  const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1);
+  const QrPlan a = plan_qr(m, (int)rc), b = plan_qr(n, (int)rc);
+  return 8 * (5 * rc * rc + 2 * rc + 4 * rc * kc + ((size_t)a.ntiles * a.hs + (size_t)b.ntiles * b.hs) * rc) + 4096;
+}
+size_t sym_bytes(int m, int rcap, int kcap) {
+  const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1);
+  const QrPlan a = plan_qr(m, (int)rc);
+  return 8 * (3 * rc * rc + 2 * rc + 2 * rc * kc + (size_t)a.ntiles * a.hs * rc) + 4096;
 }
 }  // namespace
 
+// Tasks run in groups whose workspace stays under rec_budget; each group's scratch is released
+// (stream order keeps the reuse safe) before the next is issued.
 void Engine::recompress(const std::vector<RecTask>& tasks) {
+  size_t i = 0;
+  while (i < tasks.size()) {
+    size_t j = i, sum = 0;
+    while (j < tasks.size()) {
+      const RecTask& T = tasks[j];
+      const size_t b = rec_bytes(T.m, T.n, T.rcap, T.kcap);
+      if (j > i && sum + b > rec_budget) break;
+      sum += b;
+      ++j;
+    }
+    const DevArena::Mark mk = scratch.mark();
+    recompress_group(std::vector<RecTask>(tasks.begin() + i, tasks.begin() + j));
+    scratch.rewind(mk);
+    i = j;
+  }
+}
+void Engine::compress_sym(const std::vector<SymTask>& tasks) {
+  size_t i = 0;
+  while (i < tasks.size()) {
+    size_t j = i, sum = 0;
+    while (j < tasks.size()) {
+      const size_t b = sym_bytes(tasks[j].m, tasks[j].rcap, tasks[j].kcap);
+      if (j > i && sum + b > rec_budget) break;
+      sum += b;
+      ++j;
+    }
+    const DevArena::Mark mk = scratch.mark();
+    compress_sym_group(std::vector<SymTask>(tasks.begin() + i, tasks.begin() + j));
+    scratch.rewind(mk);
+    i = j;
+  }
+}
+
+void Engine::recompress_group(const std::vector<RecTask>& tasks) {
   if (tasks.empty()) return;
   const int nt = (int)tasks.size();
   std::vector<QrTask> qv;
@@ -382,7 +429,7 @@ void Engine::recompress(const std::vector<RecTask>& tasks) {
   gemm(gUV, mmax, kmax);
 }
 
-void Engine::compress_sym(const std::vector<SymTask>& tasks) {
+void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
   if (tasks.empty()) return;
   const int nt = (int)tasks.size();
   std::vector<QrTask> qv;
@@ -495,8 +542,31 @@ void Engine::product(const std::vector<ProdTask>& batch) {
   }
   mm_thin(thin);
 
-  // 2) level sweep: C blocks of level l and the accumulated terms of level l+1
+  // 2) level sweep: C blocks of level l and the accumulated terms of level l+1.  The children's
+  // terms are allocated first; everything else of the level is released after its launches.
   for (int l = 0; l < Lmax; ++l) {
+    for (int m = 0; m < nm; ++m) {
+      const ProdTask& P = batch[m];
+      const Tree* t = P.C->t;
+      if (l >= t->L) continue;
+      const int f0 = (1 << l) - 1, cnt = 1 << l;
+      const int ldc = (int)t->ldf[l];
+      for (int p = f0; p < f0 + cnt; ++p) {
+        const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
+        const HView::Blk Au = P.A.upper(p), Bu = P.B.upper(p);
+        const int capT = std::min<int>({(int)std::max(sa, sb), std::max(P.C->cap[l], std::max(Au.cap, Bu.cap)) * 2, kMaxStack});
+        for (int c = 2 * p + 1; c <= 2 * p + 2; ++c) {
+          TermF nt;
+          nt.ld = ldc;
+          nt.cap = capT;
+          nt.E = scratch.get<double>((size_t)nt.ld * capT);
+          nt.F = scratch.get<double>((size_t)nt.ld * capT);
+          nt.r = scratch.get<int>(1);
+          termm[m][c] = nt;
+        }
+      }
+    }
+    const DevArena::Mark level_mark = scratch.mark();
     std::vector<GemmTask> gm, gg;
     std::vector<StackTask> stk;
     std::vector<RecTask> rec;
@@ -520,7 +590,6 @@ void Engine::product(const std::vector<ProdTask>& batch) {
         const TermF Tp = term[p];
         mcapA = std::max(mcapA, std::max(Au.cap, Al.cap));
         mcapB = std::max(mcapB, std::max(Bu.cap, Bl.cap));
-        const int capT = std::min<int>({(int)std::max(sa, sb), std::max(C.cap[l], std::max(Au.cap, Bu.cap)) * 2, kMaxStack});
         // --- C blocks
         for (int s = 0; s < 2; ++s) {
           if (s == 0 && !full) continue;
@@ -585,17 +654,11 @@ void Engine::product(const std::vector<ProdTask>& batch) {
           sv.src[1] = {By.V, By.r, By.ld, By.cap, 1.0};
           stk.push_back(su);
           stk.push_back(sv);
-          TermF nt;
-          nt.ld = ldc;
-          nt.cap = capT;
-          nt.E = scratch.get<double>((size_t)nt.ld * capT);
-          nt.F = scratch.get<double>((size_t)nt.ld * capT);
-          int* rr = scratch.get<int>(1);
-          nt.r = rr;
-          term[c] = nt;
+          const TermF& nt = term[c];
           RecTask r{};
           r.Us = Us; r.ldus = ldc; r.m = (int)mrow; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mrow; r.r = rs; r.rcap = rcap;
-          r.U = nt.E; r.V = nt.F; r.ldu = r.ldv = nt.ld; r.rank = rr; r.kcap = capT; r.thresh = tolT; r.fidx = P.fidx;
+          r.U = nt.E; r.V = nt.F; r.ldu = r.ldv = nt.ld; r.rank = const_cast<int*>(nt.r); r.kcap = nt.cap; r.thresh = tolT;
+          r.fidx = P.fidx;
           rec.push_back(r);
         }
       }
@@ -604,6 +667,7 @@ void Engine::product(const std::vector<ProdTask>& batch) {
     gemm(gg, maxrows, mcapB);
     stack(stk, maxrows);
     recompress(rec);
+    scratch.rewind(level_mark);
   }
   // 3) leaves
   std::vector<GemmTask> g1, g2;
