@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="disable the library's per-launch kernel timers")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: middle QDWH iterations in FP32 (GEMM on FP32 MFMA, FP32 TSQR and core SVD)")
     ap.add_argument("--no-predictor", action="store_true",
                     help="capacities from the previous iterate's ranks instead of the trained rank predictor")
     args = ap.parse_args()
@@ -148,7 +150,7 @@ def main():
           file=sys.stderr, flush=True)
     info = None
     for i in range(args.warmup):
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision)
         P.close()
         print(f"# warmup {i}: {info['seconds']:.3f} s, K={info['iters']}, max rank {info['max_rank']}",
               file=sys.stderr, flush=True)
@@ -161,7 +163,7 @@ def main():
     for i in range(args.steps):
         if P is not None:
             P.close()
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision)
         infos.append(info)
         print(f"# step {i}: {info['seconds']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -176,9 +178,9 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "Π/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "b": b, "leaf": leaf, "tol": tol, "nu": nu, "mu": mu,
-                   "gap": gap, "precision": "fp64", "parallelism": "single-gpu",
+                   "gap": gap, "precision": args.precision, "parallelism": "single-gpu",
                    "capacities": "predictor" if pred is not None else "previous ranks"},
         "iters": info["iters"], "max_rank": info["max_rank"], "launches": info["launches"],
         "setup_s": info["setup_seconds"], "givens_s": info["givens_seconds"], "peak_bytes": info["peak_bytes"],
@@ -220,7 +222,8 @@ def main_batched(args, count, leaf=128, tol=1e-10):
           f"tol={tol}, min gap={min(x[1] for x in mg):.3e}", file=sys.stderr, flush=True)
 
     def step():
-        Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol, predictor=pred)
+        Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol, predictor=pred,
+                                                      precision=args.precision)
         if st != 0:
             bad = [(i, mats[i].shape[0], bs[i], mg[i][1]) for i, P in enumerate(Ps) if P is None]
             print(f"# failed members (index, n, b, gap): {bad}; {hq.lib().hq_last_error().decode()}",
@@ -262,9 +265,9 @@ def main_batched(args, count, leaf=128, tol=1e-10):
     out = {
         "metric": METRIC, "value": count * args.steps / (t1 - t0), "unit": "Π/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
         "config": {"workload": args.workload, "count": count, "sum_n": nsum, "leaf": leaf, "tol": tol,
-                   "precision": "fp64", "parallelism": "single-gpu, batched",
+                   "precision": args.precision, "parallelism": "single-gpu, batched",
                    "capacities": "predictor" if pred is not None else "previous ranks"},
         "iters_max": max(i["iters"] for i in infos), "max_rank": max(i["max_rank"] for i in infos),
         "redo_count": sum(i["redo_count"] for i in infos), "launches": infos[0]["launches"],

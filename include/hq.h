@@ -54,7 +54,16 @@ typedef struct {
   int32_t record_ranks;      /* nonzero: fill hq_info.level_ranks (one extra readback per iteration) */
   hq_predictor_t predictor;  /* NULL: capacities of iteration k from the ranks of X_k (2r + 16);
                                 else the predictor's ranks (no readback of ranks between iterations) */
+  int32_t precision;         /* HQ_FP64 (default) or HQ_MIXED */
+  double c_fp32_max;         /* HQ_MIXED: a Cholesky iteration k >= 1 that is not the last and has
+                                c_k <= c_fp32_max runs its GEMMs, TSQRs and core SVDs in FP32 (FP32
+                                MFMA, truncation at max(tol, 8 u32 sigma_1)); default 16.  Leaf
+                                Cholesky factorisations, the first and last iterations and the
+                                symmetrisation stay FP64 (so Z = I + c X^T X, with condition number
+                                up to 1 + c, is only formed in FP32 when c is moderate). */
 } hq_opts;
+#define HQ_FP64 0
+#define HQ_MIXED 1
 
 typedef struct {
   int32_t iters;             /* QDWH iterations K */
@@ -75,6 +84,7 @@ typedef struct {
    * [k][0] X_{k+1}, and for k >= 1 [k][1] Z_k = I + c X^T X, [k][2] L_k^{-1}, [k][3] Y_k */
   int32_t level_ranks[16][4][24];
   int64_t capacity_columns;  /* sum over iterations of the factor columns allocated for X_{k+1}, Z, L, Y */
+  int32_t fp32_iter[16];     /* 1 where iteration k ran in FP32 (HQ_MIXED) */
 } hq_info;
 
 /* Fill *o with the defaults: leaf 256, tol 1e-10, delta 1e-15, max_rank 512, max_iter 10. */
@@ -150,15 +160,17 @@ const char* hq_last_error(void);
 
 /* ---- Test hooks: single building blocks of the path, exposed so that tests can compare each one
  *      with an independent reference.  All pointers device unless stated. ---- */
-/* C = alpha op(A) op(B) + beta C through the batched FP64 MFMA kernel. */
+/* fp32 != 0 selects the FP32 variant of a kernel (operands rounded to FP32, FP32 arithmetic; inputs
+ * and outputs stay FP64 in memory), as used by the middle iterations of the mixed precision mode. */
+/* C = alpha op(A) op(B) + beta C through the batched MFMA GEMM kernel. */
 hq_status hq_test_gemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k,
                        int32_t lda, int32_t ldb, int32_t ldc, int32_t opA, int32_t opB, double alpha, double beta,
-                       void* stream);
+                       int32_t fp32, void* stream);
 /* R factor (r x r, upper, ldr = r) of the Householder TSQR of M (rows x r). */
-hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, double* R, void* stream);
+hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, double* R, int32_t fp32, void* stream);
 /* Truncated recompression of Us (m x r) Vs^T (n x r): U (m x k), V (n x k), *k host. */
 hq_status hq_test_recompress(const double* Us, int32_t m, const double* Vs, int32_t n, int32_t r, double tol,
-                             int32_t kcap, double* U, double* V, int32_t* k, void* stream);
+                             int32_t kcap, double* U, double* V, int32_t* k, int32_t fp32, void* stream);
 /* HODLR approximation of a dense symmetric-or-not matrix (device, n x n, ld) by truncated SVD of
  * every off-diagonal block. */
 hq_status hq_test_from_dense(const double* dense, int64_t n, int64_t ld, const hq_opts* opts, int32_t cap,

@@ -29,7 +29,7 @@ class HQError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("leaf", c_i32), ("tol", c_d), ("delta", c_d), ("max_rank", c_i32), ("max_iter", c_i32),
-                ("record_ranks", c_i32), ("predictor", c_vp)]
+                ("record_ranks", c_i32), ("predictor", c_vp), ("precision", c_i32), ("c_fp32_max", c_d)]
 
 
 class Info(ctypes.Structure):
@@ -37,7 +37,7 @@ class Info(ctypes.Structure):
                 ("max_rank_iter", c_i32 * 16), ("max_rank", c_i32), ("redo_count", c_i32), ("bytes", c_i64),
                 ("peak_bytes", c_i64), ("launches", c_i64), ("seconds", c_d), ("setup_seconds", c_d),
                 ("givens_seconds", c_d), ("levels", c_i32), ("level_ranks", c_i32 * (16 * 4 * 24)),
-                ("capacity_columns", c_i64)]
+                ("capacity_columns", c_i64), ("fp32_iter", c_i32 * 16)]
 
     def as_dict(self) -> dict:
         K = self.iters
@@ -46,7 +46,7 @@ class Info(ctypes.Structure):
                 "redo_count": self.redo_count, "bytes": self.bytes, "peak_bytes": self.peak_bytes,
                 "launches": self.launches, "seconds": self.seconds, "setup_seconds": self.setup_seconds,
                 "givens_seconds": self.givens_seconds, "levels": self.levels,
-                "capacity_columns": self.capacity_columns}
+                "capacity_columns": self.capacity_columns, "fp32_iter": list(self.fp32_iter[:K])}
 
     def level_ranks_array(self) -> np.ndarray:
         """[k][o][l]: o = 0 X_{k+1}, 1 Z_k, 2 L_k^{-1}, 3 Y_k (filled with opts record_ranks)."""
@@ -71,9 +71,10 @@ _SIGS = {
     "hodlr_destroy": (None, [c_vp]),
     "hq_status_string": (ctypes.c_char_p, [c_i32]),
     "hq_last_error": (ctypes.c_char_p, []),
-    "hq_test_gemm": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_d, c_d, c_vp]),
-    "hq_test_qr_r": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
-    "hq_test_recompress": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_i32, c_d, c_i32, c_vp, c_vp, P(c_i32), c_vp]),
+    "hq_test_gemm": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_d, c_d, c_i32,
+                             c_vp]),
+    "hq_test_qr_r": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp]),
+    "hq_test_recompress": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_i32, c_d, c_i32, c_vp, c_vp, P(c_i32), c_i32, c_vp]),
     "hq_test_from_dense": (c_i32, [c_vp, c_i64, c_i64, P(Opts), c_i32, c_vp, P(c_vp)]),
     "hq_test_product": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_d, c_vp, c_i32, c_d, c_i32, c_i32, c_d, c_vp, P(c_vp)]),
     "hq_test_cholesky_inverse": (c_i32, [c_vp, c_i32, c_d, c_vp, P(c_vp)]),
@@ -149,12 +150,17 @@ def _check(status: int):
         raise HQError(status, f"{L.hq_status_string(status).decode()}: {L.hq_last_error().decode()}")
 
 
-def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10, record_ranks=False, predictor=None) -> Opts:
+def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10, record_ranks=False, predictor=None,
+          precision="fp64", c_fp32_max=16.0) -> Opts:
     o = Opts()
     _check(lib().hq_default_opts(ctypes.byref(o)))
     o.leaf, o.tol, o.delta, o.max_rank, o.max_iter = int(leaf), float(tol), float(delta), int(max_rank), int(max_iter)
     o.record_ranks = 1 if record_ranks else 0
     o.predictor = predictor._h if predictor is not None else None
+    if precision not in ("fp64", "mixed"):
+        raise ValueError("precision must be 'fp64' or 'mixed'")
+    o.precision = 1 if precision == "mixed" else 0
+    o.c_fp32_max = float(c_fp32_max)
     return o
 
 
@@ -324,19 +330,21 @@ def shift_for_count(band_host: np.ndarray, b: int, nu: int):
 
 
 # ---- test hooks ---------------------------------------------------------------------------------
-def test_gemm(A, B, C, m, n, k, lda, ldb, ldc, opA, opB, alpha, beta, stream=None):
+def test_gemm(A, B, C, m, n, k, lda, ldb, ldc, opA, opB, alpha, beta, stream=None, fp32=False):
     _check(lib().hq_test_gemm(c_vp(A.data_ptr()), c_vp(B.data_ptr()), c_vp(C.data_ptr()), m, n, k, lda, ldb, ldc,
-                              opA, opB, alpha, beta, _stream(stream)))
+                              opA, opB, alpha, beta, 1 if fp32 else 0, _stream(stream)))
 
 
-def test_qr_r(M, rows, r, ldm, R, stream=None):
-    _check(lib().hq_test_qr_r(c_vp(M.data_ptr()), rows, r, ldm, c_vp(R.data_ptr()), _stream(stream)))
+def test_qr_r(M, rows, r, ldm, R, stream=None, fp32=False):
+    _check(lib().hq_test_qr_r(c_vp(M.data_ptr()), rows, r, ldm, c_vp(R.data_ptr()), 1 if fp32 else 0,
+                              _stream(stream)))
 
 
-def test_recompress(Us, m, Vs, n, r, tol, kcap, U, V, stream=None) -> int:
+def test_recompress(Us, m, Vs, n, r, tol, kcap, U, V, stream=None, fp32=False) -> int:
     k = c_i32()
     _check(lib().hq_test_recompress(c_vp(Us.data_ptr()), m, c_vp(Vs.data_ptr()), n, r, tol, kcap,
-                                    c_vp(U.data_ptr()), c_vp(V.data_ptr()), ctypes.byref(k), _stream(stream)))
+                                    c_vp(U.data_ptr()), c_vp(V.data_ptr()), ctypes.byref(k), 1 if fp32 else 0,
+                                    _stream(stream)))
     return k.value
 
 

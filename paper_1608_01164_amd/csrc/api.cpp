@@ -298,6 +298,7 @@ hq_status check_opts(const hq_opts* o, hq_opts& out) {
   if (!(out.delta > 0.0)) return fail(HQ_ERR_ARG, "opts.delta must be > 0");
   if (out.max_rank < 1) return fail(HQ_ERR_ARG, "opts.max_rank must be >= 1");
   if (out.max_iter < 1 || out.max_iter > 16) return fail(HQ_ERR_ARG, "opts.max_iter must be in [1, 16]");
+  if (out.precision != HQ_FP64 && out.precision != HQ_MIXED) return fail(HQ_ERR_ARG, "opts.precision must be FP64 or MIXED");
   return HQ_OK;
 }
 
@@ -566,10 +567,22 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         }
         E.product(pv);
       } else {
-        // Alg. 3 lines 11-14: W = chol(I + c X^T X); Y W = X; V W^T = Y; X+ = b/c X + (a - b/c) V
+        // Alg. 3 lines 11-14: W = chol(I + c X^T X); Y W = X; V W^T = Y; X+ = b/c X + (a - b/c) V.
+        // Members whose iteration runs in FP32 (mixed mode) go in their own launches.
+        std::vector<int> grp[2];
+        for (int i : pend) {
+          const Member& m = ms[i];
+          const bool f32 = o.precision == HQ_MIXED && k + 1 < m.K && m.w.c[k] <= o.c_fp32_max;
+          grp[f32 ? 1 : 0].push_back(i);
+        }
+        for (int g = 0; g < 2; ++g) {
+        if (grp[g].empty()) continue;
+        E.fp32 = g == 1;
+        if (g == 1 && k < 16)
+          for (int i : grp[g]) ms[i].inf.fp32_iter[k] = 1;
         std::vector<hq::Engine::ProdTask> pz, py, px;
         std::vector<hq::Engine::CholTask> pc;
-        for (int i : pend) {
+        for (int i : grp[g]) {
           Member& m = ms[i];
           m.Z = E.alloc_hmat_in(it, &m.t, m.capZ, true);
           m.Linv = E.alloc_hmat_in(it, &m.t, m.capL, false);
@@ -611,6 +624,9 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         E.product(py);
         E.scratch.reset();
         E.product(px);
+        E.scratch.reset();
+        }
+        E.fp32 = false;
       }
       note_peak();
       const std::vector<int> f = E.read_flags(nm);
@@ -774,6 +790,8 @@ hq_status hq_default_opts(hq_opts* o) {
   o->max_iter = 10;
   o->record_ranks = 0;
   o->predictor = nullptr;
+  o->precision = HQ_FP64;
+  o->c_fp32_max = 16.0;
   return HQ_OK;
 }
 
@@ -1058,7 +1076,8 @@ void hodlr_destroy(hq_hodlr_t H) {
 
 // ---- test hooks -------------------------------------------------------------------------------
 hq_status hq_test_gemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k, int32_t lda,
-                       int32_t ldb, int32_t ldc, int32_t opA, int32_t opB, double alpha, double beta, void* stream) {
+                       int32_t ldb, int32_t ldc, int32_t opA, int32_t opB, double alpha, double beta, int32_t fp32,
+                       void* stream) {
   if (!A || !B || !C || m < 0 || n < 0 || k < 0) return fail(HQ_ERR_ARG, "bad gemm arguments");
   return guard([&]() -> hq_status {
     hq::Tree t;
@@ -1067,13 +1086,15 @@ hq_status hq_test_gemm(const double* A, const double* B, double* C, int32_t m, i
     hq::GemmTask g{};
     g.A = A; g.B = B; g.C = C; g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.opA = opA; g.opB = opB; g.alpha = alpha; g.beta = beta;
+    e.fp32 = fp32 != 0;
     e.gemm({g}, m, n);
     HQ_CHECK(hipStreamSynchronize(e.st));
     return HQ_OK;
   });
 }
 
-hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, double* R, void* stream) {
+hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, double* R, int32_t fp32,
+                       void* stream) {
   if (!M || !R || rows < 1 || r < 1 || ldm < rows) return fail(HQ_ERR_ARG, "bad qr arguments");
   return guard([&]() -> hq_status {
     hq::Tree t;
@@ -1091,15 +1112,16 @@ hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, do
     hq::QrTask* dq = e.stage.upload(std::vector<hq::QrTask>{q}, e.st);
     int nst = 0;
     while ((1 << nst) < q.ntiles) ++nst;
-    for (int s = 0; s <= nst; ++s) hq::launch_qr_stage(dq, 1, s, (q.ntiles + (1 << s) - 1) >> s, e.d_flag, e.st);
-    hq::launch_qr_final(dq, 1, e.d_flag, e.st);
+    for (int s = 0; s <= nst; ++s)
+      hq::launch_qr_stage(dq, 1, s, (q.ntiles + (1 << s) - 1) >> s, e.d_flag, fp32 != 0, e.st);
+    hq::launch_qr_final(dq, 1, e.d_flag, fp32 != 0, e.st);
     HQ_CHECK(hipStreamSynchronize(e.st));
     return HQ_OK;
   });
 }
 
 hq_status hq_test_recompress(const double* Us, int32_t m, const double* Vs, int32_t n, int32_t r, double tol,
-                             int32_t kcap, double* U, double* V, int32_t* k, void* stream) {
+                             int32_t kcap, double* U, double* V, int32_t* k, int32_t fp32, void* stream) {
   if (!Us || !Vs || !U || !V || !k || m < 1 || n < 1 || r < 0 || kcap < 1) return fail(HQ_ERR_ARG, "bad arguments");
   return guard([&]() -> hq_status {
     hq::Tree t;
@@ -1111,6 +1133,7 @@ hq_status hq_test_recompress(const double* Us, int32_t m, const double* Vs, int3
     hq::Engine::RecTask rt{};
     rt.Us = Us; rt.ldus = m; rt.m = m; rt.Vs = Vs; rt.ldvs = n; rt.n = n; rt.r = dr; rt.rcap = std::max(r, 1);
     rt.U = U; rt.V = V; rt.ldu = m; rt.ldv = n; rt.rank = dr + 1; rt.kcap = kcap; rt.thresh = tol;
+    e.fp32 = fp32 != 0;
     e.recompress({rt});
     HQ_CHECK(hipMemcpyAsync(k, dr + 1, sizeof(int), hipMemcpyDeviceToHost, e.st));
     HQ_CHECK(hipStreamSynchronize(e.st));

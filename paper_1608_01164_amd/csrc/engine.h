@@ -146,6 +146,9 @@ class Engine {
   int* d_zero = nullptr;
   double tol = 1e-10;
   int64_t launches = 0;
+  // Compute precision of the GEMM, TSQR and core-SVD kernels issued from now on (factors stay
+  // FP64 in memory; FP32 kernels round operands on load and truncate at max(tol, 8 u32 sigma_1)).
+  bool fp32 = false;
 
   HMat alloc_hmat(const Tree* t, const std::vector<int>& cap, bool lower_only = false) {
     return alloc_hmat_in(persist, t, cap, lower_only);

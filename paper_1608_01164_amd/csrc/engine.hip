@@ -154,7 +154,7 @@ void Engine::zero_ranks(HMat& h) { launch_fill_int(h.rank, 0, 2 * h.t->ninternal
 
 void Engine::gemm(const std::vector<GemmTask>& v, int max_m, int max_n) {
   if (v.empty()) return;
-  launch_gemm(stage.upload(v, st), (int)v.size(), max_m, max_n, st);
+  launch_gemm(stage.upload(v, st), (int)v.size(), max_m, max_n, fp32, st);
   ++launches;
 }
 void Engine::stack(const std::vector<StackTask>& v, int max_rows) {
@@ -298,6 +298,10 @@ size_t rec_bytes(int m, int n, int rcap, int kcap) {
   const QrPlan a = plan_qr(m, (int)rc), b = plan_qr(n, (int)rc);
   return 8 * (5 * rc * rc + 2 * rc + 4 * rc * kc + ((size_t)a.ntiles * a.hs + (size_t)b.ntiles * b.hs) * rc) + 4096;
 }
+// Relative size of the noise FP32 products and Householder steps leave in a stack of m rows
+// (u32 sqrt(m), with a safety factor of 4): singular values below it are not kept in FP32 mode.
+float fp32_floor(int m) { return 4.0f * 5.9604645e-8f * std::sqrt((float)std::max(m, 1)); }
+
 size_t sym_bytes(int m, int rcap, int kcap) {
   const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1);
   const QrPlan a = plan_qr(m, (int)rc);
@@ -396,7 +400,7 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
     SvdTask s{};
     s.B = b.B; s.C = b.J; s.Jw = b.Jw; s.aux = b.aux; s.Wk = b.Wk; s.Jk = b.Jk; s.sig = nullptr; s.rp = T.r;
     s.kout = T.rank; s.ld = rc; s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
-    s.fidx = T.fidx;
+    s.fidx = T.fidx; s.fp32_floor = fp32_floor(std::max(T.m, T.n));
     sv.push_back(s);
     GemmTask pu{};  // Pu = Rv^T Jk
     pu.A = b.Rv; pu.opA = 1; pu.lda = rc; pu.B = b.Jk; pu.ldb = rc; pu.C = b.Pu; pu.ldc = rc;
@@ -418,12 +422,12 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
   while ((1 << nst) < maxtiles) ++nst;
   for (int s = 0; s <= nst; ++s) {
     const int pairs = (maxtiles + (1 << s) - 1) >> s;
-    launch_qr_stage(dq, (int)qv.size(), s, pairs, d_flag, st);
+    launch_qr_stage(dq, (int)qv.size(), s, pairs, d_flag, fp32, st);
     ++launches;
   }
-  launch_qr_final(dq, (int)qv.size(), d_flag, st);
+  launch_qr_final(dq, (int)qv.size(), d_flag, fp32, st);
   gemm(gB, rmax, rmax);
-  launch_svd(stage.upload(sv, st), nt, d_flag, st);
+  launch_svd(stage.upload(sv, st), nt, d_flag, fp32, st);
   launches += 2;
   gemm(gP, rmax, kmax);
   gemm(gUV, mmax, kmax);
@@ -459,6 +463,7 @@ void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
     SvdTask s{};
     s.B = R; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc;
     s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh; s.fidx = T.fidx;
+    s.fp32_floor = fp32_floor(T.m);
     sv.push_back(s);
     GemmTask g{};  // out = S Jk
     g.A = T.S; g.lda = T.lds; g.B = Jk; g.ldb = rc; g.C = T.out; g.ldc = T.ldo;
@@ -470,11 +475,11 @@ void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
   while ((1 << nst) < maxtiles) ++nst;
   for (int s = 0; s <= nst; ++s) {
     const int pairs = (maxtiles + (1 << s) - 1) >> s;
-    launch_qr_stage(dq, nt, s, pairs, d_flag, st);
+    launch_qr_stage(dq, nt, s, pairs, d_flag, fp32, st);
     ++launches;
   }
-  launch_qr_final(dq, nt, d_flag, st);
-  launch_svd(stage.upload(sv, st), nt, d_flag, st);
+  launch_qr_final(dq, nt, d_flag, fp32, st);
+  launch_svd(stage.upload(sv, st), nt, d_flag, fp32, st);
   launches += 2;
   gemm(go, mmax, kmax);
 }

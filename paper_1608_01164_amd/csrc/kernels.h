@@ -87,6 +87,7 @@ struct SvdTask {
   int ld, kcap;
   double thresh, qr_thresh;
   int fidx;          // status word of the owning matrix (rank overflow sets bit 0)
+  float fp32_floor;  // FP32 variant: truncate below max(thresh, fp32_floor * sigma_1)
 };
 
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.
@@ -108,11 +109,12 @@ struct BandDesc {
   double shift, inv_scale;
 };
 
-void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, hipStream_t s);
+void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s);
 void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s);
-void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, hipStream_t s);
-void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, hipStream_t s);
-void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s);
+void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, bool fp32,
+                     hipStream_t s);
+void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s);
+void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s);
 void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s);
 // fused: A (m <= 128) -> Cholesky factor, B = its inverse; whole tile in LDS

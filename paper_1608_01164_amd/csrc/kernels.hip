@@ -7,6 +7,7 @@
 #include <cfloat>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace hq {
@@ -133,102 +134,148 @@ static __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// The same for a float (one 32-bit DPP move per step).
+template <int CTRL, int ROWS = 0xF>
+static __device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+static __device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x124>(v);
+  v += dpp_move<0x128>(v);
+  v += dpp_move<0x142, 0xA>(v);
+  v += dpp_move<0x143, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Precision traits of the recompression kernels.
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+  static constexpr double eps = DBL_EPSILON, tiny = DBL_MIN, big = DBL_MAX;
+  static constexpr double scale_below = 0x1p-800;  // squared norms below this are recomputed scaled
+  static constexpr int max_shift = 1000;           // largest single power-of-two rescaling
+};
+template <> struct Prec<float> {
+  static constexpr float eps = FLT_EPSILON, tiny = FLT_MIN, big = FLT_MAX;
+  static constexpr float scale_below = 0x1p-100f;
+  static constexpr int max_shift = 100;
+};
+
 // ----------------------------------------------------------------------------------------------
 // Batched GEMM, 64x64 output tile per workgroup (4 waves, 32x32 each = 2x2 MFMA 16x16 tiles),
 // K staged through LDS in chunks of 16.
 // ----------------------------------------------------------------------------------------------
 constexpr int GT = 64, GK = 16;
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// T = double: FP64 MFMA 16x16x4; T = float: operands rounded to FP32, FP32 MFMA 16x16x4 with FP32
+// accumulation (alpha, beta and C stay FP64).
+template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks, int tiles_n) {
-  const GemmTask T = tasks[blockIdx.y];
-  const int m = live(T.mp, T.m), n = live(T.np, T.n), k = live(T.kp, T.k);
+  using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
+  const GemmTask Tk = tasks[blockIdx.y];
+  const int m = live(Tk.mp, Tk.m), n = live(Tk.np, Tk.n), k = live(Tk.kp, Tk.k);
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
   const int row0 = tm * GT, col0 = tn * GT;
   if (row0 >= m || col0 >= n) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (blockIdx.x == 0 && tid == 0)
     count_work(K_GEMM, 2ull * m * n * k,
-               8ull * ((unsigned long long)m * k + (unsigned long long)k * n + (T.beta != 0.0 ? 2ull : 1ull) * m * n));
+               8ull * ((unsigned long long)m * k + (unsigned long long)k * n + (Tk.beta != 0.0 ? 2ull : 1ull) * m * n));
 
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
+  __shared__ T As[GK][GT + 1];
+  __shared__ T Bs[GK][GT + 1];
 
-  d4 acc[2][2];
+  Acc acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < 2; ++y) acc[x][y] = Acc{0, 0, 0, 0};
 
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
 
   for (int k0 = 0; k0 < k; k0 += GK) {
     // stage A tile (rows row0.., k cols k0..)
-    if (T.opA == 0) {
+    if (Tk.opA == 0) {
       const int i = tid & 63, kk0 = tid >> 6;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int kk = kk0 + 4 * q, gi = row0 + i, gk = k0 + kk;
-        As[kk][i] = (gi < m && gk < k) ? T.A[gi + (size_t)gk * T.lda] : 0.0;
+        As[kk][i] = (T)((gi < m && gk < k) ? Tk.A[gi + (size_t)gk * Tk.lda] : 0.0);
       }
     } else {
       const int kk = tid & 15, i0 = tid >> 4;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + 16 * q, gi = row0 + i, gk = k0 + kk;
-        As[kk][i] = (gi < m && gk < k) ? T.A[gk + (size_t)gi * T.lda] : 0.0;
+        As[kk][i] = (T)((gi < m && gk < k) ? Tk.A[gk + (size_t)gi * Tk.lda] : 0.0);
       }
     }
-    if (T.opB == 0) {
+    if (Tk.opB == 0) {
       const int kk = tid & 15, j0 = tid >> 4;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = j0 + 16 * q, gj = col0 + j, gk = k0 + kk;
-        Bs[kk][j] = (gj < n && gk < k) ? T.B[gk + (size_t)gj * T.ldb] : 0.0;
+        Bs[kk][j] = (T)((gj < n && gk < k) ? Tk.B[gk + (size_t)gj * Tk.ldb] : 0.0);
       }
     } else {
       const int j = tid & 63, kk0 = tid >> 6;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int kk = kk0 + 4 * q, gj = col0 + j, gk = k0 + kk;
-        Bs[kk][j] = (gj < n && gk < k) ? T.B[gj + (size_t)gk * T.ldb] : 0.0;
+        Bs[kk][j] = (T)((gj < n && gk < k) ? Tk.B[gj + (size_t)gk * Tk.ldb] : 0.0);
       }
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
-      const double a0 = As[kk + lk][wr + li], a1 = As[kk + lk][wr + 16 + li];
-      const double b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      const T a0 = As[kk + lk][wr + li], a1 = As[kk + lk][wr + 16 + li];
+      const T b0 = Bs[kk + lk][wc + li], b1 = Bs[kk + lk][wc + 16 + li];
+      if constexpr (std::is_same<T, double>::value) {
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      } else {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  // D(i, j) of a 16x16 block sits in lane j + 16*(i%4), element i/4
+  // D(i, j) of a 16x16 block: FP64 in lane j + 16 (i % 4), element i / 4; FP32 in lane
+  // j + 16 (i / 4), element i % 4
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gi = row0 + wr + 16 * x + lk + 4 * e;
+        const int ib = std::is_same<T, double>::value ? lk + 4 * e : 4 * lk + e;
+        const int gi = row0 + wr + 16 * x + ib;
         const int gj = col0 + wc + 16 * y + li;
         if (gi < m && gj < n) {
-          double* c = T.C + gi + (size_t)gj * T.ldc;
-          const double v = T.alpha * acc[x][y][e];
-          *c = (T.beta == 0.0) ? v : v + T.beta * *c;
+          double* c = Tk.C + gi + (size_t)gj * Tk.ldc;
+          const double v = Tk.alpha * (double)acc[x][y][e];
+          *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
         }
       }
 }
 
-void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, hipStream_t s) {
+void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s) {
   if (ntasks <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = (max_m + GT - 1) / GT, tn = (max_n + GT - 1) / GT;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn));
+    if (fp32)
+      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm<float>, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn));
+    else
+      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm<double>, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn));
   }
 }
 
@@ -284,9 +331,10 @@ void launch_scale_cols(double* p, int ld, int rows, const int* wp, double scale,
 constexpr int QR_THREADS = 1024;
 constexpr int QR_WAVES = QR_THREADS / 64;
 constexpr int QR_RMAX = 1024;
-constexpr int QR_LDS = 16384;  // doubles of dynamic LDS (128 KiB)
+constexpr int QR_LDS_BYTES = 131072;  // dynamic LDS of a TSQR stage (128 KiB)
 
-static __device__ __forceinline__ double wave_max(double v) {
+template <typename T>
+static __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
@@ -294,27 +342,28 @@ static __device__ __forceinline__ double wave_max(double v) {
 
 // Block-wide reduction (all threads of a QR_THREADS block, uniform control flow); every thread
 // gets the result.
-template <bool MAX>
-static __device__ double block_reduce(double v, double* red) {
+template <bool MAX, typename T>
+static __device__ T block_reduce(T v, T* red) {
   v = MAX ? wave_max(v) : wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  double t = red[0];
+  T t = red[0];
   for (int w = 1; w < QR_WAVES; ++w) t = MAX ? fmax(t, red[w]) : t + red[w];
   __syncthreads();
   return t;
 }
 
-static __device__ void householder_rows(double* X, int ld, int h, int r) {
-  __shared__ double cn[QR_RMAX];  // squared norm of column c below row j, for the next pivot
-  __shared__ double red[QR_WAVES];
-  __shared__ double sh_v0, sh_tau;
+template <typename T>
+static __device__ void householder_rows(T* X, int ld, int h, int r) {
+  __shared__ T cn[QR_RMAX];  // squared norm of column c below row j, for the next pivot
+  __shared__ T red[QR_WAVES];
+  __shared__ T sh_v0, sh_tau;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jend = (h - 1 < r) ? h - 1 : r;
   if (jend <= 0) return;
   if (wave == 0) {
-    double s = 0.0;
+    T s = 0;
     for (int i = 1 + lane; i < h; i += 64) s += X[i] * X[i];
     s = wave_sum(s);
     if (lane == 0) cn[0] = s;
@@ -324,25 +373,26 @@ static __device__ void householder_rows(double* X, int ld, int h, int r) {
   for (int j = 0; j < jend; ++j) {
     // cn[j] is final for this step (updates below write cn[c] for c > j only), so the branch is
     // uniform over the block; X(j, j) is read by thread 0 alone on the fast path.
-    double s = cn[j], x0 = 0.0, unscale = 1.0;
-    if (s < 0x1p-800) {
+    T s = cn[j], x0 = 0, unscale = 1;
+    if (s < Prec<T>::scale_below) {
       // Tiny column (off-diagonal factors decay exponentially, so entries near the underflow
       // threshold occur): its squared norm lost precision and 1/(nrm (nrm + |x0|)) could overflow.
       // Rescale rows j.. of the column by a power of two (exact) and recompute the norm; the
       // reflector is unchanged by the scaling, only the diagonal of R is scaled back.
-      double am = 0.0;
+      T am = 0;
       for (int i = j + tid; i < h; i += QR_THREADS) am = fmax(am, fabs(X[i + (size_t)j * ld]));
       am = block_reduce<true>(am, red);
-      s = 0.0;
-      x0 = 0.0;
-      if (am > 0.0) {
-        // 2^-e can exceed the largest double when am is subnormal: apply it as two factors
+      s = 0;
+      x0 = 0;
+      if (am > 0) {
+        // 2^-e can exceed the largest value when am is subnormal: apply it as two factors
+        constexpr int M = Prec<T>::max_shift;
         const int e = ilogb(am);
-        const double sc1 = ldexp(1.0, -e > 1000 ? 1000 : -e), sc2 = ldexp(1.0, -e > 1000 ? -e - 1000 : 0);
-        unscale = ldexp(1.0, e);
-        double ss = 0.0;
+        const T sc1 = ldexp((T)1, -e > M ? M : -e), sc2 = ldexp((T)1, -e > M ? -e - M : 0);
+        unscale = ldexp((T)1, e);
+        T ss = 0;
         for (int i = j + tid; i < h; i += QR_THREADS) {
-          const double x = (X[i + (size_t)j * ld] * sc1) * sc2;
+          const T x = (X[i + (size_t)j * ld] * sc1) * sc2;
           X[i + (size_t)j * ld] = x;
           if (i > j) ss += x * x;
         }
@@ -353,44 +403,44 @@ static __device__ void householder_rows(double* X, int ld, int h, int r) {
       x0 = X[j + (size_t)j * ld];
     }
     if (tid == 0) {
-      if (s == 0.0) {
-        sh_tau = 0.0;
-        sh_v0 = 0.0;
+      if (s == 0) {
+        sh_tau = 0;
+        sh_v0 = 0;
         X[j + (size_t)j * ld] = x0 * unscale;
       } else {
-        const double nrm = sqrt(x0 * x0 + s);
-        const double beta = x0 >= 0.0 ? -nrm : nrm;
+        const T nrm = sqrt(x0 * x0 + s);
+        const T beta = x0 >= 0 ? -nrm : nrm;
         sh_v0 = x0 - beta;
-        sh_tau = 1.0 / (nrm * (nrm + fabs(x0)));
+        sh_tau = (T)1 / (nrm * (nrm + fabs(x0)));
         X[j + (size_t)j * ld] = beta * unscale;
       }
     }
     __syncthreads();
-    const double tau = sh_tau, v0 = sh_v0;
-    const double* vj = X + (size_t)j * ld;  // reflector: v0 at row j, X[i, j] below
+    const T tau = sh_tau, v0 = sh_v0;
+    const T* vj = X + (size_t)j * ld;  // reflector: v0 at row j, X[i, j] below
     // four trailing columns per wave; the norm below row j+1 of each updated column is recorded
     for (int c0 = j + 1 + 4 * wave; c0 < r; c0 += 4 * QR_WAVES) {
       const int nc = r - c0 < 4 ? r - c0 : 4;
-      double* col[4];
-      double w[4] = {0.0, 0.0, 0.0, 0.0};
+      T* col[4];
+      T w[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int q = 0; q < 4; ++q) col[q] = X + (size_t)(q < nc ? c0 + q : c0) * ld;
-      if (tau != 0.0) {
+      if (tau != 0) {
         for (int i = j + 1 + lane; i < h; i += 64) {
-          const double vi = vj[i];
+          const T vi = vj[i];
 #pragma unroll
           for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) w[q] = (wave_sum(w[q]) + v0 * col[q][j]) * tau;
       }
-      double nn[4] = {0.0, 0.0, 0.0, 0.0};
+      T nn[4] = {0, 0, 0, 0};
       for (int i = j + 1 + lane; i < h; i += 64) {
-        const double vi = vj[i];
+        const T vi = vj[i];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double x = col[q][i] - w[q] * vi;
-          if (q < nc && tau != 0.0) col[q][i] = x;
+          const T x = col[q][i] - w[q] * vi;
+          if (q < nc && tau != 0) col[q][i] = x;
           if (i > j + 1) nn[q] += x * x;
         }
       }
@@ -400,7 +450,7 @@ static __device__ void householder_rows(double* X, int ld, int h, int r) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (q < nc) {
-            if (tau != 0.0) col[q][j] -= w[q] * v0;
+            if (tau != 0) col[q][j] -= w[q] * v0;
             cn[c0 + q] = nn[q];
           }
       }
@@ -420,107 +470,122 @@ static __device__ __forceinline__ int slot_live_rows(int a, int s, int h0, int r
   return cov < r ? (int)cov : r;
 }
 
+// One TSQR stage.  The workspace slots hold T values (the FP64-sized buffer is reinterpreted).
+template <typename T>
 __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restrict__ tasks, int stage, int* flag) {
-  extern __shared__ double qlds[];
-  const QrTask T = tasks[blockIdx.y];
-  const int r = live(T.rp, T.rcap);
+  extern __shared__ __align__(16) unsigned char qlds_raw[];
+  T* qlds = reinterpret_cast<T*>(qlds_raw);
+  constexpr int kLds = QR_LDS_BYTES / (int)sizeof(T);
+  const QrTask Tk = tasks[blockIdx.y];
+  const int r = live(Tk.rp, Tk.rcap);
   if (r <= 0) return;
   const int tid = threadIdx.x;
-  double* slot;
+  T* const work = reinterpret_cast<T*>(Tk.work);
+  T* slot;
   int h, ra = 0;
-  const double* src0;
   int ld0, rows0;
-  const double* src1 = nullptr;
+  const double* srcM = nullptr;  // stage 0: the FP64 stack
+  const T* src0 = nullptr;       // stage s: slot a
+  const T* src1 = nullptr;
   int rb = 0;
   if (stage == 0) {
     const int t = blockIdx.x;
-    if (t >= T.ntiles) return;
-    const int r0 = t * T.h0;
-    h = T.rows - r0;
-    if (h > T.h0) h = T.h0;
-    slot = T.work + (size_t)t * T.hs * T.rcap;
-    src0 = T.M + r0;
-    ld0 = T.ldm;
+    if (t >= Tk.ntiles) return;
+    const int r0 = t * Tk.h0;
+    h = Tk.rows - r0;
+    if (h > Tk.h0) h = Tk.h0;
+    slot = work + (size_t)t * Tk.hs * Tk.rcap;
+    srcM = Tk.M + r0;
+    ld0 = Tk.ldm;
     rows0 = h;
   } else {
     const int half = 1 << (stage - 1);
     const int a = blockIdx.x << stage, b = a + half;
-    if (b >= T.ntiles) return;
-    ra = slot_live_rows(a, stage - 1, T.h0, T.rows, r);
-    rb = slot_live_rows(b, stage - 1, T.h0, T.rows, r);
-    slot = T.work + (size_t)a * T.hs * T.rcap;
+    if (b >= Tk.ntiles) return;
+    ra = slot_live_rows(a, stage - 1, Tk.h0, Tk.rows, r);
+    rb = slot_live_rows(b, stage - 1, Tk.h0, Tk.rows, r);
+    slot = work + (size_t)a * Tk.hs * Tk.rcap;
     src0 = slot;
-    ld0 = T.hs;
+    ld0 = Tk.hs;
     rows0 = ra;
-    src1 = T.work + (size_t)b * T.hs * T.rcap;
+    src1 = work + (size_t)b * Tk.hs * Tk.rcap;
     h = ra + rb;
   }
-  const bool inl = h * r <= QR_LDS;
-  double* X = inl ? qlds : slot;
-  const int ldx = inl ? h : T.hs;
+  const bool inl = h * r <= kLds;
+  T* X = inl ? qlds : slot;
+  const int ldx = inl ? h : Tk.hs;
   // gather the panel (stage 0: a row tile of M; stage s: triangle of slot a over triangle of slot b)
-  if (inl || stage == 0) {
+  if (stage == 0) {
+    bool bad = false;  // non-finite stacked input is reported (value 16)
     for (int idx = tid; idx < rows0 * r; idx += QR_THREADS) {
       const int i = idx % rows0, c = idx / rows0;
-      const double v = src0[i + (size_t)c * ld0];
-      X[i + (size_t)c * ldx] = (stage == 0 || i <= c) ? v : 0.0;
+      const double v = srcM[i + (size_t)c * ld0];
+      bad |= !(fabs(v) <= DBL_MAX);
+      X[i + (size_t)c * ldx] = (T)v;
+    }
+    if (bad) atomicOr(flag + Tk.fidx, 16);
+  } else if (inl) {
+    for (int idx = tid; idx < rows0 * r; idx += QR_THREADS) {
+      const int i = idx % rows0, c = idx / rows0;
+      X[i + (size_t)c * ldx] = (i <= c) ? src0[i + (size_t)c * ld0] : (T)0;
     }
   } else {  // in place: clear the reflector entries left below the triangle of slot a
     for (int idx = tid; idx < rows0 * r; idx += QR_THREADS) {
       const int i = idx % rows0, c = idx / rows0;
-      if (i > c) X[i + (size_t)c * ldx] = 0.0;
+      if (i > c) X[i + (size_t)c * ldx] = 0;
     }
-  }
-  if (stage == 0) {  // non-finite stacked input is reported (value 16) and traced to its source by the caller
-    bool bad = false;
-    for (int idx = tid; idx < rows0 * r; idx += QR_THREADS) {
-      const int i = idx % rows0, c = idx / rows0;
-      bad |= !(fabs(X[i + (size_t)c * ldx]) <= DBL_MAX);
-    }
-    if (bad) atomicOr(flag + T.fidx, 16);
   }
   if (stage > 0)
     for (int idx = tid; idx < rb * r; idx += QR_THREADS) {
       const int i = idx % rb, c = idx / rb;
-      X[(ra + i) + (size_t)c * ldx] = (i <= c) ? src1[i + (size_t)c * T.hs] : 0.0;
+      X[(ra + i) + (size_t)c * ldx] = (i <= c) ? src1[i + (size_t)c * Tk.hs] : (T)0;
     }
   __syncthreads();
-  householder_rows(X, ldx, h, r);
+  householder_rows<T>(X, ldx, h, r);
   if (inl) {  // the triangle goes back to the slot
     const int rr = h < r ? h : r;
     for (int idx = tid; idx < rr * r; idx += QR_THREADS) {
       const int i = idx % rr, c = idx / rr;
-      slot[i + (size_t)c * T.hs] = X[i + (size_t)c * ldx];
+      slot[i + (size_t)c * Tk.hs] = X[i + (size_t)c * ldx];
     }
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tasks, int* flag) {
-  const QrTask T = tasks[blockIdx.x];
-  const int r = live(T.rp, T.rcap);
-  const int rr = T.rows < r ? T.rows : r;
+  const QrTask Tk = tasks[blockIdx.x];
+  const int r = live(Tk.rp, Tk.rcap);
+  const int rr = Tk.rows < r ? Tk.rows : r;
+  const T* work = reinterpret_cast<const T*>(Tk.work);
   bool bad = false;
   for (int idx = threadIdx.x; idx < r * r; idx += 256) {
     const int i = idx % r, c = idx / r;
-    const double v = (i < rr && i <= c) ? T.work[i + (size_t)c * T.hs] : 0.0;
+    const double v = (i < rr && i <= c) ? (double)work[i + (size_t)c * Tk.hs] : 0.0;
     bad |= !(fabs(v) <= DBL_MAX);
-    T.R[i + (size_t)c * T.ldr] = v;
+    Tk.R[i + (size_t)c * Tk.ldr] = v;
   }
-  if (bad) atomicOr(flag + T.fidx, 32);  // the triangular factor came out non-finite
+  if (bad) atomicOr(flag + Tk.fidx, 32);  // the triangular factor came out non-finite
 }
 
-void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, hipStream_t s) {
+void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, bool fp32,
+                     hipStream_t s) {
   if (ntasks <= 0 || max_pairs <= 0) return;
-  const size_t lds = sizeof(double) * (size_t)QR_LDS;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage, dim3(max_pairs, nt), dim3(QR_THREADS), lds, s, d_tasks + t0, stage,
-                                         flag));
+    if (fp32)
+      HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage<float>, dim3(max_pairs, nt), dim3(QR_THREADS), QR_LDS_BYTES, s,
+                                           d_tasks + t0, stage, flag));
+    else
+      HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage<double>, dim3(max_pairs, nt), dim3(QR_THREADS), QR_LDS_BYTES, s,
+                                           d_tasks + t0, stage, flag));
   }
 }
-void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
+void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s) {
   if (ntasks <= 0) return;
-  HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
+  if (fp32)
+    HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final<float>, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
+  else
+    HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final<double>, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -530,38 +595,49 @@ void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, hipStream_t s
 constexpr int SVD_THREADS = 1024;
 constexpr int SVD_WAVES = SVD_THREADS / 64;
 constexpr int SVD_RMAX = 1024;   // largest core handled
-constexpr int SVD_LDS = 16384;   // doubles of dynamic LDS (128 KiB) for B, C and J when they fit
+constexpr int SVD_LDS_BYTES = 131072;  // dynamic LDS (128 KiB) for B, C and J when they fit
 
-struct ArgMax { double v; int i; };
+template <typename T>
+struct ArgMax { T v; int i; };
 
-static __device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {
+template <typename T>
+static __device__ __forceinline__ ArgMax<T> wave_argmax(ArgMax<T> a) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const double v = __shfl_xor(a.v, o, 64);
+    const T v = __shfl_xor(a.v, o, 64);
     const int i = __shfl_xor(a.i, o, 64);
     if (v > a.v || (v == a.v && i < a.i)) { a.v = v; a.i = i; }
   }
   return a;
 }
 
+// T = double: FP64 throughout.  T = float: the core is rounded to FP32, everything runs in FP32, and
+// truncation uses max(thresh, fp32_floor sigma_1) (singular values below that are FP32 noise); the
+// outputs stay FP64.  Workspace buffers (C, Jw, aux) are reinterpreted as T.
+template <typename T>
 __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__ tasks, int* flag) {
-  extern __shared__ double slds[];
-  const SvdTask T = tasks[blockIdx.x];
+  extern __shared__ __align__(16) unsigned char svd_raw[];
+  T* slds = reinterpret_cast<T*>(svd_raw);
+  constexpr int SVD_LDS = SVD_LDS_BYTES / (int)sizeof(T);
+  const SvdTask Tk = tasks[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int r = *T.rp;
+  int r = *Tk.rp;
   if (r > SVD_RMAX) r = SVD_RMAX;
   if (r <= 0) {
-    if (tid == 0) *T.kout = 0;
+    if (tid == 0) *Tk.kout = 0;
     return;
   }
-  double* tau = T.aux;
-  double* vhead = T.aux + r;
-  __shared__ double cn[SVD_RMAX];   // trailing squared column norms; later sigma^2
-  __shared__ double vl[SVD_RMAX];   // current reflector when B is in global memory
+  constexpr bool dbl = std::is_same<T, double>::value;
+  T* tau = reinterpret_cast<T*>(Tk.aux);
+  T* vhead = tau + r;
+  // global copy of B in T: the input buffer itself (FP64), or the upper half of the C workspace
+  T* const Bglob = dbl ? reinterpret_cast<T*>(Tk.B) : reinterpret_cast<T*>(Tk.C) + (size_t)Tk.ld * Tk.ld;
+  __shared__ T cn[SVD_RMAX];   // trailing squared column norms; later sigma^2
+  __shared__ T vl[SVD_RMAX];   // current reflector when B is in global memory
   __shared__ int perm[SVD_RMAX];
   __shared__ int ordr[SVD_RMAX];
-  __shared__ double redv[SVD_WAVES];
-  __shared__ ArgMax reda[SVD_WAVES];
+  __shared__ T redv[SVD_WAVES];
+  __shared__ ArgMax<T> reda[SVD_WAVES];
   __shared__ int rotated;
   __shared__ unsigned long long sh_pairs, sh_rots;
   if (tid == 0) { sh_pairs = 0; sh_rots = 0; }
@@ -571,23 +647,28 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
 
   // ---- phase 1: QR with column pivoting, stopped at trailing Frobenius norm <= qr_thresh
   const bool bl = r * r <= SVD_LDS;
-  double* Bm = bl ? slds : T.B;
-  int ldb = bl ? r : T.ld;
+  T* Bm = bl ? slds : Bglob;
+  int ldb = bl ? r : Tk.ld;
   if (bl)
-    for (int idx = tid; idx < r * r; idx += SVD_THREADS) slds[idx] = T.B[(idx % r) + (size_t)(idx / r) * T.ld];
+    for (int idx = tid; idx < r * r; idx += SVD_THREADS) slds[idx] = (T)Tk.B[(idx % r) + (size_t)(idx / r) * Tk.ld];
+  else if (!dbl)
+    for (int idx = tid; idx < r * r; idx += SVD_THREADS) {
+      const size_t o = (idx % r) + (size_t)(idx / r) * Tk.ld;
+      Bglob[o] = (T)Tk.B[o];
+    }
   __syncthreads();
   for (int c = wave; c < r; c += SVD_WAVES) {
-    double s = 0.0;
+    T s = 0;
     for (int i = lane; i < r; i += 64) s += Bm[i + (size_t)c * ldb] * Bm[i + (size_t)c * ldb];
     s = wave_sum(s);
     if (lane == 0) { cn[c] = s; perm[c] = c; }
   }
   __syncthreads();
-  const double qth2 = T.qr_thresh * T.qr_thresh;
+  T qth2 = (T)(Tk.qr_thresh * Tk.qr_thresh);
   int t = r;
   for (int j = 0; j < r; ++j) {
-    double s = 0.0;
-    ArgMax am{-1.0, 0x7fffffff};
+    T s = 0;
+    ArgMax<T> am{(T)-1, 0x7fffffff};
     for (int c = j + tid; c < r; c += SVD_THREADS) {
       s += cn[c];
       if (cn[c] > am.v) { am.v = cn[c]; am.i = c; }
@@ -596,40 +677,42 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     am = wave_argmax(am);
     if (lane == 0) { redv[wave] = s; reda[wave] = am; }
     __syncthreads();
-    double tot = 0.0;
-    ArgMax best = reda[0];
+    T tot = 0;
+    ArgMax<T> best = reda[0];
     for (int w = 0; w < SVD_WAVES; ++w) {
       tot += redv[w];
-      const ArgMax x = reda[w];
+      const ArgMax<T> x = reda[w];
       if (x.v > best.v || (x.v == best.v && x.i < best.i)) best = x;
     }
+    // FP32: stop where the trailing norm reaches a tenth of the FP32 noise level of B
+    if (!dbl && j == 0) qth2 = fmax(qth2, (T)0.01 * (T)Tk.fp32_floor * (T)Tk.fp32_floor * tot);
     if (tot <= qth2) { t = j; break; }
-    if (!(tot <= DBL_MAX) || best.i < j || best.i >= r) {
+    if (!(tot <= Prec<T>::big) || best.i < j || best.i >= r) {
       // non-finite trailing norms: no valid pivot exists; report and stop (the caller discards the result)
-      if (tid == 0) atomicOr(flag + T.fidx, 8);
+      if (tid == 0) atomicOr(flag + Tk.fidx, 8);
       t = j;
       break;
     }
     const int p = best.i;
     if (p != j) {
       for (int i = tid; i < r; i += SVD_THREADS) {
-        const double x = Bm[i + (size_t)j * ldb];
+        const T x = Bm[i + (size_t)j * ldb];
         Bm[i + (size_t)j * ldb] = Bm[i + (size_t)p * ldb];
         Bm[i + (size_t)p * ldb] = x;
       }
       __syncthreads();
       if (tid == 0) {
-        const double x = cn[j]; cn[j] = cn[p]; cn[p] = x;
+        const T x = cn[j]; cn[j] = cn[p]; cn[p] = x;
         const int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
       }
       __syncthreads();
     }
     // reflector from the trailing norm of the pivot column (rows j..r-1)
-    const double nrm = sqrt(cn[j]), x0 = Bm[j + (size_t)j * ldb];
-    const double beta = x0 >= 0.0 ? -nrm : nrm;
-    const double vj = x0 - beta;
-    const double tj = nrm > 0.0 ? 1.0 / (nrm * (nrm + fabs(x0))) : 0.0;
-    const double* vcol = Bm + (size_t)j * ldb;
+    const T nrm = sqrt(cn[j]), x0 = Bm[j + (size_t)j * ldb];
+    const T beta = x0 >= 0 ? -nrm : nrm;
+    const T vj = x0 - beta;
+    const T tj = nrm > 0 ? (T)1 / (nrm * (nrm + fabs(x0))) : (T)0;
+    const T* vcol = Bm + (size_t)j * ldb;
     if (!bl) {
       for (int i = j + 1 + tid; i < r; i += SVD_THREADS) vl[i] = vcol[i];
       __syncthreads();
@@ -637,8 +720,8 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     }
     for (int cc = j + 1 + 4 * wave; cc < r; cc += 4 * SVD_WAVES) {
       const int nc = r - cc < 4 ? r - cc : 4;
-      double* col[4];
-      double w[4] = {0.0, 0.0, 0.0, 0.0}, nn[4] = {0.0, 0.0, 0.0, 0.0};
+      T* col[4];
+      T w[4] = {0, 0, 0, 0}, nn[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int q = 0; q < 4; ++q) col[q] = Bm + (size_t)(q < nc ? cc + q : cc) * ldb;
       if (lane == 0) {
@@ -646,7 +729,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
         for (int q = 0; q < 4; ++q) w[q] = vj * col[q][j];
       }
       for (int i = j + 1 + lane; i < r; i += 64) {
-        const double vi = vcol[i];
+        const T vi = vcol[i];
 #pragma unroll
         for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
       }
@@ -655,11 +738,11 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
       if (lane == 0)
         for (int q = 0; q < nc; ++q) col[q][j] -= w[q] * vj;
       for (int i = j + 1 + lane; i < r; i += 64) {
-        const double vi = vcol[i];
+        const T vi = vcol[i];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (q < nc) {
-            const double x = col[q][i] - w[q] * vi;
+            const T x = col[q][i] - w[q] * vi;
             col[q][i] = x;
             nn[q] += x * x;
           }
@@ -680,47 +763,47 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   __syncthreads();
   c1 = wall_clock64();
   if (t == 0) {
-    if (tid == 0) *T.kout = 0;
+    if (tid == 0) *Tk.kout = 0;
     return;
   }
   // ---- phase 2: one-sided Jacobi on C = R_t^T (r x t), rotations accumulated in J (t x t)
-  double *C, *J;
+  T *C, *J;
   int ldc, ldj;
   if (bl && r * r + r * t + t * t <= SVD_LDS) {
     C = slds + r * r; ldc = r;
     J = C + r * t; ldj = t;
   } else {
     if (bl) {  // free the LDS: reflectors back to global
-      for (int idx = tid; idx < r * r; idx += SVD_THREADS) T.B[(idx % r) + (size_t)(idx / r) * T.ld] = slds[idx];
+      for (int idx = tid; idx < r * r; idx += SVD_THREADS) Bglob[(idx % r) + (size_t)(idx / r) * Tk.ld] = slds[idx];
       __syncthreads();
-      Bm = T.B;
-      ldb = T.ld;
+      Bm = Bglob;
+      ldb = Tk.ld;
     }
     if (r * t + t * t <= SVD_LDS) {
       C = slds; ldc = r;
       J = slds + r * t; ldj = t;
     } else {
-      C = T.C; ldc = T.ld;
+      C = reinterpret_cast<T*>(Tk.C); ldc = Tk.ld;
       if (t * t <= SVD_LDS) { J = slds; ldj = t; }
-      else { J = T.Jw; ldj = T.ld; }
+      else { J = reinterpret_cast<T*>(Tk.Jw); ldj = Tk.ld; }
     }
   }
   for (int idx = tid; idx < r * t; idx += SVD_THREADS) {
     const int c = idx % r, i = idx / r;  // C[c, i] = R[i, c]
-    C[c + (size_t)i * ldc] = (c >= i) ? Bm[i + (size_t)c * ldb] : 0.0;
+    C[c + (size_t)i * ldc] = (c >= i) ? Bm[i + (size_t)c * ldb] : (T)0;
   }
   for (int idx = tid; idx < t * t; idx += SVD_THREADS) {
     const int i = idx % t, c = idx / t;
-    J[i + (size_t)c * ldj] = (i == c) ? 1.0 : 0.0;
+    J[i + (size_t)c * ldj] = (i == c) ? (T)1 : (T)0;
   }
   __syncthreads();
   const int tp = t + (t & 1);
-  const double tol = 4.0 * DBL_EPSILON * sqrt((double)r);
-  double* nrm2 = cn;  // squared column norms of C, tracked through the rotations
+  const T tol = (T)4 * Prec<T>::eps * sqrt((T)r);
+  T* nrm2 = cn;  // squared column norms of C, tracked through the rotations
   for (int sweep = 0; sweep < 40 && t > 1; ++sweep) {
     // exact norms at the start of every sweep
     for (int c = wave; c < t; c += SVD_WAVES) {
-      double s = 0.0;
+      T s = 0;
       for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ldc] * C[i + (size_t)c * ldc];
       s = wave_sum(s);
       if (lane == 0) nrm2[c] = s;
@@ -734,36 +817,36 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
         int q = (y == 0) ? 0 : 1 + ((y - 1 + round) % (tp - 1));
         if (p >= t || q >= t) continue;
         if (p > q) { const int tt = p; p = q; q = tt; }
-        double* cp = C + (size_t)p * ldc;
-        double* cq = C + (size_t)q * ldc;
-        double g = 0.0;
+        T* cp = C + (size_t)p * ldc;
+        T* cq = C + (size_t)q * ldc;
+        T g = 0;
         for (int i = lane; i < r; i += 64) g += cp[i] * cq[i];
         g = wave_sum(g);
-        const double a = nrm2[p], b = nrm2[q];
+        const T a = nrm2[p], b = nrm2[q];
         if (lane == 0) atomicAdd(&sh_pairs, 1ull);
-        if (a > DBL_MIN && b > DBL_MIN && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+        if (a > Prec<T>::tiny && b > Prec<T>::tiny && fabs(g) > tol * sqrt(a) * sqrt(b)) {
           if (lane == 0) atomicAdd(&sh_rots, 1ull);
-          const double zeta = (b - a) / (2.0 * g);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          double na = 0.0, nb = 0.0;
+          const T zeta = (b - a) / ((T)2 * g);
+          const T tt = (zeta >= 0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
+          const T cs = (T)1 / sqrt((T)1 + tt * tt), sn = cs * tt;
+          T na = 0, nb = 0;
           for (int i = lane; i < r; i += 64) {
-            const double u = cp[i], w = cq[i];
-            const double u2 = cs * u - sn * w, w2 = sn * u + cs * w;
+            const T u = cp[i], w = cq[i];
+            const T u2 = cs * u - sn * w, w2 = sn * u + cs * w;
             cp[i] = u2;
             cq[i] = w2;
             na += u2 * u2;
             nb += w2 * w2;
           }
-          double ea = a - tt * g, eb = b + tt * g;  // exact-arithmetic norms after the rotation
+          T ea = a - tt * g, eb = b + tt * g;  // exact-arithmetic norms after the rotation
           if (!(ea > 0.25 * a) || !(eb > 0.25 * b)) {  // cancellation: take the computed ones
             ea = wave_sum(na);
             eb = wave_sum(nb);
           }
-          double* jp = J + (size_t)p * ldj;
-          double* jq = J + (size_t)q * ldj;
+          T* jp = J + (size_t)p * ldj;
+          T* jq = J + (size_t)q * ldj;
           for (int i = lane; i < t; i += 64) {
-            const double u = jp[i], w = jq[i];
+            const T u = jp[i], w = jq[i];
             jp[i] = cs * u - sn * w;
             jq[i] = sn * u + cs * w;
           }
@@ -782,13 +865,13 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   }
   c2 = wall_clock64();
   // ---- phase 3: singular values (column norms of C J), order, truncation
-  double* sig2 = cn;
+  T* sig2 = cn;
   for (int c = wave; c < t; c += SVD_WAVES) {
-    double s = 0.0;
+    T s = 0;
     for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ldc] * C[i + (size_t)c * ldc];
     s = wave_sum(s);
-    if (!(s <= DBL_MAX)) {  // NaN or Inf: flagged, and ranked last so that the ordering stays a permutation
-      if (lane == 0) atomicOr(flag + T.fidx, 8);
+    if (!(s <= Prec<T>::big)) {  // NaN or Inf: flagged, and ranked last so that the ordering stays a permutation
+      if (lane == 0) atomicOr(flag + Tk.fidx, 8);
       s = 0.0;
     }
     if (lane == 0) sig2[c] = s;
@@ -796,37 +879,42 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   __syncthreads();
   for (int i = tid; i < t; i += SVD_THREADS) {
     int pos = 0;
-    const double si = sig2[i];
+    const T si = sig2[i];
     for (int j = 0; j < t; ++j) pos += (sig2[j] > si) || (sig2[j] == si && j < i);
     ordr[pos] = i;
   }
   __syncthreads();
-  const double th2 = T.thresh * T.thresh;
+  T th2 = (T)(Tk.thresh * Tk.thresh);
+  if (!dbl) {  // FP32: keep sigma > max(thresh, floor * sigma_1)
+    T smax = 0;
+    for (int i = 0; i < t; ++i) smax = fmax(smax, sig2[i]);
+    th2 = fmax(th2, (T)Tk.fp32_floor * (T)Tk.fp32_floor * smax);
+  }
   int kk = 0;
   for (int i = 0; i < t; ++i) kk += sig2[i] > th2;
-  if (kk > T.kcap) {
-    if (tid == 0) atomicOr(flag + T.fidx, 1);
-    kk = T.kcap;
+  if (kk > Tk.kcap) {
+    if (tid == 0) atomicOr(flag + Tk.fidx, 1);
+    kk = Tk.kcap;
   }
-  if (tid == 0) *T.kout = kk;
-  if (T.sig)
-    for (int i = tid; i < t; i += SVD_THREADS) T.sig[i] = sqrt(sig2[ordr[i]]);
+  if (tid == 0) *Tk.kout = kk;
+  if (Tk.sig)
+    for (int i = tid; i < t; i += SVD_THREADS) Tk.sig[i] = sqrt((double)sig2[ordr[i]]);
   // ---- phase 4: B ~ Q_t J S (Pi W S^{-1})^T with W = C J
   //   Jk[perm[c], o] = W[c, ord(o)] / sigma      (right singular vectors)
   //   Wk = Q_t [J[:, ord(o)] / sigma ; 0]         (left singular vectors over sigma)
   for (int idx = tid; idx < r * kk; idx += SVD_THREADS) {
     const int c = idx % r, o = idx / r, src = ordr[o];
-    const double is = 1.0 / sqrt(sig2[src]);
-    T.Jk[perm[c] + (size_t)o * T.ld] = C[c + (size_t)src * ldc] * is;
-    T.Wk[c + (size_t)o * T.ld] = (c < t) ? J[c + (size_t)src * ldj] * is : 0.0;
+    const double is = 1.0 / sqrt((double)sig2[src]);
+    Tk.Jk[perm[c] + (size_t)o * Tk.ld] = C[c + (size_t)src * ldc] * is;
+    Tk.Wk[c + (size_t)o * Tk.ld] = (c < t) ? J[c + (size_t)src * ldj] * is : 0.0;
   }
   __syncthreads();
   for (int j = t - 1; j >= 0; --j) {
     const double tj = tau[j], vj = vhead[j];
     if (tj != 0.0) {
-      const double* vcol = Bm + (size_t)j * ldb;
+      const T* vcol = Bm + (size_t)j * ldb;
       for (int o = wave; o < kk; o += SVD_WAVES) {
-        double* col = T.Wk + (size_t)o * T.ld;
+        double* col = Tk.Wk + (size_t)o * Tk.ld;
         double w = (lane == 0) ? vj * col[j] : 0.0;
         for (int i = j + 1 + lane; i < r; i += 64) w += vcol[i] * col[i];
         w = wave_sum(w) * tj;
@@ -855,10 +943,14 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   }
 }
 
-void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
+void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s) {
   if (ntasks <= 0) return;
-  HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(SVD_THREADS), sizeof(double) * SVD_LDS, s,
-                                      d_tasks, flag));
+  if (fp32)
+    HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<float>, dim3(ntasks), dim3(SVD_THREADS), SVD_LDS_BYTES, s, d_tasks,
+                                          flag));
+  else
+    HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<double>, dim3(ntasks), dim3(SVD_THREADS), SVD_LDS_BYTES, s, d_tasks,
+                                          flag));
 }
 
 // ----------------------------------------------------------------------------------------------

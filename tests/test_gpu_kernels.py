@@ -27,6 +27,44 @@ def test_gemm(m, n, k, opA, opB):
     assert np.abs(got - ref).max() <= 1e-13 * max(1.0, k) ** 0.5 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("m,n,k,opA,opB", [
+    (16, 16, 16, 0, 0), (64, 64, 16, 0, 0), (65, 63, 17, 0, 1), (130, 7, 300, 1, 0), (33, 129, 5, 1, 1),
+    (1000, 40, 40, 0, 0), (40, 40, 3000, 1, 0)])
+def test_gemm_fp32(m, n, k, opA, opB):
+    """FP32 MFMA variant: operands rounded to FP32, FP32 accumulation.  The identity product
+    pins the placement of every output row; the random product is checked within FP32 rounding."""
+    if (m, n, k) == (16, 16, 16):
+        A = np.eye(16)
+        B = np.arange(256, dtype=np.float64).reshape(16, 16)  # exact in FP32
+        dC = empty(16, 16)
+        hq.test_gemm(dev(A), dev(B), dC, 16, 16, 16, 16, 16, 16, 0, 0, 1.0, 0.0, fp32=True)
+        assert np.array_equal(host(dC, 16, 16), B)
+        return
+    rng = np.random.default_rng(m * 7 + n + 1)
+    A = rng.standard_normal((k, m) if opA else (m, k))
+    B = rng.standard_normal((n, k) if opB else (k, n))
+    C = rng.standard_normal((m, n))
+    dC = dev(C)
+    hq.test_gemm(dev(A), dev(B), dC, m, n, k, A.shape[0], B.shape[0], m, opA, opB, 1.5, -0.5, fp32=True)
+    Af, Bf = (A.T if opA else A), (B.T if opB else B)
+    ref = 1.5 * Af @ Bf - 0.5 * C
+    bound = 1.5 * np.abs(Af) @ np.abs(Bf) * 4 * k * np.finfo(np.float32).eps
+    assert (np.abs(host(dC, m, n) - ref) <= bound + 1e-12).all()
+
+
+@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (700, 200), (5000, 150)])
+def test_qr_r_fp32(rows, r):
+    rng = np.random.default_rng(rows + r + 1)
+    M = rng.standard_normal((rows, r)) * np.logspace(0, -3, r)[None, :]
+    dR = empty(r, r)
+    hq.test_qr_r(dev(M), rows, r, rows, dR, fp32=True)
+    R = host(dR, r, r)
+    assert np.abs(np.tril(R, -1)).max() == 0.0
+    Rn = np.linalg.qr(M, mode="r")
+    # backward stable in FP32: R^T R reproduces M^T M to O(u32) relative to ||M||^2
+    assert np.abs(R.T @ R - Rn.T @ Rn).max() <= 50 * np.finfo(np.float32).eps * np.linalg.norm(M, 2) ** 2
+
+
 @pytest.mark.parametrize("rows,r", [(1, 1), (5, 9), (64, 64), (300, 20), (2000, 37), (9000, 64), (700, 200)])
 def test_qr_r(rows, r):
     rng = np.random.default_rng(rows + r)
@@ -42,6 +80,27 @@ def test_qr_r(rows, r):
     assert np.abs(np.abs(R[:kk]) - np.abs(Rn[:kk])).max() < 1e-12 * np.abs(Rn).max()
     if rows < r:
         assert np.abs(R[kk:]).max() == 0.0
+
+
+@pytest.mark.parametrize("m,n,r,decay", [(300, 200, 40, 0.6), (1200, 900, 90, 0.8), (64, 64, 64, 0.5)])
+def test_recompress_fp32(m, n, r, decay):
+    """FP32 recompression: the error is at the FP32 truncation level max(tol, 4 u32 sqrt(rows)
+    sigma_1) (times a modest factor for the FP32 arithmetic), and no kept direction is spurious."""
+    rng = np.random.default_rng(m + n + r + 5)
+    s = decay ** np.arange(r)
+    Uq, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    Us = np.hstack([Uq * s, 0.5 * Uq[:, : r // 2] * s[: r // 2]])
+    Vs = np.hstack([Vq, Vq[:, : r // 2]])
+    rr = Us.shape[1]
+    M = Us @ Vs.T
+    U, V = empty(m, rr), empty(n, rr)
+    k = hq.test_recompress(dev(Us), m, dev(Vs), n, rr, 1e-10, rr, U, V, fp32=True)
+    sv = np.linalg.svd(M, compute_uv=False)
+    eff = 4 * np.finfo(np.float32).eps / 2 * np.sqrt(max(m, n)) * sv[0]  # u32 = eps / 2
+    assert int(np.sum(sv > 4 * eff)) <= k <= int(np.sum(sv > eff / 4))
+    Uh, Vh = host(U, m, k), host(V, n, k)
+    assert np.linalg.norm(Uh @ Vh.T - M, 2) <= 4 * eff
 
 
 @pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (120, 90)])

@@ -120,3 +120,35 @@ def test_batched_reports_failed_member():
     assert st == 1 and Ps[1] is None and Ps[0] is not None
     Pd = oh.to_dense(Ps[0].export())
     assert np.linalg.norm(Pd - ref.Pi, 2) <= GATE
+
+
+MIXED_CASES = [
+    ("tri-1024-leaf64", lambda: w.tridiag_uniform(1024, 0), 1, 64),
+    ("band8-2048-leaf128", lambda: w.banded_normal(2048, 8, 0), 8, 128),
+    ("metallic-777", lambda: w.tridiag_metallic(777, 2), 1, 64),
+]
+# Stated bound for the mixed mode.  FP32 iterations truncate every block at its FP32 noise level
+# 4 u32 sqrt(rows) sigma_1; the part of that perturbation that couples eigenvectors on opposite sides
+# of mu rotates the invariant subspace, and no later (FP64) iteration undoes a rotation, so the
+# error grows like (levels) x (noise level of the largest blocks), times the FP32 iterations.
+def mixed_bound(n, levels, fp32_iters):
+    return 2.0 * fp32_iters * levels * 4 * 2.0 ** -24 * np.sqrt(n / 2)
+
+
+@pytest.mark.parametrize("name,maker,b,leaf", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_precision_projector(name, maker, b, leaf):
+    """Mixed mode: middle iterations in FP32.  The error against the oracle is reported and held to
+    the stated mixed-mode bound; the FP32 iterations are the ones the schedule allows."""
+    ab = maker()
+    n = ab.shape[0]
+    ref = eig.spectral_projector(ab, nu=n // 2)
+    P, info = hq.spectral_projector(_dev_band(ab), b, ref.mu, leaf=leaf, tol=1e-10, precision="mixed")
+    D = oh.to_dense(P.export()) - ref.Pi
+    err2 = norms.lanczos_norm(lambda x: D @ x, n, steps=min(n, 80))
+    K = info["iters"]
+    want = [1 if (0 < k < K - 1 and info["c"][k] <= 16.0) else 0 for k in range(K)]
+    print(f"mixed {name}: n={n} gap={ref.gap:.3e} K={K} fp32 iterations={info['fp32_iter']} ||P-Pi||_2={err2:.3e}")
+    assert info["fp32_iter"] == want and sum(want) >= 1
+    bound = mixed_bound(n, info["levels"], sum(want))
+    print(f"    stated mixed-mode bound {bound:.2e}")
+    assert err2 <= bound
