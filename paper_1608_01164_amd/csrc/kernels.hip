@@ -7,6 +7,8 @@
 #include <cfloat>
 #include <cmath>
 #include <mutex>
+#include <stdexcept>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -97,10 +99,18 @@ static __device__ __forceinline__ void count_work(int cls, unsigned long long fl
   }
 }
 
+// A launch that the runtime rejects (resources, dimensions) must not pass silently: later kernels
+// would read outputs that were never written.
+static void check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
+}
+
 #define HQ_TIMED(cls, stream, ...)            \
   do {                                        \
     const int slot_ = prof_begin(stream);     \
     __VA_ARGS__;                              \
+    check_launch(#cls);                       \
     prof_end(slot_, cls, stream);             \
   } while (0)
 
@@ -321,6 +331,7 @@ __global__ void k_scale_cols(double* p, int ld, int rows, const int* wp, double 
 }
 void launch_scale_cols(double* p, int ld, int rows, const int* wp, double scale, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_cols, dim3(64), dim3(256), 0, s, p, ld, rows, wp, scale);
+  check_launch("scale_cols");
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -331,7 +342,7 @@ void launch_scale_cols(double* p, int ld, int rows, const int* wp, double scale,
 constexpr int QR_THREADS = 1024;
 constexpr int QR_WAVES = QR_THREADS / 64;
 constexpr int QR_RMAX = 1024;
-constexpr int QR_LDS_BYTES = 131072;  // dynamic LDS of a TSQR stage (128 KiB)
+constexpr int QR_LDS_BYTES = 153600;  // dynamic LDS of a TSQR stage: 150 KiB (160 KiB minus the static arrays)
 
 template <typename T>
 static __device__ __forceinline__ T wave_max(T v) {
@@ -461,6 +472,173 @@ static __device__ void householder_rows(T* X, int ld, int h, int r) {
   if (tid == 0) count_work(K_QR, flops, 0);
 }
 
+// Blocked Householder (compact WY) for panels held in global memory: NB columns at a time are
+// staged in LDS and factored there; the block reflector H_1..H_nb = I - V T V^T (T upper
+// triangular) then updates every trailing column with one read and one write of it
+// (w = V^T a, y = T^T w, a -= V y), instead of one pass per column.
+constexpr int QR_NB = 8;
+
+template <typename T>
+static __device__ void householder_rows_blocked(T* X, int ld, int h, int r, T* Vl) {
+  // block width: 6 columns in FP64, 8 in FP32 (the most that stay in 128 registers)
+  constexpr int NB = std::is_same<T, double>::value ? 6 : QR_NB;
+  __shared__ T Tm[QR_NB * QR_NB];  // Tm[q * QR_NB + a] = T(a, q)
+  __shared__ T v0s[QR_NB], taus[QR_NB];
+  __shared__ T gram[QR_NB * QR_NB];
+  __shared__ T red[QR_WAVES];
+  __shared__ T sh_v0, sh_tau, sh_beta;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jend = (h - 1 < r) ? h - 1 : r;
+  unsigned long long flops = 0;
+  for (int j0 = 0; j0 < jend; j0 += NB) {
+    const int nb = jend - j0 < NB ? jend - j0 : NB;
+    const int hp = h - j0;  // panel rows j0..h-1
+    // (a) stage the panel columns j0..j0+nb-1, rows j0.. into LDS, row-major: (i, c) at i * NB + c
+    for (int idx = tid; idx < hp * nb; idx += QR_THREADS) {
+      const int c = idx / hp, i = idx - c * hp;
+      Vl[(size_t)i * NB + c] = X[(j0 + i) + (size_t)(j0 + c) * ld];
+    }
+    __syncthreads();
+    // (b) unblocked Householder on the LDS panel
+    for (int jj = 0; jj < nb; ++jj) {
+      T* vj = Vl + jj;  // column jj, stride NB
+      T s = 0;
+      for (int i = jj + 1 + tid; i < hp; i += QR_THREADS) s += vj[i * NB] * vj[i * NB];
+      s = block_reduce<false>(s, red);
+      T unscale = 1;
+      if (s < Prec<T>::scale_below) {  // tiny column: exact power-of-two rescaling first (see householder_rows)
+        T am = 0;
+        for (int i = jj + tid; i < hp; i += QR_THREADS) am = fmax(am, fabs(vj[i * NB]));
+        am = block_reduce<true>(am, red);
+        s = 0;
+        if (am > 0) {
+          constexpr int M = Prec<T>::max_shift;
+          const int e = ilogb(am);
+          const T sc1 = ldexp((T)1, -e > M ? M : -e), sc2 = ldexp((T)1, -e > M ? -e - M : 0);
+          unscale = ldexp((T)1, e);
+          T ss = 0;
+          for (int i = jj + tid; i < hp; i += QR_THREADS) {
+            const T x = (vj[i * NB] * sc1) * sc2;
+            vj[i * NB] = x;
+            if (i > jj) ss += x * x;
+          }
+          s = block_reduce<false>(ss, red);
+        }
+      }
+      if (tid == 0) {
+        const T x0 = vj[jj * NB];
+        if (s == 0) {
+          sh_tau = 0;
+          sh_v0 = 0;
+          sh_beta = x0 * unscale;
+        } else {
+          const T nrm = sqrt(x0 * x0 + s);
+          const T beta = x0 >= 0 ? -nrm : nrm;
+          sh_v0 = x0 - beta;
+          sh_tau = (T)1 / (nrm * (nrm + fabs(x0)));
+          sh_beta = beta * unscale;
+        }
+      }
+      __syncthreads();
+      const T tau = sh_tau, v0 = sh_v0;
+      // columns jj+1..nb-1 of the panel, one per wave
+      for (int c = jj + 1 + wave; c < nb; c += QR_WAVES) {
+        if (tau == 0) break;
+        T* col = Vl + c;
+        T w = lane == 0 ? v0 * col[jj * NB] : (T)0;
+        for (int i = jj + 1 + lane; i < hp; i += 64) w += vj[i * NB] * col[i * NB];
+        w = wave_sum(w) * tau;
+        if (lane == 0) col[jj * NB] -= w * v0;
+        for (int i = jj + 1 + lane; i < hp; i += 64) col[i * NB] -= w * vj[i * NB];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        v0s[jj] = sh_v0;
+        taus[jj] = sh_tau;
+        vj[jj * NB] = sh_beta;  // R's diagonal; the reflector head lives in v0s
+      }
+      __syncthreads();
+    }
+    // (c) Gram of the reflectors (unit structure: v_q = [0..0, v0s[q], V(q+1.., q)])
+    for (int pq = wave; pq < nb * nb; pq += QR_WAVES) {
+      const int a = pq / nb, q = pq - a * nb;
+      if (a >= q) continue;  // T needs v_a^T v_q for a < q
+      // rows > q: both are stored; row q: v_a(q) * v0s[q]
+      T g = lane == 0 ? Vl[q * NB + a] * v0s[q] : (T)0;
+      for (int i = q + 1 + lane; i < hp; i += 64) g += Vl[i * NB + a] * Vl[i * NB + q];
+      g = wave_sum(g);
+      if (lane == 0) gram[q * QR_NB + a] = g;
+    }
+    __syncthreads();
+    if (tid == 0) {  // T(q, q) = tau_q; T(0:q, q) = -tau_q T(0:q, 0:q) (V_{0:q}^T v_q)
+      for (int q = 0; q < nb; ++q) {
+        Tm[q * QR_NB + q] = taus[q];
+        for (int a = 0; a < q; ++a) {
+          T acc = 0;
+          for (int c = a; c < q; ++c) acc += Tm[c * QR_NB + a] * gram[q * QR_NB + c];
+          Tm[q * QR_NB + a] = -taus[q] * acc;
+        }
+      }
+    }
+    // (d) panel back to global: R rows and the reflector entries below them
+    for (int idx = tid; idx < hp * nb; idx += QR_THREADS) {
+      const int c = idx / hp, i = idx - c * hp;
+      X[(j0 + i) + (size_t)(j0 + c) * ld] = Vl[(size_t)i * NB + c];
+    }
+    __syncthreads();
+    // (e) trailing columns: a <- (I - V T V^T)^T a = a - V (T^T (V^T a)), one column per wave
+    for (int c = j0 + nb + wave; c < r; c += QR_WAVES) {
+      T* col = X + (size_t)c * ld + j0;  // rows j0..h-1
+      // rows below nb hold full reflector columns; the first nb rows the unit-triangular head
+      T w[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) w[q] = 0;
+      if (lane < nb) {
+        const T x = col[lane];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < nb) w[q] += (lane > q ? Vl[lane * NB + q] : (lane == q ? v0s[q] : (T)0)) * x;
+      }
+      for (int i = nb + lane; i < hp; i += 64) {
+        const T x = col[i];
+        const T* vr = Vl + (size_t)i * NB;
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < nb) w[q] += vr[q] * x;
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) w[q] = wave_sum(w[q]);
+#pragma unroll
+      for (int q = NB - 1; q >= 0; --q) {  // w <- T^T w in place (T upper triangular: y_q uses w_0..w_q)
+        T acc = 0;
+#pragma unroll
+        for (int a = 0; a <= q; ++a) acc += Tm[q * QR_NB + a] * w[a];
+        w[q] = q < nb ? acc : (T)0;
+      }
+      if (lane < nb) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < nb) acc += (lane > q ? Vl[lane * NB + q] : (lane == q ? v0s[q] : (T)0)) * w[q];
+        col[lane] -= acc;
+      }
+      for (int i = nb + lane; i < hp; i += 64) {
+        const T* vr = Vl + (size_t)i * NB;
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < nb) acc += vr[q] * w[q];
+        col[i] -= acc;
+      }
+    }
+    if (tid == 0)
+      for (int jj = 0; jj < nb; ++jj)
+        flops += 2ull * (hp - jj) + 4ull * (unsigned long long)(hp - jj) * (r - j0 - jj - 1);
+    __syncthreads();
+  }
+  if (tid == 0) count_work(K_QR, flops, 0);
+}
+
 // rows covered by slot a after stage s, capped at r
 static __device__ __forceinline__ int slot_live_rows(int a, int s, int h0, int rows, int r) {
   long long end = (long long)(a + (1 << s)) * h0;
@@ -541,7 +719,10 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
       X[(ra + i) + (size_t)c * ldx] = (i <= c) ? src1[i + (size_t)c * Tk.hs] : (T)0;
     }
   __syncthreads();
-  householder_rows<T>(X, ldx, h, r);
+  if (inl || (size_t)h * QR_NB > (size_t)kLds)
+    householder_rows<T>(X, ldx, h, r);
+  else
+    householder_rows_blocked<T>(X, ldx, h, r, qlds);  // panel in global memory, LDS holds the block reflector
   if (inl) {  // the triangle goes back to the slot
     const int rr = h < r ? h : r;
     for (int idx = tid; idx < rr * r; idx += QR_THREADS) {
@@ -641,6 +822,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   __shared__ int rotated;
   __shared__ unsigned long long sh_pairs, sh_rots;
   if (tid == 0) { sh_pairs = 0; sh_rots = 0; }
+  unsigned my_pairs = 0, my_rots = 0;  // per wave (counted on every lane), summed once at the end
   const unsigned long long c0 = wall_clock64();
   unsigned long long c1 = c0, c2 = c0;
   int nsweeps = 0;
@@ -811,48 +993,72 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < tp - 1; ++round) {
-      for (int pi = wave; pi < tp / 2; pi += SVD_WAVES) {
-        const int x = pi, y = tp - 1 - pi;
-        int p = (x == 0) ? 0 : 1 + ((x - 1 + round) % (tp - 1));
-        int q = (y == 0) ? 0 : 1 + ((y - 1 + round) % (tp - 1));
-        if (p >= t || q >= t) continue;
-        if (p > q) { const int tt = p; p = q; q = tt; }
-        T* cp = C + (size_t)p * ldc;
-        T* cq = C + (size_t)q * ldc;
-        T g = 0;
-        for (int i = lane; i < r; i += 64) g += cp[i] * cq[i];
-        g = wave_sum(g);
-        const T a = nrm2[p], b = nrm2[q];
-        if (lane == 0) atomicAdd(&sh_pairs, 1ull);
-        if (a > Prec<T>::tiny && b > Prec<T>::tiny && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-          if (lane == 0) atomicAdd(&sh_rots, 1ull);
-          const T zeta = (b - a) / ((T)2 * g);
+      // a wave takes the pairs pi and pi + SVD_WAVES of this round together, so that their
+      // reductions and memory latencies overlap (all branches below are uniform over the wave)
+      for (int pi0 = wave; pi0 < tp / 2; pi0 += 2 * SVD_WAVES) {
+        int P[2], Q[2];
+        bool live[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int pi = pi0 + u * SVD_WAVES;
+          const int x = pi, y = tp - 1 - pi;
+          int px = x - 1 + round, qy = y - 1 + round;  // (x - 1 + round) mod (tp - 1), both < 2 (tp - 1)
+          if (px >= tp - 1) px -= tp - 1;
+          if (qy >= tp - 1) qy -= tp - 1;
+          int pp = (x == 0) ? 0 : 1 + px, qq = (y == 0) ? 0 : 1 + qy;
+          if (pp > qq) { const int w0 = pp; pp = qq; qq = w0; }
+          P[u] = pp;
+          Q[u] = qq;
+          live[u] = pi < tp / 2 && qq < t;
+        }
+        T g[2] = {0, 0};
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (live[u]) {
+            const T* cp = C + (size_t)P[u] * ldc;
+            const T* cq = C + (size_t)Q[u] * ldc;
+            for (int i = lane; i < r; i += 64) g[u] += cp[i] * cq[i];
+          }
+        g[0] = wave_sum(g[0]);
+        g[1] = wave_sum(g[1]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (!live[u]) continue;
+          ++my_pairs;
+          const int pp = P[u], qq = Q[u];
+          const T a = nrm2[pp], b = nrm2[qq], gg = g[u];
+          // rotate when |g| > tol sqrt(a b), tested without square roots
+          if (!(a > Prec<T>::tiny && b > Prec<T>::tiny && gg * gg > tol * tol * a * b)) continue;
+          ++my_rots;
+          const T zeta = (b - a) / ((T)2 * gg);
           const T tt = (zeta >= 0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
-          const T cs = (T)1 / sqrt((T)1 + tt * tt), sn = cs * tt;
+          const T cs = rsqrt((T)1 + tt * tt), sn = cs * tt;
+          T* cp = C + (size_t)pp * ldc;
+          T* cq = C + (size_t)qq * ldc;
           T na = 0, nb = 0;
           for (int i = lane; i < r; i += 64) {
-            const T u = cp[i], w = cq[i];
-            const T u2 = cs * u - sn * w, w2 = sn * u + cs * w;
+            const T uu = cp[i], w = cq[i];
+            const T u2 = cs * uu - sn * w, w2 = sn * uu + cs * w;
             cp[i] = u2;
             cq[i] = w2;
             na += u2 * u2;
             nb += w2 * w2;
           }
-          T ea = a - tt * g, eb = b + tt * g;  // exact-arithmetic norms after the rotation
-          if (!(ea > 0.25 * a) || !(eb > 0.25 * b)) {  // cancellation: take the computed ones
+          T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
+          if (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b)) {  // cancellation: take the computed ones
             ea = wave_sum(na);
             eb = wave_sum(nb);
           }
-          T* jp = J + (size_t)p * ldj;
-          T* jq = J + (size_t)q * ldj;
+          T* jp = J + (size_t)pp * ldj;
+          T* jq = J + (size_t)qq * ldj;
           for (int i = lane; i < t; i += 64) {
-            const T u = jp[i], w = jq[i];
-            jp[i] = cs * u - sn * w;
-            jq[i] = sn * u + cs * w;
+            const T uu = jp[i], w = jq[i];
+            jp[i] = cs * uu - sn * w;
+            jq[i] = sn * uu + cs * w;
           }
           if (lane == 0) {
-            nrm2[p] = ea;
-            nrm2[q] = eb;
+            nrm2[pp] = ea;
+            nrm2[qq] = eb;
             rotated = 1;
           }
         }
@@ -864,6 +1070,10 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     __syncthreads();
   }
   c2 = wall_clock64();
+  if (lane == 0 && my_pairs) {
+    atomicAdd(&sh_pairs, (unsigned long long)my_pairs);
+    atomicAdd(&sh_rots, (unsigned long long)my_rots);
+  }
   // ---- phase 3: singular values (column norms of C J), order, truncation
   T* sig2 = cn;
   for (int c = wave; c < t; c += SVD_WAVES) {
@@ -1041,10 +1251,11 @@ __global__ __launch_bounds__(512) void k_chol_inv(const LeafTask* __restrict__ t
     const double inv = 1.0 / piv;
     for (int i = j + 1 + tid; i < m; i += 512) S[i + j * m] *= inv;
     __syncthreads();
-    const int w = m - j - 1;
-    for (int idx = tid; idx < w * w; idx += 512) {
-      const int i = j + 1 + idx % w, c = j + 1 + idx / w;
-      if (c <= i) S[i + c * m] -= S[i + j * m] * S[c + j * m];
+    // trailing update of the lower triangle: one column per wave, rows over lanes
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int c = j + 1 + wave; c < m; c += 8) {
+      const double lc = S[c + j * m];
+      for (int i = c + lane; i < m; i += 64) S[i + c * m] -= S[i + j * m] * lc;
     }
     __syncthreads();
   }
@@ -1114,17 +1325,26 @@ __global__ void k_copy_int(int* d, const int* s, int n) {
   if (i < n) d[i] = s[i];
 }
 void launch_fill_int(int* p, int value, int count, hipStream_t s) {
-  if (count > 0) hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, s, p, value, count);
+  if (count > 0) {
+    hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, s, p, value, count);
+    check_launch("fill_int");
+  }
 }
 void launch_copy_int(int* dst, const int* src, int count, hipStream_t s) {
-  if (count > 0) hipLaunchKernelGGL(k_copy_int, dim3((count + 255) / 256), dim3(256), 0, s, dst, src, count);
+  if (count > 0) {
+    hipLaunchKernelGGL(k_copy_int, dim3((count + 255) / 256), dim3(256), 0, s, dst, src, count);
+    check_launch("copy_int");
+  }
 }
 __global__ void k_copy_ints(const IntCopy* __restrict__ list, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) *list[i].d = *list[i].s;
 }
 void launch_copy_ints(const IntCopy* d_list, int n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_copy_ints, dim3((n + 255) / 256), dim3(256), 0, s, d_list, n);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_copy_ints, dim3((n + 255) / 256), dim3(256), 0, s, d_list, n);
+    check_launch("copy_ints");
+  }
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -1153,6 +1373,7 @@ void launch_band_leaves(BandDesc bd, double* leaves, int ldl, const int64_t* d_l
                         int nleaves, hipStream_t s) {
   hipLaunchKernelGGL(k_band_leaves, dim3((ldl * ldl + 255) / 256, nleaves), dim3(256), 0, s, bd, leaves, ldl,
                      d_leaf_lo, d_leaf_m);
+  check_launch("band_leaves");
 }
 
 __global__ __launch_bounds__(256) void k_band_blocks(BandDesc bd, const BandBlockTask* __restrict__ tasks) {
@@ -1181,6 +1402,7 @@ void launch_band_blocks(BandDesc bd, const BandBlockTask* d_tasks, int ntasks, i
   if (ntasks <= 0) return;
   const int bx = (max_rows * bd.b + 255) / 256;
   hipLaunchKernelGGL(k_band_blocks, dim3(bx, ntasks), dim3(256), 0, s, bd, d_tasks);
+  check_launch("band_blocks");
 }
 
 }  // namespace hq

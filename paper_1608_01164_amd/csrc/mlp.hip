@@ -6,11 +6,19 @@
 // Loss: sum_{i,o} w_io (y_io - t_io)^2 / sum w  (weighted squared error, w = 0 masks an entry).
 #include <hip/hip_runtime.h>
 
+#include <stdexcept>
+#include <string>
+
 #include "mlp.h"
 
 namespace hq {
 
 namespace {
+void check_launch() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("predictor kernel launch failed: ") + hipGetErrorString(e));
+}
+
 constexpr int F = kMlpFeatures, H = kMlpHidden, O = kMlpOutputs, P = kMlpParams;
 constexpr int kW1 = 0, kB1 = kW1 + H * F, kW2 = kB1 + H, kB2 = kW2 + H * H, kW3 = kB2 + H, kB3 = kW3 + O * H;
 static_assert(kB3 + O == P, "parameter layout");
@@ -194,6 +202,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ params, fl
 void launch_mlp_forward(const float* params, const float* X, const float* prev, float* Y, int64_t rows, hipStream_t s) {
   if (rows <= 0) return;
   hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, params, X, prev, Y, rows);
+  check_launch();
 }
 
 int mlp_groups(int64_t rows) { return (int)((rows + kRowsPerGroup - 1) / kRowsPerGroup); }
@@ -204,11 +213,13 @@ void launch_mlp_grad(const float* params, const float* X, const float* T, const 
   if (g <= 0) return;
   hipLaunchKernelGGL(k_mlp_grad, dim3(g), dim3(kRowsPerGroup), 0, s, params, X, T, W, rows, inv_wsum, part);
   hipLaunchKernelGGL(k_mlp_reduce, dim3((P + 1 + 255) / 256), dim3(256), 0, s, part, g, grad);
+  check_launch();
 }
 
 void launch_mlp_adam(float* params, float* m, float* v, const float* grad, float lr, int step, hipStream_t s) {
   const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
   hipLaunchKernelGGL(k_mlp_adam, dim3((P + 255) / 256), dim3(256), 0, s, params, m, v, grad, lr, c1, c2);
+  check_launch();
 }
 
 }  // namespace hq

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -150,8 +151,11 @@ hq_status hq_predictor_forward(hq_predictor_t p, const float* X, int64_t rows, f
   if (!p || rows < 0) return pfail(HQ_ERR_ARG, "bad arguments");
   if (rows == 0) return HQ_OK;
   if (!X || !Y) return pfail(HQ_ERR_ARG, "X or Y is NULL");
-  hq::launch_mlp_forward(p->d_params, X, nullptr, Y, rows, (hipStream_t)stream);
-  if (!ok(hipGetLastError())) return pfail(HQ_ERR_DEVICE, "forward launch failed");
+  try {
+    hq::launch_mlp_forward(p->d_params, X, nullptr, Y, rows, (hipStream_t)stream);
+  } catch (const std::exception& e) {
+    return pfail(HQ_ERR_DEVICE, e.what());
+  }
   return HQ_OK;
 }
 
@@ -163,7 +167,11 @@ hq_status hq_predictor_loss_grad(hq_predictor_t p, const float* X, const float* 
   if (!weight_sum(W, rows, st, wsum)) return pfail(HQ_ERR_DEVICE, "weight readback failed");
   if (!(wsum > 0.0)) return pfail(HQ_ERR_ARG, "all weights are zero");
   if (!ensure_part(p, rows)) return pfail(HQ_ERR_ALLOC, "workspace allocation failed");
-  hq::launch_mlp_grad(p->d_params, X, T, W, rows, (float)(1.0 / wsum), p->d_part, p->d_grad, st);
+  try {
+    hq::launch_mlp_grad(p->d_params, X, T, W, rows, (float)(1.0 / wsum), p->d_part, p->d_grad, st);
+  } catch (const std::exception& e) {
+    return pfail(HQ_ERR_DEVICE, e.what());
+  }
   if (!ok(hipMemcpyAsync(grad, p->d_grad, sizeof(float) * hq::kMlpParams, hipMemcpyDeviceToDevice, st)) ||
       !ok(hipMemcpyAsync(loss, p->d_grad + hq::kMlpParams, sizeof(float), hipMemcpyDeviceToHost, st)) ||
       !ok(hipStreamSynchronize(st)))
@@ -179,9 +187,14 @@ hq_status hq_predictor_train(hq_predictor_t p, const float* X, const float* T, c
   if (!weight_sum(W, rows, st, wsum)) return pfail(HQ_ERR_DEVICE, "weight readback failed");
   if (!(wsum > 0.0)) return pfail(HQ_ERR_ARG, "all weights are zero");
   if (!ensure_part(p, rows)) return pfail(HQ_ERR_ALLOC, "workspace allocation failed");
-  for (int e = 0; e < epochs; ++e) {
-    hq::launch_mlp_grad(p->d_params, X, T, W, rows, (float)(1.0 / wsum), p->d_part, p->d_grad, st);
-    hq::launch_mlp_adam(p->d_params, p->d_m, p->d_v, p->d_grad, lr, (int)(++p->step), st);
+  try {
+    for (int e = 0; e < epochs; ++e) {
+      hq::launch_mlp_grad(p->d_params, X, T, W, rows, (float)(1.0 / wsum), p->d_part, p->d_grad, st);
+      hq::launch_mlp_adam(p->d_params, p->d_m, p->d_v, p->d_grad, lr, (int)(++p->step), st);
+    }
+  } catch (const std::exception& ex) {
+    (void)hipStreamSynchronize(st);
+    return pfail(HQ_ERR_DEVICE, ex.what());
   }
   float l = 0.0f;
   if (!ok(hipMemcpyAsync(&l, p->d_grad + hq::kMlpParams, sizeof(float), hipMemcpyDeviceToHost, st)) ||
