@@ -806,15 +806,21 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     }
     dfs(left);
     // off-diagonal factor L_ba = (Z_ba - S_b S_a^T) L_aa^{-T}, and the Schur factor of the right child
+    // A right child that is a leaf only needs S S^T for its dense update: there the stacked factor
+    // [S_b, L_ba's U] is passed on as it is (exact, and one TSQR + core SVD fewer on the critical path).
     const int ni = (int)inner.size();
     std::vector<double*> Snew(ni);
     std::vector<int*> rnew(ni);
     std::vector<int> capSb(ni);
+    std::vector<char> raw(ni);
     for (int i = 0; i < ni; ++i) {
       const Item& it = inner[i];
-      const Tree* t = batch[it.m].Z->t;
+      const CholTask& T = batch[it.m];
+      const Tree* t = T.Z->t;
       const int64_t sb = t->size(2 * it.c + 2);
-      capSb[i] = std::min<int>({(int)sb, batch[it.m].capS, kMaxStack});
+      raw[i] = t->is_leaf(2 * it.c + 2);
+      capSb[i] = raw[i] ? std::min(kMaxStack, it.S.cap + T.Lf->cap[Tree::level(it.c)])
+                        : std::min<int>({(int)sb, T.capS, kMaxStack});
       Snew[i] = scratch.get<double>((size_t)sb * capSb[i]);
       rnew[i] = scratch.get<int>(1);
     }
@@ -857,14 +863,14 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         r.thresh = tol; r.fidx = T.fidx;
         rec.push_back(r);
         const int rcS = std::min(kMaxStack, S.cap + T.Lf->cap[l]);
-        double* Sraw = scratch.get<double>((size_t)sb * rcS);
-        int* rsb = scratch.get<int>(1);
+        double* Sraw = raw[i] ? Snew[i] : scratch.get<double>((size_t)sb * rcS);
+        int* rsb = raw[i] ? rnew[i] : scratch.get<int>(1);
         StackTask ss{};
         ss.dst = Sraw; ss.ld = (int)sb; ss.rows = (int)sb; ss.wcap = rcS; ss.wout = rsb; ss.nsrc = 2; ss.fidx = T.fidx;
         ss.src[0] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
         ss.src[1] = {T.Lf->U(p, 1), T.Lf->rk(p, 1), ldc, T.Lf->cap[l], 1.0};
         stk2.push_back(ss);
-        sym.push_back(SymTask{Sraw, (int)sb, (int)sb, rsb, rcS, Snew[i], (int)sb, rnew[i], capSb[i], thS, T.fidx});
+        if (!raw[i]) sym.push_back(SymTask{Sraw, (int)sb, (int)sb, rsb, rcS, Snew[i], (int)sb, rnew[i], capSb[i], thS, T.fidx});
       }
       stack(stk, maxrows);
       mm_thin(th);
