@@ -1229,49 +1229,63 @@ __global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ task
 constexpr int CI_MAX = 128;
 __global__ __launch_bounds__(512) void k_chol_inv(const LeafTask* __restrict__ tasks, int* flag) {
   const LeafTask T = tasks[blockIdx.x];
-  const int m = T.m, tid = threadIdx.x;
+  const int m = T.m, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // 8 waves
   extern __shared__ double S[];  // m x m, ld = m
   for (int idx = tid; idx < m * m; idx += 512) {
     const int i = idx % m, c = idx / m;
     S[i + c * m] = (i >= c) ? T.A[i + (size_t)c * T.lda] : 0.0;
   }
   __syncthreads();
-  __shared__ double piv;
+  // Cholesky, one barrier per column: the trailing update uses the unscaled pivot column
+  // (a_ic -= a_ij a_cj / d), and column j is scaled by 1/sqrt(d) one step later, when no
+  // thread reads it any more.
+  __shared__ double diag[CI_MAX];  // L's diagonal, kept apart from the in-place inverse below
+  double dprev = 1.0;
   for (int j = 0; j < m; ++j) {
-    if (tid == 0) {
-      double d = S[j + j * m];
-      if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
-        atomicOr(flag + T.fidx, 2);
-        d = 1.0;
-      }
-      piv = sqrt(d);
-      S[j + j * m] = piv;
+    double d = S[j + j * m];
+    if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
+      if (tid == 0) atomicOr(flag + T.fidx, 2);
+      d = 1.0;
     }
-    __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int i = j + 1 + tid; i < m; i += 512) S[i + j * m] *= inv;
-    __syncthreads();
-    // trailing update of the lower triangle: one column per wave, rows over lanes
-    const int lane = tid & 63, wave = tid >> 6;
+    const double inv_d = 1.0 / d;
     for (int c = j + 1 + wave; c < m; c += 8) {
-      const double lc = S[c + j * m];
-      for (int i = c + lane; i < m; i += 64) S[i + c * m] -= S[i + j * m] * lc;
+      const double f = S[c + j * m] * inv_d;
+      for (int i = c + lane; i < m; i += 64) S[i + c * m] -= S[i + j * m] * f;
     }
+    if (j > 0) {  // deferred scaling of column j - 1
+      const double rs = 1.0 / sqrt(dprev);
+      for (int i = j + tid; i < m; i += 512) S[i + (j - 1) * m] *= rs;
+      if (tid == 0) {
+        S[(j - 1) + (j - 1) * m] = sqrt(dprev);
+        diag[j - 1] = sqrt(dprev);
+      }
+    }
+    dprev = d;
     __syncthreads();
   }
-  // in-place inverse of the lower triangle, columns from the right:
-  // X_jj = 1/L_jj;  X_{j+1:, j} = -X_jj * X_{j+1:, j+1:} L_{j+1:, j}
-  __shared__ double col[CI_MAX];
-  for (int j = m - 1; j >= 0; --j) {
-    const double xjj = 1.0 / S[j + j * m];
-    for (int i = j + 1 + tid; i < m; i += 512) {
-      double acc = 0.0;
-      for (int k = j + 1; k <= i; ++k) acc += S[i + k * m] * S[k + j * m];
-      col[i] = -xjj * acc;
+  {
+    const double rs = 1.0 / sqrt(dprev);
+    for (int i = m + tid; i < m; i += 512) S[i + (m - 1) * m] *= rs;  // no rows below the last column
+    if (tid == 0) {
+      S[(m - 1) + (m - 1) * m] = sqrt(dprev);
+      diag[m - 1] = sqrt(dprev);
     }
+    (void)rs;
+  }
+  __syncthreads();
+  // X = L^{-1} in place by right-looking elimination on [L | I]: at step j, row j of X is
+  // finished (scaled by 1/L_jj), then every row i > j subtracts L_ij times it; X_ij takes the
+  // place of L_ij, which is staged first because step j is the last to read it.
+  __shared__ double colL[CI_MAX];  // column j of L below the diagonal, staged before X overwrites it
+  for (int j = 0; j < m; ++j) {
+    const double xjj = 1.0 / diag[j];
+    for (int c = tid; c <= j; c += 512) S[j + c * m] = (c == j) ? xjj : S[j + c * m] * xjj;
+    for (int i = j + 1 + tid; i < m; i += 512) colL[i] = S[i + j * m];
     __syncthreads();
-    for (int i = j + 1 + tid; i < m; i += 512) S[i + j * m] = col[i];
-    if (tid == 0) S[j + j * m] = xjj;
+    for (int c = wave; c <= j; c += 8) {  // columns over waves, rows over lanes
+      const double x = S[j + c * m];
+      for (int i = j + 1 + lane; i < m; i += 64) S[i + c * m] = (c == j ? 0.0 : S[i + c * m]) - colL[i] * x;
+    }
     __syncthreads();
   }
   for (int idx = tid; idx < m * m; idx += 512) {
