@@ -159,6 +159,23 @@ static __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sum over a group of 16 consecutive lanes, returned to every lane of the group (groups stay
+// independent): butterfly exchanges of width 16.
+static __device__ __forceinline__ double row_sum(double v) {
+  v += __shfl_xor(v, 1, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 8, 16);
+  return v;
+}
+static __device__ __forceinline__ float row_sum(float v) {
+  v += __shfl_xor(v, 1, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 8, 16);
+  return v;
+}
+
 // Precision traits of the recompression kernels.
 template <typename T> struct Prec;
 template <> struct Prec<double> {
@@ -900,40 +917,27 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
       __syncthreads();
       vcol = vl;
     }
-    for (int cc = j + 1 + 4 * wave; cc < r; cc += 4 * SVD_WAVES) {
-      const int nc = r - cc < 4 ? r - cc : 4;
-      T* col[4];
-      T w[4] = {0, 0, 0, 0}, nn[4] = {0, 0, 0, 0};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) col[q] = Bm + (size_t)(q < nc ? cc + q : cc) * ldb;
-      if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w[q] = vj * col[q][j];
-      }
-      for (int i = j + 1 + lane; i < r; i += 64) {
-        const T vi = vcol[i];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w[q] += vi * col[q][i];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = wave_sum(w[q]) * tj;
-      if (lane == 0)
-        for (int q = 0; q < nc; ++q) col[q][j] -= w[q] * vj;
-      for (int i = j + 1 + lane; i < r; i += 64) {
-        const T vi = vcol[i];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q < nc) {
-            const T x = col[q][i] - w[q] * vi;
-            col[q][i] = x;
-            nn[q] += x * x;
-          }
+    // trailing columns: four per wave, one per group of 16 lanes; uniform control flow around the
+    // row reductions, invalid rows predicated off
+    {
+      const int sub = lane >> 4, sl = lane & 15;
+      for (int cc = j + 1 + 4 * wave; cc < r; cc += 4 * SVD_WAVES) {
+        const int c = cc + sub;
+        const bool valid = c < r;
+        T* col = Bm + (size_t)(valid ? c : cc) * ldb;
+        T w = (sl == 0) ? vj * col[j] : (T)0;
+        for (int i = j + 1 + sl; i < r; i += 16) w += vcol[i] * col[i];
+        w = row_sum(w) * tj;
+        if (valid && sl == 0) col[j] -= w * vj;
+        T nn = 0;
+        for (int i = j + 1 + sl; i < r; i += 16) {
+          const T x = col[i] - w * vcol[i];
+          if (valid) col[i] = x;
+          nn += x * x;
         }
+        nn = row_sum(nn);
+        if (valid && sl == 0) cn[c] = nn;  // exact trailing norm for the next step
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) nn[q] = wave_sum(nn[q]);
-      if (lane == 0)
-        for (int q = 0; q < nc; ++q) cn[cc + q] = nn[q];  // exact trailing norm for the next step
     }
     __syncthreads();
     if (tid == 0) {
@@ -992,51 +996,43 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     }
     if (tid == 0) rotated = 0;
     __syncthreads();
+    // Each pair of a round gets a group of 16 lanes, four pairs per wave: dot products reduce
+    // inside the row, and up to 4 * SVD_WAVES pairs rotate at once.  All rows of a wave run the
+    // same instructions (row reductions under uniform control flow); a row without a valid pair,
+    // or whose pair needs no rotation, is predicated off.
+    const int sub = lane >> 4, sl = lane & 15;
     for (int round = 0; round < tp - 1; ++round) {
-      // a wave takes the pairs pi and pi + SVD_WAVES of this round together, so that their
-      // reductions and memory latencies overlap (all branches below are uniform over the wave)
-      for (int pi0 = wave; pi0 < tp / 2; pi0 += 2 * SVD_WAVES) {
-        int P[2], Q[2];
-        bool live[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int pi = pi0 + u * SVD_WAVES;
-          const int x = pi, y = tp - 1 - pi;
-          int px = x - 1 + round, qy = y - 1 + round;  // (x - 1 + round) mod (tp - 1), both < 2 (tp - 1)
-          if (px >= tp - 1) px -= tp - 1;
-          if (qy >= tp - 1) qy -= tp - 1;
-          int pp = (x == 0) ? 0 : 1 + px, qq = (y == 0) ? 0 : 1 + qy;
-          if (pp > qq) { const int w0 = pp; pp = qq; qq = w0; }
-          P[u] = pp;
-          Q[u] = qq;
-          live[u] = pi < tp / 2 && qq < t;
+      for (int pi0 = wave * 4; pi0 < tp / 2; pi0 += 4 * SVD_WAVES) {
+        const int pi = pi0 + sub;
+        const int x = pi, y = tp - 1 - pi;
+        int px = x - 1 + round, qy = y - 1 + round;  // (x - 1 + round) mod (tp - 1), both < 2 (tp - 1)
+        if (px >= tp - 1) px -= tp - 1;
+        if (qy >= tp - 1) qy -= tp - 1;
+        int pp = (x == 0) ? 0 : 1 + px, qq = (y == 0) ? 0 : 1 + qy;
+        if (pp > qq) { const int w0 = pp; pp = qq; qq = w0; }
+        const bool valid = pi < tp / 2 && qq < t;
+        if (!valid) { pp = 0; qq = 0; }  // harmless addresses for predicated-off rows
+        T* cp = C + (size_t)pp * ldc;
+        T* cq = C + (size_t)qq * ldc;
+        T gg = 0;
+        if (valid)
+          for (int i = sl; i < r; i += 16) gg += cp[i] * cq[i];
+        gg = row_sum(gg);
+        const T a = nrm2[pp], b = nrm2[qq];
+        // rotate when |g| > tol sqrt(a b), tested without square roots
+        const bool rot = valid && a > Prec<T>::tiny && b > Prec<T>::tiny && gg * gg > tol * tol * a * b;
+        my_pairs += valid && sl == 0;
+        my_rots += rot && sl == 0;
+        T zeta = 0, tt = 0, cs = 1, sn = 0;
+        if (rot) {
+          zeta = (b - a) / ((T)2 * gg);
+          tt = (zeta >= 0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
+          cs = rsqrt((T)1 + tt * tt);
+          sn = cs * tt;
         }
-        T g[2] = {0, 0};
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-          if (live[u]) {
-            const T* cp = C + (size_t)P[u] * ldc;
-            const T* cq = C + (size_t)Q[u] * ldc;
-            for (int i = lane; i < r; i += 64) g[u] += cp[i] * cq[i];
-          }
-        g[0] = wave_sum(g[0]);
-        g[1] = wave_sum(g[1]);
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (!live[u]) continue;
-          ++my_pairs;
-          const int pp = P[u], qq = Q[u];
-          const T a = nrm2[pp], b = nrm2[qq], gg = g[u];
-          // rotate when |g| > tol sqrt(a b), tested without square roots
-          if (!(a > Prec<T>::tiny && b > Prec<T>::tiny && gg * gg > tol * tol * a * b)) continue;
-          ++my_rots;
-          const T zeta = (b - a) / ((T)2 * gg);
-          const T tt = (zeta >= 0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
-          const T cs = rsqrt((T)1 + tt * tt), sn = cs * tt;
-          T* cp = C + (size_t)pp * ldc;
-          T* cq = C + (size_t)qq * ldc;
-          T na = 0, nb = 0;
-          for (int i = lane; i < r; i += 64) {
+        T na = 0, nb = 0;
+        if (rot)
+          for (int i = sl; i < r; i += 16) {
             const T uu = cp[i], w = cq[i];
             const T u2 = cs * uu - sn * w, w2 = sn * uu + cs * w;
             cp[i] = u2;
@@ -1044,19 +1040,23 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
             na += u2 * u2;
             nb += w2 * w2;
           }
-          T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
-          if (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b)) {  // cancellation: take the computed ones
-            ea = wave_sum(na);
-            eb = wave_sum(nb);
-          }
+        T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
+        const bool exact = !(ea > (T)0.25 * a) || !(eb > (T)0.25 * b);  // cancellation: take the computed ones
+        na = row_sum(na);
+        nb = row_sum(nb);
+        if (exact) {
+          ea = na;
+          eb = nb;
+        }
+        if (rot) {
           T* jp = J + (size_t)pp * ldj;
           T* jq = J + (size_t)qq * ldj;
-          for (int i = lane; i < t; i += 64) {
+          for (int i = sl; i < t; i += 16) {
             const T uu = jp[i], w = jq[i];
             jp[i] = cs * uu - sn * w;
             jq[i] = sn * uu + cs * w;
           }
-          if (lane == 0) {
+          if (sl == 0) {
             nrm2[pp] = ea;
             nrm2[qq] = eb;
             rotated = 1;
@@ -1070,7 +1070,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     __syncthreads();
   }
   c2 = wall_clock64();
-  if (lane == 0 && my_pairs) {
+  if ((lane & 15) == 0 && my_pairs) {  // counted on the first lane of each 16-lane group
     atomicAdd(&sh_pairs, (unsigned long long)my_pairs);
     atomicAdd(&sh_rots, (unsigned long long)my_rots);
   }
@@ -1121,15 +1121,20 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   __syncthreads();
   for (int j = t - 1; j >= 0; --j) {
     const double tj = tau[j], vj = vhead[j];
-    if (tj != 0.0) {
+    if (tj != 0.0) {  // uniform: the output columns, one per group of 16 lanes
       const T* vcol = Bm + (size_t)j * ldb;
-      for (int o = wave; o < kk; o += SVD_WAVES) {
-        double* col = Tk.Wk + (size_t)o * Tk.ld;
-        double w = (lane == 0) ? vj * col[j] : 0.0;
-        for (int i = j + 1 + lane; i < r; i += 64) w += vcol[i] * col[i];
-        w = wave_sum(w) * tj;
-        if (lane == 0) col[j] -= w * vj;
-        for (int i = j + 1 + lane; i < r; i += 64) col[i] -= w * vcol[i];
+      const int sub = lane >> 4, sl = lane & 15;
+      for (int o0 = 4 * wave; o0 < kk; o0 += 4 * SVD_WAVES) {
+        const int o = o0 + sub;
+        const bool valid = o < kk;
+        double* col = Tk.Wk + (size_t)(valid ? o : o0) * Tk.ld;
+        double w = (sl == 0) ? vj * col[j] : 0.0;
+        for (int i = j + 1 + sl; i < r; i += 16) w += vcol[i] * col[i];
+        w = row_sum(w) * tj;
+        if (valid) {
+          if (sl == 0) col[j] -= w * vj;
+          for (int i = j + 1 + sl; i < r; i += 16) col[i] -= w * vcol[i];
+        }
       }
     }
     __syncthreads();
