@@ -303,9 +303,9 @@ size_t rec_bytes(int m, int n, int rcap, int kcap) {
 float fp32_floor(int m) { return 4.0f * 5.9604645e-8f * std::sqrt((float)std::max(m, 1)); }
 
 size_t sym_bytes(int m, int rcap, int kcap) {
+  (void)m;
   const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1);
-  const QrPlan a = plan_qr(m, (int)rc);
-  return 8 * (3 * rc * rc + 2 * rc + 2 * rc * kc + (size_t)a.ntiles * a.hs * rc) + 4096;
+  return 8 * (3 * rc * rc + 2 * rc + 2 * rc * kc) + 4096;
 }
 }  // namespace
 
@@ -433,54 +433,47 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
   gemm(gUV, mmax, kmax);
 }
 
+// Symmetric compression through the Gram matrix: G = S^T S (one MFMA GEMM), its singular vectors
+// Y (= eigenvectors) keep sigma(G) > thresh^2, and S' = S Y_k.  Then
+// ||S S^T - S' S'^T|| = ||(I - P_k) G (I - P_k)|| <= thresh^2 + O(u ||G||) whatever the gaps of G,
+// which is all the lazy Schur factor needs (its threshold is far above u^(1/2) ||S||).
 void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
   if (tasks.empty()) return;
   const int nt = (int)tasks.size();
-  std::vector<QrTask> qv;
+  std::vector<GemmTask> gg, go;
   std::vector<SvdTask> sv;
-  std::vector<GemmTask> go;
-  int maxtiles = 1, hsmax = 1, rmax = 1, kmax = 1, mmax = 1;
+  int rmax = 1, kmax = 1, mmax = 1;
   for (int i = 0; i < nt; ++i) {
     const SymTask& T = tasks[i];
     const int rc = std::max(T.rcap, 1);
     if (rc > kMaxStack) throw std::runtime_error("compress_sym: factor capacity above the kernel limit");
-    const QrPlan pl = plan_qr(T.m, rc);
-    double* R = scratch.get<double>((size_t)rc * rc);
+    double* G = scratch.get<double>((size_t)rc * rc);
     double* J = scratch.get<double>((size_t)rc * rc);
     double* Jw = scratch.get<double>((size_t)rc * rc);
     double* aux = scratch.get<double>(2 * (size_t)rc);
     double* Wk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     double* Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
-    QrTask q{};
-    q.M = T.S; q.ldm = T.lds; q.rows = T.m; q.rp = T.r; q.rcap = rc; q.hs = pl.hs; q.h0 = pl.h0;
-    q.ntiles = pl.ntiles; q.work = scratch.get<double>((size_t)pl.ntiles * pl.hs * rc); q.R = R; q.ldr = rc; q.fidx = T.fidx;
-    qv.push_back(q);
-    maxtiles = std::max(maxtiles, pl.ntiles);
-    hsmax = std::max(hsmax, pl.hs);
+    GemmTask g{};  // G = S^T S
+    g.A = T.S; g.opA = 1; g.lda = T.lds; g.B = T.S; g.ldb = T.lds; g.C = G; g.ldc = rc;
+    g.m = g.n = rc; g.mp = g.np = T.r; g.k = T.m; g.alpha = 1.0; g.beta = 0.0;
+    gg.push_back(g);
     rmax = std::max(rmax, rc);
     kmax = std::max(kmax, T.kcap);
     mmax = std::max(mmax, T.m);
     SvdTask s{};
-    s.B = R; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc;
-    s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh; s.fidx = T.fidx;
+    const double th2 = T.thresh * T.thresh;
+    s.B = G; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc;
+    s.kcap = T.kcap; s.thresh = th2; s.qr_thresh = 0.1 * th2; s.fidx = T.fidx;
     s.fp32_floor = fp32_floor(T.m);
     sv.push_back(s);
-    GemmTask g{};  // out = S Jk
-    g.A = T.S; g.lda = T.lds; g.B = Jk; g.ldb = rc; g.C = T.out; g.ldc = T.ldo;
-    g.m = T.m; g.n = T.kcap; g.np = T.rank; g.k = rc; g.kp = T.r; g.alpha = 1.0; g.beta = 0.0;
-    go.push_back(g);
+    GemmTask o{};  // out = S Jk
+    o.A = T.S; o.lda = T.lds; o.B = Jk; o.ldb = rc; o.C = T.out; o.ldc = T.ldo;
+    o.m = T.m; o.n = T.kcap; o.np = T.rank; o.k = rc; o.kp = T.r; o.alpha = 1.0; o.beta = 0.0;
+    go.push_back(o);
   }
-  QrTask* dq = stage.upload(qv, st);
-  int nst = 0;
-  while ((1 << nst) < maxtiles) ++nst;
-  for (int s = 0; s <= nst; ++s) {
-    const int pairs = (maxtiles + (1 << s) - 1) >> s;
-    launch_qr_stage(dq, nt, s, pairs, d_flag, fp32, st);
-    ++launches;
-  }
-  launch_qr_final(dq, nt, d_flag, fp32, st);
+  gemm(gg, rmax, rmax);
   launch_svd(stage.upload(sv, st), nt, d_flag, fp32, st);
-  launches += 2;
+  ++launches;
   gemm(go, mmax, kmax);
 }
 

@@ -1041,12 +1041,14 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
             nb += w2 * w2;
           }
         T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
-        const bool exact = !(ea > (T)0.25 * a) || !(eb > (T)0.25 * b);  // cancellation: take the computed ones
-        na = row_sum(na);
-        nb = row_sum(nb);
-        if (exact) {
-          ea = na;
-          eb = nb;
+        const bool exact = rot && (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b));  // cancellation: computed norms
+        if (__any(exact)) {  // wave-uniform; rare
+          na = row_sum(na);
+          nb = row_sum(nb);
+          if (exact) {
+            ea = na;
+            eb = nb;
+          }
         }
         if (rot) {
           T* jp = J + (size_t)pp * ldj;
