@@ -135,6 +135,13 @@ def lib():
         if not os.path.exists(LIBPATH):
             raise LibraryMissing(f"{LIBPATH} not found: run __graft_entry__.build() or "
                                  "python paper_1608_01164_amd/build.py")
+        # PyTorch wheels carry their own HIP runtime.  Importing torch first makes the library bind to
+        # that same runtime (one runtime per process), so that torch's device pointers and streams are
+        # valid in the library whichever side touches the device first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIBPATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)

@@ -328,6 +328,7 @@ struct Member {
   hq::HMat X, Xn, Z, Linv, Lf, Y, Q1, Q2, P;
   std::vector<int> capX, capZ, capL, capY;  // capacities of X_{k+1}, Z, L and L^{-1}, Y
   std::vector<std::array<std::vector<int>, 4>> pcap;  // predicted capacities per iteration
+  bool pred_miss = false;  // an iteration overflowed its predicted capacities
   hq_hodlr_t out = nullptr;
 };
 
@@ -522,12 +523,29 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
       if (act.size() > 1)
         for (int i : act) ms[i].inf.givens_seconds = secs(tg);
     } else if (o.predictor) {
+      // A member whose predicted capacities overflowed once gets, from then on, at least the
+      // capacities the previous iterate's ranks call for (one rank readback for those members), so
+      // that a predictor that under-estimates a problem costs at most one repeated iteration.
+      std::vector<const hq::HMat*> xs;
+      std::vector<int> miss;
+      for (int i : act)
+        if (ms[i].pred_miss) {
+          xs.push_back(&ms[i].X);
+          miss.push_back(i);
+        }
+      const std::vector<std::vector<int>> rk = xs.empty() ? std::vector<std::vector<int>>() : read_ranks_many(E, xs);
       for (int i : act) {
         Member& m = ms[i];
         m.capX = m.pcap[k][0];
         m.capZ = m.pcap[k][1];
         m.capL = m.pcap[k][2];
         m.capY = m.pcap[k][3];
+      }
+      for (size_t j = 0; j < miss.size(); ++j) {
+        Member& m = ms[miss[j]];
+        const std::vector<int> g = caps_grow(m.t, rk[j], o.max_rank, 2, 16);
+        for (std::vector<int>* cv : {&m.capX, &m.capZ, &m.capL, &m.capY})
+          for (int l = 0; l < m.t.L && l < (int)cv->size(); ++l) (*cv)[l] = std::max((*cv)[l], g[l]);
       }
     } else {
       std::vector<const hq::HMat*> xs;
@@ -660,10 +678,24 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
             continue;
           }
           ++m.inf.redo_count;
+          m.pred_miss = true;
           again.push_back(i);
           continue;
         }
         m.X = m.Xn;
+      }
+      // predicted capacities that overflowed: the repeat also gets at least what X_k's ranks call
+      // for (instead of doubling its way up from a far too small prediction)
+      if (o.predictor && k >= 1 && !again.empty()) {
+        std::vector<const hq::HMat*> xs;
+        for (int i : again) xs.push_back(&ms[i].X);
+        const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+        for (size_t j = 0; j < again.size(); ++j) {
+          Member& m = ms[again[j]];
+          const std::vector<int> g = caps_grow(m.t, rk[j], o.max_rank, 2, 16);
+          for (std::vector<int>* cv : {&m.capX, &m.capZ, &m.capL, &m.capY})
+            for (int l = 0; l < m.t.L && l < (int)cv->size(); ++l) (*cv)[l] = std::max((*cv)[l], g[l]);
+        }
       }
       pend.swap(again);
     }

@@ -293,10 +293,15 @@ QrPlan plan_qr(int m, int rcap) {
 
 namespace {
 // Device workspace of one recompression task (TSQR slots of both sides, cores, outputs).
+// Leading dimension of the core-SVD workspaces: rows padded to a multiple of 16 (the kernel keeps
+// whole 16-row segments of a column in registers).
+int svd_ld(int rc) { return (std::max(rc, 1) + 15) & ~15; }
+
 size_t rec_bytes(int m, int n, int rcap, int kcap) {
-  const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1);
+  const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1), ls = svd_ld(rcap);
   const QrPlan a = plan_qr(m, (int)rc), b = plan_qr(n, (int)rc);
-  return 8 * (5 * rc * rc + 2 * rc + 4 * rc * kc + ((size_t)a.ntiles * a.hs + (size_t)b.ntiles * b.hs) * rc) + 4096;
+  return 8 * (2 * rc * rc + 3 * ls * ls + 2 * rc + 2 * ls * kc + 2 * rc * kc +
+              ((size_t)a.ntiles * a.hs + (size_t)b.ntiles * b.hs) * rc) + 4096;
 }
 // Relative size of the noise FP32 products and Householder steps leave in a stack of m rows
 // (u32 sqrt(m), with a safety factor of 4): singular values below it are not kept in FP32 mode.
@@ -304,8 +309,8 @@ float fp32_floor(int m) { return 4.0f * 5.9604645e-8f * std::sqrt((float)std::ma
 
 size_t sym_bytes(int m, int rcap, int kcap) {
   (void)m;
-  const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1);
-  return 8 * (3 * rc * rc + 2 * rc + 2 * rc * kc) + 4096;
+  const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1), ls = svd_ld(rcap);
+  return 8 * (3 * ls * ls + 2 * rc + 2 * ls * kc) + 4096;
 }
 }  // namespace
 
@@ -360,14 +365,16 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
     if (rc > kMaxStack) throw std::runtime_error("recompress: stacked rank capacity above the kernel limit");
     Bufs& b = bufs[i];
     const size_t rr = (size_t)rc * rc;
+    const int ls = svd_ld(rc);
+    const size_t ll = (size_t)ls * ls;
     b.Ru = scratch.get<double>(rr);
     b.Rv = scratch.get<double>(rr);
-    b.B = scratch.get<double>(rr);
-    b.J = scratch.get<double>(rr);
-    b.Jw = scratch.get<double>(rr);
+    b.B = scratch.get<double>(ll);
+    b.J = scratch.get<double>(ll);
+    b.Jw = scratch.get<double>(ll);
     b.aux = scratch.get<double>(2 * (size_t)rc);
-    b.Wk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
-    b.Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    b.Wk = scratch.get<double>((size_t)ls * std::max(T.kcap, 1));
+    b.Jk = scratch.get<double>((size_t)ls * std::max(T.kcap, 1));
     b.Pu = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     b.Pv = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     for (int side = 0; side < 2; ++side) {
@@ -394,16 +401,16 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
     kmax = std::max(kmax, T.kcap);
     mmax = std::max(mmax, std::max(T.m, T.n));
     GemmTask g{};  // B = Ru Rv^T
-    g.A = b.Ru; g.lda = rc; g.B = b.Rv; g.ldb = rc; g.opB = 1; g.C = b.B; g.ldc = rc;
+    g.A = b.Ru; g.lda = rc; g.B = b.Rv; g.ldb = rc; g.opB = 1; g.C = b.B; g.ldc = ls;
     g.m = g.n = g.k = rc; g.mp = g.np = g.kp = T.r; g.alpha = 1.0; g.beta = 0.0;
     gB.push_back(g);
     SvdTask s{};
     s.B = b.B; s.C = b.J; s.Jw = b.Jw; s.aux = b.aux; s.Wk = b.Wk; s.Jk = b.Jk; s.sig = nullptr; s.rp = T.r;
-    s.kout = T.rank; s.ld = rc; s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
+    s.kout = T.rank; s.ld = ls; s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
     s.fidx = T.fidx; s.fp32_floor = fp32_floor(std::max(T.m, T.n));
     sv.push_back(s);
     GemmTask pu{};  // Pu = Rv^T Jk
-    pu.A = b.Rv; pu.opA = 1; pu.lda = rc; pu.B = b.Jk; pu.ldb = rc; pu.C = b.Pu; pu.ldc = rc;
+    pu.A = b.Rv; pu.opA = 1; pu.lda = rc; pu.B = b.Jk; pu.ldb = ls; pu.C = b.Pu; pu.ldc = rc;
     pu.m = rc; pu.mp = T.r; pu.n = T.kcap; pu.np = T.rank; pu.k = rc; pu.kp = T.r; pu.alpha = 1.0; pu.beta = 0.0;
     gP.push_back(pu);
     GemmTask pv = pu;  // Pv = Ru^T Wk
@@ -447,14 +454,15 @@ void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
     const SymTask& T = tasks[i];
     const int rc = std::max(T.rcap, 1);
     if (rc > kMaxStack) throw std::runtime_error("compress_sym: factor capacity above the kernel limit");
-    double* G = scratch.get<double>((size_t)rc * rc);
-    double* J = scratch.get<double>((size_t)rc * rc);
-    double* Jw = scratch.get<double>((size_t)rc * rc);
+    const int ls = svd_ld(rc);
+    double* G = scratch.get<double>((size_t)ls * ls);
+    double* J = scratch.get<double>((size_t)ls * ls);
+    double* Jw = scratch.get<double>((size_t)ls * ls);
     double* aux = scratch.get<double>(2 * (size_t)rc);
-    double* Wk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
-    double* Jk = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
+    double* Wk = scratch.get<double>((size_t)ls * std::max(T.kcap, 1));
+    double* Jk = scratch.get<double>((size_t)ls * std::max(T.kcap, 1));
     GemmTask g{};  // G = S^T S
-    g.A = T.S; g.opA = 1; g.lda = T.lds; g.B = T.S; g.ldb = T.lds; g.C = G; g.ldc = rc;
+    g.A = T.S; g.opA = 1; g.lda = T.lds; g.B = T.S; g.ldb = T.lds; g.C = G; g.ldc = ls;
     g.m = g.n = rc; g.mp = g.np = T.r; g.k = T.m; g.alpha = 1.0; g.beta = 0.0;
     gg.push_back(g);
     rmax = std::max(rmax, rc);
@@ -462,12 +470,12 @@ void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
     mmax = std::max(mmax, T.m);
     SvdTask s{};
     const double th2 = T.thresh * T.thresh;
-    s.B = G; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = rc;
+    s.B = G; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = ls;
     s.kcap = T.kcap; s.thresh = th2; s.qr_thresh = 0.1 * th2; s.fidx = T.fidx;
     s.fp32_floor = fp32_floor(T.m);
     sv.push_back(s);
     GemmTask o{};  // out = S Jk
-    o.A = T.S; o.lda = T.lds; o.B = Jk; o.ldb = rc; o.C = T.out; o.ldc = T.ldo;
+    o.A = T.S; o.lda = T.lds; o.B = Jk; o.ldb = ls; o.C = T.out; o.ldc = T.ldo;
     o.m = T.m; o.n = T.kcap; o.np = T.rank; o.k = rc; o.kp = T.r; o.alpha = 1.0; o.beta = 0.0;
     go.push_back(o);
   }

@@ -189,6 +189,10 @@ template <> struct Prec<float> {
   static constexpr int max_shift = 100;
 };
 
+// A value every lane of the wave holds, as the compiler's scalar (wave-uniform) value: control flow
+// that depends on it becomes scalar branches instead of lane masks.
+static __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // ----------------------------------------------------------------------------------------------
 // Batched GEMM, 64x64 output tile per workgroup (4 waves, 32x32 each = 2x2 MFMA 16x16 tiles),
 // K staged through LDS in chunks of 16.
@@ -788,11 +792,14 @@ void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, bool fp32, hi
 
 // ----------------------------------------------------------------------------------------------
 // Core SVD: pivoted Householder QR (rank-revealing, early stop) + one-sided Jacobi on R_t^T.
-// One workgroup per core; columns are handled one per wave with lanes over rows.
+// One workgroup per core; a column is worked on by a group of 16 lanes.  For r <= 256 a group keeps
+// the rows sl + 16 e of its columns in registers, so all loads of a column are in flight at once,
+// and each phase is instantiated for where its operands live (LDS or global memory), so that LDS
+// operands are reached with LDS instructions.  Larger cores take looped variants.
 // ----------------------------------------------------------------------------------------------
 constexpr int SVD_THREADS = 1024;
 constexpr int SVD_WAVES = SVD_THREADS / 64;
-constexpr int SVD_RMAX = 1024;   // largest core handled
+constexpr int SVD_RMAX = 1024;         // largest core handled
 constexpr int SVD_LDS_BYTES = 131072;  // dynamic LDS (128 KiB) for B, C and J when they fit
 
 template <typename T>
@@ -809,53 +816,64 @@ static __device__ __forceinline__ ArgMax<T> wave_argmax(ArgMax<T> a) {
   return a;
 }
 
-// T = double: FP64 throughout.  T = float: the core is rounded to FP32, everything runs in FP32, and
-// truncation uses max(thresh, fp32_floor sigma_1) (singular values below that are FP32 noise); the
-// outputs stay FP64.  Workspace buffers (C, Jw, aux) are reinterpreted as T.
-template <typename T>
-__global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__ tasks, int* flag) {
-  extern __shared__ __align__(16) unsigned char svd_raw[];
-  T* slds = reinterpret_cast<T*>(svd_raw);
-  constexpr int SVD_LDS = SVD_LDS_BYTES / (int)sizeof(T);
-  const SvdTask Tk = tasks[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int r = *Tk.rp;
-  if (r > SVD_RMAX) r = SVD_RMAX;
-  if (r <= 0) {
-    if (tid == 0) *Tk.kout = 0;
-    return;
-  }
-  constexpr bool dbl = std::is_same<T, double>::value;
-  T* tau = reinterpret_cast<T*>(Tk.aux);
-  T* vhead = tau + r;
-  // global copy of B in T: the input buffer itself (FP64), or the upper half of the C workspace
-  T* const Bglob = dbl ? reinterpret_cast<T*>(Tk.B) : reinterpret_cast<T*>(Tk.C) + (size_t)Tk.ld * Tk.ld;
-  __shared__ T cn[SVD_RMAX];   // trailing squared column norms; later sigma^2
-  __shared__ T vl[SVD_RMAX];   // current reflector when B is in global memory
-  __shared__ int perm[SVD_RMAX];
-  __shared__ int ordr[SVD_RMAX];
-  __shared__ T redv[SVD_WAVES];
-  __shared__ ArgMax<T> reda[SVD_WAVES];
-  __shared__ int rotated;
-  __shared__ unsigned long long sh_pairs, sh_rots;
-  if (tid == 0) { sh_pairs = 0; sh_rots = 0; }
-  unsigned my_pairs = 0, my_rots = 0;  // per wave (counted on every lane), summed once at the end
-  const unsigned long long c0 = wall_clock64();
-  unsigned long long c1 = c0, c2 = c0;
-  int nsweeps = 0;
+// Register segments of padded columns: element e (e0 <= e < e1, wave-uniform bounds) of the group
+// holds row sl + 16 e; elements outside [e0, e1) are zero and skipped.  Columns are stored with a
+// leading dimension that is a multiple of 16 and zero rows below their length, so whole elements
+// are always in bounds.
+template <int EM, typename T, typename X>
+static __device__ __forceinline__ void seg_load(X (&x)[EM], const T* p, int e0, int e1, int sl) {
+  const T* q = p + sl;
+#pragma unroll
+  for (int e = 0; e < EM; ++e) x[e] = (e >= e0 && e < e1) ? (X)q[16 * e] : (X)0;
+}
+template <int EM, typename T, typename X>
+static __device__ __forceinline__ void seg_store(const X (&x)[EM], T* p, int e0, int e1, int sl) {
+  T* q = p + sl;
+#pragma unroll
+  for (int e = 0; e < EM; ++e)
+    if (e >= e0 && e < e1) q[16 * e] = (T)x[e];
+}
 
-  // ---- phase 1: QR with column pivoting, stopped at trailing Frobenius norm <= qr_thresh
-  const bool bl = r * r <= SVD_LDS;
-  T* Bm = bl ? slds : Bglob;
-  int ldb = bl ? r : Tk.ld;
-  if (bl)
-    for (int idx = tid; idx < r * r; idx += SVD_THREADS) slds[idx] = (T)Tk.B[(idx % r) + (size_t)(idx / r) * Tk.ld];
-  else if (!dbl)
-    for (int idx = tid; idx < r * r; idx += SVD_THREADS) {
-      const size_t o = (idx % r) + (size_t)(idx / r) * Tk.ld;
-      Bglob[o] = (T)Tk.B[o];
-    }
-  __syncthreads();
+// Tangent, cosine and sine of the plane rotation that makes two columns with squared norms a, b
+// and inner product g orthogonal: the root of smaller magnitude of t^2 g + t (b - a) - g = 0,
+// t = sign(d) h / (|d| + sqrt(d^2 + h^2)) with d = b - a, h = 2 g (sign(0) = +1).  d and h are
+// first scaled by one power of two, so their squares neither overflow nor underflow.
+template <typename T>
+static __device__ __forceinline__ void jacobi_angle(T a, T b, T g, T& tt, T& cs, T& sn) {
+  T d = b - a, h = (T)2 * g;
+  const int ex = ilogb(fmax(fabs(d), fabs(h)));
+  d = ldexp(d, -ex);
+  h = ldexp(h, -ex);
+  tt = (d >= (T)0 ? h : -h) / (fabs(d) + sqrt(d * d + h * h));
+  cs = rsqrt((T)1 + tt * tt);
+  sn = cs * tt;
+}
+
+// Shared state of one core decomposition.
+template <typename T>
+struct SvdShared {
+  T* cn;          // trailing squared column norms; later sigma^2
+  T* vl;          // register path: reflector factors (tau, heads); looped path: current reflector
+  int* perm;      // column order of the pivoted QR
+  int* ordr;      // singular values in decreasing order
+  T* redv;
+  ArgMax<T>* reda;
+  int* rotated;
+  unsigned long long* pairs;
+  unsigned long long* rots;
+};
+
+// Phase 1: Householder QR with column pivoting of the r x r core Bm, stopped once the trailing
+// Frobenius norm is at most qr_thresh (FP32: at least a tenth of B's FP32 noise).  Returns t;
+// the reflectors sit below the diagonal of Bm's first t columns with their heads in vhead[] and
+// factors in tau[]; perm holds the column order.  Non-finite norms set bit 3 of the status word.
+template <typename T, int EM>
+static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r, const SvdTask& Tk, int* flag,
+                                               const SvdShared<T>& S, T* tau, T* vhead) {
+  constexpr bool dbl = std::is_same<T, double>::value;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane >> 4, sl = lane & 15;
+  T* cn = S.cn;
+  int* perm = S.perm;
   for (int c = wave; c < r; c += SVD_WAVES) {
     T s = 0;
     for (int i = lane; i < r; i += 64) s += Bm[i + (size_t)c * ldb] * Bm[i + (size_t)c * ldb];
@@ -864,7 +882,6 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   }
   __syncthreads();
   T qth2 = (T)(Tk.qr_thresh * Tk.qr_thresh);
-  int t = r;
   for (int j = 0; j < r; ++j) {
     T s = 0;
     ArgMax<T> am{(T)-1, 0x7fffffff};
@@ -874,32 +891,33 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     }
     s = wave_sum(s);
     am = wave_argmax(am);
-    if (lane == 0) { redv[wave] = s; reda[wave] = am; }
+    if (lane == 0) { S.redv[wave] = s; S.reda[wave] = am; }
     __syncthreads();
     T tot = 0;
-    ArgMax<T> best = reda[0];
+    ArgMax<T> best = S.reda[0];
+#pragma unroll
     for (int w = 0; w < SVD_WAVES; ++w) {
-      tot += redv[w];
-      const ArgMax<T> x = reda[w];
+      tot += S.redv[w];
+      const ArgMax<T> x = S.reda[w];
       if (x.v > best.v || (x.v == best.v && x.i < best.i)) best = x;
     }
     // FP32: stop where the trailing norm reaches a tenth of the FP32 noise level of B
     if (!dbl && j == 0) qth2 = fmax(qth2, (T)0.01 * (T)Tk.fp32_floor * (T)Tk.fp32_floor * tot);
-    if (tot <= qth2) { t = j; break; }
-    if (!(tot <= Prec<T>::big) || best.i < j || best.i >= r) {
+    // every thread reduced the same partials: the decisions are uniform
+    const int stop = uniform(tot <= qth2 ? 1 : (!(tot <= Prec<T>::big) || best.i < j || best.i >= r) ? 2 : 0);
+    if (stop == 1) return j;
+    if (stop == 2) {
       // non-finite trailing norms: no valid pivot exists; report and stop (the caller discards the result)
       if (tid == 0) atomicOr(flag + Tk.fidx, 8);
-      t = j;
-      break;
+      return j;
     }
-    const int p = best.i;
+    const int p = uniform(best.i);
     if (p != j) {
       for (int i = tid; i < r; i += SVD_THREADS) {
         const T x = Bm[i + (size_t)j * ldb];
         Bm[i + (size_t)j * ldb] = Bm[i + (size_t)p * ldb];
         Bm[i + (size_t)p * ldb] = x;
       }
-      __syncthreads();
       if (tid == 0) {
         const T x = cn[j]; cn[j] = cn[p]; cn[p] = x;
         const int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
@@ -911,32 +929,59 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     const T beta = x0 >= 0 ? -nrm : nrm;
     const T vj = x0 - beta;
     const T tj = nrm > 0 ? (T)1 / (nrm * (nrm + fabs(x0))) : (T)0;
-    const T* vcol = Bm + (size_t)j * ldb;
-    if (!bl) {
-      for (int i = j + 1 + tid; i < r; i += SVD_THREADS) vl[i] = vcol[i];
-      __syncthreads();
-      vcol = vl;
-    }
     // trailing columns: four per wave, one per group of 16 lanes; uniform control flow around the
-    // row reductions, invalid rows predicated off
-    {
-      const int sub = lane >> 4, sl = lane & 15;
+    // row reductions, rows of invalid groups predicated off
+    if constexpr (EM > 0) {
+      // whole elements from the one holding row j: the reflector is zero above row j, so rows above
+      // j pass through unchanged (and are stored back as they were)
+      const int e0 = j >> 4, e1 = (r + 15) >> 4, jl = j & 15;  // row j is lane jl of element e0
+      T v[EM];
+      seg_load<EM>(v, Bm + (size_t)j * ldb, e0, e1, sl);
+#pragma unroll
+      for (int e = 0; e < EM; ++e)
+        if (e == e0) v[e] = sl > jl ? v[e] : (sl == jl ? vj : (T)0);
+      for (int cc = j + 1 + 4 * wave; cc < r; cc += 4 * SVD_WAVES) {
+        const int c = cc + sub;
+        const bool valid = c < r;
+        T* col = Bm + (size_t)(valid ? c : cc) * ldb;
+        T x[EM];
+        seg_load<EM>(x, col, e0, e1, sl);
+        T w = 0;
+#pragma unroll
+        for (int e = 0; e < EM; ++e) w += v[e] * x[e];
+        w = row_sum(w) * tj;
+        T nn = 0;
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+          x[e] -= w * v[e];
+          if (e != e0 || sl > jl) nn += x[e] * x[e];  // rows below j
+        }
+        nn = row_sum(nn);
+        if (valid) {
+          seg_store<EM>(x, col, e0, e1, sl);
+          if (sl == 0) cn[c] = nn;  // exact trailing norm for the next step
+        }
+      }
+    } else {
+      T* vl = S.vl;
+      for (int i = j + 1 + tid; i < r; i += SVD_THREADS) vl[i] = Bm[i + (size_t)j * ldb];
+      __syncthreads();
       for (int cc = j + 1 + 4 * wave; cc < r; cc += 4 * SVD_WAVES) {
         const int c = cc + sub;
         const bool valid = c < r;
         T* col = Bm + (size_t)(valid ? c : cc) * ldb;
         T w = (sl == 0) ? vj * col[j] : (T)0;
-        for (int i = j + 1 + sl; i < r; i += 16) w += vcol[i] * col[i];
+        for (int i = j + 1 + sl; i < r; i += 16) w += vl[i] * col[i];
         w = row_sum(w) * tj;
         if (valid && sl == 0) col[j] -= w * vj;
         T nn = 0;
         for (int i = j + 1 + sl; i < r; i += 16) {
-          const T x = col[i] - w * vcol[i];
+          const T x = col[i] - w * vl[i];
           if (valid) col[i] = x;
           nn += x * x;
         }
         nn = row_sum(nn);
-        if (valid && sl == 0) cn[c] = nn;  // exact trailing norm for the next step
+        if (valid && sl == 0) cn[c] = nn;
       }
     }
     __syncthreads();
@@ -946,61 +991,53 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
       vhead[j] = vj;
     }
   }
-  __syncthreads();
-  c1 = wall_clock64();
-  if (t == 0) {
-    if (tid == 0) *Tk.kout = 0;
-    return;
+  return r;
+}
+
+// Phases 2-4 for given homes of B (reflectors), C = R_t^T (r x t) and J (t x t):
+//   2. one-sided Jacobi on C with rotations accumulated in J, squared column norms tracked through
+//      the rotations and recomputed at the start of every sweep;
+//   3. singular values (column norms of C J), decreasing order, truncation at thresh (FP32: also at
+//      fp32_floor sigma_1), capped at kcap (overflow sets bit 0 of the status word);
+//   4. B ~ Q_t J S (Pi W S^{-1})^T with W = C J:
+//        Jk[perm[c], o] = W[c, ord(o)] / sigma      (right singular vectors)
+//        Wk = Q_t [J[:, ord(o)] / sigma ; 0]         (left singular vectors over sigma)
+// Returns the number of sweeps.
+template <typename T, int EM>
+static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C, const int ldc, T* J, const int ldj,
+                                               const int r, const int t, const SvdTask& Tk, int* flag,
+                                               const SvdShared<T>& S, const T* tau, const T* vhead,
+                                               unsigned& my_pairs, unsigned& my_rots, unsigned long long& c2) {
+  constexpr bool dbl = std::is_same<T, double>::value;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane >> 4, sl = lane & 15;
+  // rows padded to multiples of 16 with zeros (rotations keep them zero)
+  const int rpad = (r + 15) & ~15, tpad = (t + 15) & ~15, er = rpad >> 4, et = tpad >> 4;
+  for (int idx = tid; idx < rpad * t; idx += SVD_THREADS) {
+    const int c = idx % rpad, i = idx / rpad;  // C[c, i] = R[i, c]
+    C[c + (size_t)i * ldc] = (c >= i && c < r) ? Bm[i + (size_t)c * ldb] : (T)0;
   }
-  // ---- phase 2: one-sided Jacobi on C = R_t^T (r x t), rotations accumulated in J (t x t)
-  T *C, *J;
-  int ldc, ldj;
-  if (bl && r * r + r * t + t * t <= SVD_LDS) {
-    C = slds + r * r; ldc = r;
-    J = C + r * t; ldj = t;
-  } else {
-    if (bl) {  // free the LDS: reflectors back to global
-      for (int idx = tid; idx < r * r; idx += SVD_THREADS) Bglob[(idx % r) + (size_t)(idx / r) * Tk.ld] = slds[idx];
-      __syncthreads();
-      Bm = Bglob;
-      ldb = Tk.ld;
-    }
-    if (r * t + t * t <= SVD_LDS) {
-      C = slds; ldc = r;
-      J = slds + r * t; ldj = t;
-    } else {
-      C = reinterpret_cast<T*>(Tk.C); ldc = Tk.ld;
-      if (t * t <= SVD_LDS) { J = slds; ldj = t; }
-      else { J = reinterpret_cast<T*>(Tk.Jw); ldj = Tk.ld; }
-    }
-  }
-  for (int idx = tid; idx < r * t; idx += SVD_THREADS) {
-    const int c = idx % r, i = idx / r;  // C[c, i] = R[i, c]
-    C[c + (size_t)i * ldc] = (c >= i) ? Bm[i + (size_t)c * ldb] : (T)0;
-  }
-  for (int idx = tid; idx < t * t; idx += SVD_THREADS) {
-    const int i = idx % t, c = idx / t;
+  for (int idx = tid; idx < tpad * t; idx += SVD_THREADS) {
+    const int i = idx % tpad, c = idx / tpad;
     J[i + (size_t)c * ldj] = (i == c) ? (T)1 : (T)0;
   }
   __syncthreads();
+  // ---- phase 2
   const int tp = t + (t & 1);
   const T tol = (T)4 * Prec<T>::eps * sqrt((T)r);
-  T* nrm2 = cn;  // squared column norms of C, tracked through the rotations
+  T* nrm2 = S.cn;
+  int nsweeps = 0;
   for (int sweep = 0; sweep < 40 && t > 1; ++sweep) {
-    // exact norms at the start of every sweep
     for (int c = wave; c < t; c += SVD_WAVES) {
       T s = 0;
       for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ldc] * C[i + (size_t)c * ldc];
       s = wave_sum(s);
       if (lane == 0) nrm2[c] = s;
     }
-    if (tid == 0) rotated = 0;
+    if (tid == 0) *S.rotated = 0;
     __syncthreads();
-    // Each pair of a round gets a group of 16 lanes, four pairs per wave: dot products reduce
-    // inside the row, and up to 4 * SVD_WAVES pairs rotate at once.  All rows of a wave run the
-    // same instructions (row reductions under uniform control flow); a row without a valid pair,
-    // or whose pair needs no rotation, is predicated off.
-    const int sub = lane >> 4, sl = lane & 15;
+    // Each pair of a round (round-robin order) gets a group of 16 lanes, four pairs per wave: dot
+    // products reduce inside the group, and up to 4 * SVD_WAVES pairs rotate at once.  A group
+    // without a valid pair, or whose pair needs no rotation, is predicated off.
     for (int round = 0; round < tp - 1; ++round) {
       for (int pi0 = wave * 4; pi0 < tp / 2; pi0 += 4 * SVD_WAVES) {
         const int pi = pi0 + sub;
@@ -1011,73 +1048,121 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
         int pp = (x == 0) ? 0 : 1 + px, qq = (y == 0) ? 0 : 1 + qy;
         if (pp > qq) { const int w0 = pp; pp = qq; qq = w0; }
         const bool valid = pi < tp / 2 && qq < t;
-        if (!valid) { pp = 0; qq = 0; }  // harmless addresses for predicated-off rows
+        if (!valid) { pp = 0; qq = 0; }  // harmless addresses for predicated-off groups
         T* cp = C + (size_t)pp * ldc;
         T* cq = C + (size_t)qq * ldc;
-        T gg = 0;
-        if (valid)
-          for (int i = sl; i < r; i += 16) gg += cp[i] * cq[i];
-        gg = row_sum(gg);
         const T a = nrm2[pp], b = nrm2[qq];
-        // rotate when |g| > tol sqrt(a b), tested without square roots
-        const bool rot = valid && a > Prec<T>::tiny && b > Prec<T>::tiny && gg * gg > tol * tol * a * b;
-        my_pairs += valid && sl == 0;
-        my_rots += rot && sl == 0;
-        T zeta = 0, tt = 0, cs = 1, sn = 0;
-        if (rot) {
-          zeta = (b - a) / ((T)2 * gg);
-          tt = (zeta >= 0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
-          cs = rsqrt((T)1 + tt * tt);
-          sn = cs * tt;
-        }
-        T na = 0, nb = 0;
-        if (rot)
-          for (int i = sl; i < r; i += 16) {
-            const T uu = cp[i], w = cq[i];
-            const T u2 = cs * uu - sn * w, w2 = sn * uu + cs * w;
-            cp[i] = u2;
-            cq[i] = w2;
+        if constexpr (EM > 0) {
+          T up[EM], uq[EM];
+          seg_load<EM>(up, cp, 0, er, sl);
+          seg_load<EM>(uq, cq, 0, er, sl);
+          T gg = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) gg += up[e] * uq[e];
+          gg = row_sum(gg);
+          // rotate when |g| > tol sqrt(a b), tested without square roots
+          const bool rot = valid && a > Prec<T>::tiny && b > Prec<T>::tiny && gg * gg > tol * tol * a * b;
+          my_pairs += valid && sl == 0;
+          my_rots += rot && sl == 0;
+          T tt = 0, cs = 1, sn = 0;
+          if (rot) jacobi_angle(a, b, gg, tt, cs, sn);
+          T na = 0, nb = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) {
+            const T u2 = cs * up[e] - sn * uq[e], w2 = sn * up[e] + cs * uq[e];
+            up[e] = u2;
+            uq[e] = w2;
             na += u2 * u2;
             nb += w2 * w2;
           }
-        T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
-        const bool exact = rot && (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b));  // cancellation: computed norms
-        if (__any(exact)) {  // wave-uniform; rare
-          na = row_sum(na);
-          nb = row_sum(nb);
-          if (exact) {
-            ea = na;
-            eb = nb;
+          T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
+          const bool exact = rot && (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b));  // cancellation: computed norms
+          if (__any(exact)) {  // wave-uniform; rare
+            na = row_sum(na);
+            nb = row_sum(nb);
+            if (exact) {
+              ea = na;
+              eb = nb;
+            }
           }
-        }
-        if (rot) {
-          T* jp = J + (size_t)pp * ldj;
-          T* jq = J + (size_t)qq * ldj;
-          for (int i = sl; i < t; i += 16) {
-            const T uu = jp[i], w = jq[i];
-            jp[i] = cs * uu - sn * w;
-            jq[i] = sn * uu + cs * w;
+          if (rot) {
+            seg_store<EM>(up, cp, 0, er, sl);
+            seg_store<EM>(uq, cq, 0, er, sl);
+            T* jp = J + (size_t)pp * ldj;
+            T* jq = J + (size_t)qq * ldj;
+            T vp[EM], vq[EM];
+            seg_load<EM>(vp, jp, 0, et, sl);
+            seg_load<EM>(vq, jq, 0, et, sl);
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+              const T u2 = cs * vp[e] - sn * vq[e], w2 = sn * vp[e] + cs * vq[e];
+              vp[e] = u2;
+              vq[e] = w2;
+            }
+            seg_store<EM>(vp, jp, 0, et, sl);
+            seg_store<EM>(vq, jq, 0, et, sl);
+            if (sl == 0) {
+              nrm2[pp] = ea;
+              nrm2[qq] = eb;
+              *S.rotated = 1;
+            }
           }
-          if (sl == 0) {
-            nrm2[pp] = ea;
-            nrm2[qq] = eb;
-            rotated = 1;
+        } else {
+          T gg = 0;
+          if (valid)
+            for (int i = sl; i < r; i += 16) gg += cp[i] * cq[i];
+          gg = row_sum(gg);
+          const bool rot = valid && a > Prec<T>::tiny && b > Prec<T>::tiny && gg * gg > tol * tol * a * b;
+          my_pairs += valid && sl == 0;
+          my_rots += rot && sl == 0;
+          T tt = 0, cs = 1, sn = 0;
+          if (rot) jacobi_angle(a, b, gg, tt, cs, sn);
+          T na = 0, nb = 0;
+          if (rot)
+            for (int i = sl; i < r; i += 16) {
+              const T uu = cp[i], w = cq[i];
+              const T u2 = cs * uu - sn * w, w2 = sn * uu + cs * w;
+              cp[i] = u2;
+              cq[i] = w2;
+              na += u2 * u2;
+              nb += w2 * w2;
+            }
+          T ea = a - tt * gg, eb = b + tt * gg;
+          const bool exact = rot && (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b));
+          if (__any(exact)) {
+            na = row_sum(na);
+            nb = row_sum(nb);
+            if (exact) {
+              ea = na;
+              eb = nb;
+            }
+          }
+          if (rot) {
+            T* jp = J + (size_t)pp * ldj;
+            T* jq = J + (size_t)qq * ldj;
+            for (int i = sl; i < t; i += 16) {
+              const T uu = jp[i], w = jq[i];
+              jp[i] = cs * uu - sn * w;
+              jq[i] = sn * uu + cs * w;
+            }
+            if (sl == 0) {
+              nrm2[pp] = ea;
+              nrm2[qq] = eb;
+              *S.rotated = 1;
+            }
           }
         }
       }
       __syncthreads();
     }
     ++nsweeps;
-    if (!rotated) break;
+    if (!uniform(*S.rotated)) break;
     __syncthreads();
   }
   c2 = wall_clock64();
-  if ((lane & 15) == 0 && my_pairs) {  // counted on the first lane of each 16-lane group
-    atomicAdd(&sh_pairs, (unsigned long long)my_pairs);
-    atomicAdd(&sh_rots, (unsigned long long)my_rots);
-  }
-  // ---- phase 3: singular values (column norms of C J), order, truncation
-  T* sig2 = cn;
+  // ---- phase 3
+  T* sig2 = S.cn;
+  int* ordr = S.ordr;
   for (int c = wave; c < t; c += SVD_WAVES) {
     T s = 0;
     for (int i = lane; i < r; i += 64) s += C[i + (size_t)c * ldc] * C[i + (size_t)c * ldc];
@@ -1104,6 +1189,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   }
   int kk = 0;
   for (int i = 0; i < t; ++i) kk += sig2[i] > th2;
+  kk = uniform(kk);
   if (kk > Tk.kcap) {
     if (tid == 0) atomicOr(flag + Tk.fidx, 1);
     kk = Tk.kcap;
@@ -1111,41 +1197,150 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   if (tid == 0) *Tk.kout = kk;
   if (Tk.sig)
     for (int i = tid; i < t; i += SVD_THREADS) Tk.sig[i] = sqrt((double)sig2[ordr[i]]);
-  // ---- phase 4: B ~ Q_t J S (Pi W S^{-1})^T with W = C J
-  //   Jk[perm[c], o] = W[c, ord(o)] / sigma      (right singular vectors)
-  //   Wk = Q_t [J[:, ord(o)] / sigma ; 0]         (left singular vectors over sigma)
+  // ---- phase 4
+  const int* perm = S.perm;
   for (int idx = tid; idx < r * kk; idx += SVD_THREADS) {
     const int c = idx % r, o = idx / r, src = ordr[o];
     const double is = 1.0 / sqrt((double)sig2[src]);
     Tk.Jk[perm[c] + (size_t)o * Tk.ld] = C[c + (size_t)src * ldc] * is;
-    Tk.Wk[c + (size_t)o * Tk.ld] = (c < t) ? J[c + (size_t)src * ldj] * is : 0.0;
+    if constexpr (EM == 0) Tk.Wk[c + (size_t)o * Tk.ld] = (c < t) ? J[c + (size_t)src * ldj] * is : 0.0;
   }
-  __syncthreads();
-  for (int j = t - 1; j >= 0; --j) {
-    const double tj = tau[j], vj = vhead[j];
-    if (tj != 0.0) {  // uniform: the output columns, one per group of 16 lanes
-      const T* vcol = Bm + (size_t)j * ldb;
-      const int sub = lane >> 4, sl = lane & 15;
-      for (int o0 = 4 * wave; o0 < kk; o0 += 4 * SVD_WAVES) {
-        const int o = o0 + sub;
-        const bool valid = o < kk;
-        double* col = Tk.Wk + (size_t)(valid ? o : o0) * Tk.ld;
-        double w = (sl == 0) ? vj * col[j] : 0.0;
-        for (int i = j + 1 + sl; i < r; i += 16) w += vcol[i] * col[i];
-        w = row_sum(w) * tj;
-        if (valid) {
-          if (sl == 0) col[j] -= w * vj;
-          for (int i = j + 1 + sl; i < r; i += 16) col[i] -= w * vcol[i];
+  if constexpr (EM > 0) {
+    // Each output column stays in registers of one group through the t reflectors (applied last to
+    // first).
+    for (int o0 = 4 * wave; o0 < kk; o0 += 4 * SVD_WAVES) {
+      const int o = o0 + sub;
+      const bool valid = o < kk;
+      const int src = ordr[valid ? o : o0];
+      const double is = 1.0 / sqrt((double)sig2[src]);
+      double x[EM];
+      seg_load<EM>(x, J + (size_t)src * ldj, 0, et, sl);
+#pragma unroll
+      for (int e = 0; e < EM; ++e) x[e] *= is;
+      for (int j = t - 1; j >= 0; --j) {
+        T v[EM];
+        const double tj = tau[j], vj = vhead[j];
+        if (uniform(tj != 0.0)) {
+          const int e0 = j >> 4, jl = j & 15;  // row j is lane jl of element e0
+          seg_load<EM>(v, Bm + (size_t)j * ldb, e0, er, sl);
+#pragma unroll
+          for (int e = 0; e < EM; ++e)
+            if (e == e0) v[e] = sl > jl ? v[e] : (sl == jl ? (T)vj : (T)0);
+          double w = 0.0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) w += (double)v[e] * x[e];
+          w = row_sum(w) * tj;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) x[e] -= w * (double)v[e];
         }
       }
+      if (valid) seg_store<EM>(x, Tk.Wk + (size_t)o * Tk.ld, 0, er, sl);
+    }
+  } else {
+    __syncthreads();
+    for (int j = t - 1; j >= 0; --j) {
+      const double tj = tau[j], vj = vhead[j];
+      if (uniform(tj != 0.0)) {  // the output columns, one per group of 16 lanes
+        const T* vcol = Bm + (size_t)j * ldb;
+        for (int o0 = 4 * wave; o0 < kk; o0 += 4 * SVD_WAVES) {
+          const int o = o0 + sub;
+          const bool valid = o < kk;
+          double* col = Tk.Wk + (size_t)(valid ? o : o0) * Tk.ld;
+          double w = (sl == 0) ? vj * col[j] : 0.0;
+          for (int i = j + 1 + sl; i < r; i += 16) w += vcol[i] * col[i];
+          w = row_sum(w) * tj;
+          if (valid) {
+            if (sl == 0) col[j] -= w * vj;
+            for (int i = j + 1 + sl; i < r; i += 16) col[i] -= w * vcol[i];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return nsweeps;
+}
+
+// T = double: FP64 throughout.  T = float: the core is rounded to FP32, everything runs in FP32, and
+// truncation uses max(thresh, fp32_floor sigma_1) (singular values below that are FP32 noise); the
+// outputs stay FP64.  Workspace buffers (C, Jw, aux) are reinterpreted as T.
+template <typename T, int EM>
+static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, const int r, T* slds,
+                                               const SvdShared<T>& S) {
+  constexpr bool dbl = std::is_same<T, double>::value;
+  constexpr int SVD_LDS = SVD_LDS_BYTES / (int)sizeof(T);
+  const int tid = threadIdx.x;
+  // reflector factors: in LDS on the register path (t <= r <= 256), else in the aux workspace
+  T* tau = EM > 0 ? S.vl : reinterpret_cast<T*>(Tk.aux);
+  T* vhead = EM > 0 ? S.vl + 256 : reinterpret_cast<T*>(Tk.aux) + r;
+  // global copy of B in T: the input buffer itself (FP64), or the upper half of the C workspace
+  T* const Bglob = dbl ? reinterpret_cast<T*>(Tk.B) : reinterpret_cast<T*>(Tk.C) + (size_t)Tk.ld * Tk.ld;
+  const unsigned long long c0 = wall_clock64();
+  unsigned long long c1 = c0, c2 = c0;
+  unsigned my_pairs = 0, my_rots = 0;  // per group lane 0, summed once at the end
+  // ---- phase 1 on B with rows padded by zeros to rpad (a multiple of 16, at most Tk.ld)
+  const int rpad = (r + 15) & ~15;
+  const bool bl = rpad * r <= SVD_LDS;
+  int t;
+  if (bl) {
+    for (int idx = tid; idx < rpad * r; idx += SVD_THREADS) {
+      const int i = idx % rpad, c = idx / rpad;
+      slds[idx] = i < r ? (T)Tk.B[i + (size_t)c * Tk.ld] : (T)0;
     }
     __syncthreads();
+    t = svd_qrcp<T, EM>(slds, rpad, r, Tk, flag, S, tau, vhead);
+  } else {
+    for (int idx = tid; idx < rpad * r; idx += SVD_THREADS) {
+      const int i = idx % rpad, c = idx / rpad;
+      const size_t o = i + (size_t)c * Tk.ld;
+      if (i >= r) Bglob[o] = (T)0;
+      else if (!dbl) Bglob[o] = (T)Tk.B[o];
+    }
+    __syncthreads();
+    t = svd_qrcp<T, EM>(Bglob, Tk.ld, r, Tk, flag, S, tau, vhead);
   }
+  __syncthreads();
+  c1 = wall_clock64();
+  if (t == 0) {
+    if (tid == 0) *Tk.kout = 0;
+    return;
+  }
+  // ---- phases 2-4: C = R_t^T (rpad x t) and J (tpad x t) in LDS when they fit (B stays there too
+  // if there is room)
+  const int tpad = (t + 15) & ~15;
+  const int nB = rpad * r, nC = rpad * t, nJ = tpad * t;
+  int nsweeps;
+  if (bl && nB + nC + nJ <= SVD_LDS) {
+    nsweeps = svd_tail<T, EM>(slds, rpad, slds + nB, rpad, slds + nB + nC, tpad, r, t, Tk, flag, S, tau, vhead,
+                              my_pairs, my_rots, c2);
+  } else {
+    if (bl) {  // free the LDS: reflectors (and the zero padding) back to global
+      for (int idx = tid; idx < nB; idx += SVD_THREADS) Bglob[(idx % rpad) + (size_t)(idx / rpad) * Tk.ld] = slds[idx];
+      __syncthreads();
+    }
+    T* const Cg = reinterpret_cast<T*>(Tk.C);
+    T* const Jg = reinterpret_cast<T*>(Tk.Jw);
+    if (nC + nJ <= SVD_LDS)
+      nsweeps = svd_tail<T, EM>(Bglob, Tk.ld, slds, rpad, slds + nC, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
+                                my_rots, c2);
+    else if (nJ <= SVD_LDS)
+      nsweeps = svd_tail<T, EM>(Bglob, Tk.ld, Cg, Tk.ld, slds, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
+                                my_rots, c2);
+    else
+      nsweeps = svd_tail<T, EM>(Bglob, Tk.ld, Cg, Tk.ld, Jg, Tk.ld, r, t, Tk, flag, S, tau, vhead, my_pairs,
+                                my_rots, c2);
+  }
+  if ((threadIdx.x & 15) == 0 && my_pairs) {  // counted on the first lane of each 16-lane group
+    atomicAdd(S.pairs, (unsigned long long)my_pairs);
+    atomicAdd(S.rots, (unsigned long long)my_rots);
+  }
+  __syncthreads();
   if (tid == 0) {
+    const int kk = *Tk.kout;
     unsigned long long f = 0;
     for (int j = 0; j < t; ++j)
       f += 2ull * (r - j) + 6ull * (unsigned long long)(r - j) * (r - j - 1) + 4ull * (r - j) * kk;
-    f += sh_pairs * 6ull * r + sh_rots * (6ull * r + 6ull * t) + 2ull * r * t;
+    f += *S.pairs * 6ull * r + *S.rots * (6ull * r + 6ull * t) + 2ull * r * t;
     count_work(K_SVD, f, 0);
     if (g_prof_on) {
       const unsigned long long c3 = wall_clock64();
@@ -1158,6 +1353,42 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
       atomicAdd(&g_svdstat[6], 1ull);
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__ tasks, int* flag) {
+  extern __shared__ __align__(16) unsigned char svd_raw[];
+  T* slds = reinterpret_cast<T*>(svd_raw);
+  const SvdTask Tk = tasks[blockIdx.x];
+  int r = uniform(*Tk.rp);
+  if (r > SVD_RMAX) r = SVD_RMAX;
+  if (r <= 0) {
+    if (threadIdx.x == 0) *Tk.kout = 0;
+    return;
+  }
+  if (Tk.ld < ((r + 15) & ~15)) {  // workspaces must hold the rows padded to a multiple of 16
+    if (threadIdx.x == 0) {
+      atomicOr(flag + Tk.fidx, 8);
+      *Tk.kout = 0;
+    }
+    return;
+  }
+  __shared__ T cn[SVD_RMAX];
+  __shared__ T vl[SVD_RMAX];
+  __shared__ int perm[SVD_RMAX];
+  __shared__ int ordr[SVD_RMAX];
+  __shared__ T redv[SVD_WAVES];
+  __shared__ ArgMax<T> reda[SVD_WAVES];
+  __shared__ int rotated;
+  __shared__ unsigned long long sh_pairs, sh_rots;
+  if (threadIdx.x == 0) { sh_pairs = 0; sh_rots = 0; }
+  const SvdShared<T> S{cn, vl, perm, ordr, redv, reda, &rotated, &sh_pairs, &sh_rots};
+  if (r <= 128)
+    svd_run<T, 8>(Tk, flag, r, slds, S);
+  else if (r <= 256)
+    svd_run<T, 16>(Tk, flag, r, slds, S);
+  else
+    svd_run<T, 0>(Tk, flag, r, slds, S);
 }
 
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s) {

@@ -23,7 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "predictor_default.json")
 FORMAT = "hq-rank-predictor-v1"
 
-# (n, b, seed, leaf, tol, kind): banded N(0,1) (kind "band") or tridiagonal uniform ("tri")
+# (n, b, seed, leaf, tol, kind): banded N(0,1) (kind "band"), tridiagonal uniform ("tri") or
+# tridiagonal with diagonal 2 + U(0, 0.1) and off-diagonal -1 ("metallic")
 TRAIN_SET = [
     (n, b, 100 + i, 128, 1e-10, "band")
     for i, (n, b) in enumerate([(2048, 1), (2048, 4), (2048, 9), (2048, 16), (3000, 2), (3000, 7), (3000, 13),
@@ -33,6 +34,9 @@ TRAIN_SET = [
 ] + [
     (4096, 1, 140, 256, 1e-10, "tri"), (16384, 1, 141, 256, 1e-10, "tri"), (32768, 1, 142, 256, 1e-8, "tri"),
     (4096, 8, 143, 256, 1e-10, "band"), (2048, 1, 144, 64, 1e-10, "tri"), (4096, 4, 145, 64, 1e-10, "band"),
+    (2048, 1, 146, 64, 1e-10, "metallic"), (4096, 1, 147, 256, 1e-10, "metallic"),
+    (8192, 1, 148, 128, 1e-10, "metallic"), (16384, 1, 149, 256, 1e-10, "metallic"),
+    (32768, 1, 150, 256, 1e-10, "metallic"),
 ]
 
 
@@ -46,7 +50,11 @@ def _workloads():
 
 def make_problem(n, b, seed, kind):
     wl = _workloads()
-    return wl.banded_normal(n, b, seed) if kind == "band" else wl.tridiag_uniform(n, seed)
+    if kind == "band":
+        return wl.banded_normal(n, b, seed)
+    if kind == "metallic":
+        return wl.tridiag_metallic(n, seed)
+    return wl.tridiag_uniform(n, seed)
 
 
 def collect(problems, verbose=False):

@@ -105,15 +105,17 @@ def test_predictor_keeps_results_and_cuts_capacity(small_predictor, n, b, seed):
 
 
 def test_underpredicting_network_only_costs_redos():
-    """A network that predicts rank 0 everywhere: every iteration overflows and is repeated with
-    larger capacities, and the projector is bit for bit the one without a predictor."""
+    """A network that predicts rank 0 everywhere: the first Cholesky iteration overflows and is
+    repeated with larger capacities; from then on the member's capacities are at least those the
+    previous iterate's ranks call for, so few further repeats happen, and the projector is bit for bit
+    the one without a predictor."""
     zero = hq.Predictor(seed=0)
     zero.set_params(np.zeros(zero.nparams(), dtype=np.float32))
     ab = w.banded_normal(1500, 4, 21)
     mu, _ = hq.shift_for_count(ab, 4, 750)
     H0, i0 = _solve(ab, 4, mu, leaf=64)
     H1, i1 = _solve(ab, 4, mu, leaf=64, predictor=zero)
-    assert i1["redo_count"] >= i1["iters"] - 1
+    assert 1 <= i1["redo_count"] <= i0["redo_count"] + 2
     assert _same(H0, H1)
 
 
