@@ -752,9 +752,11 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     // leaves: Lf_i = chol(Z_i - S S^T), Linv_i = Lf_i^{-1}
     std::vector<LeafAxpy> cp;
     std::vector<GemmTask> gs;
-    std::vector<LeafTask> small, big;
+    std::vector<LeafTask> small, big, mid2;
+    std::vector<GemmTask> m1, m2, m3, m4;  // steps of the 2 x 2 split of leaves with 128 < m <= 256
     std::vector<Item> inner;
-    int maxm = 1, maxsmall = 1;
+    int maxm = 1, maxsmall = 1, maxh = 1;
+    const DevArena::Mark lmk = scratch.mark();  // leaf scratch (W), released after the leaf launches
     for (const Item& it : items) {
       const CholTask& T = batch[it.m];
       const Tree* t = T.Z->t;
@@ -777,6 +779,36 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       if (m <= 128) {
         small.push_back(lt);
         maxsmall = std::max(maxsmall, m);
+      } else if (m <= 256) {
+        // [A11 0; A21 A22] = [L11 0; L21 L22] [L11 0; L21 L22]^T with X = L^{-1}:
+        //   X11 = L11^{-1};  L21 = A21 X11^T;  A22 -= L21 L21^T;  X22 = L22^{-1};  X21 = -X22 L21 X11.
+        // L21 is kept in X21's slot until the last step; W = L21 X11 is scratch; X12 = 0.
+        const int h1 = (m + 1) / 2, h2 = m - h1, ld = T.Lf->ldl, ldx = T.Linv->ldl;
+        double* A = T.Lf->leaf(li);
+        double* X = T.Linv->leaf(li);
+        double* W = scratch.get<double>((size_t)h2 * h1);
+        maxh = std::max(maxh, h1);
+        LeafAxpy z{};  // X = 0
+        z.out = X; z.ldo = ldx; z.X = X; z.ldx = ldx; z.m = m;
+        cp.push_back(z);
+        small.push_back(LeafTask{A, X, h1, ld, ldx, T.fidx});
+        GemmTask g{};
+        g.A = A + h1; g.lda = ld; g.B = X; g.ldb = ldx; g.opB = 1; g.C = X + h1; g.ldc = ldx;
+        g.m = h2; g.n = h1; g.k = h1; g.alpha = 1.0; g.beta = 0.0;
+        m1.push_back(g);  // L21 = A21 X11^T
+        g = GemmTask{};
+        g.A = X + h1; g.lda = ldx; g.B = X + h1; g.ldb = ldx; g.opB = 1; g.C = A + h1 + (size_t)h1 * ld; g.ldc = ld;
+        g.m = h2; g.n = h2; g.k = h1; g.alpha = -1.0; g.beta = 1.0;
+        m2.push_back(g);  // A22 -= L21 L21^T
+        mid2.push_back(LeafTask{A + h1 + (size_t)h1 * ld, X + h1 + (size_t)h1 * ldx, h2, ld, ldx, T.fidx});
+        g = GemmTask{};
+        g.A = X + h1; g.lda = ldx; g.B = X; g.ldb = ldx; g.C = W; g.ldc = h2;
+        g.m = h2; g.n = h1; g.k = h1; g.alpha = 1.0; g.beta = 0.0;
+        m3.push_back(g);  // W = L21 X11
+        g = GemmTask{};
+        g.A = X + h1 + (size_t)h1 * ldx; g.lda = ldx; g.B = W; g.ldb = h2; g.C = X + h1; g.ldc = ldx;
+        g.m = h2; g.n = h1; g.k = h2; g.alpha = -1.0; g.beta = 0.0;
+        m4.push_back(g);  // X21 = -X22 W
       } else {
         big.push_back(lt);
       }
@@ -786,9 +818,18 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       ++launches;
       gemm(gs, maxm, maxm);
       if (!small.empty()) {
-        launch_chol_inv(stage.upload(small, st), (int)small.size(), maxsmall, d_flag, st);
+        launch_chol_inv(stage.upload(small, st), (int)small.size(), std::max(maxsmall, maxh), d_flag, st);
         ++launches;
       }
+      if (!mid2.empty()) {  // the leaf factorisation stays FP64 in every mode
+        launch_gemm(stage.upload(m1, st), (int)m1.size(), maxh, maxh, false, st);
+        launch_gemm(stage.upload(m2, st), (int)m2.size(), maxh, maxh, false, st);
+        launch_chol_inv(stage.upload(mid2, st), (int)mid2.size(), maxh, d_flag, st);
+        launch_gemm(stage.upload(m3, st), (int)m3.size(), maxh, maxh, false, st);
+        launch_gemm(stage.upload(m4, st), (int)m4.size(), maxh, maxh, false, st);
+        launches += 5;
+      }
+      scratch.rewind(lmk);
       if (!big.empty()) {
         LeafTask* d = stage.upload(big, st);
         launch_potrf(d, (int)big.size(), d_flag, st);

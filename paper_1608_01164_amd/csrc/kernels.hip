@@ -1462,81 +1462,166 @@ __global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ task
   if (tid == 0) count_work(K_TRTRI, (unsigned long long)m * m * m / 3, 0);
 }
 
-// Leaf Cholesky and in-place triangular inverse with the whole leaf in LDS (m <= 128):
-// A (lower part of an SPD tile) -> A = L L^T, then L -> L^{-1} written to B.
+// Leaf Cholesky and triangular inverse for m <= 128, with the tile in registers: the lower
+// triangle is cut into 4 x 4 blocks, one per thread (at most 528 blocks), padded with the identity
+// to a multiple of 4.  Step j of either phase publishes one column (and row) through LDS, double
+// buffered, so that each step costs one barrier.
+//   Cholesky (right-looking): publish column j of the trailing matrix and the pivot; every block
+//     right of j subtracts a_ij a_cj / d; the owners of column j scale it by 1/sqrt(d).
+//   Inverse X = L^{-1} in place (right-looking elimination on [L | I]): row j of X, complete after
+//     steps < j, is scaled by 1/L_jj and published with column j of L; rows below j subtract
+//     L_ij X_j. (the slots of column j, which held L_ij, start from zero).
+// A (lower part of an SPD tile) is read; B receives L^{-1} (zero above the diagonal).
 constexpr int CI_MAX = 128;
-__global__ __launch_bounds__(512) void k_chol_inv(const LeafTask* __restrict__ tasks, int* flag) {
+constexpr int CI_PAD = CI_MAX + 4;
+__global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ tasks, int* flag) {
   const LeafTask T = tasks[blockIdx.x];
-  const int m = T.m, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // 8 waves
-  extern __shared__ double S[];  // m x m, ld = m
-  for (int idx = tid; idx < m * m; idx += 512) {
-    const int i = idx % m, c = idx / m;
-    S[i + c * m] = (i >= c) ? T.A[i + (size_t)c * T.lda] : 0.0;
+  const int m = T.m, tid = threadIdx.x;
+  const int nb = (m + 3) >> 2, mp = 4 * nb;
+  const bool own = tid < nb * (nb + 1) / 2;
+  int bi = 0, bc = 0;
+  if (own) {  // lower-triangular block number tid -> (bi, bc), bi >= bc
+    bi = (int)((sqrtf(8.0f * (float)tid + 1.0f) - 1.0f) * 0.5f);
+    while (bi * (bi + 1) / 2 > tid) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= tid) ++bi;
+    bc = tid - bi * (bi + 1) / 2;
   }
-  __syncthreads();
-  // Cholesky, one barrier per column: the trailing update uses the unscaled pivot column
-  // (a_ic -= a_ij a_cj / d), and column j is scaled by 1/sqrt(d) one step later, when no
-  // thread reads it any more.
-  __shared__ double diag[CI_MAX];  // L's diagonal, kept apart from the in-place inverse below
-  double dprev = 1.0;
-  for (int j = 0; j < m; ++j) {
-    double d = S[j + j * m];
-    if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
-      if (tid == 0) atomicOr(flag + T.fidx, 2);
-      d = 1.0;
-    }
-    const double inv_d = 1.0 / d;
-    for (int c = j + 1 + wave; c < m; c += 8) {
-      const double f = S[c + j * m] * inv_d;
-      for (int i = c + lane; i < m; i += 64) S[i + c * m] -= S[i + j * m] * f;
-    }
-    if (j > 0) {  // deferred scaling of column j - 1
-      const double rs = 1.0 / sqrt(dprev);
-      for (int i = j + tid; i < m; i += 512) S[i + (j - 1) * m] *= rs;
-      if (tid == 0) {
-        S[(j - 1) + (j - 1) * m] = sqrt(dprev);
-        diag[j - 1] = sqrt(dprev);
+  const int r0 = 4 * bi, c0 = 4 * bc;
+  double a[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = r0 + r, k = c0 + c;
+      double v = 0.0;
+      if (own) {
+        if (i < m && k < m) {
+          if (i >= k) v = T.A[i + (size_t)k * T.lda];
+        } else if (i == k) {
+          v = 1.0;
+        }
       }
+      a[r][c] = v;
     }
-    dprev = d;
+  __shared__ double colv[2][CI_PAD];  // column j below the diagonal (Cholesky) / of L (inverse)
+  __shared__ double rowv[2][CI_PAD];  // row j of X (inverse)
+  __shared__ double piv[2][2];        // 1/d and sqrt(d) of step j
+  __shared__ double rdiag[CI_PAD];    // 1 / L_jj
+  // Updates are branch-free over the 16 entries: factors that are zero outside the rows and columns
+  // a step touches.  Entries above the diagonal of diagonal blocks take junk, which nothing reads
+  // (they are written out as zeros).
+  // ---- Cholesky
+  for (int j = 0; j < mp; ++j) {
+    const int b = j & 1, jb = j >> 2, jc = j & 3;
+    if (own && bc == jb) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c == jc) {  // wave-uniform
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (r0 + r >= j) colv[b][r0 + r] = a[r][c];
+          if (bi == bc) {
+            double d = a[c][c];
+            if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
+              if (j < m) atomicOr(flag + T.fidx, 2);
+              d = 1.0;
+            }
+            const double rs = rsqrt(d);
+            piv[b][0] = rs * rs;
+            piv[b][1] = d * rs;
+            rdiag[j] = rs;
+          }
+        }
+    }
     __syncthreads();
-  }
-  {
-    const double rs = 1.0 / sqrt(dprev);
-    for (int i = m + tid; i < m; i += 512) S[i + (m - 1) * m] *= rs;  // no rows below the last column
-    if (tid == 0) {
-      S[(m - 1) + (m - 1) * m] = sqrt(dprev);
-      diag[m - 1] = sqrt(dprev);
+    if (!own) continue;
+    const double inv_d = piv[b][0], s = piv[b][1], rs = rdiag[j];
+    double li[4], fc[4], sc[4], ad[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = r0 + r;
+      li[r] = i > j ? colv[b][i] : 0.0;
+      sc[r] = i > j ? rs : (i == j ? 0.0 : 1.0);  // column j: rows below scaled, the pivot replaced by sqrt(d)
+      ad[r] = i == j ? s : 0.0;
     }
-    (void)rs;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = c0 + c;
+      fc[c] = k > j ? colv[b][k] * inv_d : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bool colj = c0 + c == j;
+        a[r][c] = colj ? a[r][c] * sc[r] + ad[r] : a[r][c] - li[r] * fc[c];
+      }
   }
   __syncthreads();
-  // X = L^{-1} in place by right-looking elimination on [L | I]: at step j, row j of X is
-  // finished (scaled by 1/L_jj), then every row i > j subtracts L_ij times it; X_ij takes the
-  // place of L_ij, which is staged first because step j is the last to read it.
-  __shared__ double colL[CI_MAX];  // column j of L below the diagonal, staged before X overwrites it
-  for (int j = 0; j < m; ++j) {
-    const double xjj = 1.0 / diag[j];
-    for (int c = tid; c <= j; c += 512) S[j + c * m] = (c == j) ? xjj : S[j + c * m] * xjj;
-    for (int i = j + 1 + tid; i < m; i += 512) colL[i] = S[i + j * m];
-    __syncthreads();
-    for (int c = wave; c <= j; c += 8) {  // columns over waves, rows over lanes
-      const double x = S[j + c * m];
-      for (int i = j + 1 + lane; i < m; i += 64) S[i + c * m] = (c == j ? 0.0 : S[i + c * m]) - colL[i] * x;
+  // ---- inverse, in place
+  for (int j = 0; j < mp; ++j) {
+    const int b = j & 1, jb = j >> 2, jc = j & 3;
+    const double rj = rdiag[j];
+    if (own && bi == jb) {  // row j of X: scale and publish
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        if (rr == jc) {  // wave-uniform
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int k = c0 + c;
+            if (k <= j) {
+              const double x = k == j ? rj : a[rr][c] * rj;
+              a[rr][c] = x;
+              rowv[b][k] = x;
+            }
+          }
+        }
+    }
+    if (own && bc == jb) {  // column j of L below the diagonal
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c == jc) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (r0 + r > j) colv[b][r0 + r] = a[r][c];
+        }
     }
     __syncthreads();
+    if (!own) continue;
+    double li[4], xc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) li[r] = r0 + r > j ? colv[b][r0 + r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xc[c] = c0 + c <= j ? rowv[b][c0 + c] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        // the slots of column j below the diagonal held L_ij: X_ij starts from zero
+        const bool fresh = c0 + c == j && r0 + r > j;
+        a[r][c] = (fresh ? 0.0 : a[r][c]) - li[r] * xc[c];
+      }
   }
-  for (int idx = tid; idx < m * m; idx += 512) {
-    const int i = idx % m, c = idx / m;
-    T.B[i + (size_t)c * T.ldb] = (i >= c) ? S[i + c * m] : 0.0;
+  // ---- B = L^{-1}: owned blocks, and zeros in the blocks above the diagonal
+  if (own)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = r0 + r, k = c0 + c;
+        if (i < m && k < m) T.B[i + (size_t)k * T.ldb] = i >= k ? a[r][c] : 0.0;
+      }
+  for (int idx = tid; idx < m * m; idx += 1024) {
+    const int i = idx % m, k = idx / m;
+    if ((i >> 2) < (k >> 2)) T.B[i + (size_t)k * T.ldb] = 0.0;
   }
   if (tid == 0) count_work(K_POTRF, 2ull * m * m * m / 3, 0);
 }
 
 void launch_chol_inv(const LeafTask* d_tasks, int ntasks, int max_m, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
-  HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(512), sizeof(double) * max_m * max_m, s,
-                                          d_tasks, flag));
+  if (max_m > CI_MAX) throw std::runtime_error("launch_chol_inv: leaf larger than 128");
+  HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(1024), 0, s, d_tasks, flag));
 }
 
 void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s) {

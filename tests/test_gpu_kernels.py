@@ -206,7 +206,9 @@ def test_product(n, leaf, tA, tB):
     assert np.abs(np.tril(Zd) - np.tril(Zref)).max() < 1e-9
 
 
-@pytest.mark.parametrize("n,leaf", [(64, 64), (200, 25), (300, 37), (512, 64)])
+# leaves up to 128 rows: one fused kernel; 129..256: 2 x 2 split around it; above: the looped kernels
+@pytest.mark.parametrize("n,leaf", [(64, 64), (200, 25), (300, 37), (512, 64), (5, 5), (128, 128), (129, 129),
+                                    (256, 256), (400, 200), (320, 160), (300, 300)])
 def test_cholesky_inverse(n, leaf):
     A = _kernel_matrix(n, 5)
     Z = np.eye(n) + 3.0 * A.T @ A
