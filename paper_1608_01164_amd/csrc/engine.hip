@@ -152,10 +152,25 @@ HMat Engine::alloc_hmat_in(DevArena& ar, const Tree* t, const std::vector<int>& 
 }
 void Engine::zero_ranks(HMat& h) { launch_fill_int(h.rank, 0, 2 * h.t->ninternal, st); }
 
-void Engine::gemm(const std::vector<GemmTask>& v, int max_m, int max_n) {
-  if (v.empty()) return;
-  launch_gemm(stage.upload(v, st), (int)v.size(), max_m, max_n, fp32, st);
-  ++launches;
+// Products whose k is a long true dimension (Gram matrices, V^T X over a block's rows) split K over
+// workgroups into a scratch workspace; the split depends on k alone.
+void Engine::gemm(const std::vector<GemmTask>& v0, int max_m, int max_n) {
+  if (v0.empty()) return;
+  std::vector<GemmTask> v = v0;
+  const DevArena::Mark mk = scratch.mark();
+  int zmax = 1;
+  for (GemmTask& g : v) {
+    const int S = g.kp ? 1 : gemm_splits(g.k);
+    if (S > 1 && g.m > 0 && g.n > 0) {
+      const size_t tiles = (size_t)((g.m + 63) / 64) * ((g.n + 63) / 64);
+      g.W = scratch.get<double>(tiles * S * 64 * 64);
+      g.splits = S;
+      zmax = std::max(zmax, S);
+    }
+  }
+  launch_gemm(stage.upload(v, st), (int)v.size(), max_m, max_n, fp32, st, zmax);
+  launches += zmax > 1 ? 2 : 1;
+  scratch.rewind(mk);  // later users of this memory are issued after the reduction (stream order)
 }
 void Engine::stack(const std::vector<StackTask>& v, int max_rows) {
   if (v.empty()) return;

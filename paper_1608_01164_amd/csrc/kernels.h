@@ -36,7 +36,12 @@ struct GemmTask {
   int lda, ldb, ldc;
   int opA, opB;
   double alpha, beta;
+  double* W;      // split-K: partial tiles (splits per output tile), summed in order by a second kernel
+  int splits;     // K ranges when W is set
 };
+// K ranges of a product whose k is a true dimension (no device count): a function of k alone, so
+// that a task's result never depends on what else shares its launch or on any capacity.
+inline int gemm_splits(int k) { return k < 512 ? 1 : (k / 256 < 32 ? k / 256 : 32); }
 
 // dst[:, off_s : off_s + w_s] = scale_s * src_s[:, 0 : w_s] for s = 0..nsrc-1, off_s = sum of previous widths.
 // Widest stack of factor columns the recompression kernels take (TSQR and core SVD limits).
@@ -109,7 +114,9 @@ struct BandDesc {
   double shift, inv_scale;
 };
 
-void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s);
+// max_splits: largest GemmTask::splits among the tasks (1 when none has a workspace).
+void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s,
+                 int max_splits = 1);
 void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s);
 void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, bool fp32,
                      hipStream_t s);

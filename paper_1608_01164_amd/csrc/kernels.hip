@@ -195,11 +195,25 @@ static __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_r
 
 // ----------------------------------------------------------------------------------------------
 // Batched GEMM, 64x64 output tile per workgroup (4 waves, 32x32 each = 2x2 MFMA 16x16 tiles),
-// K staged through LDS in chunks of 16.
+// K staged through LDS in chunks of 16, the next chunk's loads in flight during the current
+// chunk's MFMAs.  A task with a split-K workspace runs its K ranges in separate workgroups
+// (blockIdx.z) that write raw partial tiles; k_gemm_reduce sums them in range order.
 // ----------------------------------------------------------------------------------------------
 constexpr int GT = 64, GK = 16;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Staging map of the 4 elements a thread loads per chunk: (kk, i) of element q for a tile stored
+// column-major with leading dimension ld (op = 0: element (i, kk); op = 1: element (kk, i)).
+static __device__ __forceinline__ void stage_index(int op, int tid, int q, int& kk, int& i) {
+  if (op == 0) {
+    i = tid & 63;
+    kk = (tid >> 6) + 4 * q;
+  } else {
+    kk = tid & 15;
+    i = (tid >> 4) + 16 * q;
+  }
+}
 
 // T = double: FP64 MFMA 16x16x4; T = float: operands rounded to FP32, FP32 MFMA 16x16x4 with FP32
 // accumulation (alpha, beta and C stay FP64).
@@ -211,8 +225,16 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
   const int row0 = tm * GT, col0 = tn * GT;
   if (row0 >= m || col0 >= n) return;
+  const int S = Tk.W ? Tk.splits : 1, z = blockIdx.z;
+  if (z >= S) return;
+  int kb = 0, ke = k;
+  if (S > 1) {
+    const int kc = ((k + S - 1) / S + GK - 1) / GK * GK;
+    kb = z * kc < k ? z * kc : k;
+    ke = kb + kc < k ? kb + kc : k;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (blockIdx.x == 0 && tid == 0)
+  if (blockIdx.x == 0 && z == 0 && tid == 0)
     count_work(K_GEMM, 2ull * m * n * k,
                8ull * ((unsigned long long)m * k + (unsigned long long)k * n + (Tk.beta != 0.0 ? 2ull : 1ull) * m * n));
 
@@ -227,40 +249,37 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
 
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-
-  for (int k0 = 0; k0 < k; k0 += GK) {
-    // stage A tile (rows row0.., k cols k0..)
-    if (Tk.opA == 0) {
-      const int i = tid & 63, kk0 = tid >> 6;
+  T ra[4], rb[4];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kk = kk0 + 4 * q, gi = row0 + i, gk = k0 + kk;
-        As[kk][i] = (T)((gi < m && gk < k) ? Tk.A[gi + (size_t)gk * Tk.lda] : 0.0);
+    for (int q = 0; q < 4; ++q) {
+      int kk, i;
+      stage_index(Tk.opA, tid, q, kk, i);
+      {
+        const int gi = row0 + i, gk = k0 + kk;
+        const bool in = gi < m && gk < ke;
+        ra[q] = (T)(in ? (Tk.opA == 0 ? Tk.A[gi + (size_t)gk * Tk.lda] : Tk.A[gk + (size_t)gi * Tk.lda]) : 0.0);
       }
-    } else {
-      const int kk = tid & 15, i0 = tid >> 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = i0 + 16 * q, gi = row0 + i, gk = k0 + kk;
-        As[kk][i] = (T)((gi < m && gk < k) ? Tk.A[gk + (size_t)gi * Tk.lda] : 0.0);
+      stage_index(Tk.opB == 0 ? 1 : 0, tid, q, kk, i);
+      {
+        const int gj = col0 + i, gk = k0 + kk;
+        const bool in = gj < n && gk < ke;
+        rb[q] = (T)(in ? (Tk.opB == 0 ? Tk.B[gk + (size_t)gj * Tk.ldb] : Tk.B[gj + (size_t)gk * Tk.ldb]) : 0.0);
       }
     }
-    if (Tk.opB == 0) {
-      const int kk = tid & 15, j0 = tid >> 4;
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += GK) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = j0 + 16 * q, gj = col0 + j, gk = k0 + kk;
-        Bs[kk][j] = (T)((gj < n && gk < k) ? Tk.B[gk + (size_t)gj * Tk.ldb] : 0.0);
-      }
-    } else {
-      const int j = tid & 63, kk0 = tid >> 6;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kk = kk0 + 4 * q, gj = col0 + j, gk = k0 + kk;
-        Bs[kk][j] = (T)((gj < n && gk < k) ? Tk.B[gj + (size_t)gk * Tk.ldb] : 0.0);
-      }
+    for (int q = 0; q < 4; ++q) {
+      int kk, i;
+      stage_index(Tk.opA, tid, q, kk, i);
+      As[kk][i] = ra[q];
+      stage_index(Tk.opB == 0 ? 1 : 0, tid, q, kk, i);
+      Bs[kk][i] = rb[q];
     }
     __syncthreads();
+    if (k0 + GK < ke) load(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       const T a0 = As[kk + lk][wr + li], a1 = As[kk + lk][wr + 16 + li];
@@ -281,6 +300,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
   }
   // D(i, j) of a 16x16 block: FP64 in lane j + 16 (i % 4), element i / 4; FP32 in lane
   // j + 16 (i / 4), element i % 4
+  double* P = nullptr;
+  if (S > 1) P = Tk.W + ((size_t)(tm * ((Tk.n + GT - 1) / GT) + tn) * S + z) * (GT * GT);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -288,25 +309,54 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int ib = std::is_same<T, double>::value ? lk + 4 * e : 4 * lk + e;
-        const int gi = row0 + wr + 16 * x + ib;
-        const int gj = col0 + wc + 16 * y + li;
-        if (gi < m && gj < n) {
-          double* c = Tk.C + gi + (size_t)gj * Tk.ldc;
-          const double v = Tk.alpha * (double)acc[x][y][e];
-          *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
+        const int ti = wr + 16 * x + ib, tj = wc + 16 * y + li;
+        if (P) {
+          P[ti + GT * tj] = (double)acc[x][y][e];
+        } else {
+          const int gi = row0 + ti, gj = col0 + tj;
+          if (gi < m && gj < n) {
+            double* c = Tk.C + gi + (size_t)gj * Tk.ldc;
+            const double v = Tk.alpha * (double)acc[x][y][e];
+            *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
+          }
         }
       }
 }
 
-void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s) {
+// C = alpha * (sum of the split-K partial tiles, in range order) + beta * C.
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmTask* __restrict__ tasks, int tiles_n) {
+  const GemmTask Tk = tasks[blockIdx.y];
+  if (!Tk.W || Tk.splits <= 1) return;
+  const int m = live(Tk.mp, Tk.m), n = live(Tk.np, Tk.n);
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int row0 = tm * GT, col0 = tn * GT;
+  if (row0 >= m || col0 >= n) return;
+  const int S = Tk.splits;
+  const double* P = Tk.W + (size_t)(tm * ((Tk.n + GT - 1) / GT) + tn) * S * (GT * GT);
+  for (int e = threadIdx.x; e < GT * GT; e += 256) {
+    const int ti = e % GT, tj = e / GT, gi = row0 + ti, gj = col0 + tj;
+    if (gi >= m || gj >= n) continue;
+    double sum = 0.0;
+    for (int z = 0; z < S; ++z) sum += P[(size_t)z * (GT * GT) + e];
+    double* c = Tk.C + gi + (size_t)gj * Tk.ldc;
+    const double v = Tk.alpha * sum;
+    *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
+  }
+}
+
+void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s,
+                 int max_splits) {
   if (ntasks <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = (max_m + GT - 1) / GT, tn = (max_n + GT - 1) / GT;
+  const int zs = max_splits > 1 ? max_splits : 1;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
     if (fp32)
-      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm<float>, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn));
+      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm<float>, dim3(tm * tn, nt, zs), dim3(256), 0, s, d_tasks + t0, tn));
     else
-      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm<double>, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn));
+      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm<double>, dim3(tm * tn, nt, zs), dim3(256), 0, s, d_tasks + t0, tn));
+    if (zs > 1)
+      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm_reduce, dim3(tm * tn, nt), dim3(256), 0, s, d_tasks + t0, tn));
   }
 }
 
@@ -883,20 +933,26 @@ static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r
   __syncthreads();
   T qth2 = (T)(Tk.qr_thresh * Tk.qr_thresh);
   for (int j = 0; j < r; ++j) {
-    T s = 0;
-    ArgMax<T> am{(T)-1, 0x7fffffff};
-    for (int c = j + tid; c < r; c += SVD_THREADS) {
-      s += cn[c];
-      if (cn[c] > am.v) { am.v = cn[c]; am.i = c; }
+    // trailing norms and the pivot: one column per thread (r <= SVD_THREADS), and only the waves
+    // that hold trailing columns take part (waves issue nothing for the others)
+    const int nact = (r - j + 63) >> 6;
+    if (wave < nact) {
+      T s = 0;
+      ArgMax<T> am{(T)-1, 0x7fffffff};
+      const int c = j + tid;
+      if (c < r) {
+        s = cn[c];
+        am.v = s;
+        am.i = c;
+      }
+      s = wave_sum(s);
+      am = wave_argmax(am);
+      if (lane == 0) { S.redv[wave] = s; S.reda[wave] = am; }
     }
-    s = wave_sum(s);
-    am = wave_argmax(am);
-    if (lane == 0) { S.redv[wave] = s; S.reda[wave] = am; }
     __syncthreads();
     T tot = 0;
     ArgMax<T> best = S.reda[0];
-#pragma unroll
-    for (int w = 0; w < SVD_WAVES; ++w) {
+    for (int w = 0; w < nact; ++w) {
       tot += S.redv[w];
       const ArgMax<T> x = S.reda[w];
       if (x.v > best.v || (x.v == best.v && x.i < best.i)) best = x;
@@ -924,14 +980,19 @@ static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r
       }
       __syncthreads();
     }
-    // reflector from the trailing norm of the pivot column (rows j..r-1)
-    const T nrm = sqrt(cn[j]), x0 = Bm[j + (size_t)j * ldb];
-    const T beta = x0 >= 0 ? -nrm : nrm;
-    const T vj = x0 - beta;
-    const T tj = nrm > 0 ? (T)1 / (nrm * (nrm + fabs(x0))) : (T)0;
+    // reflector from the trailing norm of the pivot column (rows j..r-1); computed by the waves with
+    // trailing columns and by wave 0, which stores it
+    T beta = 0, vj = 0, tj = 0;
+    if (wave == 0 || j + 1 + 4 * wave < r) {
+      const T nrm = sqrt(cn[j]), x0 = Bm[j + (size_t)j * ldb];
+      beta = x0 >= 0 ? -nrm : nrm;
+      vj = x0 - beta;
+      tj = nrm > 0 ? (T)1 / (nrm * (nrm + fabs(x0))) : (T)0;
+    }
     // trailing columns: four per wave, one per group of 16 lanes; uniform control flow around the
     // row reductions, rows of invalid groups predicated off
     if constexpr (EM > 0) {
+      if (j + 1 + 4 * wave < r) {
       // whole elements from the one holding row j: the reflector is zero above row j, so rows above
       // j pass through unchanged (and are stored back as they were)
       const int e0 = j >> 4, e1 = (r + 15) >> 4, jl = j & 15;  // row j is lane jl of element e0
@@ -961,6 +1022,7 @@ static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r
           seg_store<EM>(x, col, e0, e1, sl);
           if (sl == 0) cn[c] = nn;  // exact trailing norm for the next step
         }
+      }
       }
     } else {
       T* vl = S.vl;
@@ -1463,9 +1525,11 @@ __global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ task
 }
 
 // Leaf Cholesky and triangular inverse for m <= 128, with the tile in registers: the lower
-// triangle is cut into 4 x 4 blocks, one per thread (at most 528 blocks), padded with the identity
-// to a multiple of 4.  Step j of either phase publishes one column (and row) through LDS, double
-// buffered, so that each step costs one barrier.
+// triangle is cut into 4 x 4 blocks, one per thread (at most 528 blocks), numbered column by column
+// so that the threads whose columns are finished (Cholesky) or not yet reached (inverse) fill whole
+// waves that skip the step; the tile is padded with the identity to a multiple of 4.  Step j of
+// either phase publishes one column (and row) through LDS, double buffered, so each step costs one
+// barrier.
 //   Cholesky (right-looking): publish column j of the trailing matrix and the pivot; every block
 //     right of j subtracts a_ij a_cj / d; the owners of column j scale it by 1/sqrt(d).
 //   Inverse X = L^{-1} in place (right-looking elimination on [L | I]): row j of X, complete after
@@ -1480,11 +1544,13 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ 
   const int nb = (m + 3) >> 2, mp = 4 * nb;
   const bool own = tid < nb * (nb + 1) / 2;
   int bi = 0, bc = 0;
-  if (own) {  // lower-triangular block number tid -> (bi, bc), bi >= bc
-    bi = (int)((sqrtf(8.0f * (float)tid + 1.0f) - 1.0f) * 0.5f);
-    while (bi * (bi + 1) / 2 > tid) --bi;
-    while ((bi + 1) * (bi + 2) / 2 <= tid) ++bi;
-    bc = tid - bi * (bi + 1) / 2;
+  if (own) {  // block number tid, column by column: column bc holds blocks bi = bc .. nb - 1
+    int t = tid;
+    while (t >= nb - bc) {
+      t -= nb - bc;
+      ++bc;
+    }
+    bi = bc + t;
   }
   const int r0 = 4 * bi, c0 = 4 * bc;
   double a[4][4];
@@ -1507,9 +1573,15 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ 
   __shared__ double rowv[2][CI_PAD];  // row j of X (inverse)
   __shared__ double piv[2][2];        // 1/d and sqrt(d) of step j
   __shared__ double rdiag[CI_PAD];    // 1 / L_jj
-  // Updates are branch-free over the 16 entries: factors that are zero outside the rows and columns
-  // a step touches.  Entries above the diagonal of diagonal blocks take junk, which nothing reads
-  // (they are written out as zeros).
+  // The updates are plain FMAs over the 16 entries with factors that vanish outside the rows and
+  // columns a step touches; entries above the diagonal of diagonal blocks take junk, which nothing
+  // reads (they are written out as zeros).  The exchange buffers start at zero, so that every
+  // entry read (then masked) is finite.
+  for (int i = tid; i < 2 * CI_PAD; i += 1024) {
+    (&colv[0][0])[i] = 0.0;
+    (&rowv[0][0])[i] = 0.0;
+  }
+  __syncthreads();
   // ---- Cholesky
   for (int j = 0; j < mp; ++j) {
     const int b = j & 1, jb = j >> 2, jc = j & 3;
@@ -1534,28 +1606,35 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ 
         }
     }
     __syncthreads();
-    if (!own) continue;
-    const double inv_d = piv[b][0], s = piv[b][1], rs = rdiag[j];
-    double li[4], fc[4], sc[4], ad[4];
+    if (!own || c0 + 3 < j) continue;  // columns of this block finished
+    if (bc == jb) {  // column j: rows below scaled by 1/sqrt(d), the pivot replaced by sqrt(d)
+      const double s = piv[b][1], rs = rdiag[j];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = r0 + r;
-      li[r] = i > j ? colv[b][i] : 0.0;
-      sc[r] = i > j ? rs : (i == j ? 0.0 : 1.0);  // column j: rows below scaled, the pivot replaced by sqrt(d)
-      ad[r] = i == j ? s : 0.0;
+      for (int c = 0; c < 4; ++c)
+        if (c == jc) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = r0 + r;
+            a[r][c] = i > j ? a[r][c] * rs : (i == j ? s : a[r][c]);
+          }
+        }
     }
+    if (c0 + 3 > j) {
+      const double inv_d = piv[b][0];
+      double li[4], fc[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = c0 + c;
-      fc[c] = k > j ? colv[b][k] * inv_d : 0.0;
+      for (int r = 0; r < 4; ++r) li[r] = colv[b][r0 + r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fc[c] = colv[b][c0 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) li[r] = r0 + r > j ? li[r] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fc[c] = c0 + c > j ? fc[c] * inv_d : 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[r][c] -= li[r] * fc[c];
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const bool colj = c0 + c == j;
-        a[r][c] = colj ? a[r][c] * sc[r] + ad[r] : a[r][c] - li[r] * fc[c];
-      }
   }
   __syncthreads();
   // ---- inverse, in place
@@ -1587,20 +1666,28 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ 
         }
     }
     __syncthreads();
-    if (!own) continue;
+    if (!own || c0 > j || r0 + 3 <= j) continue;  // no row below j, or no column up to j
+    if (bc == jb) {  // the slots of column j below the diagonal held L_ij: X_ij starts from zero
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c == jc) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[r][c] = r0 + r > j ? 0.0 : a[r][c];
+        }
+    }
     double li[4], xc[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) li[r] = r0 + r > j ? colv[b][r0 + r] : 0.0;
+    for (int r = 0; r < 4; ++r) li[r] = colv[b][r0 + r];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) xc[c] = c0 + c <= j ? rowv[b][c0 + c] : 0.0;
+    for (int c = 0; c < 4; ++c) xc[c] = rowv[b][c0 + c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) li[r] = r0 + r > j ? li[r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xc[c] = c0 + c <= j ? xc[c] : 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        // the slots of column j below the diagonal held L_ij: X_ij starts from zero
-        const bool fresh = c0 + c == j && r0 + r > j;
-        a[r][c] = (fresh ? 0.0 : a[r][c]) - li[r] * xc[c];
-      }
+      for (int c = 0; c < 4; ++c) a[r][c] -= li[r] * xc[c];
   }
   // ---- B = L^{-1}: owned blocks, and zeros in the blocks above the diagonal
   if (own)

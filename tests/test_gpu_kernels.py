@@ -11,7 +11,9 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("m,n,k,opA,opB", [
     (1, 1, 1, 0, 0), (64, 64, 16, 0, 0), (65, 63, 17, 0, 1), (130, 7, 300, 1, 0), (33, 129, 5, 1, 1),
-    (1000, 40, 40, 0, 0), (40, 40, 3000, 1, 0), (7, 3, 0, 0, 0)])
+    (1000, 40, 40, 0, 0), (40, 40, 3000, 1, 0), (7, 3, 0, 0, 0),
+    # split K (k >= 512): 2, 3 and 32 ranges, ragged tiles
+    (70, 150, 513, 1, 0), (150, 150, 1023, 1, 0), (129, 65, 8192, 1, 1), (64, 64, 8200, 0, 0)])
 def test_gemm(m, n, k, opA, opB):
     rng = np.random.default_rng(m * 7 + n)
     A = rng.standard_normal((k, m) if opA else (m, k))

@@ -4,6 +4,7 @@ import pytest
 
 import paper_1608_01164_amd as hq
 import workloads as w
+from tests.gpu_util import mixed_bound
 from oracle import eig, hodlr as oh, norms, qdwh
 
 pytestmark = pytest.mark.gpu
@@ -131,10 +132,6 @@ MIXED_CASES = [
 # 4 u32 sqrt(rows) sigma_1; the part of that perturbation that couples eigenvectors on opposite sides
 # of mu rotates the invariant subspace, and no later (FP64) iteration undoes a rotation, so the
 # error grows like (levels) x (noise level of the largest blocks), times the FP32 iterations.
-def mixed_bound(n, levels, fp32_iters):
-    return 2.0 * fp32_iters * levels * 4 * 2.0 ** -24 * np.sqrt(n / 2)
-
-
 @pytest.mark.parametrize("name,maker,b,leaf", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
 def test_mixed_precision_projector(name, maker, b, leaf):
     """Mixed mode: middle iterations in FP32.  The error against the oracle is reported and held to
