@@ -116,10 +116,15 @@ static void check_launch(const char* what) {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// A value every lane of the wave holds, as the compiler's scalar (wave-uniform) value: control flow
+// that depends on it becomes scalar branches instead of lane masks.
+static __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Live size of a task: the device count behind p (a per-task value), capped by the static bound v.
 static __device__ __forceinline__ int live(const int* p, int v) {
   if (!p) return v;
-  int x = *p;
-  return x < v ? x : v;
+  const int x = *p;
+  return uniform(x < v ? x : v);
 }
 
 // Data-parallel-primitive move of a double (two 32-bit DPP moves); rows/banks masked off read 0.
@@ -159,20 +164,22 @@ static __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Sum over a group of 16 consecutive lanes, returned to every lane of the group (groups stay
-// independent): butterfly exchanges of width 16.
+// Sum over a group of 16 consecutive lanes (one DPP row), returned to every lane of the group:
+// quad swaps, then the half-row mirror (lane i <-> 7 - i) and the row mirror (lane i <-> 15 - i).
+// Every step is a permutation inside the row, so every lane ends with the same value.  Call with
+// all lanes of the wave active.
 static __device__ __forceinline__ double row_sum(double v) {
-  v += __shfl_xor(v, 1, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 8, 16);
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
   return v;
 }
 static __device__ __forceinline__ float row_sum(float v) {
-  v += __shfl_xor(v, 1, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 8, 16);
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
   return v;
 }
 
@@ -188,10 +195,6 @@ template <> struct Prec<float> {
   static constexpr float scale_below = 0x1p-100f;
   static constexpr int max_shift = 100;
 };
-
-// A value every lane of the wave holds, as the compiler's scalar (wave-uniform) value: control flow
-// that depends on it becomes scalar branches instead of lane masks.
-static __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ----------------------------------------------------------------------------------------------
 // Batched GEMM, 64x64 output tile per workgroup (4 waves, 32x32 each = 2x2 MFMA 16x16 tiles),
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
     kb = z * kc < k ? z * kc : k;
     ke = kb + kc < k ? kb + kc : k;
   }
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
   if (blockIdx.x == 0 && z == 0 && tid == 0)
     count_work(K_GEMM, 2ull * m * n * k,
                8ull * ((unsigned long long)m * k + (unsigned long long)k * n + (Tk.beta != 0.0 ? 2ull : 1ull) * m * n));
@@ -441,7 +444,7 @@ static __device__ void householder_rows(T* X, int ld, int h, int r) {
   __shared__ T cn[QR_RMAX];  // squared norm of column c below row j, for the next pivot
   __shared__ T red[QR_WAVES];
   __shared__ T sh_v0, sh_tau;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
   const int jend = (h - 1 < r) ? h - 1 : r;
   if (jend <= 0) return;
   if (wave == 0) {
@@ -558,7 +561,7 @@ static __device__ void householder_rows_blocked(T* X, int ld, int h, int r, T* V
   __shared__ T gram[QR_NB * QR_NB];
   __shared__ T red[QR_WAVES];
   __shared__ T sh_v0, sh_tau, sh_beta;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
   const int jend = (h - 1 < r) ? h - 1 : r;
   unsigned long long flops = 0;
   for (int j0 = 0; j0 < jend; j0 += NB) {
