@@ -106,6 +106,17 @@ static void check_launch(const char* what) {
   if (e != hipSuccess) throw std::runtime_error(std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
 }
 
+// Static plus dynamic LDS of a kernel must fit the 160 KiB of a workgroup; a dispatch above it is
+// only rejected by the queue, after the launch call has returned.  Checked once per kernel.
+static void check_lds(const void* kernel, size_t dynamic_bytes, const char* what) {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, kernel) != hipSuccess)
+    throw std::runtime_error(std::string("cannot read the attributes of ") + what);
+  if (a.sharedSizeBytes + dynamic_bytes > 160 * 1024)
+    throw std::runtime_error(std::string(what) + ": static LDS " + std::to_string(a.sharedSizeBytes) + " + dynamic " +
+                             std::to_string(dynamic_bytes) + " bytes exceed 160 KiB");
+}
+
 #define HQ_TIMED(cls, stream, ...)            \
   do {                                        \
     const int slot_ = prof_begin(stream);     \
@@ -439,6 +450,148 @@ static __device__ T block_reduce(T v, T* red) {
   return t;
 }
 
+// Maximum over the 16 lanes of a DPP row (the permutations of row_sum).
+static __device__ __forceinline__ double row_max(double v) {
+  v = fmax(v, dpp_move<0xB1>(v));
+  v = fmax(v, dpp_move<0x4E>(v));
+  v = fmax(v, dpp_move<0x141>(v));
+  v = fmax(v, dpp_move<0x140>(v));
+  return v;
+}
+static __device__ __forceinline__ float row_max(float v) {
+  v = fmaxf(v, dpp_move<0xB1>(v));
+  v = fmaxf(v, dpp_move<0x4E>(v));
+  v = fmaxf(v, dpp_move<0x141>(v));
+  v = fmaxf(v, dpp_move<0x140>(v));
+  return v;
+}
+
+// Householder triangularisation of a small row tile (h <= 16 EM rows, r <= 64 CPG columns) held in
+// registers: column c belongs to the 16-lane group c % 64 (slot c / 64), its rows sl + 16 e to lane
+// sl.  Step j: the wave holding column j forms the reflector from that column (fresh norm below the
+// diagonal; a column near underflow is first rescaled by an exact power of two) and publishes it
+// through LDS, double buffered and zero above row j; the groups holding columns right of j apply
+// it.  One barrier per step, and the reflectors are not kept (R only).  R (min(h, r) x r, upper
+// trapezoidal) goes to out (leading dimension ldo).  Every row reduction runs with the whole wave
+// active; what a group computes for a column it does not own is discarded.
+template <typename T, int EM, int CPG>
+static __device__ void householder_regs(const double* src, int lds, T* out, int ldo, int h, int r, int* flag,
+                                        int fidx, T* dyn) {
+  // exchange buffers in the kernel's dynamic LDS: 2 x 16 EM reflector rows, then 2 factors
+  T(*vbuf)[16 * EM] = reinterpret_cast<T(*)[16 * EM]>(dyn);
+  T* tbuf = dyn + 2 * 16 * EM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane >> 4, sl = lane & 15;
+  const int g = tid >> 4;  // group: 4 * wave + sub
+  T x[CPG][EM];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < CPG; ++k)
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+      const int c = 64 * k + g, i = sl + 16 * e;
+      double v = 0.0;
+      if (c < r && i < h) v = src[i + (size_t)c * lds];
+      bad |= !(fabs(v) <= DBL_MAX);
+      x[k][e] = (T)v;
+    }
+  if (bad) atomicOr(flag + fidx, 16);  // non-finite stacked input
+  const int jend = (h - 1 < r) ? h - 1 : r;
+  unsigned long long flops = 0;
+  for (int j = 0; j < jend; ++j) {
+    const int b = j & 1, go = j & 63, kj = j >> 6;
+    if (wave == (go >> 2)) {
+      const bool owner = sub == (go & 3);
+#pragma unroll
+      for (int k = 0; k < CPG; ++k)
+        if (k == kj) {  // wave-uniform
+          T x0 = 0, s = 0, am = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) {
+            const int i = sl + 16 * e;
+            const T v = x[k][e];
+            x0 += i == j ? v : (T)0;
+            s += i > j ? v * v : (T)0;
+            am = fmax(am, i >= j ? fabs(v) : (T)0);
+          }
+          x0 = row_sum(x0);
+          s = row_sum(s);
+          am = row_max(am);
+          // near underflow: rows j.. rescaled by 2^-e (as two factors when 2^-e is not representable)
+          const bool scaled = s < Prec<T>::scale_below && am > (T)0;
+          T sc1 = 1, sc2 = 1, unscale = 1;
+          if (scaled) {
+            constexpr int M = Prec<T>::max_shift;
+            const int ex = ilogb(am);
+            sc1 = ldexp((T)1, -ex > M ? M : -ex);
+            sc2 = ldexp((T)1, -ex > M ? -ex - M : 0);
+            unscale = ldexp((T)1, ex);
+          }
+          T x0s = 0, ss = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) {
+            const int i = sl + 16 * e;
+            const T v = i >= j ? (x[k][e] * sc1) * sc2 : x[k][e];
+            x0s += i == j ? v : (T)0;
+            ss += i > j ? v * v : (T)0;
+            if (owner) x[k][e] = v;
+          }
+          x0s = row_sum(x0s);
+          ss = row_sum(ss);
+          if (scaled) {
+            x0 = x0s;
+            s = ss;
+          }
+          T tau = 0, v0 = 0, rjj = x0 * unscale;
+          if (s != (T)0) {
+            const T nrm = sqrt(x0 * x0 + s);
+            const T beta = x0 >= 0 ? -nrm : nrm;
+            v0 = x0 - beta;
+            tau = (T)1 / (nrm * (nrm + fabs(x0)));
+            rjj = beta * unscale;
+          }
+#pragma unroll
+          for (int e = 0; e < EM; ++e) {
+            const int i = sl + 16 * e;
+            if (owner) {
+              vbuf[b][i] = i > j ? x[k][e] : (i == j ? v0 : (T)0);
+              if (i == j) x[k][e] = rjj;
+            }
+          }
+          if (owner && sl == 0) tbuf[b] = tau;
+        }
+    }
+    __syncthreads();
+    const T tau = tbuf[b];
+    if (64 * (CPG - 1) + 4 * wave + 3 > j && tau != (T)0) {  // some slot of this wave right of j
+      T v[EM];
+#pragma unroll
+      for (int e = 0; e < EM; ++e) v[e] = vbuf[b][sl + 16 * e];
+#pragma unroll
+      for (int k = 0; k < CPG; ++k)
+        if (64 * k + 4 * wave + 3 > j && 64 * k + 4 * wave < r) {  // wave-uniform
+          const int c = 64 * k + g;
+          const bool act = c > j && c < r;
+          T w = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) w += v[e] * x[k][e];
+          w = row_sum(w) * tau;
+          if (!act) w = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) x[k][e] -= w * v[e];
+        }
+    }
+    if (tid == 0) flops += 2ull * (h - j) + 4ull * (unsigned long long)(h - j) * (r - j - 1);
+  }
+#pragma unroll
+  for (int k = 0; k < CPG; ++k)
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+      const int c = 64 * k + g, i = sl + 16 * e;
+      if (c < r && i < h && i <= c) out[i + (size_t)c * ldo] = x[k][e];
+    }
+  if (tid == 0) count_work(K_QR, flops, 0);
+}
+
 template <typename T>
 static __device__ void householder_rows(T* X, int ld, int h, int r) {
   __shared__ T cn[QR_RMAX];  // squared norm of column c below row j, for the next pivot
@@ -763,6 +916,15 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
     src1 = work + (size_t)b * Tk.hs * Tk.rcap;
     h = ra + rb;
   }
+  // small row tiles: the whole tile in registers
+  if (stage == 0 && h <= 128 && r <= 256) {
+    householder_regs<T, 8, 4>(srcM, ld0, slot, Tk.hs, h, r, flag, Tk.fidx, qlds);
+    return;
+  }
+  if (stage == 0 && h <= 256 && r <= 128) {
+    householder_regs<T, 16, 2>(srcM, ld0, slot, Tk.hs, h, r, flag, Tk.fidx, qlds);
+    return;
+  }
   const bool inl = h * r <= kLds;
   T* X = inl ? qlds : slot;
   const int ldx = inl ? h : Tk.hs;
@@ -825,6 +987,11 @@ __global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tas
 void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, bool fp32,
                      hipStream_t s) {
   if (ntasks <= 0 || max_pairs <= 0) return;
+  static std::once_flag lds_ok;
+  std::call_once(lds_ok, [] {
+    check_lds((const void*)k_qr_stage<double>, QR_LDS_BYTES, "k_qr_stage<double>");
+    check_lds((const void*)k_qr_stage<float>, QR_LDS_BYTES, "k_qr_stage<float>");
+  });
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
     if (fp32)
@@ -1458,6 +1625,11 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
 
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s) {
   if (ntasks <= 0) return;
+  static std::once_flag lds_ok;
+  std::call_once(lds_ok, [] {
+    check_lds((const void*)k_svd<double>, SVD_LDS_BYTES, "k_svd<double>");
+    check_lds((const void*)k_svd<float>, SVD_LDS_BYTES, "k_svd<float>");
+  });
   if (fp32)
     HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<float>, dim3(ntasks), dim3(SVD_THREADS), SVD_LDS_BYTES, s, d_tasks,
                                           flag));

@@ -54,7 +54,7 @@ def test_gemm_fp32(m, n, k, opA, opB):
     assert (np.abs(host(dC, m, n) - ref) <= bound + 1e-12).all()
 
 
-@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (700, 200), (5000, 150)])
+@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (700, 200), (5000, 150), (128, 100), (200, 90)])
 def test_qr_r_fp32(rows, r):
     rng = np.random.default_rng(rows + r + 1)
     M = rng.standard_normal((rows, r)) * np.logspace(0, -3, r)[None, :]
@@ -67,7 +67,10 @@ def test_qr_r_fp32(rows, r):
     assert np.abs(R.T @ R - Rn.T @ Rn).max() <= 50 * np.finfo(np.float32).eps * np.linalg.norm(M, 2) ** 2
 
 
-@pytest.mark.parametrize("rows,r", [(1, 1), (5, 9), (64, 64), (300, 20), (2000, 37), (9000, 64), (700, 200)])
+# tiles of at most 128 rows and 256 columns, or 256 rows and 128 columns, are factored in registers
+@pytest.mark.parametrize("rows,r", [(1, 1), (5, 9), (64, 64), (300, 20), (2000, 37), (9000, 64), (700, 200),
+                                    (128, 200), (128, 256), (100, 130), (129, 60), (200, 100), (256, 128),
+                                    (250, 129)])
 def test_qr_r(rows, r):
     rng = np.random.default_rng(rows + r)
     M = rng.standard_normal((rows, r)) * np.logspace(0, -12, r)[None, :]
@@ -105,7 +108,7 @@ def test_recompress_fp32(m, n, r, decay):
     assert np.linalg.norm(Uh @ Vh.T - M, 2) <= 4 * eff
 
 
-@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (120, 90)])
+@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (120, 90), (200, 60)])
 def test_qr_r_columns_near_underflow(rows, r):
     """Columns scaled into the range where squared norms are denormal or underflow: the
     triangular factor stays finite and matches LAPACK's column by column (relative to each
