@@ -68,7 +68,7 @@ class DevArena {
   size_t cur_ = 0, inuse_ = 0, high_ = 0;
 };
 
-// Host-pinned staging + device copies for task descriptors.
+// Task descriptors in pinned host memory that the kernels read directly.
 class DescStage {
  public:
   DescStage() = default;
@@ -80,7 +80,7 @@ class DescStage {
   void reset();  // only after the stream has drained
  private:
   void* up(const void* src, size_t bytes, hipStream_t s);
-  struct Chunk { char* h; char* d; size_t cap, used; };
+  struct Chunk { char* h; size_t cap, used; };
   std::vector<Chunk> chunks_;
   size_t cur_ = 0;
 };

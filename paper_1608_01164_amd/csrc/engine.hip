@@ -74,12 +74,14 @@ void DevArena::reset() {
 }
 
 DescStage::~DescStage() {
-  for (auto& c : chunks_) {
-    (void)hipHostFree(c.h);
-    (void)hipFree(c.d);
-  }
+  for (auto& c : chunks_) (void)hipHostFree(c.h);
 }
+// Descriptors are written into pinned, device-visible host memory and read by the kernels from
+// there: no copy launch per kernel launch (each workgroup reads its few hundred bytes once).  The
+// host stores precede the launch that reads them; chunks are reused only after reset(), which the
+// callers issue once the stream has drained.
 void* DescStage::up(const void* src, size_t bytes, hipStream_t s) {
+  (void)s;
   if (bytes == 0) return nullptr;
   const size_t need = (bytes + 255) & ~size_t(255);
   while (cur_ < chunks_.size() && chunks_[cur_].used + need > chunks_[cur_].cap) ++cur_;
@@ -87,14 +89,12 @@ void* DescStage::up(const void* src, size_t bytes, hipStream_t s) {
     Chunk c;
     c.cap = std::max(need, size_t(32) << 20);
     HQ_CHECK(hipHostMalloc((void**)&c.h, c.cap, hipHostMallocDefault));
-    HQ_CHECK(hipMalloc((void**)&c.d, c.cap));
     c.used = 0;
     chunks_.push_back(c);
   }
   Chunk& c = chunks_[cur_];
   std::memcpy(c.h + c.used, src, bytes);
-  HQ_CHECK(hipMemcpyAsync(c.d + c.used, c.h + c.used, bytes, hipMemcpyHostToDevice, s));
-  void* d = c.d + c.used;
+  void* d = c.h + c.used;
   c.used += need;
   return d;
 }
