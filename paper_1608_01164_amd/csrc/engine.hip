@@ -308,9 +308,9 @@ QrPlan plan_qr(int m, int rcap) {
 
 namespace {
 // Device workspace of one recompression task (TSQR slots of both sides, cores, outputs).
-// Leading dimension of the core-SVD workspaces: rows padded to a multiple of 16 (the kernel keeps
-// whole 16-row segments of a column in registers).
-int svd_ld(int rc) { return (std::max(rc, 1) + 15) & ~15; }
+// Leading dimension of the core-SVD workspaces: rows padded to a multiple of 32 (the kernel keeps
+// whole 16- or 32-row segments of a column in registers).
+int svd_ld(int rc) { return (std::max(rc, 1) + 31) & ~31; }
 
 size_t rec_bytes(int m, int n, int rcap, int kcap) {
   const size_t rc = std::max(rcap, 1), kc = std::max(kcap, 1), ls = svd_ld(rcap);

@@ -1036,22 +1036,30 @@ static __device__ __forceinline__ ArgMax<T> wave_argmax(ArgMax<T> a) {
   return a;
 }
 
-// Register segments of padded columns: element e (e0 <= e < e1, wave-uniform bounds) of the group
-// holds row sl + 16 e; elements outside [e0, e1) are zero and skipped.  Columns are stored with a
-// leading dimension that is a multiple of 16 and zero rows below their length, so whole elements
-// are always in bounds.
-template <int EM, typename T, typename X>
+// Register segments of padded columns: a group of G lanes (16 or 32) holds a column, element e
+// (e0 <= e < e1, wave-uniform bounds) of lane sl being row sl + G e; elements outside [e0, e1) are
+// zero and skipped.  Columns are stored with a leading dimension that is a multiple of G and zero
+// rows below their length, so whole elements are always in bounds.
+template <int EM, int G, typename T, typename X>
 static __device__ __forceinline__ void seg_load(X (&x)[EM], const T* p, int e0, int e1, int sl) {
   const T* q = p + sl;
 #pragma unroll
-  for (int e = 0; e < EM; ++e) x[e] = (e >= e0 && e < e1) ? (X)q[16 * e] : (X)0;
+  for (int e = 0; e < EM; ++e) x[e] = (e >= e0 && e < e1) ? (X)q[G * e] : (X)0;
 }
-template <int EM, typename T, typename X>
+template <int EM, int G, typename T, typename X>
 static __device__ __forceinline__ void seg_store(const X (&x)[EM], T* p, int e0, int e1, int sl) {
   T* q = p + sl;
 #pragma unroll
   for (int e = 0; e < EM; ++e)
-    if (e >= e0 && e < e1) q[16 * e] = (T)x[e];
+    if (e >= e0 && e < e1) q[G * e] = (T)x[e];
+}
+
+// Sum over a group of G lanes (one or two DPP rows), returned to every lane of the group.
+template <int G, typename T>
+static __device__ __forceinline__ T group_sum(T v) {
+  v = row_sum(v);
+  if constexpr (G == 32) v += __shfl_xor(v, 16, 64);
+  return v;
 }
 
 // Tangent, cosine and sine of the plane rotation that makes two columns with squared norms a, b
@@ -1087,11 +1095,12 @@ struct SvdShared {
 // Frobenius norm is at most qr_thresh (FP32: at least a tenth of B's FP32 noise).  Returns t;
 // the reflectors sit below the diagonal of Bm's first t columns with their heads in vhead[] and
 // factors in tau[]; perm holds the column order.  Non-finite norms set bit 3 of the status word.
-template <typename T, int EM>
+template <typename T, int EM, int G>
 static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r, const SvdTask& Tk, int* flag,
                                                const SvdShared<T>& S, T* tau, T* vhead) {
   constexpr bool dbl = std::is_same<T, double>::value;
-  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane >> 4, sl = lane & 15;
+  constexpr int GPW = 64 / G;  // groups per wave
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane / G, sl = lane & (G - 1);
   T* cn = S.cn;
   int* perm = S.perm;
   for (int c = wave; c < r; c += SVD_WAVES) {
@@ -1153,7 +1162,7 @@ static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r
     // reflector from the trailing norm of the pivot column (rows j..r-1); computed by the waves with
     // trailing columns and by wave 0, which stores it
     T beta = 0, vj = 0, tj = 0;
-    if (wave == 0 || j + 1 + 4 * wave < r) {
+    if (wave == 0 || j + 1 + GPW * wave < r) {
       const T nrm = sqrt(cn[j]), x0 = Bm[j + (size_t)j * ldb];
       beta = x0 >= 0 ? -nrm : nrm;
       vj = x0 - beta;
@@ -1162,34 +1171,34 @@ static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r
     // trailing columns: four per wave, one per group of 16 lanes; uniform control flow around the
     // row reductions, rows of invalid groups predicated off
     if constexpr (EM > 0) {
-      if (j + 1 + 4 * wave < r) {
+      if (j + 1 + GPW * wave < r) {
       // whole elements from the one holding row j: the reflector is zero above row j, so rows above
       // j pass through unchanged (and are stored back as they were)
-      const int e0 = j >> 4, e1 = (r + 15) >> 4, jl = j & 15;  // row j is lane jl of element e0
+      const int e0 = j / G, e1 = (r + G - 1) / G, jl = j % G;  // row j is lane jl of element e0
       T v[EM];
-      seg_load<EM>(v, Bm + (size_t)j * ldb, e0, e1, sl);
+      seg_load<EM, G>(v, Bm + (size_t)j * ldb, e0, e1, sl);
 #pragma unroll
       for (int e = 0; e < EM; ++e)
         if (e == e0) v[e] = sl > jl ? v[e] : (sl == jl ? vj : (T)0);
-      for (int cc = j + 1 + 4 * wave; cc < r; cc += 4 * SVD_WAVES) {
+      for (int cc = j + 1 + GPW * wave; cc < r; cc += GPW * SVD_WAVES) {
         const int c = cc + sub;
         const bool valid = c < r;
         T* col = Bm + (size_t)(valid ? c : cc) * ldb;
         T x[EM];
-        seg_load<EM>(x, col, e0, e1, sl);
+        seg_load<EM, G>(x, col, e0, e1, sl);
         T w = 0;
 #pragma unroll
         for (int e = 0; e < EM; ++e) w += v[e] * x[e];
-        w = row_sum(w) * tj;
+        w = group_sum<G>(w) * tj;
         T nn = 0;
 #pragma unroll
         for (int e = 0; e < EM; ++e) {
           x[e] -= w * v[e];
           if (e != e0 || sl > jl) nn += x[e] * x[e];  // rows below j
         }
-        nn = row_sum(nn);
+        nn = group_sum<G>(nn);
         if (valid) {
-          seg_store<EM>(x, col, e0, e1, sl);
+          seg_store<EM, G>(x, col, e0, e1, sl);
           if (sl == 0) cn[c] = nn;  // exact trailing norm for the next step
         }
       }
@@ -1235,15 +1244,16 @@ static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r
 //        Jk[perm[c], o] = W[c, ord(o)] / sigma      (right singular vectors)
 //        Wk = Q_t [J[:, ord(o)] / sigma ; 0]         (left singular vectors over sigma)
 // Returns the number of sweeps.
-template <typename T, int EM>
+template <typename T, int EM, int G>
 static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C, const int ldc, T* J, const int ldj,
                                                const int r, const int t, const SvdTask& Tk, int* flag,
                                                const SvdShared<T>& S, const T* tau, const T* vhead,
                                                unsigned& my_pairs, unsigned& my_rots, unsigned long long& c2) {
   constexpr bool dbl = std::is_same<T, double>::value;
-  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane >> 4, sl = lane & 15;
-  // rows padded to multiples of 16 with zeros (rotations keep them zero)
-  const int rpad = (r + 15) & ~15, tpad = (t + 15) & ~15, er = rpad >> 4, et = tpad >> 4;
+  constexpr int GPW = 64 / G;  // groups per wave
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane / G, sl = lane & (G - 1);
+  // rows padded to multiples of G with zeros (rotations keep them zero)
+  const int rpad = (r + G - 1) / G * G, tpad = (t + G - 1) / G * G, er = rpad / G, et = tpad / G;
   for (int idx = tid; idx < rpad * t; idx += SVD_THREADS) {
     const int c = idx % rpad, i = idx / rpad;  // C[c, i] = R[i, c]
     C[c + (size_t)i * ldc] = (c >= i && c < r) ? Bm[i + (size_t)c * ldb] : (T)0;
@@ -1267,11 +1277,11 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
     }
     if (tid == 0) *S.rotated = 0;
     __syncthreads();
-    // Each pair of a round (round-robin order) gets a group of 16 lanes, four pairs per wave: dot
-    // products reduce inside the group, and up to 4 * SVD_WAVES pairs rotate at once.  A group
+    // Each pair of a round (round-robin order) gets a group of G lanes, 64 / G pairs per wave: dot
+    // products reduce inside the group, and up to (64 / G) SVD_WAVES pairs rotate at once.  A group
     // without a valid pair, or whose pair needs no rotation, is predicated off.
     for (int round = 0; round < tp - 1; ++round) {
-      for (int pi0 = wave * 4; pi0 < tp / 2; pi0 += 4 * SVD_WAVES) {
+      for (int pi0 = wave * GPW; pi0 < tp / 2; pi0 += GPW * SVD_WAVES) {
         const int pi = pi0 + sub;
         const int x = pi, y = tp - 1 - pi;
         int px = x - 1 + round, qy = y - 1 + round;  // (x - 1 + round) mod (tp - 1), both < 2 (tp - 1)
@@ -1286,12 +1296,12 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
         const T a = nrm2[pp], b = nrm2[qq];
         if constexpr (EM > 0) {
           T up[EM], uq[EM];
-          seg_load<EM>(up, cp, 0, er, sl);
-          seg_load<EM>(uq, cq, 0, er, sl);
+          seg_load<EM, G>(up, cp, 0, er, sl);
+          seg_load<EM, G>(uq, cq, 0, er, sl);
           T gg = 0;
 #pragma unroll
           for (int e = 0; e < EM; ++e) gg += up[e] * uq[e];
-          gg = row_sum(gg);
+          gg = group_sum<G>(gg);
           // rotate when |g| > tol sqrt(a b), tested without square roots
           const bool rot = valid && a > Prec<T>::tiny && b > Prec<T>::tiny && gg * gg > tol * tol * a * b;
           my_pairs += valid && sl == 0;
@@ -1310,29 +1320,29 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
           T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
           const bool exact = rot && (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b));  // cancellation: computed norms
           if (__any(exact)) {  // wave-uniform; rare
-            na = row_sum(na);
-            nb = row_sum(nb);
+            na = group_sum<G>(na);
+            nb = group_sum<G>(nb);
             if (exact) {
               ea = na;
               eb = nb;
             }
           }
           if (rot) {
-            seg_store<EM>(up, cp, 0, er, sl);
-            seg_store<EM>(uq, cq, 0, er, sl);
+            seg_store<EM, G>(up, cp, 0, er, sl);
+            seg_store<EM, G>(uq, cq, 0, er, sl);
             T* jp = J + (size_t)pp * ldj;
             T* jq = J + (size_t)qq * ldj;
             T vp[EM], vq[EM];
-            seg_load<EM>(vp, jp, 0, et, sl);
-            seg_load<EM>(vq, jq, 0, et, sl);
+            seg_load<EM, G>(vp, jp, 0, et, sl);
+            seg_load<EM, G>(vq, jq, 0, et, sl);
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
               const T u2 = cs * vp[e] - sn * vq[e], w2 = sn * vp[e] + cs * vq[e];
               vp[e] = u2;
               vq[e] = w2;
             }
-            seg_store<EM>(vp, jp, 0, et, sl);
-            seg_store<EM>(vq, jq, 0, et, sl);
+            seg_store<EM, G>(vp, jp, 0, et, sl);
+            seg_store<EM, G>(vq, jq, 0, et, sl);
             if (sl == 0) {
               nrm2[pp] = ea;
               nrm2[qq] = eb;
@@ -1440,33 +1450,33 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
   if constexpr (EM > 0) {
     // Each output column stays in registers of one group through the t reflectors (applied last to
     // first).
-    for (int o0 = 4 * wave; o0 < kk; o0 += 4 * SVD_WAVES) {
+    for (int o0 = GPW * wave; o0 < kk; o0 += GPW * SVD_WAVES) {
       const int o = o0 + sub;
       const bool valid = o < kk;
       const int src = ordr[valid ? o : o0];
       const double is = 1.0 / sqrt((double)sig2[src]);
       double x[EM];
-      seg_load<EM>(x, J + (size_t)src * ldj, 0, et, sl);
+      seg_load<EM, G>(x, J + (size_t)src * ldj, 0, et, sl);
 #pragma unroll
       for (int e = 0; e < EM; ++e) x[e] *= is;
       for (int j = t - 1; j >= 0; --j) {
         T v[EM];
         const double tj = tau[j], vj = vhead[j];
         if (uniform(tj != 0.0)) {
-          const int e0 = j >> 4, jl = j & 15;  // row j is lane jl of element e0
-          seg_load<EM>(v, Bm + (size_t)j * ldb, e0, er, sl);
+          const int e0 = j / G, jl = j % G;  // row j is lane jl of element e0
+          seg_load<EM, G>(v, Bm + (size_t)j * ldb, e0, er, sl);
 #pragma unroll
           for (int e = 0; e < EM; ++e)
             if (e == e0) v[e] = sl > jl ? v[e] : (sl == jl ? (T)vj : (T)0);
           double w = 0.0;
 #pragma unroll
           for (int e = 0; e < EM; ++e) w += (double)v[e] * x[e];
-          w = row_sum(w) * tj;
+          w = group_sum<G>(w) * tj;
 #pragma unroll
           for (int e = 0; e < EM; ++e) x[e] -= w * (double)v[e];
         }
       }
-      if (valid) seg_store<EM>(x, Tk.Wk + (size_t)o * Tk.ld, 0, er, sl);
+      if (valid) seg_store<EM, G>(x, Tk.Wk + (size_t)o * Tk.ld, 0, er, sl);
     }
   } else {
     __syncthreads();
@@ -1496,22 +1506,22 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
 // T = double: FP64 throughout.  T = float: the core is rounded to FP32, everything runs in FP32, and
 // truncation uses max(thresh, fp32_floor sigma_1) (singular values below that are FP32 noise); the
 // outputs stay FP64.  Workspace buffers (C, Jw, aux) are reinterpreted as T.
-template <typename T, int EM>
+template <typename T, int EM, int G>
 static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, const int r, T* slds,
                                                const SvdShared<T>& S) {
   constexpr bool dbl = std::is_same<T, double>::value;
   constexpr int SVD_LDS = SVD_LDS_BYTES / (int)sizeof(T);
   const int tid = threadIdx.x;
-  // reflector factors: in LDS on the register path (t <= r <= 256), else in the aux workspace
+  // reflector factors: in LDS on the register path (t <= r <= 512: tau in [0, 512), heads in [512, 1024)), else in the aux workspace
   T* tau = EM > 0 ? S.vl : reinterpret_cast<T*>(Tk.aux);
-  T* vhead = EM > 0 ? S.vl + 256 : reinterpret_cast<T*>(Tk.aux) + r;
+  T* vhead = EM > 0 ? S.vl + 512 : reinterpret_cast<T*>(Tk.aux) + r;
   // global copy of B in T: the input buffer itself (FP64), or the upper half of the C workspace
   T* const Bglob = dbl ? reinterpret_cast<T*>(Tk.B) : reinterpret_cast<T*>(Tk.C) + (size_t)Tk.ld * Tk.ld;
   const unsigned long long c0 = wall_clock64();
   unsigned long long c1 = c0, c2 = c0;
   unsigned my_pairs = 0, my_rots = 0;  // per group lane 0, summed once at the end
-  // ---- phase 1 on B with rows padded by zeros to rpad (a multiple of 16, at most Tk.ld)
-  const int rpad = (r + 15) & ~15;
+  // ---- phase 1 on B with rows padded by zeros to rpad (a multiple of G, at most Tk.ld)
+  const int rpad = (r + G - 1) / G * G;
   const bool bl = rpad * r <= SVD_LDS;
   int t;
   if (bl) {
@@ -1520,7 +1530,7 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
       slds[idx] = i < r ? (T)Tk.B[i + (size_t)c * Tk.ld] : (T)0;
     }
     __syncthreads();
-    t = svd_qrcp<T, EM>(slds, rpad, r, Tk, flag, S, tau, vhead);
+    t = svd_qrcp<T, EM, G>(slds, rpad, r, Tk, flag, S, tau, vhead);
   } else {
     for (int idx = tid; idx < rpad * r; idx += SVD_THREADS) {
       const int i = idx % rpad, c = idx / rpad;
@@ -1529,7 +1539,7 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
       else if (!dbl) Bglob[o] = (T)Tk.B[o];
     }
     __syncthreads();
-    t = svd_qrcp<T, EM>(Bglob, Tk.ld, r, Tk, flag, S, tau, vhead);
+    t = svd_qrcp<T, EM, G>(Bglob, Tk.ld, r, Tk, flag, S, tau, vhead);
   }
   __syncthreads();
   c1 = wall_clock64();
@@ -1539,11 +1549,11 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
   }
   // ---- phases 2-4: C = R_t^T (rpad x t) and J (tpad x t) in LDS when they fit (B stays there too
   // if there is room)
-  const int tpad = (t + 15) & ~15;
+  const int tpad = (t + G - 1) / G * G;
   const int nB = rpad * r, nC = rpad * t, nJ = tpad * t;
   int nsweeps;
   if (bl && nB + nC + nJ <= SVD_LDS) {
-    nsweeps = svd_tail<T, EM>(slds, rpad, slds + nB, rpad, slds + nB + nC, tpad, r, t, Tk, flag, S, tau, vhead,
+    nsweeps = svd_tail<T, EM, G>(slds, rpad, slds + nB, rpad, slds + nB + nC, tpad, r, t, Tk, flag, S, tau, vhead,
                               my_pairs, my_rots, c2);
   } else {
     if (bl) {  // free the LDS: reflectors (and the zero padding) back to global
@@ -1553,16 +1563,16 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
     T* const Cg = reinterpret_cast<T*>(Tk.C);
     T* const Jg = reinterpret_cast<T*>(Tk.Jw);
     if (nC + nJ <= SVD_LDS)
-      nsweeps = svd_tail<T, EM>(Bglob, Tk.ld, slds, rpad, slds + nC, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
+      nsweeps = svd_tail<T, EM, G>(Bglob, Tk.ld, slds, rpad, slds + nC, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
                                 my_rots, c2);
     else if (nJ <= SVD_LDS)
-      nsweeps = svd_tail<T, EM>(Bglob, Tk.ld, Cg, Tk.ld, slds, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
+      nsweeps = svd_tail<T, EM, G>(Bglob, Tk.ld, Cg, Tk.ld, slds, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
                                 my_rots, c2);
     else
-      nsweeps = svd_tail<T, EM>(Bglob, Tk.ld, Cg, Tk.ld, Jg, Tk.ld, r, t, Tk, flag, S, tau, vhead, my_pairs,
+      nsweeps = svd_tail<T, EM, G>(Bglob, Tk.ld, Cg, Tk.ld, Jg, Tk.ld, r, t, Tk, flag, S, tau, vhead, my_pairs,
                                 my_rots, c2);
   }
-  if ((threadIdx.x & 15) == 0 && my_pairs) {  // counted on the first lane of each 16-lane group
+  if ((threadIdx.x & (G - 1)) == 0 && my_pairs) {  // counted on the first lane of each group
     atomicAdd(S.pairs, (unsigned long long)my_pairs);
     atomicAdd(S.rots, (unsigned long long)my_rots);
   }
@@ -1598,7 +1608,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     if (threadIdx.x == 0) *Tk.kout = 0;
     return;
   }
-  if (Tk.ld < ((r + 15) & ~15)) {  // workspaces must hold the rows padded to a multiple of 16
+  if (Tk.ld < ((r + 15) & ~15)) {  // workspaces must hold the rows padded to a multiple of 16 (32 above 256)
     if (threadIdx.x == 0) {
       atomicOr(flag + Tk.fidx, 8);
       *Tk.kout = 0;
@@ -1616,11 +1626,13 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   if (threadIdx.x == 0) { sh_pairs = 0; sh_rots = 0; }
   const SvdShared<T> S{cn, vl, perm, ordr, redv, reda, &rotated, &sh_pairs, &sh_rots};
   if (r <= 128)
-    svd_run<T, 8>(Tk, flag, r, slds, S);
+    svd_run<T, 8, 16>(Tk, flag, r, slds, S);
   else if (r <= 256)
-    svd_run<T, 16>(Tk, flag, r, slds, S);
+    svd_run<T, 16, 16>(Tk, flag, r, slds, S);
+  else if (r <= 512 && Tk.ld >= ((r + 31) & ~31))
+    svd_run<T, 16, 32>(Tk, flag, r, slds, S);  // 32-lane groups
   else
-    svd_run<T, 0>(Tk, flag, r, slds, S);
+    svd_run<T, 0, 16>(Tk, flag, r, slds, S);
 }
 
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s) {

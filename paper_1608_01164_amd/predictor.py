@@ -37,6 +37,11 @@ TRAIN_SET = [
     (2048, 1, 146, 64, 1e-10, "metallic"), (4096, 1, 147, 256, 1e-10, "metallic"),
     (8192, 1, 148, 128, 1e-10, "metallic"), (16384, 1, 149, 256, 1e-10, "metallic"),
     (32768, 1, 150, 256, 1e-10, "metallic"),
+] + [
+    # the size and bandwidth ranges of independent banded matrices solved together
+    (n, b, 160 + i, 128, 1e-10, "band")
+    for i, (n, b) in enumerate([(2500, 3), (3500, 11), (5000, 14), (6500, 2), (7500, 9), (9000, 16), (10500, 5),
+                                (11500, 12), (13000, 7), (14500, 15), (15500, 4), (16000, 10)])
 ]
 
 
@@ -79,7 +84,7 @@ def collect(problems, verbose=False):
     return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Ws)
 
 
-def train(X, T, W, epochs=4000, lr=3e-3, seed=0, quantile=0.995):
+def train(X, T, W, epochs=4000, lr=3e-3, seed=0, quantile=0.998):
     """A new predictor fitted on the rows with the library's Adam kernels; returns (net, loss).
 
     The capacity margins are set from the residuals: per output, the `quantile` of the amount by

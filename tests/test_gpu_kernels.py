@@ -127,8 +127,11 @@ def test_qr_r_columns_near_underflow(rows, r):
         assert np.abs(np.abs(R[:kk, c]) - np.abs(Rn[:kk, c])).max() <= 1e-12 * ref * np.sqrt(rows)
 
 
+# stacked widths 1.5 r: cores of up to 128, 256 and 512 columns take the register paths (16-lane
+# groups, then 32-lane groups), wider ones the looped path
 @pytest.mark.parametrize("m,n,r,decay", [(50, 60, 10, 1.0), (300, 200, 40, 0.6), (1200, 900, 90, 0.8),
-                                         (64, 64, 64, 0.5), (10, 400, 30, 0.3)])
+                                         (64, 64, 64, 0.5), (10, 400, 30, 0.3), (600, 700, 180, 0.85),
+                                         (1500, 1200, 200, 0.88), (2000, 2000, 300, 0.92), (2000, 1800, 360, 0.9)])
 def test_recompress(m, n, r, decay):
     rng = np.random.default_rng(m + n + r)
     s = decay ** np.arange(r)
