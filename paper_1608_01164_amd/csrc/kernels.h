@@ -65,6 +65,9 @@ struct StackTask {
 // the source into a workspace slot and triangularises it; stage s >= 1 stacks the triangle of
 // slot i + 2^(s-1) under that of slot i and triangularises again.  After the last stage slot 0
 // holds R (min(rows, r) x r, upper trapezoidal), copied to R (ldr) with zero padding to r x r.
+// In FP64 a single-tile stack with rows <= r is its own factor (M = I M) and is passed on
+// unfactored, so R is then the stack itself; what the recompression needs holds either way: M = Q R with Q
+// orthonormal columns, i.e. R^T R = M^T M.
 struct QrTask {
   const double* M;   // source (rows x r), ld = ldm
   const int* rp;     // live column count r

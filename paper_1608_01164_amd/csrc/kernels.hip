@@ -916,6 +916,20 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
     src1 = work + (size_t)b * Tk.hs * Tk.rcap;
     h = ra + rb;
   }
+  // FP64: a stack with no more rows than columns is its own triangular factor up to an orthogonal
+  // one (M = I M): the recompression only needs R with M = Q R, so the tile is passed on as it is.
+  // (FP32 keeps the Householder factor, whose norm-preserving rounding its error bound assumes.)
+  if (std::is_same<T, double>::value && stage == 0 && Tk.ntiles == 1 && h <= r) {
+    bool bad = false;
+    for (int idx = tid; idx < h * r; idx += QR_THREADS) {
+      const int i = idx % h, c = idx / h;
+      const double v = srcM[i + (size_t)c * ld0];
+      bad |= !(fabs(v) <= DBL_MAX);
+      slot[i + (size_t)c * Tk.hs] = (T)v;
+    }
+    if (bad) atomicOr(flag + Tk.fidx, 16);
+    return;
+  }
   // small row tiles: the whole tile in registers
   if (stage == 0 && h <= 128 && r <= 256) {
     householder_regs<T, 8, 4>(srcM, ld0, slot, Tk.hs, h, r, flag, Tk.fidx, qlds);
@@ -975,9 +989,11 @@ __global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tas
   const int rr = Tk.rows < r ? Tk.rows : r;
   const T* work = reinterpret_cast<const T*>(Tk.work);
   bool bad = false;
+  // FP64 single tile with no more rows than columns: the stack itself
+  const bool full = std::is_same<T, double>::value && Tk.ntiles == 1 && Tk.rows <= r;
   for (int idx = threadIdx.x; idx < r * r; idx += 256) {
     const int i = idx % r, c = idx / r;
-    const double v = (i < rr && i <= c) ? (double)work[i + (size_t)c * Tk.hs] : 0.0;
+    const double v = (i < rr && (full || i <= c)) ? (double)work[i + (size_t)c * Tk.hs] : 0.0;
     bad |= !(fabs(v) <= DBL_MAX);
     Tk.R[i + (size_t)c * Tk.ldr] = v;
   }

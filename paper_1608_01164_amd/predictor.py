@@ -23,8 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "predictor_default.json")
 FORMAT = "hq-rank-predictor-v1"
 
-# (n, b, seed, leaf, tol, kind): banded N(0,1) (kind "band"), tridiagonal uniform ("tri") or
-# tridiagonal with diagonal 2 + U(0, 0.1) and off-diagonal -1 ("metallic")
+# (n, b, seed, leaf, tol, kind): banded N(0,1) (kind "band") or tridiagonal uniform ("tri")
 TRAIN_SET = [
     (n, b, 100 + i, 128, 1e-10, "band")
     for i, (n, b) in enumerate([(2048, 1), (2048, 4), (2048, 9), (2048, 16), (3000, 2), (3000, 7), (3000, 13),
@@ -34,14 +33,6 @@ TRAIN_SET = [
 ] + [
     (4096, 1, 140, 256, 1e-10, "tri"), (16384, 1, 141, 256, 1e-10, "tri"), (32768, 1, 142, 256, 1e-8, "tri"),
     (4096, 8, 143, 256, 1e-10, "band"), (2048, 1, 144, 64, 1e-10, "tri"), (4096, 4, 145, 64, 1e-10, "band"),
-    (2048, 1, 146, 64, 1e-10, "metallic"), (4096, 1, 147, 256, 1e-10, "metallic"),
-    (8192, 1, 148, 128, 1e-10, "metallic"), (16384, 1, 149, 256, 1e-10, "metallic"),
-    (32768, 1, 150, 256, 1e-10, "metallic"),
-] + [
-    # the size and bandwidth ranges of independent banded matrices solved together
-    (n, b, 160 + i, 128, 1e-10, "band")
-    for i, (n, b) in enumerate([(2500, 3), (3500, 11), (5000, 14), (6500, 2), (7500, 9), (9000, 16), (10500, 5),
-                                (11500, 12), (13000, 7), (14500, 15), (15500, 4), (16000, 10)])
 ]
 
 
@@ -57,7 +48,7 @@ def make_problem(n, b, seed, kind):
     wl = _workloads()
     if kind == "band":
         return wl.banded_normal(n, b, seed)
-    if kind == "metallic":
+    if kind == "metallic":  # tridiagonal, diagonal 2 + U(0, 0.1), off-diagonal -1
         return wl.tridiag_metallic(n, seed)
     return wl.tridiag_uniform(n, seed)
 
@@ -84,7 +75,7 @@ def collect(problems, verbose=False):
     return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Ws)
 
 
-def train(X, T, W, epochs=4000, lr=3e-3, seed=0, quantile=0.998):
+def train(X, T, W, epochs=4000, lr=3e-3, seed=0, quantile=0.995):
     """A new predictor fitted on the rows with the library's Adam kernels; returns (net, loss).
 
     The capacity margins are set from the residuals: per output, the `quantile` of the amount by
