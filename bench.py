@@ -73,7 +73,28 @@ KERNEL_NAMES = {"gemm": "k_gemm", "tsqr": "k_qr_stage", "core_svd": "k_svd", "le
                 "leaf_inverse": "k_trtri", "stack": "k_stack", "leaf_elementwise": "k_leaf_axpy", "other": "misc"}
 
 
-def roofline(prof):
+def measured_traffic(workload, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary of `workload`, or None when
+    there is none or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic-{kernel}-{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split(None, 1)
+            kv[k] = v
+    src = os.path.join(ROOT, "paper_1608_01164_amd", "csrc", "kernels.hip")
+    if kv.get("kernel") != kernel or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
+        return None
+    kib = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"]) + \
+        float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+    return kib * 1024.0
+
+
+def roofline(prof, workload=None):
     """Roofline entry of the kernel class with the largest measured time (HIP events on the library's stream)."""
     kern = {}
     for k, v in prof.items():
@@ -87,7 +108,8 @@ def roofline(prof):
     peak = PEAK_FP64_MFMA if bound == "mfma" else PEAK_FP64_ALU
     achieved = d["tflops"]
     return ({"kernel": d["kernel"], "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-             "frac": achieved / peak, "traffic": None, "avg_launch_ms": d["ms_avg"],
+             "frac": achieved / peak, "traffic": measured_traffic(workload, d["kernel"]) if workload else None,
+             "traffic_unit": "bytes per launch", "avg_launch_ms": d["ms_avg"],
              "flops_per_launch": d["gflop_per_launch"] * 1e9}, kern)
 
 
@@ -188,7 +210,7 @@ def main():
         "checks": props,
     }
     if prof is not None:
-        out["roofline"], out["kernels"] = roofline(prof)
+        out["roofline"], out["kernels"] = roofline(prof, args.workload)
         out["core_svd_phases"] = svd_stats
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ab, b, nu)
