@@ -1727,24 +1727,72 @@ __global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ task
   if (tid == 0) count_work(K_TRTRI, (unsigned long long)m * m * m / 3, 0);
 }
 
-// Leaf Cholesky and triangular inverse for m <= 128, with the tile in registers: the lower
-// triangle is cut into 4 x 4 blocks, one per thread (at most 528 blocks), numbered column by column
-// so that the threads whose columns are finished (Cholesky) or not yet reached (inverse) fill whole
-// waves that skip the step; the tile is padded with the identity to a multiple of 4.  Step j of
-// either phase publishes one column (and row) through LDS, double buffered, so each step costs one
-// barrier.
-//   Cholesky (right-looking): publish column j of the trailing matrix and the pivot; every block
-//     right of j subtracts a_ij a_cj / d; the owners of column j scale it by 1/sqrt(d).
-//   Inverse X = L^{-1} in place (right-looking elimination on [L | I]): row j of X, complete after
-//     steps < j, is scaled by 1/L_jj and published with column j of L; rows below j subtract
-//     L_ij X_j. (the slots of column j, which held L_ij, start from zero).
+// Leaf Cholesky and triangular inverse for m <= 128, with the tile in registers, by 4 x 4 blocks.
+// The lower triangle of the tile (padded with the identity to a multiple of 4) is cut into 4 x 4
+// blocks, one per thread (at most 528), numbered column by column.  Block step J factors block
+// column J and, in the same sweep, eliminates block row J of X = L^{-1} (right-looking on [L | I]):
+//   A: every block in a row below J - 1 applies step J - 1: trailing blocks (column >= J) subtract
+//      L_{i,J-1} L_{c,J-1}^T; blocks of X subtract L_{i,J-1} X_{J-1,c}, the former panel blocks
+//      (column J - 1, which held L_{i,J-1}) starting from zero.  The diagonal block then holds the
+//      Schur complement A_JJ; its thread factors it (4 x 4 Cholesky) and inverts the factor,
+//      W = L_JJ^{-1}, which is also X_JJ.
+//   B: the panel L_{iJ} = A_{iJ} W^T, and block row J of X scaled by W, are published.
+// Two barriers per block step; the panel, the row of X and W each need one LDS buffer, since every
+// read of one happens in the half step before its next write.
 // A (lower part of an SPD tile) is read; B receives L^{-1} (zero above the diagonal).
 constexpr int CI_MAX = 128;
 constexpr int CI_PAD = CI_MAX + 4;
-__global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ tasks, int* flag) {
+constexpr int CI_THREADS = 576;  // nine waves cover the 528 blocks of a 128 x 128 tile
+
+// 4 x 4 Cholesky of the lower part of d and the inverse of its factor, in one thread: w = L^{-1}
+// (lower).  A pivot that is not positive (or not finite) is replaced by 1 and reported.
+static __device__ __forceinline__ void chol4_inv(const double (&d)[4][4], double (&w)[4][4], int valid_rows,
+                                                 bool& bad) {
+  double l[4][4], rinv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) l[r][c] = r >= c ? d[r][c] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double p = l[k][k];
+    if (!(p > 0.0)) {
+      if (k < valid_rows) bad = true;
+      p = 1.0;
+    }
+    const double rs = rsqrt(p);
+    rinv[k] = rs;
+    l[k][k] = p * rs;
+#pragma unroll
+    for (int r = k + 1; r < 4; ++r) l[r][k] *= rs;
+#pragma unroll
+    for (int c = k + 1; c < 4; ++c)
+#pragma unroll
+      for (int r = c; r < 4; ++r) l[r][c] -= l[r][k] * l[c][k];
+  }
+  // forward substitution, column by column of the identity
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r < c) {
+        w[r][c] = 0.0;
+      } else if (r == c) {
+        w[r][c] = rinv[r];
+      } else {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = c; k < r; ++k) acc += l[r][k] * w[k][c];
+        w[r][c] = -acc * rinv[r];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(CI_THREADS) void k_chol_inv(const LeafTask* __restrict__ tasks, int* flag) {
   const LeafTask T = tasks[blockIdx.x];
   const int m = T.m, tid = threadIdx.x;
-  const int nb = (m + 3) >> 2, mp = 4 * nb;
+  const int nb = (m + 3) >> 2;
   const bool own = tid < nb * (nb + 1) / 2;
   int bi = 0, bc = 0;
   if (own) {  // block number tid, column by column: column bc holds blocks bi = bc .. nb - 1
@@ -1772,126 +1820,100 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ 
       }
       a[r][c] = v;
     }
-  __shared__ double colv[2][CI_PAD];  // column j below the diagonal (Cholesky) / of L (inverse)
-  __shared__ double rowv[2][CI_PAD];  // row j of X (inverse)
-  __shared__ double piv[2][2];        // 1/d and sqrt(d) of step j
-  __shared__ double rdiag[CI_PAD];    // 1 / L_jj
-  // The updates are plain FMAs over the 16 entries with factors that vanish outside the rows and
-  // columns a step touches; entries above the diagonal of diagonal blocks take junk, which nothing
-  // reads (they are written out as zeros).  The exchange buffers start at zero, so that every
-  // entry read (then masked) is finite.
-  for (int i = tid; i < 2 * CI_PAD; i += 1024) {
-    (&colv[0][0])[i] = 0.0;
-    (&rowv[0][0])[i] = 0.0;
-  }
-  __syncthreads();
-  // ---- Cholesky
-  for (int j = 0; j < mp; ++j) {
-    const int b = j & 1, jb = j >> 2, jc = j & 3;
-    if (own && bc == jb) {
+  __shared__ double pan[4][CI_PAD];   // panel L_{:,J}: column k of the block column, by row
+  __shared__ double xrow[4][CI_PAD];  // block row J of X: row k, by column
+  __shared__ double wsh[4][4];        // W = L_JJ^{-1}
+  bool bad = false;
+  for (int J = 0; J < nb; ++J) {
+    // ---- A: step J - 1 applied below row block J - 1; the diagonal block factored
+    if (own && bi >= J) {
+      if (J > 0) {
+        const double* ysrc = bc >= J ? &pan[0][0] : &xrow[0][0];  // L_{c,J-1}^T or X_{J-1,c}
+        double li[4][4], y[4][4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c == jc) {  // wave-uniform
+        for (int k = 0; k < 4; ++k) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (r0 + r >= j) colv[b][r0 + r] = a[r][c];
-          if (bi == bc) {
-            double d = a[c][c];
-            if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
-              if (j < m) atomicOr(flag + T.fidx, 2);
-              d = 1.0;
-            }
-            const double rs = rsqrt(d);
-            piv[b][0] = rs * rs;
-            piv[b][1] = d * rs;
-            rdiag[j] = rs;
-          }
+          for (int r = 0; r < 4; ++r) li[r][k] = pan[k][r0 + r];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) y[k][c] = ysrc[k * CI_PAD + c0 + c];
         }
+        const bool fresh = bc == J - 1;  // former panel block: X starts from zero
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            double acc = fresh ? 0.0 : a[r][c];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc -= li[r][k] * y[k][c];
+            a[r][c] = acc;
+          }
+      }
+      if (bi == J && bc == J) {
+        double w[4][4];
+        chol4_inv(a, w, m - r0, bad);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            a[r][c] = w[r][c];
+            wsh[r][c] = w[r][c];
+          }
+      }
     }
     __syncthreads();
-    if (!own || c0 + 3 < j) continue;  // columns of this block finished
-    if (bc == jb) {  // column j: rows below scaled by 1/sqrt(d), the pivot replaced by sqrt(d)
-      const double s = piv[b][1], rs = rdiag[j];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c == jc) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = r0 + r;
-            a[r][c] = i > j ? a[r][c] * rs : (i == j ? s : a[r][c]);
-          }
-        }
-    }
-    if (c0 + 3 > j) {
-      const double inv_d = piv[b][0];
-      double li[4], fc[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) li[r] = colv[b][r0 + r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) fc[c] = colv[b][c0 + c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) li[r] = r0 + r > j ? li[r] : 0.0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) fc[c] = c0 + c > j ? fc[c] * inv_d : 0.0;
+    // ---- B: the panel L_{iJ} = A_{iJ} W^T and block row J of X (W X_{Jc}; X_JJ = W) published
+    if (own && (bc == J || bi == J)) {
+      double w[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a[r][c] -= li[r] * fc[c];
-    }
-  }
-  __syncthreads();
-  // ---- inverse, in place
-  for (int j = 0; j < mp; ++j) {
-    const int b = j & 1, jb = j >> 2, jc = j & 3;
-    const double rj = rdiag[j];
-    if (own && bi == jb) {  // row j of X: scale and publish
+        for (int c = 0; c < 4; ++c) w[r][c] = r >= c ? wsh[r][c] : 0.0;
+      if (bc == J && bi > J) {
+        double o[4][4];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-        if (rr == jc) {  // wave-uniform
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const int k = c0 + c;
-            if (k <= j) {
-              const double x = k == j ? rj : a[rr][c] * rj;
-              a[rr][c] = x;
-              rowv[b][k] = x;
-            }
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k <= c; ++k) acc += a[r][k] * w[c][k];
+            o[r][c] = acc;
           }
-        }
-    }
-    if (own && bc == jb) {  // column j of L below the diagonal
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c == jc) {
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (r0 + r > j) colv[b][r0 + r] = a[r][c];
-        }
+          for (int c = 0; c < 4; ++c) {
+            a[r][c] = o[r][c];
+            pan[c][r0 + r] = o[r][c];
+          }
+      } else if (bi == J && bc < J) {
+        double o[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k <= r; ++k) acc += w[r][k] * a[k][c];
+            o[r][c] = acc;
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            a[r][c] = o[r][c];
+            xrow[r][c0 + c] = o[r][c];
+          }
+      } else {  // the diagonal block: X_JJ = W
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) xrow[r][c0 + c] = a[r][c];
+      }
     }
     __syncthreads();
-    if (!own || c0 > j || r0 + 3 <= j) continue;  // no row below j, or no column up to j
-    if (bc == jb) {  // the slots of column j below the diagonal held L_ij: X_ij starts from zero
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c == jc) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) a[r][c] = r0 + r > j ? 0.0 : a[r][c];
-        }
-    }
-    double li[4], xc[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) li[r] = colv[b][r0 + r];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) xc[c] = rowv[b][c0 + c];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) li[r] = r0 + r > j ? li[r] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) xc[c] = c0 + c <= j ? xc[c] : 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a[r][c] -= li[r] * xc[c];
   }
+  if (bad) atomicOr(flag + T.fidx, 2);  // breakdown: a unit pivot kept the rest finite
   // ---- B = L^{-1}: owned blocks, and zeros in the blocks above the diagonal
   if (own)
 #pragma unroll
@@ -1901,7 +1923,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ 
         const int i = r0 + r, k = c0 + c;
         if (i < m && k < m) T.B[i + (size_t)k * T.ldb] = i >= k ? a[r][c] : 0.0;
       }
-  for (int idx = tid; idx < m * m; idx += 1024) {
+  for (int idx = tid; idx < m * m; idx += CI_THREADS) {
     const int i = idx % m, k = idx / m;
     if ((i >> 2) < (k >> 2)) T.B[i + (size_t)k * T.ldb] = 0.0;
   }
@@ -1911,7 +1933,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const LeafTask* __restrict__ 
 void launch_chol_inv(const LeafTask* d_tasks, int ntasks, int max_m, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
   if (max_m > CI_MAX) throw std::runtime_error("launch_chol_inv: leaf larger than 128");
-  HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(1024), 0, s, d_tasks, flag));
+  HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(CI_THREADS), 0, s, d_tasks, flag));
 }
 
 void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s) {

@@ -233,6 +233,24 @@ def test_cholesky_inverse(n, leaf):
     assert np.abs(G - np.linalg.inv(Lref)).max() < 1e-9
 
 
+@pytest.mark.parametrize("n,leaf,row", [(64, 64, 0), (128, 128, 93), (126, 126, 125), (300, 37, 41)])
+def test_cholesky_inverse_indefinite_is_reported(n, leaf, row):
+    """A leaf whose Schur complement loses positive definiteness (a negative eigenvalue planted in
+    the coupling of row `row`) reports status 2; padded rows of a ragged leaf never do."""
+    A = _kernel_matrix(n, 5)
+    Z = np.eye(n) + 0.1 * A.T @ A
+    d0 = Z[row, row]
+    Z[row, row] = -1.0
+    hZ = hq.test_from_dense(dev(Z), n, leaf, 1e-13, 200)
+    with pytest.raises(hq.HQError) as e:
+        hq.test_cholesky_inverse(hZ, 200, 1e-12)
+    assert e.value.status == 2
+    Z[row, row] = d0 + 1.0  # the library stays usable, and the same matrix made definite factors
+    hZ = hq.test_from_dense(dev(Z), n, leaf, 1e-13, 200)
+    G = oh.to_dense(hq.test_cholesky_inverse(hZ, 200, 1e-12).export())
+    assert np.abs(G @ Z @ G.T - np.eye(n)).max() < 1e-9
+
+
 @pytest.mark.parametrize("n,b,leaf", [(64, 1, 8), (300, 1, 64), (257, 5, 40), (512, 8, 64)])
 def test_q_factors_device(n, b, leaf):
     import workloads as w
