@@ -229,6 +229,10 @@ void hq_predictor_destroy(hq_predictor_t p);
  * total milliseconds, flops and bytes since the last reset; reset != 0 clears them. */
 typedef struct { int64_t launches; double ms, flops, bytes; } hq_kstat;
 hq_status hq_profile_enable(int32_t on);
+/* Restricts the timers to the classes in mask (bit c for class c; -1, the initial value, times all):
+ * launches of other classes get no events, so a run that needs one class's durations pays for no
+ * others.  The kernels' work counters run for every class while profiling is on. */
+hq_status hq_profile_select(int32_t mask);
 hq_status hq_profile_read(hq_kstat* out /* [8] */, int32_t reset);
 /* Core-SVD internals since the last reset: [0..2] cycles of the pivoted-QR, Jacobi and output phases
  * (wall clock at 100 MHz), [3] sum of r, [4] sum of t, [5] sum of sweeps, [6] cores. */

@@ -81,6 +81,7 @@ _SIGS = {
     "hq_test_q_factors": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, P(c_vp), P(c_vp), P(c_i64)]),
     "hq_test_q_dense_host": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, c_vp, P(c_i64)]),
     "hq_profile_enable": (c_i32, [c_i32]),
+    "hq_profile_select": (c_i32, [c_i32]),
     "hq_profile_read": (c_i32, [c_vp, c_i32]),
     "hq_profile_svd": (c_i32, [c_vp]),
     "hq_predictor_create": (c_i32, [ctypes.c_uint64, P(c_vp)]),
@@ -104,10 +105,13 @@ class KStat(ctypes.Structure):
     _fields_ = [("launches", c_i64), ("ms", c_d), ("flops", c_d), ("bytes", c_d)]
 
 
-def profile(on: bool):
-    """Enable/disable the library's kernel timers (and clear them when enabling)."""
+def profile(on: bool, classes=None):
+    """Enable/disable the library's kernel timers (and clear them when enabling); `classes` (names
+    from KCLASSES) restricts the timers to those kernel classes, None times all of them."""
     if on:
         profile_read(reset=True)
+        mask = -1 if classes is None else sum(1 << KCLASSES.index(c) for c in classes)
+        _check(lib().hq_profile_select(mask))
     _check(lib().hq_profile_enable(1 if on else 0))
 
 

@@ -1319,6 +1319,13 @@ hq_status hq_profile_enable(int32_t on) {
   });
 }
 
+hq_status hq_profile_select(int32_t mask) {
+  return guard([&]() -> hq_status {
+    hq::prof_select((unsigned)mask);
+    return HQ_OK;
+  });
+}
+
 hq_status hq_profile_read(hq_kstat* out, int32_t reset) {
   if (!out) return fail(HQ_ERR_ARG, "out is NULL");
   return guard([&]() -> hq_status {

@@ -18,11 +18,12 @@ struct ProfStat {
   double ms, flops, bytes;
 };
 void prof_enable(bool on);
+void prof_select(unsigned mask);  // classes whose launches get timers (bit c for class c; default all)
 bool prof_enabled();
 void prof_read(ProfStat out[K_NCLASS], bool reset);
 void prof_svd_stats(unsigned long long out[8]);  // core-SVD phase cycles and sizes (test/bench aid)
-int prof_begin(hipStream_t s);             // returns a record slot or -1 when profiling is off
-void prof_end(int slot, int cls, hipStream_t s);
+int prof_begin(int cls, hipStream_t s);    // a record slot, or -1 when profiling is off for cls
+void prof_end(int slot, hipStream_t s);
 
 // C = alpha * op(A) * op(B) + beta * C, column-major, op = N (0) or T (1).
 struct GemmTask {

@@ -25,6 +25,7 @@ namespace {
 struct Rec { hipEvent_t a, b; int cls; };
 std::mutex g_mu;
 bool g_on = false;
+unsigned g_mask = ~0u;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 hipEvent_t take_event() {
@@ -45,19 +46,22 @@ void prof_enable(bool on) {
   const int v = on ? 1 : 0;
   (void)hipMemcpyToSymbol(HIP_SYMBOL(g_prof_on), &v, sizeof(int));
 }
-bool prof_enabled() { return g_on; }
-int prof_begin(hipStream_t s) {
-  if (!g_on) return -1;
+void prof_select(unsigned mask) {
   std::lock_guard<std::mutex> lk(g_mu);
-  Rec r{take_event(), take_event(), 0};
+  g_mask = mask;
+}
+bool prof_enabled() { return g_on; }
+int prof_begin(int cls, hipStream_t s) {
+  if (!g_on || !((g_mask >> cls) & 1u)) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Rec r{take_event(), take_event(), cls};
   (void)hipEventRecord(r.a, s);
   g_recs.push_back(r);
   return (int)g_recs.size() - 1;
 }
-void prof_end(int slot, int cls, hipStream_t s) {
+void prof_end(int slot, hipStream_t s) {
   if (slot < 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_recs[slot].cls = cls;
   (void)hipEventRecord(g_recs[slot].b, s);
 }
 void prof_svd_stats(unsigned long long out[8]) {
@@ -119,10 +123,10 @@ static void check_lds(const void* kernel, size_t dynamic_bytes, const char* what
 
 #define HQ_TIMED(cls, stream, ...)            \
   do {                                        \
-    const int slot_ = prof_begin(stream);     \
+    const int slot_ = prof_begin(cls, stream); \
     __VA_ARGS__;                              \
     check_launch(#cls);                       \
-    prof_end(slot_, cls, stream);             \
+    prof_end(slot_, stream);                  \
   } while (0)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
