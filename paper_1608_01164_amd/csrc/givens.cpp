@@ -26,20 +26,23 @@ namespace hq {
 
 namespace {
 
-// A row of R kept as a short window of columns [c0, c0 + W).
+// A row of R kept as a short window of columns [c0, c0 + len), len <= W (entries outside are zero).
 struct RowStore {
   int W;
   std::vector<int64_t> c0;
+  std::vector<int> len;
   std::vector<double> v;
   double* row(int64_t r) { return v.data() + (size_t)r * W; }
   double get(int64_t r, int64_t col) {
     const int64_t k = col - c0[r];
-    return (k >= 0 && k < W) ? v[(size_t)r * W + k] : 0.0;
+    return (k >= 0 && k < len[r]) ? v[(size_t)r * W + k] : 0.0;
   }
 };
 
 inline void make_rot(double f, double g, double& c, double& s) {
-  const double r = std::hypot(f, g);
+  const double m = std::max(std::fabs(f), std::fabs(g));
+  // plain sqrt where neither square can overflow or underflow, hypot's scaling otherwise
+  const double r = (m > 1e-150 && m < 1e150) ? std::sqrt(f * f + g * g) : std::hypot(f, g);
   if (r == 0.0) {
     c = 1.0;
     s = 0.0;
@@ -57,10 +60,12 @@ GivensSweep structured_qr(const double* ab, int64_t n, int b, int64_t ldab, doub
   R.W = 4 * b + 8;
   const int W = R.W;
   R.c0.assign(2 * n, 0);
+  R.len.assign(2 * n, 1);
   R.v.assign((size_t)2 * n * W, 0.0);
   // rows 0..n-1: scale * (A - shift I); window starts at column i - b
   for (int64_t i = 0; i < n; ++i) {
     R.c0[i] = i - b;
+    R.len[i] = 2 * b + 1;
     double* r = R.row(i);
     for (int64_t j = std::max<int64_t>(0, i - b); j <= std::min<int64_t>(n - 1, i + b); ++j) {
       const int64_t d = i >= j ? i - j : j - i, col = std::min(i, j);
@@ -74,37 +79,46 @@ GivensSweep structured_qr(const double* ab, int64_t n, int b, int64_t ldab, doub
     R.c0[n + i] = i;
     R.row(n + i)[0] = 1.0;
   }
-  std::vector<double> tp(2 * W), tq(2 * W);
-  auto store = [&](int64_t r, const double* t, int64_t lo, int64_t span) {
-    int64_t first = -1, last = -1;
-    for (int64_t k = 0; k < span; ++k)
-      if (t[k] != 0.0) {
-        if (first < 0) first = k;
-        last = k;
-      }
+  std::vector<double> xp(2 * W), xq(2 * W), tp(2 * W), tq(2 * W);
+  auto store = [&](int64_t r, const double* t, int64_t lo, int span) {
+    int first = 0, last = span - 1;
+    while (first < span && t[first] == 0.0) ++first;
     double* out = R.row(r);
-    std::fill(out, out + W, 0.0);
-    if (first < 0) return;
+    if (first == span) {
+      R.len[r] = 0;
+      return;
+    }
+    while (t[last] == 0.0) --last;
     if (last - first >= W) throw std::runtime_error("structured_qr: row window overflow");
-    for (int64_t k = first; k <= last; ++k) out[k - first] = t[k];
+    std::copy(t + first, t + last + 1, out);
     R.c0[r] = lo + first;
+    R.len[r] = last - first + 1;
   };
-  // rotation in rows (P, Q) chosen so that R(Q, col) becomes zero
+  // rotation in rows (P, Q) chosen so that R(Q, col) becomes zero; both windows are laid side by
+  // side over their union [lo, lo + span) and rotated there
   auto rot = [&](int64_t P, int64_t Q, int64_t col) {
+    const int64_t cP = R.c0[P], cQ = R.c0[Q];
+    const double* rp = R.row(P);
+    const double* rq = R.row(Q);
     double c, s;
     make_rot(R.get(P, col), R.get(Q, col), c, s);
     g.rots.push_back({P, Q, c, s});
-    const int64_t lo = std::min(R.c0[P], R.c0[Q]);
-    const int64_t span = std::max(R.c0[P], R.c0[Q]) + W - lo;
-    for (int64_t k = 0; k < span; ++k) {
-      const double x = R.get(P, lo + k), y = R.get(Q, lo + k);
-      tp[k] = c * x + s * y;
-      tq[k] = -s * x + c * y;
+    const int lP = R.len[P], lQ = R.len[Q];
+    const int64_t lo = std::min(lP ? cP : cQ, lQ ? cQ : cP);
+    const int span = (int)(std::max(cP + lP, cQ + lQ) - lo);
+    std::fill(xp.begin(), xp.begin() + span, 0.0);
+    std::fill(xq.begin(), xq.begin() + span, 0.0);
+    if (lP) std::copy(rp, rp + lP, xp.begin() + (cP - lo));
+    if (lQ) std::copy(rq, rq + lQ, xq.begin() + (cQ - lo));
+    for (int k = 0; k < span; ++k) {
+      tp[k] = c * xp[k] + s * xq[k];
+      tq[k] = -s * xp[k] + c * xq[k];
     }
-    tq[col - lo] = 0.0;
+    if (col >= lo && col < lo + span) tq[col - lo] = 0.0;
     store(P, tp.data(), lo, span);
     store(Q, tq.data(), lo, span);
   };
+  g.rots.reserve((size_t)n * (2 * b + 2));
   g.step.reserve(n + 1);
   for (int64_t i = 0; i < n; ++i) {
     g.step.push_back((int64_t)g.rots.size());
