@@ -138,6 +138,10 @@ class Engine {
   Engine& operator=(const Engine&) = delete;
   ~Engine();
   hipStream_t st;
+  // Second stream (default priority) for work off the critical path of the H-Cholesky; created on
+  // first use.  Work issued there is always joined back into st before its memory is released.
+  hipStream_t side = nullptr;
+  bool keep_scratch = false;  // set while issuing side-stream work: helpers then keep their workspace
   DevArena persist, scratch;
   DescStage stage;
   // d_flag[i], status of batch member i: bit 0 rank overflow, bit 1 not positive definite, bit 2 stack
@@ -172,8 +176,12 @@ class Engine {
     double* U; double* V; int ldu, ldv; int* rank; int kcap;
     double thresh;
     int fidx;
+    const double* Rv = nullptr;  // R factor of Vs (rcap x rcap, ld rcap) when already computed
   };
   void recompress(const std::vector<RecTask>& tasks);
+  // R factor (rcap x rcap, ld rcap) of each stack M (rows x live r), by the TSQR of recompress.
+  struct QrJob { const double* M; int ldm; int rows; const int* r; int rcap; double* R; int fidx; };
+  void qr_r(const std::vector<QrJob>& jobs);
   size_t rec_budget = size_t(3) << 30;  // device workspace of one group of recompressions
   // Symmetric factor compression: S (m x r) -> S J_k with S S^T ~ S' S'^T, drop sigma(S) <= thresh.
   struct SymTask {
@@ -181,7 +189,9 @@ class Engine {
     int fidx;
   };
   void compress_sym(const std::vector<SymTask>& tasks);
-  void recompress_group(const std::vector<RecTask>& tasks);
+  // `core_after`: the stream waits for it between the TSQR and the core of the group (a task's Rv
+  // may be produced on another stream).
+  void recompress_group(const std::vector<RecTask>& tasks, hipEvent_t core_after = nullptr);
   void compress_sym_group(const std::vector<SymTask>& tasks);
 
   // C = alpha op(A) op(B) + delta op(D)  (D absent, a HODLR, or the identity), for a batch of
@@ -213,8 +223,13 @@ class Engine {
   std::vector<int> read_ranks(const HMat& h);
 
   // helpers
+  hipEvent_t take_event();
+  void give_event(hipEvent_t e) { ev_free.push_back(e); }
   void gemm(const std::vector<GemmTask>& v, int max_m, int max_n);
   void stack(const std::vector<StackTask>& v, int max_rows);
+
+ private:
+  std::vector<hipEvent_t> ev_all, ev_free;
 };
 
 }  // namespace hq

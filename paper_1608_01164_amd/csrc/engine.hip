@@ -129,7 +129,24 @@ Engine::Engine(hipStream_t s) : st(s) {
   HQ_CHECK(hipMemsetAsync(d_flag, 0, sizeof(int) * (kFlagSlots + 64), st));
 }
 Engine::~Engine() {
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  for (hipEvent_t e : ev_all) (void)hipEventDestroy(e);
   if (d_flag) (void)hipFree(d_flag);
+}
+
+hipEvent_t Engine::take_event() {
+  if (!ev_free.empty()) {
+    hipEvent_t e = ev_free.back();
+    ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HQ_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  ev_all.push_back(e);
+  return e;
 }
 
 HMat Engine::alloc_hmat_in(DevArena& ar, const Tree* t, const std::vector<int>& cap, bool lower_only) {
@@ -170,7 +187,7 @@ void Engine::gemm(const std::vector<GemmTask>& v0, int max_m, int max_n) {
   }
   launch_gemm(stage.upload(v, st), (int)v.size(), max_m, max_n, fp32, st, zmax);
   launches += zmax > 1 ? 2 : 1;
-  scratch.rewind(mk);  // later users of this memory are issued after the reduction (stream order)
+  if (!keep_scratch) scratch.rewind(mk);  // later users of this memory are issued after the reduction (stream order)
 }
 void Engine::stack(const std::vector<StackTask>& v, int max_rows) {
   if (v.empty()) return;
@@ -365,7 +382,33 @@ void Engine::compress_sym(const std::vector<SymTask>& tasks) {
   }
 }
 
-void Engine::recompress_group(const std::vector<RecTask>& tasks) {
+void Engine::qr_r(const std::vector<QrJob>& jobs) {
+  if (jobs.empty()) return;
+  std::vector<QrTask> qv;
+  int maxtiles = 1;
+  for (const QrJob& J : jobs) {
+    const int rc = std::max(J.rcap, 1);
+    if (rc > kMaxStack) throw std::runtime_error("qr_r: stacked rank capacity above the kernel limit");
+    const QrPlan pl = plan_qr(J.rows, rc);
+    QrTask q{};
+    q.M = J.M; q.ldm = J.ldm; q.rows = J.rows; q.rp = J.r; q.rcap = rc; q.hs = pl.hs; q.h0 = pl.h0;
+    q.ntiles = pl.ntiles; q.work = scratch.get<double>((size_t)pl.ntiles * pl.hs * rc); q.R = J.R; q.ldr = rc;
+    q.fidx = J.fidx;
+    qv.push_back(q);
+    maxtiles = std::max(maxtiles, pl.ntiles);
+  }
+  QrTask* dq = stage.upload(qv, st);
+  int nst = 0;
+  while ((1 << nst) < maxtiles) ++nst;
+  for (int s = 0; s <= nst; ++s) {
+    launch_qr_stage(dq, (int)qv.size(), s, (maxtiles + (1 << s) - 1) >> s, d_flag, fp32, st);
+    ++launches;
+  }
+  launch_qr_final(dq, (int)qv.size(), d_flag, fp32, st);
+  ++launches;
+}
+
+void Engine::recompress_group(const std::vector<RecTask>& tasks, hipEvent_t core_after) {
   if (tasks.empty()) return;
   const int nt = (int)tasks.size();
   std::vector<QrTask> qv;
@@ -383,7 +426,7 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
     const int ls = svd_ld(rc);
     const size_t ll = (size_t)ls * ls;
     b.Ru = scratch.get<double>(rr);
-    b.Rv = scratch.get<double>(rr);
+    b.Rv = T.Rv ? const_cast<double*>(T.Rv) : scratch.get<double>(rr);
     b.B = scratch.get<double>(ll);
     b.J = scratch.get<double>(ll);
     b.Jw = scratch.get<double>(ll);
@@ -393,6 +436,7 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
     b.Pu = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     b.Pv = scratch.get<double>((size_t)rc * std::max(T.kcap, 1));
     for (int side = 0; side < 2; ++side) {
+      if (side == 1 && T.Rv) continue;  // R of Vs given
       const int m = side == 0 ? T.m : T.n;
       const QrPlan pl = plan_qr(m, rc);
       QrTask q{};
@@ -448,6 +492,7 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks) {
     ++launches;
   }
   launch_qr_final(dq, (int)qv.size(), d_flag, fp32, st);
+  if (core_after) HQ_CHECK(hipStreamWaitEvent(st, core_after, 0));
   gemm(gB, rmax, rmax);
   launch_svd(stage.upload(sv, st), nt, d_flag, fp32, st);
   launches += 2;
@@ -862,32 +907,42 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       left.push_back(Item{it.m, a, SF{it.S.p ? it.S.p + la : nullptr, it.S.ld, it.S.r, it.S.cap}});
     }
     dfs(left);
-    // off-diagonal factor L_ba = (Z_ba - S_b S_a^T) L_aa^{-T}, and the Schur factor of the right child
-    // A right child that is a leaf only needs S S^T for its dense update: there the stacked factor
-    // [S_b, L_ba's U] is passed on as it is (exact, and one TSQR + core SVD fewer on the critical path).
+    // Off-diagonal factor L_ba = (Z_ba - S_b S_a^T) L_aa^{-T} = Us Vs^T with Us = [U(Z_ba), S_b] and
+    // Vs = L_aa^{-1} [V(Z_ba), -S_a], and the Schur factor of the right child.  With Vs = Qv Rv,
+    // L_ba L_ba^T = (Us Rv^T)(Us Rv^T)^T exactly, so the new Schur factor comes from [S_b, Us Rv^T]
+    // (compressed through its Gram matrix unless the right child is a leaf, which takes it as it is)
+    // as soon as Rv exists.  The truncated recompression of L_ba itself (TSQR of Us, core SVD) is not
+    // needed before the inverse blocks of p: it runs on the second stream, joined just before them.
     const int ni = (int)inner.size();
     std::vector<double*> Snew(ni);
     std::vector<int*> rnew(ni);
-    std::vector<int> capSb(ni);
+    std::vector<int> capSb(ni), rcapv(ni);
     std::vector<char> raw(ni);
     for (int i = 0; i < ni; ++i) {
       const Item& it = inner[i];
       const CholTask& T = batch[it.m];
       const Tree* t = T.Z->t;
+      const int l = Tree::level(it.c);
       const int64_t sb = t->size(2 * it.c + 2);
       raw[i] = t->is_leaf(2 * it.c + 2);
-      capSb[i] = raw[i] ? std::min(kMaxStack, it.S.cap + T.Lf->cap[Tree::level(it.c)])
-                        : std::min<int>({(int)sb, T.capS, kMaxStack});
+      rcapv[i] = std::min(kMaxStack, T.Z->cap[l] + it.S.cap);
+      capSb[i] = raw[i] ? std::min(kMaxStack, it.S.cap + rcapv[i]) : std::min<int>({(int)sb, T.capS, kMaxStack});
       Snew[i] = scratch.get<double>((size_t)sb * capSb[i]);
       rnew[i] = scratch.get<int>(1);
     }
+    // stacks, Rv and the second stream's workspace stay allocated until the join
+    const DevArena::Mark mk = scratch.mark();
+    hipEvent_t done = nullptr;
     {
-      const DevArena::Mark mk = scratch.mark();
       std::vector<StackTask> stk, stk2;
       std::vector<ThinTask> th;
       std::vector<RecTask> rec;
+      std::vector<QrJob> vq;
+      std::vector<GemmTask> gw;
       std::vector<SymTask> sym;
-      int maxrows = 1, maxsb = 1;
+      std::vector<double*> Usv(ni), Rvv(ni);
+      std::vector<int*> rsv(ni);
+      int maxrows = 1, maxsb = 1, rmax = 1;
       for (int i = 0; i < ni; ++i) {
         const Item& it = inner[i];
         const CholTask& T = batch[it.m];
@@ -898,11 +953,16 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         const SF& S = it.S;
         maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
         maxsb = std::max<int>(maxsb, (int)sb);
-        const int rcap = std::min(kMaxStack, T.Z->cap[l] + S.cap);
+        const int rcap = rcapv[i];
+        rmax = std::max(rmax, rcap);
         double* Us = scratch.get<double>((size_t)ldc * rcap);
         double* Vs0 = scratch.get<double>((size_t)ldc * rcap);
         double* Vs = scratch.get<double>((size_t)ldc * rcap);
+        double* Rv = scratch.get<double>((size_t)rcap * rcap);
         int* rs = scratch.get<int>(1);
+        Usv[i] = Us;
+        Rvv[i] = Rv;
+        rsv[i] = rs;
         StackTask su{};
         su.dst = Us; su.ld = ldc; su.rows = (int)sb; su.wcap = rcap; su.wout = rs; su.nsrc = 2; su.fidx = T.fidx;
         su.src[0] = {T.Z->U(p, 1), T.Z->rk(p, 1), ldc, T.Z->cap[l], 1.0};
@@ -914,27 +974,73 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         stk.push_back(su);
         stk.push_back(sv);
         th.push_back(ThinTask{view(*T.Linv), a, Vs0, ldc, Vs, ldc, rs, rcap, 1.0, 0.0});
+        vq.push_back(QrJob{Vs, ldc, (int)sa, rs, rcap, Rv, T.fidx});
         RecTask r{};
         r.Us = Us; r.ldus = ldc; r.m = (int)sb; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sa; r.r = rs; r.rcap = rcap;
         r.U = T.Lf->U(p, 1); r.V = T.Lf->V(p, 1); r.ldu = r.ldv = ldc; r.rank = T.Lf->rk(p, 1); r.kcap = T.Lf->cap[l];
-        r.thresh = tol; r.fidx = T.fidx;
+        r.thresh = tol; r.fidx = T.fidx; r.Rv = Rv;
         rec.push_back(r);
-        const int rcS = std::min(kMaxStack, S.cap + T.Lf->cap[l]);
+      }
+      stack(stk, maxrows);
+      if (!side) HQ_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+      hipEvent_t ev_us = take_event(), ev_rv = take_event();
+      HQ_CHECK(hipEventRecord(ev_us, st));
+      // The second stream starts on Us while these run: their workspace must not be handed out again
+      // (to the second stream's buffers below) before the join.
+      keep_scratch = true;
+      mm_thin(th);
+      qr_r(vq);
+      keep_scratch = false;
+      HQ_CHECK(hipEventRecord(ev_rv, st));
+      {  // second stream: TSQR of Us (from when Us exists), then the core once Rv exists
+        HQ_CHECK(hipStreamWaitEvent(side, ev_us, 0));
+        const hipStream_t main_st = st;
+        st = side;
+        keep_scratch = true;
+        try {
+          recompress_group(rec, ev_rv);
+        } catch (...) {
+          st = main_st;
+          keep_scratch = false;
+          throw;
+        }
+        st = main_st;
+        keep_scratch = false;
+        done = take_event();
+        HQ_CHECK(hipEventRecord(done, side));
+      }
+      give_event(ev_us);
+      give_event(ev_rv);
+      // library stream: the Schur factor
+      const DevArena::Mark mk_main = scratch.mark();
+      for (int i = 0; i < ni; ++i) {
+        const Item& it = inner[i];
+        const CholTask& T = batch[it.m];
+        const Tree* t = T.Z->t;
+        const int p = it.c, b = 2 * p + 2, l = Tree::level(p);
+        const int64_t sb = t->size(b), lb = t->lo[b] - t->lo[p];
+        const int ldc = (int)t->ldf[l], rcap = rcapv[i];
+        const SF& S = it.S;
+        double* W = scratch.get<double>((size_t)sb * rcap);
+        GemmTask g{};  // W = Us Rv^T
+        g.A = Usv[i]; g.lda = ldc; g.B = Rvv[i]; g.ldb = rcap; g.opB = 1; g.C = W; g.ldc = (int)sb;
+        g.m = (int)sb; g.n = rcap; g.np = rsv[i]; g.k = rcap; g.kp = rsv[i]; g.alpha = 1.0; g.beta = 0.0;
+        gw.push_back(g);
+        const int rcS = std::min(kMaxStack, S.cap + rcap);
         double* Sraw = raw[i] ? Snew[i] : scratch.get<double>((size_t)sb * rcS);
         int* rsb = raw[i] ? rnew[i] : scratch.get<int>(1);
         StackTask ss{};
-        ss.dst = Sraw; ss.ld = (int)sb; ss.rows = (int)sb; ss.wcap = rcS; ss.wout = rsb; ss.nsrc = 2; ss.fidx = T.fidx;
+        ss.dst = Sraw; ss.ld = (int)sb; ss.rows = (int)sb; ss.wcap = raw[i] ? capSb[i] : rcS; ss.wout = rsb; ss.nsrc = 2;
+        ss.fidx = T.fidx;
         ss.src[0] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
-        ss.src[1] = {T.Lf->U(p, 1), T.Lf->rk(p, 1), ldc, T.Lf->cap[l], 1.0};
+        ss.src[1] = {W, rsv[i], (int)sb, rcap, 1.0};
         stk2.push_back(ss);
         if (!raw[i]) sym.push_back(SymTask{Sraw, (int)sb, (int)sb, rsb, rcS, Snew[i], (int)sb, rnew[i], capSb[i], thS, T.fidx});
       }
-      stack(stk, maxrows);
-      mm_thin(th);
-      recompress(rec);
+      gemm(gw, maxsb, rmax);
       stack(stk2, maxsb);
       compress_sym(sym);
-      scratch.rewind(mk);
+      scratch.rewind(mk_main);
     }
     // right subtrees
     std::vector<Item> right;
@@ -944,6 +1050,8 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       right.push_back(Item{it.m, 2 * it.c + 2, SF{Snew[i], (int)t->size(2 * it.c + 2), rnew[i], capSb[i]}});
     }
     dfs(right);
+    HQ_CHECK(hipStreamWaitEvent(st, done, 0));  // L_ba recompressed
+    give_event(done);
     // inverse blocks
     const DevArena::Mark mk2 = scratch.mark();
     std::vector<ThinTask> th;
@@ -960,6 +1068,7 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     launch_copy_ints(stage.upload(rk, st), (int)rk.size(), st);
     ++launches;
     scratch.rewind(mk2);
+    scratch.rewind(mk);
   };
   std::vector<Item> roots;
   for (int m = 0; m < (int)batch.size(); ++m) roots.push_back(Item{m, 0, SF{nullptr, 1, d_zero, 0}});
