@@ -138,9 +138,11 @@ class Engine {
   Engine& operator=(const Engine&) = delete;
   ~Engine();
   hipStream_t st;
-  // Second stream (default priority) for work off the critical path of the H-Cholesky; created on
-  // first use.  Work issued there is always joined back into st before its memory is released.
-  hipStream_t side = nullptr;
+  // Further streams (default priority) for work off the critical path: the recompression of L_ba in
+  // the H-Cholesky, the C blocks of each level of a product.  Created on first use; work issued there
+  // is always joined back into st before its memory is released.
+  static constexpr int kSides = 3;
+  hipStream_t side_stream(int i);
   bool keep_scratch = false;  // set while issuing side-stream work: helpers then keep their workspace
   DevArena persist, scratch;
   DescStage stage;
@@ -230,6 +232,7 @@ class Engine {
 
  private:
   std::vector<hipEvent_t> ev_all, ev_free;
+  hipStream_t sides_[kSides] = {};
 };
 
 }  // namespace hq

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <map>
+#include <mutex>
 
 namespace hq {
 
@@ -35,8 +37,67 @@ void Tree::build(int64_t n_, int leaf_) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Chunk cache.  Every call builds its engine and arenas afresh; the device chunks (256 MiB or one
+// larger allocation) and pinned descriptor chunks they release are kept per device for the next
+// call instead of going back to the runtime (hipMalloc / hipHostMalloc of large blocks cost
+// milliseconds per call, and hipFree synchronises the device).  Chunks are returned only after the
+// device has drained, so a later call on any stream may reuse them at once.
+namespace {
+struct ChunkCache {
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<char*>> dev, host;  // (device, capacity) -> chunks
+};
+ChunkCache& cache() {
+  static ChunkCache* c = new ChunkCache;  // never destroyed: chunks live until the process ends
+  return *c;
+}
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+// Smallest cached chunk of capacity in [bytes, 2 bytes], or nullptr.
+char* take_cached(std::map<std::pair<int, size_t>, std::vector<char*>>& m, int dev, size_t bytes, size_t& cap) {
+  auto it = m.lower_bound({dev, bytes});
+  for (; it != m.end() && it->first.first == dev && it->first.second <= 2 * bytes; ++it)
+    if (!it->second.empty()) {
+      char* p = it->second.back();
+      it->second.pop_back();
+      cap = it->first.second;
+      return p;
+    }
+  return nullptr;
+}
+}  // namespace
+
+static char* chunk_alloc(size_t bytes, size_t& cap, bool host) {
+  ChunkCache& c = cache();
+  const int dev = current_device();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (char* p = take_cached(host ? c.host : c.dev, dev, bytes, cap)) return p;
+  }
+  char* p = nullptr;
+  cap = bytes;
+  if (host)
+    HQ_CHECK(hipHostMalloc((void**)&p, bytes, hipHostMallocDefault));
+  else
+    HQ_CHECK(hipMalloc((void**)&p, bytes));
+  return p;
+}
+static void chunks_release(const std::vector<std::pair<char*, size_t>>& v, bool host) {
+  if (v.empty()) return;
+  (void)hipDeviceSynchronize();  // no kernel may still use them
+  ChunkCache& c = cache();
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (const auto& x : v) (host ? c.host : c.dev)[{dev, x.second}].push_back(x.first);
+}
+
 DevArena::~DevArena() {
-  for (auto& c : chunks_) (void)hipFree(c.p);
+  std::vector<std::pair<char*, size_t>> v;
+  for (auto& c : chunks_) v.push_back({c.p, c.cap});
+  chunks_release(v, false);
 }
 void* DevArena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
@@ -52,8 +113,7 @@ void* DevArena::alloc(size_t bytes) {
     ++cur_;
   }
   Chunk c;
-  c.cap = std::max(chunk_bytes, bytes);
-  HQ_CHECK(hipMalloc(&c.p, c.cap));
+  c.p = chunk_alloc(std::max(chunk_bytes, bytes), c.cap, false);
   c.used = bytes;
   chunks_.push_back(c);
   cur_ = chunks_.size() - 1;
@@ -74,7 +134,9 @@ void DevArena::reset() {
 }
 
 DescStage::~DescStage() {
-  for (auto& c : chunks_) (void)hipHostFree(c.h);
+  std::vector<std::pair<char*, size_t>> v;
+  for (auto& c : chunks_) v.push_back({c.h, c.cap});
+  chunks_release(v, true);
 }
 // Descriptors are written into pinned, device-visible host memory and read by the kernels from
 // there: no copy launch per kernel launch (each workgroup reads its few hundred bytes once).  The
@@ -87,8 +149,7 @@ void* DescStage::up(const void* src, size_t bytes, hipStream_t s) {
   while (cur_ < chunks_.size() && chunks_[cur_].used + need > chunks_[cur_].cap) ++cur_;
   if (cur_ == chunks_.size()) {
     Chunk c;
-    c.cap = std::max(need, size_t(32) << 20);
-    HQ_CHECK(hipHostMalloc((void**)&c.h, c.cap, hipHostMallocDefault));
+    c.h = chunk_alloc(std::max(need, size_t(32) << 20), c.cap, true);
     c.used = 0;
     chunks_.push_back(c);
   }
@@ -129,12 +190,19 @@ Engine::Engine(hipStream_t s) : st(s) {
   HQ_CHECK(hipMemsetAsync(d_flag, 0, sizeof(int) * (kFlagSlots + 64), st));
 }
 Engine::~Engine() {
-  if (side) {
-    (void)hipStreamSynchronize(side);
-    (void)hipStreamDestroy(side);
-  }
+  for (hipStream_t& sd : sides_)
+    if (sd) {
+      (void)hipStreamSynchronize(sd);
+      (void)hipStreamDestroy(sd);
+    }
   for (hipEvent_t e : ev_all) (void)hipEventDestroy(e);
   if (d_flag) (void)hipFree(d_flag);
+}
+
+hipStream_t Engine::side_stream(int i) {
+  hipStream_t& sd = sides_[i % kSides];
+  if (!sd) HQ_CHECK(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+  return sd;
 }
 
 hipEvent_t Engine::take_event() {
@@ -608,8 +676,10 @@ void Engine::product(const std::vector<ProdTask>& batch) {
   }
   mm_thin(thin);
 
-  // 2) level sweep: C blocks of level l and the accumulated terms of level l+1.  The children's
-  // terms are allocated first; everything else of the level is released after its launches.
+  // 2) level sweep: the accumulated terms of level l+1 (each level needs the previous one's).  The
+  // children's terms are allocated first and kept; everything else of the level is released after
+  // its launches.
+  std::vector<hipEvent_t> cdone;
   for (int l = 0; l < Lmax; ++l) {
     for (int m = 0; m < nm; ++m) {
       const ProdTask& P = batch[m];
@@ -632,6 +702,90 @@ void Engine::product(const std::vector<ProdTask>& batch) {
         }
       }
     }
+    // C blocks of level l feed no later level: they are stacked and recompressed on side stream
+    // l mod kSides as soon as the terms of level l exist, while the library stream goes on with the
+    // terms of level l+1.  Their buffers sit below the level mark and are kept until the join.
+    {
+      std::vector<StackTask> stk;
+      std::vector<RecTask> rec;
+      int maxrows = 1;
+      for (int m = 0; m < nm; ++m) {
+        const ProdTask& P = batch[m];
+        const Tree* t = P.C->t;
+        if (l >= t->L) continue;
+        const bool full = !P.C->lower_only;
+        const HView* D = P.D.h ? &P.D : nullptr;
+        const double alpha = P.alpha, delta = P.delta;
+        HMat& C = *P.C;
+        std::vector<TermF>& term = termm[m];
+        const int f0 = (1 << l) - 1, cnt = 1 << l;
+        const int ldc = (int)t->ldf[l];
+        for (int p = f0; p < f0 + cnt; ++p) {
+          const int a = 2 * p + 1, b = 2 * p + 2;
+          const int64_t sa = t->size(a), sb = t->size(b), ofa = t->lo[a] - t->lo[p], ofb = t->lo[b] - t->lo[p];
+          maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
+          const HView::Blk Au = P.A.upper(p), Al = P.A.lower(p), Bu = P.B.upper(p), Bl = P.B.lower(p);
+          const TermF Tp = term[p];
+          for (int s = 0; s < 2; ++s) {
+            if (s == 0 && !full) continue;
+            const int64_t mr = s == 0 ? sa : sb, mc = s == 0 ? sb : sa;
+            const int64_t ofr = s == 0 ? ofa : ofb, ofc = s == 0 ? ofb : ofa;
+            const HView::Blk Ax = s == 0 ? Au : Al, Bx = s == 0 ? Bu : Bl;
+            const NodeBufs& q = nbm[m][p];
+            double* P_left = s == 0 ? q.P1 : q.P3;   // A_xx U_B  (rows r)
+            double* P_right = s == 0 ? q.P2 : q.P4;  // B_yy^T V_A (rows c)
+            HView::Blk Dx{nullptr, nullptr, d_zero, 1, 0};
+            if (D && !P.d_identity) Dx = s == 0 ? D->upper(p) : D->lower(p);
+            const int rcap = std::min(kMaxStack, Bx.cap + Ax.cap + Tp.cap + Dx.cap);  // wider: flagged by k_stack
+            double* Us = scratch.get<double>((size_t)ldc * rcap);
+            double* Vs = scratch.get<double>((size_t)ldc * rcap);
+            int* rs = scratch.get<int>(1);
+            StackTask su{};
+            su.dst = Us; su.ld = ldc; su.rows = (int)mr; su.wcap = rcap; su.wout = rs; su.nsrc = 4; su.fidx = P.fidx;
+            su.src[0] = {P_left, Bx.r, ldc, Bx.cap, alpha};
+            su.src[1] = {Ax.U, Ax.r, Ax.ld, Ax.cap, alpha};
+            su.src[2] = {Tp.E ? Tp.E + ofr : nullptr, Tp.r, Tp.ld, Tp.cap, alpha};
+            su.src[3] = {Dx.U, Dx.r, Dx.ld, Dx.cap, delta};
+            StackTask sv = su;
+            sv.dst = Vs; sv.rows = (int)mc; sv.wout = nullptr;
+            sv.src[0] = {Bx.V, Bx.r, Bx.ld, Bx.cap, 1.0};
+            sv.src[1] = {P_right, Ax.r, ldc, Ax.cap, 1.0};
+            sv.src[2] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
+            sv.src[3] = {Dx.V, Dx.r, Dx.ld, Dx.cap, 1.0};
+            stk.push_back(su);
+            stk.push_back(sv);
+            RecTask r{};
+            r.Us = Us; r.ldus = ldc; r.m = (int)mr; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mc; r.r = rs; r.rcap = rcap;
+            r.U = C.U(p, s); r.V = C.V(p, s); r.ldu = r.ldv = ldc; r.rank = C.rk(p, s); r.kcap = C.cap[l];
+            r.thresh = tol; r.fidx = P.fidx;
+            rec.push_back(r);
+          }
+        }
+      }
+      if (!rec.empty()) {
+        const hipStream_t sd = side_stream(l);
+        hipEvent_t ready = take_event();
+        HQ_CHECK(hipEventRecord(ready, st));
+        HQ_CHECK(hipStreamWaitEvent(sd, ready, 0));
+        give_event(ready);
+        const hipStream_t main_st = st;
+        st = sd;
+        keep_scratch = true;
+        try {
+          stack(stk, maxrows);
+          recompress_group(rec);
+        } catch (...) {
+          st = main_st;
+          keep_scratch = false;
+          throw;
+        }
+        st = main_st;
+        keep_scratch = false;
+        hipEvent_t d = take_event();
+        HQ_CHECK(hipEventRecord(d, sd));
+        cdone.push_back(d);
+      }
+    }
     const DevArena::Mark level_mark = scratch.mark();
     std::vector<GemmTask> gm, gg;
     std::vector<StackTask> stk;
@@ -641,10 +795,6 @@ void Engine::product(const std::vector<ProdTask>& batch) {
       const ProdTask& P = batch[m];
       const Tree* t = P.C->t;
       if (l >= t->L) continue;
-      const bool full = !P.C->lower_only;
-      const HView* D = P.D.h ? &P.D : nullptr;
-      const double alpha = P.alpha, delta = P.delta;
-      HMat& C = *P.C;
       std::vector<TermF>& term = termm[m];
       const int f0 = (1 << l) - 1, cnt = 1 << l;
       const int ldc = (int)t->ldf[l];
@@ -656,41 +806,6 @@ void Engine::product(const std::vector<ProdTask>& batch) {
         const TermF Tp = term[p];
         mcapA = std::max(mcapA, std::max(Au.cap, Al.cap));
         mcapB = std::max(mcapB, std::max(Bu.cap, Bl.cap));
-        // --- C blocks
-        for (int s = 0; s < 2; ++s) {
-          if (s == 0 && !full) continue;
-          const int64_t mr = s == 0 ? sa : sb, mc = s == 0 ? sb : sa;
-          const int64_t ofr = s == 0 ? ofa : ofb, ofc = s == 0 ? ofb : ofa;
-          const HView::Blk Ax = s == 0 ? Au : Al, Bx = s == 0 ? Bu : Bl;
-          const NodeBufs& q = nbm[m][p];
-          double* P_left = s == 0 ? q.P1 : q.P3;   // A_xx U_B  (rows r)
-          double* P_right = s == 0 ? q.P2 : q.P4;  // B_yy^T V_A (rows c)
-          HView::Blk Dx{nullptr, nullptr, d_zero, 1, 0};
-          if (D && !P.d_identity) Dx = s == 0 ? D->upper(p) : D->lower(p);
-          const int rcap = std::min(kMaxStack, Bx.cap + Ax.cap + Tp.cap + Dx.cap);  // wider: flagged by k_stack
-          double* Us = scratch.get<double>((size_t)ldc * rcap);
-          double* Vs = scratch.get<double>((size_t)ldc * rcap);
-          int* rs = scratch.get<int>(1);
-          StackTask su{};
-          su.dst = Us; su.ld = ldc; su.rows = (int)mr; su.wcap = rcap; su.wout = rs; su.nsrc = 4; su.fidx = P.fidx;
-          su.src[0] = {P_left, Bx.r, ldc, Bx.cap, alpha};
-          su.src[1] = {Ax.U, Ax.r, Ax.ld, Ax.cap, alpha};
-          su.src[2] = {Tp.E ? Tp.E + ofr : nullptr, Tp.r, Tp.ld, Tp.cap, alpha};
-          su.src[3] = {Dx.U, Dx.r, Dx.ld, Dx.cap, delta};
-          StackTask sv = su;
-          sv.dst = Vs; sv.rows = (int)mc; sv.wout = nullptr;
-          sv.src[0] = {Bx.V, Bx.r, Bx.ld, Bx.cap, 1.0};
-          sv.src[1] = {P_right, Ax.r, ldc, Ax.cap, 1.0};
-          sv.src[2] = {Tp.F ? Tp.F + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
-          sv.src[3] = {Dx.V, Dx.r, Dx.ld, Dx.cap, 1.0};
-          stk.push_back(su);
-          stk.push_back(sv);
-          RecTask r{};
-          r.Us = Us; r.ldus = ldc; r.m = (int)mr; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mc; r.r = rs; r.rcap = rcap;
-          r.U = C.U(p, s); r.V = C.V(p, s); r.ldu = r.ldv = ldc; r.rank = C.rk(p, s); r.kcap = C.cap[l];
-          r.thresh = tol; r.fidx = P.fidx;
-          rec.push_back(r);
-        }
         // --- terms for the children: T_a = T_p|aa + Uu_A (Vu_A^T Ul_B) Vl_B^T, T_b = T_p|bb + Ul_A (Vl_A^T Uu_B) Vu_B^T
         for (int s = 0; s < 2; ++s) {
           const int c = s == 0 ? a : b;
@@ -788,6 +903,10 @@ void Engine::product(const std::vector<ProdTask>& batch) {
   if (!zr.empty()) {
     launch_copy_ints(stage.upload(zr, st), (int)zr.size(), st);
     ++launches;
+  }
+  for (hipEvent_t d : cdone) {  // C blocks of every level
+    HQ_CHECK(hipStreamWaitEvent(st, d, 0));
+    give_event(d);
   }
 }
 
@@ -982,7 +1101,7 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         rec.push_back(r);
       }
       stack(stk, maxrows);
-      if (!side) HQ_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+      const hipStream_t side = side_stream(0);
       hipEvent_t ev_us = take_event(), ev_rv = take_event();
       HQ_CHECK(hipEventRecord(ev_us, st));
       // The second stream starts on Us while these run: their workspace must not be handed out again
