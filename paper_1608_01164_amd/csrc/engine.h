@@ -233,6 +233,7 @@ class Engine {
  private:
   std::vector<hipEvent_t> ev_all, ev_free;
   hipStream_t sides_[kSides] = {};
+  int next_side = 0;
 };
 
 }  // namespace hq

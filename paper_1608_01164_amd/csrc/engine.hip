@@ -1101,7 +1101,7 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         rec.push_back(r);
       }
       stack(stk, maxrows);
-      const hipStream_t side = side_stream(0);
+      const hipStream_t side = side_stream(next_side++);  // consecutive nodes on different streams
       hipEvent_t ev_us = take_event(), ev_rv = take_event();
       HQ_CHECK(hipEventRecord(ev_us, st));
       // The second stream starts on Us while these run: their workspace must not be handed out again
