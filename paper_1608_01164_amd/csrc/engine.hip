@@ -674,7 +674,29 @@ void Engine::product(const std::vector<ProdTask>& batch) {
       thin.push_back({P.B.T(), a, Al.V, Al.ld, q.P4, ld, Al.r, Al.cap, 1.0, 0.0});  // B_aa^T Vl_A
     }
   }
-  mm_thin(thin);
+  // The thin products only feed the C blocks: they run on side stream 0, ahead of the C blocks of
+  // level 0, while the library stream starts on the terms.
+  hipEvent_t thin_ready = take_event();
+  {
+    const hipStream_t sd = side_stream(0);
+    hipEvent_t ev = take_event();
+    HQ_CHECK(hipEventRecord(ev, st));
+    HQ_CHECK(hipStreamWaitEvent(sd, ev, 0));
+    give_event(ev);
+    const hipStream_t main_st = st;
+    st = sd;
+    keep_scratch = true;
+    try {
+      mm_thin(thin);
+    } catch (...) {
+      st = main_st;
+      keep_scratch = false;
+      throw;
+    }
+    st = main_st;
+    keep_scratch = false;
+    HQ_CHECK(hipEventRecord(thin_ready, sd));
+  }
 
   // 2) level sweep: the accumulated terms of level l+1 (each level needs the previous one's).  The
   // children's terms are allocated first and kept; everything else of the level is released after
@@ -767,6 +789,7 @@ void Engine::product(const std::vector<ProdTask>& batch) {
         hipEvent_t ready = take_event();
         HQ_CHECK(hipEventRecord(ready, st));
         HQ_CHECK(hipStreamWaitEvent(sd, ready, 0));
+        HQ_CHECK(hipStreamWaitEvent(sd, thin_ready, 0));
         give_event(ready);
         const hipStream_t main_st = st;
         st = sd;
@@ -908,6 +931,8 @@ void Engine::product(const std::vector<ProdTask>& batch) {
     HQ_CHECK(hipStreamWaitEvent(st, d, 0));
     give_event(d);
   }
+  HQ_CHECK(hipStreamWaitEvent(st, thin_ready, 0));
+  give_event(thin_ready);
 }
 
 // ---------------------------------------------------------------------------------------------
