@@ -477,8 +477,9 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
   } drain{st};
   size_t peak = 0;
   auto note_peak = [&] {
-    peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + xa[0].high_water() +
-                              xa[1].high_water() + it.high_water() + qa.high_water() + pa.high_water());
+    peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + E.side_high_water() +
+                              xa[0].high_water() + xa[1].high_water() + it.high_water() + qa.high_water() +
+                              pa.high_water());
   };
   if (o.predictor) {
     predict_capacities(ms, o, st, E);
@@ -909,9 +910,7 @@ hq_status spectral_projector_batched(int32_t count, const double* const* bands, 
     // Members run in consecutive chunks whose estimated working set fits 60% of the free device
     // memory: about 8.5 KB per n (b + 1) L, L the tree depth (measured on banded workloads with
     // capacities of twice the previous ranks).
-    size_t free_b = 0, total_b = 0;
-    HQ_CHECK(hipMemGetInfo(&free_b, &total_b));
-    const double budget = 0.6 * (double)free_b;
+    const double budget = 0.6 * (double)hq::free_device_bytes();
     std::vector<Member> ms(count);
     for (int i = 0; i < count; ++i) {
       ms[i].band = bands[i];

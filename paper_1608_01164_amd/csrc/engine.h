@@ -8,6 +8,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kernels.h"
@@ -56,6 +57,13 @@ class DevArena {
   template <class T>
   T* get(size_t count) { return static_cast<T*>(alloc(sizeof(T) * (count ? count : 1))); }
   void reset();  // keeps chunks, rewinds
+  void swap(DevArena& o) {
+    chunks_.swap(o.chunks_);
+    std::swap(cur_, o.cur_);
+    std::swap(inuse_, o.inuse_);
+    std::swap(high_, o.high_);
+    std::swap(chunk_bytes, o.chunk_bytes);
+  }
   struct Mark { size_t cur, used, inuse; };
   Mark mark() const { return Mark{cur_, cur_ < chunks_.size() ? chunks_[cur_].used : 0, inuse_}; }
   void rewind(const Mark& m);  // memory handed out after m may be reused (stream order keeps it safe)
@@ -67,6 +75,10 @@ class DevArena {
   std::vector<Chunk> chunks_;
   size_t cur_ = 0, inuse_ = 0, high_ = 0;
 };
+
+// Device memory free for this library's use: the runtime's free memory plus the chunks kept for
+// reuse by earlier calls.
+size_t free_device_bytes();
 
 // Task descriptors in pinned host memory that the kernels read directly.
 class DescStage {
@@ -234,6 +246,16 @@ class Engine {
   std::vector<hipEvent_t> ev_all, ev_free;
   hipStream_t sides_[kSides] = {};
   int next_side = 0;
+
+ public:
+  // Workspace of the product's C blocks issued on side stream k: reset when stream k is next used
+  // for them (stream order makes the reuse safe), so at most kSides levels hold buffers at a time.
+  DevArena side_arena[kSides];
+  size_t side_high_water() const {
+    size_t h = 0;
+    for (const DevArena& a : side_arena) h += a.high_water();
+    return h;
+  }
 };
 
 }  // namespace hq

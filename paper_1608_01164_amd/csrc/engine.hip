@@ -85,6 +85,17 @@ static char* chunk_alloc(size_t bytes, size_t& cap, bool host) {
     HQ_CHECK(hipMalloc((void**)&p, bytes));
   return p;
 }
+size_t free_device_bytes() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+  ChunkCache& c = cache();
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (const auto& kv : c.dev)
+    if (kv.first.first == dev) free_b += kv.first.second * kv.second.size();
+  return free_b;
+}
+
 static void chunks_release(const std::vector<std::pair<char*, size_t>>& v, bool host) {
   if (v.empty()) return;
   (void)hipDeviceSynchronize();  // no kernel may still use them
@@ -183,8 +194,7 @@ HView::Blk HView::lower(int p) const {
 
 // ---------------------------------------------------------------------------------------------
 Engine::Engine(hipStream_t s) : st(s) {
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) rec_budget = std::max(rec_budget, free_b / 4);
+  rec_budget = std::max(rec_budget, free_device_bytes() / 4);
   HQ_CHECK(hipMalloc(&d_flag, sizeof(int) * (kFlagSlots + 64)));
   d_zero = d_flag + kFlagSlots;
   HQ_CHECK(hipMemsetAsync(d_flag, 0, sizeof(int) * (kFlagSlots + 64), st));
@@ -726,11 +736,15 @@ void Engine::product(const std::vector<ProdTask>& batch) {
     }
     // C blocks of level l feed no later level: they are stacked and recompressed on side stream
     // l mod kSides as soon as the terms of level l exist, while the library stream goes on with the
-    // terms of level l+1.  Their buffers sit below the level mark and are kept until the join.
+    // terms of level l+1.  Their stacks and workspace come from that stream's own arena, whose
+    // previous contents only work issued earlier on the same stream used.
     {
       std::vector<StackTask> stk;
       std::vector<RecTask> rec;
       int maxrows = 1;
+      DevArena& sa_l = side_arena[l % kSides];
+      sa_l.reset();
+      scratch.swap(sa_l);
       for (int m = 0; m < nm; ++m) {
         const ProdTask& P = batch[m];
         const Tree* t = P.C->t;
@@ -798,6 +812,7 @@ void Engine::product(const std::vector<ProdTask>& batch) {
           stack(stk, maxrows);
           recompress_group(rec);
         } catch (...) {
+          scratch.swap(sa_l);
           st = main_st;
           keep_scratch = false;
           throw;
@@ -808,6 +823,7 @@ void Engine::product(const std::vector<ProdTask>& batch) {
         HQ_CHECK(hipEventRecord(d, sd));
         cdone.push_back(d);
       }
+      scratch.swap(sa_l);
     }
     const DevArena::Mark level_mark = scratch.mark();
     std::vector<GemmTask> gm, gg;
