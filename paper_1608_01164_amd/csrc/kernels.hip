@@ -1264,7 +1264,9 @@ static __device__ __forceinline__ int svd_qrcp(T* Bm, const int ldb, const int r
 //        Jk[perm[c], o] = W[c, ord(o)] / sigma      (right singular vectors)
 //        Wk = Q_t [J[:, ord(o)] / sigma ; 0]         (left singular vectors over sigma)
 // Returns the number of sweeps.
-template <typename T, int EM, int G>
+// PAD: the columns of C and J have EM G rows of storage each (ldc = ldj = EM G), zero beyond r and t,
+// so the rotation loop moves whole register segments with no per-element bounds.
+template <typename T, int EM, int G, bool PAD = false>
 static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C, const int ldc, T* J, const int ldj,
                                                const int r, const int t, const SvdTask& Tk, int* flag,
                                                const SvdShared<T>& S, const T* tau, const T* vhead,
@@ -1274,12 +1276,14 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane / G, sl = lane & (G - 1);
   // rows padded to multiples of G with zeros (rotations keep them zero)
   const int rpad = (r + G - 1) / G * G, tpad = (t + G - 1) / G * G, er = rpad / G, et = tpad / G;
-  for (int idx = tid; idx < rpad * t; idx += SVD_THREADS) {
-    const int c = idx % rpad, i = idx / rpad;  // C[c, i] = R[i, c]
+  const int crows = PAD ? EM * G : rpad, jrows = PAD ? EM * G : tpad;  // rows initialised
+  const int ser = PAD ? EM : er, set = PAD ? EM : et;                  // elements moved by the rotations
+  for (int idx = tid; idx < crows * t; idx += SVD_THREADS) {
+    const int c = idx % crows, i = idx / crows;  // C[c, i] = R[i, c]
     C[c + (size_t)i * ldc] = (c >= i && c < r) ? Bm[i + (size_t)c * ldb] : (T)0;
   }
-  for (int idx = tid; idx < tpad * t; idx += SVD_THREADS) {
-    const int i = idx % tpad, c = idx / tpad;
+  for (int idx = tid; idx < jrows * t; idx += SVD_THREADS) {
+    const int i = idx % jrows, c = idx / jrows;
     J[i + (size_t)c * ldj] = (i == c) ? (T)1 : (T)0;
   }
   __syncthreads();
@@ -1316,8 +1320,8 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
         const T a = nrm2[pp], b = nrm2[qq];
         if constexpr (EM > 0) {
           T up[EM], uq[EM];
-          seg_load<EM, G>(up, cp, 0, er, sl);
-          seg_load<EM, G>(uq, cq, 0, er, sl);
+          seg_load<EM, G>(up, cp, 0, ser, sl);
+          seg_load<EM, G>(uq, cq, 0, ser, sl);
           T gg = 0;
 #pragma unroll
           for (int e = 0; e < EM; ++e) gg += up[e] * uq[e];
@@ -1328,18 +1332,21 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
           my_rots += rot && sl == 0;
           T tt = 0, cs = 1, sn = 0;
           if (rot) jacobi_angle(a, b, gg, tt, cs, sn);
-          T na = 0, nb = 0;
 #pragma unroll
           for (int e = 0; e < EM; ++e) {
             const T u2 = cs * up[e] - sn * uq[e], w2 = sn * up[e] + cs * uq[e];
             up[e] = u2;
             uq[e] = w2;
-            na += u2 * u2;
-            nb += w2 * w2;
           }
           T ea = a - tt * gg, eb = b + tt * gg;  // exact-arithmetic norms after the rotation
           const bool exact = rot && (!(ea > (T)0.25 * a) || !(eb > (T)0.25 * b));  // cancellation: computed norms
           if (__any(exact)) {  // wave-uniform; rare
+            T na = 0, nb = 0;
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+              na += up[e] * up[e];
+              nb += uq[e] * uq[e];
+            }
             na = group_sum<G>(na);
             nb = group_sum<G>(nb);
             if (exact) {
@@ -1348,21 +1355,21 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
             }
           }
           if (rot) {
-            seg_store<EM, G>(up, cp, 0, er, sl);
-            seg_store<EM, G>(uq, cq, 0, er, sl);
+            seg_store<EM, G>(up, cp, 0, ser, sl);
+            seg_store<EM, G>(uq, cq, 0, ser, sl);
             T* jp = J + (size_t)pp * ldj;
             T* jq = J + (size_t)qq * ldj;
             T vp[EM], vq[EM];
-            seg_load<EM, G>(vp, jp, 0, et, sl);
-            seg_load<EM, G>(vq, jq, 0, et, sl);
+            seg_load<EM, G>(vp, jp, 0, set, sl);
+            seg_load<EM, G>(vq, jq, 0, set, sl);
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
               const T u2 = cs * vp[e] - sn * vq[e], w2 = sn * vp[e] + cs * vq[e];
               vp[e] = u2;
               vq[e] = w2;
             }
-            seg_store<EM, G>(vp, jp, 0, et, sl);
-            seg_store<EM, G>(vq, jq, 0, et, sl);
+            seg_store<EM, G>(vp, jp, 0, set, sl);
+            seg_store<EM, G>(vq, jq, 0, set, sl);
             if (sl == 0) {
               nrm2[pp] = ea;
               nrm2[qq] = eb;
@@ -1572,7 +1579,16 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
   const int tpad = (t + G - 1) / G * G;
   const int nB = rpad * r, nC = rpad * t, nJ = tpad * t;
   int nsweeps;
-  if (bl && nB + nC + nJ <= SVD_LDS) {
+  if (EM > 0 && 2 * EM * G * t <= SVD_LDS && !(bl && nB + nC + nJ <= SVD_LDS && EM * G > 2 * rpad)) {
+    // C and J in LDS with whole-segment columns; B (reflectors) in global memory
+    if (bl) {
+      for (int idx = tid; idx < nB; idx += SVD_THREADS) Bglob[(idx % rpad) + (size_t)(idx / rpad) * Tk.ld] = slds[idx];
+      __syncthreads();
+    }
+    constexpr int LD = EM > 0 ? EM * G : 1;
+    nsweeps = svd_tail<T, EM, G, true>(Bglob, Tk.ld, slds, LD, slds + LD * t, LD, r, t, Tk, flag, S, tau, vhead,
+                                       my_pairs, my_rots, c2);
+  } else if (bl && nB + nC + nJ <= SVD_LDS) {
     nsweeps = svd_tail<T, EM, G>(slds, rpad, slds + nB, rpad, slds + nB + nC, tpad, r, t, Tk, flag, S, tau, vhead,
                               my_pairs, my_rots, c2);
   } else {
@@ -1582,9 +1598,13 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
     }
     T* const Cg = reinterpret_cast<T*>(Tk.C);
     T* const Jg = reinterpret_cast<T*>(Tk.Jw);
+    constexpr int LD = EM > 0 ? EM * G : 1;
     if (nC + nJ <= SVD_LDS)
       nsweeps = svd_tail<T, EM, G>(Bglob, Tk.ld, slds, rpad, slds + nC, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
                                 my_rots, c2);
+    else if (EM > 0 && LD * t <= SVD_LDS && Tk.ld >= LD)  // C in LDS with whole-segment columns, J global
+      nsweeps = svd_tail<T, EM, G, true>(Bglob, Tk.ld, slds, LD, Jg, Tk.ld, r, t, Tk, flag, S, tau, vhead, my_pairs,
+                                         my_rots, c2);
     else if (nJ <= SVD_LDS)
       nsweeps = svd_tail<T, EM, G>(Bglob, Tk.ld, Cg, Tk.ld, slds, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
                                 my_rots, c2);
