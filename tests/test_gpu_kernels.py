@@ -132,10 +132,12 @@ def test_qr_r_columns_near_underflow(rows, r):
 
 
 # stacked widths 1.5 r: cores of up to 128, 256 and 512 columns take the register paths (16-lane
-# groups, then 32-lane groups), wider ones the looped path
+# groups, then 32-lane groups), wider ones the looped path; the two 256-column cases keep whole
+# 256-row column segments in LDS (rank about 31: C and J there; about 60: C there, J global)
 @pytest.mark.parametrize("m,n,r,decay", [(50, 60, 10, 1.0), (300, 200, 40, 0.6), (1200, 900, 90, 0.8),
                                          (64, 64, 64, 0.5), (10, 400, 30, 0.3), (600, 700, 180, 0.85),
-                                         (1500, 1200, 200, 0.88), (2000, 2000, 300, 0.92), (2000, 1800, 360, 0.9)])
+                                         (1500, 1200, 200, 0.88), (2000, 2000, 300, 0.92), (2000, 1800, 360, 0.9),
+                                         (600, 500, 171, 0.45), (1500, 1200, 171, 0.656)])
 def test_recompress(m, n, r, decay):
     rng = np.random.default_rng(m + n + r)
     s = decay ** np.arange(r)
@@ -233,7 +235,8 @@ def test_cholesky_inverse(n, leaf):
     assert np.abs(G - np.linalg.inv(Lref)).max() < 1e-9
 
 
-@pytest.mark.parametrize("n,leaf,row", [(64, 64, 0), (128, 128, 93), (126, 126, 125), (300, 37, 41)])
+@pytest.mark.parametrize("n,leaf,row", [(64, 64, 0), (128, 128, 93), (126, 126, 125), (300, 37, 41),
+                                        (200, 200, 50), (200, 200, 150), (255, 255, 254)])
 def test_cholesky_inverse_indefinite_is_reported(n, leaf, row):
     """A leaf whose Schur complement loses positive definiteness (a negative eigenvalue planted in
     the coupling of row `row`) reports status 2; padded rows of a ragged leaf never do."""
