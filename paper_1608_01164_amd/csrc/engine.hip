@@ -719,16 +719,18 @@ void Engine::product(const std::vector<ProdTask>& batch) {
       if (l >= t->L) continue;
       const int f0 = (1 << l) - 1, cnt = 1 << l;
       const int ldc = (int)t->ldf[l];
+      // terms of leaves only enter the dense leaf products: they stay stacked (no recompression)
+      const bool raw = l == t->L - 1;
       for (int p = f0; p < f0 + cnt; ++p) {
         const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
-        const HView::Blk Au = P.A.upper(p), Bu = P.B.upper(p);
+        const HView::Blk Au = P.A.upper(p), Bu = P.B.upper(p), Bl = P.B.lower(p);
         const int capT = std::min<int>({(int)std::max(sa, sb), std::max(P.C->cap[l], std::max(Au.cap, Bu.cap)) * 2, kMaxStack});
         for (int c = 2 * p + 1; c <= 2 * p + 2; ++c) {
           TermF nt;
           nt.ld = ldc;
-          nt.cap = capT;
-          nt.E = scratch.get<double>((size_t)nt.ld * capT);
-          nt.F = scratch.get<double>((size_t)nt.ld * capT);
+          nt.cap = raw ? std::min(kMaxStack, termm[m][p].cap + (c == 2 * p + 1 ? Bl.cap : Bu.cap)) : capT;
+          nt.E = scratch.get<double>((size_t)nt.ld * nt.cap);
+          nt.F = scratch.get<double>((size_t)nt.ld * nt.cap);
           nt.r = scratch.get<int>(1);
           termm[m][c] = nt;
         }
@@ -861,9 +863,11 @@ void Engine::product(const std::vector<ProdTask>& batch) {
           g2.m = (int)mrow; g2.n = By.cap; g2.np = By.r; g2.k = Ax.cap; g2.kp = Ax.r; g2.alpha = 1.0; g2.beta = 0.0;
           gg.push_back(g2);
           const int rcap = std::min(kMaxStack, Tp.cap + By.cap);
-          double* Us = scratch.get<double>((size_t)ldc * rcap);
-          double* Vs = scratch.get<double>((size_t)ldc * rcap);
-          int* rs = scratch.get<int>(1);
+          const TermF& nt = term[c];
+          const bool raw = l == t->L - 1;  // stacked straight into the leaf's term
+          double* Us = raw ? nt.E : scratch.get<double>((size_t)ldc * rcap);
+          double* Vs = raw ? nt.F : scratch.get<double>((size_t)ldc * rcap);
+          int* rs = raw ? const_cast<int*>(nt.r) : scratch.get<int>(1);
           StackTask su{};
           su.dst = Us; su.ld = ldc; su.rows = (int)mrow; su.wcap = rcap; su.wout = rs; su.nsrc = 2; su.fidx = P.fidx;
           su.src[0] = {Tp.E ? Tp.E + ofc : nullptr, Tp.r, Tp.ld, Tp.cap, 1.0};
@@ -874,7 +878,7 @@ void Engine::product(const std::vector<ProdTask>& batch) {
           sv.src[1] = {By.V, By.r, By.ld, By.cap, 1.0};
           stk.push_back(su);
           stk.push_back(sv);
-          const TermF& nt = term[c];
+          if (raw) continue;
           RecTask r{};
           r.Us = Us; r.ldus = ldc; r.m = (int)mrow; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mrow; r.r = rs; r.rcap = rcap;
           r.U = nt.E; r.V = nt.F; r.ldu = r.ldv = nt.ld; r.rank = const_cast<int*>(nt.r); r.kcap = nt.cap; r.thresh = tolT;
