@@ -1,6 +1,6 @@
 // HODLR engine: cluster tree, device storage of HODLR matrices, and the formatted operations of
 // the QDWH iteration (Sec. 3.1.1 of the paper: products with recompression, Cholesky, triangular
-// solves), issued as batched kernel launches on one HIP stream.
+// solves), issued as batched kernel launches on the caller's stream and three side streams.
 #pragma once
 #include <hip/hip_runtime.h>
 

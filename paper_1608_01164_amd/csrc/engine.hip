@@ -1,6 +1,8 @@
 // HODLR engine: storage and formatted arithmetic (Sec. 3.1.1 of the paper, Table complexity_HODLR)
-// mapped onto batched kernels.  Everything is issued on one stream; sizes that depend on ranks are
-// read by the kernels from device memory.
+// mapped onto batched kernels.  Work goes to the caller's stream, except what lies off the critical
+// path (C blocks of a product, the H-Cholesky's off-diagonal recompressions), which goes to side
+// streams joined back through events; sizes that depend on ranks are read by the kernels from
+// device memory.
 #include "engine.h"
 
 #include <algorithm>
