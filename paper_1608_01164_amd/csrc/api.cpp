@@ -206,10 +206,10 @@ int max_of(const std::vector<int>& v) {
 
 void upload_host(hq::Engine& e, const hq::HostHodlr& h, hq::HMat& H, bool sync = true) {
   const hq::Tree& t = *H.t;
-  HQ_CHECK(hipMemcpyAsync(H.leaves, h.leaves.data(), sizeof(double) * h.leaves.size(), hipMemcpyHostToDevice, e.st));
+  HQ_CHECK(hipMemcpyAsync(H.leaves, h.leaves, sizeof(double) * h.nleaves, hipMemcpyHostToDevice, e.st));
   for (int l = 0; l < t.L; ++l) {
-    HQ_CHECK(hipMemcpyAsync(H.Ubase[l], h.U[l].data(), sizeof(double) * h.U[l].size(), hipMemcpyHostToDevice, e.st));
-    HQ_CHECK(hipMemcpyAsync(H.Vbase[l], h.V[l].data(), sizeof(double) * h.V[l].size(), hipMemcpyHostToDevice, e.st));
+    HQ_CHECK(hipMemcpyAsync(H.Ubase[l], h.U[l], sizeof(double) * h.fsize[l], hipMemcpyHostToDevice, e.st));
+    HQ_CHECK(hipMemcpyAsync(H.Vbase[l], h.V[l], sizeof(double) * h.fsize[l], hipMemcpyHostToDevice, e.st));
   }
   if (t.ninternal > 0)
     HQ_CHECK(hipMemcpyAsync(H.rank, h.rank.data(), sizeof(int) * 2 * t.ninternal, hipMemcpyHostToDevice, e.st));
@@ -468,6 +468,7 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
       m.inf.levels = m.t.L;
     }
 
+  std::unique_ptr<hq::PinnedHost> qimg;  // host images of Q1, Q2 (read by copies on the stream)
   hq::Engine E(st);
   E.tol = o.tol;
   hq::DevArena xa[2], it, qa, pa;
@@ -499,19 +500,28 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
     if (act.empty()) break;
     if (k == 0) {
       for (int i : act) ms[i].capX = caps_from(ms[i].t, 3 * ms[i].beff + 8, o.max_rank);
-      // Alg. 3 lines 7-8: structured QR of [sqrt(c0) X0; I] (Algorithms 1/2) and Q1, Q2 in HODLR
+      // Alg. 3 lines 7-8: structured QR of [sqrt(c0) X0; I] (Algorithms 1/2) and Q1, Q2 in HODLR,
+      // built in place in pinned memory (kept until the call ends) and copied from there
       const auto tg = clk::now();
       std::vector<hq::HostHodlr> h1(act.size()), h2(act.size());
+      std::vector<size_t> qoff(act.size() + 1, 0);
+      for (size_t j = 0; j < act.size(); ++j) {
+        const Member& m = ms[act[j]];
+        qoff[j + 1] = qoff[j] + 2 * hq::host_hodlr_doubles(m.t, std::vector<int>(m.t.L, 2 * m.beff), (int)m.t.maxleaf);
+      }
+      qimg.reset(new hq::PinnedHost(sizeof(double) * qoff.back()));
 #pragma omp parallel for schedule(dynamic, 1) if (act.size() > 1)
       for (int j = 0; j < (int)act.size(); ++j) {
         Member& m = ms[act[j]];
         const auto tj = clk::now();
-        const hq::GivensSweep gs = hq::structured_qr(m.ab.data(), m.n, m.beff, m.ldab, m.mu,
-                                                     std::sqrt(m.w.c[0]) / m.inf.alpha);
         const std::vector<int> capQ(m.t.L, 2 * m.beff);
-        hq::q_factors_hodlr(gs, m.t, m.beff, capQ, (int)m.t.maxleaf, h1[j], h2[j]);
+        hq::q_factors_from_band(m.ab.data(), m.n, m.beff, m.ldab, m.mu, std::sqrt(m.w.c[0]) / m.inf.alpha, m.t,
+                                capQ, (int)m.t.maxleaf, h1[j], h2[j], qimg->as<double>() + qoff[j]);
         m.inf.givens_seconds = secs(tj);
       }
+      // The setup launches have long finished by now; the drained stream lets the iteration below
+      // reuse the descriptor stage, while the copies of the images overlap the next host work.
+      HQ_CHECK(hipStreamSynchronize(st));
       for (size_t j = 0; j < act.size(); ++j) {
         Member& m = ms[act[j]];
         const std::vector<int> capQ(m.t.L, 2 * m.beff);
@@ -520,7 +530,6 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         upload_host(E, h1[j], m.Q1, false);
         upload_host(E, h2[j], m.Q2, false);
       }
-      HQ_CHECK(hipStreamSynchronize(st));  // the host copies go out of scope
       if (act.size() > 1)
         for (int i : act) ms[i].inf.givens_seconds = secs(tg);
     } else if (o.predictor) {
@@ -1296,11 +1305,10 @@ hq_status hq_test_q_factors(const double* band, int64_t n, int32_t b, int64_t ld
     hq::Tree t;
     t.build(n, leaf);
     if (t.L > 0 && (int64_t)b > n / (int64_t(1) << t.L)) return fail(HQ_ERR_UNSUPPORTED, "b > smallest leaf");
-    const hq::GivensSweep gs = hq::structured_qr(band, n, b, ldab, shift, scale);
-    if (nrot) *nrot = (int64_t)gs.rots.size();
     const std::vector<int> capQ(t.L, 2 * b);
     hq::HostHodlr h1, h2;
-    hq::q_factors_hodlr(gs, t, b, capQ, (int)t.maxleaf, h1, h2);
+    const int64_t nr = hq::q_factors_from_band(band, n, b, ldab, shift, scale, t, capQ, (int)t.maxleaf, h1, h2);
+    if (nrot) *nrot = nr;
     hq::Engine E(st);
     hq::HMat Q1 = E.alloc_hmat(&t, capQ, false), Q2 = E.alloc_hmat(&t, capQ, false);
     upload_host(E, h1, Q1);
@@ -1354,12 +1362,11 @@ hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t
     hq::Tree t;
     t.build(n, leaf);
     if (t.L > 0 && (int64_t)b > n / (int64_t(1) << t.L)) return fail(HQ_ERR_UNSUPPORTED, "b > smallest leaf");
-    const hq::GivensSweep gs = hq::structured_qr(band, n, b, ldab, shift, scale);
-    if (nrot) *nrot = (int64_t)gs.rots.size();
     const std::vector<int> cap(t.L, 2 * b);
     hq::HostHodlr h[2];
     const int ldl = (int)t.maxleaf;
-    hq::q_factors_hodlr(gs, t, b, cap, ldl, h[0], h[1]);
+    const int64_t nr = hq::q_factors_from_band(band, n, b, ldab, shift, scale, t, cap, ldl, h[0], h[1]);
+    if (nrot) *nrot = nr;
     for (int w = 0; w < 2; ++w) {
       double* Q = w == 0 ? Q1 : Q2;
       std::fill(Q, Q + n * n, 0.0);
@@ -1376,8 +1383,8 @@ hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t
           const int a = 2 * p + 1, bb = 2 * p + 2;
           const int64_t r0 = s2 == 0 ? t.lo[a] : t.lo[bb], c0 = s2 == 0 ? t.lo[bb] : t.lo[a];
           const int64_t mr = s2 == 0 ? t.size(a) : t.size(bb), mc = s2 == 0 ? t.size(bb) : t.size(a);
-          const double* U = h[w].U[l].data() + (size_t)(2 * i + s2) * ld * cap[l];
-          const double* V = h[w].V[l].data() + (size_t)(2 * i + s2) * ld * cap[l];
+          const double* U = h[w].U[l] + (size_t)(2 * i + s2) * ld * cap[l];
+          const double* V = h[w].V[l] + (size_t)(2 * i + s2) * ld * cap[l];
           const int rk = h[w].rank[2 * p + s2];
           for (int64_t c = 0; c < mc; ++c)
             for (int64_t r = 0; r < mr; ++r) {

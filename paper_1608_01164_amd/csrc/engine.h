@@ -80,6 +80,22 @@ class DevArena {
 // reuse by earlier calls.
 size_t free_device_bytes();
 
+// Pinned host block taken from the chunk cache and handed back to it (once the device has drained)
+// when the object goes; host images of matrices are built in place in it and copied to the device
+// without a staging copy.
+class PinnedHost {
+ public:
+  explicit PinnedHost(size_t bytes);
+  PinnedHost(const PinnedHost&) = delete;
+  PinnedHost& operator=(const PinnedHost&) = delete;
+  ~PinnedHost();
+  template <class T>
+  T* as() const { return reinterpret_cast<T*>(p_); }
+ private:
+  char* p_ = nullptr;
+  size_t cap_ = 0;
+};
+
 // Task descriptors in pinned host memory that the kernels read directly.
 class DescStage {
  public:

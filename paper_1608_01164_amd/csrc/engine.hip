@@ -146,6 +146,9 @@ void DevArena::reset() {
   inuse_ = 0;
 }
 
+PinnedHost::PinnedHost(size_t bytes) { p_ = chunk_alloc(std::max<size_t>(bytes, 256), cap_, true); }
+PinnedHost::~PinnedHost() { chunks_release({{p_, cap_}}, true); }
+
 DescStage::~DescStage() {
   std::vector<std::pair<char*, size_t>> v;
   for (auto& c : chunks_) v.push_back({c.h, c.cap});

@@ -55,7 +55,8 @@ def test_shift_for_count_matches_oracle(maker, b):
     assert eig.count(ab, mu) == n // 2
 
 
-@pytest.mark.parametrize("n,b,leaf", [(2, 1, 2), (16, 1, 4), (100, 4, 12), (257, 5, 40), (600, 1, 64)])
+@pytest.mark.parametrize("n,b,leaf", [(2, 1, 2), (16, 1, 4), (100, 4, 12), (257, 5, 40), (600, 1, 64),
+                                      (2048, 8, 64)])
 def test_structured_qr_host_vs_oracle(n, b, leaf):
     import paper_1608_01164_amd as hq
     from oracle import givens_qr as g
@@ -66,3 +67,6 @@ def test_structured_qr_host_vs_oracle(n, b, leaf):
     assert nr == len(rots) == g.rotation_count(n, b)
     assert np.abs(Q1 - Q[:n, :n]).max() < 1e-13
     assert np.abs(Q2 - Q[n:, :n]).max() < 1e-13
+    # the replays run as parallel tasks: the result must not depend on their scheduling
+    R1, R2, _ = hq.test_q_dense_host(ab, b, 0.1, 2.3, leaf)
+    assert np.array_equal(R1, Q1) and np.array_equal(R2, Q2)
