@@ -550,6 +550,7 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks, hipEvent_t core
     s.B = b.B; s.C = b.J; s.Jw = b.Jw; s.aux = b.aux; s.Wk = b.Wk; s.Jk = b.Jk; s.sig = nullptr; s.rp = T.r;
     s.kout = T.rank; s.ld = ls; s.kcap = T.kcap; s.thresh = T.thresh; s.qr_thresh = 0.1 * T.thresh;
     s.fidx = T.fidx; s.fp32_floor = fp32_floor(std::max(T.m, T.n));
+    s.rlim = std::max(T.m, T.n);  // R factors of stacks with fewer rows than columns end in zero rows
     sv.push_back(s);
     GemmTask pu{};  // Pu = Rv^T Jk
     pu.A = b.Rv; pu.opA = 1; pu.lda = rc; pu.B = b.Jk; pu.ldb = ls; pu.C = b.Pu; pu.ldc = rc;

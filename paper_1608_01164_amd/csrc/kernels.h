@@ -97,6 +97,10 @@ struct SvdTask {
   double thresh, qr_thresh;
   int fidx;          // status word of the owning matrix (rank overflow sets bit 0)
   float fp32_floor;  // FP32 variant: truncate below max(thresh, fp32_floor * sigma_1)
+  // Rows and columns of B at or beyond rlim are zero (the core of a block with fewer rows than
+  // stacked columns): the decomposition runs on the leading min(r, rlim) square, and rows from
+  // there to r of Wk and Jk come out zero.
+  int rlim = 1 << 30;
 };
 
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.

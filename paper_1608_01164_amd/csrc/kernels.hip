@@ -1642,8 +1642,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   extern __shared__ __align__(16) unsigned char svd_raw[];
   T* slds = reinterpret_cast<T*>(svd_raw);
   const SvdTask Tk = tasks[blockIdx.x];
-  int r = uniform(*Tk.rp);
-  if (r > SVD_RMAX) r = SVD_RMAX;
+  int rfull = uniform(*Tk.rp);
+  if (rfull > SVD_RMAX) rfull = SVD_RMAX;
+  const int r = rfull < Tk.rlim ? rfull : Tk.rlim;
   if (r <= 0) {
     if (threadIdx.x == 0) *Tk.kout = 0;
     return;
@@ -1673,6 +1674,15 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     svd_run<T, 16, 32>(Tk, flag, r, slds, S);  // 32-lane groups
   else
     svd_run<T, 0, 16>(Tk, flag, r, slds, S);
+  if (rfull > r) {  // rows r..rfull-1 of the singular vectors of a core with zero rows and columns there
+    __syncthreads();
+    const int kk = *Tk.kout, nr = rfull - r;
+    for (int idx = threadIdx.x; idx < nr * kk; idx += SVD_THREADS) {
+      const size_t o = (size_t)(r + idx % nr) + (size_t)(idx / nr) * Tk.ld;
+      Tk.Jk[o] = 0.0;
+      Tk.Wk[o] = 0.0;
+    }
+  }
 }
 
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s) {
