@@ -1605,6 +1605,9 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
     else if (EM > 0 && LD * t <= SVD_LDS && Tk.ld >= LD)  // C in LDS with whole-segment columns, J global
       nsweeps = svd_tail<T, EM, G, true>(Bglob, Tk.ld, slds, LD, Jg, Tk.ld, r, t, Tk, flag, S, tau, vhead, my_pairs,
                                          my_rots, c2);
+    else if (nC <= SVD_LDS)  // C (the longer columns) in LDS, J global
+      nsweeps = svd_tail<T, EM, G>(Bglob, Tk.ld, slds, rpad, Jg, Tk.ld, r, t, Tk, flag, S, tau, vhead, my_pairs,
+                                my_rots, c2);
     else if (nJ <= SVD_LDS)
       nsweeps = svd_tail<T, EM, G>(Bglob, Tk.ld, Cg, Tk.ld, slds, tpad, r, t, Tk, flag, S, tau, vhead, my_pairs,
                                 my_rots, c2);

@@ -137,7 +137,8 @@ def test_qr_r_columns_near_underflow(rows, r):
 @pytest.mark.parametrize("m,n,r,decay", [(50, 60, 10, 1.0), (300, 200, 40, 0.6), (1200, 900, 90, 0.8),
                                          (64, 64, 64, 0.5), (10, 400, 30, 0.3), (600, 700, 180, 0.85),
                                          (1500, 1200, 200, 0.88), (2000, 2000, 300, 0.92), (2000, 1800, 360, 0.9),
-                                         (600, 500, 171, 0.45), (1500, 1200, 171, 0.656)])
+                                         (600, 500, 171, 0.45), (1500, 1200, 171, 0.656),
+                                         (800, 700, 140, 0.72), (900, 800, 200, 0.6)])
 def test_recompress(m, n, r, decay):
     rng = np.random.default_rng(m + n + r)
     s = decay ** np.arange(r)
