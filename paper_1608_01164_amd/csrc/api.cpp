@@ -1154,7 +1154,6 @@ hq_status hq_test_qr_r(const double* M, int32_t rows, int32_t r, int32_t ldm, do
     while ((1 << nst) < q.ntiles) ++nst;
     for (int s = 0; s <= nst; ++s)
       hq::launch_qr_stage(dq, 1, s, (q.ntiles + (1 << s) - 1) >> s, e.d_flag, fp32 != 0, e.st);
-    hq::launch_qr_final(dq, 1, e.d_flag, fp32 != 0, e.st);
     HQ_CHECK(hipStreamSynchronize(e.st));
     return HQ_OK;
   });

@@ -487,8 +487,6 @@ void Engine::qr_r(const std::vector<QrJob>& jobs) {
     launch_qr_stage(dq, (int)qv.size(), s, (maxtiles + (1 << s) - 1) >> s, d_flag, fp32, st);
     ++launches;
   }
-  launch_qr_final(dq, (int)qv.size(), d_flag, fp32, st);
-  ++launches;
 }
 
 void Engine::recompress_group(const std::vector<RecTask>& tasks, hipEvent_t core_after) {
@@ -575,7 +573,6 @@ void Engine::recompress_group(const std::vector<RecTask>& tasks, hipEvent_t core
     launch_qr_stage(dq, (int)qv.size(), s, pairs, d_flag, fp32, st);
     ++launches;
   }
-  launch_qr_final(dq, (int)qv.size(), d_flag, fp32, st);
   if (core_after) HQ_CHECK(hipStreamWaitEvent(st, core_after, 0));
   gemm(gB, rmax, rmax);
   launch_svd(stage.upload(sv, st), nt, d_flag, fp32, st);

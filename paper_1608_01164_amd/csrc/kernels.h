@@ -126,9 +126,9 @@ struct BandDesc {
 void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s,
                  int max_splits = 1);
 void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s);
+// Stage `stage` of the TSQR of every task; a task's last stage (ceil(log2 ntiles)) also writes its R.
 void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, bool fp32,
                      hipStream_t s);
-void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s);
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s);
 void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s);

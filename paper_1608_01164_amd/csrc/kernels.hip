@@ -879,15 +879,12 @@ static __device__ __forceinline__ int slot_live_rows(int a, int s, int h0, int r
   return cov < r ? (int)cov : r;
 }
 
-// One TSQR stage.  The workspace slots hold T values (the FP64-sized buffer is reinterpreted).
+// One TSQR stage for one workgroup's tile or pair of slots; false when the workgroup has nothing to
+// do at this stage.  The workspace slots hold T values (the FP64-sized buffer is reinterpreted).
 template <typename T>
-__global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restrict__ tasks, int stage, int* flag) {
-  extern __shared__ __align__(16) unsigned char qlds_raw[];
-  T* qlds = reinterpret_cast<T*>(qlds_raw);
+static __device__ __forceinline__ bool qr_stage_body(const QrTask& Tk, const int r, int stage, int* flag,
+                                                     T* qlds) {
   constexpr int kLds = QR_LDS_BYTES / (int)sizeof(T);
-  const QrTask Tk = tasks[blockIdx.y];
-  const int r = live(Tk.rp, Tk.rcap);
-  if (r <= 0) return;
   const int tid = threadIdx.x;
   T* const work = reinterpret_cast<T*>(Tk.work);
   T* slot;
@@ -899,7 +896,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
   int rb = 0;
   if (stage == 0) {
     const int t = blockIdx.x;
-    if (t >= Tk.ntiles) return;
+    if (t >= Tk.ntiles) return false;
     const int r0 = t * Tk.h0;
     h = Tk.rows - r0;
     if (h > Tk.h0) h = Tk.h0;
@@ -910,7 +907,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
   } else {
     const int half = 1 << (stage - 1);
     const int a = blockIdx.x << stage, b = a + half;
-    if (b >= Tk.ntiles) return;
+    if (b >= Tk.ntiles) return false;
     ra = slot_live_rows(a, stage - 1, Tk.h0, Tk.rows, r);
     rb = slot_live_rows(b, stage - 1, Tk.h0, Tk.rows, r);
     slot = work + (size_t)a * Tk.hs * Tk.rcap;
@@ -932,16 +929,16 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
       slot[i + (size_t)c * Tk.hs] = (T)v;
     }
     if (bad) atomicOr(flag + Tk.fidx, 16);
-    return;
+    return true;
   }
   // small row tiles: the whole tile in registers
   if (stage == 0 && h <= 128 && r <= 256) {
     householder_regs<T, 8, 4>(srcM, ld0, slot, Tk.hs, h, r, flag, Tk.fidx, qlds);
-    return;
+    return true;
   }
   if (stage == 0 && h <= 256 && r <= 128) {
     householder_regs<T, 16, 2>(srcM, ld0, slot, Tk.hs, h, r, flag, Tk.fidx, qlds);
-    return;
+    return true;
   }
   const bool inl = h * r <= kLds;
   T* X = inl ? qlds : slot;
@@ -984,24 +981,42 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restric
       slot[i + (size_t)c * Tk.hs] = X[i + (size_t)c * ldx];
     }
   }
+  return true;
 }
 
+// The triangle of slot 0 (the whole tile when a single FP64 tile has no more rows than columns:
+// the stack is its own factor) as the r x r factor R, zero below and beyond; non-finite entries
+// are reported (value 32).
 template <typename T>
-__global__ __launch_bounds__(256) void k_qr_final(const QrTask* __restrict__ tasks, int* flag) {
-  const QrTask Tk = tasks[blockIdx.x];
-  const int r = live(Tk.rp, Tk.rcap);
+static __device__ __forceinline__ void qr_write_r(const QrTask& Tk, const int r, int* flag, int nthreads) {
   const int rr = Tk.rows < r ? Tk.rows : r;
   const T* work = reinterpret_cast<const T*>(Tk.work);
   bool bad = false;
-  // FP64 single tile with no more rows than columns: the stack itself
   const bool full = std::is_same<T, double>::value && Tk.ntiles == 1 && Tk.rows <= r;
-  for (int idx = threadIdx.x; idx < r * r; idx += 256) {
+  for (int idx = threadIdx.x; idx < r * r; idx += nthreads) {
     const int i = idx % r, c = idx / r;
     const double v = (i < rr && (full || i <= c)) ? (double)work[i + (size_t)c * Tk.hs] : 0.0;
     bad |= !(fabs(v) <= DBL_MAX);
     Tk.R[i + (size_t)c * Tk.ldr] = v;
   }
   if (bad) atomicOr(flag + Tk.fidx, 32);  // the triangular factor came out non-finite
+}
+
+// One TSQR stage; the workgroup that completes a task's last stage also writes its R.
+template <typename T>
+__global__ __launch_bounds__(QR_THREADS) void k_qr_stage(const QrTask* __restrict__ tasks, int stage, int* flag) {
+  extern __shared__ __align__(16) unsigned char qlds_raw[];
+  T* qlds = reinterpret_cast<T*>(qlds_raw);
+  const QrTask Tk = tasks[blockIdx.y];
+  const int r = live(Tk.rp, Tk.rcap);
+  if (r <= 0) return;
+  if (!qr_stage_body<T>(Tk, r, stage, flag, qlds)) return;
+  int last = 0;  // a task of ntiles tiles ends at stage ceil(log2 ntiles), in the pair of slot 0
+  while ((1 << last) < Tk.ntiles) ++last;
+  if (stage == last && blockIdx.x == 0) {
+    __syncthreads();
+    qr_write_r<T>(Tk, r, flag, QR_THREADS);
+  }
 }
 
 void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, bool fp32,
@@ -1021,13 +1036,6 @@ void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs
       HQ_TIMED(K_QR, s, hipLaunchKernelGGL(k_qr_stage<double>, dim3(max_pairs, nt), dim3(QR_THREADS), QR_LDS_BYTES, s,
                                            d_tasks + t0, stage, flag));
   }
-}
-void launch_qr_final(const QrTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s) {
-  if (ntasks <= 0) return;
-  if (fp32)
-    HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final<float>, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
-  else
-    HQ_TIMED(K_OTHER, s, hipLaunchKernelGGL(k_qr_final<double>, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
 }
 
 // ----------------------------------------------------------------------------------------------
