@@ -1166,6 +1166,14 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         keep_scratch = true;
         try {
           recompress_group(rec, ev_rv);
+          // rank of L^{-1}'s block (p, lower) = rank of L's, set here so the join carries it
+          std::vector<IntCopy> rk;
+          for (const Item& it : inner) {
+            const CholTask& T = batch[it.m];
+            rk.push_back(IntCopy{T.Linv->rk(it.c, 1), T.Lf->rk(it.c, 1)});
+          }
+          launch_copy_ints(stage.upload(rk, st), (int)rk.size(), st);
+          ++launches;
         } catch (...) {
           st = main_st;
           keep_scratch = false;
@@ -1222,18 +1230,14 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     // inverse blocks
     const DevArena::Mark mk2 = scratch.mark();
     std::vector<ThinTask> th;
-    std::vector<IntCopy> rk;
     for (const Item& it : inner) {
       const CholTask& T = batch[it.m];
       const int p = it.c, a = 2 * p + 1, b = 2 * p + 2, l = Tree::level(p);
       const int ldc = (int)T.Z->t->ldf[l];
       th.push_back(ThinTask{view(*T.Linv), b, T.Lf->U(p, 1), ldc, T.Linv->U(p, 1), ldc, T.Lf->rk(p, 1), T.Lf->cap[l], -1.0, 0.0});
       th.push_back(ThinTask{view(*T.Linv, true), a, T.Lf->V(p, 1), ldc, T.Linv->V(p, 1), ldc, T.Lf->rk(p, 1), T.Lf->cap[l], 1.0, 0.0});
-      rk.push_back(IntCopy{T.Linv->rk(p, 1), T.Lf->rk(p, 1)});
     }
     mm_thin(th);
-    launch_copy_ints(stage.upload(rk, st), (int)rk.size(), st);
-    ++launches;
     scratch.rewind(mk2);
     scratch.rewind(mk);
   };
