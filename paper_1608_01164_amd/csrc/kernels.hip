@@ -1048,7 +1048,9 @@ void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs
 constexpr int SVD_THREADS = 1024;
 constexpr int SVD_WAVES = SVD_THREADS / 64;
 constexpr int SVD_RMAX = 1024;         // largest core handled
-constexpr int SVD_LDS_BYTES = 131072;  // dynamic LDS (128 KiB) for B, C and J when they fit
+// dynamic LDS: B, C and J when they fit, then the per-core index and norm arrays sized for the
+// variant's largest core (160 KiB minus the few static reduction slots)
+constexpr int SVD_DYN_BYTES = 163328;
 
 template <typename T>
 struct ArgMax { T v; int i; };
@@ -1542,14 +1544,24 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
 // truncation uses max(thresh, fp32_floor sigma_1) (singular values below that are FP32 noise); the
 // outputs stay FP64.  Workspace buffers (C, Jw, aux) are reinterpreted as T.
 template <typename T, int EM, int G>
-static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, const int r, T* slds,
-                                               const SvdShared<T>& S) {
+static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, const int r, unsigned char* raw,
+                                               const SvdShared<T>& S0) {
   constexpr bool dbl = std::is_same<T, double>::value;
-  constexpr int SVD_LDS = SVD_LDS_BYTES / (int)sizeof(T);
+  // largest core of the variant; its arrays (norms, reflector factors or the current reflector,
+  // pivot order, singular value order) sit after the data region
+  constexpr int RM = EM > 0 ? EM * G : SVD_RMAX;
+  constexpr int ARR = RM * (int)sizeof(T) * (EM > 0 ? 3 : 2) + 2 * RM * (int)sizeof(int);
+  constexpr int SVD_LDS = ((SVD_DYN_BYTES - ARR) / (int)sizeof(T)) & ~1;
+  static_assert(SVD_LDS >= 16384, "data region below 16384 entries");
+  T* const slds = reinterpret_cast<T*>(raw);
+  T* const cn = slds + SVD_LDS;
+  T* const vl = cn + RM;
+  int* const perm = reinterpret_cast<int*>(vl + (EM > 0 ? 2 * RM : RM));
+  const SvdShared<T> S{cn, vl, perm, perm + RM, S0.redv, S0.reda, S0.rotated, S0.pairs, S0.rots};
   const int tid = threadIdx.x;
-  // reflector factors: in LDS on the register path (t <= r <= 512: tau in [0, 512), heads in [512, 1024)), else in the aux workspace
+  // reflector factors: in LDS on the register path (t <= r <= RM: tau in [0, RM), heads in [RM, 2 RM)), else in the aux workspace
   T* tau = EM > 0 ? S.vl : reinterpret_cast<T*>(Tk.aux);
-  T* vhead = EM > 0 ? S.vl + 512 : reinterpret_cast<T*>(Tk.aux) + r;
+  T* vhead = EM > 0 ? S.vl + RM : reinterpret_cast<T*>(Tk.aux) + r;
   // global copy of B in T: the input buffer itself (FP64), or the upper half of the C workspace
   T* const Bglob = dbl ? reinterpret_cast<T*>(Tk.B) : reinterpret_cast<T*>(Tk.C) + (size_t)Tk.ld * Tk.ld;
   const unsigned long long c0 = wall_clock64();
@@ -1651,7 +1663,6 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
 template <typename T>
 __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__ tasks, int* flag) {
   extern __shared__ __align__(16) unsigned char svd_raw[];
-  T* slds = reinterpret_cast<T*>(svd_raw);
   const SvdTask Tk = tasks[blockIdx.x];
   int rfull = uniform(*Tk.rp);
   if (rfull > SVD_RMAX) rfull = SVD_RMAX;
@@ -1667,24 +1678,20 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     }
     return;
   }
-  __shared__ T cn[SVD_RMAX];
-  __shared__ T vl[SVD_RMAX];
-  __shared__ int perm[SVD_RMAX];
-  __shared__ int ordr[SVD_RMAX];
   __shared__ T redv[SVD_WAVES];
   __shared__ ArgMax<T> reda[SVD_WAVES];
   __shared__ int rotated;
   __shared__ unsigned long long sh_pairs, sh_rots;
   if (threadIdx.x == 0) { sh_pairs = 0; sh_rots = 0; }
-  const SvdShared<T> S{cn, vl, perm, ordr, redv, reda, &rotated, &sh_pairs, &sh_rots};
+  const SvdShared<T> S{nullptr, nullptr, nullptr, nullptr, redv, reda, &rotated, &sh_pairs, &sh_rots};
   if (r <= 128)
-    svd_run<T, 8, 16>(Tk, flag, r, slds, S);
+    svd_run<T, 8, 16>(Tk, flag, r, svd_raw, S);
   else if (r <= 256)
-    svd_run<T, 16, 16>(Tk, flag, r, slds, S);
+    svd_run<T, 16, 16>(Tk, flag, r, svd_raw, S);
   else if (r <= 512 && Tk.ld >= ((r + 31) & ~31))
-    svd_run<T, 16, 32>(Tk, flag, r, slds, S);  // 32-lane groups
+    svd_run<T, 16, 32>(Tk, flag, r, svd_raw, S);  // 32-lane groups
   else
-    svd_run<T, 0, 16>(Tk, flag, r, slds, S);
+    svd_run<T, 0, 16>(Tk, flag, r, svd_raw, S);
   if (rfull > r) {  // rows r..rfull-1 of the singular vectors of a core with zero rows and columns there
     __syncthreads();
     const int kk = *Tk.kout, nr = rfull - r;
@@ -1700,14 +1707,14 @@ void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStr
   if (ntasks <= 0) return;
   static std::once_flag lds_ok;
   std::call_once(lds_ok, [] {
-    check_lds((const void*)k_svd<double>, SVD_LDS_BYTES, "k_svd<double>");
-    check_lds((const void*)k_svd<float>, SVD_LDS_BYTES, "k_svd<float>");
+    check_lds((const void*)k_svd<double>, SVD_DYN_BYTES, "k_svd<double>");
+    check_lds((const void*)k_svd<float>, SVD_DYN_BYTES, "k_svd<float>");
   });
   if (fp32)
-    HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<float>, dim3(ntasks), dim3(SVD_THREADS), SVD_LDS_BYTES, s, d_tasks,
+    HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<float>, dim3(ntasks), dim3(SVD_THREADS), SVD_DYN_BYTES, s, d_tasks,
                                           flag));
   else
-    HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<double>, dim3(ntasks), dim3(SVD_THREADS), SVD_LDS_BYTES, s, d_tasks,
+    HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<double>, dim3(ntasks), dim3(SVD_THREADS), SVD_DYN_BYTES, s, d_tasks,
                                           flag));
 }
 
