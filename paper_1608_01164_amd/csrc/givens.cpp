@@ -19,7 +19,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 
 #include "engine.h"
@@ -329,13 +331,23 @@ void q_factors_hodlr(const GivensSweep& g, const Tree& t, int b, const std::vect
     }
   };
 
+  // a failed window check (an exception) must not leave the parallel region: the first is kept and
+  // rethrown after it
+  std::exception_ptr err;
+  std::mutex err_mu;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int p = 0; p < ntask; ++p) {
-    if (t.is_leaf(p))
-      leaf_task(p);
-    else
-      node_task(p);
+    try {
+      if (t.is_leaf(p))
+        leaf_task(p);
+      else
+        node_task(p);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(err_mu);
+      if (!err) err = std::current_exception();
+    }
   }
+  if (err) std::rethrow_exception(err);
 
   // U factors and the bases of internal nodes, bottom-up: per level, one task per (node, column of
   // the 2b-wide basis), copies and 2b-term combinations only
