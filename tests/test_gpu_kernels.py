@@ -138,7 +138,9 @@ def test_qr_r_columns_near_underflow(rows, r):
                                          (64, 64, 64, 0.5), (10, 400, 30, 0.3), (600, 700, 180, 0.85),
                                          (1500, 1200, 200, 0.88), (2000, 2000, 300, 0.92), (2000, 1800, 360, 0.9),
                                          (600, 500, 171, 0.45), (1500, 1200, 171, 0.656),
-                                         (800, 700, 140, 0.72), (900, 800, 200, 0.6)])
+                                         (800, 700, 140, 0.72), (900, 800, 200, 0.6),
+                                         # stacks wider than the block: the core runs on its leading square
+                                         (120, 110, 200, 0.8), (200, 150, 300, 0.7)])
 def test_recompress(m, n, r, decay):
     rng = np.random.default_rng(m + n + r)
     s = decay ** np.arange(r)
