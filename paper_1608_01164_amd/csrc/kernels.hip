@@ -783,13 +783,15 @@ static __device__ void householder_rows_blocked(T* X, int ld, int h, int r, T* V
         for (int i = jj + 1 + lane; i < hp; i += 64) col[i * NB] -= w * vj[i * NB];
       }
       __syncthreads();
+      // No barrier after these stores: the next column's steps touch other entries until their
+      // first reduction's barrier, and sh_* are rewritten only after that.
       if (tid == 0) {
         v0s[jj] = sh_v0;
         taus[jj] = sh_tau;
         vj[jj * NB] = sh_beta;  // R's diagonal; the reflector head lives in v0s
       }
-      __syncthreads();
     }
+    __syncthreads();
     // (c) Gram of the reflectors (unit structure: v_q = [0..0, v0s[q], V(q+1.., q)])
     for (int pq = wave; pq < nb * nb; pq += QR_WAVES) {
       const int a = pq / nb, q = pq - a * nb;
