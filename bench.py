@@ -162,8 +162,8 @@ def main():
                     help="capacities from the previous iterate's ranks instead of the trained rank predictor")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is described in DESIGN.md and not implemented", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); sharding "
+              "matrices or subtrees across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1608_01164_amd as hq

@@ -11,7 +11,7 @@ j+i < n (entries past the end of the matrix are zero).  Viewed as a flat buffer
 this is column-major ``ab[i + j*ld]``, i.e. exactly LAPACK's ``dsbev`` lower
 layout, so it crosses the C ABI without copies.
 
-Workload families (recipes restated in DESIGN.md, "Inputs"):
+Workload families (seeded; shapes and value distributions of the paper's test problems):
 
 * ``tridiag_uniform``   : diag ~ U(-2,2), off-diag ~ U(0.5,1)   (n=1024 and n=100000 runs)
 * ``banded_normal``     : band entries N(0,1) mirrored, + 4*i/n on the diagonal
