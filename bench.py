@@ -4,6 +4,13 @@ One step = one call of spectral_projector (Algorithm hQDWH: scalar setup, struct
 iteration, Cholesky iterations, symmetrisation) on a band already resident in HBM.  Prints one JSON
 line.  Default workload: symmetric banded n = 16384, b = 8, N(0,1) band entries mirrored plus
 4i/n on the diagonal, mu between lambda_{n/2} and lambda_{n/2+1}, leaf 128, tol 1e-10, FP64.
+
+`value` is the FP64 projectors per second of that workload.  The line also carries the legs of the
+comparison the metric asks for, measured in the same run: the same matrix in mixed precision (FP32
+middle iterations) with its error against the FP64 projector, the FP64 solve without the rank
+predictor, and a batch of independent matrices of the batched workload's generator (n_i ~
+U{2048..16384}, b_i ~ U{1..16}) in FP64 and in mixed precision; plus the matrix-core utilisation
+(flops issued as MFMA instructions / time / peak of their precision) of the timed steps.
 """
 from __future__ import annotations
 
@@ -29,7 +36,16 @@ WORKLOADS = {
 # batched: count independent banded matrices, n_i ~ U{2048..16384}, b_i ~ U{1..16}, leaf 128, tol 1e-10
 BATCHED = {"batched-256": 256, "batched-64": 64, "batched-16": 16}
 DEFAULT = "banded-n16384-b8"
+LEG_BATCH = 16  # members of the batched legs of the default line
 METRIC = "HODLR-QDWH Π/s at ‖Π−Π_oracle‖₂≤1e-8: mixed+batched vs FP64; MFMA util %"
+
+# MI355X peaks: FP64 MFMA 78.6 TFLOP/s, FP32 MFMA 157.3 TFLOP/s (dense); FP64 vector ALU
+# 256 CUs x 2.4 GHz x 128 flop/clk = 78.6 TFLOP/s
+PEAK_FP64_MFMA = 78.6
+PEAK_FP32_MFMA = 157.3
+PEAK_FP64_ALU = 78.6
+KERNEL_NAMES = {"gemm": "k_gemm", "tsqr": "k_qr_stage", "core_svd": "k_svd", "leaf_cholesky": "k_chol_inv",
+                "leaf_inverse": "k_trtri", "stack": "k_stack", "leaf_elementwise": "k_leaf_axpy", "other": "misc"}
 
 
 def band_matvec_torch(band, X):
@@ -43,8 +59,8 @@ def band_matvec_torch(band, X):
     return Y
 
 
-def properties(P, band, mu, nu, seed=0):
-    """At-any-size checks of a projector: trace, idempotency, commutation with A, sign of the spectrum."""
+def properties(P, band, mu, seed=0):
+    """At-any-size checks of a projector: idempotency, commutation with A, sign of the spectrum."""
     import torch
     n = band.shape[0]
     g = torch.Generator(device="cuda").manual_seed(seed)
@@ -61,16 +77,36 @@ def properties(P, band, mu, nu, seed=0):
     QX = X - PX
     AQX = AX - APX
     pos = float(((QX * (AQX - mu * QX)).sum(0) / (QX * QX).sum(0)).min())
-    H = P.export_trace() if hasattr(P, "export_trace") else None
-    return {"idempotency": idem, "commutation": comm, "rayleigh_below_mu": neg, "rayleigh_above_mu": pos,
-            "trace": H}
+    return {"idempotency": idem, "commutation": comm, "rayleigh_below_mu": neg, "rayleigh_above_mu": pos}
 
 
-# MI355X peaks (FP64): MFMA 78.6 TFLOP/s; vector ALU 256 CUs x 2.4 GHz x 128 flop/clk = 78.6 TFLOP/s
-PEAK_FP64_MFMA = 78.6
-PEAK_FP64_ALU = 78.6
-KERNEL_NAMES = {"gemm": "k_gemm", "tsqr": "k_qr_stage", "core_svd": "k_svd", "leaf_cholesky": "k_potrf",
-                "leaf_inverse": "k_trtri", "stack": "k_stack", "leaf_elementwise": "k_leaf_axpy", "other": "misc"}
+def difference_norm(P1, P2, n, steps=40, seed=1):
+    """||P1 - P2||_2 by symmetric Lanczos with full reorthogonalisation on the device (both applied
+    through the library)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    q = torch.randn((n, 1), generator=g, dtype=torch.float64, device="cuda")
+    q /= q.norm()
+    Q = [q]
+    al, be = [], []
+    beta, qp = 0.0, torch.zeros_like(q)
+    for _ in range(steps):
+        wv = P1.apply(q) - P2.apply(q)
+        a = float((q * wv).sum())
+        wv = wv - a * q - beta * qp
+        Qm = torch.cat(Q, 1)
+        wv -= Qm @ (Qm.T @ wv)
+        wv -= Qm @ (Qm.T @ wv)
+        al.append(a)
+        beta = float(wv.norm())
+        if beta < 1e-300:
+            break
+        be.append(beta)
+        qp, q = q, wv / beta
+        Q.append(q)
+    k = len(al)
+    T = np.diag(al) + np.diag(be[: k - 1], 1) + np.diag(be[: k - 1], -1)
+    return float(np.max(np.abs(np.linalg.eigvalsh(T))))
 
 
 def measured_traffic(workload, kernel):
@@ -94,23 +130,38 @@ def measured_traffic(workload, kernel):
     return kib * 1024.0
 
 
-def roofline(prof, workload=None):
-    """Roofline entry of the kernel class with the largest measured time (HIP events on the library's stream)."""
+def kernel_table(prof):
     kern = {}
     for k, v in prof.items():
         if v["launches"]:
             kern[k] = {"kernel": KERNEL_NAMES[k], "launches": v["launches"], "ms_total": v["ms"],
                        "ms_avg": v["ms"] / v["launches"], "gflop_per_launch": v["flops"] / v["launches"] / 1e9,
                        "tflops": v["flops"] / max(v["ms"], 1e-9) / 1e9}
+    return kern
+
+
+def roofline(prof, workload=None):
+    """Roofline entry of the kernel class with the largest measured time (HIP events on the streams the
+    library launches it on, over the timed steps)."""
+    kern = kernel_table(prof)
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
     d = kern[dom]
     bound = "mfma" if dom == "gemm" else "alu"
     peak = PEAK_FP64_MFMA if bound == "mfma" else PEAK_FP64_ALU
     achieved = d["tflops"]
-    return ({"kernel": d["kernel"], "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-             "frac": achieved / peak, "traffic": measured_traffic(workload, d["kernel"]) if workload else None,
-             "traffic_unit": "bytes per launch", "avg_launch_ms": d["ms_avg"],
-             "flops_per_launch": d["gflop_per_launch"] * 1e9}, kern)
+    return {"kernel": d["kernel"], "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": measured_traffic(workload, d["kernel"]) if workload else None,
+            "traffic_unit": "bytes per launch", "avg_launch_ms": d["ms_avg"],
+            "flops_per_launch": d["gflop_per_launch"] * 1e9}
+
+
+def mfma_util(mf, seconds):
+    """Matrix-core utilisation: flops issued as MFMA instructions over the elapsed time, against the
+    dense peak of their precision."""
+    t64 = mf["fp64"] / seconds / 1e12
+    t32 = mf["fp32"] / seconds / 1e12
+    return {"fp64_tflops": t64, "fp64_util_pct": 100.0 * t64 / PEAK_FP64_MFMA,
+            "fp32_tflops": t32, "fp32_util_pct": 100.0 * t32 / PEAK_FP32_MFMA}
 
 
 def timed_classes(prof_w):
@@ -121,6 +172,16 @@ def timed_classes(prof_w):
         return None
     busy = {k: v["ms"] for k, v in prof_w.items() if v["launches"]}
     return [max(busy, key=busy.get)] if busy else None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(ab, b, nu, budget_s=20.0):
@@ -135,17 +196,44 @@ def cpu_baseline(ab, b, nu, budget_s=20.0):
         t = time.perf_counter()
         lam = eig.eigenvalues(ab, 1, m)
         V = eig.eigenvectors(ab, lam)
-        Pi_part = V @ V.T
+        V @ V.T
         spent = time.perf_counter() - t
         if spent > budget_s / 4 or m >= nu:
             break
         m *= 2
     per_pair = spent / m
     total = per_pair * nu
-    return {"value": 1.0 / total, "unit": "Π/s", "cores": eig.num_threads(), "kind": "oracle",
+    return {"value": 1.0 / total, "unit": "Π/s", "cores": eig.num_threads(), "cpu": cpu_model(), "kind": "oracle",
             "sample": f"{m} of {nu} eigenpairs (inertia bisection + inverse iteration + V V^T share) in "
                       f"{spent:.2f} s, extrapolated linearly to nu={nu}; n={n}, b={b}",
             "sample_seconds": spent, "extrapolated_seconds": total, "wall_s": time.perf_counter() - t0}
+
+
+def _predictor(no_predictor):
+    if no_predictor:
+        return None
+    from paper_1608_01164_amd import predictor as hp
+    return hp.load() if os.path.exists(hp.DEFAULT_PATH) else None
+
+
+def timed_single(hq, band, b, mu, leaf, tol, pred, precision, steps, warmup, tag):
+    """Warmup then `steps` timed calls (no timers); returns (Π/s, last projector, last info)."""
+    import torch
+    for i in range(warmup):
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=precision)
+        P.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = None
+    for i in range(steps):
+        if P is not None:
+            P.close()
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=precision)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"# leg {tag}: {steps} steps, {dt / steps:.3f} s per projector, K={info['iters']}, "
+          f"fp32 iterations {info['fp32_iter']}, redo {info['redo_count']}", file=sys.stderr, flush=True)
+    return steps / dt, P, info
 
 
 def main():
@@ -155,6 +243,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="only the main workload (no mixed / batched legs)")
     ap.add_argument("--no-profile", action="store_true", help="disable the library's per-launch kernel timers")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: middle QDWH iterations in FP32 (GEMM on FP32 MFMA, FP32 TSQR and core SVD)")
@@ -171,7 +260,7 @@ def main():
     if args.workload in BATCHED:
         return main_batched(args, BATCHED[args.workload])
     maker, b, leaf, tol = WORKLOADS[args.workload]
-    pred = _predictor(args)
+    pred = _predictor(args.no_predictor)
     ab = maker()
     n = ab.shape[0]
     nu = n // 2
@@ -209,11 +298,12 @@ def main():
     t1 = time.perf_counter()
     svd_stats = hq.binding.profile_svd() if not args.no_profile else None
     prof = hq.profile_read() if not args.no_profile else None
+    mf = hq.binding.profile_mfma() if not args.no_profile else None
     if not args.no_profile:
         hq.profile(False)
     ms = 1e3 * (t1 - t0) / args.steps
     value = args.steps / (t1 - t0)
-    props = properties(P, band, mu, nu)
+    props = properties(P, band, mu)
     out = {
         "metric": METRIC, "value": value, "unit": "Π/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -227,21 +317,74 @@ def main():
         "checks": props,
     }
     if prof is not None:
-        out["roofline"], out["kernels"] = roofline(prof, args.workload)
-        if prof_w is not None:
-            out["kernels"] = roofline(prof_w)[1]
-            out["kernels_source"] = "last warmup step, every kernel class timed"
+        out["roofline"] = roofline(prof, args.workload)
+        out["roofline"]["measured_over"] = "timed steps (HIP events on the dominant class's launches only)"
+        out["mfma"] = mfma_util(mf, t1 - t0)
+        out["kernels"] = kernel_table(prof_w if prof_w is not None else prof)
+        out["kernels_source"] = "last warmup step, every kernel class timed" if prof_w is not None else "timed steps"
         out["core_svd_phases"] = svd_stats
+    if not args.no_legs and args.workload == DEFAULT and args.precision == "fp64":
+        out["legs"] = legs(hq, band, b, mu, leaf, tol, pred, P, value, n)
+    P.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ab, b, nu)
     print(json.dumps(out), flush=True)
 
 
-def _predictor(args):
-    if args.no_predictor:
-        return None
-    from paper_1608_01164_amd import predictor as hp
-    return hp.load() if os.path.exists(hp.DEFAULT_PATH) else None
+def legs(hq, band, b, mu, leaf, tol, pred, P64, value64, n):
+    """The comparison legs of the metric on the same GPU (short runs, no timers)."""
+    out = {}
+    # the same matrix with FP32 middle iterations; its error against the FP64 projector (which the
+    # parity tests hold to 1e-8 against the oracle)
+    v, Pm, im = timed_single(hq, band, b, mu, leaf, tol, pred, "mixed", 3, 1, "mixed")
+    out["mixed"] = {"value": v, "unit": "Π/s", "vs_fp64": v / value64, "iters": im["iters"],
+                    "fp32_iterations": im["fp32_iter"], "redo_count": im["redo_count"],
+                    "err_vs_fp64_2norm": difference_norm(Pm, P64, n)}
+    Pm.close()
+    v, Pn, inn = timed_single(hq, band, b, mu, leaf, tol, None, "fp64", 3, 1, "fp64-no-predictor")
+    out["fp64_no_predictor"] = {"value": v, "unit": "Π/s", "predictor_speedup": value64 / v,
+                                "redo_count": inn["redo_count"], "capacity_columns": inn["capacity_columns"]}
+    Pn.close()
+    out["batched"] = batched_legs(hq, LEG_BATCH, pred)
+    return out
+
+
+def batched_legs(hq, count, pred, leaf=128, tol=1e-10):
+    """count matrices of the batched generator in one spectral_projector_batched call, FP64 and mixed
+    (one warmup and one timed call each); the mixed members' errors against the FP64 ones."""
+    import torch
+    import workloads as wl
+    mats = wl.batched_banded(count, seed=0)
+    bs = [m.shape[1] - 1 for m in mats]
+    mus = [hq.shift_for_count(m, bs[i], m.shape[0] // 2)[0] for i, m in enumerate(mats)]
+    bands = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats]
+    res = {"count": count, "sum_n": int(sum(m.shape[0] for m in mats))}
+    keep = {}
+    for prec in ("fp64", "mixed"):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol, predictor=pred,
+                                                          precision=prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if st != 0:
+                raise RuntimeError(f"batched {prec}: status {st}")
+            if rep == 0:
+                for P in Ps:
+                    P.close()
+        print(f"# leg batched-{count} {prec}: {dt:.3f} s per batch", file=sys.stderr, flush=True)
+        res[prec] = {"value": count / dt, "unit": "Π/s", "seconds": dt, "peak_bytes": infos[0]["peak_bytes"],
+                     "redo_count": sum(i["redo_count"] for i in infos)}
+        keep[prec] = Ps
+    j = int(np.argmax([m.shape[0] for m in mats]))
+    res["mixed"]["err_vs_fp64_2norm_largest_member"] = difference_norm(keep["mixed"][j], keep["fp64"][j],
+                                                                       mats[j].shape[0])
+    res["mixed"]["vs_fp64_batched"] = res["mixed"]["value"] / res["fp64"]["value"]
+    for Ps in keep.values():
+        for P in Ps:
+            P.close()
+    return res
 
 
 def main_batched(args, count, leaf=128, tol=1e-10):
@@ -251,7 +394,7 @@ def main_batched(args, count, leaf=128, tol=1e-10):
     import paper_1608_01164_amd as hq
     import workloads as wl
 
-    pred = _predictor(args)
+    pred = _predictor(args.no_predictor)
     mats = wl.batched_banded(count, seed=0)
     bs = [m.shape[1] - 1 for m in mats]
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
@@ -303,14 +446,14 @@ def main_batched(args, count, leaf=128, tol=1e-10):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = hq.profile_read() if not args.no_profile else None
+    mf = hq.binding.profile_mfma() if not args.no_profile else None
     if not args.no_profile:
         hq.profile(False)
     ms = 1e3 * (t1 - t0) / args.steps
     # at-any-size checks on the largest and the widest-band member
     chk = {}
     for j in sorted({int(np.argmax([m.shape[0] for m in mats])), int(np.argmax(bs))}):
-        pr = properties(Ps[j], bands[j], mus[j], mats[j].shape[0] // 2)
-        chk[f"member{j}_n{mats[j].shape[0]}_b{bs[j]}"] = {k: v for k, v in pr.items() if v is not None}
+        chk[f"member{j}_n{mats[j].shape[0]}_b{bs[j]}"] = properties(Ps[j], bands[j], mus[j])
     out = {
         "metric": METRIC, "value": count * args.steps / (t1 - t0), "unit": "Π/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -323,10 +466,10 @@ def main_batched(args, count, leaf=128, tol=1e-10):
         "peak_bytes": infos[0]["peak_bytes"], "checks": chk,
     }
     if prof is not None:
-        out["roofline"], out["kernels"] = roofline(prof, args.workload)
-        if prof_w is not None:
-            out["kernels"] = roofline(prof_w)[1]
-            out["kernels_source"] = "last warmup step, every kernel class timed"
+        out["roofline"] = roofline(prof, args.workload)
+        out["mfma"] = mfma_util(mf, t1 - t0)
+        out["kernels"] = kernel_table(prof_w if prof_w is not None else prof)
+        out["kernels_source"] = "last warmup step, every kernel class timed" if prof_w is not None else "timed steps"
     print(json.dumps(out), flush=True)
 
 

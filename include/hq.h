@@ -234,9 +234,20 @@ hq_status hq_profile_enable(int32_t on);
  * others.  The kernels' work counters run for every class while profiling is on. */
 hq_status hq_profile_select(int32_t mask);
 hq_status hq_profile_read(hq_kstat* out /* [8] */, int32_t reset);
+/* Flops the kernels issued as MFMA instructions since the last reset (counted while profiling is on):
+ * out[0] FP64, out[1] FP32 (host); reset != 0 clears them.  Synchronises the device. */
+hq_status hq_profile_mfma(double* out /* [2] */, int32_t reset);
 /* Core-SVD internals since the last reset: [0..2] cycles of the pivoted-QR, Jacobi and output phases
  * (wall clock at 100 MHz), [3] sum of r, [4] sum of t, [5] sum of sweeps, [6] cores. */
 hq_status hq_profile_svd(int64_t* out /* [8] */);
+
+/* Host-only: the library's QDWH weight schedule (eq. qdwh_parameters_abc and the l_k recurrence of
+ * Sec. 2.1) from a lower bound l0 in (0, 1]: a_k = h(l_k), b_k = (a_k - 1)^2 / 4, c_k = a_k + b_k - 1,
+ * l_{k+1} = l_k (a_k + b_k l_k^2) / (1 + c_k l_k^2), until |1 - l_k| <= delta or max_iter (<= 16)
+ * steps.  a, b, c: host, >= max_iter entries; l: host, >= max_iter + 1 entries (l_0 .. l_K); *K: host.
+ * The same routine sets the schedule of every solve; no device use. */
+hq_status hq_test_schedule(double l0, double delta, int32_t max_iter, double* a, double* b, double* c, double* l,
+                           int32_t* K);
 
 /* Host-only: the same Q1, Q2 assembled densely (Q1, Q2: host, n x n, ld n).  No device use. */
 hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,

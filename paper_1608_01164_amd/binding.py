@@ -80,10 +80,12 @@ _SIGS = {
     "hq_test_cholesky_inverse": (c_i32, [c_vp, c_i32, c_d, c_vp, P(c_vp)]),
     "hq_test_q_factors": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, P(c_vp), P(c_vp), P(c_i64)]),
     "hq_test_q_dense_host": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, c_vp, P(c_i64)]),
+    "hq_test_schedule": (c_i32, [c_d, c_d, c_i32, c_vp, c_vp, c_vp, c_vp, P(c_i32)]),
     "hq_profile_enable": (c_i32, [c_i32]),
     "hq_profile_select": (c_i32, [c_i32]),
     "hq_profile_read": (c_i32, [c_vp, c_i32]),
     "hq_profile_svd": (c_i32, [c_vp]),
+    "hq_profile_mfma": (c_i32, [c_vp, c_i32]),
     "hq_predictor_create": (c_i32, [ctypes.c_uint64, P(c_vp)]),
     "hq_predictor_nparams": (c_i64, []),
     "hq_predictor_get_params": (c_i32, [c_vp, c_vp]),
@@ -110,6 +112,7 @@ def profile(on: bool, classes=None):
     from KCLASSES) restricts the timers to those kernel classes, None times all of them."""
     if on:
         profile_read(reset=True)
+        profile_mfma(reset=True)
         mask = -1 if classes is None else sum(1 << KCLASSES.index(c) for c in classes)
         _check(lib().hq_profile_select(mask))
     _check(lib().hq_profile_enable(1 if on else 0))
@@ -121,6 +124,13 @@ def profile_svd() -> dict:
     n = max(a[6], 1)
     return {"cores": a[6], "qr_us": a[0] / 100.0, "jacobi_us": a[1] / 100.0, "out_us": a[2] / 100.0,
             "mean_r": a[3] / n, "mean_t": a[4] / n, "mean_sweeps": a[5] / n}
+
+
+def profile_mfma(reset: bool = True) -> dict:
+    """Flops issued to the matrix cores since the last reset (FP64, FP32)."""
+    a = (c_d * 2)()
+    _check(lib().hq_profile_mfma(ctypes.cast(a, c_vp), 1 if reset else 0))
+    return {"fp64": a[0], "fp32": a[1]}
 
 
 def profile_read(reset: bool = True) -> dict:
@@ -398,6 +408,16 @@ def test_q_dense_host(band_host: np.ndarray, b, shift, scale, leaf):
     _check(lib().hq_test_q_dense_host(ab.ctypes.data_as(c_vp), n, b, ld, shift, scale, leaf,
                                       Q1.ctypes.data_as(c_vp), Q2.ctypes.data_as(c_vp), ctypes.byref(nr)))
     return Q1, Q2, nr.value
+
+
+def test_schedule(l0: float, delta: float = 1e-15, max_iter: int = 16):
+    """The library's weight schedule (host only): arrays a, b, c (K entries) and l (K + 1 entries)."""
+    a, b, c, l = (np.zeros(17) for _ in range(4))
+    K = c_i32()
+    _check(lib().hq_test_schedule(l0, delta, max_iter, a.ctypes.data_as(c_vp), b.ctypes.data_as(c_vp),
+                                  c.ctypes.data_as(c_vp), l.ctypes.data_as(c_vp), ctypes.byref(K)))
+    k = K.value
+    return a[:k].copy(), b[:k].copy(), c[:k].copy(), l[: k + 1].copy()
 
 
 # ---- rank predictor --------------------------------------------------------------------------

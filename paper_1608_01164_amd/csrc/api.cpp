@@ -469,6 +469,9 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
     }
 
   std::unique_ptr<hq::PinnedHost> qimg;  // host images of Q1, Q2 (read by copies on the stream)
+  // Q1, Q2 of the structured QR on the host; their rank arrays are pageable and read by copies on
+  // the stream, so they outlive the stream's drain below (declared before it, destroyed after it)
+  std::vector<hq::HostHodlr> h1, h2;
   hq::Engine E(st);
   E.tol = o.tol;
   hq::DevArena xa[2], it, qa, pa;
@@ -503,7 +506,8 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
       // Alg. 3 lines 7-8: structured QR of [sqrt(c0) X0; I] (Algorithms 1/2) and Q1, Q2 in HODLR,
       // built in place in pinned memory (kept until the call ends) and copied from there
       const auto tg = clk::now();
-      std::vector<hq::HostHodlr> h1(act.size()), h2(act.size());
+      h1.assign(act.size(), hq::HostHodlr());
+      h2.assign(act.size(), hq::HostHodlr());
       std::vector<size_t> qoff(act.size() + 1, 0);
       for (size_t j = 0; j < act.size(); ++j) {
         const Member& m = ms[act[j]];
@@ -1342,12 +1346,43 @@ hq_status hq_profile_read(hq_kstat* out, int32_t reset) {
   });
 }
 
+hq_status hq_profile_mfma(double* out, int32_t reset) {
+  if (!out) return fail(HQ_ERR_ARG, "out is NULL");
+  return guard([&]() -> hq_status {
+    hq::prof_mfma(out, reset != 0);
+    return HQ_OK;
+  });
+}
+
 hq_status hq_profile_svd(int64_t* out) {
   if (!out) return fail(HQ_ERR_ARG, "out is NULL");
   return guard([&]() -> hq_status {
     unsigned long long v[8];
     hq::prof_svd_stats(v);
     for (int i = 0; i < 8; ++i) out[i] = (int64_t)v[i];
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_schedule(double l0, double delta, int32_t max_iter, double* a, double* b, double* c, double* l,
+                           int32_t* K) {
+  return guard([&] {
+    if (!(l0 > 0.0) || !(l0 <= 1.0)) return fail(HQ_ERR_ARG, "l0 must lie in (0, 1]");
+    if (!(delta > 0.0)) return fail(HQ_ERR_ARG, "delta must be positive");
+    if (max_iter < 1 || max_iter > 16) return fail(HQ_ERR_ARG, "max_iter must lie in [1, 16]");
+    if (!a || !b || !c || !l || !K) return fail(HQ_ERR_ARG, "output pointer is NULL");
+    const Weights w = schedule(l0, delta, max_iter);
+    double lk = l0;
+    for (size_t k = 0; k < w.a.size(); ++k) {
+      a[k] = w.a[k];
+      b[k] = w.b[k];
+      c[k] = w.c[k];
+      l[k] = lk;
+      lk = lk * (w.a[k] + w.b[k] * lk * lk) / (1.0 + w.c[k] * lk * lk);
+      if (lk > 1.0) lk = 1.0;
+    }
+    l[w.a.size()] = w.lK;
+    *K = (int32_t)w.a.size();
     return HQ_OK;
   });
 }

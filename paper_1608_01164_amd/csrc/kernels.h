@@ -21,6 +21,7 @@ void prof_enable(bool on);
 void prof_select(unsigned mask);  // classes whose launches get timers (bit c for class c; default all)
 bool prof_enabled();
 void prof_read(ProfStat out[K_NCLASS], bool reset);
+void prof_mfma(double out[2], bool reset);  // flops issued to the matrix cores, FP64 and FP32
 void prof_svd_stats(unsigned long long out[8]);  // core-SVD phase cycles and sizes (test/bench aid)
 int prof_begin(int cls, hipStream_t s);    // a record slot, or -1 when profiling is off for cls
 void prof_end(int slot, hipStream_t s);

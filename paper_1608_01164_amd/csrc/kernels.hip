@@ -20,6 +20,7 @@ namespace hq {
 __device__ unsigned long long g_prof[2 * K_NCLASS];  // [flops..., bytes...]
 __device__ unsigned long long g_svdstat[8];  // phase cycles (qr, jacobi, out), sum r, sum t, sum sweeps, calls
 __device__ int g_prof_on;
+__device__ unsigned long long g_mfma[2];  // flops issued to the matrix cores: [0] FP64, [1] FP32
 
 namespace {
 struct Rec { hipEvent_t a, b; int cls; };
@@ -68,6 +69,17 @@ void prof_svd_stats(unsigned long long out[8]) {
   (void)hipDeviceSynchronize();
   (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_svdstat), sizeof(unsigned long long) * 8);
 }
+void prof_mfma(double out[2], bool reset) {
+  (void)hipDeviceSynchronize();
+  unsigned long long h[2];
+  (void)hipMemcpyFromSymbol(h, HIP_SYMBOL(g_mfma), sizeof(h));
+  out[0] = (double)h[0];
+  out[1] = (double)h[1];
+  if (reset) {
+    unsigned long long z[2] = {0, 0};
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(g_mfma), z, sizeof(z));
+  }
+}
 void prof_read(ProfStat out[K_NCLASS], bool reset) {
   std::lock_guard<std::mutex> lk(g_mu);
   (void)hipDeviceSynchronize();
@@ -101,6 +113,10 @@ static __device__ __forceinline__ void count_work(int cls, unsigned long long fl
     atomicAdd(&g_prof[cls], flops);
     if (bytes) atomicAdd(&g_prof[K_NCLASS + cls], bytes);
   }
+}
+// Flops a kernel issued as MFMA instructions (precision 0 FP64, 1 FP32), for the matrix-core utilisation.
+static __device__ __forceinline__ void count_mfma(int prec, unsigned long long flops) {
+  if (g_prof_on) atomicAdd(&g_mfma[prec], flops);
 }
 
 // A launch that the runtime rejects (resources, dimensions) must not pass silently: later kernels
@@ -252,9 +268,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
     ke = kb + kc < k ? kb + kc : k;
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
-  if (blockIdx.x == 0 && z == 0 && tid == 0)
+  if (blockIdx.x == 0 && z == 0 && tid == 0) {
     count_work(K_GEMM, 2ull * m * n * k,
                8ull * ((unsigned long long)m * k + (unsigned long long)k * n + (Tk.beta != 0.0 ? 2ull : 1ull) * m * n));
+    count_mfma(std::is_same<T, double>::value ? 0 : 1, 2ull * m * n * k);
+  }
 
   __shared__ T As[GK][GT + 1];
   __shared__ T Bs[GK][GT + 1];

@@ -21,9 +21,3 @@ def host(T, rows, cols):
 def empty(rows, cols):
     import torch
     return torch.zeros(max(rows * cols, 1), dtype=torch.float64, device="cuda")
-
-
-def mixed_bound(n, levels, fp32_iters):
-    """Stated accuracy of the mixed mode: each FP32 iteration truncates at 4 u32 sqrt(rows) sigma_1 per
-    level, and the part of that error that couples eigenvectors across mu survives the FP64 iterations."""
-    return 2.0 * fp32_iters * levels * 4 * 2.0 ** -24 * np.sqrt(n / 2)

@@ -23,8 +23,8 @@ def test_exports_every_declared_symbol():
     assert "spectral_projector" in names and "apply_projector" in names and "hodlr_build" in names
     for name in names:
         assert hasattr(L, name), name
-    assert set(names) == set(hq.binding.EXPORTED) | {"hq_test_q_dense_host"} - set() or True
-    assert set(hq.binding.EXPORTED) >= set(names)
+    # the binding wraps exactly the declared entry points, no more and no fewer
+    assert set(names) == set(hq.binding.EXPORTED)
 
 
 def test_errors_without_device_work():
