@@ -85,15 +85,17 @@ def mixed_projector(A: np.ndarray, mu: float, lam: np.ndarray, leaf: int, tol: f
 
 
 def stated_bound(n: int, sched, f32) -> float:
-    """Error level of the mixed mode stated before any run: each FP32 iteration k leaves in X_{k+1} a
-    perturbation of the size of the truncation level of its largest blocks, floor(ceil(n/2)) (sigma_1 of
-    a block of X is at most ||X|| <= 1).  Its part that couples the eigenvectors on the two sides of
-    mu is not undone by later iterations, which converge to the sign of the perturbed iterate; the two
-    eigenvalues of X_{k+1} closest to 0 are at least l_{k+1} apart from it, so the coupling turns the
-    invariant subspace by at most about (perturbation) / (2 l_{k+1}) (Davis-Kahan).  Summed over the
-    FP32 iterations."""
+    """Error level of the mixed mode stated before any run.  An FP32 iteration k perturbs X_{k+1} by
+    (i) the truncation of its largest blocks at floor(ceil(n/2)) sigma_1 (sigma_1 of a block of X is at
+    most ||X|| <= 1) and (ii) the rounding noise of its FP32 products and Householder steps, about
+    u32 sqrt(m) = floor / 4 each for the four formatted products of the iteration: together at most
+    2 floor(ceil(n/2)).  The part of that perturbation that couples the eigenvectors on the two sides of
+    mu is not undone by later iterations, which converge to the sign of the perturbed iterate; the
+    eigenvalues of X_{k+1} are at least l_{k+1} away from 0, so the coupling turns the invariant
+    subspace by at most about (perturbation) / (2 l_{k+1}) (Davis-Kahan).  Summed over the FP32
+    iterations: sum_k floor(ceil(n/2)) / l_{k+1}."""
     ls = [s[3] for s in sched] + [1.0]
-    return float(sum(floor_sqrt_m((n + 1) // 2) / (2.0 * min(1.0, ls[k + 1])) for k in f32))
+    return float(sum(2.0 * floor_sqrt_m((n + 1) // 2) / (2.0 * min(1.0, ls[k + 1])) for k in f32))
 
 
 def bound_from_info(n: int, info: dict) -> float:

@@ -68,12 +68,16 @@ def _properties(P, band, mu, seed=0):
     }
 
 
-def _check_properties(name, ab, P, band, mu, bound):
+def _check_properties(name, ab, P, band, mu, bound, levels, tol):
     pr = _properties(P, band, mu)
     anorm = float(np.abs(ab).sum(1).max()) * 2  # ||A||_inf of the symmetric matrix (band stores one triangle)
-    print(f"    {name}: idem {pr['idem']:.2e} (<= {4 * bound:.1e})  comm {pr['comm']:.2e} "
+    # The last iteration and the symmetrisation run in FP64 in every mode and drive the eigenvalues to
+    # 0 and 1 up to the truncations of the final iterate (at most tol per level), whatever the
+    # rotation of the invariant subspace: ||P^2 - P|| <= levels * tol as well as <= 4 ||D||.
+    idem_bound = min(4 * bound, levels * tol)
+    print(f"    {name}: idem {pr['idem']:.2e} (<= {idem_bound:.1e})  comm {pr['comm']:.2e} "
           f"(<= {2 * anorm * bound:.1e})  rayleigh {pr['neg']:.3f} / {pr['pos']:.3f}", flush=True)
-    assert pr["idem"] <= 4 * bound
+    assert pr["idem"] <= idem_bound
     assert pr["comm"] <= 2 * anorm * bound
     assert pr["neg"] < 0 < pr["pos"]
 
@@ -139,7 +143,7 @@ def test_banded16384_norm_parity(default_predictor, banded16384, precision):
     assert two <= bound
     if precision == "fp64":
         assert frob <= 10 * GATE
-    _check_properties("banded-n16384-b8", ab, P, band, mu, bound)
+    _check_properties("banded-n16384-b8", ab, P, band, mu, bound, info["levels"], 1e-10)
     P.close()
 
 
@@ -175,7 +179,7 @@ def test_full_size_sampled_parity(default_predictor, name, maker, b, leaf, tol, 
           f"to mu {err[near].max():.3e}, elsewhere {err[~near].max() if (~near).any() else 0:.3e} | bound {bound:.2e}",
           flush=True)
     assert err.max() <= bound
-    _check_properties(name, ab, P, band, mu, bound)
+    _check_properties(name, ab, P, band, mu, bound, info["levels"], tol)
     P.close()
 
 
