@@ -23,6 +23,7 @@
  */
 #ifndef HQ_H
 #define HQ_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -133,6 +134,22 @@ hq_status spectral_projector_batched(int32_t count, const double* const* bands, 
  */
 hq_status apply_projector(hq_hodlr_t P, const double* X, int64_t ldx, int32_t ncols, double* Y, int64_t ldy,
                           void* stream);
+
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same product Y = P X as apply_projector, with the same kernels and
+ * arguments, but its device workspace comes from one static device array per GPU
+ * (apply_projector_noalloc_max_bytes() bytes, 64 MiB, held until the process ends) and its task
+ * descriptors from pinned memory the handle reserved when it was made; no device or pinned memory is
+ * allocated or freed.  A call whose workspace would exceed the maximum (it grows with ncols and the
+ * ranks of P) returns HQ_ERR_ARG before launching anything.  Every call on a GPU uses that GPU's one
+ * array, which keeps the last call's contents: calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  Like apply_projector, a call waits on the host
+ * until the previous apply of the same handle has read its descriptors.  Stream-ordered otherwise.
+ */
+hq_status apply_projector_noalloc(hq_hodlr_t P, const double* X, int64_t ldx, int32_t ncols, double* Y,
+                                  int64_t ldy, void* stream);
+size_t apply_projector_noalloc_max_bytes(void);
 
 /* Dense copy (device, n x n, ld >= n) of a HODLR matrix; meant for tests and small n. */
 hq_status hodlr_to_dense(hq_hodlr_t H, double* out, int64_t ld, void* stream);

@@ -63,6 +63,8 @@ _SIGS = {
     "spectral_projector_batched": (c_i32, [c_i32, P(c_vp), P(c_i64), P(c_i32), P(c_i64), P(c_d), P(Opts), c_vp,
                                            P(c_vp), P(Info)]),
     "apply_projector": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp]),
+    "apply_projector_noalloc": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp]),
+    "apply_projector_noalloc_max_bytes": (ctypes.c_size_t, []),
     "hodlr_to_dense": (c_i32, [c_vp, c_vp, c_i64, c_vp]),
     "hodlr_shape": (c_i32, [c_vp, P(c_i64), P(c_i32), P(c_i32), P(c_i32)]),
     "hodlr_get_leaf": (c_i32, [c_vp, c_i32, c_vp, c_i64, P(c_i64), P(c_i64)]),
@@ -241,6 +243,18 @@ class HODLR:
                                      _stream(stream)))
         Y = Y.t()
         return Y.reshape(self.n) if vec else Y
+
+    def apply_noalloc(self, Xt, Yt, stream=None):
+        """Y = H X through apply_projector_noalloc, which allocates nothing.  Xt, Yt: contiguous (k, n)
+        float64 device tensors holding X and Y column-major (row j of Xt is column j of X)."""
+        _dev_f64(Xt, "Xt")
+        _dev_f64(Yt, "Yt")
+        if Xt.dim() != 2 or Xt.shape[1] != self.n or tuple(Yt.shape) != tuple(Xt.shape) or \
+                not (Xt.is_contiguous() and Yt.is_contiguous()):
+            raise ValueError("Xt and Yt must be contiguous (k, n) tensors")
+        _check(lib().apply_projector_noalloc(self._h, c_vp(Xt.data_ptr()), self.n, Xt.shape[0], c_vp(Yt.data_ptr()),
+                                             self.n, _stream(stream)))
+        return Yt
 
     def to_dense(self, stream=None):
         import torch

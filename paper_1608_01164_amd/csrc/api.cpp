@@ -14,19 +14,9 @@
 
 #include "engine.h"
 #include "givens.h"
+#include "handle.h"
 #include "predictor.h"
 
-struct hq_hodlr_s {
-  hq::Tree t;
-  std::unique_ptr<hq::Engine> e;
-  hq::HMat H;
-  int* d_w = nullptr;     // device int: width of the current apply
-  hipEvent_t done = nullptr;
-  ~hq_hodlr_s() {
-    if (done) (void)hipEventDestroy(done);
-    e.reset();
-  }
-};
 
 namespace {
 
@@ -287,6 +277,7 @@ hq_hodlr_t compact_copy(hq::Engine& E, const hq::HMat& H, hipStream_t st, int le
   h->d_w = h->e->persist.get<int>(1);
   HQ_CHECK(hipStreamSynchronize(st));
   h->e->stage.reset();
+  reserve_apply_staging(*h);
   return h.release();
 }
 
@@ -879,6 +870,7 @@ hq_status hodlr_build(const double* band, int64_t n, int32_t b, int64_t ldab, do
     build_x0(*h->e, band, n, b, ldab, shift, 1.0 / scale, h->H);
     HQ_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
     h->d_w = h->e->persist.get<int>(1);
+    reserve_apply_staging(*h);
     HQ_CHECK(hipEventRecord(h->done, st));
     *out = h.release();
     return HQ_OK;
@@ -1244,6 +1236,7 @@ hq_status hq_test_from_dense(const double* dense, int64_t n, int64_t ld, const h
     HQ_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
     h->d_w = e.persist.get<int>(1);
     e.stage.reset();
+    reserve_apply_staging(*h);
     *out = h.release();
     return HQ_OK;
   });

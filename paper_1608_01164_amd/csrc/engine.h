@@ -57,12 +57,16 @@ class DevArena {
   template <class T>
   T* get(size_t count) { return static_cast<T*>(alloc(sizeof(T) * (count ? count : 1))); }
   void reset();  // keeps chunks, rewinds
+  // Serve every request from one caller-owned device buffer of `cap` bytes (256-byte aligned), never
+  // from the runtime: a request beyond it throws NoAlloc.  The buffer is not released.
+  void attach_fixed(void* p, size_t cap);
   void swap(DevArena& o) {
     chunks_.swap(o.chunks_);
     std::swap(cur_, o.cur_);
     std::swap(inuse_, o.inuse_);
     std::swap(high_, o.high_);
     std::swap(chunk_bytes, o.chunk_bytes);
+    std::swap(fixed_, o.fixed_);
   }
   struct Mark { size_t cur, used, inuse; };
   Mark mark() const { return Mark{cur_, cur_ < chunks_.size() ? chunks_[cur_].used : 0, inuse_}; }
@@ -74,6 +78,12 @@ class DevArena {
   struct Chunk { char* p; size_t cap, used; };
   std::vector<Chunk> chunks_;
   size_t cur_ = 0, inuse_ = 0, high_ = 0;
+  bool fixed_ = false;  // chunks_ is one external buffer
+};
+
+// A request that an allocation-free call cannot serve from its fixed buffers.
+struct NoAlloc : std::runtime_error {
+  using std::runtime_error::runtime_error;
 };
 
 // Device memory free for this library's use: the runtime's free memory plus the chunks kept for
@@ -106,6 +116,11 @@ class DescStage {
   template <class T>
   T* upload(const std::vector<T>& v, hipStream_t s) { return static_cast<T*>(up(v.data(), sizeof(T) * v.size(), s)); }
   void reset();  // only after the stream has drained
+  // Make sure one chunk of at least `bytes` exists (allocating if needed), so that later uploads of
+  // up to that size in total, after a reset(), take no new pinned memory.
+  void reserve(size_t bytes);
+  size_t capacity() const;
+  bool no_grow = false;  // set: an upload that needs a new chunk throws NoAlloc instead
  private:
   void* up(const void* src, size_t bytes, hipStream_t s);
   struct Chunk { char* h; size_t cap, used; };
@@ -196,6 +211,9 @@ class Engine {
     HView H; int root; const double* X; int ldx; double* Y; int ldy; const int* w; int wcap; double alpha, beta;
   };
   void mm_thin(const std::vector<ThinTask>& tasks);
+  // Device workspace mm_thin takes from `scratch` for these tasks (block-sized V^T X buffers, then
+  // the largest split-K workspace of its launches), in the arena's 256-byte granules.
+  static size_t thin_scratch_bytes(const std::vector<ThinTask>& tasks);
 
   // Truncated recompression of stacked factors Us (m x r) Vs (n x r) into (U, V, rank):
   // U' = Us Rv^T J_k (scaled by sigma), V' = Vs Ru^T (B J)_k / sigma^2 (orthonormal columns).

@@ -108,12 +108,30 @@ static void chunks_release(const std::vector<std::pair<char*, size_t>>& v, bool 
 }
 
 DevArena::~DevArena() {
+  if (fixed_) return;  // the caller's buffer
   std::vector<std::pair<char*, size_t>> v;
   for (auto& c : chunks_) v.push_back({c.p, c.cap});
   chunks_release(v, false);
 }
+void DevArena::attach_fixed(void* p, size_t cap) {
+  if (!chunks_.empty()) throw std::logic_error("attach_fixed: the arena already holds chunks");
+  chunks_.push_back(Chunk{static_cast<char*>(p), cap, 0});
+  cur_ = 0;
+  fixed_ = true;
+}
 void* DevArena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
+  if (fixed_) {
+    Chunk& c = chunks_[0];
+    if (c.used + bytes > c.cap)
+      throw NoAlloc("fixed workspace of " + std::to_string(c.cap) + " bytes exhausted (request of " +
+                    std::to_string(bytes) + " bytes beyond " + std::to_string(c.used) + " in use)");
+    void* p = c.p + c.used;
+    c.used += bytes;
+    inuse_ += bytes;
+    high_ = std::max(high_, inuse_);
+    return p;
+  }
   while (cur_ < chunks_.size()) {
     Chunk& c = chunks_[cur_];
     if (c.used + bytes <= c.cap) {
@@ -164,6 +182,7 @@ void* DescStage::up(const void* src, size_t bytes, hipStream_t s) {
   const size_t need = (bytes + 255) & ~size_t(255);
   while (cur_ < chunks_.size() && chunks_[cur_].used + need > chunks_[cur_].cap) ++cur_;
   if (cur_ == chunks_.size()) {
+    if (no_grow) throw NoAlloc("descriptor staging of " + std::to_string(capacity()) + " bytes exhausted");
     Chunk c;
     c.h = chunk_alloc(std::max(need, size_t(32) << 20), c.cap, true);
     c.used = 0;
@@ -178,6 +197,19 @@ void* DescStage::up(const void* src, size_t bytes, hipStream_t s) {
 void DescStage::reset() {
   for (auto& c : chunks_) c.used = 0;
   cur_ = 0;
+}
+void DescStage::reserve(size_t bytes) {
+  for (const auto& c : chunks_)
+    if (c.cap >= bytes) return;
+  Chunk c;
+  c.h = chunk_alloc(std::max(bytes, size_t(32) << 20), c.cap, true);
+  c.used = 0;
+  chunks_.push_back(c);
+}
+size_t DescStage::capacity() const {
+  size_t b = 0;
+  for (const auto& c : chunks_) b += c.cap;
+  return b;
 }
 
 size_t HMat::bytes() const {
@@ -391,6 +423,34 @@ void Engine::mm_thin(const std::vector<ThinTask>& tasks) {
   gemm(leafv, maxleaf, wmax);
   gemm(tv, capmax, wmax);
   for (int l = 0; l < Lmax; ++l) gemm(upd[l], (int)rowmax, wmax);
+}
+
+size_t Engine::thin_scratch_bytes(const std::vector<ThinTask>& tasks) {
+  auto granule = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
+  auto splitk = [&](int m, int n, int k) -> size_t {  // Engine::gemm's workspace of one task (kp unset)
+    const int S = gemm_splits(k);
+    if (S <= 1 || m <= 0 || n <= 0) return 0;
+    const size_t tiles = (size_t)((m + 63) / 64) * ((n + 63) / 64);
+    return granule(sizeof(double) * tiles * S * 64 * 64);
+  };
+  size_t tmp = 0, ws_leaf = 0, ws_t = 0;
+  for (const ThinTask& T : tasks) {
+    const Tree* t = T.H.h->t;
+    const int lr = Tree::level(T.root), L = t->L;
+    const int nl = 1 << (L - lr), first = ((T.root + 1) << (L - lr)) - 1;
+    for (int q = first; q < first + nl; ++q) ws_leaf += splitk((int)t->size(q), T.wcap, (int)t->size(q));
+    for (int l = lr; l < L; ++l) {
+      const int cnt = 1 << (l - lr), f0 = ((T.root + 1) << (l - lr)) - 1;
+      for (int q = f0; q < f0 + cnt; ++q)
+        for (int s = 0; s < 2; ++s) {
+          const HView::Blk B = s == 0 ? T.H.upper(q) : T.H.lower(q);
+          const int64_t mcol = s == 0 ? t->size(2 * q + 2) : t->size(2 * q + 1);
+          tmp += granule(sizeof(double) * (size_t)B.cap * T.wcap);
+          ws_t += splitk(B.cap, T.wcap, (int)mcol);
+        }
+    }
+  }
+  return tmp + std::max(ws_leaf, ws_t);
 }
 
 // ---------------------------------------------------------------------------------------------
