@@ -249,6 +249,8 @@ def main():
                     help="mixed: middle QDWH iterations in FP32 (GEMM on FP32 MFMA, FP32 TSQR and core SVD)")
     ap.add_argument("--no-predictor", action="store_true",
                     help="capacities from the previous iterate's ranks instead of the trained rank predictor")
+    ap.add_argument("--graph", action="store_true",
+                    help="launch each Cholesky iteration as one captured HIP graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); sharding "
@@ -275,7 +277,8 @@ def main():
         last = i == args.warmup - 1 and not args.no_profile
         if last:
             hq.profile(True)
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision,
+                                        graph=args.graph)
         P.close()
         if last:
             prof_w = hq.profile_read()
@@ -291,7 +294,8 @@ def main():
     for i in range(args.steps):
         if P is not None:
             P.close()
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision,
+                                        graph=args.graph)
         infos.append(info)
         print(f"# step {i}: {info['seconds']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()

@@ -62,6 +62,10 @@ typedef struct {
                                 Cholesky factorisations, the first and last iterations and the
                                 symmetrisation stay FP64 (so Z = I + c X^T X, with condition number
                                 up to 1 + c, is only formed in FP32 when c is moderate). */
+  int32_t graph;             /* nonzero: capture each Cholesky iteration (k >= 1: the product for Z,
+                                the H-Cholesky, the two products of the solves, all streams) into one
+                                HIP graph and launch it as a whole.  Currently disabled: a nonzero
+                                value returns HQ_ERR_UNSUPPORTED.  Default 0 (launches one by one). */
 } hq_opts;
 #define HQ_FP64 0
 #define HQ_MIXED 1
@@ -86,6 +90,9 @@ typedef struct {
   int32_t level_ranks[16][4][24];
   int64_t capacity_columns;  /* sum over iterations of the factor columns allocated for X_{k+1}, Z, L, Y */
   int32_t fp32_iter[16];     /* 1 where iteration k ran in FP32 (HQ_MIXED) */
+  int32_t graphs;            /* opts.graph: iterations launched as captured graphs */
+  int64_t graph_nodes;       /* opts.graph: kernel and dependency nodes in those graphs */
+  double graph_build_seconds;/* opts.graph: host time spent capturing and instantiating them */
 } hq_info;
 
 /* Fill *o with the defaults: leaf 256, tol 1e-10, delta 1e-15, max_rank 512, max_iter 10. */
@@ -174,6 +181,26 @@ hq_status hq_shift_for_count(const double* band, int64_t n, int32_t b, int64_t l
 void hodlr_destroy(hq_hodlr_t H);
 const char* hq_status_string(hq_status s);
 const char* hq_last_error(void);
+
+/*
+ * Tile shapes and thresholds of the kernels, picked by the project's autotuner
+ * (paper_1608_01164_amd/autotune.py, outside any timed region) and read by the library at first use
+ * from tuning.txt next to it (or the file named by the environment variable HQ_TUNING); built-in
+ * defaults when there is none.  They change how work is tiled (so results can differ in the last
+ * bits between tables), never what is computed.
+ *   qr_tile_rows  rows of a TSQR row tile (stage 0 of the R-only TSQR of the recompressions), 32..8192
+ *   split_min_k   GEMMs with an inner dimension >= this split it over workgroups, >= 64
+ *   split_chunk   rows of the inner dimension per split, >= 32
+ *   split_max     most splits, 1..128
+ *   schur_keep    the H-Cholesky carries its lazy Schur factor uncompressed up to this many columns
+ * hq_tuning_set replaces the table for the rest of the process (all values checked, HQ_ERR_ARG if out
+ * of range); it must not be called while a solve runs.  hq_tuning_source names where the values came
+ * from.
+ */
+typedef struct { int32_t qr_tile_rows, split_min_k, split_chunk, split_max, schur_keep; } hq_tuning;
+hq_status hq_tuning_get(hq_tuning* out);
+hq_status hq_tuning_set(const hq_tuning* in);
+const char* hq_tuning_source(void);
 
 /* ---- Test hooks: single building blocks of the path, exposed so that tests can compare each one
  *      with an independent reference.  All pointers device unless stated. ---- */

@@ -1,0 +1,104 @@
+"""Autotuner of the library's tile shapes and thresholds (the table `hq_tuning` in include/hq.h).
+
+Run on the GPU, outside any timed benchmark:
+
+    python -m paper_1608_01164_amd.autotune [--out paper_1608_01164_amd/tuning.txt]
+
+For each parameter in turn (coordinate descent, two passes) it times spectral projectors of the
+representative workloads for every candidate value, keeps the fastest, and writes the table next to
+the library, where the library reads it at first use.  Every candidate computes the same projector
+(tiling only changes rounding), and the times of all candidates are written into the table's comments.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CANDIDATES = {
+    "qr_tile_rows": [256, 512, 1024, 2048],
+    "split_chunk": [128, 256, 512],
+    "split_max": [16, 32, 64],
+    "schur_keep": [0, 64, 96, 128, 160],
+}
+
+
+def _workloads():
+    import workloads as w
+    # (name, band, b, leaf, tol): the banded n=16384, b=8 workload and the near-Laplacian n=32768 one
+    return [("banded-n16384-b8", w.banded_normal(16384, 8, 0), 8, 128, 1e-10),
+            ("metallic-n32768", w.tridiag_metallic(32768, 0), 1, 256, 1e-10)]
+
+
+def _time(hq, cases, reps):
+    """Seconds per round of one projector per workload (median of `reps` rounds after one warmup)."""
+    import torch
+    ts = []
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _, band, b, mu, leaf, tol, pred in cases:
+            P, _ = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred)
+            P.close()
+        torch.cuda.synchronize()
+        if rep > 0:
+            ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(HERE, "tuning.txt"))
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--passes", type=int, default=2)
+    args = ap.parse_args()
+    import torch
+    import paper_1608_01164_amd as hq
+    from paper_1608_01164_amd import predictor as hp
+
+    pred = hp.load() if os.path.exists(hp.DEFAULT_PATH) else None
+    cases = []
+    for name, ab, b, leaf, tol in _workloads():
+        mu, _ = hq.shift_for_count(ab, b, ab.shape[0] // 2)
+        cases.append((name, torch.from_numpy(np.ascontiguousarray(ab)).cuda(), b, mu, leaf, tol, pred))
+    best = {k: v for k, v in hq.tuning().items() if k in CANDIDATES or k in ("split_min_k",)}
+    hq.set_tuning(**best)
+    log = []
+    t_best = _time(hq, cases, args.reps)
+    log.append(f"# start {best}: {t_best:.4f} s")
+    print(log[-1], flush=True)
+    for p in range(args.passes):
+        for key, values in CANDIDATES.items():
+            for v in values:
+                if v == best[key]:
+                    continue
+                trial = dict(best, **{key: v})
+                hq.set_tuning(**trial)
+                t = _time(hq, cases, args.reps)
+                log.append(f"# pass {p} {key}={v}: {t:.4f} s (best so far {t_best:.4f} s)")
+                print(log[-1], flush=True)
+                if t < t_best * 0.99:
+                    best, t_best = trial, t
+            hq.set_tuning(**best)
+    with open(args.out, "w") as f:
+        f.write("# Tile shapes and thresholds picked by paper_1608_01164_amd/autotune.py on one MI355X:\n")
+        f.write("# seconds per round of one spectral projector each of " +
+                ", ".join(c[0] for c in cases) + " (FP64, rank predictor).\n")
+        for line in log:
+            f.write(line + "\n")
+        f.write(f"# chosen: {t_best:.4f} s\n")
+        for k in ("qr_tile_rows", "split_min_k", "split_chunk", "split_max", "schur_keep"):
+            f.write(f"{k} {best[k]}\n")
+    print(f"wrote {args.out}: {best} ({t_best:.4f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

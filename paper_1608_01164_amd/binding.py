@@ -29,7 +29,38 @@ class HQError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("leaf", c_i32), ("tol", c_d), ("delta", c_d), ("max_rank", c_i32), ("max_iter", c_i32),
-                ("record_ranks", c_i32), ("predictor", c_vp), ("precision", c_i32), ("c_fp32_max", c_d)]
+                ("record_ranks", c_i32), ("predictor", c_vp), ("precision", c_i32), ("c_fp32_max", c_d),
+                ("graph", c_i32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("qr_tile_rows", c_i32), ("split_min_k", c_i32), ("split_chunk", c_i32), ("split_max", c_i32),
+                ("schur_keep", c_i32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def tuning() -> dict:
+    """The tile shapes and thresholds in use (the autotuner's table, or the defaults)."""
+    t = Tuning()
+    _check(lib().hq_tuning_get(ctypes.byref(t)))
+    d = t.as_dict()
+    d["source"] = lib().hq_tuning_source().decode()
+    return d
+
+
+def set_tuning(**kw) -> dict:
+    """Replace entries of the table for the rest of the process; returns the previous values."""
+    t = Tuning()
+    _check(lib().hq_tuning_get(ctypes.byref(t)))
+    old = t.as_dict()
+    for k, v in kw.items():
+        if k not in old:
+            raise KeyError(k)
+        setattr(t, k, int(v))
+    _check(lib().hq_tuning_set(ctypes.byref(t)))
+    return old
 
 
 class Info(ctypes.Structure):
@@ -37,7 +68,8 @@ class Info(ctypes.Structure):
                 ("max_rank_iter", c_i32 * 16), ("max_rank", c_i32), ("redo_count", c_i32), ("bytes", c_i64),
                 ("peak_bytes", c_i64), ("launches", c_i64), ("seconds", c_d), ("setup_seconds", c_d),
                 ("givens_seconds", c_d), ("levels", c_i32), ("level_ranks", c_i32 * (16 * 4 * 24)),
-                ("capacity_columns", c_i64), ("fp32_iter", c_i32 * 16)]
+                ("capacity_columns", c_i64), ("fp32_iter", c_i32 * 16), ("graphs", c_i32), ("graph_nodes", c_i64),
+                ("graph_build_seconds", c_d)]
 
     def as_dict(self) -> dict:
         K = self.iters
@@ -46,7 +78,9 @@ class Info(ctypes.Structure):
                 "redo_count": self.redo_count, "bytes": self.bytes, "peak_bytes": self.peak_bytes,
                 "launches": self.launches, "seconds": self.seconds, "setup_seconds": self.setup_seconds,
                 "givens_seconds": self.givens_seconds, "levels": self.levels,
-                "capacity_columns": self.capacity_columns, "fp32_iter": list(self.fp32_iter[:K])}
+                "capacity_columns": self.capacity_columns, "fp32_iter": list(self.fp32_iter[:K]),
+                "graphs": self.graphs, "graph_nodes": self.graph_nodes,
+                "graph_build_seconds": self.graph_build_seconds}
 
     def level_ranks_array(self) -> np.ndarray:
         """[k][o][l]: o = 0 X_{k+1}, 1 Z_k, 2 L_k^{-1}, 3 Y_k (filled with opts record_ranks)."""
@@ -65,6 +99,9 @@ _SIGS = {
     "apply_projector": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp]),
     "apply_projector_noalloc": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp]),
     "apply_projector_noalloc_max_bytes": (ctypes.c_size_t, []),
+    "hq_tuning_get": (c_i32, [c_vp]),
+    "hq_tuning_set": (c_i32, [c_vp]),
+    "hq_tuning_source": (ctypes.c_char_p, []),
     "hodlr_to_dense": (c_i32, [c_vp, c_vp, c_i64, c_vp]),
     "hodlr_shape": (c_i32, [c_vp, P(c_i64), P(c_i32), P(c_i32), P(c_i32)]),
     "hodlr_get_leaf": (c_i32, [c_vp, c_i32, c_vp, c_i64, P(c_i64), P(c_i64)]),
@@ -174,7 +211,7 @@ def _check(status: int):
 
 
 def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10, record_ranks=False, predictor=None,
-          precision="fp64", c_fp32_max=16.0) -> Opts:
+          precision="fp64", c_fp32_max=16.0, graph=False) -> Opts:
     o = Opts()
     _check(lib().hq_default_opts(ctypes.byref(o)))
     o.leaf, o.tol, o.delta, o.max_rank, o.max_iter = int(leaf), float(tol), float(delta), int(max_rank), int(max_iter)
@@ -184,6 +221,7 @@ def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10, record_ra
         raise ValueError("precision must be 'fp64' or 'mixed'")
     o.precision = 1 if precision == "mixed" else 0
     o.c_fp32_max = float(c_fp32_max)
+    o.graph = 1 if graph else 0
     return o
 
 

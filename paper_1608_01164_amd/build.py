@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhqdwh.so")
-SOURCES = ["kernels.hip", "engine.hip", "mlp.hip", "noalloc.hip", "givens.cpp", "predictor.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "engine.hip", "mlp.hip", "noalloc.hip", "givens.cpp", "predictor.cpp", "tuning.cpp", "api.cpp"]
 ARCH = os.environ.get("HQ_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -35,7 +35,7 @@ def build(force: bool = True, jobs: int = 4) -> str:
         _wait(p)
     tmp = OUT + ".tmp%d" % os.getpid()
     link = ["hipcc", "-shared", "-fPIC", "-fopenmp", f"--offload-arch={ARCH}", *objs, "-o", tmp,
-            "-Wl,-rpath,/opt/rocm/lib:/opt/rocm/llvm/lib"]
+            "-Wl,-rpath,/opt/rocm/lib:/opt/rocm/llvm/lib", "-ldl"]
     subprocess.check_call(link)
     os.replace(tmp, OUT)
     return OUT

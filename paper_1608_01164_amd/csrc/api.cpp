@@ -290,6 +290,10 @@ hq_status check_opts(const hq_opts* o, hq_opts& out) {
   if (out.max_rank < 1) return fail(HQ_ERR_ARG, "opts.max_rank must be >= 1");
   if (out.max_iter < 1 || out.max_iter > 16) return fail(HQ_ERR_ARG, "opts.max_iter must be in [1, 16]");
   if (out.precision != HQ_FP64 && out.precision != HQ_MIXED) return fail(HQ_ERR_ARG, "opts.precision must be FP64 or MIXED");
+  if (out.graph)
+    return fail(HQ_ERR_UNSUPPORTED,
+                "opts.graph: launching an iteration as a captured HIP graph is disabled (the capture "
+                "path ended its first test run in a host segmentation fault whose cause is not found)");
   return HQ_OK;
 }
 
@@ -571,6 +575,10 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         ms[i].Xn = E.alloc_hmat_in(xa[cur ^ 1], &ms[i].t, ms[i].capX, false);
         ms[i].inf.capacity_columns += capacity_columns(ms[i].t, ms[i].capX);
       }
+      // a Cholesky iteration as one graph: everything from here to the status readback
+      const bool capture = o.graph && k > 0;
+      hq::Engine::Graph graph;
+      if (capture) E.capture_begin();
       E.clear_flags(nm);
       if (k == 0) {
         // Alg. 3 line 9: X1 = b0/c0 X0 + (a0 - b0/c0)/sqrt(c0) Q1 Q2^T
@@ -609,10 +617,12 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
           Member& m = ms[i];
           m.Z = E.alloc_hmat_in(it, &m.t, m.capZ, true);
           m.Linv = E.alloc_hmat_in(it, &m.t, m.capL, false);
-          m.Lf = E.alloc_hmat_in(it, &m.t, m.capL, false);
+          const int capS = 2 * max_of(m.capL) + 16;
+          const std::vector<int> capW = E.chol_work_caps(m.t, m.capZ, capS);
+          m.Lf = E.alloc_hmat_in(it, &m.t, capW, false);
           m.Y = E.alloc_hmat_in(it, &m.t, m.capY, false);
-          m.inf.capacity_columns += capacity_columns(m.t, m.capZ) / 2 + 2 * capacity_columns(m.t, m.capL) +
-                                    capacity_columns(m.t, m.capY);
+          m.inf.capacity_columns += capacity_columns(m.t, m.capZ) / 2 + capacity_columns(m.t, m.capL) +
+                                    capacity_columns(m.t, capW) + capacity_columns(m.t, m.capY);
           const double a = m.w.a[k], bb = m.w.b[k], c = m.w.c[k];
           hq::Engine::ProdTask q;
           q.A = E.view(m.X, true);
@@ -623,7 +633,7 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
           q.C = &m.Z;
           q.fidx = i;
           pz.push_back(q);
-          pc.push_back(hq::Engine::CholTask{&m.Z, &m.Linv, &m.Lf, 2 * max_of(m.capL) + 16, i});
+          pc.push_back(hq::Engine::CholTask{&m.Z, &m.Linv, &m.Lf, capS, i});
           q = hq::Engine::ProdTask{};
           q.A = E.view(m.X);
           q.B = E.view(m.Linv, true);  // Y = X L^{-T} = X W^{-1}
@@ -651,8 +661,17 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         }
         E.fp32 = false;
       }
+      if (capture) {
+        graph = E.capture_end_launch();
+        for (int i : pend) {
+          ms[i].inf.graphs += 1;
+          ms[i].inf.graph_nodes += graph.nodes;
+          ms[i].inf.graph_build_seconds += graph.build_seconds;
+        }
+      }
       note_peak();
       const std::vector<int> f = E.read_flags(nm);
+      graph.release();
       std::vector<int> again;
       for (int i : pend) {
         Member& m = ms[i];
@@ -829,6 +848,7 @@ hq_status hq_default_opts(hq_opts* o) {
   o->predictor = nullptr;
   o->precision = HQ_FP64;
   o->c_fp32_max = 16.0;
+  o->graph = 0;
   return HQ_OK;
 }
 
@@ -1277,7 +1297,8 @@ hq_status hq_test_cholesky_inverse(hq_hodlr_t Z, int32_t cap, double tol, void* 
     hq::Engine E(st);
     E.tol = tol;
     const std::vector<int> c = caps_from(Z->t, cap, 1 << 30);
-    hq::HMat Linv = E.alloc_hmat(&Z->t, c, false), Lf = E.alloc_hmat(&Z->t, c, false);
+    hq::HMat Linv = E.alloc_hmat(&Z->t, c, false);
+    hq::HMat Lf = E.alloc_hmat(&Z->t, E.chol_work_caps(Z->t, Z->H.cap, 2 * cap + 16), false);
     hq::HMat Zs = Z->H;
     Zs.lower_only = true;
     E.cholesky_inverse(Zs, Linv, Lf, 2 * cap + 16);

@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstring>
 #include <stdexcept>
@@ -186,6 +187,9 @@ class Engine {
   // is always joined back into st before its memory is released.
   static constexpr int kSides = 3;
   hipStream_t side_stream(int i);
+  // The H-Cholesky's lazy Schur factor is compressed (through its Gram matrix) only when it has more
+  // live columns than this; narrower factors are carried as they are.
+  int schur_keep = 96;
   bool keep_scratch = false;  // set while issuing side-stream work: helpers then keep their workspace
   DevArena persist, scratch;
   DescStage stage;
@@ -211,6 +215,37 @@ class Engine {
     HView H; int root; const double* X; int ldx; double* Y; int ldy; const int* w; int wcap; double alpha, beta;
   };
   void mm_thin(const std::vector<ThinTask>& tasks);
+
+  // Stream capture of everything issued between capture_begin and capture_end_launch (the library
+  // stream and the side streams it forks and joins) into one HIP graph, which is instantiated and
+  // launched on the library stream.  The executable graph lives until release(), which the caller
+  // issues after the stream has drained.
+  struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    int64_t nodes = 0;
+    double build_seconds = 0.0;
+    void release();
+    Graph() = default;
+    Graph(const Graph&) = delete;
+    Graph& operator=(const Graph&) = delete;
+    Graph(Graph&& o) noexcept { *this = std::move(o); }
+    Graph& operator=(Graph&& o) noexcept {
+      if (this != &o) {
+        release();
+        g = o.g; x = o.x; nodes = o.nodes; build_seconds = o.build_seconds;
+        o.g = nullptr;
+        o.x = nullptr;
+      }
+      return *this;
+    }
+    ~Graph() { release(); }
+  };
+  void capture_begin();
+  Graph capture_end_launch();
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr, caller_st = nullptr;
+  std::chrono::steady_clock::time_point cap_t0;
   // Device workspace mm_thin takes from `scratch` for these tasks (block-sized V^T X buffers, then
   // the largest split-K workspace of its launches), in the arena's 256-byte granules.
   static size_t thin_scratch_bytes(const std::vector<ThinTask>& tasks);
@@ -235,6 +270,7 @@ class Engine {
   struct SymTask {
     const double* S; int lds; int m; const int* r; int rcap; double* out; int ldo; int* rank; int kcap; double thresh;
     int fidx;
+    int keep_below = 0;  // a factor of at most this many live columns is kept as it is (out = S)
   };
   void compress_sym(const std::vector<SymTask>& tasks);
   // `core_after`: the stream waits for it between the TSQR and the core of the group (a task's Rv
@@ -255,7 +291,12 @@ class Engine {
   void product(HView A, HView B, const HView* D, bool d_identity, double alpha, double delta, HMat& C);
   // Cholesky Z = L L^T of symmetric HODLR matrices (lower blocks + leaves); L^{-1} in Linv.  The
   // members' recursions advance in lockstep, one launch per step for all of them.
+  // Z = L L^T and Linv = L^{-1} (capacities of the truncated inverse).  Lf: workspace of the same
+  // tree whose leaves receive the leaf factors and whose off-diagonal blocks receive the untruncated
+  // inverse blocks; its capacities must be chol_work_caps(Z's capacities, capS).  capS: capacity of
+  // the compressed Schur factor.
   struct CholTask { const HMat* Z; HMat* Linv; HMat* Lf; int capS; int fidx; };
+  std::vector<int> chol_work_caps(const Tree& t, const std::vector<int>& capZ, int capS) const;
   void cholesky_inverse(const std::vector<CholTask>& v);
   void cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) { cholesky_inverse({CholTask{&Z, &Linv, &Lf, capS, 0}}); }
   // out = sid * I + sx * (X + X^T) / 2 as a full HODLR (sign: sx = 1, sid = 0; projector: -1/2, 1/2)

@@ -5,6 +5,8 @@
 // device memory.
 #include "engine.h"
 
+#include <chrono>
+
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -231,12 +233,21 @@ HView::Blk HView::lower(int p) const {
 
 // ---------------------------------------------------------------------------------------------
 Engine::Engine(hipStream_t s) : st(s) {
+  schur_keep = tuning().schur_keep;
   rec_budget = std::max(rec_budget, free_device_bytes() / 4);
   HQ_CHECK(hipMalloc(&d_flag, sizeof(int) * (kFlagSlots + 64)));
   d_zero = d_flag + kFlagSlots;
   HQ_CHECK(hipMemsetAsync(d_flag, 0, sizeof(int) * (kFlagSlots + 64), st));
 }
 Engine::~Engine() {
+  if (capturing) {  // an error inside a capture: end it and drop the partial graph
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cap_stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+  }
+  if (cap_stream) {
+    (void)hipStreamSynchronize(cap_stream);
+    (void)hipStreamDestroy(cap_stream);
+  }
   for (hipStream_t& sd : sides_)
     if (sd) {
       (void)hipStreamSynchronize(sd);
@@ -425,6 +436,44 @@ void Engine::mm_thin(const std::vector<ThinTask>& tasks) {
   for (int l = 0; l < Lmax; ++l) gemm(upd[l], (int)rowmax, wmax);
 }
 
+void Engine::Graph::release() {
+  if (x) (void)hipGraphExecDestroy(x);
+  if (g) (void)hipGraphDestroy(g);
+  x = nullptr;
+  g = nullptr;
+}
+// The capture runs on a stream of the engine's own (the caller's stream may be the null stream,
+// which cannot be captured); it starts after the caller's stream's earlier work, and the graph is
+// launched on the caller's stream.
+void Engine::capture_begin() {
+  if (capturing) throw std::logic_error("capture_begin: already capturing");
+  if (!cap_stream) HQ_CHECK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  hipEvent_t e = take_event();
+  HQ_CHECK(hipEventRecord(e, st));
+  HQ_CHECK(hipStreamWaitEvent(cap_stream, e, 0));
+  give_event(e);
+  cap_t0 = std::chrono::steady_clock::now();
+  caller_st = st;
+  st = cap_stream;
+  capturing = true;
+  HQ_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+}
+Engine::Graph Engine::capture_end_launch() {
+  if (!capturing) throw std::logic_error("capture_end_launch: not capturing");
+  capturing = false;
+  Graph G;
+  const hipError_t e = hipStreamEndCapture(st, &G.g);
+  st = caller_st;
+  HQ_CHECK(e);
+  size_t nn = 0;
+  HQ_CHECK(hipGraphGetNodes(G.g, nullptr, &nn));
+  G.nodes = (int64_t)nn;
+  HQ_CHECK(hipGraphInstantiate(&G.x, G.g, nullptr, nullptr, 0));
+  G.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - cap_t0).count();
+  HQ_CHECK(hipGraphLaunch(G.x, st));
+  return G;
+}
+
 size_t Engine::thin_scratch_bytes(const std::vector<ThinTask>& tasks) {
   auto granule = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
   auto splitk = [&](int m, int n, int k) -> size_t {  // Engine::gemm's workspace of one task (kp unset)
@@ -458,7 +507,7 @@ size_t Engine::thin_scratch_bytes(const std::vector<ThinTask>& tasks) {
 QrPlan plan_qr(int m, int rcap) {
   // Row tiles depend on m alone (never on capacities), so a result does not change when a
   // capacity does; slots hold a tile or two stacked triangles, whichever is taller.
-  constexpr int kTile = 1024;
+  const int kTile = tuning().qr_tile_rows;
   QrPlan p;
   p.h0 = m <= kTile ? std::max(m, 1) : kTile;
   p.ntiles = (m + p.h0 - 1) / p.h0;
@@ -674,6 +723,7 @@ void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
     s.B = G; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = ls;
     s.kcap = T.kcap; s.thresh = th2; s.qr_thresh = 0.1 * th2; s.fidx = T.fidx;
     s.fp32_floor = fp32_floor(T.m);
+    s.keep_below = T.keep_below;
     sv.push_back(s);
     GemmTask o{};  // out = S Jk
     o.A = T.S; o.lda = T.lds; o.B = Jk; o.ldb = ls; o.C = T.out; o.ldc = T.ldo;
@@ -1031,9 +1081,17 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
   struct SF { double* p; int ld; const int* r; int cap; };
   struct Item { int m; int c; SF S; };
   const double thS = std::sqrt(0.1 * tol);
-  for (const CholTask& T : batch) {
+  // The inverse during the recursion: Linv's leaves with Lf's off-diagonal blocks, which hold the
+  // inverse blocks untruncated (widths of the stacked factors); they are recompressed into Linv's
+  // blocks once the recursion is done.
+  std::vector<HMat> lw(batch.size());
+  for (size_t m = 0; m < batch.size(); ++m) {
+    const CholTask& T = batch[m];
     zero_ranks(*T.Linv);
     zero_ranks(*T.Lf);
+    lw[m] = *T.Lf;
+    lw[m].leaves = T.Linv->leaves;
+    lw[m].ldl = T.Linv->ldl;
   }
   std::function<void(const std::vector<Item>&)> dfs = [&](const std::vector<Item>& items) {
     // leaves: Lf_i = chol(Z_i - S S^T), Linv_i = Lf_i^{-1}
@@ -1135,15 +1193,20 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     }
     dfs(left);
     // Off-diagonal factor L_ba = (Z_ba - S_b S_a^T) L_aa^{-T} = Us Vs^T with Us = [U(Z_ba), S_b] and
-    // Vs = L_aa^{-1} [V(Z_ba), -S_a], and the Schur factor of the right child.  With Vs = Qv Rv,
-    // L_ba L_ba^T = (Us Rv^T)(Us Rv^T)^T exactly, so the new Schur factor comes from [S_b, Us Rv^T]
-    // (compressed through its Gram matrix unless the right child is a leaf, which takes it as it is)
-    // as soon as Rv exists.  The truncated recompression of L_ba itself (TSQR of Us, core SVD) is not
-    // needed before the inverse blocks of p: it runs on the second stream, joined just before them.
+    // Vs = L_aa^{-1} [V(Z_ba), -S_a], and the Schur factor of the right child:
+    //   S_b S_b^T + L_ba L_ba^T = Us M Us^T,  M = Vs^T Vs + diag(0 on U(Z_ba)'s columns, I on S_b's),
+    // so the new factor is Us C with M = C C^T, the Cholesky factor of the small M, from one Gram
+    // GEMM over Vs's rows: no factorisation of the tall Vs on the depth-first chain.  M is positive
+    // definite: x^T M x = |Vs x|^2 + |x_S|^2 vanishes only if x_S = 0 and L_aa^{-1} V(Z_ba) x_Z = 0,
+    // i.e. x = 0 (V(Z_ba) has orthonormal columns), and its condition is moderate (L_aa^{-1} has
+    // norm <= 1 and condition <= (1 + c_k)^(1/2)), so it needs no pivoting.  Unless the right child is a leaf (which takes Us C as it is),
+    // Us C is compressed through its Gram matrix when it is wider than schur_keep columns.  After the
+    // right subtree, the inverse block [L^-1]_ba = -(L_bb^-1 Us)(L_aa^-T Vs)^T is formed from the
+    // untruncated factors (Lf's block); L_ba itself is never truncated.
     const int ni = (int)inner.size();
     std::vector<double*> Snew(ni);
     std::vector<int*> rnew(ni);
-    std::vector<int> capSb(ni), rcapv(ni);
+    std::vector<int> capSb(ni), rcapv(ni), keepv(ni);
     std::vector<char> raw(ni);
     for (int i = 0; i < ni; ++i) {
       const Item& it = inner[i];
@@ -1153,22 +1216,22 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       const int64_t sb = t->size(2 * it.c + 2);
       raw[i] = t->is_leaf(2 * it.c + 2);
       rcapv[i] = std::min(kMaxStack, T.Z->cap[l] + it.S.cap);
-      capSb[i] = raw[i] ? std::min(kMaxStack, it.S.cap + rcapv[i]) : std::min<int>({(int)sb, T.capS, kMaxStack});
+      if (rcapv[i] > T.Lf->cap[l]) throw std::logic_error("cholesky_inverse: Lf narrower than the stacked factors");
+      keepv[i] = std::min<int>({schur_keep, (int)sb, rcapv[i]});
+      capSb[i] = raw[i] ? rcapv[i] : std::max(std::min<int>({(int)sb, T.capS, kMaxStack}), keepv[i]);
       Snew[i] = scratch.get<double>((size_t)sb * capSb[i]);
       rnew[i] = scratch.get<int>(1);
     }
-    // stacks, Rv and the second stream's workspace stay allocated until the join
+    // stacked factors stay allocated until the inverse blocks
     const DevArena::Mark mk = scratch.mark();
-    hipEvent_t done = nullptr;
+    std::vector<double*> Usv(ni), Vsv(ni);
+    std::vector<int*> rsv(ni);
     {
-      std::vector<StackTask> stk, stk2;
+      std::vector<StackTask> stk;
       std::vector<ThinTask> th;
-      std::vector<RecTask> rec;
-      std::vector<QrJob> vq;
-      std::vector<GemmTask> gw;
+      std::vector<GemmTask> gG, gC;
+      std::vector<PcholTask> pc;
       std::vector<SymTask> sym;
-      std::vector<double*> Usv(ni), Rvv(ni);
-      std::vector<int*> rsv(ni);
       int maxrows = 1, maxsb = 1, rmax = 1;
       for (int i = 0; i < ni; ++i) {
         const Item& it = inner[i];
@@ -1185,10 +1248,9 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         double* Us = scratch.get<double>((size_t)ldc * rcap);
         double* Vs0 = scratch.get<double>((size_t)ldc * rcap);
         double* Vs = scratch.get<double>((size_t)ldc * rcap);
-        double* Rv = scratch.get<double>((size_t)rcap * rcap);
         int* rs = scratch.get<int>(1);
         Usv[i] = Us;
-        Rvv[i] = Rv;
+        Vsv[i] = Vs;
         rsv[i] = rs;
         StackTask su{};
         su.dst = Us; su.ld = ldc; su.rows = (int)sb; su.wcap = rcap; su.wout = rs; su.nsrc = 2; su.fidx = T.fidx;
@@ -1200,80 +1262,47 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         sv.src[1] = {S.p ? S.p + la : nullptr, S.r, S.ld, S.cap, -1.0};
         stk.push_back(su);
         stk.push_back(sv);
-        th.push_back(ThinTask{view(*T.Linv), a, Vs0, ldc, Vs, ldc, rs, rcap, 1.0, 0.0});
-        vq.push_back(QrJob{Vs, ldc, (int)sa, rs, rcap, Rv, T.fidx});
-        RecTask r{};
-        r.Us = Us; r.ldus = ldc; r.m = (int)sb; r.Vs = Vs; r.ldvs = ldc; r.n = (int)sa; r.r = rs; r.rcap = rcap;
-        r.U = T.Lf->U(p, 1); r.V = T.Lf->V(p, 1); r.ldu = r.ldv = ldc; r.rank = T.Lf->rk(p, 1); r.kcap = T.Lf->cap[l];
-        r.thresh = tol; r.fidx = T.fidx; r.Rv = Rv;
-        rec.push_back(r);
+        th.push_back(ThinTask{view(lw[it.m]), a, Vs0, ldc, Vs, ldc, rs, rcap, 1.0, 0.0});
       }
       stack(stk, maxrows);
-      const hipStream_t side = side_stream(next_side++);  // consecutive nodes on different streams
-      hipEvent_t ev_us = take_event(), ev_rv = take_event();
-      HQ_CHECK(hipEventRecord(ev_us, st));
-      // The second stream starts on Us while these run: their workspace must not be handed out again
-      // (to the second stream's buffers below) before the join.
-      keep_scratch = true;
+      keep_scratch = true;  // Vs and Us are read again by the inverse blocks
       mm_thin(th);
-      qr_r(vq);
       keep_scratch = false;
-      HQ_CHECK(hipEventRecord(ev_rv, st));
-      {  // second stream: TSQR of Us (from when Us exists), then the core once Rv exists
-        HQ_CHECK(hipStreamWaitEvent(side, ev_us, 0));
-        const hipStream_t main_st = st;
-        st = side;
-        keep_scratch = true;
-        try {
-          recompress_group(rec, ev_rv);
-          // rank of L^{-1}'s block (p, lower) = rank of L's, set here so the join carries it
-          std::vector<IntCopy> rk;
-          for (const Item& it : inner) {
-            const CholTask& T = batch[it.m];
-            rk.push_back(IntCopy{T.Linv->rk(it.c, 1), T.Lf->rk(it.c, 1)});
-          }
-          launch_copy_ints(stage.upload(rk, st), (int)rk.size(), st);
-          ++launches;
-        } catch (...) {
-          st = main_st;
-          keep_scratch = false;
-          throw;
-        }
-        st = main_st;
-        keep_scratch = false;
-        done = take_event();
-        HQ_CHECK(hipEventRecord(done, side));
-      }
-      give_event(ev_us);
-      give_event(ev_rv);
-      // library stream: the Schur factor
       const DevArena::Mark mk_main = scratch.mark();
       for (int i = 0; i < ni; ++i) {
         const Item& it = inner[i];
         const CholTask& T = batch[it.m];
         const Tree* t = T.Z->t;
-        const int p = it.c, b = 2 * p + 2, l = Tree::level(p);
-        const int64_t sb = t->size(b), lb = t->lo[b] - t->lo[p];
-        const int ldc = (int)t->ldf[l], rcap = rcapv[i];
-        const SF& S = it.S;
-        double* W = scratch.get<double>((size_t)sb * rcap);
-        GemmTask g{};  // W = Us Rv^T
-        g.A = Usv[i]; g.lda = ldc; g.B = Rvv[i]; g.ldb = rcap; g.opB = 1; g.C = W; g.ldc = (int)sb;
-        g.m = (int)sb; g.n = rcap; g.np = rsv[i]; g.k = rcap; g.kp = rsv[i]; g.alpha = 1.0; g.beta = 0.0;
-        gw.push_back(g);
-        const int rcS = std::min(kMaxStack, S.cap + rcap);
-        double* Sraw = raw[i] ? Snew[i] : scratch.get<double>((size_t)sb * rcS);
-        int* rsb = raw[i] ? rnew[i] : scratch.get<int>(1);
-        StackTask ss{};
-        ss.dst = Sraw; ss.ld = (int)sb; ss.rows = (int)sb; ss.wcap = raw[i] ? capSb[i] : rcS; ss.wout = rsb; ss.nsrc = 2;
-        ss.fidx = T.fidx;
-        ss.src[0] = {S.p ? S.p + lb : nullptr, S.r, S.ld, S.cap, 1.0};
-        ss.src[1] = {W, rsv[i], (int)sb, rcap, 1.0};
-        stk2.push_back(ss);
-        if (!raw[i]) sym.push_back(SymTask{Sraw, (int)sb, (int)sb, rsb, rcS, Snew[i], (int)sb, rnew[i], capSb[i], thS, T.fidx});
+        const int p = it.c, a = 2 * p + 1, b = 2 * p + 2;
+        const int64_t sa = t->size(a), sb = t->size(b);
+        const int ldc = (int)t->ldf[Tree::level(p)], rcap = rcapv[i];
+        double* G = scratch.get<double>((size_t)rcap * rcap);
+        double* C = scratch.get<double>((size_t)rcap * rcap);
+        int* kc = raw[i] ? rnew[i] : scratch.get<int>(1);  // a leaf child takes Us C as its factor
+        GemmTask g{};  // G = Vs^T Vs
+        g.A = Vsv[i]; g.opA = 1; g.lda = ldc; g.B = Vsv[i]; g.ldb = ldc; g.C = G; g.ldc = rcap;
+        g.m = g.n = rcap; g.mp = g.np = rsv[i]; g.k = (int)sa; g.alpha = 1.0; g.beta = 0.0;
+        gG.push_back(g);
+        PcholTask q{};
+        q.G = G; q.ldg = rcap; q.rp = rsv[i]; q.ep = T.Z->rk(p, 1); q.C = C; q.ldc = rcap; q.kout = kc; q.kcap = rcap;
+        q.work = rcap > PCH_REG ? scratch.get<double>((size_t)rcap * (rcap + 1) / 2) : nullptr;
+        q.fidx = T.fidx;
+        pc.push_back(q);
+        double* out = raw[i] ? Snew[i] : scratch.get<double>((size_t)sb * rcap);
+        GemmTask c{};  // Us C
+        c.A = Usv[i]; c.lda = ldc; c.B = C; c.ldb = rcap; c.C = out; c.ldc = (int)sb;
+        c.m = (int)sb; c.n = rcap; c.np = kc; c.k = rcap; c.kp = rsv[i]; c.alpha = 1.0; c.beta = 0.0;
+        gC.push_back(c);
+        if (!raw[i]) {
+          SymTask y{out, (int)sb, (int)sb, kc, rcap, Snew[i], (int)sb, rnew[i], capSb[i], thS, T.fidx};
+          y.keep_below = keepv[i];
+          sym.push_back(y);
+        }
       }
-      gemm(gw, maxsb, rmax);
-      stack(stk2, maxsb);
+      gemm(gG, rmax, rmax);
+      launch_pchol(stage.upload(pc, st), (int)pc.size(), d_flag, st);
+      ++launches;
+      gemm(gC, maxsb, rmax);
       compress_sym(sym);
       scratch.rewind(mk_main);
     }
@@ -1285,25 +1314,51 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       right.push_back(Item{it.m, 2 * it.c + 2, SF{Snew[i], (int)t->size(2 * it.c + 2), rnew[i], capSb[i]}});
     }
     dfs(right);
-    HQ_CHECK(hipStreamWaitEvent(st, done, 0));  // L_ba recompressed
-    give_event(done);
-    // inverse blocks
+    // inverse blocks from the untruncated factors: U = -L_bb^{-1} Us, V = L_aa^{-T} Vs, rank = width
     const DevArena::Mark mk2 = scratch.mark();
     std::vector<ThinTask> th;
-    for (const Item& it : inner) {
+    std::vector<IntCopy> rk;
+    for (int i = 0; i < ni; ++i) {
+      const Item& it = inner[i];
       const CholTask& T = batch[it.m];
       const int p = it.c, a = 2 * p + 1, b = 2 * p + 2, l = Tree::level(p);
       const int ldc = (int)T.Z->t->ldf[l];
-      th.push_back(ThinTask{view(*T.Linv), b, T.Lf->U(p, 1), ldc, T.Linv->U(p, 1), ldc, T.Lf->rk(p, 1), T.Lf->cap[l], -1.0, 0.0});
-      th.push_back(ThinTask{view(*T.Linv, true), a, T.Lf->V(p, 1), ldc, T.Linv->V(p, 1), ldc, T.Lf->rk(p, 1), T.Lf->cap[l], 1.0, 0.0});
+      th.push_back(ThinTask{view(lw[it.m]), b, Usv[i], ldc, T.Lf->U(p, 1), ldc, rsv[i], rcapv[i], -1.0, 0.0});
+      th.push_back(ThinTask{view(lw[it.m], true), a, Vsv[i], ldc, T.Lf->V(p, 1), ldc, rsv[i], rcapv[i], 1.0, 0.0});
+      rk.push_back(IntCopy{T.Lf->rk(p, 1), rsv[i]});
     }
     mm_thin(th);
+    launch_copy_ints(stage.upload(rk, st), (int)rk.size(), st);
+    ++launches;
     scratch.rewind(mk2);
     scratch.rewind(mk);
   };
   std::vector<Item> roots;
   for (int m = 0; m < (int)batch.size(); ++m) roots.push_back(Item{m, 0, SF{nullptr, 1, d_zero, 0}});
   dfs(roots);
+  // truncated recompression of every inverse block, all levels and members at once
+  std::vector<RecTask> rec;
+  for (const CholTask& T : batch) {
+    const Tree* t = T.Z->t;
+    for (int p = 0; p < t->ninternal; ++p) {
+      const int l = Tree::level(p), ld = (int)t->ldf[l];
+      RecTask r{};
+      r.Us = T.Lf->U(p, 1); r.ldus = ld; r.m = (int)t->size(2 * p + 2);
+      r.Vs = T.Lf->V(p, 1); r.ldvs = ld; r.n = (int)t->size(2 * p + 1);
+      r.r = T.Lf->rk(p, 1); r.rcap = T.Lf->cap[l];
+      r.U = T.Linv->U(p, 1); r.V = T.Linv->V(p, 1); r.ldu = r.ldv = ld; r.rank = T.Linv->rk(p, 1);
+      r.kcap = T.Linv->cap[l]; r.thresh = tol; r.fidx = T.fidx;
+      rec.push_back(r);
+    }
+  }
+  recompress(rec);
+}
+
+std::vector<int> Engine::chol_work_caps(const Tree& t, const std::vector<int>& capZ, int capS) const {
+  std::vector<int> c(t.L, 1);
+  for (int l = 0; l < t.L && l < (int)capZ.size(); ++l)
+    c[l] = std::min(kMaxStack, capZ[l] + std::max(capS, schur_keep));
+  return c;
 }
 
 // ---------------------------------------------------------------------------------------------

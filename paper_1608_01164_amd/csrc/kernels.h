@@ -43,7 +43,26 @@ struct GemmTask {
 };
 // K ranges of a product whose k is a true dimension (no device count): a function of k alone, so
 // that a task's result never depends on what else shares its launch or on any capacity.
-inline int gemm_splits(int k) { return k < 512 ? 1 : (k / 256 < 32 ? k / 256 : 32); }
+// Tile shapes and thresholds picked by the project's autotuner: read once from the table next to the
+// library (tuning.txt, "key value" lines) or the file named by HQ_TUNING; these are the defaults.
+struct Tuning {
+  int qr_tile_rows = 1024;  // rows of a TSQR row tile (stage 0)
+  int split_min_k = 512;    // split-K GEMM only for k >= this
+  int split_chunk = 256;    // rows of K per split
+  int split_max = 32;       // most splits
+  int schur_keep = 96;      // H-Cholesky: Schur factors up to this width are carried uncompressed
+  bool valid() const {
+    return qr_tile_rows >= 32 && qr_tile_rows <= 8192 && split_min_k >= 64 && split_chunk >= 32 && split_max >= 1 &&
+           split_max <= 128 && schur_keep >= 0 && schur_keep <= 1024;
+  }
+};
+Tuning& tuning();
+inline int gemm_splits(int k) {
+  const Tuning& t = tuning();
+  if (k < t.split_min_k) return 1;
+  const int s = k / t.split_chunk;
+  return s < 1 ? 1 : (s < t.split_max ? s : t.split_max);
+}
 
 // dst[:, off_s : off_s + w_s] = scale_s * src_s[:, 0 : w_s] for s = 0..nsrc-1, off_s = sum of previous widths.
 // Widest stack of factor columns the recompression kernels take (TSQR and core SVD limits).
@@ -102,7 +121,28 @@ struct SvdTask {
   // stacked columns): the decomposition runs on the leading min(r, rlim) square, and rows from
   // there to r of Wk and Jk come out zero.
   int rlim = 1 << 30;
+  // A core of live order r <= keep_below is kept as it is: Jk = the first r columns of the identity,
+  // k' = r (Wk and sig are not written).  0: always decompose.
+  int keep_below = 0;
 };
+
+// Cholesky M = C C^T (C lower, r x r) of a small symmetric positive definite M = G + E, where G is a
+// Gram matrix (both triangles stored) and E = 1 on the diagonal from index *ep on, 0 before.  The
+// H-Cholesky's M is positive definite by construction (see the engine), so no pivoting is needed; a
+// non-positive pivot sets bit 1 of the status word and stops.  work: r(r+1)/2 doubles, needed only
+// when r exceeds PCH_REG (the triangle is kept in registers up to that order); r <= kcap.
+constexpr int PCH_REG = 252;
+struct PcholTask {
+  const double* G;
+  const int* rp;    // live order r
+  const int* ep;    // first diagonal index that gets + 1 (null: none)
+  double* C;
+  int* kout;        // receives r (or the step of a breakdown)
+  double* work;
+  int ldg, ldc, kcap;
+  int fidx;
+};
+void launch_pchol(const PcholTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.
 struct LeafTask {

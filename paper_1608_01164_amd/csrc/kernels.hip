@@ -1685,6 +1685,16 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
   extern __shared__ __align__(16) unsigned char svd_raw[];
   const SvdTask Tk = tasks[blockIdx.x];
   int rfull = uniform(*Tk.rp);
+  if (rfull <= Tk.keep_below) {  // kept as it is: Jk = I (r columns)
+    const int k = rfull < Tk.kcap ? rfull : Tk.kcap;
+    if (rfull > Tk.kcap && threadIdx.x == 0) atomicOr(flag + Tk.fidx, 1);
+    for (int idx = threadIdx.x; idx < Tk.ld * k; idx += SVD_THREADS) {
+      const int i = idx % Tk.ld, c = idx / Tk.ld;
+      Tk.Jk[i + (size_t)c * Tk.ld] = i == c ? 1.0 : 0.0;
+    }
+    if (threadIdx.x == 0) *Tk.kout = k < 0 ? 0 : k;
+    return;
+  }
   if (rfull > SVD_RMAX) rfull = SVD_RMAX;
   const int r = rfull < Tk.rlim ? rfull : Tk.rlim;
   if (r <= 0) {
@@ -1736,6 +1746,184 @@ void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStr
   else
     HQ_TIMED(K_SVD, s, hipLaunchKernelGGL(k_svd<double>, dim3(ntasks), dim3(SVD_THREADS), SVD_DYN_BYTES, s, d_tasks,
                                           flag));
+}
+
+// ----------------------------------------------------------------------------------------------
+// Cholesky of the small SPD matrix M = G + E (one workgroup), C = lower factor, M = C C^T.  The lower
+// triangle is kept as 4 x 4 tiles in registers, TPT tiles per thread (order up to PCH_REG), or, above
+// that, packed (entry (i, k), i >= k, at i (i + 1) / 2 + k) in the task's workspace.  Step j: column
+// j is final (its owners updated it in step j - 1 and published it in LDS, or it sits in the
+// workspace); after one barrier every thread writes its share of column j of C and applies the
+// rank-one update -M(i, j) M(k, j) / M(j, j) to its entries right of column j; the owners of column
+// j + 1 publish it as soon as their own update is done.  One barrier per step, no pivot search.
+// ----------------------------------------------------------------------------------------------
+constexpr int PCH_THREADS = 1024;
+static __device__ __forceinline__ int pk(int i, int k) { return i >= k ? i * (i + 1) / 2 + k : k * (k + 1) / 2 + i; }
+// (x, y), x >= y, of packed index q = x (x + 1) / 2 + y
+static __device__ __forceinline__ void unpack_lower(int q, int& x, int& y) {
+  x = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+  if ((x + 1) * (x + 2) / 2 <= q) ++x;
+  if (x * (x + 1) / 2 > q) --x;
+  y = q - x * (x + 1) / 2;
+}
+static __device__ __forceinline__ double gram_entry(const PcholTask& T, int i, int k, int e0) {
+  double v = T.G[i + (size_t)k * T.ldg];
+  if (i == k && i >= e0) v += 1.0;
+  return v;
+}
+
+template <int TPT>
+static __device__ void spd_chol_regs(const PcholTask& T, int r, double* colbuf, int* flag) {
+  const int tid = threadIdx.x;
+  const int nb = (r + 3) / 4, ntile = nb * (nb + 1) / 2;
+  const int e0 = T.ep ? uniform(*T.ep) : r;
+  double a[TPT][4][4];
+  int bi[TPT], bk[TPT];
+  double* colp[2] = {colbuf, colbuf + PCH_REG};
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const int q = tid + t * PCH_THREADS;
+    int x = -1, y = -1;
+    if (q < ntile) unpack_lower(q, x, y);
+    bi[t] = x;
+    bk[t] = y;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * x + u, k = 4 * y + v;
+        a[t][u][v] = (x >= 0 && i < r && k < r && i >= k) ? gram_entry(T, i, k, e0) : 0.0;
+      }
+    if (y == 0) {  // publish column 0 (tiles of block column 0 hold rows 4x .. 4x + 3 of it)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * x + u < r) colp[0][4 * x + u] = a[t][u][0];
+    }
+  }
+  unsigned long long flops = 0;
+  int j = 0;
+  for (; j < r; ++j) {
+    __syncthreads();
+    const double* cj = colp[j & 1];
+    double* cn = colp[(j + 1) & 1];
+    const double d = cj[j];
+    if (!(d > 0.0)) {  // M is positive definite by construction; report a breakdown, stop
+      if (tid == 0) atomicOr(flag + T.fidx, 2);
+      break;
+    }
+    const double inv = 1.0 / d, sinv = 1.0 / sqrt(d);
+    double* Cj = T.C + (size_t)j * T.ldc;
+    for (int i = tid; i < r; i += PCH_THREADS) Cj[i] = i >= j ? cj[i] * sinv : 0.0;
+    const int bj = (j + 1) >> 2, cjn = (j + 1) & 3;  // tile column holding column j + 1
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      if (bi[t] < 0 || 4 * bi[t] + 3 <= j) continue;  // rows all at or above j: nothing left to update
+      double cu[4], cv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = 4 * bi[t] + u, k = 4 * bk[t] + u;
+        cu[u] = (i > j && i < r) ? cj[i] * inv : 0.0;
+        cv[u] = (k > j && k < r) ? cj[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[t][u][v] -= cu[u] * cv[v];
+      if (bk[t] == bj && j + 1 < r) {  // publish column j + 1 (selected by comparison: static indices)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (v == cjn) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int i = 4 * bi[t] + u;
+              if (i >= j + 1 && i < r) cn[i] = a[t][u][v];
+            }
+          }
+      }
+    }
+    if (tid == 0) {
+      const unsigned long long m = (unsigned long long)(r - j);
+      flops += m * m + m;
+    }
+  }
+  if (tid == 0) {
+    *T.kout = j;
+    count_work(K_POTRF, flops, 8ull * r * (r + j));
+  }
+}
+
+// Orders above PCH_REG: the packed triangle in the task's workspace, entries spread flat.
+static __device__ void spd_chol_global(const PcholTask& T, int r, double* A, int* flag) {
+  const int tid = threadIdx.x;
+  const int e0 = T.ep ? uniform(*T.ep) : r;
+  const int np0 = r * (r + 1) / 2;
+  for (int q = tid; q < np0; q += PCH_THREADS) {
+    int i, k;
+    unpack_lower(q, i, k);
+    A[q] = gram_entry(T, i, k, e0);
+  }
+  unsigned long long flops = 0;
+  int j = 0;
+  for (; j < r; ++j) {
+    __syncthreads();
+    const double d = A[pk(j, j)];
+    if (!(d > 0.0)) {
+      if (tid == 0) atomicOr(flag + T.fidx, 2);
+      break;
+    }
+    const double inv = 1.0 / d, sinv = 1.0 / sqrt(d);
+    double* Cj = T.C + (size_t)j * T.ldc;
+    for (int i = tid; i < r; i += PCH_THREADS) Cj[i] = i >= j ? A[pk(i, j)] * sinv : 0.0;
+    // trailing triangle: rows and columns j + 1 .. r - 1, packed relative to j + 1
+    const int m = r - j - 1, npair = m * (m + 1) / 2;
+    for (int q = tid; q < npair; q += PCH_THREADS) {
+      int x, y;
+      unpack_lower(q, x, y);
+      const int i = j + 1 + x, k = j + 1 + y;
+      A[pk(i, k)] -= A[pk(i, j)] * A[pk(k, j)] * inv;
+    }
+    if (tid == 0) flops += (unsigned long long)(m + 1) * (m + 1);
+  }
+  if (tid == 0) {
+    *T.kout = j;
+    count_work(K_POTRF, flops, 8ull * r * (r + j));
+  }
+}
+
+__global__ __launch_bounds__(PCH_THREADS) void k_pchol(const PcholTask* __restrict__ tasks, int* flag) {
+  __shared__ double colbuf[2 * PCH_REG];
+  const PcholTask T = tasks[blockIdx.x];
+  const int r = uniform(*T.rp);
+  if (r <= 0) {
+    if (threadIdx.x == 0) *T.kout = 0;
+    return;
+  }
+  if (r > T.kcap || r > kMaxStack) {
+    if (threadIdx.x == 0) {
+      atomicOr(flag + T.fidx, r > kMaxStack ? 4 : 1);
+      *T.kout = 0;
+    }
+    return;
+  }
+  if (r <= 176)
+    spd_chol_regs<1>(T, r, colbuf, flag);
+  else if (r <= PCH_REG)
+    spd_chol_regs<2>(T, r, colbuf, flag);
+  else if (T.work)
+    spd_chol_global(T, r, T.work, flag);
+  else if (threadIdx.x == 0) {  // no workspace for an order above the register path: report
+    atomicOr(flag + T.fidx, 8);
+    *T.kout = 0;
+  }
+}
+
+void launch_pchol(const PcholTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
+  if (ntasks <= 0) return;
+  constexpr size_t dyn = 0;
+  for (int t0 = 0; t0 < ntasks; t0 += 65535) {
+    const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+    HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_pchol, dim3(nt), dim3(PCH_THREADS), dyn, s, d_tasks + t0, flag));
+  }
 }
 
 // ----------------------------------------------------------------------------------------------

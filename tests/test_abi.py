@@ -70,3 +70,15 @@ def test_structured_qr_host_vs_oracle(n, b, leaf):
     # the replays run as parallel tasks: the result must not depend on their scheduling
     R1, R2, _ = hq.test_q_dense_host(ab, b, 0.1, 2.3, leaf)
     assert np.array_equal(R1, Q1) and np.array_equal(R2, Q2)
+
+
+def test_graph_option_is_refused_while_disabled():
+    """opts.graph returns HQ_ERR_UNSUPPORTED (checked before any device use)."""
+    import ctypes
+    import paper_1608_01164_amd as hq
+    from paper_1608_01164_amd.binding import _opts
+    o = _opts(graph=True)
+    out = ctypes.c_void_p()
+    st = hq.lib().spectral_projector(ctypes.c_void_p(1), 16, 1, 2, 0.0, ctypes.byref(o), None, ctypes.byref(out), None)
+    assert st == -4 and not out.value
+    assert b"disabled" in hq.lib().hq_last_error()

@@ -62,3 +62,24 @@ def test_batch_member_equals_single_call():
         # the same arithmetic, only grouped into shared launches: tasks are independent, so the
         # results agree (in practice bit for bit; 1e-12 leaves room for capacity-independent reorderings)
         assert np.abs(Dj - Db).max() <= 1e-12, j
+
+
+@pytest.mark.skip(reason="opts.graph is disabled: the stream-capture path ended its first GPU run in a host "
+                         "segmentation fault whose cause has not been found; the option returns "
+                         "HQ_ERR_UNSUPPORTED until it is")
+@pytest.mark.parametrize("n,b,leaf", [(4096, 8, 128), (3000, 3, 64)])
+def test_graph_iterations_are_bitwise_identical(n, b, leaf):
+    """Each Cholesky iteration launched as one captured HIP graph (opts.graph) replays the same
+    kernels with the same arguments as the launches issued one by one: the projector is the same bit
+    for bit, on repeated calls too."""
+    import torch
+    ab = w.banded_normal(n, b, 22)
+    mu, _ = hq.shift_for_count(ab, b, n // 2)
+    band = torch.from_numpy(np.ascontiguousarray(ab)).cuda()
+    P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=1e-10)
+    ref = _dense(_export(P))
+    assert info["graphs"] == 0
+    for _ in range(2):
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=1e-10, graph=True)
+        assert info["graphs"] == info["iters"] - 1 + info["redo_count"] and info["graph_nodes"] > 0
+        assert np.array_equal(_dense(_export(P)), ref)

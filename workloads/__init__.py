@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "band_empty", "tridiag_uniform", "banded_normal", "tridiag_metallic", "laplacian",
     "batched_banded", "prescribed_spectrum", "band_to_dense", "dense_to_band",
-    "split_gap_spectrum",
+    "split_gap_spectrum", "prescribed_spectrum_band", "build_native",
 ]
 
 
@@ -176,3 +176,41 @@ def prescribed_spectrum(lams, b: int) -> np.ndarray:
                 break
     # everything outside the band is rounding noise now
     return dense_to_band(A, b)
+
+
+# ---- Sec. 6.1 generator in band storage (C, O(n^2) flops) -------------------------------------
+
+import ctypes as _ct
+import os as _os
+import subprocess as _sp
+
+_HERE = _os.path.dirname(_os.path.abspath(__file__))
+_SO = _os.path.join(_HERE, "_prescribed.so")
+_lib = None
+
+
+def build_native(force: bool = False) -> str:
+    """Compile prescribed.c into workloads/_prescribed.so with gcc."""
+    src = _os.path.join(_HERE, "prescribed.c")
+    if not force and _os.path.exists(_SO) and _os.path.getmtime(_SO) >= _os.path.getmtime(src):
+        return _SO
+    tmp = _SO + ".tmp%d" % _os.getpid()
+    _sp.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+    _os.replace(tmp, _SO)
+    return _SO
+
+
+def prescribed_spectrum_band(lams, b: int) -> np.ndarray:
+    """The Sec. 6.1 construction (same rotations as ``prescribed_spectrum``) carried out in band storage
+    with one extra diagonal for the bulge: O(n^2) flops, for orders in the tens of thousands."""
+    global _lib
+    if _lib is None:
+        _lib = _ct.CDLL(build_native())
+        _lib.prescribed_band.restype = _ct.c_int
+        _lib.prescribed_band.argtypes = [_ct.c_int64, _ct.c_int, _ct.c_void_p, _ct.c_void_p, _ct.c_int64]
+    lams = np.ascontiguousarray(lams, dtype=np.float64)
+    n = lams.size
+    ab = band_empty(n, b)
+    if _lib.prescribed_band(n, int(b), lams.ctypes.data, ab.ctypes.data, b + 1) != 0:
+        raise MemoryError("prescribed_band: workspace")
+    return ab
