@@ -1071,8 +1071,8 @@ void Engine::product(const std::vector<ProdTask>& batch) {
 // ---------------------------------------------------------------------------------------------
 // Recursive Cholesky (left subtree, off-diagonal factor, Schur update, right subtree).  The
 // Schur complement updates from all ancestors are carried lazily as one symmetric low-rank
-// factor S (Z_bb - L_ba L_ba^T restricted = Z_bb - S S^T), compressed at every right turn.
-// Alongside, the inverse factor is assembled bottom-up:
+// factor S (Z_bb - L_ba L_ba^T restricted = Z_bb - S S^T), compressed at a right turn once it is
+// wider than schur_keep columns.  Alongside, the inverse factor is assembled bottom-up:
 //   [L^-1]_aa = L_aa^-1, [L^-1]_bb = L_bb^-1, [L^-1]_ba = -(L_bb^-1 U)(L_aa^-T V)^T for L_ba = U V^T.
 // A batch runs the recursions of all members in lockstep: a step handles the members' nodes at
 // the same position of the depth-first order together, leaves and internal nodes alike.
@@ -1230,7 +1230,7 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       std::vector<StackTask> stk;
       std::vector<ThinTask> th;
       std::vector<GemmTask> gG, gC;
-      std::vector<PcholTask> pc;
+      std::vector<SpdCholTask> pc;
       std::vector<SymTask> sym;
       int maxrows = 1, maxsb = 1, rmax = 1;
       for (int i = 0; i < ni; ++i) {
@@ -1283,9 +1283,9 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         g.A = Vsv[i]; g.opA = 1; g.lda = ldc; g.B = Vsv[i]; g.ldb = ldc; g.C = G; g.ldc = rcap;
         g.m = g.n = rcap; g.mp = g.np = rsv[i]; g.k = (int)sa; g.alpha = 1.0; g.beta = 0.0;
         gG.push_back(g);
-        PcholTask q{};
+        SpdCholTask q{};
         q.G = G; q.ldg = rcap; q.rp = rsv[i]; q.ep = T.Z->rk(p, 1); q.C = C; q.ldc = rcap; q.kout = kc; q.kcap = rcap;
-        q.work = rcap > PCH_REG ? scratch.get<double>((size_t)rcap * (rcap + 1) / 2) : nullptr;
+        q.work = rcap > SPD_REG ? scratch.get<double>((size_t)rcap * (rcap + 1) / 2) : nullptr;
         q.fidx = T.fidx;
         pc.push_back(q);
         double* out = raw[i] ? Snew[i] : scratch.get<double>((size_t)sb * rcap);
@@ -1300,7 +1300,7 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         }
       }
       gemm(gG, rmax, rmax);
-      launch_pchol(stage.upload(pc, st), (int)pc.size(), d_flag, st);
+      launch_spd_chol(stage.upload(pc, st), (int)pc.size(), d_flag, st);
       ++launches;
       gemm(gC, maxsb, rmax);
       compress_sym(sym);

@@ -130,9 +130,9 @@ struct SvdTask {
 // Gram matrix (both triangles stored) and E = 1 on the diagonal from index *ep on, 0 before.  The
 // H-Cholesky's M is positive definite by construction (see the engine), so no pivoting is needed; a
 // non-positive pivot sets bit 1 of the status word and stops.  work: r(r+1)/2 doubles, needed only
-// when r exceeds PCH_REG (the triangle is kept in registers up to that order); r <= kcap.
-constexpr int PCH_REG = 252;
-struct PcholTask {
+// when r exceeds SPD_REG (the triangle is kept in registers up to that order); r <= kcap.
+constexpr int SPD_REG = 252;
+struct SpdCholTask {
   const double* G;
   const int* rp;    // live order r
   const int* ep;    // first diagonal index that gets + 1 (null: none)
@@ -142,7 +142,7 @@ struct PcholTask {
   int ldg, ldc, kcap;
   int fidx;
 };
-void launch_pchol(const PcholTask* d_tasks, int ntasks, int* flag, hipStream_t s);
+void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int* flag, hipStream_t s);
 
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.
 struct LeafTask {

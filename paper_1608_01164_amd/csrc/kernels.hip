@@ -1750,14 +1750,14 @@ void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStr
 
 // ----------------------------------------------------------------------------------------------
 // Cholesky of the small SPD matrix M = G + E (one workgroup), C = lower factor, M = C C^T.  The lower
-// triangle is kept as 4 x 4 tiles in registers, TPT tiles per thread (order up to PCH_REG), or, above
+// triangle is kept as 4 x 4 tiles in registers, TPT tiles per thread (order up to SPD_REG), or, above
 // that, packed (entry (i, k), i >= k, at i (i + 1) / 2 + k) in the task's workspace.  Step j: column
 // j is final (its owners updated it in step j - 1 and published it in LDS, or it sits in the
 // workspace); after one barrier every thread writes its share of column j of C and applies the
 // rank-one update -M(i, j) M(k, j) / M(j, j) to its entries right of column j; the owners of column
 // j + 1 publish it as soon as their own update is done.  One barrier per step, no pivot search.
 // ----------------------------------------------------------------------------------------------
-constexpr int PCH_THREADS = 1024;
+constexpr int SPD_THREADS = 1024;
 static __device__ __forceinline__ int pk(int i, int k) { return i >= k ? i * (i + 1) / 2 + k : k * (k + 1) / 2 + i; }
 // (x, y), x >= y, of packed index q = x (x + 1) / 2 + y
 static __device__ __forceinline__ void unpack_lower(int q, int& x, int& y) {
@@ -1766,23 +1766,23 @@ static __device__ __forceinline__ void unpack_lower(int q, int& x, int& y) {
   if (x * (x + 1) / 2 > q) --x;
   y = q - x * (x + 1) / 2;
 }
-static __device__ __forceinline__ double gram_entry(const PcholTask& T, int i, int k, int e0) {
+static __device__ __forceinline__ double gram_entry(const SpdCholTask& T, int i, int k, int e0) {
   double v = T.G[i + (size_t)k * T.ldg];
   if (i == k && i >= e0) v += 1.0;
   return v;
 }
 
 template <int TPT>
-static __device__ void spd_chol_regs(const PcholTask& T, int r, double* colbuf, int* flag) {
+static __device__ void spd_chol_regs(const SpdCholTask& T, int r, double* colbuf, int* flag) {
   const int tid = threadIdx.x;
   const int nb = (r + 3) / 4, ntile = nb * (nb + 1) / 2;
   const int e0 = T.ep ? uniform(*T.ep) : r;
   double a[TPT][4][4];
   int bi[TPT], bk[TPT];
-  double* colp[2] = {colbuf, colbuf + PCH_REG};
+  double* colp[2] = {colbuf, colbuf + SPD_REG};
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
-    const int q = tid + t * PCH_THREADS;
+    const int q = tid + t * SPD_THREADS;
     int x = -1, y = -1;
     if (q < ntile) unpack_lower(q, x, y);
     bi[t] = x;
@@ -1813,7 +1813,7 @@ static __device__ void spd_chol_regs(const PcholTask& T, int r, double* colbuf, 
     }
     const double inv = 1.0 / d, sinv = 1.0 / sqrt(d);
     double* Cj = T.C + (size_t)j * T.ldc;
-    for (int i = tid; i < r; i += PCH_THREADS) Cj[i] = i >= j ? cj[i] * sinv : 0.0;
+    for (int i = tid; i < r; i += SPD_THREADS) Cj[i] = i >= j ? cj[i] * sinv : 0.0;
     const int bj = (j + 1) >> 2, cjn = (j + 1) & 3;  // tile column holding column j + 1
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
@@ -1852,12 +1852,12 @@ static __device__ void spd_chol_regs(const PcholTask& T, int r, double* colbuf, 
   }
 }
 
-// Orders above PCH_REG: the packed triangle in the task's workspace, entries spread flat.
-static __device__ void spd_chol_global(const PcholTask& T, int r, double* A, int* flag) {
+// Orders above SPD_REG: the packed triangle in the task's workspace, entries spread flat.
+static __device__ void spd_chol_global(const SpdCholTask& T, int r, double* A, int* flag) {
   const int tid = threadIdx.x;
   const int e0 = T.ep ? uniform(*T.ep) : r;
   const int np0 = r * (r + 1) / 2;
-  for (int q = tid; q < np0; q += PCH_THREADS) {
+  for (int q = tid; q < np0; q += SPD_THREADS) {
     int i, k;
     unpack_lower(q, i, k);
     A[q] = gram_entry(T, i, k, e0);
@@ -1873,10 +1873,10 @@ static __device__ void spd_chol_global(const PcholTask& T, int r, double* A, int
     }
     const double inv = 1.0 / d, sinv = 1.0 / sqrt(d);
     double* Cj = T.C + (size_t)j * T.ldc;
-    for (int i = tid; i < r; i += PCH_THREADS) Cj[i] = i >= j ? A[pk(i, j)] * sinv : 0.0;
+    for (int i = tid; i < r; i += SPD_THREADS) Cj[i] = i >= j ? A[pk(i, j)] * sinv : 0.0;
     // trailing triangle: rows and columns j + 1 .. r - 1, packed relative to j + 1
     const int m = r - j - 1, npair = m * (m + 1) / 2;
-    for (int q = tid; q < npair; q += PCH_THREADS) {
+    for (int q = tid; q < npair; q += SPD_THREADS) {
       int x, y;
       unpack_lower(q, x, y);
       const int i = j + 1 + x, k = j + 1 + y;
@@ -1890,9 +1890,9 @@ static __device__ void spd_chol_global(const PcholTask& T, int r, double* A, int
   }
 }
 
-__global__ __launch_bounds__(PCH_THREADS) void k_pchol(const PcholTask* __restrict__ tasks, int* flag) {
-  __shared__ double colbuf[2 * PCH_REG];
-  const PcholTask T = tasks[blockIdx.x];
+__global__ __launch_bounds__(SPD_THREADS) void k_spd_chol(const SpdCholTask* __restrict__ tasks, int* flag) {
+  __shared__ double colbuf[2 * SPD_REG];
+  const SpdCholTask T = tasks[blockIdx.x];
   const int r = uniform(*T.rp);
   if (r <= 0) {
     if (threadIdx.x == 0) *T.kout = 0;
@@ -1907,7 +1907,7 @@ __global__ __launch_bounds__(PCH_THREADS) void k_pchol(const PcholTask* __restri
   }
   if (r <= 176)
     spd_chol_regs<1>(T, r, colbuf, flag);
-  else if (r <= PCH_REG)
+  else if (r <= SPD_REG)
     spd_chol_regs<2>(T, r, colbuf, flag);
   else if (T.work)
     spd_chol_global(T, r, T.work, flag);
@@ -1917,12 +1917,12 @@ __global__ __launch_bounds__(PCH_THREADS) void k_pchol(const PcholTask* __restri
   }
 }
 
-void launch_pchol(const PcholTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
+void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
   constexpr size_t dyn = 0;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_pchol, dim3(nt), dim3(PCH_THREADS), dyn, s, d_tasks + t0, flag));
+    HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_spd_chol, dim3(nt), dim3(SPD_THREADS), dyn, s, d_tasks + t0, flag));
   }
 }
 

@@ -82,3 +82,24 @@ def test_graph_option_is_refused_while_disabled():
     st = hq.lib().spectral_projector(ctypes.c_void_p(1), 16, 1, 2, 0.0, ctypes.byref(o), None, ctypes.byref(out), None)
     assert st == -4 and not out.value
     assert b"disabled" in hq.lib().hq_last_error()
+
+
+def test_tuning_table_is_read_and_checked():
+    """The committed autotuner table is what the library uses; out-of-range values are refused."""
+    import os
+    import paper_1608_01164_amd as hq
+    t = hq.tuning()
+    path = os.path.join(os.path.dirname(hq.__file__), "tuning.txt")
+    assert os.path.samefile(t["source"], path)
+    table = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            table[k] = int(v)
+    assert all(t[k] == v for k, v in table.items())
+    with pytest.raises(hq.HQError):
+        hq.set_tuning(qr_tile_rows=8)
+    assert hq.tuning()["qr_tile_rows"] == t["qr_tile_rows"]   # a refused table leaves the old one
+    old = hq.set_tuning(schur_keep=t["schur_keep"] + 1)
+    assert hq.tuning()["schur_keep"] == t["schur_keep"] + 1 and hq.tuning()["source"] == "hq_tuning_set"
+    hq.set_tuning(**{k: v for k, v in old.items() if k != "source"})
