@@ -614,6 +614,130 @@ static __device__ void householder_regs(const double* src, int lds, T* out, int 
   if (tid == 0) count_work(K_QR, flops, 0);
 }
 
+// Tree step of the TSQR for two stacked triangles: R_a (r x r, upper) over R_b (rb x r, upper
+// trapezoidal, rb <= r), factored without touching the zeros.  Step j's reflector has the support
+// {row j of R_a} U {rows 0..min(j, rb - 1) of R_b}: it is formed from R_a(j, j) and the top of
+// column j of R_b, and changes row j of R_a and those rows of R_b right of column j (2(j + 2)(r - j)
+// multiply-adds instead of 2(2r - j)(r - j) for the dense stack).  R_a sits in LDS as a packed upper
+// triangle (row j from j (2r - j + 1) / 2, columns j .. r - 1); R_b in registers, column c in the
+// 16-lane group c % 64 (slot c / 64), rows sl + 16 e in lane sl.  One barrier per step.  The result
+// (the new R_a) replaces slot a; columns near underflow are rescaled as in householder_regs.
+template <typename T, int EM, int CPG>
+static __device__ void householder_tri_pair(const T* A, const T* B, int ld, T* out, int r, int rb, T* dyn) {
+  T* Ra = dyn;                                   // packed upper triangle, r (r + 1) / 2 entries
+  T(*vbuf)[16 * EM] = reinterpret_cast<T(*)[16 * EM]>(dyn + (size_t)r * (r + 1) / 2);
+  T* sbuf = dyn + (size_t)r * (r + 1) / 2 + 2 * 16 * EM;  // [2]: v0, tau per parity
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6), sub = lane >> 4, sl = lane & 15;
+  const int g = tid >> 4;
+  auto off = [r](int j) { return j * (2 * r - j + 1) / 2; };
+  for (int idx = tid; idx < r * r; idx += QR_THREADS) {
+    const int i = idx % r, c = idx / r;
+    if (i <= c) Ra[off(i) + (c - i)] = A[i + (size_t)c * ld];
+  }
+  T x[CPG][EM];
+#pragma unroll
+  for (int k = 0; k < CPG; ++k)
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+      const int c = 64 * k + g, i = sl + 16 * e;
+      x[k][e] = (c < r && i < rb && i <= c) ? B[i + (size_t)c * ld] : (T)0;
+    }
+  __syncthreads();
+  unsigned long long flops = 0;
+  for (int j = 0; j < r; ++j) {
+    const int b = j & 1, go = j & 63, kj = j >> 6;
+    const int jb = j < rb - 1 ? j : rb - 1;  // last row of R_b in the reflector's support
+    if (wave == (go >> 2)) {
+      const bool owner = sub == (go & 3);
+#pragma unroll
+      for (int k = 0; k < CPG; ++k)
+        if (k == kj) {  // wave-uniform
+          const T x0 = Ra[off(j)];
+          T s = 0, am = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) {
+            const T v = (sl + 16 * e <= jb) ? x[k][e] : (T)0;
+            s += v * v;
+            am = fmax(am, fabs(v));
+          }
+          s = row_sum(s);
+          am = fmax(row_max(am), fabs(x0));
+          const bool scaled = s < Prec<T>::scale_below && am > (T)0;
+          T sc1 = 1, sc2 = 1, unscale = 1;
+          if (scaled) {
+            constexpr int M = Prec<T>::max_shift;
+            const int ex = ilogb(am);
+            sc1 = ldexp((T)1, -ex > M ? M : -ex);
+            sc2 = ldexp((T)1, -ex > M ? -ex - M : 0);
+            unscale = ldexp((T)1, ex);
+          }
+          T vv[EM];
+          T ss = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) {
+            const T v = (sl + 16 * e <= jb) ? x[k][e] : (T)0;
+            vv[e] = scaled ? (v * sc1) * sc2 : v;
+            ss += vv[e] * vv[e];
+          }
+          T x0s = x0;
+          if (scaled) {
+            x0s = (x0 * sc1) * sc2;
+            s = row_sum(ss);
+          }
+          T tau = 0, v0 = 0, rjj = x0;
+          if (s != (T)0) {
+            const T nrm = sqrt(x0s * x0s + s);
+            const T beta = x0s >= 0 ? -nrm : nrm;
+            v0 = x0s - beta;
+            tau = (T)1 / (nrm * (nrm + fabs(x0s)));
+            rjj = beta * unscale;
+          }
+          if (owner) {
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+              vbuf[b][sl + 16 * e] = vv[e];
+              if (tau != (T)0 && sl + 16 * e <= jb) x[k][e] = 0;  // annihilated
+            }
+            if (sl == 0) {
+              sbuf[2 * b] = v0;
+              sbuf[2 * b + 1] = tau;
+              Ra[off(j)] = rjj;
+            }
+          }
+        }
+    }
+    __syncthreads();
+    const T v0 = sbuf[2 * b], tau = sbuf[2 * b + 1];
+    if (tau != (T)0 && 64 * (CPG - 1) + 4 * wave + 3 > j) {
+      T v[EM];
+#pragma unroll
+      for (int e = 0; e < EM; ++e) v[e] = vbuf[b][sl + 16 * e];
+#pragma unroll
+      for (int k = 0; k < CPG; ++k)
+        if (64 * k + 4 * wave + 3 > j && 64 * k + 4 * wave < r) {  // wave-uniform
+          const int c = 64 * k + g;
+          const bool act = c > j && c < r;
+          const T a0 = act ? Ra[off(j) + (c - j)] : (T)0;
+          T w = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) w += v[e] * x[k][e];
+          w = (row_sum(w) + v0 * a0) * tau;
+          if (!act) w = 0;
+#pragma unroll
+          for (int e = 0; e < EM; ++e) x[k][e] -= w * v[e];
+          if (act && sl == 0) Ra[off(j) + (c - j)] = a0 - w * v0;
+        }
+    }
+    if (tid == 0) flops += 2ull * (jb + 2) + 4ull * (unsigned long long)(jb + 2) * (r - j - 1);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < r * r; idx += QR_THREADS) {
+    const int i = idx % r, c = idx / r;
+    out[i + (size_t)c * ld] = i <= c ? Ra[off(i) + (c - i)] : (T)0;
+  }
+  if (tid == 0) count_work(K_QR, flops, 0);
+}
+
 template <typename T>
 static __device__ void householder_rows(T* X, int ld, int h, int r) {
   __shared__ T cn[QR_RMAX];  // squared norm of column c below row j, for the next pivot
@@ -958,6 +1082,22 @@ static __device__ __forceinline__ bool qr_stage_body(const QrTask& Tk, const int
   }
   if (stage == 0 && h <= 256 && r <= 128) {
     householder_regs<T, 16, 2>(srcM, ld0, slot, Tk.hs, h, r, flag, Tk.fidx, qlds);
+    return true;
+  }
+  // two stacked triangles (the first one full): structured combine, R_b in registers
+  if (stage > 0 && ra == r && rb >= 1 && r <= 192 && (size_t)r * (r + 1) / 2 + 2 * 16 * 12 + 4 <= (size_t)kLds) {
+    const int cpg = (r + 63) / 64, em = (rb + 15) / 16;
+    if (cpg == 1) {
+      if (em <= 4) householder_tri_pair<T, 4, 1>(src0, src1, Tk.hs, slot, r, rb, qlds);
+      else householder_tri_pair<T, 8, 1>(src0, src1, Tk.hs, slot, r, rb, qlds);   // rb <= r <= 64 < 128
+    } else if (cpg == 2) {
+      if (em <= 4) householder_tri_pair<T, 4, 2>(src0, src1, Tk.hs, slot, r, rb, qlds);
+      else householder_tri_pair<T, 8, 2>(src0, src1, Tk.hs, slot, r, rb, qlds);
+    } else {
+      if (em <= 4) householder_tri_pair<T, 4, 3>(src0, src1, Tk.hs, slot, r, rb, qlds);
+      else if (em <= 8) householder_tri_pair<T, 8, 3>(src0, src1, Tk.hs, slot, r, rb, qlds);
+      else householder_tri_pair<T, 12, 3>(src0, src1, Tk.hs, slot, r, rb, qlds);
+    }
     return true;
   }
   const bool inl = h * r <= kLds;

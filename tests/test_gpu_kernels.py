@@ -69,9 +69,12 @@ def test_qr_r_fp32(rows, r):
 
 # tiles of at most 128 rows and 256 columns, or 256 rows and 128 columns, are factored in registers;
 # a stack with no more rows than columns is passed on as its own factor (M = I M)
+# several row tiles: the tree steps combine two stacked triangles (structured for r <= 192, a ragged
+# last tile giving a trapezoid below), dense above
 @pytest.mark.parametrize("rows,r", [(1, 1), (5, 9), (64, 64), (300, 20), (2000, 37), (9000, 64), (700, 200),
                                     (128, 200), (100, 130), (128, 127), (128, 60), (129, 60), (200, 100),
-                                    (256, 128), (250, 129)])
+                                    (256, 128), (250, 129), (3000, 150), (4100, 190), (2500, 100), (5000, 131),
+                                    (1100, 192), (2100, 200), (8300, 70), (2150, 120)])
 def test_qr_r(rows, r):
     rng = np.random.default_rng(rows + r)
     M = rng.standard_normal((rows, r)) * np.logspace(0, -12, r)[None, :]
@@ -112,7 +115,7 @@ def test_recompress_fp32(m, n, r, decay):
     assert np.linalg.norm(Uh @ Vh.T - M, 2) <= 4 * eff
 
 
-@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (120, 90), (200, 60)])
+@pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (120, 90), (200, 60), (3000, 150), (2200, 100)])
 def test_qr_r_columns_near_underflow(rows, r):
     """Columns scaled into the range where squared norms are denormal or underflow: the
     triangular factor stays finite and matches LAPACK's column by column (relative to each
