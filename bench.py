@@ -251,6 +251,9 @@ def main():
                     help="capacities from the previous iterate's ranks instead of the trained rank predictor")
     ap.add_argument("--graph", action="store_true",
                     help="launch each Cholesky iteration as one captured HIP graph")
+    ap.add_argument("--sweep", choices=["nmin", "memory", "scaling", "breakeven"],
+                    help="one of the paper's timing/memory experiments on Sec. 6.1 test matrices instead of "
+                         "the benchmark line (JSON lines, one per case)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); sharding "
@@ -259,6 +262,8 @@ def main():
     import torch
     import paper_1608_01164_amd as hq
 
+    if args.sweep:
+        return SWEEPS[args.sweep](hq)
     if args.workload in BATCHED:
         return main_batched(args, BATCHED[args.workload])
     maker, b, leaf, tol = WORKLOADS[args.workload]
@@ -475,6 +480,103 @@ def main_batched(args, count, leaf=128, tol=1e-10):
         out["kernels"] = kernel_table(prof_w if prof_w is not None else prof)
         out["kernels_source"] = "last warmup step, every kernel class timed" if prof_w is not None else "timed steps"
     print(json.dumps(out), flush=True)
+
+
+# ---- the paper's timing and memory experiments (Sec. 6) on its synthetic test matrices ----------
+# Matrices from the Sec. 6.1 construction: eigenvalues uniform in [-1, -gap] U [gap, 1] (half on each
+# side, mu = 0) imposed on a b-banded matrix by plane rotations and bulge chasing.
+
+# Memory of the HODLR projector reported in the paper's Table 2 (n = 16000, n_min = 250, eps = 1e-10,
+# MATLAB on one Xeon core): MB for b = 1, 2, 4, 8, 16.
+PAPER_TABLE2_MB = {1e-1: [55.72, 79.38, 127.04, 219.92, 395.91], 1e-4: [86.03, 129.71, 206.32, 340.88, 567.69]}
+
+
+def _sec61(n, b, gap, seed=0):
+    import workloads as wl
+    return wl.prescribed_spectrum_band(wl.split_gap_spectrum(n, gap, seed), b)
+
+
+def _time_projector(hq, ab, b, leaf, tol, reps=2):
+    """Median seconds of `reps` projectors after one warmup, and the last call's info."""
+    import torch
+    band = torch.from_numpy(np.ascontiguousarray(ab)).cuda()
+    ts = []
+    info = None
+    for i in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P, info = hq.spectral_projector(band, b, 0.0, leaf=leaf, tol=tol)
+        torch.cuda.synchronize()
+        if i > 0:
+            ts.append(time.perf_counter() - t0)
+        P.close()
+    return float(np.median(ts)), info
+
+
+def sweep_nmin(hq):
+    """Example time_vs_nb_tridiag: time versus n_min for tridiagonal n = 50000."""
+    for gap in (1e-1, 1e-4, 1e-6):
+        ab = _sec61(50000, 1, gap)
+        for leaf in (64, 128, 256, 512, 1024):
+            t, info = _time_projector(hq, ab, 1, leaf, 1e-10)
+            print(json.dumps({"sweep": "nmin", "n": 50000, "b": 1, "gap": gap, "n_min": leaf, "seconds": t,
+                              "iters": info["iters"], "max_rank": info["max_rank"], "mb": info["bytes"] / 2**20}),
+                  flush=True)
+
+
+def sweep_memory(hq):
+    """Example hodlrvshmatrix / Table 2: memory of the HODLR projector, n = 16000, n_min = 250."""
+    for gap in (1e-1, 1e-4):
+        for j, b in enumerate((1, 2, 4, 8, 16)):
+            ab = _sec61(16000, b, gap)
+            t, info = _time_projector(hq, ab, b, 250, 1e-10, reps=1)
+            print(json.dumps({"sweep": "memory", "n": 16000, "b": b, "gap": gap, "n_min": 250, "seconds": t,
+                              "mb": info["bytes"] / 2**20, "paper_mb": PAPER_TABLE2_MB[gap][j],
+                              "max_rank": info["max_rank"], "iters": info["iters"]}), flush=True)
+
+
+def sweep_scaling(hq):
+    """Examples scaling_tridiag / band: time and memory versus n (gap 1e-6 tridiagonal, gap 1e-1 b = 4),
+    and the 1D Laplacian (gap ~ 1/n)."""
+    import workloads as wl
+    for n in (4096, 8192, 16384, 32768, 65536, 131072):
+        for kind, b in (("tridiag-gap1e-6", 1), ("band4-gap1e-1", 4), ("laplacian", 1)):
+            if kind != "laplacian" and n > 32768:  # the O(n^2) construction of the test matrix
+                continue
+            ab = wl.laplacian(n) if kind == "laplacian" else _sec61(n, b, 1e-6 if b == 1 else 1e-1)
+            t, info = _time_projector(hq, ab, b, 256 if b == 1 else 512, 1e-10, reps=1)
+            print(json.dumps({"sweep": "scaling", "kind": kind, "n": n, "b": b, "seconds": t,
+                              "mb": info["bytes"] / 2**20, "max_rank": info["max_rank"], "iters": info["iters"]}),
+                  flush=True)
+
+
+def sweep_breakeven(hq):
+    """Breakeven versus a dense eigensolver (the paper: MATLAB eig on one core; here the GPU's dense
+    symmetric eigensolver through torch.linalg.eigh, projector formed as V V^T), tridiagonal and b = 8."""
+    import torch
+    import workloads as wl
+    for b, gap in ((1, 1e-1), (1, 1e-4), (8, 1e-1), (8, 1e-4)):
+        for n in (1024, 2048, 4096, 8192, 16384):
+            ab = _sec61(n, b, gap)
+            t_h, info = _time_projector(hq, ab, b, 256 if b == 1 else 512, 1e-10)
+            A = torch.from_numpy(wl.band_to_dense(ab)).cuda()
+            ts = []
+            for i in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lam, V = torch.linalg.eigh(A)
+                Vn = V[:, : n // 2]
+                Pi = Vn @ Vn.T
+                torch.cuda.synchronize()
+                if i > 0:
+                    ts.append(time.perf_counter() - t0)
+            del A, V, Vn, Pi
+            print(json.dumps({"sweep": "breakeven", "n": n, "b": b, "gap": gap, "hqdwh_seconds": t_h,
+                              "dense_eigh_seconds": float(np.median(ts)), "max_rank": info["max_rank"]}),
+                  flush=True)
+
+
+SWEEPS = {"nmin": sweep_nmin, "memory": sweep_memory, "scaling": sweep_scaling, "breakeven": sweep_breakeven}
 
 
 if __name__ == "__main__":

@@ -59,7 +59,9 @@ def main():
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.txt"))
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--only", default="", help="comma-separated subset of the parameters to search")
     args = ap.parse_args()
+    cands = {k: v for k, v in CANDIDATES.items() if not args.only or k in args.only.split(",")}
     import torch
     import paper_1608_01164_amd as hq
     from paper_1608_01164_amd import predictor as hp
@@ -76,7 +78,7 @@ def main():
     log.append(f"# start {best}: {t_best:.4f} s")
     print(log[-1], flush=True)
     for p in range(args.passes):
-        for key, values in CANDIDATES.items():
+        for key, values in cands.items():
             for v in values:
                 if v == best[key]:
                     continue

@@ -46,6 +46,9 @@ hq_status guard(F&& f) {
 }
 
 using clk = std::chrono::steady_clock;
+
+// Mixed precision: truncation tolerance of the FP64 iterations that follow FP32 ones (at least opts.tol).
+constexpr double kTolAfterFp32 = 1e-8;
 double secs(clk::time_point a) { return std::chrono::duration<double>(clk::now() - a).count(); }
 
 // ---- host setup: alpha, l0, weights ---------------------------------------------------------
@@ -599,16 +602,22 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         E.product(pv);
       } else {
         // Alg. 3 lines 11-14: W = chol(I + c X^T X); Y W = X; V W^T = Y; X+ = b/c X + (a - b/c) V.
-        // Members whose iteration runs in FP32 (mixed mode) go in their own launches.
-        std::vector<int> grp[2];
+        // Members whose iteration runs in FP32 (mixed mode) go in their own launches, and so do the
+        // FP64 iterations that follow FP32 ones: those truncate at max(tol, kTolAfterFp32), since the
+        // iterate already carries the FP32 iterations' perturbation (orders of magnitude above it)
+        // and a finer truncation would only keep that noise as rank.
+        std::vector<int> grp[3];
         for (int i : pend) {
           const Member& m = ms[i];
           const bool f32 = o.precision == HQ_MIXED && k + 1 < m.K && m.w.c[k] <= o.c_fp32_max;
-          grp[f32 ? 1 : 0].push_back(i);
+          bool after = false;
+          for (int j = 0; j < k && j < 16; ++j) after |= m.inf.fp32_iter[j] != 0;
+          grp[f32 ? 1 : (after ? 2 : 0)].push_back(i);
         }
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < 3; ++g) {
         if (grp[g].empty()) continue;
         E.fp32 = g == 1;
+        E.tol = g == 2 ? std::max(o.tol, kTolAfterFp32) : o.tol;
         if (g == 1 && k < 16)
           for (int i : grp[g]) ms[i].inf.fp32_iter[k] = 1;
         std::vector<hq::Engine::ProdTask> pz, py, px;
@@ -660,6 +669,7 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         E.scratch.reset();
         }
         E.fp32 = false;
+        E.tol = o.tol;
       }
       if (capture) {
         graph = E.capture_end_launch();

@@ -16,6 +16,7 @@ import numpy as np
 from oracle import qdwh
 
 U32 = 2.0 ** -24
+TOL_AFTER_FP32 = 1e-8   # the library's truncation of FP64 iterations after FP32 ones (at least tol)
 
 
 def floor_sqrt_m(m: int) -> float:
@@ -72,6 +73,7 @@ def mixed_projector(A: np.ndarray, mu: float, lam: np.ndarray, leaf: int, tol: f
     X = M / alpha
     for k, (a, b, c, _l) in enumerate(sched):
         lowp = k in f32
+        after = any(j < k for j in f32)
         dt = np.float32 if lowp else np.float64
         Xl = X.astype(dt)
         Z = np.eye(n, dtype=dt) + dt(c) * (Xl.T @ Xl)
@@ -79,7 +81,7 @@ def mixed_projector(A: np.ndarray, mu: float, lam: np.ndarray, leaf: int, tol: f
         Y = np.linalg.solve(W.T, Xl.T).T      # Y W = X
         V = np.linalg.solve(W, Y.T).T         # V W^T = Y
         X = ((b / c) * Xl + dt(a - b / c) * V).astype(np.float64)
-        truncate(X, leaf, tol, floor if lowp else None)
+        truncate(X, leaf, max(tol, TOL_AFTER_FP32) if after and not lowp else tol, floor if lowp else None)
     P = 0.5 * (np.eye(n) - 0.5 * (X + X.T))
     return P, sched, f32
 
@@ -93,9 +95,14 @@ def stated_bound(n: int, sched, f32) -> float:
     mu is not undone by later iterations, which converge to the sign of the perturbed iterate; the
     eigenvalues of X_{k+1} are at least l_{k+1} away from 0, so the coupling turns the invariant
     subspace by at most about (perturbation) / (2 l_{k+1}) (Davis-Kahan).  Summed over the FP32
-    iterations: sum_k floor(ceil(n/2)) / l_{k+1}."""
+    iterations: sum_k floor(ceil(n/2)) / l_{k+1}.  The FP64 iterations after them truncate at
+    TOL_AFTER_FP32 per block, at most levels x TOL_AFTER_FP32 on X_{k+1}, turned into a rotation the
+    same way (l_{k+1} is near 1 by then)."""
     ls = [s[3] for s in sched] + [1.0]
-    return float(sum(2.0 * floor_sqrt_m((n + 1) // 2) / (2.0 * min(1.0, ls[k + 1])) for k in f32))
+    levels = max(1, int(np.ceil(np.log2(max(n, 2)))))
+    post = [k for k in range(len(sched)) if f32 and k > min(f32) and k not in f32]
+    return float(sum(2.0 * floor_sqrt_m((n + 1) // 2) / (2.0 * min(1.0, ls[k + 1])) for k in f32) +
+                 sum(levels * TOL_AFTER_FP32 / (2.0 * min(1.0, ls[k + 1])) for k in post))
 
 
 def bound_from_info(n: int, info: dict) -> float:
