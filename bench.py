@@ -525,14 +525,27 @@ def sweep_nmin(hq):
 
 
 def sweep_memory(hq):
-    """Example hodlrvshmatrix / Table 2: memory of the HODLR projector, n = 16000, n_min = 250."""
+    """Example hodlrvshmatrix / Table 2: memory of the HODLR projector, n = 16000, n_min = 250, on the
+    Sec. 6.1 matrices; and, for comparison, on banded matrices whose b bands are full (entries N(0,1),
+    diagonal shift 4 i / n, mu at the middle of the spectrum, gap not controlled)."""
+    import torch
+    import workloads as wl
     for gap in (1e-1, 1e-4):
         for j, b in enumerate((1, 2, 4, 8, 16)):
             ab = _sec61(16000, b, gap)
             t, info = _time_projector(hq, ab, b, 250, 1e-10, reps=1)
-            print(json.dumps({"sweep": "memory", "n": 16000, "b": b, "gap": gap, "n_min": 250, "seconds": t,
-                              "mb": info["bytes"] / 2**20, "paper_mb": PAPER_TABLE2_MB[gap][j],
+            print(json.dumps({"sweep": "memory", "matrix": "sec6.1", "n": 16000, "b": b, "gap": gap, "n_min": 250,
+                              "seconds": t, "mb": info["bytes"] / 2**20, "paper_mb": PAPER_TABLE2_MB[gap][j],
                               "max_rank": info["max_rank"], "iters": info["iters"]}), flush=True)
+    for b in (1, 2, 4, 8, 16):
+        ab = wl.banded_normal(16000, b, 0)
+        mu, gap = hq.shift_for_count(ab, b, 8000)
+        band = torch.from_numpy(np.ascontiguousarray(ab)).cuda()
+        P, info = hq.spectral_projector(band, b, mu, leaf=250, tol=1e-10)
+        P.close()
+        print(json.dumps({"sweep": "memory", "matrix": "full-band normal", "n": 16000, "b": b, "gap": gap,
+                          "n_min": 250, "seconds": info["seconds"], "mb": info["bytes"] / 2**20,
+                          "max_rank": info["max_rank"], "iters": info["iters"]}), flush=True)
 
 
 def sweep_scaling(hq):
@@ -544,7 +557,7 @@ def sweep_scaling(hq):
             if kind != "laplacian" and n > 32768:  # the O(n^2) construction of the test matrix
                 continue
             ab = wl.laplacian(n) if kind == "laplacian" else _sec61(n, b, 1e-6 if b == 1 else 1e-1)
-            t, info = _time_projector(hq, ab, b, 256 if b == 1 else 512, 1e-10, reps=1)
+            t, info = _time_projector(hq, ab, b, 256 if b == 1 else 128, 1e-10, reps=1)
             print(json.dumps({"sweep": "scaling", "kind": kind, "n": n, "b": b, "seconds": t,
                               "mb": info["bytes"] / 2**20, "max_rank": info["max_rank"], "iters": info["iters"]}),
                   flush=True)
@@ -558,7 +571,7 @@ def sweep_breakeven(hq):
     for b, gap in ((1, 1e-1), (1, 1e-4), (8, 1e-1), (8, 1e-4)):
         for n in (1024, 2048, 4096, 8192, 16384):
             ab = _sec61(n, b, gap)
-            t_h, info = _time_projector(hq, ab, b, 256 if b == 1 else 512, 1e-10)
+            t_h, info = _time_projector(hq, ab, b, 256 if b == 1 else 128, 1e-10)
             A = torch.from_numpy(wl.band_to_dense(ab)).cuda()
             ts = []
             for i in range(3):

@@ -537,7 +537,13 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
     } else if (o.predictor) {
       // A member whose predicted capacities overflowed once gets, from then on, at least the
       // capacities the previous iterate's ranks call for (one rank readback for those members), so
-      // that a predictor that under-estimates a problem costs at most one repeated iteration.
+      // that a predictor that under-estimates a problem costs at most one repeated iteration.  The
+      // network is trained on FP64 solves: in the mixed mode the FP32 iterations and those after
+      // them get the same treatment from the first FP32 iteration on.
+      for (int i : act) {
+        Member& m = ms[i];
+        if (o.precision == HQ_MIXED && k + 1 < m.K && m.w.c[k] <= o.c_fp32_max) m.pred_miss = true;
+      }
       std::vector<const hq::HMat*> xs;
       std::vector<int> miss;
       for (int i : act)

@@ -298,6 +298,7 @@ class Engine {
   struct CholTask { const HMat* Z; HMat* Linv; HMat* Lf; int capS; int fidx; };
   std::vector<int> chol_work_caps(const Tree& t, const std::vector<int>& capZ, int capS) const;
   void cholesky_inverse(const std::vector<CholTask>& v);
+  void leaf_chol_inv(const std::vector<LeafTask>& blocks);
   void cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) { cholesky_inverse({CholTask{&Z, &Linv, &Lf, capS, 0}}); }
   // out = sid * I + sx * (X + X^T) / 2 as a full HODLR (sign: sx = 1, sid = 0; projector: -1/2, 1/2)
   struct AffTask { const HMat* X; HMat* P; double sx, sid; int fidx; };

@@ -1069,6 +1069,74 @@ void Engine::product(const std::vector<ProdTask>& batch) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Cholesky and inverse of dense diagonal blocks (A = L L^T in place, X = L^{-1}, X zero on entry), all
+// blocks of a list together.  Blocks of at most 128 rows go to the fused register kernel; larger ones
+// are split 2 x 2 around h1 = ceil(m / 2):
+//   X11 = L11^{-1} (recursively);  L21 = A21 X11^T;  A22 -= L21 L21^T;  X22 = L22^{-1} (recursively);
+//   X21 = -X22 (L21 X11),
+// with L21 kept in X21's place until the last step.  Every step is one batched launch for all the
+// blocks at that depth; FP64 in every precision mode.
+void Engine::leaf_chol_inv(const std::vector<LeafTask>& blocks) {
+  std::vector<LeafTask> small, big;
+  int maxsmall = 1;
+  for (const LeafTask& b : blocks) {
+    if (b.m <= 0) continue;
+    if (b.m <= 128) {
+      small.push_back(b);
+      maxsmall = std::max(maxsmall, b.m);
+    } else {
+      big.push_back(b);
+    }
+  }
+  if (!small.empty()) {
+    launch_chol_inv(stage.upload(small, st), (int)small.size(), maxsmall, d_flag, st);
+    ++launches;
+  }
+  if (big.empty()) return;
+  std::vector<LeafTask> top, bottom;
+  std::vector<GemmTask> m1, m2, m3, m4;
+  int maxh = 1;
+  const DevArena::Mark mk = scratch.mark();
+  for (const LeafTask& b : big) {
+    const int h1 = (b.m + 1) / 2, h2 = b.m - h1;
+    maxh = std::max(maxh, h1);
+    double* A = b.A;
+    double* X = b.B;
+    const int ld = b.lda, ldx = b.ldb;
+    double* W = scratch.get<double>((size_t)h2 * h1);
+    top.push_back(LeafTask{A, X, h1, ld, ldx, b.fidx});
+    bottom.push_back(LeafTask{A + h1 + (size_t)h1 * ld, X + h1 + (size_t)h1 * ldx, h2, ld, ldx, b.fidx});
+    GemmTask g{};
+    g.A = A + h1; g.lda = ld; g.B = X; g.ldb = ldx; g.opB = 1; g.C = X + h1; g.ldc = ldx;
+    g.m = h2; g.n = h1; g.k = h1; g.alpha = 1.0; g.beta = 0.0;
+    m1.push_back(g);  // L21 = A21 X11^T
+    g = GemmTask{};
+    g.A = X + h1; g.lda = ldx; g.B = X + h1; g.ldb = ldx; g.opB = 1; g.C = A + h1 + (size_t)h1 * ld; g.ldc = ld;
+    g.m = h2; g.n = h2; g.k = h1; g.alpha = -1.0; g.beta = 1.0;
+    m2.push_back(g);  // A22 -= L21 L21^T
+    g = GemmTask{};
+    g.A = X + h1; g.lda = ldx; g.B = X; g.ldb = ldx; g.C = W; g.ldc = h2;
+    g.m = h2; g.n = h1; g.k = h1; g.alpha = 1.0; g.beta = 0.0;
+    m3.push_back(g);  // W = L21 X11
+    g = GemmTask{};
+    g.A = X + h1 + (size_t)h1 * ldx; g.lda = ldx; g.B = W; g.ldb = h2; g.C = X + h1; g.ldc = ldx;
+    g.m = h2; g.n = h1; g.k = h2; g.alpha = -1.0; g.beta = 0.0;
+    m4.push_back(g);  // X21 = -X22 W
+  }
+  // the leaf factorisation stays FP64 in every mode
+  const bool f = fp32;
+  fp32 = false;
+  leaf_chol_inv(top);
+  gemm(m1, maxh, maxh);
+  gemm(m2, maxh, maxh);
+  leaf_chol_inv(bottom);
+  gemm(m3, maxh, maxh);
+  gemm(m4, maxh, maxh);
+  fp32 = f;
+  scratch.rewind(mk);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Recursive Cholesky (left subtree, off-diagonal factor, Schur update, right subtree).  The
 // Schur complement updates from all ancestors are carried lazily as one symmetric low-rank
 // factor S (Z_bb - L_ba L_ba^T restricted = Z_bb - S S^T), compressed at a right turn once it is
@@ -1097,11 +1165,9 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     // leaves: Lf_i = chol(Z_i - S S^T), Linv_i = Lf_i^{-1}
     std::vector<LeafAxpy> cp;
     std::vector<GemmTask> gs;
-    std::vector<LeafTask> small, big, mid2;
-    std::vector<GemmTask> m1, m2, m3, m4;  // steps of the 2 x 2 split of leaves with 128 < m <= 256
+    std::vector<LeafTask> blocks;
     std::vector<Item> inner;
-    int maxm = 1, maxsmall = 1, maxh = 1;
-    const DevArena::Mark lmk = scratch.mark();  // leaf scratch (W), released after the leaf launches
+    int maxm = 1;
     for (const Item& it : items) {
       const CholTask& T = batch[it.m];
       const Tree* t = T.Z->t;
@@ -1114,73 +1180,22 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       LeafAxpy x{};
       x.out = T.Lf->leaf(li); x.ldo = T.Lf->ldl; x.X = T.Z->leaf(li); x.ldx = T.Z->ldl; x.m = m; x.alpha = 1.0;
       cp.push_back(x);
+      LeafAxpy z{};  // Linv_i = 0 (the recursion writes its lower triangle block by block)
+      z.out = T.Linv->leaf(li); z.ldo = T.Linv->ldl; z.X = z.out; z.ldx = z.ldo; z.m = m;
+      cp.push_back(z);
       if (it.S.cap > 0) {
         GemmTask g{};
         g.A = it.S.p; g.lda = it.S.ld; g.B = it.S.p; g.ldb = it.S.ld; g.opB = 1; g.C = T.Lf->leaf(li); g.ldc = T.Lf->ldl;
         g.m = g.n = m; g.k = it.S.cap; g.kp = it.S.r; g.alpha = -1.0; g.beta = 1.0;
         gs.push_back(g);
       }
-      const LeafTask lt{T.Lf->leaf(li), T.Linv->leaf(li), m, T.Lf->ldl, T.Linv->ldl, T.fidx};
-      if (m <= 128) {
-        small.push_back(lt);
-        maxsmall = std::max(maxsmall, m);
-      } else if (m <= 256) {
-        // [A11 0; A21 A22] = [L11 0; L21 L22] [L11 0; L21 L22]^T with X = L^{-1}:
-        //   X11 = L11^{-1};  L21 = A21 X11^T;  A22 -= L21 L21^T;  X22 = L22^{-1};  X21 = -X22 L21 X11.
-        // L21 is kept in X21's slot until the last step; W = L21 X11 is scratch; X12 = 0.
-        const int h1 = (m + 1) / 2, h2 = m - h1, ld = T.Lf->ldl, ldx = T.Linv->ldl;
-        double* A = T.Lf->leaf(li);
-        double* X = T.Linv->leaf(li);
-        double* W = scratch.get<double>((size_t)h2 * h1);
-        maxh = std::max(maxh, h1);
-        LeafAxpy z{};  // X = 0
-        z.out = X; z.ldo = ldx; z.X = X; z.ldx = ldx; z.m = m;
-        cp.push_back(z);
-        small.push_back(LeafTask{A, X, h1, ld, ldx, T.fidx});
-        GemmTask g{};
-        g.A = A + h1; g.lda = ld; g.B = X; g.ldb = ldx; g.opB = 1; g.C = X + h1; g.ldc = ldx;
-        g.m = h2; g.n = h1; g.k = h1; g.alpha = 1.0; g.beta = 0.0;
-        m1.push_back(g);  // L21 = A21 X11^T
-        g = GemmTask{};
-        g.A = X + h1; g.lda = ldx; g.B = X + h1; g.ldb = ldx; g.opB = 1; g.C = A + h1 + (size_t)h1 * ld; g.ldc = ld;
-        g.m = h2; g.n = h2; g.k = h1; g.alpha = -1.0; g.beta = 1.0;
-        m2.push_back(g);  // A22 -= L21 L21^T
-        mid2.push_back(LeafTask{A + h1 + (size_t)h1 * ld, X + h1 + (size_t)h1 * ldx, h2, ld, ldx, T.fidx});
-        g = GemmTask{};
-        g.A = X + h1; g.lda = ldx; g.B = X; g.ldb = ldx; g.C = W; g.ldc = h2;
-        g.m = h2; g.n = h1; g.k = h1; g.alpha = 1.0; g.beta = 0.0;
-        m3.push_back(g);  // W = L21 X11
-        g = GemmTask{};
-        g.A = X + h1 + (size_t)h1 * ldx; g.lda = ldx; g.B = W; g.ldb = h2; g.C = X + h1; g.ldc = ldx;
-        g.m = h2; g.n = h1; g.k = h2; g.alpha = -1.0; g.beta = 0.0;
-        m4.push_back(g);  // X21 = -X22 W
-      } else {
-        big.push_back(lt);
-      }
+      blocks.push_back(LeafTask{T.Lf->leaf(li), T.Linv->leaf(li), m, T.Lf->ldl, T.Linv->ldl, T.fidx});
     }
     if (!cp.empty()) {
       launch_leaf_axpy(stage.upload(cp, st), (int)cp.size(), maxm, st);
       ++launches;
       gemm(gs, maxm, maxm);
-      if (!small.empty()) {
-        launch_chol_inv(stage.upload(small, st), (int)small.size(), std::max(maxsmall, maxh), d_flag, st);
-        ++launches;
-      }
-      if (!mid2.empty()) {  // the leaf factorisation stays FP64 in every mode
-        launch_gemm(stage.upload(m1, st), (int)m1.size(), maxh, maxh, false, st);
-        launch_gemm(stage.upload(m2, st), (int)m2.size(), maxh, maxh, false, st);
-        launch_chol_inv(stage.upload(mid2, st), (int)mid2.size(), maxh, d_flag, st);
-        launch_gemm(stage.upload(m3, st), (int)m3.size(), maxh, maxh, false, st);
-        launch_gemm(stage.upload(m4, st), (int)m4.size(), maxh, maxh, false, st);
-        launches += 5;
-      }
-      scratch.rewind(lmk);
-      if (!big.empty()) {
-        LeafTask* d = stage.upload(big, st);
-        launch_potrf(d, (int)big.size(), d_flag, st);
-        launch_trtri(d, (int)big.size(), st);
-        launches += 2;
-      }
+      leaf_chol_inv(blocks);
     }
     if (inner.empty()) return;
     // left subtrees

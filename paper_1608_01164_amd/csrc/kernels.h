@@ -147,7 +147,7 @@ void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int* flag, hipStrea
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.
 struct LeafTask {
   double* A;
-  double* B;    // second operand (trtri output)
+  double* B;    // the inverse of the factor (output)
   int m, lda, ldb;
   int fidx;     // status word of the owning matrix
 };
@@ -171,8 +171,6 @@ void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag,
 void launch_qr_stage(const QrTask* d_tasks, int ntasks, int stage, int max_pairs, int* flag, bool fp32,
                      hipStream_t s);
 void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStream_t s);
-void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s);
-void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s);
 // fused: A (m <= 128) -> Cholesky factor, B = its inverse; whole tile in LDS
 void launch_chol_inv(const LeafTask* d_tasks, int ntasks, int max_m, int* flag, hipStream_t s);
 // leaves: out = alpha*X + beta*op(X)^T + gamma*I over m x m tiles (symmetrise / identity shifts)

@@ -2067,66 +2067,6 @@ void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int* flag, hipStrea
 }
 
 // ----------------------------------------------------------------------------------------------
-// Leaf Cholesky (lower, right-looking, in place) and lower-triangular inverse.
-// ----------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_potrf(const LeafTask* __restrict__ tasks, int* flag) {
-  const LeafTask T = tasks[blockIdx.x];
-  double* A = T.A;
-  const int m = T.m, ld = T.lda, tid = threadIdx.x;
-  __shared__ double piv;
-  for (int j = 0; j < m; ++j) {
-    if (tid == 0) {
-      double d = A[j + (size_t)j * ld];
-      if (!(d > 0.0)) {  // breakdown: flagged; a unit pivot keeps the rest finite
-        atomicOr(flag + T.fidx, 2);
-        d = 1.0;
-      }
-      d = sqrt(d);
-      A[j + (size_t)j * ld] = d;
-      piv = d;
-    }
-    __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int i = j + 1 + tid; i < m; i += 256) A[i + (size_t)j * ld] *= inv;
-    __syncthreads();
-    const int w = m - j - 1;
-    for (int idx = tid; idx < w * w; idx += 256) {
-      const int i = j + 1 + idx % w, c = j + 1 + idx / w;
-      if (c <= i) A[i + (size_t)c * ld] -= A[i + (size_t)j * ld] * A[c + (size_t)j * ld];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < m * m; idx += 256) {
-    const int i = idx % m, c = idx / m;
-    if (i < c) A[i + (size_t)c * ld] = 0.0;
-  }
-  if (tid == 0) count_work(K_POTRF, (unsigned long long)m * m * m / 3, 0);
-}
-
-__global__ __launch_bounds__(256) void k_trtri(const LeafTask* __restrict__ tasks) {
-  const LeafTask T = tasks[blockIdx.x];
-  const double* L = T.A;
-  double* X = T.B;
-  const int m = T.m, tid = threadIdx.x;
-  for (int idx = tid; idx < m * m; idx += 256) {
-    const int i = idx % m, c = idx / m;
-    X[i + (size_t)c * T.ldb] = (i == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int k = 0; k < m; ++k) {
-    const double inv = 1.0 / L[k + (size_t)k * T.lda];
-    for (int c = tid; c <= k; c += 256) X[k + (size_t)c * T.ldb] *= inv;
-    __syncthreads();
-    const int rows = m - k - 1, cols = k + 1;
-    for (int idx = tid; idx < rows * cols; idx += 256) {
-      const int i = k + 1 + idx % rows, c = idx / rows;
-      X[i + (size_t)c * T.ldb] -= L[i + (size_t)k * T.lda] * X[k + (size_t)c * T.ldb];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) count_work(K_TRTRI, (unsigned long long)m * m * m / 3, 0);
-}
-
 // Leaf Cholesky and triangular inverse for m <= 128, with the tile in registers, by 4 x 4 blocks.
 // The lower triangle of the tile (padded with the identity to a multiple of 4) is cut into 4 x 4
 // blocks, one per thread (at most 528), numbered column by column.  Block step J factors block
@@ -2336,12 +2276,6 @@ void launch_chol_inv(const LeafTask* d_tasks, int ntasks, int max_m, int* flag, 
   HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(CI_THREADS), 0, s, d_tasks, flag));
 }
 
-void launch_potrf(const LeafTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
-  if (ntasks > 0) HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_potrf, dim3(ntasks), dim3(256), 0, s, d_tasks, flag));
-}
-void launch_trtri(const LeafTask* d_tasks, int ntasks, hipStream_t s) {
-  if (ntasks > 0) HQ_TIMED(K_TRTRI, s, hipLaunchKernelGGL(k_trtri, dim3(ntasks), dim3(256), 0, s, d_tasks));
-}
 
 // ----------------------------------------------------------------------------------------------
 // Leaf-level elementwise: out = alpha*X + beta*op(Y) + gamma*I.

@@ -28,6 +28,10 @@ CASES = [
     ("band8-2048-leaf128", lambda: w.banded_normal(2048, 8, 0), 8, 128, 1e-10),
     # off-diagonal factors decay to the underflow range (wide gap, 71-row leaves, depth 5)
     ("tri-2284-leaf128-decay", lambda: w.banded_normal(2284, 1, rng=np.random.default_rng([0, 7])), 1, 128, 1e-10),
+    # leaves above 128 rows: the leaf Cholesky-inverse splits them 2 x 2 recursively (375 -> 188/187 ->
+    # 94/94 ..., 525 -> 263/262 -> 132/131 -> 66/66 ...)
+    ("band4-1500-leaf512", lambda: w.banded_normal(1500, 4, 9), 4, 512, 1e-10),
+    ("tri-2100-leaf600", lambda: w.tridiag_uniform(2100, 10), 1, 600, 1e-10),
 ]
 
 
