@@ -9,8 +9,10 @@ line.  Default workload: symmetric banded n = 16384, b = 8, N(0,1) band entries 
 comparison the metric asks for, measured in the same run: the same matrix in mixed precision (FP32
 middle iterations) with its error against the FP64 projector, the FP64 solve without the rank
 predictor, and a batch of independent matrices of the batched workload's generator (n_i ~
-U{2048..16384}, b_i ~ U{1..16}) in FP64 and in mixed precision; plus the matrix-core utilisation
-(flops issued as MFMA instructions / time / peak of their precision) of the timed steps.
+U{2048..16384}, b_i ~ U{1..16}) in FP64 and in mixed precision; Zolo-pd (the two-step alternative
+that Sec. 2.1 cites) on the same matrix with its difference to the QDWH projector; plus the
+matrix-core utilisation (flops issued as MFMA instructions / time / peak of their precision) of the
+timed steps.
 """
 from __future__ import annotations
 
@@ -216,11 +218,12 @@ def _predictor(no_predictor):
     return hp.load() if os.path.exists(hp.DEFAULT_PATH) else None
 
 
-def timed_single(hq, band, b, mu, leaf, tol, pred, precision, steps, warmup, tag):
+def timed_single(hq, band, b, mu, leaf, tol, pred, precision, steps, warmup, tag, method="qdwh"):
     """Warmup then `steps` timed calls (no timers); returns (Π/s, last projector, last info)."""
     import torch
     for i in range(warmup):
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=precision)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=precision,
+                                        method=method)
         P.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -228,7 +231,8 @@ def timed_single(hq, band, b, mu, leaf, tol, pred, precision, steps, warmup, tag
     for i in range(steps):
         if P is not None:
             P.close()
-        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=precision)
+        P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=precision,
+                                        method=method)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"# leg {tag}: {steps} steps, {dt / steps:.3f} s per projector, K={info['iters']}, "
@@ -355,6 +359,12 @@ def legs(hq, band, b, mu, leaf, tol, pred, P64, value64, n):
                                 "redo_count": inn["redo_count"], "capacity_columns": inn["capacity_columns"]}
     Pn.close()
     out["batched"] = batched_legs(hq, LEG_BATCH, pred)
+    # Zolo-pd on the same matrix (two steps of degree r instead of the QDWH iterations)
+    v, Pz, iz = timed_single(hq, band, b, mu, leaf, tol, None, "fp64", 2, 1, "zolo", method="zolo")
+    out["zolo"] = {"value": v, "unit": "Π/s", "vs_qdwh": v / value64, "steps": iz["iters"], "r": iz["zolo_r"],
+                   "redo_count": iz["redo_count"], "max_rank": iz["max_rank"], "peak_bytes": iz["peak_bytes"],
+                   "err_vs_qdwh_2norm": difference_norm(Pz, P64, n)}
+    Pz.close()
     return out
 
 

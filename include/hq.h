@@ -66,12 +66,27 @@ typedef struct {
                                 the H-Cholesky, the two products of the solves, all streams) into one
                                 HIP graph and launch it as a whole.  Currently disabled: a nonzero
                                 value returns HQ_ERR_UNSUPPORTED.  Default 0 (launches one by one). */
+  int32_t method;            /* HQ_METHOD_QDWH (default): Alg. 3.  HQ_METHOD_ZOLO: Zolo-pd, the
+                                polar decomposition by Zolotarev's rational functions that Sec. 2.1
+                                cites (Nakatsukasa and Freund, SIAM Review 58, 2016): each step maps
+                                X to mhat (X + sum_{j=1..r} a_j X (X^T X + c_{2j-1} I)^{-1}), about
+                                two steps in all; the first step takes r structured QR factorisations
+                                of [X_0; sqrt(c_{2j-1}) I] (Algorithms 1/2), the later ones r
+                                H-Cholesky factorisations of X^T X + c_{2j-1} I issued as one batch.
+                                FP64 only (precision and predictor are ignored); batched calls solve
+                                their members one after another. */
+  int32_t zolo_r;            /* HQ_METHOD_ZOLO: the degree r in [1, 8]; 0 (default) picks the smallest
+                                r reaching |1 - l_K| <= delta in two steps (r = 8 and more steps when
+                                none does) */
 } hq_opts;
+#define HQ_METHOD_QDWH 0
+#define HQ_METHOD_ZOLO 1
 #define HQ_FP64 0
 #define HQ_MIXED 1
 
 typedef struct {
-  int32_t iters;             /* QDWH iterations K */
+  int32_t iters;             /* QDWH iterations K (Zolo-pd: its steps; then a[k] holds mhat_k, b[k]
+                                the lower bound l_k, c[k] the smallest shift c_1 of step k) */
   double alpha;              /* scaling alpha >= ||A - mu I||_2 */
   double l0;                 /* certified lower bound of sigma_min((A - mu I)/alpha) */
   double a[16], b[16], c[16];/* weights of each iteration */
@@ -93,6 +108,7 @@ typedef struct {
   int32_t graphs;            /* opts.graph: iterations launched as captured graphs */
   int64_t graph_nodes;       /* opts.graph: kernel and dependency nodes in those graphs */
   double graph_build_seconds;/* opts.graph: host time spent capturing and instantiating them */
+  int32_t zolo_r;            /* HQ_METHOD_ZOLO: the degree r used (0 for QDWH) */
 } hq_info;
 
 /* Fill *o with the defaults: leaf 256, tol 1e-10, delta 1e-15, max_rank 512, max_iter 10. */
@@ -294,6 +310,12 @@ hq_status hq_test_schedule(double l0, double delta, int32_t max_iter, double* a,
                            int32_t* K);
 
 /* Host-only: the same Q1, Q2 assembled densely (Q1, Q2: host, n x n, ld n).  No device use. */
+/* Host-only: the library's Zolo-pd coefficients of one step (see hq_opts.method) for the lower bound
+ * l in [1e-150, 1) and r in [1, 16]: c[1..2r] (c_i = l^2 sc^2(i K'/(2r+1); l'), l' = sqrt(1 - l^2)),
+ * a[1..r] (partial-fraction residues), *mhat = prod_j (1 + c_{2j-1})/(1 + c_{2j}) and *lnext = Zhat(l).
+ * c: host, >= 2r + 1 entries; a: host, >= r + 1 entries (index 0 set to 0).  No device use. */
+hq_status hq_test_zolo(double l, int32_t r, double* c, double* a, double* mhat, double* lnext);
+
 hq_status hq_test_q_dense_host(const double* band, int64_t n, int32_t b, int64_t ldab, double shift, double scale,
                                int32_t leaf, double* Q1, double* Q2, int64_t* nrot);
 

@@ -30,7 +30,7 @@ class HQError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("leaf", c_i32), ("tol", c_d), ("delta", c_d), ("max_rank", c_i32), ("max_iter", c_i32),
                 ("record_ranks", c_i32), ("predictor", c_vp), ("precision", c_i32), ("c_fp32_max", c_d),
-                ("graph", c_i32)]
+                ("graph", c_i32), ("method", c_i32), ("zolo_r", c_i32)]
 
 
 class Tuning(ctypes.Structure):
@@ -69,7 +69,7 @@ class Info(ctypes.Structure):
                 ("peak_bytes", c_i64), ("launches", c_i64), ("seconds", c_d), ("setup_seconds", c_d),
                 ("givens_seconds", c_d), ("levels", c_i32), ("level_ranks", c_i32 * (16 * 4 * 24)),
                 ("capacity_columns", c_i64), ("fp32_iter", c_i32 * 16), ("graphs", c_i32), ("graph_nodes", c_i64),
-                ("graph_build_seconds", c_d)]
+                ("graph_build_seconds", c_d), ("zolo_r", c_i32)]
 
     def as_dict(self) -> dict:
         K = self.iters
@@ -80,7 +80,7 @@ class Info(ctypes.Structure):
                 "givens_seconds": self.givens_seconds, "levels": self.levels,
                 "capacity_columns": self.capacity_columns, "fp32_iter": list(self.fp32_iter[:K]),
                 "graphs": self.graphs, "graph_nodes": self.graph_nodes,
-                "graph_build_seconds": self.graph_build_seconds}
+                "graph_build_seconds": self.graph_build_seconds, "zolo_r": self.zolo_r}
 
     def level_ranks_array(self) -> np.ndarray:
         """[k][o][l]: o = 0 X_{k+1}, 1 Z_k, 2 L_k^{-1}, 3 Y_k (filled with opts record_ranks)."""
@@ -120,6 +120,7 @@ _SIGS = {
     "hq_test_q_factors": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, P(c_vp), P(c_vp), P(c_i64)]),
     "hq_test_q_dense_host": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, c_i32, c_vp, c_vp, P(c_i64)]),
     "hq_test_schedule": (c_i32, [c_d, c_d, c_i32, c_vp, c_vp, c_vp, c_vp, P(c_i32)]),
+    "hq_test_zolo": (c_i32, [c_d, c_i32, c_vp, c_vp, P(c_d), P(c_d)]),
     "hq_profile_enable": (c_i32, [c_i32]),
     "hq_profile_select": (c_i32, [c_i32]),
     "hq_profile_read": (c_i32, [c_vp, c_i32]),
@@ -211,7 +212,7 @@ def _check(status: int):
 
 
 def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10, record_ranks=False, predictor=None,
-          precision="fp64", c_fp32_max=16.0, graph=False) -> Opts:
+          precision="fp64", c_fp32_max=16.0, graph=False, method="qdwh", zolo_r=0) -> Opts:
     o = Opts()
     _check(lib().hq_default_opts(ctypes.byref(o)))
     o.leaf, o.tol, o.delta, o.max_rank, o.max_iter = int(leaf), float(tol), float(delta), int(max_rank), int(max_iter)
@@ -222,6 +223,10 @@ def _opts(leaf=256, tol=1e-10, delta=1e-15, max_rank=512, max_iter=10, record_ra
     o.precision = 1 if precision == "mixed" else 0
     o.c_fp32_max = float(c_fp32_max)
     o.graph = 1 if graph else 0
+    if method not in ("qdwh", "zolo"):
+        raise ValueError("method must be 'qdwh' or 'zolo'")
+    o.method = 1 if method == "zolo" else 0
+    o.zolo_r = int(zolo_r)
     return o
 
 
@@ -470,6 +475,16 @@ def test_schedule(l0: float, delta: float = 1e-15, max_iter: int = 16):
                                   c.ctypes.data_as(c_vp), l.ctypes.data_as(c_vp), ctypes.byref(K)))
     k = K.value
     return a[:k].copy(), b[:k].copy(), c[:k].copy(), l[: k + 1].copy()
+
+
+def test_zolo(l: float, r: int):
+    """The library's Zolo-pd coefficients of one step (host only): c (2r + 1 entries, c[0] = 0),
+    a (r + 1 entries, a[0] = 0), mhat, l_next."""
+    c, a = np.zeros(2 * r + 1), np.zeros(r + 1)
+    m, ln = c_d(), c_d()
+    _check(lib().hq_test_zolo(float(l), int(r), c.ctypes.data_as(c_vp), a.ctypes.data_as(c_vp), ctypes.byref(m),
+                              ctypes.byref(ln)))
+    return c, a, m.value, ln.value
 
 
 # ---- rank predictor --------------------------------------------------------------------------

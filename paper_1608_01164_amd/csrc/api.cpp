@@ -16,6 +16,7 @@
 #include "givens.h"
 #include "handle.h"
 #include "predictor.h"
+#include "zolo.h"
 
 
 namespace {
@@ -293,6 +294,8 @@ hq_status check_opts(const hq_opts* o, hq_opts& out) {
   if (out.max_rank < 1) return fail(HQ_ERR_ARG, "opts.max_rank must be >= 1");
   if (out.max_iter < 1 || out.max_iter > 16) return fail(HQ_ERR_ARG, "opts.max_iter must be in [1, 16]");
   if (out.precision != HQ_FP64 && out.precision != HQ_MIXED) return fail(HQ_ERR_ARG, "opts.precision must be FP64 or MIXED");
+  if (out.method != HQ_METHOD_QDWH && out.method != HQ_METHOD_ZOLO) return fail(HQ_ERR_ARG, "opts.method must be QDWH or ZOLO");
+  if (out.zolo_r < 0 || out.zolo_r > 8) return fail(HQ_ERR_ARG, "opts.zolo_r must be in [0, 8]");
   if (out.graph)
     return fail(HQ_ERR_UNSUPPORTED,
                 "opts.graph: launching an iteration as a captured HIP graph is disabled (the capture "
@@ -829,6 +832,240 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
   }
 }
 
+// ---- the Zolo-pd driver -----------------------------------------------------------------------
+// Zolo-pd (cited in Sec. 2.1; Nakatsukasa and Freund 2016) on one member: the setup of Alg. 3
+// line 1, then the steps of zolo_schedule, X <- mhat (X + sum_j a_j X (X^T X + c_{2j-1} I)^{-1}):
+//   step 0 (X_0 banded): X_0 (X_0^T X_0 + c I)^{-1} = Q1 Q2^T / sqrt(c) with [X_0 / sqrt(c); I] =
+//     [Q1; Q2] R, the structured QR of Algorithms 1/2 at scale 1 / (sqrt(c) alpha) (r sweeps on
+//     the host, r products in one batch);
+//   steps k >= 1: G = X^T X + c_1 I (one product), Z_j = G + (c_{2j-1} - c_1) I sharing G's blocks
+//     (only the leaves differ), their r H-Cholesky factorisations in one batch, Y_j = X L_j^{-T} and
+//     V_j = Y_j L_j^{-1} (two batched products);
+// and X_{k+1} as one HODLR sum of the r + 1 terms.  Capacities come from the previous iterate's
+// ranks (twice plus 16) and double on overflow; the result is symmetrised as in Alg. 3.
+void run_zolo(Member& m, const hq_opts& o, hipStream_t st, bool projector) {
+  const auto t0 = clk::now();
+  m.ab.resize((size_t)m.n * m.ldab);
+  HQ_CHECK(hipMemcpyAsync(m.ab.data(), m.band, sizeof(double) * m.ab.size(), hipMemcpyDeviceToHost, st));
+  HQ_CHECK(hipStreamSynchronize(st));
+  std::memset(&m.inf, 0, sizeof(m.inf));
+  m.t.build(m.n, o.leaf);
+  if (m.t.L > 0 && (int64_t)m.b > m.n / (int64_t(1) << m.t.L))
+    return set_fail(m, HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block; raise opts.leaf");
+  m.beff = (int)std::min<int64_t>(m.b, std::max<int64_t>(1, m.n - 1));
+  const double alpha = norm_inf_shifted(m.ab.data(), m.n, m.beff, m.ldab, m.mu);
+  if (!(alpha > 0.0)) return set_fail(m, HQ_ERR_SINGULAR_SHIFT, "A - mu I is zero");
+  const double dist = certified_distance(m.ab.data(), m.n, m.beff, m.ldab, m.mu, alpha);
+  if (!(dist > 0.0)) return set_fail(m, HQ_ERR_SINGULAR_SHIFT, "mu is numerically an eigenvalue of A");
+  const double l0 = std::max(dist / alpha, 1e-150);
+  const std::vector<hq::ZoloStep> zs = hq::zolo_schedule(l0, o.delta, o.zolo_r, o.max_iter);
+  if (zs.empty()) return set_fail(m, HQ_ERR_NO_CONVERGENCE, "Zolotarev steps did not reach 1 - delta within max_iter");
+  const int K = (int)zs.size(), r = zs[0].r;
+  m.K = K;
+  m.inf.alpha = alpha;
+  m.inf.l0 = dist / alpha;
+  m.inf.iters = K;
+  m.inf.zolo_r = r;
+  m.inf.levels = m.t.L;
+  for (int k = 0; k < K && k < 16; ++k) {
+    m.inf.a[k] = zs[k].mhat;
+    m.inf.b[k] = zs[k].l;
+    m.inf.c[k] = zs[k].c[1];
+  }
+  m.inf.setup_seconds = secs(t0);
+
+  hq::Engine E(st);
+  E.tol = o.tol;
+  hq::DevArena xa[2], it, qa, pa;
+  struct Drain {
+    hipStream_t s;
+    ~Drain() { (void)hipStreamSynchronize(s); }
+  } drain{st};
+  size_t peak = 0;
+  auto note_peak = [&] {
+    peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + E.side_high_water() + xa[0].high_water() +
+                              xa[1].high_water() + it.high_water() + qa.high_water() + pa.high_water());
+  };
+  auto grow = [&](std::vector<int>& cv) {
+    bool g = false;
+    for (int l = 0; l < m.t.L && l < (int)cv.size(); ++l) {
+      const int nc = (int)std::min<int64_t>({(int64_t)cv[l] * 2, (int64_t)o.max_rank, m.t.ldf[l]});
+      g |= nc > cv[l];
+      cv[l] = nc;
+    }
+    return g;
+  };
+  int cur = 0;
+  m.X = E.alloc_hmat_in(xa[cur], &m.t, caps_from(m.t, m.beff, o.max_rank), false);
+  build_x0(E, m.band, m.n, m.beff, m.ldab, m.mu, 1.0 / alpha, m.X);
+  std::unique_ptr<hq::PinnedHost> qimg;
+  std::vector<hq::HostHodlr> h1, h2;
+  std::vector<hq::HMat> Q1(r), Q2(r);
+  for (int k = 0; k < K; ++k) {
+    const hq::ZoloStep& z = zs[k];
+    std::vector<int> capT, capX;  // terms, X_{k+1}
+    if (k == 0) {
+      // r structured QR sweeps on the host (in parallel), their Q factors copied to the device
+      const auto tg = clk::now();
+      const std::vector<int> capQ(m.t.L, 2 * m.beff);
+      const size_t per = 2 * hq::host_hodlr_doubles(m.t, capQ, (int)m.t.maxleaf);
+      h1.assign(r, hq::HostHodlr());
+      h2.assign(r, hq::HostHodlr());
+      qimg.reset(new hq::PinnedHost(sizeof(double) * per * r));
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int j = 0; j < r; ++j)
+        hq::q_factors_from_band(m.ab.data(), m.n, m.beff, m.ldab, m.mu, 1.0 / (std::sqrt(z.c[2 * j + 1]) * alpha), m.t,
+                                capQ, (int)m.t.maxleaf, h1[j], h2[j], qimg->as<double>() + per * j);
+      m.inf.givens_seconds = secs(tg);
+      HQ_CHECK(hipStreamSynchronize(st));
+      for (int j = 0; j < r; ++j) {
+        Q1[j] = E.alloc_hmat_in(qa, &m.t, capQ, false);
+        Q2[j] = E.alloc_hmat_in(qa, &m.t, capQ, false);
+        upload_host(E, h1[j], Q1[j], false);
+        upload_host(E, h2[j], Q2[j], false);
+      }
+      capT = caps_from(m.t, 3 * m.beff + 8, o.max_rank);
+      capX = caps_from(m.t, 2 * (3 * m.beff + 8), o.max_rank);
+    } else {
+      const std::vector<int> rk = E.read_ranks(m.X);
+      capT = caps_grow(m.t, rk, o.max_rank, 2, 16);
+      capX = capT;
+    }
+    for (int attempt = 0;; ++attempt) {
+      E.stage.reset();
+      E.scratch.reset();
+      it.reset();
+      xa[cur ^ 1].reset();
+      m.Xn = E.alloc_hmat_in(xa[cur ^ 1], &m.t, capX, false);
+      m.inf.capacity_columns += capacity_columns(m.t, capX);
+      E.clear_flags(1);
+      std::vector<hq::HMat> V(r);
+      hq::Engine::SumTask sum;
+      sum.C = &m.Xn;
+      sum.fidx = 0;
+      sum.terms.push_back({z.mhat, &m.X});
+      if (k == 0) {
+        std::vector<hq::Engine::ProdTask> pv;
+        for (int j = 0; j < r; ++j) {
+          V[j] = E.alloc_hmat_in(it, &m.t, capT, false);
+          hq::Engine::ProdTask q;
+          q.A = E.view(Q1[j]);
+          q.B = E.view(Q2[j], true);
+          q.alpha = z.mhat * z.a[j + 1] / std::sqrt(z.c[2 * j + 1]);
+          q.C = &V[j];
+          q.fidx = 0;
+          pv.push_back(q);
+        }
+        E.product(pv);
+      } else {
+        // G = X^T X + c_1 I, then Z_j = G + (c_{2j-1} - c_1) I with their own leaves
+        hq::HMat G = E.alloc_hmat_in(it, &m.t, capT, true);
+        hq::Engine::ProdTask q;
+        q.A = E.view(m.X, true);
+        q.B = E.view(m.X);
+        q.d_identity = true;
+        q.alpha = 1.0;
+        q.delta = z.c[1];
+        q.C = &G;
+        q.fidx = 0;
+        E.product(std::vector<hq::Engine::ProdTask>{q});
+        E.scratch.reset();
+        std::vector<hq::HMat> Zj(r, G), Li(r), Lf(r), Y(r);
+        std::vector<hq::LeafAxpy> ax;
+        for (int j = 1; j < r; ++j) {
+          Zj[j].leaves = it.get<double>((size_t)m.t.nleaves * G.ldl * G.ldl);
+          for (int qn = m.t.ninternal; qn < m.t.nnodes; ++qn) {
+            const int li = m.t.leaf_index(qn);
+            hq::LeafAxpy x{};
+            x.out = Zj[j].leaf(li); x.ldo = G.ldl; x.X = G.leaf(li); x.ldx = G.ldl; x.m = (int)m.t.size(qn);
+            x.alpha = 1.0;
+            x.gamma = z.c[2 * j + 1] - z.c[1];
+            ax.push_back(x);
+          }
+        }
+        if (!ax.empty()) {
+          hq::launch_leaf_axpy(E.stage.upload(ax, st), (int)ax.size(), (int)m.t.maxleaf, st);
+          ++E.launches;
+        }
+        const int capS = 2 * max_of(capT) + 16;
+        const std::vector<int> capW = E.chol_work_caps(m.t, capT, capS);
+        std::vector<hq::Engine::CholTask> pc;
+        for (int j = 0; j < r; ++j) {
+          Li[j] = E.alloc_hmat_in(it, &m.t, capT, false);
+          Lf[j] = E.alloc_hmat_in(it, &m.t, capW, false);
+          Y[j] = E.alloc_hmat_in(it, &m.t, capT, false);
+          V[j] = E.alloc_hmat_in(it, &m.t, capT, false);
+          pc.push_back(hq::Engine::CholTask{&Zj[j], &Li[j], &Lf[j], capS, 0});
+        }
+        E.cholesky_inverse(pc);
+        E.scratch.reset();
+        std::vector<hq::Engine::ProdTask> py, pv;
+        for (int j = 0; j < r; ++j) {
+          hq::Engine::ProdTask a;
+          a.A = E.view(m.X);
+          a.B = E.view(Li[j], true);  // Y_j = X L_j^{-T}
+          a.C = &Y[j];
+          a.fidx = 0;
+          py.push_back(a);
+          hq::Engine::ProdTask b;
+          b.A = E.view(Y[j]);
+          b.B = E.view(Li[j]);  // V_j = Y_j L_j^{-1} = X Z_j^{-1}, weighted
+          b.alpha = z.mhat * z.a[j + 1];
+          b.C = &V[j];
+          b.fidx = 0;
+          pv.push_back(b);
+        }
+        E.product(py);
+        E.scratch.reset();
+        E.product(pv);
+      }
+      E.scratch.reset();
+      for (int j = 0; j < r; ++j) sum.terms.push_back({1.0, &V[j]});
+      E.sum(std::vector<hq::Engine::SumTask>{sum});
+      note_peak();
+      const int f = E.read_flags(1)[0];
+      if (f & 2) return set_fail(m, HQ_ERR_NOT_POSDEF, "a leaf of X^T X + c I is not positive definite");
+      if (f & (8 | 16 | 32)) return set_fail(m, HQ_ERR_NONFINITE, "non-finite values in a recompression");
+      if (f & 4) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
+      if (f & 1) {
+        const bool g1 = grow(capT), g2 = grow(capX);
+        if ((!g1 && !g2) || attempt > 6) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
+        ++m.inf.redo_count;
+        continue;
+      }
+      break;
+    }
+    m.X = m.Xn;
+    cur ^= 1;
+    if (k < 16) m.inf.max_rank_iter[k] = max_of(E.read_ranks(m.X));
+  }
+  // Alg. 3 lines 17-18: U = X_K (symmetrised), P = (I - U)/2
+  std::vector<int> cp = caps_grow(m.t, E.read_ranks(m.X), o.max_rank, 1, 0);
+  for (int attempt = 0;; ++attempt) {
+    pa.reset();
+    E.stage.reset();
+    E.scratch.reset();
+    m.P = E.alloc_hmat_in(pa, &m.t, cp, false);
+    E.clear_flags(1);
+    E.sym_affine(std::vector<hq::Engine::AffTask>{{&m.X, &m.P, projector ? -0.5 : 1.0, projector ? 0.5 : 0.0, 0}});
+    note_peak();
+    const int f = E.read_flags(1)[0];
+    if (f & (8 | 16 | 32)) return set_fail(m, HQ_ERR_NONFINITE, "non-finite values in the symmetrisation");
+    if (f & 4) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
+    if (f & 1) {
+      if (!grow(cp) || attempt > 6) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
+      continue;
+    }
+    break;
+  }
+  m.out = compact_copy(E, m.P, st, o.leaf);
+  m.inf.max_rank = m.out ? max_of(E.read_ranks(m.out->H)) : 0;
+  m.inf.bytes = (int64_t)m.out->H.bytes();
+  m.inf.peak_bytes = (int64_t)peak;
+  m.inf.launches = E.launches;
+  m.inf.seconds = secs(t0);
+}
+
 hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu, const hq_opts& o, hipStream_t st,
                    bool projector, hq_hodlr_t* out, hq_info* info) {
   std::vector<Member> ms(1);
@@ -837,7 +1074,10 @@ hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu
   ms[0].b = b;
   ms[0].ldab = ldab;
   ms[0].mu = mu;
-  run_batch(ms, o, st, projector);
+  if (o.method == HQ_METHOD_ZOLO)
+    run_zolo(ms[0], o, st, projector);
+  else
+    run_batch(ms, o, st, projector);
   Member& m = ms[0];
   if (m.status != HQ_OK) {
     if (m.out) hodlr_destroy(m.out);
@@ -865,6 +1105,8 @@ hq_status hq_default_opts(hq_opts* o) {
   o->precision = HQ_FP64;
   o->c_fp32_max = 16.0;
   o->graph = 0;
+  o->method = HQ_METHOD_QDWH;
+  o->zolo_r = 0;
   return HQ_OK;
 }
 
@@ -980,7 +1222,10 @@ hq_status spectral_projector_batched(int32_t count, const double* const* bands, 
         chunk[i - i0].ldab = ms[i].ldab;
         chunk[i - i0].mu = ms[i].mu;
       }
-      run_batch(chunk, o, (hipStream_t)stream, true);
+      if (o.method == HQ_METHOD_ZOLO)
+        for (Member& c : chunk) run_zolo(c, o, (hipStream_t)stream, true);
+      else
+        run_batch(chunk, o, (hipStream_t)stream, true);
       for (int i = i0; i < i1; ++i) {
         Member& c = chunk[i - i0];
         ms[i].status = c.status;
@@ -1413,6 +1658,19 @@ hq_status hq_test_schedule(double l0, double delta, int32_t max_iter, double* a,
     }
     l[w.a.size()] = w.lK;
     *K = (int32_t)w.a.size();
+    return HQ_OK;
+  });
+}
+
+hq_status hq_test_zolo(double l, int32_t r, double* c, double* a, double* mhat, double* lnext) {
+  if (!c || !a || !mhat || !lnext) return fail(HQ_ERR_ARG, "NULL output");
+  if (!(l >= 1e-150 && l < 1.0) || r < 1 || r > 16) return fail(HQ_ERR_ARG, "l must be in [1e-150, 1), r in [1, 16]");
+  return guard([&] {
+    const hq::ZoloStep z = hq::zolo_step(l, r);
+    for (int i = 0; i <= 2 * r; ++i) c[i] = z.c[i];
+    for (int j = 0; j <= r; ++j) a[j] = z.a[j];
+    *mhat = z.mhat;
+    *lnext = z.lnext;
     return HQ_OK;
   });
 }

@@ -301,6 +301,10 @@ class Engine {
   void leaf_chol_inv(const std::vector<LeafTask>& blocks);
   void cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) { cholesky_inverse({CholTask{&Z, &Linv, &Lf, capS, 0}}); }
   // out = sid * I + sx * (X + X^T) / 2 as a full HODLR (sign: sx = 1, sid = 0; projector: -1/2, 1/2)
+  // C = sum_i w_i T_i (general HODLR matrices of one tree, at most kStackSrc terms): each block's
+  // factors stacked with the weights on the U side and recompressed at tol; leaves summed.
+  struct SumTask { std::vector<std::pair<double, const HMat*>> terms; HMat* C; int fidx; };
+  void sum(const std::vector<SumTask>& v);
   struct AffTask { const HMat* X; HMat* P; double sx, sid; int fidx; };
   void sym_affine(const std::vector<AffTask>& v);
   void sym_affine(const HMat& X, HMat& P, double sx, double sid) { sym_affine({AffTask{&X, &P, sx, sid, 0}}); }

@@ -1440,6 +1440,82 @@ void Engine::sym_affine(const std::vector<AffTask>& batch) {
   }
 }
 
+void Engine::sum(const std::vector<SumTask>& batch) {
+  if (batch.empty()) return;
+  std::vector<StackTask> stk;
+  std::vector<RecTask> rec;
+  int maxrows = 1, ldlmax = 1, nmax = 0;
+  for (const SumTask& T : batch) {
+    const int nt = (int)T.terms.size();
+    if (nt < 1 || nt > kStackSrc) throw std::invalid_argument("Engine::sum: 1 to kStackSrc terms");
+    const Tree* t = T.C->t;
+    for (const auto& w : T.terms)
+      if (w.second->t != t || w.second->lower_only) throw std::invalid_argument("Engine::sum: terms of another tree");
+    nmax = std::max(nmax, nt);
+    ldlmax = std::max(ldlmax, (int)t->maxleaf);
+    for (int p = 0; p < t->ninternal; ++p) {
+      const int l = Tree::level(p), ldc = (int)t->ldf[l];
+      const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
+      maxrows = std::max<int>(maxrows, (int)std::max(sa, sb));
+      int rcap = 0;
+      for (const auto& w : T.terms) rcap += w.second->cap[l];
+      rcap = std::max(1, std::min(kMaxStack, rcap));  // wider: flagged by k_stack
+      for (int s = 0; s < 2; ++s) {
+        const int64_t mr = s == 0 ? sa : sb, mc = s == 0 ? sb : sa;
+        double* Us = scratch.get<double>((size_t)ldc * rcap);
+        double* Vs = scratch.get<double>((size_t)ldc * rcap);
+        int* rs = scratch.get<int>(1);
+        StackTask su{};
+        su.dst = Us; su.ld = ldc; su.rows = (int)mr; su.wcap = rcap; su.wout = rs; su.nsrc = nt; su.fidx = T.fidx;
+        StackTask sv = su;
+        sv.dst = Vs; sv.rows = (int)mc; sv.wout = nullptr;
+        for (int i = 0; i < nt; ++i) {
+          const HMat& H = *T.terms[i].second;
+          su.src[i] = {H.U(p, s), H.rk(p, s), ldc, H.cap[l], T.terms[i].first};
+          sv.src[i] = {H.V(p, s), H.rk(p, s), ldc, H.cap[l], 1.0};
+        }
+        stk.push_back(su);
+        stk.push_back(sv);
+        RecTask r{};
+        r.Us = Us; r.ldus = ldc; r.m = (int)mr; r.Vs = Vs; r.ldvs = ldc; r.n = (int)mc; r.r = rs; r.rcap = rcap;
+        r.U = T.C->U(p, s); r.V = T.C->V(p, s); r.ldu = r.ldv = ldc; r.rank = T.C->rk(p, s); r.kcap = T.C->cap[l];
+        r.thresh = tol; r.fidx = T.fidx;
+        rec.push_back(r);
+      }
+    }
+  }
+  stack(stk, maxrows);
+  recompress(rec);
+  // leaves: out = w_0 T_0 + w_1 T_1, then out += w_i T_i, one launch per term for all leaves
+  for (int i = 0; i == 0 || i < nmax; i = i == 0 ? 2 : i + 1) {
+    std::vector<LeafAxpy> ax;
+    for (const SumTask& T : batch) {
+      const int nt = (int)T.terms.size();
+      if (i > 0 && i >= nt) continue;
+      const Tree* t = T.C->t;
+      for (int q = t->ninternal; q < t->nnodes; ++q) {
+        const int li = t->leaf_index(q);
+        LeafAxpy x{};
+        x.out = T.C->leaf(li); x.ldo = T.C->ldl; x.m = (int)t->size(q);
+        if (i == 0) {
+          x.X = T.terms[0].second->leaf(li); x.ldx = T.terms[0].second->ldl; x.alpha = T.terms[0].first;
+          if (nt > 1) {
+            x.Y = T.terms[1].second->leaf(li); x.ldy = T.terms[1].second->ldl; x.beta = T.terms[1].first;
+          }
+        } else {
+          x.X = x.out; x.ldx = x.ldo; x.alpha = 1.0;
+          x.Y = T.terms[i].second->leaf(li); x.ldy = T.terms[i].second->ldl; x.beta = T.terms[i].first;
+        }
+        ax.push_back(x);
+      }
+    }
+    if (!ax.empty()) {
+      launch_leaf_axpy(stage.upload(ax, st), (int)ax.size(), ldlmax, st);
+      ++launches;
+    }
+  }
+}
+
 void Engine::copy_hmat(const HMat& src, HMat& dst) {
   const Tree* t = src.t;
   HQ_CHECK(hipMemcpyAsync(dst.leaves, src.leaves, sizeof(double) * (size_t)t->nleaves * src.ldl * src.ldl,

@@ -74,12 +74,13 @@ struct StackSrc {
   int ld, w;
   double scale;
 };
+constexpr int kStackSrc = 10;  // most sources of one stack (a sum of up to nine terms and a D block)
 struct StackTask {
   double* dst;
   int* wout;      // receives the total width (may be null)
   int ld, rows, nsrc, wcap;  // wcap: capacity of dst in columns (overflow -> flag[fidx])
   int fidx;
-  StackSrc src[4];
+  StackSrc src[kStackSrc];
 };
 
 // R-only Householder QR of a tall matrix, tree-reduced (TSQR).  Stage 0 copies a row tile of

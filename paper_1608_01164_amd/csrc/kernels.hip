@@ -233,20 +233,18 @@ template <> struct Prec<float> {
 // chunk's MFMAs.  A task with a split-K workspace runs its K ranges in separate workgroups
 // (blockIdx.z) that write raw partial tiles; k_gemm_reduce sums them in range order.
 // ----------------------------------------------------------------------------------------------
-constexpr int GT = 64, GK = 16;
+constexpr int GT = 64, GK = 16, GQ = GT * GK / 256;  // GQ: elements of each operand a thread stages per chunk
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Staging map of the 4 elements a thread loads per chunk: (kk, i) of element q for a tile stored
-// column-major with leading dimension ld (op = 0: element (i, kk); op = 1: element (kk, i)).
-static __device__ __forceinline__ void stage_index(int op, int tid, int q, int& kk, int& i) {
-  if (op == 0) {
-    i = tid & 63;
-    kk = (tid >> 6) + 4 * q;
-  } else {
-    kk = tid & 15;
-    i = (tid >> 4) + 16 * q;
-  }
+// Staging map of the GQ elements a thread loads per chunk: (kk, i) of element q for a tile stored
+// column-major (op = 0: element (i, kk), consecutive threads on consecutive rows i; op = 1: element
+// (kk, i), consecutive threads on consecutive kk).
+static __device__ __forceinline__ int stage_kk(int op, int tid, int q) {
+  return op == 0 ? (tid / GT) + (256 / GT) * q : tid & (GK - 1);
+}
+static __device__ __forceinline__ int stage_i(int op, int tid, int q) {
+  return op == 0 ? tid & (GT - 1) : (tid / GK) + (256 / GK) * q;
 }
 
 // T = double: FP64 MFMA 16x16x4; T = float: operands rounded to FP32, FP32 MFMA 16x16x4 with FP32
@@ -285,20 +283,18 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
 
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-  T ra[4], rb[4];
+  T ra[GQ], rb[GQ];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int kk, i;
-      stage_index(Tk.opA, tid, q, kk, i);
+    for (int q = 0; q < GQ; ++q) {
       {
-        const int gi = row0 + i, gk = k0 + kk;
+        const int gi = row0 + stage_i(Tk.opA, tid, q), gk = k0 + stage_kk(Tk.opA, tid, q);
         const bool in = gi < m && gk < ke;
         ra[q] = (T)(in ? (Tk.opA == 0 ? Tk.A[gi + (size_t)gk * Tk.lda] : Tk.A[gk + (size_t)gi * Tk.lda]) : 0.0);
       }
-      stage_index(Tk.opB == 0 ? 1 : 0, tid, q, kk, i);
       {
-        const int gj = col0 + i, gk = k0 + kk;
+        const int ob = Tk.opB == 0 ? 1 : 0;
+        const int gj = col0 + stage_i(ob, tid, q), gk = k0 + stage_kk(ob, tid, q);
         const bool in = gj < n && gk < ke;
         rb[q] = (T)(in ? (Tk.opB == 0 ? Tk.B[gk + (size_t)gj * Tk.ldb] : Tk.B[gj + (size_t)gk * Tk.ldb]) : 0.0);
       }
@@ -307,12 +303,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
   if (kb < ke) load(kb);
   for (int k0 = kb; k0 < ke; k0 += GK) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int kk, i;
-      stage_index(Tk.opA, tid, q, kk, i);
-      As[kk][i] = ra[q];
-      stage_index(Tk.opB == 0 ? 1 : 0, tid, q, kk, i);
-      Bs[kk][i] = rb[q];
+    for (int q = 0; q < GQ; ++q) {
+      const int ob = Tk.opB == 0 ? 1 : 0;
+      As[stage_kk(Tk.opA, tid, q)][stage_i(Tk.opA, tid, q)] = ra[q];
+      Bs[stage_kk(ob, tid, q)][stage_i(ob, tid, q)] = rb[q];
     }
     __syncthreads();
     if (k0 + GK < ke) load(k0 + GK);
@@ -399,35 +393,53 @@ void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool
 // ----------------------------------------------------------------------------------------------
 // Column stacking with scaling at device-determined offsets.
 // ----------------------------------------------------------------------------------------------
+// A workgroup covers 64 rows and 4 column phases; blockIdx.z spreads the columns further, so that a
+// stack of a few thousand rows still fills many workgroups, and each thread has four loads in flight
+// before it stores.
+constexpr int STK_ROWS = 64, STK_PH = 4, STK_Z = 4;
 __global__ __launch_bounds__(256) void k_stack(const StackTask* __restrict__ tasks, int* flag) {
   const StackTask* T = tasks + blockIdx.y;
-  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int row = blockIdx.x * STK_ROWS + (threadIdx.x & (STK_ROWS - 1));
+  const int c0 = blockIdx.z * STK_PH + threadIdx.x / STK_ROWS, cs = STK_PH * gridDim.z;
   const int rows = T->rows, ld = T->ld, nsrc = T->nsrc, wcap = T->wcap;
-  double* dst = T->dst;
+  const bool lead = blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0;
+  double* __restrict__ dst = T->dst;
   int off = 0;
   for (int s = 0; s < nsrc; ++s) {
-    const double* p = T->src[s].p;
+    const double* __restrict__ p = T->src[s].p;
     const int* wp = T->src[s].wp;
     const int lds = T->src[s].ld;
     const double sc = T->src[s].scale;
     int w = wp ? *wp : T->src[s].w;
     if (off + w > wcap) {
       w = wcap - off;
-      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag + T->fidx, 4);
+      if (lead) atomicOr(flag + T->fidx, 4);
     }
-    if (row < rows)
-      for (int c = 0; c < w; ++c) dst[row + (size_t)(off + c) * ld] = sc * p[row + (size_t)c * lds];
+    if (row < rows) {
+      const double* q = p + row;
+      double* d = dst + row + (size_t)off * ld;
+      int c = c0;
+      for (; c + 3 * cs < w; c += 4 * cs) {
+        const double v0 = q[(size_t)c * lds], v1 = q[(size_t)(c + cs) * lds];
+        const double v2 = q[(size_t)(c + 2 * cs) * lds], v3 = q[(size_t)(c + 3 * cs) * lds];
+        d[(size_t)c * ld] = sc * v0;
+        d[(size_t)(c + cs) * ld] = sc * v1;
+        d[(size_t)(c + 2 * cs) * ld] = sc * v2;
+        d[(size_t)(c + 3 * cs) * ld] = sc * v3;
+      }
+      for (; c < w; c += cs) d[(size_t)c * ld] = sc * q[(size_t)c * lds];
+    }
     off += w;
   }
-  if (T->wout && blockIdx.x == 0 && threadIdx.x == 0) *T->wout = off;
+  if (T->wout && lead) *T->wout = off;
 }
 
 void launch_stack(const StackTask* d_tasks, int ntasks, int max_rows, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
-  const int bx = max_rows > 0 ? (max_rows + 255) / 256 : 1;
+  const int bx = max_rows > 0 ? (max_rows + STK_ROWS - 1) / STK_ROWS : 1;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    HQ_TIMED(K_STACK, s, hipLaunchKernelGGL(k_stack, dim3(bx, nt), dim3(256), 0, s, d_tasks + t0, flag));
+    HQ_TIMED(K_STACK, s, hipLaunchKernelGGL(k_stack, dim3(bx, nt, STK_Z), dim3(256), 0, s, d_tasks + t0, flag));
   }
 }
 
