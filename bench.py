@@ -251,6 +251,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="disable the library's per-launch kernel timers")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: middle QDWH iterations in FP32 (GEMM on FP32 MFMA, FP32 TSQR and core SVD)")
+    ap.add_argument("--method", default="qdwh", choices=["qdwh", "zolo"],
+                    help="zolo: Zolo-pd (two Zolotarev steps, FP64) instead of the QDWH iterations")
     ap.add_argument("--no-predictor", action="store_true",
                     help="capacities from the previous iterate's ranks instead of the trained rank predictor")
     ap.add_argument("--graph", action="store_true",
@@ -287,7 +289,7 @@ def main():
         if last:
             hq.profile(True)
         P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision,
-                                        graph=args.graph)
+                                        graph=args.graph, method=args.method)
         P.close()
         if last:
             prof_w = hq.profile_read()
@@ -304,7 +306,7 @@ def main():
         if P is not None:
             P.close()
         P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=pred, precision=args.precision,
-                                        graph=args.graph)
+                                        graph=args.graph, method=args.method)
         infos.append(info)
         print(f"# step {i}: {info['seconds']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -322,7 +324,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "b": b, "leaf": leaf, "tol": tol, "nu": nu, "mu": mu,
-                   "gap": gap, "precision": args.precision, "parallelism": "single-gpu",
+                   "gap": gap, "precision": args.precision, "method": args.method, "parallelism": "single-gpu",
                    "capacities": "predictor" if pred is not None else "previous ranks"},
         "iters": info["iters"], "max_rank": info["max_rank"], "launches": info["launches"],
         "setup_s": info["setup_seconds"], "givens_s": info["givens_seconds"], "peak_bytes": info["peak_bytes"],
@@ -336,7 +338,7 @@ def main():
         out["kernels"] = kernel_table(prof_w if prof_w is not None else prof)
         out["kernels_source"] = "last warmup step, every kernel class timed" if prof_w is not None else "timed steps"
         out["core_svd_phases"] = svd_stats
-    if not args.no_legs and args.workload == DEFAULT and args.precision == "fp64":
+    if not args.no_legs and args.workload == DEFAULT and args.precision == "fp64" and args.method == "qdwh":
         out["legs"] = legs(hq, band, b, mu, leaf, tol, pred, P, value, n)
     P.close()
     if not args.no_cpu_baseline:
@@ -369,8 +371,9 @@ def legs(hq, band, b, mu, leaf, tol, pred, P64, value64, n):
 
 
 def batched_legs(hq, count, pred, leaf=128, tol=1e-10):
-    """count matrices of the batched generator in one spectral_projector_batched call, FP64 and mixed
-    (one warmup and one timed call each); the mixed members' errors against the FP64 ones."""
+    """count matrices of the batched generator in one spectral_projector_batched call: QDWH in FP64 and
+    mixed precision, and Zolo-pd (one warmup and one timed call each); the errors of the mixed and
+    Zolo-pd members against the FP64 ones."""
     import torch
     import workloads as wl
     mats = wl.batched_banded(count, seed=0)
@@ -379,12 +382,12 @@ def batched_legs(hq, count, pred, leaf=128, tol=1e-10):
     bands = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in mats]
     res = {"count": count, "sum_n": int(sum(m.shape[0] for m in mats))}
     keep = {}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "zolo"):
+        kw = {"method": "zolo"} if prec == "zolo" else {"precision": prec}
         for rep in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol, predictor=pred,
-                                                          precision=prec)
+            Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol, predictor=pred, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             if st != 0:
@@ -400,6 +403,9 @@ def batched_legs(hq, count, pred, leaf=128, tol=1e-10):
     res["mixed"]["err_vs_fp64_2norm_largest_member"] = difference_norm(keep["mixed"][j], keep["fp64"][j],
                                                                        mats[j].shape[0])
     res["mixed"]["vs_fp64_batched"] = res["mixed"]["value"] / res["fp64"]["value"]
+    res["zolo"]["err_vs_fp64_2norm_largest_member"] = difference_norm(keep["zolo"][j], keep["fp64"][j],
+                                                                      mats[j].shape[0])
+    res["zolo"]["vs_fp64_batched"] = res["zolo"]["value"] / res["fp64"]["value"]
     for Ps in keep.values():
         for P in Ps:
             P.close()
@@ -427,7 +433,7 @@ def main_batched(args, count, leaf=128, tol=1e-10):
 
     def step():
         Ps, infos, st = hq.spectral_projector_batched(bands, bs, mus, leaf=leaf, tol=tol, predictor=pred,
-                                                      precision=args.precision)
+                                                      precision=args.precision, method=args.method)
         if st != 0:
             bad = [(i, mats[i].shape[0], bs[i], mg[i][1]) for i, P in enumerate(Ps) if P is None]
             print(f"# failed members (index, n, b, gap): {bad}; {hq.lib().hq_last_error().decode()}",
@@ -478,7 +484,7 @@ def main_batched(args, count, leaf=128, tol=1e-10):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
         "config": {"workload": args.workload, "count": count, "sum_n": nsum, "leaf": leaf, "tol": tol,
-                   "precision": args.precision, "parallelism": "single-gpu, batched",
+                   "precision": args.precision, "method": args.method, "parallelism": "single-gpu, batched",
                    "capacities": "predictor" if pred is not None else "previous ranks"},
         "iters_max": max(i["iters"] for i in infos), "max_rank": max(i["max_rank"] for i in infos),
         "redo_count": sum(i["redo_count"] for i in infos), "launches": infos[0]["launches"],

@@ -73,8 +73,8 @@ typedef struct {
                                 two steps in all; the first step takes r structured QR factorisations
                                 of [X_0; sqrt(c_{2j-1}) I] (Algorithms 1/2), the later ones r
                                 H-Cholesky factorisations of X^T X + c_{2j-1} I issued as one batch.
-                                FP64 only (precision and predictor are ignored); batched calls solve
-                                their members one after another. */
+                                FP64 only (precision and predictor are ignored); batched calls advance
+                                their members together, each with its own degree and schedule. */
   int32_t zolo_r;            /* HQ_METHOD_ZOLO: the degree r in [1, 8]; 0 (default) picks the smallest
                                 r reaching |1 - l_K| <= delta in two steps (r = 8 and more steps when
                                 none does) */

@@ -833,50 +833,76 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
 }
 
 // ---- the Zolo-pd driver -----------------------------------------------------------------------
-// Zolo-pd (cited in Sec. 2.1; Nakatsukasa and Freund 2016) on one member: the setup of Alg. 3
-// line 1, then the steps of zolo_schedule, X <- mhat (X + sum_j a_j X (X^T X + c_{2j-1} I)^{-1}):
+// Zolo-pd (cited in Sec. 2.1; Nakatsukasa and Freund 2016): the setup of Alg. 3 line 1, then the
+// steps of zolo_schedule, X <- mhat (X + sum_j a_j X (X^T X + c_{2j-1} I)^{-1}):
 //   step 0 (X_0 banded): X_0 (X_0^T X_0 + c I)^{-1} = Q1 Q2^T / sqrt(c) with [X_0 / sqrt(c); I] =
-//     [Q1; Q2] R, the structured QR of Algorithms 1/2 at scale 1 / (sqrt(c) alpha) (r sweeps on
-//     the host, r products in one batch);
-//   steps k >= 1: G = X^T X + c_1 I (one product), Z_j = G + (c_{2j-1} - c_1) I sharing G's blocks
-//     (only the leaves differ), their r H-Cholesky factorisations in one batch, Y_j = X L_j^{-T} and
-//     V_j = Y_j L_j^{-1} (two batched products);
-// and X_{k+1} as one HODLR sum of the r + 1 terms.  Capacities come from the previous iterate's
-// ranks (twice plus 16) and double on overflow; the result is symmetrised as in Alg. 3.
-void run_zolo(Member& m, const hq_opts& o, hipStream_t st, bool projector) {
+//     [Q1; Q2] R, the structured QR of Algorithms 1/2 at scale 1 / (sqrt(c) alpha) (all sweeps of all
+//     members on the host in parallel, all products in one batch);
+//   steps k >= 1: G = X^T X + c_1 I (one product per member), Z_j = G + (c_{2j-1} - c_1) I sharing
+//     G's blocks (only the leaves differ), all H-Cholesky factorisations in one lockstep batch,
+//     Y_j = X L_j^{-T} and V_j = Y_j L_j^{-1} (two batched products);
+// and X_{k+1} as one HODLR sum of the r + 1 terms per member.  Members of a batch advance together
+// (each with its own schedule, degree and status word); capacities come from the previous iterate's
+// ranks (twice plus 16) and double for the members that overflow; a member is symmetrised as in
+// Alg. 3 as soon as its schedule ends.
+void run_zolo(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool projector) {
   const auto t0 = clk::now();
-  m.ab.resize((size_t)m.n * m.ldab);
-  HQ_CHECK(hipMemcpyAsync(m.ab.data(), m.band, sizeof(double) * m.ab.size(), hipMemcpyDeviceToHost, st));
-  HQ_CHECK(hipStreamSynchronize(st));
-  std::memset(&m.inf, 0, sizeof(m.inf));
-  m.t.build(m.n, o.leaf);
-  if (m.t.L > 0 && (int64_t)m.b > m.n / (int64_t(1) << m.t.L))
-    return set_fail(m, HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block; raise opts.leaf");
-  m.beff = (int)std::min<int64_t>(m.b, std::max<int64_t>(1, m.n - 1));
-  const double alpha = norm_inf_shifted(m.ab.data(), m.n, m.beff, m.ldab, m.mu);
-  if (!(alpha > 0.0)) return set_fail(m, HQ_ERR_SINGULAR_SHIFT, "A - mu I is zero");
-  const double dist = certified_distance(m.ab.data(), m.n, m.beff, m.ldab, m.mu, alpha);
-  if (!(dist > 0.0)) return set_fail(m, HQ_ERR_SINGULAR_SHIFT, "mu is numerically an eigenvalue of A");
-  const double l0 = std::max(dist / alpha, 1e-150);
-  const std::vector<hq::ZoloStep> zs = hq::zolo_schedule(l0, o.delta, o.zolo_r, o.max_iter);
-  if (zs.empty()) return set_fail(m, HQ_ERR_NO_CONVERGENCE, "Zolotarev steps did not reach 1 - delta within max_iter");
-  const int K = (int)zs.size(), r = zs[0].r;
-  m.K = K;
-  m.inf.alpha = alpha;
-  m.inf.l0 = dist / alpha;
-  m.inf.iters = K;
-  m.inf.zolo_r = r;
-  m.inf.levels = m.t.L;
-  for (int k = 0; k < K && k < 16; ++k) {
-    m.inf.a[k] = zs[k].mhat;
-    m.inf.b[k] = zs[k].l;
-    m.inf.c[k] = zs[k].c[1];
+  const int nm = (int)ms.size();
+  if (nm > hq::Engine::kFlagSlots) throw std::runtime_error("batch larger than the engine's status slots");
+  for (Member& m : ms) {
+    m.ab.resize((size_t)m.n * m.ldab);
+    HQ_CHECK(hipMemcpyAsync(m.ab.data(), m.band, sizeof(double) * m.ab.size(), hipMemcpyDeviceToHost, st));
   }
-  m.inf.setup_seconds = secs(t0);
+  HQ_CHECK(hipStreamSynchronize(st));
+  std::vector<std::vector<hq::ZoloStep>> zs(nm);
+#pragma omp parallel for schedule(dynamic, 1) if (nm > 1)
+  for (int i = 0; i < nm; ++i) {
+    Member& m = ms[i];
+    const auto ts = clk::now();
+    std::memset(&m.inf, 0, sizeof(m.inf));
+    m.t.build(m.n, o.leaf);
+    if (m.t.L > 0 && (int64_t)m.b > m.n / (int64_t(1) << m.t.L)) {
+      set_fail(m, HQ_ERR_UNSUPPORTED, "bandwidth exceeds the smallest diagonal block; raise opts.leaf");
+      continue;
+    }
+    m.beff = (int)std::min<int64_t>(m.b, std::max<int64_t>(1, m.n - 1));
+    const double alpha = norm_inf_shifted(m.ab.data(), m.n, m.beff, m.ldab, m.mu);
+    if (!(alpha > 0.0)) {
+      set_fail(m, HQ_ERR_SINGULAR_SHIFT, "A - mu I is zero");
+      continue;
+    }
+    const double dist = certified_distance(m.ab.data(), m.n, m.beff, m.ldab, m.mu, alpha);
+    if (!(dist > 0.0)) {
+      set_fail(m, HQ_ERR_SINGULAR_SHIFT, "mu is numerically an eigenvalue of A");
+      continue;
+    }
+    zs[i] = hq::zolo_schedule(std::max(dist / alpha, 1e-150), o.delta, o.zolo_r, o.max_iter);
+    if (zs[i].empty()) {
+      set_fail(m, HQ_ERR_NO_CONVERGENCE, "Zolotarev steps did not reach 1 - delta within max_iter");
+      continue;
+    }
+    m.K = (int)zs[i].size();
+    m.inf.alpha = alpha;
+    m.inf.l0 = dist / alpha;
+    m.inf.iters = m.K;
+    m.inf.zolo_r = zs[i][0].r;
+    m.inf.levels = m.t.L;
+    for (int k = 0; k < m.K && k < 16; ++k) {
+      m.inf.a[k] = zs[i][k].mhat;
+      m.inf.b[k] = zs[i][k].l;
+      m.inf.c[k] = zs[i][k].c[1];
+    }
+    m.inf.setup_seconds = secs(ts);
+  }
+  int Kmax = 0;
+  for (Member& m : ms)
+    if (m.status == HQ_OK) Kmax = std::max(Kmax, m.K);
 
   hq::Engine E(st);
   E.tol = o.tol;
   hq::DevArena xa[2], it, qa, pa;
+  std::unique_ptr<hq::PinnedHost> qimg;
+  std::vector<std::vector<hq::HostHodlr>> h1(nm), h2(nm);
   struct Drain {
     hipStream_t s;
     ~Drain() { (void)hipStreamSynchronize(s); }
@@ -886,7 +912,7 @@ void run_zolo(Member& m, const hq_opts& o, hipStream_t st, bool projector) {
     peak = std::max(peak, E.persist.high_water() + E.scratch.high_water() + E.side_high_water() + xa[0].high_water() +
                               xa[1].high_water() + it.high_water() + qa.high_water() + pa.high_water());
   };
-  auto grow = [&](std::vector<int>& cv) {
+  auto grow = [&](const Member& m, std::vector<int>& cv) {
     bool g = false;
     for (int l = 0; l < m.t.L && l < (int)cv.size(); ++l) {
       const int nc = (int)std::min<int64_t>({(int64_t)cv[l] * 2, (int64_t)o.max_rank, m.t.ldf[l]});
@@ -896,174 +922,279 @@ void run_zolo(Member& m, const hq_opts& o, hipStream_t st, bool projector) {
     return g;
   };
   int cur = 0;
-  m.X = E.alloc_hmat_in(xa[cur], &m.t, caps_from(m.t, m.beff, o.max_rank), false);
-  build_x0(E, m.band, m.n, m.beff, m.ldab, m.mu, 1.0 / alpha, m.X);
-  std::unique_ptr<hq::PinnedHost> qimg;
-  std::vector<hq::HostHodlr> h1, h2;
-  std::vector<hq::HMat> Q1(r), Q2(r);
-  for (int k = 0; k < K; ++k) {
-    const hq::ZoloStep& z = zs[k];
-    std::vector<int> capT, capX;  // terms, X_{k+1}
+  for (Member& m : ms) {
+    if (m.status != HQ_OK) continue;
+    m.X = E.alloc_hmat_in(xa[cur], &m.t, caps_from(m.t, m.beff, o.max_rank), false);
+    build_x0(E, m.band, m.n, m.beff, m.ldab, m.mu, 1.0 / m.inf.alpha, m.X);
+  }
+  std::vector<std::vector<hq::HMat>> Q1(nm), Q2(nm);
+  std::vector<std::vector<int>> capT(nm), capX(nm);  // terms and X_{k+1}, per member
+  for (int k = 0; k < Kmax; ++k) {
+    std::vector<int> act;
+    for (int i = 0; i < nm; ++i)
+      if (ms[i].status == HQ_OK && k < ms[i].K) act.push_back(i);
+    if (act.empty()) break;
     if (k == 0) {
-      // r structured QR sweeps on the host (in parallel), their Q factors copied to the device
+      // every member's r structured QR sweeps on the host in one parallel loop, then the copies
       const auto tg = clk::now();
-      const std::vector<int> capQ(m.t.L, 2 * m.beff);
-      const size_t per = 2 * hq::host_hodlr_doubles(m.t, capQ, (int)m.t.maxleaf);
-      h1.assign(r, hq::HostHodlr());
-      h2.assign(r, hq::HostHodlr());
-      qimg.reset(new hq::PinnedHost(sizeof(double) * per * r));
-#pragma omp parallel for schedule(dynamic, 1)
-      for (int j = 0; j < r; ++j)
-        hq::q_factors_from_band(m.ab.data(), m.n, m.beff, m.ldab, m.mu, 1.0 / (std::sqrt(z.c[2 * j + 1]) * alpha), m.t,
-                                capQ, (int)m.t.maxleaf, h1[j], h2[j], qimg->as<double>() + per * j);
-      m.inf.givens_seconds = secs(tg);
-      HQ_CHECK(hipStreamSynchronize(st));
-      for (int j = 0; j < r; ++j) {
-        Q1[j] = E.alloc_hmat_in(qa, &m.t, capQ, false);
-        Q2[j] = E.alloc_hmat_in(qa, &m.t, capQ, false);
-        upload_host(E, h1[j], Q1[j], false);
-        upload_host(E, h2[j], Q2[j], false);
+      std::vector<std::pair<int, int>> jobs;
+      std::vector<size_t> off(1, 0);
+      for (int i : act) {
+        const Member& m = ms[i];
+        const int r = zs[i][0].r;
+        const size_t per = 2 * hq::host_hodlr_doubles(m.t, std::vector<int>(m.t.L, 2 * m.beff), (int)m.t.maxleaf);
+        h1[i].assign(r, hq::HostHodlr());
+        h2[i].assign(r, hq::HostHodlr());
+        for (int j = 0; j < r; ++j) {
+          jobs.push_back({i, j});
+          off.push_back(off.back() + per);
+        }
       }
-      capT = caps_from(m.t, 3 * m.beff + 8, o.max_rank);
-      capX = caps_from(m.t, 2 * (3 * m.beff + 8), o.max_rank);
+      qimg.reset(new hq::PinnedHost(sizeof(double) * off.back()));
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int q = 0; q < (int)jobs.size(); ++q) {
+        const int i = jobs[q].first, j = jobs[q].second;
+        Member& m = ms[i];
+        const std::vector<int> capQ(m.t.L, 2 * m.beff);
+        hq::q_factors_from_band(m.ab.data(), m.n, m.beff, m.ldab, m.mu,
+                                1.0 / (std::sqrt(zs[i][0].c[2 * j + 1]) * m.inf.alpha), m.t, capQ, (int)m.t.maxleaf,
+                                h1[i][j], h2[i][j], qimg->as<double>() + off[q]);
+      }
+      HQ_CHECK(hipStreamSynchronize(st));
+      for (int i : act) {
+        Member& m = ms[i];
+        const int r = zs[i][0].r;
+        const std::vector<int> capQ(m.t.L, 2 * m.beff);
+        Q1[i].resize(r);
+        Q2[i].resize(r);
+        for (int j = 0; j < r; ++j) {
+          Q1[i][j] = E.alloc_hmat_in(qa, &m.t, capQ, false);
+          Q2[i][j] = E.alloc_hmat_in(qa, &m.t, capQ, false);
+          upload_host(E, h1[i][j], Q1[i][j], false);
+          upload_host(E, h2[i][j], Q2[i][j], false);
+        }
+        m.inf.givens_seconds = secs(tg);
+        capT[i] = caps_from(m.t, 3 * m.beff + 8, o.max_rank);
+        capX[i] = caps_from(m.t, 2 * (3 * m.beff + 8), o.max_rank);
+      }
     } else {
-      const std::vector<int> rk = E.read_ranks(m.X);
-      capT = caps_grow(m.t, rk, o.max_rank, 2, 16);
-      capX = capT;
+      std::vector<const hq::HMat*> xs;
+      for (int i : act) xs.push_back(&ms[i].X);
+      const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+      for (size_t q = 0; q < act.size(); ++q) {
+        capT[act[q]] = caps_grow(ms[act[q]].t, rk[q], o.max_rank, 2, 16);
+        capX[act[q]] = capT[act[q]];
+      }
     }
-    for (int attempt = 0;; ++attempt) {
+    std::vector<int> pend = act;
+    xa[cur ^ 1].reset();
+    for (int attempt = 0; !pend.empty(); ++attempt) {
       E.stage.reset();
       E.scratch.reset();
       it.reset();
-      xa[cur ^ 1].reset();
-      m.Xn = E.alloc_hmat_in(xa[cur ^ 1], &m.t, capX, false);
-      m.inf.capacity_columns += capacity_columns(m.t, capX);
-      E.clear_flags(1);
-      std::vector<hq::HMat> V(r);
-      hq::Engine::SumTask sum;
-      sum.C = &m.Xn;
-      sum.fidx = 0;
-      sum.terms.push_back({z.mhat, &m.X});
+      E.clear_flags(nm);
+      // per member: the r weighted terms V_j (and, for k >= 1, the Cholesky data)
+      std::vector<std::vector<hq::HMat>> V(nm), Li(nm), Lf(nm), Y(nm), Zj(nm);
+      std::vector<hq::HMat> G(nm);
+      std::vector<hq::Engine::SumTask> sums;
+      for (int i : pend) {
+        Member& m = ms[i];
+        m.Xn = E.alloc_hmat_in(xa[cur ^ 1], &m.t, capX[i], false);
+        m.inf.capacity_columns += capacity_columns(m.t, capX[i]);
+        V[i].resize(zs[i][k].r);
+        for (hq::HMat& v : V[i]) v = E.alloc_hmat_in(it, &m.t, capT[i], false);
+      }
       if (k == 0) {
         std::vector<hq::Engine::ProdTask> pv;
-        for (int j = 0; j < r; ++j) {
-          V[j] = E.alloc_hmat_in(it, &m.t, capT, false);
-          hq::Engine::ProdTask q;
-          q.A = E.view(Q1[j]);
-          q.B = E.view(Q2[j], true);
-          q.alpha = z.mhat * z.a[j + 1] / std::sqrt(z.c[2 * j + 1]);
-          q.C = &V[j];
-          q.fidx = 0;
-          pv.push_back(q);
+        for (int i : pend) {
+          const hq::ZoloStep& z = zs[i][k];
+          for (int j = 0; j < z.r; ++j) {
+            hq::Engine::ProdTask q;
+            q.A = E.view(Q1[i][j]);
+            q.B = E.view(Q2[i][j], true);
+            q.alpha = z.mhat * z.a[j + 1] / std::sqrt(z.c[2 * j + 1]);
+            q.C = &V[i][j];
+            q.fidx = i;
+            pv.push_back(q);
+          }
         }
         E.product(pv);
       } else {
         // G = X^T X + c_1 I, then Z_j = G + (c_{2j-1} - c_1) I with their own leaves
-        hq::HMat G = E.alloc_hmat_in(it, &m.t, capT, true);
-        hq::Engine::ProdTask q;
-        q.A = E.view(m.X, true);
-        q.B = E.view(m.X);
-        q.d_identity = true;
-        q.alpha = 1.0;
-        q.delta = z.c[1];
-        q.C = &G;
-        q.fidx = 0;
-        E.product(std::vector<hq::Engine::ProdTask>{q});
+        std::vector<hq::Engine::ProdTask> pg;
+        for (int i : pend) {
+          Member& m = ms[i];
+          G[i] = E.alloc_hmat_in(it, &m.t, capT[i], true);
+          hq::Engine::ProdTask q;
+          q.A = E.view(m.X, true);
+          q.B = E.view(m.X);
+          q.d_identity = true;
+          q.alpha = 1.0;
+          q.delta = zs[i][k].c[1];
+          q.C = &G[i];
+          q.fidx = i;
+          pg.push_back(q);
+        }
+        E.product(pg);
         E.scratch.reset();
-        std::vector<hq::HMat> Zj(r, G), Li(r), Lf(r), Y(r);
         std::vector<hq::LeafAxpy> ax;
-        for (int j = 1; j < r; ++j) {
-          Zj[j].leaves = it.get<double>((size_t)m.t.nleaves * G.ldl * G.ldl);
-          for (int qn = m.t.ninternal; qn < m.t.nnodes; ++qn) {
-            const int li = m.t.leaf_index(qn);
-            hq::LeafAxpy x{};
-            x.out = Zj[j].leaf(li); x.ldo = G.ldl; x.X = G.leaf(li); x.ldx = G.ldl; x.m = (int)m.t.size(qn);
-            x.alpha = 1.0;
-            x.gamma = z.c[2 * j + 1] - z.c[1];
-            ax.push_back(x);
+        std::vector<hq::Engine::CholTask> pc;
+        int maxleaf = 1;
+        for (int i : pend) {
+          Member& m = ms[i];
+          const hq::ZoloStep& z = zs[i][k];
+          maxleaf = std::max(maxleaf, (int)m.t.maxleaf);
+          Zj[i].assign(z.r, G[i]);
+          for (int j = 1; j < z.r; ++j) {
+            Zj[i][j].leaves = it.get<double>((size_t)m.t.nleaves * G[i].ldl * G[i].ldl);
+            for (int qn = m.t.ninternal; qn < m.t.nnodes; ++qn) {
+              const int li = m.t.leaf_index(qn);
+              hq::LeafAxpy x{};
+              x.out = Zj[i][j].leaf(li); x.ldo = G[i].ldl; x.X = G[i].leaf(li); x.ldx = G[i].ldl;
+              x.m = (int)m.t.size(qn); x.alpha = 1.0; x.gamma = z.c[2 * j + 1] - z.c[1];
+              ax.push_back(x);
+            }
           }
+          const int capS = 2 * max_of(capT[i]) + 16;
+          const std::vector<int> capW = E.chol_work_caps(m.t, capT[i], capS);
+          Li[i].resize(z.r);
+          Lf[i].resize(z.r);
+          Y[i].resize(z.r);
+          for (int j = 0; j < z.r; ++j) {
+            Li[i][j] = E.alloc_hmat_in(it, &m.t, capT[i], false);
+            Lf[i][j] = E.alloc_hmat_in(it, &m.t, capW, false);
+            Y[i][j] = E.alloc_hmat_in(it, &m.t, capT[i], false);
+          }
+          for (int j = 0; j < z.r; ++j) pc.push_back(hq::Engine::CholTask{&Zj[i][j], &Li[i][j], &Lf[i][j], capS, i});
         }
         if (!ax.empty()) {
-          hq::launch_leaf_axpy(E.stage.upload(ax, st), (int)ax.size(), (int)m.t.maxleaf, st);
+          hq::launch_leaf_axpy(E.stage.upload(ax, st), (int)ax.size(), maxleaf, st);
           ++E.launches;
-        }
-        const int capS = 2 * max_of(capT) + 16;
-        const std::vector<int> capW = E.chol_work_caps(m.t, capT, capS);
-        std::vector<hq::Engine::CholTask> pc;
-        for (int j = 0; j < r; ++j) {
-          Li[j] = E.alloc_hmat_in(it, &m.t, capT, false);
-          Lf[j] = E.alloc_hmat_in(it, &m.t, capW, false);
-          Y[j] = E.alloc_hmat_in(it, &m.t, capT, false);
-          V[j] = E.alloc_hmat_in(it, &m.t, capT, false);
-          pc.push_back(hq::Engine::CholTask{&Zj[j], &Li[j], &Lf[j], capS, 0});
         }
         E.cholesky_inverse(pc);
         E.scratch.reset();
         std::vector<hq::Engine::ProdTask> py, pv;
-        for (int j = 0; j < r; ++j) {
-          hq::Engine::ProdTask a;
-          a.A = E.view(m.X);
-          a.B = E.view(Li[j], true);  // Y_j = X L_j^{-T}
-          a.C = &Y[j];
-          a.fidx = 0;
-          py.push_back(a);
-          hq::Engine::ProdTask b;
-          b.A = E.view(Y[j]);
-          b.B = E.view(Li[j]);  // V_j = Y_j L_j^{-1} = X Z_j^{-1}, weighted
-          b.alpha = z.mhat * z.a[j + 1];
-          b.C = &V[j];
-          b.fidx = 0;
-          pv.push_back(b);
+        for (int i : pend) {
+          const hq::ZoloStep& z = zs[i][k];
+          for (int j = 0; j < z.r; ++j) {
+            hq::Engine::ProdTask a;
+            a.A = E.view(ms[i].X);
+            a.B = E.view(Li[i][j], true);  // Y_j = X L_j^{-T}
+            a.C = &Y[i][j];
+            a.fidx = i;
+            py.push_back(a);
+            hq::Engine::ProdTask b;
+            b.A = E.view(Y[i][j]);
+            b.B = E.view(Li[i][j]);  // V_j = Y_j L_j^{-1} = X Z_j^{-1}, weighted
+            b.alpha = z.mhat * z.a[j + 1];
+            b.C = &V[i][j];
+            b.fidx = i;
+            pv.push_back(b);
+          }
         }
         E.product(py);
         E.scratch.reset();
         E.product(pv);
       }
       E.scratch.reset();
-      for (int j = 0; j < r; ++j) sum.terms.push_back({1.0, &V[j]});
-      E.sum(std::vector<hq::Engine::SumTask>{sum});
-      note_peak();
-      const int f = E.read_flags(1)[0];
-      if (f & 2) return set_fail(m, HQ_ERR_NOT_POSDEF, "a leaf of X^T X + c I is not positive definite");
-      if (f & (8 | 16 | 32)) return set_fail(m, HQ_ERR_NONFINITE, "non-finite values in a recompression");
-      if (f & 4) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
-      if (f & 1) {
-        const bool g1 = grow(capT), g2 = grow(capX);
-        if ((!g1 && !g2) || attempt > 6) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
-        ++m.inf.redo_count;
-        continue;
+      for (int i : pend) {
+        hq::Engine::SumTask sm;
+        sm.C = &ms[i].Xn;
+        sm.fidx = i;
+        sm.terms.push_back({zs[i][k].mhat, &ms[i].X});
+        for (hq::HMat& v : V[i]) sm.terms.push_back({1.0, &v});
+        sums.push_back(std::move(sm));
       }
-      break;
+      E.sum(sums);
+      note_peak();
+      const std::vector<int> f = E.read_flags(nm);
+      std::vector<int> again;
+      for (int i : pend) {
+        Member& m = ms[i];
+        if (f[i] & 2) {
+          set_fail(m, HQ_ERR_NOT_POSDEF, "a leaf of X^T X + c I is not positive definite");
+        } else if (f[i] & (8 | 16 | 32)) {
+          set_fail(m, HQ_ERR_NONFINITE, "non-finite values in a recompression");
+        } else if (f[i] & 4) {
+          set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
+        } else if (f[i] & 1) {
+          const bool g1 = grow(m, capT[i]), g2 = grow(m, capX[i]);
+          if ((!g1 && !g2) || attempt > 6) {
+            set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
+          } else {
+            ++m.inf.redo_count;
+            again.push_back(i);
+          }
+        } else {
+          m.X = m.Xn;
+        }
+      }
+      pend.swap(again);
     }
-    m.X = m.Xn;
     cur ^= 1;
-    if (k < 16) m.inf.max_rank_iter[k] = max_of(E.read_ranks(m.X));
-  }
-  // Alg. 3 lines 17-18: U = X_K (symmetrised), P = (I - U)/2
-  std::vector<int> cp = caps_grow(m.t, E.read_ranks(m.X), o.max_rank, 1, 0);
-  for (int attempt = 0;; ++attempt) {
-    pa.reset();
-    E.stage.reset();
-    E.scratch.reset();
-    m.P = E.alloc_hmat_in(pa, &m.t, cp, false);
-    E.clear_flags(1);
-    E.sym_affine(std::vector<hq::Engine::AffTask>{{&m.X, &m.P, projector ? -0.5 : 1.0, projector ? 0.5 : 0.0, 0}});
-    note_peak();
-    const int f = E.read_flags(1)[0];
-    if (f & (8 | 16 | 32)) return set_fail(m, HQ_ERR_NONFINITE, "non-finite values in the symmetrisation");
-    if (f & 4) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
-    if (f & 1) {
-      if (!grow(cp) || attempt > 6) return set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
-      continue;
+    // ranks of the new iterates; members whose schedule ends here are finished now, before their
+    // iterate's arena is recycled
+    std::vector<const hq::HMat*> xs;
+    std::vector<int> ok;
+    for (int i : act)
+      if (ms[i].status == HQ_OK) {
+        xs.push_back(&ms[i].X);
+        ok.push_back(i);
+      }
+    const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+    std::vector<hq::Engine::AffTask> fin;
+    std::vector<std::vector<int>> capP(nm);
+    for (size_t q = 0; q < ok.size(); ++q) {
+      Member& m = ms[ok[q]];
+      if (k < 16) m.inf.max_rank_iter[k] = max_of(rk[q]);
+      if (k + 1 == m.K) {
+        capP[ok[q]] = caps_grow(m.t, rk[q], o.max_rank, 1, 0);
+        fin.push_back(hq::Engine::AffTask{&m.X, &m.P, projector ? -0.5 : 1.0, projector ? 0.5 : 0.0, ok[q]});
+      }
     }
-    break;
+    // Alg. 3 lines 17-18: U = X_K (symmetrised), P = (I - U)/2
+    for (int attempt = 0; !fin.empty(); ++attempt) {
+      pa.reset();
+      E.stage.reset();
+      E.scratch.reset();
+      for (const auto& a : fin) ms[a.fidx].P = E.alloc_hmat_in(pa, &ms[a.fidx].t, capP[a.fidx], false);
+      E.clear_flags(nm);
+      E.sym_affine(fin);
+      note_peak();
+      const std::vector<int> f = E.read_flags(nm);
+      std::vector<hq::Engine::AffTask> again;
+      for (const auto& a : fin) {
+        Member& m = ms[a.fidx];
+        if (f[a.fidx] & (8 | 16 | 32)) {
+          set_fail(m, HQ_ERR_NONFINITE, "non-finite values in the symmetrisation");
+        } else if (f[a.fidx] & 4) {
+          set_fail(m, HQ_ERR_RANK_OVERFLOW, "stacked factor width above the recompression kernels' limit of 1024");
+        } else if (f[a.fidx] & 1) {
+          if (!grow(m, capP[a.fidx]) || attempt > 6)
+            set_fail(m, HQ_ERR_RANK_OVERFLOW, "off-diagonal rank above opts.max_rank");
+          else
+            again.push_back(a);
+        }
+      }
+      // every member that succeeded is copied out before pa is reset for the repeats
+      for (const auto& a : fin) {
+        Member& m = ms[a.fidx];
+        if (m.status != HQ_OK ||
+            std::any_of(again.begin(), again.end(), [&](const hq::Engine::AffTask& x) { return x.fidx == a.fidx; }))
+          continue;
+        m.out = compact_copy(E, m.P, st, o.leaf);
+        m.inf.max_rank = m.out ? max_of(E.read_ranks(m.out->H)) : 0;
+        m.inf.bytes = (int64_t)m.out->H.bytes();
+      }
+      fin.swap(again);
+    }
   }
-  m.out = compact_copy(E, m.P, st, o.leaf);
-  m.inf.max_rank = m.out ? max_of(E.read_ranks(m.out->H)) : 0;
-  m.inf.bytes = (int64_t)m.out->H.bytes();
-  m.inf.peak_bytes = (int64_t)peak;
-  m.inf.launches = E.launches;
-  m.inf.seconds = secs(t0);
+  const double total = secs(t0);
+  for (Member& m : ms) {
+    m.inf.peak_bytes = (int64_t)peak;
+    m.inf.launches = E.launches;
+    m.inf.seconds = total;
+  }
 }
 
 hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu, const hq_opts& o, hipStream_t st,
@@ -1075,7 +1206,7 @@ hq_status run_qdwh(const double* band, int64_t n, int b, int64_t ldab, double mu
   ms[0].ldab = ldab;
   ms[0].mu = mu;
   if (o.method == HQ_METHOD_ZOLO)
-    run_zolo(ms[0], o, st, projector);
+    run_zolo(ms, o, st, projector);
   else
     run_batch(ms, o, st, projector);
   Member& m = ms[0];
@@ -1209,7 +1340,9 @@ hq_status spectral_projector_batched(int32_t count, const double* const* bands, 
       while (i1 < count) {
         hq::Tree t;
         t.build(n[i1], o.leaf);
-        const double est = 8.5e3 * (double)n[i1] * (b[i1] + 1) * std::max(1, t.L) + 64e6;
+        // Zolo-pd keeps r Cholesky factorisations and terms per member: about 3.5 times as much
+        const double est = (o.method == HQ_METHOD_ZOLO ? 3.5 : 1.0) * 8.5e3 * (double)n[i1] * (b[i1] + 1) *
+                               std::max(1, t.L) + 64e6;
         if (i1 > i0 && sum + est > budget) break;
         sum += est;
         ++i1;
@@ -1223,7 +1356,7 @@ hq_status spectral_projector_batched(int32_t count, const double* const* bands, 
         chunk[i - i0].mu = ms[i].mu;
       }
       if (o.method == HQ_METHOD_ZOLO)
-        for (Member& c : chunk) run_zolo(c, o, (hipStream_t)stream, true);
+        run_zolo(chunk, o, (hipStream_t)stream, true);
       else
         run_batch(chunk, o, (hipStream_t)stream, true);
       for (int i = i0; i < i1; ++i) {

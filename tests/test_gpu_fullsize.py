@@ -113,18 +113,24 @@ def banded16384():
     return ab, lam, V, Vd
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def _method_opts(precision):
+    """'zolo' selects Zolo-pd (FP64); otherwise QDWH in that precision."""
+    return {"method": "zolo"} if precision == "zolo" else {"precision": precision}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "zolo"])
 def test_banded16384_norm_parity(default_predictor, banded16384, precision):
-    """||P - Pi_o||_2 (Lanczos) and the certified ||P - Pi_o||_F on the benchmark's workload."""
+    """||P - Pi_o||_2 (Lanczos) and the certified ||P - Pi_o||_F on the benchmark's workload (QDWH in
+    FP64 and mixed precision, and Zolo-pd)."""
     import torch
     ab, lam, V, Vd = banded16384
     n = ab.shape[0]
     nu = n // 2
     mu = 0.5 * (lam[nu - 1] + lam[nu])
     band = torch.from_numpy(np.ascontiguousarray(ab)).cuda()
-    P, info = hq.spectral_projector(band, 8, mu, leaf=128, tol=1e-10, precision=precision,
-                                    predictor=default_predictor)
-    bound = GATE if precision == "fp64" else bound_from_info(n, info)
+    P, info = hq.spectral_projector(band, 8, mu, leaf=128, tol=1e-10, predictor=default_predictor,
+                                    **_method_opts(precision))
+    bound = GATE if precision != "mixed" else bound_from_info(n, info)
     # certified Frobenius norm over the whole eigenbasis
     ss = 0.0
     for c0 in range(0, n, 2048):
@@ -147,7 +153,7 @@ def test_banded16384_norm_parity(default_predictor, banded16384, precision):
           f"t={info['seconds']:.2f}s | ||P-Pi||_2 (Lanczos) {two:.3e}  ||P-Pi||_F {frob:.3e}  bound {bound:.2e}",
           flush=True)
     assert two <= bound
-    if precision == "fp64":
+    if precision != "mixed":
         assert frob <= 10 * GATE
     _check_properties("banded-n16384-b8", ab, P, band, mu, bound, info["levels"], _last_tol(info, 1e-10))
     P.close()
@@ -159,6 +165,7 @@ FULL = [
     ("metallic-n32768-mixed", lambda: w.tridiag_metallic(32768, 0), 1, 256, 1e-10, "mixed", None),
     ("tridiag-n100000-tol1e-8", lambda: w.tridiag_uniform(100000, 0), 1, 256, 1e-8, "fp64", GATE),
     ("tridiag-n100000-tol1e-8-mixed", lambda: w.tridiag_uniform(100000, 0), 1, 256, 1e-8, "mixed", None),
+    ("metallic-n32768-zolo", lambda: w.tridiag_metallic(32768, 0), 1, 256, 1e-10, "zolo", GATE),
 ]
 
 
@@ -171,8 +178,8 @@ def test_full_size_sampled_parity(default_predictor, name, maker, b, leaf, tol, 
     mu, gap, _ = eig.midpoint_shift(ab, nu)
     idx, lam, V = _sample(ab, nu, np.random.default_rng(n))
     band = torch.from_numpy(np.ascontiguousarray(ab)).cuda()
-    P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, precision=precision,
-                                    predictor=default_predictor)
+    P, info = hq.spectral_projector(band, b, mu, leaf=leaf, tol=tol, predictor=default_predictor,
+                                    **_method_opts(precision))
     PV = P.apply(torch.from_numpy(np.ascontiguousarray(V)).cuda()).cpu().numpy()
     below = lam < mu
     assert below.sum() == np.count_nonzero(idx <= nu)
