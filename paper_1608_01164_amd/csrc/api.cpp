@@ -2,6 +2,7 @@
 #include "../../include/hq.h"
 
 #include <hip/hip_runtime.h>
+#include <omp.h>
 
 #include <algorithm>
 #include <array>
@@ -951,8 +952,15 @@ void run_zolo(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool pr
         }
       }
       qimg.reset(new hq::PinnedHost(sizeof(double) * off.back()));
-#pragma omp parallel for schedule(dynamic, 1)
-      for (int q = 0; q < (int)jobs.size(); ++q) {
+      // fewer sweeps than threads: each sweep's replays (its inner parallel loops) get a share of the
+      // threads, instead of running serially inside a one-thread outer iteration
+      const int nthr = omp_get_max_threads(), nj = (int)jobs.size();
+      const int outer = std::max(1, std::min(nj, nthr)), inner = std::max(1, nthr / outer);
+      const int levels = omp_get_max_active_levels();
+      omp_set_max_active_levels(std::max(levels, 2));
+#pragma omp parallel for schedule(dynamic, 1) num_threads(outer)
+      for (int q = 0; q < nj; ++q) {
+        omp_set_num_threads(inner);
         const int i = jobs[q].first, j = jobs[q].second;
         Member& m = ms[i];
         const std::vector<int> capQ(m.t.L, 2 * m.beff);
@@ -960,6 +968,7 @@ void run_zolo(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool pr
                                 1.0 / (std::sqrt(zs[i][0].c[2 * j + 1]) * m.inf.alpha), m.t, capQ, (int)m.t.maxleaf,
                                 h1[i][j], h2[i][j], qimg->as<double>() + off[q]);
       }
+      omp_set_max_active_levels(levels);
       HQ_CHECK(hipStreamSynchronize(st));
       for (int i : act) {
         Member& m = ms[i];
