@@ -257,7 +257,7 @@ def main():
                     help="capacities from the previous iterate's ranks instead of the trained rank predictor")
     ap.add_argument("--graph", action="store_true",
                     help="launch each Cholesky iteration as one captured HIP graph")
-    ap.add_argument("--sweep", choices=["nmin", "memory", "scaling", "breakeven"],
+    ap.add_argument("--sweep", choices=["nmin", "memory", "scaling", "breakeven", "hmatrix"],
                     help="one of the paper's timing/memory experiments on Sec. 6.1 test matrices instead of "
                          "the benchmark line (JSON lines, one per case)")
     args = ap.parse_args()
@@ -564,6 +564,42 @@ def sweep_memory(hq):
                           "max_rank": info["max_rank"], "iters": info["iters"]}), flush=True)
 
 
+PAPER_TABLE2_H_MB = {1e-1: [95.16, 96.42, 106.54, 151.06, 291.85], 1e-4: [128.58, 160.56, 225.72, 352.54, 583.93]}
+
+
+def sweep_hmatrix(hq):
+    """Example hodlrvshmatrix / Table storage_spec: storage of the projector in HODLR and in the
+    H-matrix format with the standard admissibility condition (Sec. 3.1.2), n = 16000, n_min = 250,
+    eps = 1e-10, on the Sec. 6.1 matrices and on full-band normal ones.  Both counts use the actual
+    ranks ((rows + cols) x rank per low-rank block, rows x cols per dense block)."""
+    import torch
+    import workloads as wl
+    cases = [("sec6.1", gap, b, j) for gap in (1e-1, 1e-4) for j, b in enumerate((1, 2, 4, 8, 16))]
+    cases += [("full-band normal", None, b, None) for b in (1, 2, 4, 8, 16)]
+    for kind, gap, b, j in cases:
+        if kind == "sec6.1":
+            ab, mu = _sec61(16000, b, gap), 0.0
+        else:
+            ab = wl.banded_normal(16000, b, 0)
+            mu, gap = hq.shift_for_count(ab, b, 8000)
+        band = torch.from_numpy(np.ascontiguousarray(ab)).cuda()
+        P, info = hq.spectral_projector(band, b, mu, leaf=250, tol=1e-10)
+        t0 = time.perf_counter()
+        H = hq.hodlr_to_hmatrix(P, 1e-10)
+        dt = time.perf_counter() - t0
+        sh = H.shape()
+        row = {"sweep": "hmatrix", "matrix": kind, "n": 16000, "b": b, "gap": gap, "n_min": 250,
+               "hodlr_mb": sh["hodlr_bytes"] / 2**20, "h_mb": sh["bytes"] / 2**20, "convert_s": dt,
+               "low_rank_blocks": sh["low_rank_blocks"], "dense_blocks": sh["dense_blocks"],
+               "h_max_rank": sh["max_rank"], "hodlr_max_rank": info["max_rank"]}
+        if j is not None:
+            row["paper_hodlr_mb"] = PAPER_TABLE2_MB[gap][j]
+            row["paper_h_mb"] = PAPER_TABLE2_H_MB[gap][j]
+        print(json.dumps(row), flush=True)
+        H.close()
+        P.close()
+
+
 def sweep_scaling(hq):
     """Examples scaling_tridiag / band: time and memory versus n (gap 1e-6 tridiagonal, gap 1e-1 b = 4),
     and the 1D Laplacian (gap ~ 1/n)."""
@@ -605,7 +641,8 @@ def sweep_breakeven(hq):
                   flush=True)
 
 
-SWEEPS = {"nmin": sweep_nmin, "memory": sweep_memory, "scaling": sweep_scaling, "breakeven": sweep_breakeven}
+SWEEPS = {"nmin": sweep_nmin, "memory": sweep_memory, "scaling": sweep_scaling, "breakeven": sweep_breakeven,
+          "hmatrix": sweep_hmatrix}
 
 
 if __name__ == "__main__":

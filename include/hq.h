@@ -45,6 +45,7 @@ typedef enum {
 
 typedef struct hq_hodlr_s* hq_hodlr_t;         /* opaque HODLR matrix on the device */
 typedef struct hq_predictor_s* hq_predictor_t; /* opaque rank predictor (see below) */
+typedef struct hq_hmatrix_s* hq_hmatrix_t;     /* opaque H-matrix (Sec. 3.1.2) on the device */
 
 typedef struct {
   int32_t leaf;      /* n_min: diagonal blocks have at most this many rows (Alg. 3 input), >= 2 */
@@ -300,6 +301,33 @@ hq_status hq_profile_mfma(double* out /* [2] */, int32_t reset);
 /* Core-SVD internals since the last reset: [0..2] cycles of the pivoted-QR, Jacobi and output phases
  * (wall clock at 100 MHz), [3] sum of r, [4] sum of t, [5] sum of sweeps, [6] cores. */
 hq_status hq_profile_svd(int64_t* out /* [8] */);
+
+/* Sec. 3.1.2 (eq. stand_adm) and Example hodlrvshmatrix: the H-matrix form of a HODLR matrix P (for
+ * instance a projector from spectral_projector), for the partition of the HODLR cluster tree in which
+ * a block t x s of two clusters of one level is admissible iff min(diam t, diam s) <= dist(t, s)
+ * (diam t = max |i - j| over t, dist(t, s) = min |i - j|, i in t, j in s), the recursion over the
+ * children pairs stopping at an admissible block (stored as U V^T) or at a leaf cluster (stored
+ * dense).  Every admissible sub-block of a HODLR off-diagonal block is recompressed on its own at the
+ * absolute tolerance tol (> 0; opts.tol of the solve is the natural choice); the dense blocks are the
+ * HODLR leaves and one corner per off-diagonal block next to the diagonal.  P must outlive the result
+ * (its diagonal blocks are shared).  Runs on `stream` and returns with it synchronised.  Errors:
+ * HQ_ERR_ARG (NULL handle or output, tol <= 0), HQ_ERR_NONFINITE (a sub-block recompression met
+ * non-finite values). */
+hq_status hodlr_to_hmatrix(hq_hodlr_t P, double tol, void* stream, hq_hmatrix_t* out);
+/* Counts and storage of an H-matrix (host outputs, each may be NULL): *n; *nlr low-rank and *ndense
+ * dense blocks; *bytes = 8 x (sum over low-rank blocks of (rows + cols) x rank + sum over dense blocks
+ * of rows x cols) with the blocks' actual ranks, and *hodlr_bytes the same count for the HODLR matrix
+ * it was made from (off-diagonal blocks with their ranks, plus the leaves): the two columns of Table
+ * storage_spec; *max_rank the largest rank of a low-rank block. */
+hq_status hmatrix_shape(hq_hmatrix_t H, int64_t* n, int64_t* nlr, int64_t* ndense, int64_t* bytes,
+                        int64_t* hodlr_bytes, int32_t* max_rank);
+/* Block i to host memory: 0 <= i < nlr are the low-rank blocks, nlr <= i < nlr + ndense the dense ones.
+ * *row0, *col0, *m, *ncols locate it; *rank is its rank (-1 for a dense block).  A low-rank block writes
+ * U (m x rank) and V (ncols x rank), a dense block itself into U (m x ncols) (V unused, may be NULL);
+ * column-major, leading dimension ld >= max(m, ncols).  U = NULL returns the sizes only.  Synchronous. */
+hq_status hmatrix_get_block(hq_hmatrix_t H, int64_t i, int64_t* row0, int64_t* col0, int64_t* m, int64_t* ncols,
+                            int32_t* rank, double* U, double* V, int64_t ld);
+void hmatrix_destroy(hq_hmatrix_t H);
 
 /* Host-only: the library's QDWH weight schedule (eq. qdwh_parameters_abc and the l_k recurrence of
  * Sec. 2.1) from a lower bound l0 in (0, 1]: a_k = h(l_k), b_k = (a_k - 1)^2 / 4, c_k = a_k + b_k - 1,

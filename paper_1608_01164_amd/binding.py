@@ -108,6 +108,10 @@ _SIGS = {
     "hodlr_get_block": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp, c_i64, P(c_i32), P(c_i64), P(c_i64), P(c_i64)]),
     "hq_shift_for_count": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_i64, P(c_d), P(c_d)]),
     "hodlr_destroy": (None, [c_vp]),
+    "hodlr_to_hmatrix": (c_i32, [c_vp, c_d, c_vp, P(c_vp)]),
+    "hmatrix_shape": (c_i32, [c_vp, P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i32)]),
+    "hmatrix_get_block": (c_i32, [c_vp, c_i64, P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i32), c_vp, c_vp, c_i64]),
+    "hmatrix_destroy": (None, [c_vp]),
     "hq_status_string": (ctypes.c_char_p, [c_i32]),
     "hq_last_error": (ctypes.c_char_p, []),
     "hq_test_gemm": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_d, c_d, c_i32,
@@ -345,6 +349,61 @@ class HODLR:
             self.close()
         except Exception:
             pass
+
+
+class HMatrix:
+    """An H-matrix made from a HODLR matrix (standard admissibility, Sec. 3.1.2); see hq.h."""
+
+    def __init__(self, handle: c_vp, source):
+        self._h = handle
+        self._src = source  # keeps the HODLR matrix whose diagonal blocks it shares alive
+
+    def shape(self) -> dict:
+        n, nlr, nd, by, hb = (c_i64() for _ in range(5))
+        mr = c_i32()
+        _check(lib().hmatrix_shape(self._h, ctypes.byref(n), ctypes.byref(nlr), ctypes.byref(nd), ctypes.byref(by),
+                                   ctypes.byref(hb), ctypes.byref(mr)))
+        return {"n": n.value, "low_rank_blocks": nlr.value, "dense_blocks": nd.value, "bytes": by.value,
+                "hodlr_bytes": hb.value, "max_rank": mr.value}
+
+    def blocks(self):
+        """[(row0, col0, U, V)] for low-rank blocks and [(row0, col0, D)] for dense ones (host arrays)."""
+        sh = self.shape()
+        r0, c0, m, nc = (c_i64() for _ in range(4))
+        rk = c_i32()
+        lr, dn = [], []
+        for i in range(sh["low_rank_blocks"] + sh["dense_blocks"]):
+            args = (ctypes.byref(r0), ctypes.byref(c0), ctypes.byref(m), ctypes.byref(nc), ctypes.byref(rk))
+            _check(lib().hmatrix_get_block(self._h, i, *args, None, None, 0))  # sizes
+            ld = max(m.value, nc.value, 1)
+            if rk.value >= 0:
+                k = rk.value
+                U = np.zeros((ld, max(k, 1)), order="F")
+                V = np.zeros((ld, max(k, 1)), order="F")
+                _check(lib().hmatrix_get_block(self._h, i, *args, U.ctypes.data_as(c_vp), V.ctypes.data_as(c_vp), ld))
+                lr.append((r0.value, c0.value, U[: m.value, :k].copy(), V[: nc.value, :k].copy()))
+            else:
+                D = np.zeros((ld, ld), order="F")
+                _check(lib().hmatrix_get_block(self._h, i, *args, D.ctypes.data_as(c_vp), None, ld))
+                dn.append((r0.value, c0.value, D[: m.value, : nc.value].copy()))
+        return lr, dn
+
+    def close(self):
+        if self._h:
+            lib().hmatrix_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hodlr_to_hmatrix(P, tol: float = 1e-10, stream=None) -> HMatrix:
+    h = c_vp()
+    _check(lib().hodlr_to_hmatrix(P.handle, float(tol), _stream(stream), ctypes.byref(h)))
+    return HMatrix(h, P)
 
 
 def hodlr_build(band, b: int, shift: float, scale: float, leaf: int = 256, stream=None) -> HODLR:

@@ -16,6 +16,7 @@
 #include "engine.h"
 #include "givens.h"
 #include "handle.h"
+#include "hmatrix.h"
 #include "predictor.h"
 #include "zolo.h"
 
@@ -1803,6 +1804,80 @@ hq_status hq_test_schedule(double l0, double delta, int32_t max_iter, double* a,
     return HQ_OK;
   });
 }
+
+hq_status hodlr_to_hmatrix(hq_hodlr_t P, double tol, void* stream, hq_hmatrix_t* out) {
+  if (!P || !out) return fail(HQ_ERR_ARG, "NULL handle or output");
+  *out = nullptr;
+  if (!(tol > 0.0)) return fail(HQ_ERR_ARG, "tol must be > 0");
+  return guard([&]() -> hq_status {
+    std::unique_ptr<hq_hmatrix_s> h(new hq_hmatrix_s());
+    hipStream_t st = (hipStream_t)stream;
+    HQ_CHECK(hipStreamWaitEvent(st, P->done, 0));  // any earlier use of P on its own stream
+    try {
+      h->H.convert(P->H, tol, st);
+    } catch (const std::runtime_error& e) {
+      return fail(HQ_ERR_NONFINITE, e.what());
+    }
+    const std::vector<int> r = P->e->read_ranks(P->H);
+    const hq::Tree& t = P->t;
+    int64_t b = 0;
+    for (int p = 0; p < t.ninternal; ++p) {
+      const int64_t sa = t.size(2 * p + 1), sb = t.size(2 * p + 2);
+      b += (sa + sb) * (int64_t)(r[2 * p] + r[2 * p + 1]);
+    }
+    for (int q = t.ninternal; q < t.nnodes; ++q) b += t.size(q) * t.size(q);
+    h->hodlr_bytes = 8 * b;
+    *out = h.release();
+    return HQ_OK;
+  });
+}
+
+hq_status hmatrix_shape(hq_hmatrix_t H, int64_t* n, int64_t* nlr, int64_t* ndense, int64_t* bytes,
+                        int64_t* hodlr_bytes, int32_t* max_rank) {
+  if (!H) return fail(HQ_ERR_ARG, "NULL handle");
+  if (n) *n = H->H.n;
+  if (nlr) *nlr = (int64_t)H->H.lr.size();
+  if (ndense) *ndense = (int64_t)H->H.dn.size();
+  if (bytes) *bytes = H->H.bytes;
+  if (hodlr_bytes) *hodlr_bytes = H->hodlr_bytes;
+  if (max_rank) *max_rank = H->H.max_rank;
+  return HQ_OK;
+}
+
+hq_status hmatrix_get_block(hq_hmatrix_t H, int64_t i, int64_t* row0, int64_t* col0, int64_t* m, int64_t* ncols,
+                            int32_t* rank, double* U, double* V, int64_t ld) {
+  if (!H || !row0 || !col0 || !m || !ncols || !rank) return fail(HQ_ERR_ARG, "NULL argument");
+  const int64_t nlr = (int64_t)H->H.lr.size(), nd = (int64_t)H->H.dn.size();
+  if (i < 0 || i >= nlr + nd) return fail(HQ_ERR_ARG, "block index out of range");
+  return guard([&]() -> hq_status {
+    if (i < nlr) {
+      const hq::HMatrixH::LowRank& b = H->H.lr[i];
+      const int k = H->H.ranks[i];
+      *row0 = b.r0; *col0 = b.c0; *m = b.m; *ncols = b.n; *rank = k;
+      if (!U) return HQ_OK;  // sizes only
+      if (!V) return fail(HQ_ERR_ARG, "V is NULL for a low-rank block");
+      if (ld < std::max(b.m, b.n)) return fail(HQ_ERR_ARG, "ld smaller than the block");
+      if (k > 0) {
+        HQ_CHECK(hipMemcpy2D(U, sizeof(double) * ld, b.U, sizeof(double) * b.ld, sizeof(double) * b.m, k,
+                             hipMemcpyDeviceToHost));
+        HQ_CHECK(hipMemcpy2D(V, sizeof(double) * ld, b.V, sizeof(double) * b.ld, sizeof(double) * b.n, k,
+                             hipMemcpyDeviceToHost));
+      }
+    } else {
+      const hq::HMatrixH::Dense& d = H->H.dn[i - nlr];
+      *row0 = d.r0; *col0 = d.c0; *m = d.m; *ncols = d.n; *rank = -1;
+      if (!U) return HQ_OK;  // sizes only
+      if (ld < std::max(d.m, d.n)) return fail(HQ_ERR_ARG, "ld smaller than the block");
+      const double* src = d.from_leaf ? H->H.leaves + (size_t)d.leaf * H->H.ldl * H->H.ldl : d.D;
+      const int64_t lds = d.from_leaf ? H->H.ldl : d.m;
+      HQ_CHECK(hipMemcpy2D(U, sizeof(double) * ld, src, sizeof(double) * lds, sizeof(double) * d.m, d.n,
+                           hipMemcpyDeviceToHost));
+    }
+    return HQ_OK;
+  });
+}
+
+void hmatrix_destroy(hq_hmatrix_t H) { delete H; }
 
 hq_status hq_test_zolo(double l, int32_t r, double* c, double* a, double* mhat, double* lnext) {
   if (!c || !a || !mhat || !lnext) return fail(HQ_ERR_ARG, "NULL output");

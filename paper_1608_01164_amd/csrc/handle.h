@@ -6,6 +6,7 @@
 #include <memory>
 
 #include "engine.h"
+#include "hmatrix.h"
 
 struct hq_hodlr_s {
   hq::Tree t;
@@ -26,3 +27,9 @@ inline void reserve_apply_staging(hq_hodlr_s& h) {
   const size_t tasks = (size_t)h.t.nleaves + 4 * (size_t)h.t.ninternal + 16;
   h.e->stage.reserve(tasks * sizeof(hq::GemmTask) + (size_t(64) << 10));
 }
+
+// The object behind hq_hmatrix_t: an H-matrix made from a HODLR one (whose leaves it shares).
+struct hq_hmatrix_s {
+  hq::HMatrixH H;
+  int64_t hodlr_bytes = 0;  // storage of the source HODLR matrix with its actual ranks
+};
