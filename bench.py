@@ -512,7 +512,7 @@ def _sec61(n, b, gap, seed=0):
     return wl.prescribed_spectrum_band(wl.split_gap_spectrum(n, gap, seed), b)
 
 
-def _time_projector(hq, ab, b, leaf, tol, reps=2):
+def _time_projector(hq, ab, b, leaf, tol, reps=2, **kw):
     """Median seconds of `reps` projectors after one warmup, and the last call's info."""
     import torch
     band = torch.from_numpy(np.ascontiguousarray(ab)).cuda()
@@ -521,7 +521,7 @@ def _time_projector(hq, ab, b, leaf, tol, reps=2):
     for i in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        P, info = hq.spectral_projector(band, b, 0.0, leaf=leaf, tol=tol)
+        P, info = hq.spectral_projector(band, b, 0.0, leaf=leaf, tol=tol, **kw)
         torch.cuda.synchronize()
         if i > 0:
             ts.append(time.perf_counter() - t0)
@@ -617,13 +617,15 @@ def sweep_scaling(hq):
 
 def sweep_breakeven(hq):
     """Breakeven versus a dense eigensolver (the paper: MATLAB eig on one core; here the GPU's dense
-    symmetric eigensolver through torch.linalg.eigh, projector formed as V V^T), tridiagonal and b = 8."""
+    symmetric eigensolver through torch.linalg.eigh, projector formed as V V^T), tridiagonal and b = 8;
+    hQDWH and Zolo-pd."""
     import torch
     import workloads as wl
     for b, gap in ((1, 1e-1), (1, 1e-4), (8, 1e-1), (8, 1e-4)):
         for n in (1024, 2048, 4096, 8192, 16384):
             ab = _sec61(n, b, gap)
             t_h, info = _time_projector(hq, ab, b, 256 if b == 1 else 128, 1e-10)
+            t_z, _ = _time_projector(hq, ab, b, 256 if b == 1 else 128, 1e-10, method="zolo")
             A = torch.from_numpy(wl.band_to_dense(ab)).cuda()
             ts = []
             for i in range(3):
@@ -637,7 +639,8 @@ def sweep_breakeven(hq):
                     ts.append(time.perf_counter() - t0)
             del A, V, Vn, Pi
             print(json.dumps({"sweep": "breakeven", "n": n, "b": b, "gap": gap, "hqdwh_seconds": t_h,
-                              "dense_eigh_seconds": float(np.median(ts)), "max_rank": info["max_rank"]}),
+                              "zolo_seconds": t_z, "dense_eigh_seconds": float(np.median(ts)),
+                              "max_rank": info["max_rank"]}),
                   flush=True)
 
 
