@@ -210,11 +210,14 @@ const char* hq_last_error(void);
  *   split_chunk   rows of the inner dimension per split, >= 32
  *   split_max     most splits, 1..128
  *   schur_keep    the H-Cholesky carries its lazy Schur factor uncompressed up to this many columns
+ *   gemm_small_tiles  batched GEMM launches of at most this many 64 x 64 output tiles (inner dimension
+ *                 not split) run with 32 x 32 tiles and register-staged operands, 0..2^20 (0: never);
+ *                 both kernels give the same result bit for bit
  * hq_tuning_set replaces the table for the rest of the process (all values checked, HQ_ERR_ARG if out
  * of range); it must not be called while a solve runs.  hq_tuning_source names where the values came
  * from.
  */
-typedef struct { int32_t qr_tile_rows, split_min_k, split_chunk, split_max, schur_keep; } hq_tuning;
+typedef struct { int32_t qr_tile_rows, split_min_k, split_chunk, split_max, schur_keep, gemm_small_tiles; } hq_tuning;
 hq_status hq_tuning_get(hq_tuning* out);
 hq_status hq_tuning_set(const hq_tuning* in);
 const char* hq_tuning_source(void);

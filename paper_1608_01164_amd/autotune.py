@@ -28,6 +28,7 @@ CANDIDATES = {
     "split_chunk": [128, 256, 512],
     "split_max": [16, 32, 64],
     "schur_keep": [0, 64, 96, 128, 160],
+    "gemm_small_tiles": [0, 16, 32, 64, 128, 256],
 }
 
 
@@ -97,7 +98,7 @@ def main():
         for line in log:
             f.write(line + "\n")
         f.write(f"# chosen: {t_best:.4f} s\n")
-        for k in ("qr_tile_rows", "split_min_k", "split_chunk", "split_max", "schur_keep"):
+        for k in ("qr_tile_rows", "split_min_k", "split_chunk", "split_max", "schur_keep", "gemm_small_tiles"):
             f.write(f"{k} {best[k]}\n")
     print(f"wrote {args.out}: {best} ({t_best:.4f} s)", flush=True)
 

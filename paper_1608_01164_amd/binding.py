@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("qr_tile_rows", c_i32), ("split_min_k", c_i32), ("split_chunk", c_i32), ("split_max", c_i32),
-                ("schur_keep", c_i32)]
+                ("schur_keep", c_i32), ("gemm_small_tiles", c_i32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

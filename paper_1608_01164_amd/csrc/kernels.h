@@ -51,9 +51,11 @@ struct Tuning {
   int split_chunk = 256;    // rows of K per split
   int split_max = 32;       // most splits
   int schur_keep = 96;      // H-Cholesky: Schur factors up to this width are carried uncompressed
+  int gemm_small_tiles = 64;  // GEMM launches of at most this many 64 x 64 tiles (no split-K) use 32 x 32 tiles
   bool valid() const {
     return qr_tile_rows >= 32 && qr_tile_rows <= 8192 && split_min_k >= 64 && split_chunk >= 32 && split_max >= 1 &&
-           split_max <= 128 && schur_keep >= 0 && schur_keep <= 1024;
+           split_max <= 128 && schur_keep >= 0 && schur_keep <= 1024 && gemm_small_tiles >= 0 &&
+           gemm_small_tiles <= (1 << 20);
   }
 };
 Tuning& tuning();

@@ -374,11 +374,140 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmTask* __restrict_
   }
 }
 
+// Small batched GEMMs (a launch of few output tiles, K not split): the GPU would leave most compute
+// units idle under 64 x 64 tiles, and each tile would wait on one memory round trip per 16-deep K
+// chunk.  Here a workgroup covers 32 x 32 outputs, each wave one 16 x 16 block, GSK deep in K at a
+// time with the next chunk's loads in flight during the current chunk's MFMAs.  Lane l takes
+// A(i0 + l % 16, k0 + 4 s + l / 16) and B(k0 + 4 s + l / 16, j0 + l % 16) into step s.  An operand
+// whose rows run along memory (A not transposed, B transposed) is loaded in that layout directly;
+// one stored K-contiguous (A^T, B) is read with consecutive lanes on consecutive K, GSK values of a
+// row per instruction, and turned into the step layout through a slice of LDS that only its own
+// wave touches (no workgroup barrier).  Loads are unconditional (an element outside the operand
+// reads element 0 and is replaced by zero), so that a chunk's loads are all in flight together.
+// A task runs 4 ceil(k / 16) steps in K order, as in k_gemm (zeros past k), so both kernels give
+// the same result bit for bit.
+constexpr int GS_T = 32, GSK = 64, GSS = GSK / 4, GS_LD = GSK + 1;
+
+template <typename T, bool AKC, bool BKC>
+static __device__ __forceinline__ void gemm_small_loop(const GemmTask& Tk, const int m, const int n, const int k,
+                                                       const int row0, const int col0, const int lane, T* sa, T* sb,
+                                                       typename std::conditional<std::is_same<T, double>::value, d4,
+                                                                                 f4>::type& acc) {
+  const int li = lane & 15, lk = lane >> 4;
+  T ra[GSS], rb[GSS];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < GSS; ++q) {
+      const int ai = AKC ? row0 + q : row0 + li, ak = AKC ? k0 + lane : k0 + 4 * q + lk;
+      const bool ain = ai < m && ak < k;
+      const size_t aidx = ain ? (AKC ? ak + (size_t)ai * Tk.lda : ai + (size_t)ak * Tk.lda) : 0;
+      const double av = Tk.A[aidx];
+      ra[q] = (T)(ain ? av : 0.0);
+      const int bj = BKC ? col0 + q : col0 + li, bk = BKC ? k0 + lane : k0 + 4 * q + lk;
+      const bool bin = bj < n && bk < k;
+      const size_t bidx = bin ? (BKC ? bk + (size_t)bj * Tk.ldb : bj + (size_t)bk * Tk.ldb) : 0;
+      const double bv = Tk.B[bidx];
+      rb[q] = (T)(bin ? bv : 0.0);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < k; k0 += GSK) {
+    T ca[GSS], cb[GSS];
+    if constexpr (AKC) {
+#pragma unroll
+      for (int q = 0; q < GSS; ++q) sa[q * GS_LD + lane] = ra[q];
+    }
+    if constexpr (BKC) {
+#pragma unroll
+      for (int q = 0; q < GSS; ++q) sb[q * GS_LD + lane] = rb[q];
+    }
+    // the slices are this wave's alone and a wave's LDS accesses complete in order: only the
+    // compiler must keep the reads below after the writes above
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int q = 0; q < GSS; ++q) {
+      ca[q] = AKC ? sa[li * GS_LD + 4 * q + lk] : ra[q];
+      cb[q] = BKC ? sb[li * GS_LD + 4 * q + lk] : rb[q];
+    }
+    // and the next chunk's writes after these reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (k0 + GSK < k) load(k0 + GSK);
+    const int left = k - k0;  // groups of 16 K (four steps) as k_gemm's chunks, zeros past k
+#pragma unroll
+    for (int g = 0; g < GSK / 16; ++g) {
+      if (g * 16 >= left) break;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = 4 * g + u;
+        if constexpr (std::is_same<T, double>::value)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[q], cb[q], acc, 0, 0, 0);
+        else
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], cb[q], acc, 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_small(const GemmTask* __restrict__ tasks, int tiles_n) {
+  using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
+  __shared__ T slab[4][2][16 * GS_LD];  // per wave: A rows, B columns of the current chunk
+  const GemmTask Tk = tasks[blockIdx.y];
+  const int m = live(Tk.mp, Tk.m), n = live(Tk.np, Tk.n), k = live(Tk.kp, Tk.k);
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
+  if (blockIdx.x == 0 && tid == 0) {
+    count_work(K_GEMM, 2ull * m * n * k,
+               8ull * ((unsigned long long)m * k + (unsigned long long)k * n + (Tk.beta != 0.0 ? 2ull : 1ull) * m * n));
+    count_mfma(std::is_same<T, double>::value ? 0 : 1, 2ull * m * n * k);
+  }
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int row0 = tm * GS_T + (wave >> 1) * 16, col0 = tn * GS_T + (wave & 1) * 16;
+  if (row0 >= m || col0 >= n) return;  // wave-uniform: this wave's block lies outside C
+  Acc acc = Acc{0, 0, 0, 0};
+  if (k > 0) {
+    T* const sa = slab[wave][0];
+    T* const sb = slab[wave][1];
+    const int akc = uniform(Tk.opA != 0), bkc = uniform(Tk.opB == 0);  // operands stored with K contiguous
+    if (akc && bkc)
+      gemm_small_loop<T, true, true>(Tk, m, n, k, row0, col0, lane, sa, sb, acc);
+    else if (akc)
+      gemm_small_loop<T, true, false>(Tk, m, n, k, row0, col0, lane, sa, sb, acc);
+    else if (bkc)
+      gemm_small_loop<T, false, true>(Tk, m, n, k, row0, col0, lane, sa, sb, acc);
+    else
+      gemm_small_loop<T, false, false>(Tk, m, n, k, row0, col0, lane, sa, sb, acc);
+  }
+  // D(i, j) of the 16x16 block: FP64 in lane j + 16 (i % 4), element i / 4; FP32 in lane
+  // j + 16 (i / 4), element i % 4
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = row0 + (std::is_same<T, double>::value ? lk + 4 * e : 4 * lk + e), j = col0 + li;
+    if (i < m && j < n) {
+      double* c = Tk.C + i + (size_t)j * Tk.ldc;
+      const double v = Tk.alpha * (double)acc[e];
+      *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
+    }
+  }
+}
+
 void launch_gemm(const GemmTask* d_tasks, int ntasks, int max_m, int max_n, bool fp32, hipStream_t s,
                  int max_splits) {
   if (ntasks <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = (max_m + GT - 1) / GT, tn = (max_n + GT - 1) / GT;
   const int zs = max_splits > 1 ? max_splits : 1;
+  if (zs == 1 && ntasks <= 65535 && (long long)tm * tn * ntasks <= tuning().gemm_small_tiles) {
+    const int sm = (max_m + GS_T - 1) / GS_T, sn = (max_n + GS_T - 1) / GS_T;
+    if (fp32)
+      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm_small<float>, dim3(sm * sn, ntasks), dim3(256), 0, s, d_tasks, sn));
+    else
+      HQ_TIMED(K_GEMM, s, hipLaunchKernelGGL(k_gemm_small<double>, dim3(sm * sn, ntasks), dim3(256), 0, s, d_tasks, sn));
+    return;
+  }
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
     if (fp32)

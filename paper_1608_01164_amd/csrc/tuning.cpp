@@ -44,6 +44,7 @@ void load(Tuning& t) {
     else if (!std::strcmp(key, "split_chunk")) n.split_chunk = (int)v;
     else if (!std::strcmp(key, "split_max")) n.split_max = (int)v;
     else if (!std::strcmp(key, "schur_keep")) n.schur_keep = (int)v;
+    else if (!std::strcmp(key, "gemm_small_tiles")) n.gemm_small_tiles = (int)v;
   }
   std::fclose(f);
   if (n.valid()) {
@@ -72,6 +73,7 @@ extern "C" hq_status hq_tuning_get(hq_tuning* out) {
   out->split_chunk = t.split_chunk;
   out->split_max = t.split_max;
   out->schur_keep = t.schur_keep;
+  out->gemm_small_tiles = t.gemm_small_tiles;
   return HQ_OK;
 }
 
@@ -86,6 +88,7 @@ extern "C" hq_status hq_tuning_set(const hq_tuning* in) {
   n.split_chunk = in->split_chunk;
   n.split_max = in->split_max;
   n.schur_keep = in->schur_keep;
+  n.gemm_small_tiles = in->gemm_small_tiles;
   if (!n.valid()) {
     hq::set_last_error("tuning values out of range");
     return HQ_ERR_ARG;

@@ -54,6 +54,36 @@ def test_gemm_fp32(m, n, k, opA, opB):
     assert (np.abs(host(dC, m, n) - ref) <= bound + 1e-12).all()
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("m,n,k,opA,opB", [
+    (1, 1, 1, 0, 0), (16, 16, 4, 0, 1), (65, 63, 17, 0, 1), (130, 7, 300, 1, 0), (33, 129, 5, 1, 1),
+    (128, 128, 128, 0, 1), (1000, 40, 65, 1, 1), (300, 300, 511, 0, 0), (7, 3, 0, 0, 0)])
+def test_gemm_small_and_tiled_kernels_agree(m, n, k, opA, opB, fp32):
+    """The 32 x 32 register-staged kernel (launches of few tiles) and the 64 x 64 LDS-staged one issue
+    the same MFMAs in the same K order: forcing either through the tuning table gives the same C bit
+    for bit, and both match numpy."""
+    rng = np.random.default_rng(m * 11 + n * 3 + k)
+    A = rng.standard_normal((max(k, 1), m) if opA else (m, max(k, 1)))
+    B = rng.standard_normal((n, max(k, 1)) if opB else (max(k, 1), n))
+    C = rng.standard_normal((m, n))
+    out = []
+    for small in (0, 1 << 20):
+        old = hq.set_tuning(gemm_small_tiles=small)
+        try:
+            dC = dev(C)
+            hq.test_gemm(dev(A), dev(B), dC, m, n, k, A.shape[0], B.shape[0], m, opA, opB, 1.5, -0.5, fp32=fp32)
+            out.append(host(dC, m, n))
+        finally:
+            hq.set_tuning(gemm_small_tiles=old["gemm_small_tiles"])
+    assert np.array_equal(out[0], out[1])
+    Af = (A.T if opA else A)[:, :k]
+    Bf = (B.T if opB else B)[:k, :]
+    ref = 1.5 * Af @ Bf - 0.5 * C
+    eps = np.finfo(np.float32 if fp32 else np.float64).eps
+    bound = 1.5 * np.abs(Af) @ np.abs(Bf) * 4 * max(k, 1) * eps
+    assert (np.abs(out[0] - ref) <= bound + 1e-12).all()
+
+
 @pytest.mark.parametrize("rows,r", [(300, 20), (3000, 40), (700, 200), (5000, 150), (128, 100), (200, 90)])
 def test_qr_r_fp32(rows, r):
     rng = np.random.default_rng(rows + r + 1)

@@ -15,7 +15,7 @@ GATE = 1e-8
 CANDIDATES = [
     {"qr_tile_rows": 256}, {"qr_tile_rows": 512}, {"qr_tile_rows": 2048},
     {"split_chunk": 128, "split_min_k": 256}, {"split_chunk": 512, "split_max": 16}, {"split_max": 64},
-    {"schur_keep": 0}, {"schur_keep": 160},
+    {"schur_keep": 0}, {"schur_keep": 160}, {"gemm_small_tiles": 0}, {"gemm_small_tiles": 1 << 20},
 ]
 
 
