@@ -1177,23 +1177,40 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       }
       const int li = t->leaf_index(it.c), m = (int)t->size(it.c);
       maxm = std::max(maxm, m);
-      LeafAxpy x{};
-      x.out = T.Lf->leaf(li); x.ldo = T.Lf->ldl; x.X = T.Z->leaf(li); x.ldx = T.Z->ldl; x.m = m; x.alpha = 1.0;
-      cp.push_back(x);
-      LeafAxpy z{};  // Linv_i = 0 (the recursion writes its lower triangle block by block)
-      z.out = T.Linv->leaf(li); z.ldo = T.Linv->ldl; z.X = z.out; z.ldx = z.ldo; z.m = m;
-      cp.push_back(z);
-      if (it.S.cap > 0) {
+      // A leaf of up to 128 rows is factored by one kernel that only reads its input and writes
+      // all of Linv_i: Z_i - S S^T goes straight from Z_i into Lf's leaf (or Z_i itself is the
+      // input without a Schur factor).  Larger leaves are factored in place by the 2x2 split, which
+      // writes Linv_i's lower part block by block: a copy of Z_i and a zeroed Linv_i first.
+      const bool split = m > 128;
+      if (split) {
+        LeafAxpy x{};
+        x.out = T.Lf->leaf(li); x.ldo = T.Lf->ldl; x.X = T.Z->leaf(li); x.ldx = T.Z->ldl; x.m = m; x.alpha = 1.0;
+        cp.push_back(x);
+        LeafAxpy z{};
+        z.out = T.Linv->leaf(li); z.ldo = T.Linv->ldl; z.X = z.out; z.ldx = z.ldo; z.m = m;
+        cp.push_back(z);
+      }
+      const bool schur = it.S.cap > 0;
+      if (schur) {
         GemmTask g{};
         g.A = it.S.p; g.lda = it.S.ld; g.B = it.S.p; g.ldb = it.S.ld; g.opB = 1; g.C = T.Lf->leaf(li); g.ldc = T.Lf->ldl;
         g.m = g.n = m; g.k = it.S.cap; g.kp = it.S.r; g.alpha = -1.0; g.beta = 1.0;
+        if (!split) {
+          g.Cin = T.Z->leaf(li);
+          g.ldcin = T.Z->ldl;
+        }
         gs.push_back(g);
       }
-      blocks.push_back(LeafTask{T.Lf->leaf(li), T.Linv->leaf(li), m, T.Lf->ldl, T.Linv->ldl, T.fidx});
+      if (split || schur)
+        blocks.push_back(LeafTask{T.Lf->leaf(li), T.Linv->leaf(li), m, T.Lf->ldl, T.Linv->ldl, T.fidx});
+      else
+        blocks.push_back(LeafTask{T.Z->leaf(li), T.Linv->leaf(li), m, T.Z->ldl, T.Linv->ldl, T.fidx});
     }
-    if (!cp.empty()) {
-      launch_leaf_axpy(stage.upload(cp, st), (int)cp.size(), maxm, st);
-      ++launches;
+    if (!blocks.empty()) {
+      if (!cp.empty()) {
+        launch_leaf_axpy(stage.upload(cp, st), (int)cp.size(), maxm, st);
+        ++launches;
+      }
       gemm(gs, maxm, maxm);
       leaf_chol_inv(blocks);
     }
@@ -1263,7 +1280,10 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         double* Us = scratch.get<double>((size_t)ldc * rcap);
         double* Vs0 = scratch.get<double>((size_t)ldc * rcap);
         double* Vs = scratch.get<double>((size_t)ldc * rcap);
-        int* rs = scratch.get<int>(1);
+        // the stacked width is also the width of the untruncated inverse block [L^-1]_ba that Lf's
+        // block (p, lower) receives below: the stack writes it into that block's rank slot, which
+        // nothing reads before the recursion ends except through this pointer
+        int* rs = T.Lf->rk(p, 1);
         Usv[i] = Us;
         Vsv[i] = Vs;
         rsv[i] = rs;
@@ -1332,7 +1352,6 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     // inverse blocks from the untruncated factors: U = -L_bb^{-1} Us, V = L_aa^{-T} Vs, rank = width
     const DevArena::Mark mk2 = scratch.mark();
     std::vector<ThinTask> th;
-    std::vector<IntCopy> rk;
     for (int i = 0; i < ni; ++i) {
       const Item& it = inner[i];
       const CholTask& T = batch[it.m];
@@ -1340,11 +1359,8 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       const int ldc = (int)T.Z->t->ldf[l];
       th.push_back(ThinTask{view(lw[it.m]), b, Usv[i], ldc, T.Lf->U(p, 1), ldc, rsv[i], rcapv[i], -1.0, 0.0});
       th.push_back(ThinTask{view(lw[it.m], true), a, Vsv[i], ldc, T.Lf->V(p, 1), ldc, rsv[i], rcapv[i], 1.0, 0.0});
-      rk.push_back(IntCopy{T.Lf->rk(p, 1), rsv[i]});
     }
     mm_thin(th);
-    launch_copy_ints(stage.upload(rk, st), (int)rk.size(), st);
-    ++launches;
     scratch.rewind(mk2);
     scratch.rewind(mk);
   };

@@ -40,6 +40,8 @@ struct GemmTask {
   double alpha, beta;
   double* W;      // split-K: partial tiles (splits per output tile), summed in order by a second kernel
   int splits;     // K ranges when W is set
+  const double* Cin;  // if non-null, beta scales Cin (leading dimension ldcin) instead of C: C = alpha AB + beta Cin
+  int ldcin;
 };
 // K ranges of a product whose k is a true dimension (no device count): a function of k alone, so
 // that a task's result never depends on what else shares its launch or on any capacity.

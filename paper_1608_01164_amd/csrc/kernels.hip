@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
           if (gi < m && gj < n) {
             double* c = Tk.C + gi + (size_t)gj * Tk.ldc;
             const double v = Tk.alpha * (double)acc[x][y][e];
-            *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
+            *c = (Tk.beta == 0.0) ? v : v + Tk.beta * (Tk.Cin ? Tk.Cin[gi + (size_t)gj * Tk.ldcin] : *c);
           }
         }
       }
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmTask* __restrict_
     for (int z = 0; z < S; ++z) sum += P[(size_t)z * (GT * GT) + e];
     double* c = Tk.C + gi + (size_t)gj * Tk.ldc;
     const double v = Tk.alpha * sum;
-    *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
+    *c = (Tk.beta == 0.0) ? v : v + Tk.beta * (Tk.Cin ? Tk.Cin[gi + (size_t)gj * Tk.ldcin] : *c);
   }
 }
 
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(256) void k_gemm_small(const GemmTask* __restrict__
     if (i < m && j < n) {
       double* c = Tk.C + i + (size_t)j * Tk.ldc;
       const double v = Tk.alpha * (double)acc[e];
-      *c = (Tk.beta == 0.0) ? v : v + Tk.beta * *c;
+      *c = (Tk.beta == 0.0) ? v : v + Tk.beta * (Tk.Cin ? Tk.Cin[i + (size_t)j * Tk.ldcin] : *c);
     }
   }
 }
