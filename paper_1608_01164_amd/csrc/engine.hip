@@ -1335,7 +1335,7 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
         }
       }
       gemm(gG, rmax, rmax);
-      launch_spd_chol(stage.upload(pc, st), (int)pc.size(), d_flag, st);
+      launch_spd_chol(stage.upload(pc, st), (int)pc.size(), rmax, d_flag, st);
       ++launches;
       gemm(gC, maxsb, rmax);
       compress_sym(sym);

@@ -147,7 +147,8 @@ struct SpdCholTask {
   int ldg, ldc, kcap;
   int fidx;
 };
-void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int* flag, hipStream_t s);
+// max_r: the largest kcap of the tasks (sets the launch's thread count)
+void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int max_r, int* flag, hipStream_t s);
 
 // Leaf Cholesky Z = L L^T (lower, in place) and lower-triangular inverse.
 struct LeafTask {

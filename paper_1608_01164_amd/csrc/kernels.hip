@@ -151,6 +151,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // that depends on it becomes scalar branches instead of lane masks.
 static __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads() it does not wait for this
+// thread's outstanding global loads and stores, so loads issued ahead (prefetch) stay in flight and
+// stores drain in the background.  For loops whose threads exchange data through LDS alone (no
+// thread reads global memory another thread of the workgroup wrote during the kernel).
+static __device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Live size of a task: the device count behind p (a per-task value), capped by the static bound v.
 static __device__ __forceinline__ int live(const int* p, int v) {
   if (!p) return v;
@@ -308,7 +318,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
       As[stage_kk(Tk.opA, tid, q)][stage_i(Tk.opA, tid, q)] = ra[q];
       Bs[stage_kk(ob, tid, q)][stage_i(ob, tid, q)] = rb[q];
     }
-    __syncthreads();
+    lds_barrier();
     if (k0 + GK < ke) load(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
@@ -326,7 +336,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
         acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   // D(i, j) of a 16x16 block: FP64 in lane j + 16 (i % 4), element i / 4; FP32 in lane
   // j + 16 (i / 4), element i % 4
@@ -2032,11 +2042,15 @@ void launch_svd(const SvdTask* d_tasks, int ntasks, int* flag, bool fp32, hipStr
 // ----------------------------------------------------------------------------------------------
 // Cholesky of the small SPD matrix M = G + E (one workgroup), C = lower factor, M = C C^T.  The lower
 // triangle is kept as 4 x 4 tiles in registers, TPT tiles per thread (order up to SPD_REG), or, above
-// that, packed (entry (i, k), i >= k, at i (i + 1) / 2 + k) in the task's workspace.  Step j: column
-// j is final (its owners updated it in step j - 1 and published it in LDS, or it sits in the
-// workspace); after one barrier every thread writes its share of column j of C and applies the
-// rank-one update -M(i, j) M(k, j) / M(j, j) to its entries right of column j; the owners of column
-// j + 1 publish it as soon as their own update is done.  One barrier per step, no pivot search.
+// that, packed (entry (i, k), i >= k, at i (i + 1) / 2 + k) in the task's workspace.  Register path,
+// two columns per step: at step j, column j is final and column j + 1 lacks only column j's
+// contribution; both sit in LDS, published by their owners in the step before.  After one barrier
+// every thread forms the pivots M(j, j) and M(j + 1, j + 1) - M(j + 1, j)^2 / M(j, j) itself, writes
+// its share of columns j and j + 1 of C, applies the rank-two update of both columns to its entries
+// right of column j + 1 and, if it owns columns j + 2 and j + 3, publishes them.  One barrier per two
+// columns, no pivot search.  Orders whose tiles need two per thread take one column per step (the
+// two-column step's temporaries would not stay in registers beside two tiles).  The launch has as many threads as the largest order's tiles need
+// (blockDim.x, a multiple of 64), so that small orders wait on few waves at each barrier.
 // ----------------------------------------------------------------------------------------------
 constexpr int SPD_THREADS = 1024;
 static __device__ __forceinline__ int pk(int i, int k) { return i >= k ? i * (i + 1) / 2 + k : k * (k + 1) / 2 + i; }
@@ -2053,17 +2067,136 @@ static __device__ __forceinline__ double gram_entry(const SpdCholTask& T, int i,
   return v;
 }
 
+// 4 x 4 tiles of the lower triangle of an order-r matrix (r <= 4 sqrt(2 SPD_THREADS) covers one tile per thread)
+static __host__ __device__ __forceinline__ int spd_tiles(int r) {
+  const int nb = (r + 3) / 4;
+  return nb * (nb + 1) / 2;
+}
+
 template <int TPT>
-static __device__ void spd_chol_regs(const SpdCholTask& T, int r, double* colbuf, int* flag) {
+static __device__ void spd_chol_regs(const SpdCholTask& T, int r, double (*cols)[2][SPD_REG], int* flag,
+                                     const int nthr) {
   const int tid = threadIdx.x;
+  const int ntile = spd_tiles(r);
+  const int e0 = T.ep ? uniform(*T.ep) : r;
+  double a[TPT][4][4];
+  int bi[TPT], bk[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const int q = tid + t * nthr;
+    int x = -1, y = -1;
+    if (q < ntile) unpack_lower(q, x, y);
+    bi[t] = x;
+    bk[t] = y;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * x + u, k = 4 * y + v;
+        a[t][u][v] = (x >= 0 && i < r && k < r && i >= k) ? gram_entry(T, i, k, e0) : 0.0;
+      }
+    if (y == 0) {  // publish columns 0 and 1 (tiles of block column 0 hold rows 4x .. 4x + 3 of them)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * x + u < r) {
+          cols[0][0][4 * x + u] = a[t][u][0];
+          cols[0][1][4 * x + u] = a[t][u][1];
+        }
+    }
+  }
+  unsigned long long flops = 0;
+  int j = 0;
+  for (; j < r; j += 2) {
+    lds_barrier();
+    const double* c0 = cols[(j >> 1) & 1][0];
+    const double* c1 = cols[(j >> 1) & 1][1];
+    double* n0 = cols[((j >> 1) + 1) & 1][0];
+    double* n1 = cols[((j >> 1) + 1) & 1][1];
+    const bool two = j + 1 < r;
+    const double d0 = c0[j];
+    if (!(d0 > 0.0)) {  // M is positive definite by construction; report a breakdown, stop
+      if (tid == 0) atomicOr(flag + T.fidx, 2);
+      break;
+    }
+    const double inv0 = 1.0 / d0, s0 = rsqrt(d0);
+    const double g = two ? c0[j + 1] * inv0 : 0.0;  // column j+1 gets -g * column j
+    const double d1 = two ? c1[j + 1] - g * c0[j + 1] : 1.0;
+    const bool bad1 = two && !(d1 > 0.0);
+    const double inv1 = bad1 ? 0.0 : 1.0 / d1, s1 = bad1 ? 0.0 : rsqrt(d1);
+    double* Cj = T.C + (size_t)j * T.ldc;
+    for (int i = tid; i < r; i += nthr) Cj[i] = i >= j ? c0[i] * s0 : 0.0;
+    if (bad1) {  // column j is done; the breakdown is at j + 1
+      if (tid == 0) atomicOr(flag + T.fidx, 2);
+      j += 1;
+      break;
+    }
+    if (!two) {
+      j += 1;
+      break;
+    }
+    double* Cj1 = T.C + (size_t)(j + 1) * T.ldc;
+    for (int i = tid; i < r; i += nthr) Cj1[i] = i >= j + 1 ? (c1[i] - g * c0[i]) * s1 : 0.0;
+    const int bj = (j + 2) >> 2, cjn = (j + 2) & 3;  // tile column holding columns j + 2, j + 3
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      if (bi[t] < 0 || 4 * bi[t] + 3 <= j + 1) continue;  // rows all at or above j + 1: nothing left to update
+      double v0[4], v1[4];  // columns j and j + 1 (the latter after column j's step) at this tile's columns
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 4 * bk[t] + v;
+        const bool kin = k > j + 1 && k < r;
+        v0[v] = kin ? c0[k] : 0.0;
+        v1[v] = kin ? c1[k] - g * v0[v] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = 4 * bi[t] + u;
+        const bool iin = i > j + 1 && i < r;
+        const double ci0 = iin ? c0[i] : 0.0;
+        const double ui0 = ci0 * inv0, ui1 = iin ? (c1[i] - g * ci0) * inv1 : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[t][u][v] -= ui0 * v0[v] + ui1 * v1[v];
+      }
+      if (bk[t] == bj && j + 2 < r) {  // publish columns j + 2 and j + 3 (static indices by comparison)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (v == cjn) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int i = 4 * bi[t] + u;
+              if (i >= j + 2 && i < r) {
+                n0[i] = a[t][u][v];
+                if (v + 1 < 4) n1[i] = a[t][u][v + 1];
+              }
+            }
+          }
+      }
+    }
+    if (tid == 0) {
+      const unsigned long long m0 = (unsigned long long)(r - j), m1 = m0 - 1;
+      flops += m0 * m0 + m0 + m1 * m1 + m1;
+    }
+  }
+  if (j > r) j = r;
+  if (tid == 0) {
+    *T.kout = j;
+    count_work(K_POTRF, flops, 8ull * r * (r + j));
+  }
+}
+
+// Orders whose tiles need two per thread: one column per step (the two-column step's temporaries
+// would not stay in registers beside two tiles).
+template <int TPT>
+static __device__ void spd_chol_regs_1col(const SpdCholTask& T, int r, double (*cols)[2][SPD_REG], int* flag) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
   const int nb = (r + 3) / 4, ntile = nb * (nb + 1) / 2;
   const int e0 = T.ep ? uniform(*T.ep) : r;
   double a[TPT][4][4];
   int bi[TPT], bk[TPT];
-  double* colp[2] = {colbuf, colbuf + SPD_REG};
+  double* colp[2] = {cols[0][0], cols[1][0]};
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
-    const int q = tid + t * SPD_THREADS;
+    const int q = tid + t * nthr;
     int x = -1, y = -1;
     if (q < ntile) unpack_lower(q, x, y);
     bi[t] = x;
@@ -2084,7 +2217,7 @@ static __device__ void spd_chol_regs(const SpdCholTask& T, int r, double* colbuf
   unsigned long long flops = 0;
   int j = 0;
   for (; j < r; ++j) {
-    __syncthreads();
+    lds_barrier();
     const double* cj = colp[j & 1];
     double* cn = colp[(j + 1) & 1];
     const double d = cj[j];
@@ -2094,7 +2227,7 @@ static __device__ void spd_chol_regs(const SpdCholTask& T, int r, double* colbuf
     }
     const double inv = 1.0 / d, sinv = 1.0 / sqrt(d);
     double* Cj = T.C + (size_t)j * T.ldc;
-    for (int i = tid; i < r; i += SPD_THREADS) Cj[i] = i >= j ? cj[i] * sinv : 0.0;
+    for (int i = tid; i < r; i += nthr) Cj[i] = i >= j ? cj[i] * sinv : 0.0;
     const int bj = (j + 1) >> 2, cjn = (j + 1) & 3;  // tile column holding column j + 1
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
@@ -2138,7 +2271,7 @@ static __device__ void spd_chol_global(const SpdCholTask& T, int r, double* A, i
   const int tid = threadIdx.x;
   const int e0 = T.ep ? uniform(*T.ep) : r;
   const int np0 = r * (r + 1) / 2;
-  for (int q = tid; q < np0; q += SPD_THREADS) {
+  for (int q = tid; q < np0; q += blockDim.x) {
     int i, k;
     unpack_lower(q, i, k);
     A[q] = gram_entry(T, i, k, e0);
@@ -2154,10 +2287,10 @@ static __device__ void spd_chol_global(const SpdCholTask& T, int r, double* A, i
     }
     const double inv = 1.0 / d, sinv = 1.0 / sqrt(d);
     double* Cj = T.C + (size_t)j * T.ldc;
-    for (int i = tid; i < r; i += SPD_THREADS) Cj[i] = i >= j ? A[pk(i, j)] * sinv : 0.0;
+    for (int i = tid; i < r; i += blockDim.x) Cj[i] = i >= j ? A[pk(i, j)] * sinv : 0.0;
     // trailing triangle: rows and columns j + 1 .. r - 1, packed relative to j + 1
     const int m = r - j - 1, npair = m * (m + 1) / 2;
-    for (int q = tid; q < npair; q += SPD_THREADS) {
+    for (int q = tid; q < npair; q += blockDim.x) {
       int x, y;
       unpack_lower(q, x, y);
       const int i = j + 1 + x, k = j + 1 + y;
@@ -2171,8 +2304,13 @@ static __device__ void spd_chol_global(const SpdCholTask& T, int r, double* A, i
   }
 }
 
+// TPT = 1: launches whose largest order's tiles fit one per thread; TPT = 2: launches with a larger
+// order (1024 threads; two tiles per thread up to SPD_REG, the packed workspace above), in a kernel
+// of their own so that the common one keeps every tile in registers without spilling.  A task whose
+// tiles fit one per thread takes the two-column path in either kernel.
+template <int TPT>
 __global__ __launch_bounds__(SPD_THREADS) void k_spd_chol(const SpdCholTask* __restrict__ tasks, int* flag) {
-  __shared__ double colbuf[2 * SPD_REG];
+  __shared__ double cols[2][2][SPD_REG];
   const SpdCholTask T = tasks[blockIdx.x];
   const int r = uniform(*T.rp);
   if (r <= 0) {
@@ -2186,10 +2324,18 @@ __global__ __launch_bounds__(SPD_THREADS) void k_spd_chol(const SpdCholTask* __r
     }
     return;
   }
-  if (r <= 176)
-    spd_chol_regs<1>(T, r, colbuf, flag);
-  else if (r <= SPD_REG)
-    spd_chol_regs<2>(T, r, colbuf, flag);
+  const int nt = spd_tiles(r), nthr = blockDim.x;
+  // the variant depends on the order alone (never on what shares the launch), so that a task's
+  // factor is the same bit for bit in any batch
+  if (nt <= SPD_THREADS && nt <= nthr) {
+    // Waves past this order's tiles leave at once: a wave that has ended is not waited for at the
+    // barriers of the others, which then synchronise only the waves that hold tiles.
+    const int nact = (nt + 63) / 64 * 64;
+    if ((int)threadIdx.x >= nact) return;
+    spd_chol_regs<1>(T, r, cols, flag, nact);
+  }
+  else if (TPT == 2 && r <= SPD_REG && nt <= 2 * nthr)
+    spd_chol_regs_1col<2>(T, r, cols, flag);
   else if (T.work)
     spd_chol_global(T, r, T.work, flag);
   else if (threadIdx.x == 0) {  // no workspace for an order above the register path: report
@@ -2198,12 +2344,19 @@ __global__ __launch_bounds__(SPD_THREADS) void k_spd_chol(const SpdCholTask* __r
   }
 }
 
-void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int* flag, hipStream_t s) {
+void launch_spd_chol(const SpdCholTask* d_tasks, int ntasks, int max_r, int* flag, hipStream_t s) {
   if (ntasks <= 0) return;
   constexpr size_t dyn = 0;
+  // one tile per thread when the largest order allows it, else the full workgroup
+  const int need = spd_tiles(max_r < 1 ? 1 : max_r);
+  const bool one = need <= SPD_THREADS;
+  const int threads = one ? (need + 63) / 64 * 64 : SPD_THREADS;
   for (int t0 = 0; t0 < ntasks; t0 += 65535) {
     const int nt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-    HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_spd_chol, dim3(nt), dim3(SPD_THREADS), dyn, s, d_tasks + t0, flag));
+    if (one)
+      HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_spd_chol<1>, dim3(nt), dim3(threads), dyn, s, d_tasks + t0, flag));
+    else
+      HQ_TIMED(K_POTRF, s, hipLaunchKernelGGL(k_spd_chol<2>, dim3(nt), dim3(threads), dyn, s, d_tasks + t0, flag));
   }
 }
 
