@@ -257,6 +257,8 @@ def main():
                     help="capacities from the previous iterate's ranks instead of the trained rank predictor")
     ap.add_argument("--graph", action="store_true",
                     help="launch each Cholesky iteration as one captured HIP graph")
+    ap.add_argument("--iter-log", metavar="PATH",
+                    help="append one JSON line per iteration of every timed step to PATH (weights, rank, seconds)")
     ap.add_argument("--sweep", choices=["nmin", "memory", "scaling", "breakeven", "hmatrix"],
                     help="one of the paper's timing/memory experiments on Sec. 6.1 test matrices instead of "
                          "the benchmark line (JSON lines, one per case)")
@@ -311,6 +313,12 @@ def main():
         print(f"# step {i}: {info['seconds']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if args.iter_log:  # written after the timed region
+        with open(args.iter_log, "a") as f:
+            for i, inf in enumerate(infos):
+                for rec in hq.iteration_records(inf, workload=args.workload, step=i, method=args.method,
+                                                precision=args.precision):
+                    f.write(json.dumps(rec) + "\n")
     svd_stats = hq.binding.profile_svd() if not args.no_profile else None
     prof = hq.profile_read() if not args.no_profile else None
     mf = hq.binding.profile_mfma() if not args.no_profile else None

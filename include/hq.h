@@ -110,6 +110,8 @@ typedef struct {
   int64_t graph_nodes;       /* opts.graph: kernel and dependency nodes in those graphs */
   double graph_build_seconds;/* opts.graph: host time spent capturing and instantiating them */
   int32_t zolo_r;            /* HQ_METHOD_ZOLO: the degree r used (0 for QDWH) */
+  double iter_seconds[16];   /* wall time of iteration k (Zolo-pd: step k), host work of k = 0 and
+                                repeats after a capacity overflow included, up to its rank readback */
 } hq_info;
 
 /* Fill *o with the defaults: leaf 256, tol 1e-10, delta 1e-15, max_rank 512, max_iter 10. */

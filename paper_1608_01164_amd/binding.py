@@ -69,7 +69,7 @@ class Info(ctypes.Structure):
                 ("peak_bytes", c_i64), ("launches", c_i64), ("seconds", c_d), ("setup_seconds", c_d),
                 ("givens_seconds", c_d), ("levels", c_i32), ("level_ranks", c_i32 * (16 * 4 * 24)),
                 ("capacity_columns", c_i64), ("fp32_iter", c_i32 * 16), ("graphs", c_i32), ("graph_nodes", c_i64),
-                ("graph_build_seconds", c_d), ("zolo_r", c_i32)]
+                ("graph_build_seconds", c_d), ("zolo_r", c_i32), ("iter_seconds", c_d * 16)]
 
     def as_dict(self) -> dict:
         K = self.iters
@@ -80,11 +80,26 @@ class Info(ctypes.Structure):
                 "givens_seconds": self.givens_seconds, "levels": self.levels,
                 "capacity_columns": self.capacity_columns, "fp32_iter": list(self.fp32_iter[:K]),
                 "graphs": self.graphs, "graph_nodes": self.graph_nodes,
-                "graph_build_seconds": self.graph_build_seconds, "zolo_r": self.zolo_r}
+                "graph_build_seconds": self.graph_build_seconds, "zolo_r": self.zolo_r,
+                "iter_seconds": list(self.iter_seconds[:K])}
 
     def level_ranks_array(self) -> np.ndarray:
         """[k][o][l]: o = 0 X_{k+1}, 1 Z_k, 2 L_k^{-1}, 3 Y_k (filled with opts record_ranks)."""
         return np.ctypeslib.as_array(self.level_ranks).reshape(16, 4, 24)[: self.iters, :, : self.levels].copy()
+
+
+def iteration_records(info: dict, **tags) -> list:
+    """One record per iteration (Zolo-pd: per step) of a solve's info, for a JSON-lines log: k, the
+    weights (a, b, c), whether it ran in FP32, the largest off-diagonal rank of X_{k+1}, its wall time,
+    plus the given tags."""
+    out = []
+    for k in range(info["iters"]):
+        rec = dict(tags)
+        rec.update({"k": k, "a": info["a"][k], "b": info["b"][k], "c": info["c"][k],
+                    "fp32": bool(info["fp32_iter"][k]), "max_rank": info["max_rank_iter"][k],
+                    "seconds": info["iter_seconds"][k]})
+        out.append(rec)
+    return out
 
 
 _lib = None

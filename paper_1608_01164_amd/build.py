@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhqdwh.so")
-SOURCES = ["kernels.hip", "engine.hip", "mlp.hip", "noalloc.hip", "givens.cpp", "predictor.cpp", "tuning.cpp", "zolo.cpp", "hmatrix.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "engine.hip", "mlp.hip", "noalloc.hip", "givens.cpp", "predictor.cpp", "tuning.cpp", "zolo.cpp", "hmatrix.cpp", "tree.cpp", "api.cpp"]
 ARCH = os.environ.get("HQ_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

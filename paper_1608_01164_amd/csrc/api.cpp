@@ -504,6 +504,7 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
     for (int i = 0; i < nm; ++i)
       if (ms[i].status == HQ_OK && k < ms[i].K) act.push_back(i);
     if (act.empty()) break;
+    const auto tk = clk::now();
     if (k == 0) {
       for (int i : act) ms[i].capX = caps_from(ms[i].t, 3 * ms[i].beff + 8, o.max_rank);
       // Alg. 3 lines 7-8: structured QR of [sqrt(c0) X0; I] (Algorithms 1/2) and Q1, Q2 in HODLR,
@@ -761,6 +762,8 @@ void run_batch(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool p
         xs.push_back(&ms[i].Y);
       }
     const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+    if (k < 16)
+      for (int i : act) ms[i].inf.iter_seconds[k] = secs(tk);
     if (o.record_ranks && k < 16)
       for (size_t j = 0; j < ok.size(); ++j) {
         Member& m = ms[ok[j]];
@@ -936,6 +939,7 @@ void run_zolo(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool pr
     for (int i = 0; i < nm; ++i)
       if (ms[i].status == HQ_OK && k < ms[i].K) act.push_back(i);
     if (act.empty()) break;
+    const auto tk = clk::now();
     if (k == 0) {
       // every member's r structured QR sweeps on the host in one parallel loop, then the copies
       const auto tg = clk::now();
@@ -1152,6 +1156,8 @@ void run_zolo(std::vector<Member>& ms, const hq_opts& o, hipStream_t st, bool pr
         ok.push_back(i);
       }
     const std::vector<std::vector<int>> rk = read_ranks_many(E, xs);
+    if (k < 16)
+      for (int i : act) ms[i].inf.iter_seconds[k] = secs(tk);
     std::vector<hq::Engine::AffTask> fin;
     std::vector<std::vector<int>> capP(nm);
     for (size_t q = 0; q < ok.size(); ++q) {

@@ -16,31 +16,6 @@
 namespace hq {
 
 // ---------------------------------------------------------------------------------------------
-void Tree::build(int64_t n_, int leaf_) {
-  n = n_;
-  leaf = leaf_;
-  L = 0;
-  while (((n + (int64_t(1) << L) - 1) >> L) > leaf) ++L;
-  nnodes = (2 << L) - 1;
-  ninternal = (1 << L) - 1;
-  nleaves = 1 << L;
-  lo.assign(nnodes, 0);
-  hi.assign(nnodes, 0);
-  hi[0] = n;
-  for (int p = 0; p < ninternal; ++p) {
-    const int64_t m = mid(p);
-    lo[2 * p + 1] = lo[p];
-    hi[2 * p + 1] = m;
-    lo[2 * p + 2] = m;
-    hi[2 * p + 2] = hi[p];
-  }
-  maxleaf = 0;
-  for (int p = ninternal; p < nnodes; ++p) maxleaf = std::max(maxleaf, size(p));
-  ldf.assign(L, 0);
-  for (int l = 0; l < L; ++l) ldf[l] = (n + (int64_t(2) << l) - 1) >> (l + 1);
-}
-
-// ---------------------------------------------------------------------------------------------
 // Chunk cache.  Every call builds its engine and arenas afresh; the device chunks (256 MiB or one
 // larger allocation) and pinned descriptor chunks they release are kept per device for the next
 // call instead of going back to the runtime (hipMalloc / hipHostMalloc of large blocks cost

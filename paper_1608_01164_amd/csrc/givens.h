@@ -1,6 +1,7 @@
 // Structured QR of [c*(A - shift I); I] for symmetric b-banded A (Sec. 4 of the paper) and the
 // HODLR factors of its orthogonal factor.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 

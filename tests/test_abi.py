@@ -103,3 +103,14 @@ def test_tuning_table_is_read_and_checked():
     old = hq.set_tuning(schur_keep=t["schur_keep"] + 1)
     assert hq.tuning()["schur_keep"] == t["schur_keep"] + 1 and hq.tuning()["source"] == "hq_tuning_set"
     hq.set_tuning(**{k: v for k, v in old.items() if k != "source"})
+
+
+def test_iteration_records_from_info():
+    """Per-iteration log records are built from an info dictionary alone (no library call)."""
+    import paper_1608_01164_amd as hq
+    info = {"iters": 2, "a": [3.0, 2.5], "b": [1.0, 0.9], "c": [3.5, 3.1], "fp32_iter": [0, 1],
+            "max_rank_iter": [12, 15], "iter_seconds": [0.1, 0.2]}
+    recs = hq.iteration_records(info, workload="w", step=4)
+    assert recs == [
+        {"workload": "w", "step": 4, "k": 0, "a": 3.0, "b": 1.0, "c": 3.5, "fp32": False, "max_rank": 12, "seconds": 0.1},
+        {"workload": "w", "step": 4, "k": 1, "a": 2.5, "b": 0.9, "c": 3.1, "fp32": True, "max_rank": 15, "seconds": 0.2}]

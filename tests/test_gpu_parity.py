@@ -172,3 +172,19 @@ def test_hodlr_build_is_exact(n, b, leaf):
     # every off-diagonal block is stored with rank b (the b x b corner next to the diagonal)
     assert ex["blocks"] and all(F.shape[1] == b for blk in ex["blocks"] for F in blk[3:])
     H.close()
+
+
+def test_iteration_times_and_records():
+    """Each iteration's wall time is reported (positive, summing to at most the call's time) and the
+    per-iteration records carry the schedule's weights and the reported ranks."""
+    ab = w.banded_normal(1024, 4, 3)
+    mu, _ = hq.shift_for_count(ab, 4, 512)
+    P, info = hq.spectral_projector(_dev_band(ab), 4, mu, leaf=64, tol=1e-10)
+    P.close()
+    t = info["iter_seconds"]
+    assert len(t) == info["iters"] and all(x > 0 for x in t)
+    assert sum(t) <= info["seconds"]
+    recs = hq.iteration_records(info, case="band4")
+    assert [r["k"] for r in recs] == list(range(info["iters"]))
+    assert all(r["case"] == "band4" and r["seconds"] == t[r["k"]] and r["a"] == info["a"][r["k"]] and
+               r["max_rank"] == info["max_rank_iter"][r["k"]] for r in recs)
