@@ -684,7 +684,6 @@ void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
     double* J = scratch.get<double>((size_t)ls * ls);
     double* Jw = scratch.get<double>((size_t)ls * ls);
     double* aux = scratch.get<double>(2 * (size_t)rc);
-    double* Wk = scratch.get<double>((size_t)ls * std::max(T.kcap, 1));
     double* Jk = scratch.get<double>((size_t)ls * std::max(T.kcap, 1));
     GemmTask g{};  // G = S^T S
     g.A = T.S; g.opA = 1; g.lda = T.lds; g.B = T.S; g.ldb = T.lds; g.C = G; g.ldc = ls;
@@ -695,7 +694,8 @@ void Engine::compress_sym_group(const std::vector<SymTask>& tasks) {
     mmax = std::max(mmax, T.m);
     SvdTask s{};
     const double th2 = T.thresh * T.thresh;
-    s.B = G; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = Wk; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = ls;
+    // only the right singular vectors (G's eigenvectors) are used: no left ones (Wk null)
+    s.B = G; s.C = J; s.Jw = Jw; s.aux = aux; s.Wk = nullptr; s.Jk = Jk; s.rp = T.r; s.kout = T.rank; s.ld = ls;
     s.kcap = T.kcap; s.thresh = th2; s.qr_thresh = 0.1 * th2; s.fidx = T.fidx;
     s.fp32_floor = fp32_floor(T.m);
     s.keep_below = T.keep_below;

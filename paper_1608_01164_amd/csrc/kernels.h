@@ -113,7 +113,7 @@ struct SvdTask {
   double* C;         // r x r workspace
   double* Jw;        // r x r workspace (rotations when t exceeds the LDS copy)
   double* aux;       // 2r workspace
-  double* Wk;        // r x kcap output
+  double* Wk;        // r x kcap output (null: the left singular vectors are not formed)
   double* Jk;        // r x kcap output
   double* sig;       // r sorted singular values (may be null)
   const int* rp;

@@ -1793,8 +1793,10 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
     const int c = idx % r, o = idx / r, src = ordr[o];
     const double is = 1.0 / sqrt((double)sig2[src]);
     Tk.Jk[perm[c] + (size_t)o * Tk.ld] = C[c + (size_t)src * ldc] * is;
-    if constexpr (EM == 0) Tk.Wk[c + (size_t)o * Tk.ld] = (c < t) ? J[c + (size_t)src * ldj] * is : 0.0;
+    if constexpr (EM == 0)
+      if (Tk.Wk) Tk.Wk[c + (size_t)o * Tk.ld] = (c < t) ? J[c + (size_t)src * ldj] * is : 0.0;
   }
+  if (!Tk.Wk) return nsweeps;  // right singular vectors only (symmetric compressions): no reflector replay
   if constexpr (EM > 0) {
     // Each output column stays in registers of one group through the t reflectors (applied last to
     // first).
@@ -2019,7 +2021,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd(const SvdTask* __restrict__
     for (int idx = threadIdx.x; idx < nr * kk; idx += SVD_THREADS) {
       const size_t o = (size_t)(r + idx % nr) + (size_t)(idx / nr) * Tk.ld;
       Tk.Jk[o] = 0.0;
-      Tk.Wk[o] = 0.0;
+      if (Tk.Wk) Tk.Wk[o] = 0.0;
     }
   }
 }
