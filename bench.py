@@ -259,7 +259,7 @@ def main():
                     help="launch each Cholesky iteration as one captured HIP graph")
     ap.add_argument("--iter-log", metavar="PATH",
                     help="append one JSON line per iteration of every timed step to PATH (weights, rank, seconds)")
-    ap.add_argument("--sweep", choices=["nmin", "memory", "scaling", "breakeven", "hmatrix"],
+    ap.add_argument("--sweep", choices=["nmin", "memory", "scaling", "breakeven", "hmatrix", "solve"],
                     help="one of the paper's timing/memory experiments on Sec. 6.1 test matrices instead of "
                          "the benchmark line (JSON lines, one per case)")
     args = ap.parse_args()
@@ -652,8 +652,38 @@ def sweep_breakeven(hq):
                   flush=True)
 
 
+def sweep_solve(hq):
+    """HODLR triangular solves (substitution with the H-Cholesky factor) against the products with the
+    inverse factor, on diagonally dominant banded SPD matrices: factorisation and solve times, and
+    the solution error against a dense solve where one fits."""
+    import torch
+    import workloads as wl
+    for n, b, leaf in ((4096, 8, 128), (16384, 8, 128), (32768, 1, 256)):
+        ab = np.array(wl.banded_normal(n, b, 17), dtype=np.float64)
+        ab[:, 0] = np.abs(ab[:, 0]) + 2 * b * np.abs(ab).max() + 1.0
+        H = hq.hodlr_build(torch.from_numpy(np.ascontiguousarray(ab)).cuda(), b, 0.0, 1.0, leaf=leaf)
+        Bh = np.random.default_rng(3).standard_normal((8, n))
+        B = torch.from_numpy(Bh).cuda()
+        row = {"sweep": "solve", "n": n, "b": b, "leaf": leaf, "ncols": 8}
+        xs = {}
+        for method in ("substitution", "inverse"):
+            X = torch.zeros_like(B)
+            hq.cholesky_solve(H, B, X, tol=1e-12, method=method)  # warm
+            tf, ts = hq.cholesky_solve(H, B, X, tol=1e-12, method=method)
+            row[f"{method}_factor_s"] = tf
+            row[f"{method}_solve_s"] = ts
+            xs[method] = X.cpu().numpy()
+        row["max_diff"] = float(np.abs(xs["substitution"] - xs["inverse"]).max())
+        if n <= 4096:
+            ref = np.linalg.solve(wl.band_to_dense(ab), Bh.T).T
+            row["err_substitution"] = float(np.abs(xs["substitution"] - ref).max() / np.abs(ref).max())
+            row["err_inverse"] = float(np.abs(xs["inverse"] - ref).max() / np.abs(ref).max())
+        H.close()
+        print(json.dumps(row), flush=True)
+
+
 SWEEPS = {"nmin": sweep_nmin, "memory": sweep_memory, "scaling": sweep_scaling, "breakeven": sweep_breakeven,
-          "hmatrix": sweep_hmatrix}
+          "hmatrix": sweep_hmatrix, "solve": sweep_solve}
 
 
 if __name__ == "__main__":

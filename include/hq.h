@@ -126,6 +126,20 @@ hq_status hodlr_build(const double* band, int64_t n, int32_t b, int64_t ldab, do
                       const hq_opts* opts, void* stream, hq_hodlr_t* out);
 
 /*
+ * Solve H X = B for a symmetric positive definite HODLR matrix H (for instance hodlr_build of an SPD
+ * band; the lower blocks are read): the H-Cholesky H = L L^T of Alg. 3 (truncation at tol), then
+ *   method 0: the HODLR triangular solves of Table complexity_HODLR by substitution over the tree
+ *             (L T = B, then L^T X = T: one leaf product and two thin products per block, depth first);
+ *   method 1: the products with L^{-1} that the factorisation also forms, X = L^{-T} (L^{-1} B), the
+ *             route the QDWH iteration takes (level-parallel launches).
+ * B and X: device, n x ncols, column-major (ldb, ldx >= n); B is not modified.  cap: rank capacity of
+ * the inverse blocks (0: 64; HQ_ERR_RANK_OVERFLOW above it).  seconds (host, may be NULL) receives
+ * the wall times [factorisation, solve].  Blocks until done.  HQ_ERR_NOT_POSDEF if H is not.
+ */
+hq_status hodlr_cholesky_solve(hq_hodlr_t H, const double* B, int64_t ldb, int32_t ncols, double* X, int64_t ldx,
+                               double tol, int32_t cap, int32_t method, void* stream, double* seconds);
+
+/*
  * U ~ sign(A - mu I) in HODLR format (Sec. 2; Alg. 3 lines up to "U = X_k", symmetrised).
  * band: device.  Blocks until done (returns host status and info).  info may be NULL.
  */

@@ -11,4 +11,5 @@ from .binding import (  # noqa: F401
     shift_for_count, test_gemm, test_qr_r, test_recompress, test_from_dense, test_product,
     test_cholesky_inverse, test_q_factors, test_q_dense_host, profile, profile_read, KCLASSES,
     Predictor, predictor_rows, tuning, set_tuning, HMatrix, hodlr_to_hmatrix, iteration_records,
+    cholesky_solve,
 )

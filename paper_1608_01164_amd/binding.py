@@ -107,6 +107,7 @@ _lib = None
 _SIGS = {
     "hq_default_opts": (c_i32, [P(Opts)]),
     "hodlr_build": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, c_d, P(Opts), c_vp, P(c_vp)]),
+    "hodlr_cholesky_solve": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_d, c_i32, c_i32, c_vp, P(c_d)]),
     "qdwh_sign": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, P(Opts), c_vp, P(c_vp), P(Info)]),
     "spectral_projector": (c_i32, [c_vp, c_i64, c_i32, c_i64, c_d, P(Opts), c_vp, P(c_vp), P(Info)]),
     "spectral_projector_batched": (c_i32, [c_i32, P(c_vp), P(c_i64), P(c_i32), P(c_i64), P(c_d), P(Opts), c_vp,
@@ -427,6 +428,19 @@ def hodlr_build(band, b: int, shift: float, scale: float, leaf: int = 256, strea
     _check(lib().hodlr_build(p, n, int(b), ld, float(shift), float(scale), ctypes.byref(_opts(leaf=leaf)),
                              _stream(stream), ctypes.byref(h)))
     return HODLR(h)
+
+
+def cholesky_solve(H, B, X, tol: float = 1e-12, cap: int = 0, method: str = "substitution", stream=None):
+    """X = H^{-1} B for a symmetric positive definite HODLR handle H (device tensors, B and X of shape
+    (ncols, n) row-major = n x ncols column-major).  method "substitution": HODLR triangular solves with
+    the H-Cholesky factor; "inverse": products with the L^{-1} it forms.  Returns the seconds of the
+    factorisation and of the solve."""
+    m = {"substitution": 0, "inverse": 1}[method]
+    ncols, n = B.shape
+    sec = (c_d * 2)()
+    _check(lib().hodlr_cholesky_solve(H.handle, c_vp(B.data_ptr()), n, ncols, c_vp(X.data_ptr()), X.shape[1],
+                                      float(tol), int(cap), m, _stream(stream), sec))
+    return sec[0], sec[1]
 
 
 def _solve(fn, band, b, mu, stream, raw_info=False, **kw):

@@ -1302,6 +1302,59 @@ hq_status hodlr_build(const double* band, int64_t n, int32_t b, int64_t ldab, do
   });
 }
 
+hq_status hodlr_cholesky_solve(hq_hodlr_t H, const double* B, int64_t ldb, int32_t ncols, double* X, int64_t ldx,
+                               double tol, int32_t cap, int32_t method, void* stream, double* seconds) {
+  if (!H || !B || !X) return fail(HQ_ERR_ARG, "NULL argument");
+  const int64_t n = H->t.n;
+  if (ncols < 1 || ldb < n || ldx < n) return fail(HQ_ERR_ARG, "bad right-hand side shape");
+  if (!(tol > 0.0)) return fail(HQ_ERR_ARG, "tol must be positive");
+  if (cap < 0 || cap > hq::kMaxStack) return fail(HQ_ERR_ARG, "cap out of range");
+  if (method != 0 && method != 1) return fail(HQ_ERR_ARG, "method must be 0 (substitution) or 1 (inverse)");
+  return guard([&]() -> hq_status {
+    hipStream_t st = (hipStream_t)stream;
+    HQ_CHECK(hipEventSynchronize(H->done));
+    hq::Engine E(st);
+    E.tol = tol;
+    const int c = cap > 0 ? cap : 64;
+    const hq::Tree& t = H->t;
+    hq::HMat Linv = E.alloc_hmat(&t, caps_from(t, c, 1 << 30), false);
+    const std::vector<int> capW = E.chol_work_caps(t, H->H.cap, 2 * c + 16);
+    hq::HMat Lf = E.alloc_hmat(&t, capW, false);
+    hq::HMat L = E.alloc_hmat(&t, capW, false);
+    hq::HMat Zs = H->H;
+    Zs.lower_only = true;
+    const auto t0 = clk::now();
+    E.clear_flags(1);
+    E.cholesky_inverse({hq::Engine::CholTask{&Zs, &Linv, &Lf, 2 * c + 16, 0, method == 0 ? &L : nullptr}});
+    const int f = E.read_flag();
+    if (f & 2) return fail(HQ_ERR_NOT_POSDEF, "a leaf of H is not positive definite");
+    if (f & (4 | 8 | 16 | 32)) return fail(HQ_ERR_NONFINITE, "non-finite values in the factorisation");
+    if (f & 1) return fail(HQ_ERR_RANK_OVERFLOW, "a block rank above cap");
+    const double tf = secs(t0);
+    int* dw = E.persist.get<int>(1);
+    hq::launch_fill_int(dw, ncols, 1, E.st);
+    double* Bw = E.persist.get<double>((size_t)n * ncols);
+    double* T1 = E.persist.get<double>((size_t)n * ncols);
+    HQ_CHECK(hipMemcpy2DAsync(Bw, sizeof(double) * n, B, sizeof(double) * ldb, sizeof(double) * n, ncols,
+                              hipMemcpyDeviceToDevice, E.st));
+    HQ_CHECK(hipStreamSynchronize(E.st));
+    const auto t1 = clk::now();
+    if (method == 0) {
+      E.trsm_thin(L, false, Bw, (int)n, T1, (int)n, dw, ncols);  // L T = B (Bw updated in place)
+      E.trsm_thin(L, true, T1, (int)n, X, (int)ldx, dw, ncols);  // L^T X = T
+    } else {
+      E.mm_thin({hq::Engine::ThinTask{E.view(Linv), 0, Bw, (int)n, T1, (int)n, dw, ncols, 1.0, 0.0}});
+      E.mm_thin({hq::Engine::ThinTask{E.view(Linv, true), 0, T1, (int)n, X, (int)ldx, dw, ncols, 1.0, 0.0}});
+    }
+    HQ_CHECK(hipStreamSynchronize(E.st));
+    if (seconds) {
+      seconds[0] = tf;
+      seconds[1] = secs(t1);
+    }
+    return HQ_OK;
+  });
+}
+
 hq_status qdwh_sign(const double* band, int64_t n, int32_t b, int64_t ldab, double mu, const hq_opts* opts,
                     void* stream, hq_hodlr_t* sign_out, hq_info* info) {
   if (!sign_out) return fail(HQ_ERR_ARG, "sign_out is NULL");

@@ -295,11 +295,20 @@ class Engine {
   // tree whose leaves receive the leaf factors and whose off-diagonal blocks receive the untruncated
   // inverse blocks; its capacities must be chol_work_caps(Z's capacities, capS).  capS: capacity of
   // the compressed Schur factor.
-  struct CholTask { const HMat* Z; HMat* Linv; HMat* Lf; int capS; int fidx; };
+  // L (optional): receives the factor's off-diagonal blocks L_ba = Us Vs^T, untruncated (capacities
+  // of Lf); its leaves are Linv's (the inverses of the diagonal blocks), which is what substitution
+  // with L needs.
+  struct CholTask { const HMat* Z; HMat* Linv; HMat* Lf; int capS; int fidx; HMat* L = nullptr; };
   std::vector<int> chol_work_caps(const Tree& t, const std::vector<int>& capZ, int capS) const;
   void cholesky_inverse(const std::vector<CholTask>& v);
   void leaf_chol_inv(const std::vector<LeafTask>& blocks);
   void cholesky_inverse(const HMat& Z, HMat& Linv, HMat& Lf, int capS) { cholesky_inverse({CholTask{&Z, &Linv, &Lf, capS, 0}}); }
+  // Triangular solve with a thin dense right-hand side by substitution over the tree (Table
+  // complexity_HODLR: HODLR times triangular = given): L Z = B (trans false) or L^T Z = B (trans
+  // true), L lower triangular with the inverses of its diagonal blocks as leaves (CholTask::L).  B
+  // (n x w, leading dimension ldb) is overwritten by the updates, Z receives the solution.  Depth
+  // first: one GEMM per leaf and two per off-diagonal block, in dependency order.
+  void trsm_thin(const HMat& L, bool trans, double* B, int ldb, double* Z, int ldz, const int* w, int wcap, int p = 0);
   // out = sid * I + sx * (X + X^T) / 2 as a full HODLR (sign: sx = 1, sid = 0; projector: -1/2, 1/2)
   // C = sum_i w_i T_i (general HODLR matrices of one tree, at most kStackSrc terms): each block's
   // factors stacked with the weights on the U side and recompressed at tol; leaves summed.

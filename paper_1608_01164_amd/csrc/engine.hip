@@ -1132,6 +1132,11 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     const CholTask& T = batch[m];
     zero_ranks(*T.Linv);
     zero_ranks(*T.Lf);
+    if (T.L) {
+      zero_ranks(*T.L);
+      T.L->leaves = T.Linv->leaves;
+      T.L->ldl = T.Linv->ldl;
+    }
     lw[m] = *T.Lf;
     lw[m].leaves = T.Linv->leaves;
     lw[m].ldl = T.Linv->ldl;
@@ -1336,6 +1341,29 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
       th.push_back(ThinTask{view(lw[it.m], true), a, Vsv[i], ldc, T.Lf->V(p, 1), ldc, rsv[i], rcapv[i], 1.0, 0.0});
     }
     mm_thin(th);
+    // the factor's own block L_ba = Us Vs^T, where the caller keeps L
+    std::vector<StackTask> lc;
+    int lrows = 1;
+    for (int i = 0; i < ni; ++i) {
+      const Item& it = inner[i];
+      const CholTask& T = batch[it.m];
+      if (!T.L) continue;
+      const Tree* t = T.Z->t;
+      const int p = it.c, l = Tree::level(p);
+      const int ldc = (int)t->ldf[l];
+      const int64_t sa = t->size(2 * p + 1), sb = t->size(2 * p + 2);
+      StackTask u{};
+      u.dst = T.L->U(p, 1); u.ld = ldc; u.rows = (int)sb; u.wcap = T.L->cap[l]; u.wout = T.L->rk(p, 1); u.nsrc = 1;
+      u.fidx = T.fidx;
+      u.src[0] = {Usv[i], rsv[i], ldc, rcapv[i], 1.0};
+      StackTask v = u;
+      v.dst = T.L->V(p, 1); v.rows = (int)sa; v.wout = nullptr;
+      v.src[0] = {Vsv[i], rsv[i], ldc, rcapv[i], 1.0};
+      lc.push_back(u);
+      lc.push_back(v);
+      lrows = std::max<int>(lrows, (int)std::max(sa, sb));
+    }
+    stack(lc, lrows);
     scratch.rewind(mk2);
     scratch.rewind(mk);
   };
@@ -1358,6 +1386,44 @@ void Engine::cholesky_inverse(const std::vector<CholTask>& batch) {
     }
   }
   recompress(rec);
+}
+
+void Engine::trsm_thin(const HMat& L, bool trans, double* B, int ldb, double* Z, int ldz, const int* w, int wcap,
+                       int p) {
+  const Tree& t = *L.t;
+  const int64_t lo = t.lo[p];
+  if (t.is_leaf(p)) {  // Z_i = L_i^{-1} B_i (or L_i^{-T} B_i)
+    const int m = (int)t.size(p);
+    GemmTask g{};
+    g.A = L.leaf(t.leaf_index(p)); g.lda = L.ldl; g.opA = trans ? 1 : 0;
+    g.B = B + lo; g.ldb = ldb; g.C = Z + lo; g.ldc = ldz;
+    g.m = m; g.k = m; g.n = wcap; g.np = w; g.alpha = 1.0; g.beta = 0.0;
+    gemm({g}, m, wcap);
+    return;
+  }
+  const int a = 2 * p + 1, b = 2 * p + 2, l = Tree::level(p), ld = (int)t.ldf[l], cap = L.cap[l];
+  const int64_t la = t.lo[a], lb = t.lo[b];
+  const int sa = (int)t.size(a), sb = (int)t.size(b);
+  const DevArena::Mark mk = scratch.mark();
+  double* tmp = scratch.get<double>((size_t)std::max(cap, 1) * wcap);
+  // L = [L_aa 0; L_ba L_bb], L_ba = U V^T (block (p, lower)).  Forward: Z_a, then
+  // B_b -= U (V^T Z_a), then Z_b.  Transposed (L^T upper): Z_b, then B_a -= V (U^T Z_b), then Z_a.
+  const int first = trans ? b : a, second = trans ? a : b;
+  trsm_thin(L, trans, B, ldb, Z, ldz, w, wcap, first);
+  const double* Pz = Z + (trans ? lb : la);   // solved part
+  double* Bu = B + (trans ? la : lb);          // part to update
+  const double* Left = trans ? L.V(p, 1) : L.U(p, 1);    // rows of the updated part
+  const double* Right = trans ? L.U(p, 1) : L.V(p, 1);   // rows of the solved part
+  GemmTask g1{};  // tmp = Right^T Z_solved  (cap x w)
+  g1.A = Right; g1.opA = 1; g1.lda = ld; g1.B = Pz; g1.ldb = ldz; g1.C = tmp; g1.ldc = std::max(cap, 1);
+  g1.m = cap; g1.mp = L.rk(p, 1); g1.n = wcap; g1.np = w; g1.k = trans ? sb : sa; g1.alpha = 1.0; g1.beta = 0.0;
+  gemm({g1}, cap, wcap);
+  GemmTask g2{};  // B_upd -= Left tmp
+  g2.A = Left; g2.lda = ld; g2.B = tmp; g2.ldb = std::max(cap, 1); g2.C = Bu; g2.ldc = ldb;
+  g2.m = trans ? sa : sb; g2.n = wcap; g2.np = w; g2.k = cap; g2.kp = L.rk(p, 1); g2.alpha = -1.0; g2.beta = 1.0;
+  gemm({g2}, g2.m, wcap);
+  scratch.rewind(mk);
+  trsm_thin(L, trans, B, ldb, Z, ldz, w, wcap, second);
 }
 
 std::vector<int> Engine::chol_work_caps(const Tree& t, const std::vector<int>& capZ, int capS) const {

@@ -301,3 +301,30 @@ def test_q_factors_device(n, b, leaf):
     assert nr == len(rots)
     assert np.abs(oh.to_dense(h1.export()) - Q[:n, :n]).max() < 1e-13
     assert np.abs(h2.to_dense().cpu().numpy() - Q[n:, :n]).max() < 1e-13
+
+
+@pytest.mark.parametrize("n,b,leaf", [(1000, 3, 64), (777, 1, 32), (2048, 8, 128), (300, 2, 300)])
+def test_cholesky_solve_substitution_and_inverse(n, b, leaf):
+    """HODLR triangular solves by substitution with the H-Cholesky factor, and the route through the
+    inverse factor the iteration takes, both solve a symmetric positive definite banded system to the
+    truncation level and agree with each other; B is left as it was."""
+    import torch
+    import workloads as w
+    ab = np.array(w.banded_normal(n, b, 17), dtype=np.float64)
+    ab[:, 0] = np.abs(ab[:, 0]) + 2 * b * np.abs(ab).max() + 1.0  # diagonally dominant: SPD
+    A = w.band_to_dense(ab)
+    H = hq.hodlr_build(torch.from_numpy(np.ascontiguousarray(ab)).cuda(), b, 0.0, 1.0, leaf=leaf)
+    Bh = np.random.default_rng(3).standard_normal((5, n))  # five right-hand sides (n x 5 column-major)
+    B = torch.from_numpy(Bh).cuda()
+    ref = np.linalg.solve(A, Bh.T)
+    out = {}
+    for method in ("substitution", "inverse"):
+        X = torch.zeros_like(B)
+        tf, ts = hq.cholesky_solve(H, B, X, tol=1e-13, method=method)
+        Xh = X.cpu().numpy().T
+        assert np.abs(Xh - ref).max() <= 1e-9 * np.abs(ref).max(), method
+        assert np.array_equal(B.cpu().numpy(), Bh)
+        assert tf > 0 and ts > 0
+        out[method] = Xh
+    assert np.abs(out["substitution"] - out["inverse"]).max() <= 1e-9 * np.abs(ref).max()
+    H.close()
