@@ -1603,10 +1603,14 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
     const int c = idx % crows, i = idx / crows;  // C[c, i] = R[i, c]
     C[c + (size_t)i * ldc] = (c >= i && c < r) ? Bm[i + (size_t)c * ldb] : (T)0;
   }
-  for (int idx = tid; idx < jrows * t; idx += SVD_THREADS) {
-    const int i = idx % jrows, c = idx / jrows;
-    J[i + (size_t)c * ldj] = (i == c) ? (T)1 : (T)0;
-  }
+  // J is read only to form the left singular vectors: without them (Wk null) it is neither set up nor
+  // rotated, and C, hence every output, is the same either way
+  const bool needJ = Tk.Wk != nullptr;
+  if (needJ)
+    for (int idx = tid; idx < jrows * t; idx += SVD_THREADS) {
+      const int i = idx % jrows, c = idx / jrows;
+      J[i + (size_t)c * ldj] = (i == c) ? (T)1 : (T)0;
+    }
   __syncthreads();
   // ---- phase 2
   const int tp = t + (t & 1);
@@ -1678,19 +1682,21 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
           if (rot) {
             seg_store<EM, G>(up, cp, 0, ser, sl);
             seg_store<EM, G>(uq, cq, 0, ser, sl);
-            T* jp = J + (size_t)pp * ldj;
-            T* jq = J + (size_t)qq * ldj;
-            T vp[EM], vq[EM];
-            seg_load<EM, G>(vp, jp, 0, set, sl);
-            seg_load<EM, G>(vq, jq, 0, set, sl);
+            if (needJ) {
+              T* jp = J + (size_t)pp * ldj;
+              T* jq = J + (size_t)qq * ldj;
+              T vp[EM], vq[EM];
+              seg_load<EM, G>(vp, jp, 0, set, sl);
+              seg_load<EM, G>(vq, jq, 0, set, sl);
 #pragma unroll
-            for (int e = 0; e < EM; ++e) {
-              const T u2 = cs * vp[e] - sn * vq[e], w2 = sn * vp[e] + cs * vq[e];
-              vp[e] = u2;
-              vq[e] = w2;
+              for (int e = 0; e < EM; ++e) {
+                const T u2 = cs * vp[e] - sn * vq[e], w2 = sn * vp[e] + cs * vq[e];
+                vp[e] = u2;
+                vq[e] = w2;
+              }
+              seg_store<EM, G>(vp, jp, 0, set, sl);
+              seg_store<EM, G>(vq, jq, 0, set, sl);
             }
-            seg_store<EM, G>(vp, jp, 0, set, sl);
-            seg_store<EM, G>(vq, jq, 0, set, sl);
             if (sl == 0) {
               nrm2[pp] = ea;
               nrm2[qq] = eb;
@@ -1728,12 +1734,14 @@ static __device__ __forceinline__ int svd_tail(const T* Bm, const int ldb, T* C,
             }
           }
           if (rot) {
-            T* jp = J + (size_t)pp * ldj;
-            T* jq = J + (size_t)qq * ldj;
-            for (int i = sl; i < t; i += 16) {
-              const T uu = jp[i], w = jq[i];
-              jp[i] = cs * uu - sn * w;
-              jq[i] = sn * uu + cs * w;
+            if (needJ) {
+              T* jp = J + (size_t)pp * ldj;
+              T* jq = J + (size_t)qq * ldj;
+              for (int i = sl; i < t; i += 16) {
+                const T uu = jp[i], w = jq[i];
+                jp[i] = cs * uu - sn * w;
+                jq[i] = sn * uu + cs * w;
+              }
             }
             if (sl == 0) {
               nrm2[pp] = ea;
@@ -1958,7 +1966,7 @@ static __device__ __forceinline__ void svd_run(const SvdTask& Tk, int* flag, con
     unsigned long long f = 0;
     for (int j = 0; j < t; ++j)
       f += 2ull * (r - j) + 6ull * (unsigned long long)(r - j) * (r - j - 1) + 4ull * (r - j) * kk;
-    f += *S.pairs * 6ull * r + *S.rots * (6ull * r + 6ull * t) + 2ull * r * t;
+    f += *S.pairs * 6ull * r + *S.rots * (6ull * r + (Tk.Wk ? 6ull * t : 0ull)) + 2ull * r * t;
     count_work(K_SVD, f, 0);
     if (g_prof_on) {
       const unsigned long long c3 = wall_clock64();
